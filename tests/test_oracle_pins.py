@@ -1,0 +1,477 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by
+mathematics (no GPU).  Every test here checks the oracle against something
+other than itself: a library routine, a closed form, an invariant stated in
+the paper, or brute force on tiny inputs."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from paper_2006_16438_amd import synth
+
+
+# ----------------------------------------------------------------- helpers --
+def krp_rows(factors, modes):
+    """Explicit KRP of factors[modes] (first listed mode fastest), eq. (2.1)."""
+    Z = factors[modes[0]].copy()
+    for m in modes[1:]:
+        A = factors[m]
+        Z = (A[:, None, :] * Z[None, :, :]).reshape(A.shape[0] * Z.shape[0], -1)
+    return Z
+
+
+def unfold(dims, coords, vals, k):
+    """Dense mode-k unfolding X_(k), columns indexed by the other modes'
+    linear index (first other mode fastest)."""
+    others = [m for m in range(len(dims)) if m != k]
+    N = int(np.prod([dims[m] for m in others]))
+    lin = np.zeros(coords.shape[1], dtype=np.int64)
+    stride = 1
+    for m in others:
+        lin += coords[m].astype(np.int64) * stride
+        stride *= dims[m]
+    X = np.zeros((dims[k], N))
+    np.add.at(X, (coords[k], lin), vals)
+    return X
+
+
+def q_vectors(factors, R):
+    qs = []
+    for A in factors:
+        lev, _ = oracle.leverage(A)
+        _, _, q, _ = oracle.sampling_vectors(lev, R)
+        qs.append(q)
+    return qs
+
+
+def concentrated_factors(dims, R, seed):
+    rng = np.random.default_rng(seed)
+    fac = []
+    for n in dims:
+        A = rng.standard_normal((n, R)) * 0.05
+        hot = rng.choice(n, size=min(n, R), replace=False)
+        for j, h in enumerate(hot):
+            A[h, j % R] += 3.0 + j
+        fac.append(A)
+    return fac
+
+
+# ------------------------------------------------------------------ Philox --
+@pytest.mark.parametrize("key", [(0, 0), (0x1234, 0x5678), (2**64 - 1, 7), (0xDEADBEEF, 2**63)])
+def test_philox_matches_numpy(key):
+    """numpy's Philox (4x64, 10 rounds) increments its 256-bit counter and
+    then emits that block, so a numpy counter of c-1 yields block c."""
+    for c0 in [0, 1, 2, 12345, 2**40 + 3]:
+        for rest in [(0, 0, 0), (5 | (2 << 8), 9, 0), (2**64 - 1, 3, 1)]:
+            ctr = [c0, *rest]
+            v = sum(int(c) << (64 * i) for i, c in enumerate(ctr))
+            v = (v - 1) % (1 << 256)
+            prev = [(v >> (64 * i)) & (2**64 - 1) for i in range(4)]
+            ref = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                                  counter=np.array(prev, dtype=np.uint64)).random_raw(4)
+            assert np.array_equal(oracle.philox(ctr, key), ref), (ctr, key)
+
+
+def test_scale128_exact():
+    rng = np.random.default_rng(3)
+    for _ in range(2000):
+        u0, u1 = (int(x) for x in rng.integers(0, 2**64, size=2, dtype=np.uint64))
+        W = int(rng.integers(1, 2**53, dtype=np.uint64))
+        U = (u1 << 64) | u0
+        assert oracle.scale128(u0, u1, W) == (U * W) >> 128
+    # extremes
+    assert oracle.scale128(2**64 - 1, 2**64 - 1, 2**53) == 2**53 - 1
+    assert oracle.scale128(0, 0, 12345) == 0
+
+
+def test_integer_cdf_map_is_exact():
+    """Each v in [0, W) maps to the unique i with C[i-1] <= v < C[i], so a
+    uniform v picks i with probability exactly w_i / W (multinomial draw)."""
+    w = np.array([3, 0, 5, 1, 0, 7, 2], dtype=np.uint64)
+    Cdf = np.cumsum(w).astype(np.uint64)
+    counts = np.zeros(w.size, dtype=np.int64)
+    for v in range(int(Cdf[-1])):
+        i = oracle.upper_bound(Cdf, v)
+        counts[i] += 1
+        lo = 0 if i == 0 else int(Cdf[i - 1])
+        assert lo <= v < int(Cdf[i])
+    assert np.array_equal(counts, w.astype(np.int64))
+
+
+# ---------------------------------------------------------------- leverage --
+@pytest.mark.parametrize("n,R", [(7, 7), (50, 5), (300, 7), (513, 25), (1000, 64)])
+def test_leverage_matches_qr(n, R):
+    """Def. 3.4: l_i = ||Q(i,:)||^2 for an orthonormal basis Q of range(A);
+    0 <= l <= 1 and sum l = r."""
+    rng = np.random.default_rng(n * 100 + R)
+    A = rng.standard_normal((n, R))
+    lev, fl = oracle.leverage(A)
+    Q, _ = np.linalg.qr(A)
+    ref = (Q * Q).sum(axis=1)
+    assert fl == 0
+    assert np.max(np.abs(lev - ref)) <= 1e-12 * max(1.0, R)
+    assert abs(lev.sum() - R) <= 1e-11 * R
+    assert lev.min() >= 0 and lev.max() <= 1 + 1e-12
+
+
+def test_leverage_rank_deficient_uses_pinv():
+    """Rank-deficient A: leverage is the diagonal of the projector onto
+    range(A), sum = rank(A)."""
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((120, 4))
+    A = np.concatenate([B, B[:, :1] * 2.0], axis=1)      # rank 4, R = 5
+    lev, fl = oracle.leverage(A)
+    assert fl & oracle.FLAG_PINV
+    U, S, _ = np.linalg.svd(A, full_matrices=False)
+    Ur = U[:, :4]
+    ref = (Ur * Ur).sum(axis=1)
+    assert np.max(np.abs(lev - ref)) <= 1e-10
+    assert abs(lev.sum() - 4.0) <= 1e-9
+
+
+def test_gram_blocked_matches_numpy():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((1000, 9))
+    G = oracle.gram(A)
+    assert np.allclose(G, A.T @ A, rtol=1e-13, atol=1e-12)
+    assert np.array_equal(G, G.T)
+
+
+def test_sampling_vectors_integer_weights():
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((400, 6))
+    lev, _ = oracle.leverage(A)
+    w, Cdf, q, W = oracle.sampling_vectors(lev, 6)
+    assert W == int(Cdf[-1]) == int(w.astype(object).sum())
+    assert np.array_equal(np.cumsum(w.astype(object)).astype(np.uint64), Cdf)
+    # w_i / 2^52 underestimates l_i / R by less than 2^-52
+    err = lev / 6 - w.astype(np.float64) / 2.0**52
+    assert err.min() >= 0 and err.max() < 2.0**-52 * 1.0000001
+    assert abs(q.sum() - 1.0) < 1e-13
+    # total mass lost to flooring is below n * 2^-52
+    assert 2**52 - W <= 400 + 1
+
+
+def test_lemma51_krp_leverage_bound():
+    """Lemma 5.1: l_i(Z) <= prod_k l_{i_k}(A_k) for Z a Khatri-Rao product."""
+    rng = np.random.default_rng(21)
+    for dims, R in [((6, 5, 4), 3), ((9, 7), 4), ((4, 3, 5, 2), 2)]:
+        fac = [rng.standard_normal((n, R)) for n in dims]
+        Z = krp_rows(fac, list(range(len(dims))))
+        lz, _ = oracle.leverage(Z)
+        levs = [oracle.leverage(A)[0] for A in fac]
+        bound = krp_rows([l[:, None] for l in levs], list(range(len(dims))))[:, 0]
+        assert np.all(lz <= bound + 1e-12)
+        assert abs(lz.sum() - R) < 1e-10
+
+
+# ---------------------------------------------------------------- sampling --
+def test_lemma53_per_mode_draws_follow_product_distribution():
+    """Lemma 5.3: independent per-mode draws from l(A_m)/r give KRP row i
+    with probability prod q.  Chi-square over 2e5 draws on N = 4*6 rows."""
+    dims = (5, 4, 6)
+    R = 2
+    rng = np.random.default_rng(31)
+    fac = [rng.standard_normal((n, R)) for n in dims]
+    T = synth.random_sparse(dims, 40, seed=2)
+    OT = oracle.Tensor.from_synth(T)
+    s = 200_000
+    out = oracle.mode_update(OT, [f.copy() for f in fac], 0, 7, R, s, tau=1.0)
+    raw = out["raw"].astype(np.int64)
+    assert raw.size == s and out["stats"]["s_det"] == 0 and out["stats"]["draws"] == s
+    qs = q_vectors(fac, R)
+    p = (qs[2][:, None] * qs[1][None, :]).reshape(-1)   # lin = i1 + 4*i2
+    counts = np.bincount(raw, minlength=p.size)
+    chi2 = ((counts - s * p) ** 2 / (s * p)).sum()
+    assert stats.chi2.sf(chi2, p.size - 1) > 1e-6
+
+
+@pytest.mark.parametrize("tau", [1 / 8, 1 / 32, 1 / 128, 1 / 1024])
+def test_det_set_bruteforce(tau):
+    """Sec. 5.3: D = {i : p_i > tau} computed without visiting all N rows
+    equals the brute-force set over all N; D is inside the product of the
+    candidate sets; |D| < 1/tau."""
+    dims = (7, 9, 8, 6)
+    R = 3
+    fac = concentrated_factors(dims, R, 41)
+    qs = q_vectors(fac, R)
+    k = 2
+    others = [0, 1, 3]
+    idx, p, pdet, fl = oracle.det_set(dims, qs, k, 10_000, tau)
+    true = []
+    for i3, i1, i0 in itertools.product(range(dims[3]), range(dims[1]), range(dims[0])):
+        pr = qs[0][i0] * qs[1][i1]
+        pr = pr * qs[3][i3]
+        if pr > tau:
+            true.append((i0 + dims[0] * (i1 + dims[1] * i3), pr))
+    true.sort()
+    assert fl == 0
+    assert [int(x) for x in idx] == [t[0] for t in true]
+    assert np.array_equal(p, np.array([t[1] for t in true]))
+    assert len(true) < 1 / tau
+    assert math.isclose(pdet, math.fsum(t[1] for t in true), rel_tol=1e-14, abs_tol=1e-300)
+    assert others == [0, 1, 3]
+
+
+def test_det_set_truncation_keeps_most_probable():
+    dims = (5, 6, 4)
+    R = 2
+    fac = concentrated_factors(dims, R, 43)
+    qs = q_vectors(fac, R)
+    s = 16
+    idx, p, pdet, fl = oracle.det_set(dims, qs, 0, s, 1e-12)
+    assert fl & oracle.FLAG_DET_TRUNC
+    allp = []
+    for i2, i1 in itertools.product(range(dims[2]), range(dims[1])):
+        allp.append((-(qs[1][i1] * qs[2][i2]), i1 + dims[1] * i2))
+    allp.sort()
+    keep = sorted(lin for _, lin in allp[:s])
+    assert [int(x) for x in idx] == keep
+
+
+def test_det_cap_falls_back_to_random():
+    dims = (6, 5, 4)
+    T = synth.random_sparse(dims, 60, seed=3)
+    OT = oracle.Tensor.from_synth(T)
+    fac = concentrated_factors(dims, 2, 44)
+    out = oracle.mode_update(OT, fac, 0, 0, 2, 64, tau=1e-6, det_cap=3)
+    assert out["stats"]["flags"] & oracle.FLAG_DETCAP
+    assert out["stats"]["s_det"] == 0 and out["stats"]["p_det"] == 0.0
+    assert out["stats"]["draws"] == 64
+
+
+def test_combining_preserves_sketch_norm():
+    """Sec. 4.1/4.3: ||Omega_bar x|| = ||Omega x|| for every x, where the
+    uncombined random rows have weight^2 = (1 - p_det) / (s_rnd p_i)."""
+    dims = (10, 8, 6)
+    R = 3
+    T = synth.random_sparse(dims, 200, seed=5)
+    OT = oracle.Tensor.from_synth(T)
+    fac = concentrated_factors(dims, R, 45)
+    qs = q_vectors(fac, R)
+    out = oracle.mode_update(OT, [f.copy() for f in fac], 1, 3, R, 300)
+    st = out["stats"]
+    assert st["s_det"] > 0 and st["s_rnd"] > 0
+    N = dims[0] * dims[2]
+    pfull = (qs[2][:, None] * qs[0][None, :]).reshape(-1)    # lin = i0 + 10*i2
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        x = rng.standard_normal(N)
+        raw = out["raw"].astype(np.int64)
+        unc = np.sum((1 - st["p_det"]) / (st["s_rnd"] * pfull[raw]) * x[raw] ** 2)
+        sd = st["s_det"]
+        det = np.sum(x[out["idx"][:sd].astype(np.int64)] ** 2)
+        comb = np.sum(out["omega"][sd:] * x[out["idx"][sd:].astype(np.int64)] ** 2)
+        assert math.isclose(det + unc, det + comb, rel_tol=1e-12)
+    # counts: omega_j = c_j (1 - p_det) / (s_rnd p_j) with c_j the multiplicity
+    uniq, cnt = np.unique(out["raw"], return_counts=True)
+    sd = st["s_det"]
+    assert np.array_equal(uniq, out["idx"][sd:])
+    expect = cnt * (1 - st["p_det"]) / (st["s_rnd"] * pfull[uniq.astype(np.int64)])
+    assert np.allclose(out["omega"][sd:], expect, rtol=1e-14)
+    assert np.array_equal(out["wgt"], np.sqrt(out["omega"]))
+    # deterministic and random rows are disjoint and each part is ascending
+    assert not set(out["idx"][:sd].tolist()) & set(uniq.tolist())
+    assert np.all(np.diff(out["idx"][:sd].astype(np.int64)) > 0)
+
+
+def test_hybrid_sketch_is_unbiased():
+    """Lemma 3.2 with the hybrid reweighting of Sec. 4.2: E||Omega x||^2 =
+    ||x||^2.  Monte Carlo over 600 seeds, 5 standard errors."""
+    dims = (6, 5, 4)
+    R = 2
+    T = synth.random_sparse(dims, 30, seed=6)
+    OT = oracle.Tensor.from_synth(T)
+    fac = concentrated_factors(dims, R, 46)
+    N = dims[1] * dims[2]
+    x = np.random.default_rng(1).standard_normal(N)
+    ests = []
+    saw_det = False
+    for seed in range(600):
+        out = oracle.mode_update(OT, [f.copy() for f in fac], 0, 0, R, 8, tau=1 / 8, seed=seed)
+        saw_det |= out["stats"]["s_det"] > 0
+        ests.append(np.sum(out["omega"] * x[out["idx"].astype(np.int64)] ** 2))
+    ests = np.array(ests)
+    se = ests.std(ddof=1) / math.sqrt(ests.size)
+    assert saw_det
+    assert abs(ests.mean() - np.sum(x * x)) < 5 * se
+
+
+# ----------------------------------------------------------- mode update --
+@pytest.mark.parametrize("dims,k", [((9, 7, 5), 0), ((9, 7, 5), 2), ((6, 5, 4, 3), 1), ((40, 30), 0)])
+def test_all_rows_update_equals_cp_als(dims, k):
+    """tau = 0 and s > N: every KRP row is deterministic with weight 1 and
+    the sampled update is the CP-ALS normal-equations step
+    A_k = X_(k) Z (Z^T Z)^{-1}, Z^T Z = Hadamard product of the Grams."""
+    R = 3
+    T = synth.random_sparse(dims, int(0.4 * np.prod(dims)), seed=7)
+    OT = oracle.Tensor.from_synth(T)
+    fac = synth.gaussian_factors(dims, R, 8)
+    others = [m for m in range(len(dims)) if m != k]
+    N = int(np.prod([dims[m] for m in others]))
+    Z = krp_rows(fac, others)
+    Xk = unfold(dims, T.coords, T.values, k)
+    V = np.ones((R, R))
+    for m in others:
+        V *= fac[m].T @ fac[m]
+    assert np.allclose(Z.T @ Z, V, rtol=1e-12)
+    ref = np.linalg.solve(V, (Xk @ Z).T).T
+    f2 = [f.copy() for f in fac]
+    out = oracle.mode_update(OT, f2, k, 0, R, N + 5, tau=0.0, det_cap=N + 1)
+    st = out["stats"]
+    assert st["s_det"] == N and st["s_rnd"] == 0 and st["flags"] & oracle.FLAG_PDET_ONE
+    assert np.array_equal(out["idx"], np.arange(N, dtype=np.uint64))
+    assert np.all(out["omega"] == 1.0)
+    assert st["gathered_nnz"] == T.nnz
+    err = np.max(np.abs(f2[k] - ref)) / np.max(np.abs(ref))
+    assert err < 1e-12
+
+
+def test_update_solves_the_explicit_sketched_problem():
+    """Eq. (1.2): the update is argmin ||Omega Z B^T - Omega X_(k)^T|| with
+    Omega given by the returned rows and weights; built explicitly here and
+    solved by QR (numpy lstsq).  Sparse X, so some sampled fibers are empty
+    and still enter the system as zero rows."""
+    dims = (12, 10, 8)
+    R = 4
+    T = synth.random_sparse(dims, 60, seed=9)
+    OT = oracle.Tensor.from_synth(T)
+    fac = concentrated_factors(dims, R, 47)
+    saw_empty = False
+    for k in range(3):
+        f2 = [f.copy() for f in fac]
+        out = oracle.mode_update(OT, f2, k, 11 + k, R, 96)
+        others = [m for m in range(3) if m != k]
+        Z = krp_rows(fac, others)
+        Xk = unfold(dims, T.coords, T.values, k)
+        ii = out["idx"].astype(np.int64)
+        wv = out["wgt"][:, None]
+        Zs = wv * Z[ii]
+        Xs = wv * Xk[:, ii].T
+        saw_empty |= bool(np.any(np.all(Xk[:, ii] == 0, axis=0)))
+        B, *_ = np.linalg.lstsq(Zs, Xs, rcond=None)
+        ref = B.T
+        err = np.max(np.abs(f2[k] - ref)) / np.max(np.abs(ref))
+        assert err < 1e-9
+        assert out["stats"]["gathered_nnz"] == int(np.count_nonzero(Xk[:, ii]))
+    assert saw_empty, "want at least one empty sampled fiber"
+
+
+def test_exact_model_is_recovered_from_any_sample():
+    """Noise-free rank-R tensor, all entries stored, other factors exact:
+    the sampled LS is consistent, so the true A_k comes back."""
+    dims = (8, 7, 6)
+    R = 3
+    T, fac = synth.planted(dims, R, seed=12, rel_noise=0.0)
+    OT = oracle.Tensor.from_synth(T)
+    for k in range(3):
+        f2 = [f.copy() for f in fac]
+        f2[k] = np.random.default_rng(k).standard_normal(f2[k].shape)
+        oracle.mode_update(OT, f2, k, k, R, 40)
+        assert np.max(np.abs(f2[k] - fac[k])) < 1e-10
+
+
+def _fms(A, B):
+    """Factor match score over the best column permutation (congruence)."""
+    R = A[0].shape[1]
+    best = 0.0
+    for perm in itertools.permutations(range(R)):
+        sc = 0.0
+        for r in range(R):
+            prod = 1.0
+            for Am, Bm in zip(A, B):
+                a = Am[:, r] / np.linalg.norm(Am[:, r])
+                b = Bm[:, perm[r]] / np.linalg.norm(Bm[:, perm[r]])
+                prod *= abs(a @ b)
+            sc += prod
+        best = max(best, sc / R)
+    return best
+
+
+def test_planted_model_recovery():
+    """Whole loop (Alg. 3 with fixed iterations): a fully stored planted
+    rank-3 tensor with 1% noise is recovered (FMS >= 0.99, fit near 1 - noise)
+    from at least one of four random starts."""
+    dims = (30, 25, 20)
+    R = 3
+    T, fac = synth.planted(dims, R, seed=13, rel_noise=0.01)
+    OT = oracle.Tensor.from_synth(T)
+    results = []
+    for restart in range(4):
+        f = synth.gaussian_factors(dims, R, 100 + restart)
+        oracle.cp_arls_lev(OT, f, R, 512, 25, seed=restart)
+        results.append((oracle.fit_exact(OT, f, R), _fms(fac, f)))
+    fit, fms = max(results)
+    assert fms >= 0.99, results
+    assert fit >= 1 - 1.5 * 0.01, results
+
+
+def test_zero_factor_is_a_state_error():
+    dims = (5, 4, 3)
+    T = synth.random_sparse(dims, 20, seed=1)
+    OT = oracle.Tensor.from_synth(T)
+    fac = synth.gaussian_factors(dims, 2, 1)
+    fac[1][:] = 0.0
+    with pytest.raises(RuntimeError):
+        oracle.mode_update(OT, fac, 0, 0, 2, 16)
+
+
+# --------------------------------------------------------------------- fit --
+def test_exact_fit_matches_dense():
+    dims = (7, 6, 5)
+    R = 3
+    T = synth.random_sparse(dims, 80, seed=14)
+    OT = oracle.Tensor.from_synth(T)
+    fac = synth.gaussian_factors(dims, R, 15)
+    X = np.zeros(dims)
+    X[tuple(T.coords)] = T.values
+    M = np.einsum("ir,jr,kr->ijk", *fac)
+    ref = 1 - np.linalg.norm(X - M) / np.linalg.norm(X)
+    assert math.isclose(oracle.fit_exact(OT, fac, R), ref, rel_tol=1e-11, abs_tol=1e-11)
+    coord = T.coords[:, 3]
+    assert math.isclose(oracle.model_entry(fac, coord), M[tuple(coord)], rel_tol=1e-13)
+
+
+def test_fit_estimate_is_unbiased_and_stratified():
+    """Sec. 6.4: ceil(alpha s_fit) nonzeros and floor((1-alpha) s_fit) zeros,
+    zeros never stored coordinates, and E[F_hat] = ||X - M||^2."""
+    dims = (8, 7, 6)
+    R = 2
+    T = synth.random_sparse(dims, 50, seed=16)
+    OT = oracle.Tensor.from_synth(T)
+    fac = synth.gaussian_factors(dims, R, 17)
+    X = np.zeros(dims)
+    X[tuple(T.coords)] = T.values
+    M = np.einsum("ir,jr,kr->ijk", *fac)
+    F = np.sum((X - M) ** 2)
+    stored = set(map(tuple, T.coords.T.tolist()))
+    ests = []
+    for sid in range(300):
+        fs = oracle.FitSample(OT, 33, 0.5, seed=4, stream_id=sid)
+        assert fs.n == 33
+        zc = fs.coords[:, 17:33]
+        assert all(tuple(c) not in stored for c in zc.T.tolist())
+        assert np.all(fs.x[17:33] == 0)
+        assert np.all(fs.phi[:17] == 50 / 17) and np.all(fs.phi[17:33] == (336 - 50) / 16)
+        fhat = (1 - fs.estimate(fac)) ** 2 * OT.norm ** 2
+        ests.append(fhat)
+    ests = np.array(ests)
+    se = ests.std(ddof=1) / math.sqrt(ests.size)
+    assert abs(ests.mean() - F) < 5 * se
+
+
+def test_single_row_krp_is_always_accepted():
+    """Degenerate N = 1 (every other mode has size 1): p = 1 = tau for the
+    random-only setting, and Alg. 2 keeps rows with p <= tau, so all s draws
+    are accepted and combine into one row of weight sqrt(s/s)."""
+    dims = (5, 1)
+    T = synth.random_sparse(dims, 4, seed=2)
+    OT = oracle.Tensor.from_synth(T)
+    fac = synth.gaussian_factors(dims, 1, 3)
+    out = oracle.mode_update(OT, fac, 0, 0, 1, 7, tau=1.0)
+    st = out["stats"]
+    assert st["draws"] == 7 and st["s_rnd"] == 7 and st["s_bar"] == 1
+    assert out["omega"][0] == 1.0 and st["flags"] == 0
