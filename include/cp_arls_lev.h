@@ -1,0 +1,172 @@
+/*
+ * cp_arls_lev.h -- C ABI of the MI355X (gfx950) CP-ARLS-LEV mode-update library.
+ *
+ * The library runs the per-mode step of CP via alternating randomized least
+ * squares with leverage-score sampling (Larsen & Kolda, "Practical
+ * Leverage-Based Sampling for Low-Rank Tensor Decomposition", Alg. 3):
+ * leverage scores of the factor matrices (Def. 3.4), hybrid deterministic +
+ * random sampling of Khatri-Rao-product rows (Alg. 1, Alg. 2, Sec. 4.2-4.3,
+ * Sec. 5.3), extraction of the sampled tensor fibers (Sec. 6.3) and the
+ * sampled least-squares solve, plus the stratified fit estimate (Sec. 6.4).
+ *
+ * Conventions
+ *  - Pointers are DEVICE pointers unless marked "host".
+ *  - Factor matrices are FP64, row-major n_m x R, owned by the caller; the
+ *    library reads them and overwrites factors[k] on a mode-k update.
+ *  - Tensor coordinates are 0-based int32 in structure-of-arrays layout
+ *    coords[m * nnz + e]; coordinates must be distinct.
+ *  - Linear index of a KRP row for the update of mode k: the other modes in
+ *    ascending order, first other mode fastest (eq. (2.2), 0-based).
+ *  - All work is enqueued on the stream given at init; calls are
+ *    asynchronous unless stated.  A context is not thread-safe.
+ *  - Status codes report argument/state errors synchronously; data-dependent
+ *    conditions are reported through cpal_mode_stats.flags in device memory.
+ */
+#ifndef CP_ARLS_LEV_H
+#define CP_ARLS_LEV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpal_ctx cpal_ctx;
+
+typedef enum {
+  CPAL_OK = 0,
+  CPAL_E_ARG = 1,      /* invalid argument (null pointer, bad size, bad option)  */
+  CPAL_E_NOMEM = 2,    /* device allocation failed                               */
+  CPAL_E_DEVICE = 3,   /* a HIP call or kernel launch failed                     */
+  CPAL_E_STATE = 4     /* invalid state (e.g. an all-zero factor matrix)          */
+} cpal_status;
+
+typedef enum { CPAL_F64 = 0, CPAL_F32 = 1, CPAL_BF16 = 2 } cpal_dtype;
+
+/* Bits of cpal_mode_stats.flags. */
+enum {
+  CPAL_FLAG_PINV = 1,       /* a Gram matrix was singular: pseudo-inverse used        */
+  CPAL_FLAG_DETCAP = 2,     /* deterministic enumeration exceeded det_enum_cap: the
+                               update sampled randomly only (tau treated as 1)        */
+  CPAL_FLAG_DET_TRUNC = 4,  /* >= s rows above tau: the s most probable kept          */
+  CPAL_FLAG_PDET_ONE = 8,   /* 1 - p_det <= 2^-40: no random rows                     */
+  CPAL_FLAG_DRAWCAP = 16,   /* random draws hit 64*s_rnd + 2^20 before s_rnd accepts  */
+  CPAL_FLAG_OVERFLOW = 32,  /* the deterministic set exceeded its buffer (4s+4096)    */
+  CPAL_FLAG_STATE = 64      /* a probability vector summed to zero                    */
+};
+
+typedef struct {
+  int32_t order;             /* D >= 2, <= 8                                           */
+  const int64_t *dims;       /* host, order entries; prod(dims) < 2^62                 */
+  int64_t nnz;               /* >= 1, < 2^32                                           */
+  const int32_t *coords;     /* device, [order][nnz], distinct coordinates             */
+  const void *values;        /* device, nnz values of value_dtype                      */
+  int32_t value_dtype;       /* CPAL_F32 or CPAL_F64                                   */
+} cpal_tensor;
+
+typedef struct {
+  int32_t rank;              /* R, 1..64                                               */
+  int64_t samples;           /* s >= 1 (rows sampled per least-squares problem)        */
+  double tau;                /* deterministic threshold in [0,1]; 1 = random only      */
+  uint64_t seed;             /* Philox key word 0                                      */
+  uint64_t stream_id;        /* Philox key word 1 (e.g. the restart number)            */
+  int32_t gather_dtype;      /* CPAL_F64 (parity) or CPAL_F32: precision of the fiber
+                                values, the weighted KRP rows and the sampled MTTKRP;
+                                Gram matrices, solves and leverage are always FP64   */
+  int64_t fit_samples;       /* s_fit for cp_arls_lev_fit_estimate; 0 = no fit sample  */
+  double fit_nnz_fraction;   /* alpha in [0,1] (Sec. 6.4), default 0.5                 */
+  int64_t det_enum_cap;      /* max candidate combinations examined by the
+                                deterministic enumeration; 0 = 2^26                  */
+} cpal_options;
+
+typedef struct {
+  int64_t s_det;             /* deterministic rows                                     */
+  int64_t s_rnd;             /* accepted random draws                                  */
+  int64_t s_bar;             /* rows of the sampled system (s_det + unique random)     */
+  int64_t draws;             /* random draws made                                      */
+  int64_t gathered_nnz;      /* nonzeros in the sampled fibers                         */
+  double p_det;              /* total probability of the deterministic rows            */
+  int32_t flags;             /* CPAL_FLAG_* bits                                       */
+  int32_t pad;
+} cpal_mode_stats;
+
+/* Create a context (Alg. 3 setup): copies X into per-mode fiber indexes
+ * (Sec. 6.3: every nonzero keyed by the linear index of its other-mode
+ * coordinates, sorted, with a hash table key -> fiber), computes the
+ * leverage scores of every initial factor (Alg. 3, first loop) and, if
+ * fit_samples > 0, draws the stratified fit sample once (Sec. 6.4).
+ * factors: host array of `order` device pointers, each n_m x R FP64,
+ * caller-owned, must outlive the context.  hip_stream: hipStream_t (may be
+ * NULL for the default stream).  Synchronizes the stream before returning;
+ * X may be freed afterwards.  Errors: CPAL_E_ARG (bad sizes/options/null),
+ * CPAL_E_NOMEM, CPAL_E_DEVICE, CPAL_E_STATE (an all-zero factor). */
+cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
+                             double *const *factors, void *hip_stream, cpal_ctx **out);
+
+/* One mode update of Alg. 3 for mode `mode`: SkrpLev (Alg. 1) over the
+ * cached leverage of the other modes -- deterministic rows with p > tau
+ * (Sec. 5.3), random rows by per-mode Philox draws (Lemma 5.3, Alg. 2) with
+ * rejection of p > tau, repeats combined (Sec. 4.1, 4.3) -- then the sampled
+ * fibers (Sec. 6.3), the weighted normal equations G_s = Z~^T Z~,
+ * M = X~^T Z~ and A_k = M G_s^{-1} (pseudo-inverse if singular) written to
+ * factors[mode], and the leverage of the new A_k.  The step counter t (the
+ * third Philox counter word) increments by one per call.  stats_dev: device
+ * pointer to one cpal_mode_stats, or NULL.  Asynchronous; errors:
+ * CPAL_E_ARG (mode out of range), CPAL_E_STATE (context failed earlier),
+ * CPAL_E_DEVICE. */
+cpal_status cp_arls_lev_mode_update(cpal_ctx *ctx, int32_t mode, cpal_mode_stats *stats_dev);
+
+/* Estimated fit 1 - sqrt(F^)/||X|| (Sec. 6.4) with the fit sample drawn at
+ * init, from the current factors.  fit_dev: device pointer to one double.
+ * CPAL_E_STATE if the context was created with fit_samples = 0. */
+cpal_status cp_arls_lev_fit_estimate(cpal_ctx *ctx, double *fit_dev);
+
+/* Copy the last update's sampled rows: linear indices, omega (= weight^2)
+ * and weights; deterministic rows first (ascending), then combined random
+ * rows (ascending).  Copies min(s_bar, cap) rows; *count_dev = s_bar.
+ * Asynchronous.  Exists so that callers can audit the sketch. */
+cpal_status cp_arls_lev_samples(const cpal_ctx *ctx, uint64_t *idx_dev, double *omega_dev,
+                                double *w_dev, int64_t cap, int64_t *count_dev);
+
+/* Copy the cached leverage scores (Def. 3.4) of a mode: n_mode doubles. */
+cpal_status cp_arls_lev_leverage(const cpal_ctx *ctx, int32_t mode, double *lev_dev);
+
+/* Recompute the cached leverage of `mode` from the current factors[mode]
+ * (call after the caller changed a factor matrix). */
+cpal_status cp_arls_lev_refresh(cpal_ctx *ctx, int32_t mode);
+
+/* Get / set the step counter t used in the Philox counter of the next update. */
+cpal_status cp_arls_lev_get_step(const cpal_ctx *ctx, uint64_t *t_host);
+cpal_status cp_arls_lev_set_step(cpal_ctx *ctx, uint64_t t);
+
+/* Stages of a mode update timed by cp_arls_lev_stage_times. */
+enum {
+  CPAL_STAGE_SAMPLE = 0,   /* deterministic + random rows, combining (Alg. 1, 2)  */
+  CPAL_STAGE_ROWS = 1,     /* weights, KRP rows, fiber probes, G_s partials       */
+  CPAL_STAGE_GATHER = 2,   /* fiber gather + sampled MTTKRP (Sec. 6.3)            */
+  CPAL_STAGE_SOLVE = 3,    /* G_s factorization and A_k = M G_s^{-1}              */
+  CPAL_STAGE_LEVERAGE = 4, /* leverage scores and CDF of the new A_k (Def. 3.4)   */
+  CPAL_NSTAGES = 5
+};
+
+/* Enable (1) or disable (0) recording of HIP events around every stage of
+ * each mode update on the context's stream (profiling aid; off by default). */
+cpal_status cp_arls_lev_set_timing(cpal_ctx *ctx, int32_t enable);
+
+/* Synchronizes the stream and returns, per stage, the summed duration in
+ * milliseconds (ms_host[CPAL_NSTAGES]) and the number of timed updates
+ * (count_host[CPAL_NSTAGES]) since the last reset; reset != 0 clears them. */
+cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *count_host,
+                                    int32_t reset);
+
+/* Text of the last error on this context (never NULL). */
+const char *cp_arls_lev_last_error(const cpal_ctx *ctx);
+
+/* Free everything the library allocated for the context (synchronizes). */
+void cp_arls_lev_destroy(cpal_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CP_ARLS_LEV_H */

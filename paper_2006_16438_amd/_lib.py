@@ -1,0 +1,93 @@
+"""ctypes binding of the C ABI in ``include/cp_arls_lev.h``.
+
+Argument marshalling only: every step of a mode update runs in the HIP
+library ``libcpal.so``.  PyTorch provides device memory and the stream.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpal.so")
+
+CPAL_OK, CPAL_E_ARG, CPAL_E_NOMEM, CPAL_E_DEVICE, CPAL_E_STATE = 0, 1, 2, 3, 4
+CPAL_F64, CPAL_F32, CPAL_BF16 = 0, 1, 2
+FLAG_PINV, FLAG_DETCAP, FLAG_DET_TRUNC, FLAG_PDET_ONE, FLAG_DRAWCAP, FLAG_OVERFLOW, FLAG_STATE = (
+    1, 2, 4, 8, 16, 32, 64)
+
+# every extern "C" symbol declared in include/cp_arls_lev.h
+SYMBOLS = (
+    "cp_arls_lev_init", "cp_arls_lev_mode_update", "cp_arls_lev_fit_estimate",
+    "cp_arls_lev_samples", "cp_arls_lev_leverage", "cp_arls_lev_refresh",
+    "cp_arls_lev_get_step", "cp_arls_lev_set_step", "cp_arls_lev_set_timing",
+    "cp_arls_lev_stage_times", "cp_arls_lev_last_error", "cp_arls_lev_destroy",
+)
+STAGES = ("sample", "rows", "gather", "solve", "leverage")
+
+
+class cpal_tensor(C.Structure):
+    _fields_ = [("order", C.c_int32), ("dims", C.POINTER(C.c_int64)), ("nnz", C.c_int64),
+                ("coords", C.c_void_p), ("values", C.c_void_p), ("value_dtype", C.c_int32)]
+
+
+class cpal_options(C.Structure):
+    _fields_ = [("rank", C.c_int32), ("samples", C.c_int64), ("tau", C.c_double),
+                ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("gather_dtype", C.c_int32),
+                ("fit_samples", C.c_int64), ("fit_nnz_fraction", C.c_double),
+                ("det_enum_cap", C.c_int64)]
+
+
+class cpal_mode_stats(C.Structure):
+    _fields_ = [("s_det", C.c_int64), ("s_rnd", C.c_int64), ("s_bar", C.c_int64),
+                ("draws", C.c_int64), ("gathered_nnz", C.c_int64), ("p_det", C.c_double),
+                ("flags", C.c_int32), ("pad", C.c_int32)]
+
+
+STATS_BYTES = C.sizeof(cpal_mode_stats)
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libcpal.so and declare the C signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    L = C.CDLL(path)
+    P = C.POINTER
+    vp = C.c_void_p
+    L.cp_arls_lev_init.argtypes = [P(cpal_tensor), P(cpal_options), P(vp), vp, P(vp)]
+    L.cp_arls_lev_init.restype = C.c_int
+    L.cp_arls_lev_mode_update.argtypes = [vp, C.c_int32, vp]
+    L.cp_arls_lev_mode_update.restype = C.c_int
+    L.cp_arls_lev_fit_estimate.argtypes = [vp, vp]
+    L.cp_arls_lev_fit_estimate.restype = C.c_int
+    L.cp_arls_lev_samples.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
+    L.cp_arls_lev_samples.restype = C.c_int
+    L.cp_arls_lev_leverage.argtypes = [vp, C.c_int32, vp]
+    L.cp_arls_lev_leverage.restype = C.c_int
+    L.cp_arls_lev_refresh.argtypes = [vp, C.c_int32]
+    L.cp_arls_lev_refresh.restype = C.c_int
+    L.cp_arls_lev_get_step.argtypes = [vp, P(C.c_uint64)]
+    L.cp_arls_lev_get_step.restype = C.c_int
+    L.cp_arls_lev_set_step.argtypes = [vp, C.c_uint64]
+    L.cp_arls_lev_set_step.restype = C.c_int
+    L.cp_arls_lev_set_timing.argtypes = [vp, C.c_int32]
+    L.cp_arls_lev_set_timing.restype = C.c_int
+    L.cp_arls_lev_stage_times.argtypes = [vp, P(C.c_double), P(C.c_int64), C.c_int32]
+    L.cp_arls_lev_stage_times.restype = C.c_int
+    L.cp_arls_lev_last_error.argtypes = [vp]
+    L.cp_arls_lev_last_error.restype = C.c_char_p
+    L.cp_arls_lev_destroy.argtypes = [vp]
+    L.cp_arls_lev_destroy.restype = None
+    _lib = L
+    return L
+
+
+class CpalError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"cp_arls_lev error {code}: {msg}")
+        self.code = code

@@ -1,0 +1,679 @@
+// Host runtime behind the C ABI of include/cp_arls_lev.h: validation, device
+// memory, the per-mode fiber indexes built at init and the kernel sequence of
+// one mode update.  Every stage runs on the context's stream; no count is
+// read back to the host during an update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cpal_common.h"
+
+namespace cpal {
+void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_blk, int R,
+                       Decomp *out, int *flag_or, double *gram_tmp, hipStream_t s);
+int gather_tile_rows(i64 nk, int R, bool f64);
+void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
+                         const uint2 *pairs, const int *ik, const double *v64, const void *zhat,
+                         void *P, void *M, i64 nk, int G, hipStream_t s);
+int lev_row_blocks(i64 n);
+void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
+                  void *scratch, hipStream_t s);
+void launch_det_cand(const OtherModes &om, double tau, u64 cap, DevState *st, int *cand,
+                     hipStream_t s);
+void launch_det_enum(const OtherModes &om, double tau, DevState *st, const int *cand,
+                     u64 *det_keys, u64 det_cap, hipStream_t s);
+void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, double *det_p,
+                       double *kept_p, double *psum, u64 det_cap, i64 s, u64 *samp_idx,
+                       hipStream_t st_);
+void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
+                 unsigned char *bpos, unsigned *chunk_cnt, int grid, hipStream_t s);
+void launch_chunk_scan(DevState *st, const unsigned *chunk_cnt, u64 *chunk_off,
+                       const unsigned char *bpos, hipStream_t s);
+void launch_compact(const DevState *st, const u64 *buf, const unsigned *chunk_cnt,
+                    const u64 *chunk_off, u64 *keys, int grid, hipStream_t s);
+void launch_unique_mark(const DevState *st, const u64 *keys, i64 cap, unsigned *flag,
+                        hipStream_t s);
+void launch_unique_scatter(const DevState *st, const u64 *keys, i64 cap, const unsigned *flag,
+                           const u64 *upos, u64 *ukey, u64 *ustart, hipStream_t s);
+void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
+                 double *samp_om, double *samp_w, const u64 *ukey, const u64 *ustart,
+                 const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
+                 unsigned *flen, double *gpart, void *M, i64 mlen, hipStream_t s);
+int rows_blocks(i64 cap);
+void launch_gather(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
+                   const uint2 *pairs, const int *ik, const double *v64, const void *zhat, void *M,
+                   int grid, hipStream_t s);
+void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, const Decomp *dc,
+                       double *A, float *A32, hipStream_t s);
+void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s);
+void launch_to_f32(const double *a, float *b, i64 n, hipStream_t s);
+void launch_mode_keys(const int *coords, i64 nnz, int D, const OtherModes &om, i64 nk, u64 *comp,
+                      unsigned *ids, int *err, hipStream_t s);
+void launch_fiber_mark(const u64 *comp, i64 nnz, i64 nk, unsigned *flag, int *err,
+                       hipStream_t s);
+void launch_fiber_starts(const unsigned *flag, const u64 *fid, i64 nnz, unsigned *fstart,
+                         hipStream_t s);
+void launch_hash_build(const u64 *comp, i64 nnz, i64 nk, const unsigned *fstart, u64 nfib,
+                       FiberSlot *slots, u64 nslots, int hshift, hipStream_t s);
+void launch_mode_pairs(const u64 *comp, const unsigned *ids, i64 nnz, i64 nk, const void *vals,
+                       int vdt, uint2 *pairs, int *ik32, double *v64, hipStream_t s);
+struct FullModes {
+  int D;
+  i64 n[CPAL_MAXORDER];
+  u64 stride[CPAL_MAXORDER];
+  const double *A[CPAL_MAXORDER];
+};
+void fit_build_set(const int *coords, i64 nnz, const FullModes &fm, u64 *set, u64 nslots,
+                   int shift, hipStream_t s);
+void fit_draw(const int *coords, const void *vals, int vdt, i64 nnz, const FullModes &fm, i64 n_nz,
+              i64 n_z, u64 seed, u64 stream_id, const u64 *set, u64 nslots, int shift, u64 *ctl,
+              u64 *buf, unsigned *chunk_cnt, int *sc, i64 ld, double *sx, hipStream_t s);
+void fit_norm(const void *vals, int vdt, i64 nnz, double *part, DevState *st, hipStream_t s);
+void fit_eval(const FullModes &fm, int R, i64 n_nz, i64 n_fit, double phi_nz, double phi_z,
+              const int *sc, i64 ld, const double *sx, double *part, const DevState *st,
+              double *fit_out, hipStream_t s);
+}  // namespace cpal
+
+using namespace cpal;
+
+namespace {
+
+int bits_for(u64 n) {  // bits needed to hold values in [0, n)
+  int b = 0;
+  while (b < 64 && (n - 1) >> b) ++b;
+  return std::max(b, 1);
+}
+
+struct Mode {
+  i64 n = 0;
+  u64 Nk = 1;
+  int key_bits = 1;
+  double *A = nullptr;
+  float *A32 = nullptr;
+  double *lev = nullptr;
+  u64 *w = nullptr;
+  u64 *C = nullptr;
+  double *q = nullptr;
+  FiberSlot *slots = nullptr;
+  u64 nslots = 0;
+  int hshift = 0;
+  u64 nfib = 0;
+  uint2 *pairs = nullptr;
+  int *ik = nullptr;
+  double *v64 = nullptr;
+};
+
+}  // namespace
+
+struct cpal_ctx {
+  int D = 0;
+  i64 dims[CPAL_MAXORDER] = {0};
+  int R = 0;
+  i64 s = 0;
+  double tau = 1.0;
+  u64 seed = 0, stream_id = 0;
+  bool f64 = true;
+  i64 nnz = 0;
+  u64 enum_cap = 1ull << 26;
+  hipStream_t stream = nullptr;
+  u64 t = 0;
+  bool failed = false;
+  std::string err;
+  std::vector<void *> allocs;
+  Mode mode[CPAL_MAXORDER];
+  // scratch
+  DevState *st = nullptr;
+  Decomp *dc = nullptr;
+  double *lev_part = nullptr;
+  u64 *lev_bsum = nullptr;
+  int *cand = nullptr;
+  i64 cand_off[CPAL_MAXORDER] = {0};
+  u64 det_cap = 0;
+  u64 *det_keys = nullptr, *det_tmp = nullptr;
+  double *det_p = nullptr, *kept_p = nullptr, *psum = nullptr;
+  u64 *dbuf = nullptr;
+  unsigned char *dpos = nullptr;
+  unsigned *chunk_cnt = nullptr;
+  u64 *chunk_off = nullptr;
+  i64 max_chunks = 0;
+  u64 *keys = nullptr, *keys_tmp = nullptr;
+  unsigned *uflag = nullptr;
+  u64 *upos = nullptr, *ukey = nullptr, *ustart = nullptr;
+  u64 *samp_idx = nullptr;
+  double *samp_om = nullptr, *samp_w = nullptr;
+  void *zhat = nullptr;
+  unsigned *foff = nullptr, *flen = nullptr;
+  u64 *fpos = nullptr;
+  double *gpart = nullptr;
+  void *M = nullptr;
+  void *sort_scratch = nullptr;
+  void *scan_scratch = nullptr;
+  int draw_grid = 1024;
+  int gather_grid = 2048;
+  int tile_grid = 256;          // workgroups per row tile of the shared-memory gather
+  void *Ppart = nullptr;        // their partial accumulators
+  double *gram_tmp = nullptr;
+  // fit sample (Sec. 6.4)
+  i64 fit_nz = 0, fit_n = 0, fit_ld = 0;
+  double phi_nz = 0.0, phi_z = 0.0;
+  int *fit_sc = nullptr;
+  double *fit_x = nullptr;
+  double *fit_part = nullptr;
+  int fit_flags = 0;
+  // stage timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_rec;
+
+  hipEvent_t take_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+  }
+  hipEvent_t stage_begin() {
+    if (!timing) return nullptr;
+    hipEvent_t e = take_event();
+    hipEventRecord(e, stream);
+    return e;
+  }
+  void stage_end(int stage, hipEvent_t b) {
+    if (!timing || !b) return;
+    hipEvent_t e = take_event();
+    hipEventRecord(e, stream);
+    ev_rec.push_back({stage, {b, e}});
+  }
+
+  template <typename T>
+  T *alloc(size_t count) {
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (hipMalloc(&p, bytes) != hipSuccess) throw cpal_status(CPAL_E_NOMEM);
+    allocs.push_back(p);
+    return (T *)p;
+  }
+  void release() {
+    for (void *p : allocs) hipFree(p);
+    allocs.clear();
+    for (auto &r : ev_rec) { hipEventDestroy(r.second.first); hipEventDestroy(r.second.second); }
+    ev_rec.clear();
+    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+    ev_pool.clear();
+  }
+};
+
+namespace {
+
+cpal_status fail(cpal_ctx *c, cpal_status code, const char *msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+FullModes full_modes(const cpal_ctx *c) {
+  FullModes fm;
+  std::memset(&fm, 0, sizeof(fm));
+  fm.D = c->D;
+  u64 stride = 1;
+  for (int m = 0; m < c->D; ++m) {
+    fm.n[m] = c->dims[m];
+    fm.stride[m] = stride;
+    stride *= (u64)c->dims[m];
+    fm.A[m] = c->mode[m].A;
+  }
+  return fm;
+}
+
+OtherModes others_of(const cpal_ctx *c, int k) {
+  OtherModes om;
+  std::memset(&om, 0, sizeof(om));
+  om.k = k;
+  u64 stride = 1;
+  for (int m = 0; m < c->D; ++m) {
+    if (m == k) continue;
+    const int u = om.d++;
+    om.mode[u] = m;
+    om.n[u] = c->dims[m];
+    om.stride[u] = stride;
+    stride *= (u64)c->dims[m];
+    om.q[u] = c->mode[m].q;
+    om.C[u] = c->mode[m].C;
+    om.A[u] = c->mode[m].A;
+    om.A32[u] = c->mode[m].A32;
+    om.cand_off[u] = c->cand_off[m];
+  }
+  return om;
+}
+
+// Leverage of mode m from the current factor (Def. 3.4), cached.
+void refresh_leverage(cpal_ctx *c, int m) {
+  Mode &md = c->mode[m];
+  launch_lev_gram_partial(md.A, md.n, c->R, c->lev_part, c->stream);
+  const int nblk = (int)((md.n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
+  launch_decomp(c->lev_part, nblk, c->R, c->dc, &c->st->lev_pinv[m], c->stream);
+  launch_lev_rows(md.A, md.n, c->R, c->dc, md.lev, md.w, c->lev_bsum, c->stream);
+  launch_lev_cdf(md.w, md.n, c->lev_bsum, md.C, md.q, nullptr, c->stream);
+}
+
+cpal_status check_hip(cpal_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return CPAL_OK;
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+  c->err = buf;
+  c->failed = true;
+  return CPAL_E_DEVICE;
+}
+
+void build_index(cpal_ctx *c, int k, const cpal_tensor *X, u64 *comp, unsigned *ids, u64 *comp_t,
+                 unsigned *ids_t, unsigned *flag, u64 *fid, unsigned *fstart, void *sscratch,
+                 void *cscratch, int *err_dev, u64 *nfib_dev) {
+  const i64 nnz = c->nnz;
+  Mode &md = c->mode[k];
+  OtherModes om = others_of(c, k);
+  launch_mode_keys(X->coords, nnz, c->D, om, md.n, comp, ids, err_dev, c->stream);
+  u64 full = 1;
+  for (int m = 0; m < c->D; ++m) full *= (u64)c->dims[m];
+  sort_keys(comp, ids, comp_t, ids_t, sscratch, nnz, nullptr, nnz, bits_for(full), c->stream);
+  launch_fiber_mark(comp, nnz, md.n, flag, err_dev, c->stream);
+  scan_u32_to_u64(flag, fid, nnz, nfib_dev, cscratch, c->stream);
+  launch_fiber_starts(flag, fid, nnz, fstart, c->stream);
+  u64 nfib = 0;
+  hipMemcpyAsync(&nfib, nfib_dev, sizeof(u64), hipMemcpyDeviceToHost, c->stream);
+  hipStreamSynchronize(c->stream);
+  md.nfib = nfib;
+  u64 ns = 64;
+  while (ns < 2 * nfib) ns <<= 1;
+  int lg = 0;
+  while ((1ull << lg) < ns) ++lg;
+  md.nslots = ns;
+  md.hshift = 64 - lg;
+  md.slots = c->alloc<FiberSlot>(ns);
+  launch_hash_build(comp, nnz, md.n, fstart, nfib, md.slots, ns, md.hshift, c->stream);
+  if (c->f64) {
+    md.ik = c->alloc<int>(nnz);
+    md.v64 = c->alloc<double>(nnz);
+  } else {
+    md.pairs = c->alloc<uint2>(nnz);
+  }
+  launch_mode_pairs(comp, ids, nnz, md.n, X->values, X->value_dtype, md.pairs, md.ik, md.v64,
+                    c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
+                             double *const *factors, void *hip_stream, cpal_ctx **out) {
+  if (!out) return CPAL_E_ARG;
+  *out = nullptr;
+  if (!X || !opt || !factors) return CPAL_E_ARG;
+  if (X->order < 2 || X->order > CPAL_MAXORDER || !X->dims || !X->coords || !X->values)
+    return CPAL_E_ARG;
+  if (X->nnz < 1 || X->nnz >= (1ll << 32)) return CPAL_E_ARG;
+  if (X->value_dtype != CPAL_F32 && X->value_dtype != CPAL_F64) return CPAL_E_ARG;
+  if (opt->rank < 1 || opt->rank > CPAL_MAXR || opt->samples < 1) return CPAL_E_ARG;
+  if (opt->samples > (1ll << 28)) return CPAL_E_ARG;
+  if (!(opt->tau >= 0.0 && opt->tau <= 1.0)) return CPAL_E_ARG;
+  if (opt->gather_dtype != CPAL_F64 && opt->gather_dtype != CPAL_F32) return CPAL_E_ARG;
+  if (opt->det_enum_cap < 0 || opt->det_enum_cap > (1ll << 31)) return CPAL_E_ARG;
+  if (opt->fit_samples < 0) return CPAL_E_ARG;
+  long double fulld = 1;
+  for (int m = 0; m < X->order; ++m) {
+    if (X->dims[m] < 1 || X->dims[m] > (1ll << 31) - 1) return CPAL_E_ARG;
+    if (!factors[m]) return CPAL_E_ARG;
+    fulld *= (long double)X->dims[m];
+  }
+  if (fulld >= 4611686018427387904.0L) return CPAL_E_ARG;  // 2^62
+  u64 full = 1;
+  for (int m = 0; m < X->order; ++m) full *= (u64)X->dims[m];
+
+  cpal_ctx *c = new cpal_ctx();
+  c->D = X->order;
+  for (int m = 0; m < c->D; ++m) c->dims[m] = X->dims[m];
+  c->R = opt->rank;
+  c->s = opt->samples;
+  c->tau = opt->tau;
+  c->seed = opt->seed;
+  c->stream_id = opt->stream_id;
+  c->f64 = opt->gather_dtype == CPAL_F64;
+  c->nnz = X->nnz;
+  c->enum_cap = opt->det_enum_cap ? (u64)opt->det_enum_cap : (1ull << 26);
+  c->stream = (hipStream_t)hip_stream;
+  try {
+    const int R = c->R;
+    const i64 s = c->s;
+    i64 maxn = 0, sumn = 0;
+    for (int m = 0; m < c->D; ++m) {
+      Mode &md = c->mode[m];
+      md.n = c->dims[m];
+      md.A = factors[m];
+      u64 Nk = 1;
+      for (int o = 0; o < c->D; ++o) if (o != m) Nk *= (u64)c->dims[o];
+      md.Nk = Nk;
+      md.key_bits = bits_for(Nk);
+      md.A32 = c->alloc<float>((size_t)md.n * R);
+      md.lev = c->alloc<double>(md.n);
+      md.w = c->alloc<u64>(md.n);
+      md.C = c->alloc<u64>(md.n);
+      md.q = c->alloc<double>(md.n);
+      c->cand_off[m] = sumn;
+      sumn += md.n;
+      maxn = std::max(maxn, md.n);
+    }
+    c->st = c->alloc<DevState>(1);
+    hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream);
+    c->dc = c->alloc<Decomp>(1);
+    const int np = R * (R + 1) / 2;
+    c->lev_part = c->alloc<double>((size_t)((maxn + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS) * np);
+    c->lev_bsum = c->alloc<u64>(lev_row_blocks(maxn) + 1);
+    c->cand = c->alloc<int>(sumn);
+    c->det_cap = 4 * (u64)s + 4096;
+    c->det_keys = c->alloc<u64>(c->det_cap);
+    c->det_tmp = c->alloc<u64>(c->det_cap);
+    c->det_p = c->alloc<double>(c->det_cap);
+    c->kept_p = c->alloc<double>(s);
+    c->psum = c->alloc<double>(c->det_cap / 256 + 2);
+    const i64 max_draws = 64 * s + (1ll << 20);
+    c->max_chunks = (max_draws + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK;
+    c->dbuf = c->alloc<u64>((size_t)c->max_chunks * CPAL_DRAW_CHUNK);
+    c->dpos = c->alloc<unsigned char>((size_t)c->max_chunks * CPAL_DRAW_CHUNK);
+    c->chunk_cnt = c->alloc<unsigned>(c->max_chunks);
+    c->chunk_off = c->alloc<u64>(c->max_chunks);
+    c->keys = c->alloc<u64>(s);
+    c->keys_tmp = c->alloc<u64>(s);
+    c->uflag = c->alloc<unsigned>(s);
+    c->upos = c->alloc<u64>(s);
+    c->ukey = c->alloc<u64>(s);
+    c->ustart = c->alloc<u64>(s + 1);
+    c->samp_idx = c->alloc<u64>(s);
+    c->samp_om = c->alloc<double>(s);
+    c->samp_w = c->alloc<double>(s);
+    const size_t tsz = c->f64 ? sizeof(double) : sizeof(float);
+    c->zhat = c->alloc<char>((size_t)s * R * tsz);
+    c->foff = c->alloc<unsigned>(s);
+    c->flen = c->alloc<unsigned>(s);
+    c->fpos = c->alloc<u64>(s + 1);
+    c->gpart = c->alloc<double>((size_t)rows_blocks(s) * np);
+    c->M = c->alloc<char>((size_t)maxn * R * tsz);
+    c->Ppart = c->alloc<char>((size_t)c->tile_grid * maxn * R * tsz);
+    c->gram_tmp = c->alloc<double>(np);
+    const i64 sort_cap = std::max<i64>((i64)c->det_cap, c->nnz);
+    c->sort_scratch = c->alloc<char>(sort_scratch_bytes(sort_cap, true));
+    c->scan_scratch = c->alloc<char>(scan_scratch_bytes(std::max<i64>(sort_cap, s)));
+
+    // per-mode fiber indexes (Sec. 6.3)
+    const i64 nnz = c->nnz;
+    u64 *comp = nullptr, *comp_t = nullptr, *fid = nullptr, *nfib_dev = nullptr;
+    unsigned *ids = nullptr, *ids_t = nullptr, *flag = nullptr, *fstart = nullptr;
+    int *err_dev = nullptr;
+    std::vector<void *> tmp;
+    auto talloc = [&](size_t bytes) {
+      void *p = nullptr;
+      if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+        for (void *q : tmp) hipFree(q);
+        throw cpal_status(CPAL_E_NOMEM);
+      }
+      tmp.push_back(p);
+      return p;
+    };
+    comp = (u64 *)talloc(sizeof(u64) * nnz);
+    comp_t = (u64 *)talloc(sizeof(u64) * nnz);
+    fid = (u64 *)talloc(sizeof(u64) * nnz);
+    ids = (unsigned *)talloc(sizeof(unsigned) * nnz);
+    ids_t = (unsigned *)talloc(sizeof(unsigned) * nnz);
+    flag = (unsigned *)talloc(sizeof(unsigned) * nnz);
+    fstart = (unsigned *)talloc(sizeof(unsigned) * nnz);
+    nfib_dev = (u64 *)talloc(sizeof(u64));
+    err_dev = (int *)talloc(sizeof(int));
+    hipMemsetAsync(err_dev, 0, sizeof(int), c->stream);
+    for (int k = 0; k < c->D; ++k)
+      build_index(c, k, X, comp, ids, comp_t, ids_t, flag, fid, fstart, c->sort_scratch,
+                  c->scan_scratch, err_dev, nfib_dev);
+    int err_host = 0;
+    hipMemcpyAsync(&err_host, err_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    // ||X||^2 (uses fid as scratch for the block partials)
+    fit_norm(X->values, X->value_dtype, nnz, (double *)fid, c->st, c->stream);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    for (void *q : tmp) hipFree(q);
+    tmp.clear();
+    if (e == hipSuccess && !err_host && opt->fit_samples > 0) {
+      // stratified fit sample, drawn once (Sec. 6.4)
+      const double alpha = opt->fit_nnz_fraction;
+      if (!(alpha >= 0.0 && alpha <= 1.0)) throw cpal_status(CPAL_E_ARG);
+      const i64 n_nz = (i64)std::ceil(alpha * (double)opt->fit_samples);
+      i64 n_z = (i64)std::floor((1.0 - alpha) * (double)opt->fit_samples);
+      const u64 zeros = (u64)full - (u64)nnz;
+      if (zeros == 0) n_z = 0;
+      c->fit_ld = n_nz + n_z;
+      c->fit_nz = n_nz;
+      c->phi_nz = n_nz ? (double)nnz / (double)n_nz : 0.0;
+      c->phi_z = n_z ? (double)zeros / (double)n_z : 0.0;
+      c->fit_sc = c->alloc<int>((size_t)c->D * std::max<i64>(c->fit_ld, 1));
+      c->fit_x = c->alloc<double>(std::max<i64>(c->fit_ld, 1));
+      c->fit_part = c->alloc<double>(c->fit_ld / 256 + 2);
+      u64 ns = 64;
+      while (ns < 2 * (u64)nnz) ns <<= 1;
+      int lg = 0;
+      while ((1ull << lg) < ns) ++lg;
+      const i64 zd = 64 * n_z + (1ll << 20);
+      const i64 zchunks = (zd + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK;
+      u64 *set = (u64 *)talloc(sizeof(u64) * ns);
+      u64 *ctl = (u64 *)talloc(sizeof(u64) * 4);
+      u64 *zbuf = (u64 *)talloc(sizeof(u64) * (size_t)zchunks * CPAL_DRAW_CHUNK);
+      unsigned *zcnt = (unsigned *)talloc(sizeof(unsigned) * zchunks);
+      hipMemsetAsync(ctl, 0, sizeof(u64) * 4, c->stream);
+      const FullModes fm = full_modes(c);
+      fit_build_set(X->coords, nnz, fm, set, ns, 64 - lg, c->stream);
+      fit_draw(X->coords, X->values, X->value_dtype, nnz, fm, n_nz, n_z, c->seed, c->stream_id,
+               set, ns, 64 - lg, ctl, zbuf, zcnt, c->fit_sc, c->fit_ld, c->fit_x, c->stream);
+      u64 got = 0;
+      if (n_z > 0) hipMemcpyAsync(&got, ctl + 2, sizeof(u64), hipMemcpyDeviceToHost, c->stream);
+      e = hipStreamSynchronize(c->stream);
+      for (void *q : tmp) hipFree(q);
+      tmp.clear();
+      c->fit_n = n_nz + (i64)got;
+      if ((i64)got < n_z) c->fit_flags |= CPAL_FLAG_DRAWCAP;
+    }
+    if (e != hipSuccess) {
+      cpal_status st = check_hip(c, e, "init (fiber index)");
+      c->release();
+      delete c;
+      return st;
+    }
+    if (err_host) {
+      c->release();
+      delete c;
+      return CPAL_E_ARG;  // coordinate out of range (1) or duplicate coordinate (2)
+    }
+    // mirrors and leverage of every initial factor (Alg. 3 setup)
+    for (int m = 0; m < c->D; ++m) {
+      launch_to_f32(c->mode[m].A, c->mode[m].A32, c->mode[m].n * R, c->stream);
+      refresh_leverage(c, m);
+    }
+    std::vector<u64> W(c->D, 0);
+    for (int m = 0; m < c->D; ++m)
+      hipMemcpyAsync(&W[m], c->mode[m].C + (c->mode[m].n - 1), sizeof(u64), hipMemcpyDeviceToHost,
+                     c->stream);
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      cpal_status st = check_hip(c, e, "init (leverage)");
+      c->release();
+      delete c;
+      return st;
+    }
+    for (int m = 0; m < c->D; ++m) {
+      if (W[m] == 0) {
+        c->release();
+        delete c;
+        return CPAL_E_STATE;
+      }
+    }
+  } catch (cpal_status st) {
+    c->release();
+    delete c;
+    return st;
+  }
+  *out = c;
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *stats_dev) {
+  if (!c) return CPAL_E_ARG;
+  if (k < 0 || k >= c->D) return fail(c, CPAL_E_ARG, "mode out of range");
+  if (c->failed) return fail(c, CPAL_E_STATE, "context failed earlier");
+  hipStream_t s = c->stream;
+  Mode &md = c->mode[k];
+  const OtherModes om = others_of(c, k);
+  const int R = c->R;
+  // SkrpLev (Alg. 1): deterministic rows
+  hipEvent_t tb = c->stage_begin();
+  launch_det_cand(om, c->tau, c->enum_cap, c->st, c->cand, s);
+  if (c->tau < 1.0) {
+    launch_det_enum(om, c->tau, c->st, c->cand, c->det_keys, c->det_cap, s);
+    sort_keys(c->det_keys, nullptr, c->det_tmp, nullptr, c->sort_scratch, (i64)c->det_cap,
+              (const i64 *)&c->st->det_count, 0, md.key_bits, s);
+  }
+  launch_det_finish(om, c->st, c->det_keys, c->det_p, c->kept_p, c->psum, c->det_cap, c->s,
+                    c->samp_idx, s);
+  // random rows (Alg. 2) and combining repeats (Sec. 4.1, 4.3)
+  launch_draw(om, c->st, c->seed, c->stream_id, c->t, c->dbuf, c->dpos, c->chunk_cnt,
+              c->draw_grid, s);
+  launch_chunk_scan(c->st, c->chunk_cnt, c->chunk_off, c->dpos, s);
+  launch_compact(c->st, c->dbuf, c->chunk_cnt, c->chunk_off, c->keys, c->draw_grid, s);
+  sort_keys(c->keys, nullptr, c->keys_tmp, nullptr, c->sort_scratch, c->s,
+            &c->st->s_rnd_used, 0, md.key_bits, s);
+  launch_unique_mark(c->st, c->keys, c->s, c->uflag, s);
+  scan_u32_dev(c->uflag, c->upos, c->s, &c->st->s_rnd_used, (u64 *)&c->st->n_urnd,
+               c->scan_scratch, s);
+  launch_unique_scatter(c->st, c->keys, c->s, c->uflag, c->upos, c->ukey, c->ustart, s);
+  c->stage_end(CPAL_STAGE_SAMPLE, tb);
+  tb = c->stage_begin();
+  // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
+  launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->ukey, c->ustart,
+              md.slots, md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->M,
+              md.n * R, s);
+  scan_u32_dev(c->flen, c->fpos, c->s, &c->st->s_bar, (u64 *)&c->st->gathered, c->scan_scratch,
+               s);
+  c->stage_end(CPAL_STAGE_ROWS, tb);
+  tb = c->stage_begin();
+  {
+    const int tr = gather_tile_rows(md.n, R, c->f64);
+    const i64 ntiles = (md.n + tr - 1) / tr;
+    if (ntiles <= 4)
+      launch_gather_tiled(c->f64, c->st, R, c->fpos, c->foff, md.pairs, md.ik, md.v64, c->zhat,
+                          c->Ppart, c->M, md.n, c->tile_grid, s);
+    else
+      launch_gather(c->f64, c->st, R, c->fpos, c->foff, md.pairs, md.ik, md.v64, c->zhat, c->M,
+                    c->gather_grid, s);
+  }
+  c->stage_end(CPAL_STAGE_GATHER, tb);
+  // solve A_k = M G_s^{-1}, then the leverage of the new A_k
+  tb = c->stage_begin();
+  launch_decomp_dev(c->gpart, &c->st->s_bar, 128, R, c->dc, &c->st->flags, c->gram_tmp, s);
+  launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->dc, md.A, md.A32, s);
+  c->stage_end(CPAL_STAGE_SOLVE, tb);
+  tb = c->stage_begin();
+  refresh_leverage(c, k);
+  c->stage_end(CPAL_STAGE_LEVERAGE, tb);
+  if (stats_dev) launch_stats(c->st, k, c->D, stats_dev, s);
+  c->t += 1;
+  return check_hip(c, hipGetLastError(), "mode_update launch");
+}
+
+cpal_status cp_arls_lev_fit_estimate(cpal_ctx *c, double *fit_dev) {
+  if (!c || !fit_dev) return CPAL_E_ARG;
+  if (c->failed) return fail(c, CPAL_E_STATE, "context failed earlier");
+  if (c->fit_n <= 0) return fail(c, CPAL_E_STATE, "no fit sample (fit_samples = 0)");
+  fit_eval(full_modes(c), c->R, c->fit_nz, c->fit_n, c->phi_nz, c->phi_z, c->fit_sc, c->fit_ld,
+           c->fit_x, c->fit_part, c->st, fit_dev, c->stream);
+  return check_hip(c, hipGetLastError(), "fit_estimate launch");
+}
+
+cpal_status cp_arls_lev_samples(const cpal_ctx *c, uint64_t *idx_dev, double *omega_dev,
+                                double *w_dev, int64_t cap, int64_t *count_dev) {
+  if (!c || cap < 0) return CPAL_E_ARG;
+  const i64 n = std::min<i64>(cap, c->s);
+  // copy the full buffers up to cap; entries past s_bar are stale
+  if (idx_dev && n) hipMemcpyAsync(idx_dev, c->samp_idx, sizeof(u64) * n, hipMemcpyDeviceToDevice, c->stream);
+  if (omega_dev && n) hipMemcpyAsync(omega_dev, c->samp_om, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream);
+  if (w_dev && n) hipMemcpyAsync(w_dev, c->samp_w, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream);
+  if (count_dev) hipMemcpyAsync(count_dev, &c->st->s_bar, sizeof(i64), hipMemcpyDeviceToDevice, c->stream);
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_leverage(const cpal_ctx *c, int32_t m, double *lev_dev) {
+  if (!c || !lev_dev || m < 0 || m >= c->D) return CPAL_E_ARG;
+  hipMemcpyAsync(lev_dev, c->mode[m].lev, sizeof(double) * c->mode[m].n, hipMemcpyDeviceToDevice,
+                 c->stream);
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_refresh(cpal_ctx *c, int32_t m) {
+  if (!c || m < 0 || m >= c->D) return CPAL_E_ARG;
+  launch_to_f32(c->mode[m].A, c->mode[m].A32, c->mode[m].n * c->R, c->stream);
+  refresh_leverage(c, m);
+  return check_hip(c, hipGetLastError(), "refresh");
+}
+
+cpal_status cp_arls_lev_get_step(const cpal_ctx *c, uint64_t *t) {
+  if (!c || !t) return CPAL_E_ARG;
+  *t = c->t;
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_set_step(cpal_ctx *c, uint64_t t) {
+  if (!c) return CPAL_E_ARG;
+  c->t = t;
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_set_timing(cpal_ctx *c, int32_t enable) {
+  if (!c) return CPAL_E_ARG;
+  c->timing = enable != 0;
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_stage_times(cpal_ctx *c, double *ms, int64_t *count, int32_t reset) {
+  if (!c || !ms || !count) return CPAL_E_ARG;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return check_hip(c, e, "stage_times");
+  for (int i = 0; i < CPAL_NSTAGES; ++i) { ms[i] = 0.0; count[i] = 0; }
+  for (auto &r : c->ev_rec) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.second.first, r.second.second) == hipSuccess) {
+      ms[r.first] += (double)t;
+      count[r.first] += 1;
+    }
+  }
+  if (reset) {
+    for (auto &r : c->ev_rec) {
+      c->ev_pool.push_back(r.second.first);
+      c->ev_pool.push_back(r.second.second);
+    }
+    c->ev_rec.clear();
+  }
+  return CPAL_OK;
+}
+
+const char *cp_arls_lev_last_error(const cpal_ctx *c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+void cp_arls_lev_destroy(cpal_ctx *c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  c->release();
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+// Internal declarations of the gfx950 CP-ARLS-LEV library: device state,
+// per-update mode descriptors, device helpers and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cp_arls_lev.h"
+
+#define CPAL_MAXR 64
+#define CPAL_MAXORDER 8
+#define CPAL_GRAM_ROWS 256      // rows per block of the canonical Gram summation
+#define CPAL_DRAW_CHUNK 256     // draws per chunk of the persistent draw kernel
+
+typedef unsigned long long u64;
+typedef long long i64;
+
+// Scalars of one decomposition that kernels read and write on the device, so
+// that a whole mode update runs without reading counts back to the host.
+struct DevState {
+  u64 det_count;      // rows with p > tau found by the enumeration (atomic)
+  u64 combos;         // size of the candidate product set
+  i64 s_det;
+  i64 s_rnd;          // random rows requested
+  i64 s_rnd_used;     // accepted random draws used for the weights
+  i64 s_bar;          // rows of the sampled system
+  i64 n_urnd;         // unique random rows
+  i64 draws;
+  u64 chunk_next;     // next draw chunk (atomic ticket)
+  u64 accepted;       // accepted draws so far (atomic)
+  i64 nchunks;        // chunks handed out (a prefix of the chunk sequence)
+  i64 gathered;       // nnz of the sampled fibers
+  double p_det;
+  double tau_eff;     // 1.0 when the enumeration was skipped or capped
+  int flags;
+  int lev_flags;
+  i64 fit_nz;         // fit sample: nonzero entries
+  i64 fit_z;          // fit sample: zero entries (accepted)
+  u64 ncand[CPAL_MAXORDER];   // candidate rows per other mode (Sec. 5.3)
+  int lev_pinv[CPAL_MAXORDER];  // pseudo-inverse used for a mode's leverage
+  double fit;
+  double normX2;
+};
+
+// Symmetric R x R factorization: Cholesky, or eigen-decomposition when the
+// matrix is numerically singular.
+struct Decomp {
+  int pinv;
+  int R;
+  double etol;
+  double pad;
+  double L[CPAL_MAXR * CPAL_MAXR];
+  double V[CPAL_MAXR * CPAL_MAXR];
+  double lam[CPAL_MAXR];
+};
+
+// The other modes of an update (ascending), with their sampling vectors.
+struct OtherModes {
+  int d;
+  int k;
+  int mode[CPAL_MAXORDER];
+  i64 n[CPAL_MAXORDER];
+  u64 stride[CPAL_MAXORDER];
+  const double *q[CPAL_MAXORDER];
+  const u64 *C[CPAL_MAXORDER];
+  const double *A[CPAL_MAXORDER];
+  const float *A32[CPAL_MAXORDER];
+  i64 cand_off[CPAL_MAXORDER];
+};
+
+// One hash slot of a per-mode fiber index: complement key -> [off, off+len)
+// of the mode-sorted nonzeros.
+struct __attribute__((aligned(16))) FiberSlot {
+  u64 key;
+  unsigned off;
+  unsigned len;
+};
+#define CPAL_EMPTY_KEY (~0ull)
+
+// ------------------------------------------------------------ device helpers
+__device__ __forceinline__ void philox4x64_10(u64 c[4], u64 k0, u64 k1) {
+  // Salmon et al. SC'11: 10 rounds; S-box multipliers and Weyl key increments.
+  const u64 M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const u64 W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const u64 lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+    const u64 lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+    const u64 n0 = hi1 ^ c[1] ^ k0;
+    const u64 n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    k0 += W0; k1 += W1;
+  }
+}
+
+// floor(U * W / 2^128), U = u1 * 2^64 + u0.
+__device__ __forceinline__ u64 scale128(u64 u0, u64 u1, u64 W) {
+  const u64 a_hi = __umul64hi(u0, W);
+  const u64 b_lo = u1 * W, b_hi = __umul64hi(u1, W);
+  const u64 mid = b_lo + a_hi;
+  return b_hi + (mid < b_lo ? 1ull : 0ull);
+}
+
+// Smallest i in [0,n) with C[i] > v.
+__device__ __forceinline__ i64 upper_bound_u64(const u64 *__restrict__ C, i64 n, u64 v) {
+  i64 lo = 0, hi = n;
+  while (lo < hi) {
+    const i64 mid = (lo + hi) >> 1;
+    if (C[mid] > v) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// p of the KRP row encoded in lin (other modes ascending, first fastest):
+// product of the per-mode q in ascending mode order.
+__device__ __forceinline__ double prob_of(const OtherModes &om, u64 lin) {
+  double p = 0.0;
+  u64 rem = lin;
+  for (int u = 0; u < om.d; ++u) {
+    const u64 n = (u64)om.n[u];
+    const u64 i = rem % n;
+    rem /= n;
+    const double qv = om.q[u][i];
+    p = (u == 0) ? qv : p * qv;
+  }
+  return p;
+}
+
+// Multiplicative hash of a fiber key into a table of 2^(64-shift) slots.
+__device__ __forceinline__ u64 fiber_hash(u64 key, int shift) {
+  return (key * 0x9E3779B97F4A7C15ull) >> shift;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    T o = __shfl_up(v, off, 64);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide exclusive scan (blockDim.x multiple of 64, <= 1024); returns the
+// exclusive prefix of v and writes the block total to *total.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T *total) {
+  __shared__ T wsum[17];  // 16 wave slots + the block total
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  T inc = wave_incl_scan(v);
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    T x = lane < nw ? wsum[lane] : T(0);
+    T xi = wave_incl_scan(x);
+    if (lane < nw) wsum[lane] = xi - x;
+    if (lane == nw - 1) wsum[16] = xi;
+  }
+  __syncthreads();
+  T res = inc - v + wsum[wid];
+  *total = wsum[16];
+  __syncthreads();
+  return res;
+}
+
+// ------------------------------------------------------------ launchers
+namespace cpal {
+
+struct Sorter;   // radix sort scratch
+
+// leverage pipeline for one factor matrix (n x R) ---------------------------
+void launch_lev_gram_partial(const double *A, i64 n, int R, double *part, hipStream_t s);
+void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_store,
+                   hipStream_t s);
+void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *lev, u64 *w,
+                     u64 *blocksum, hipStream_t s);
+void launch_lev_cdf(const u64 *w, i64 n, const u64 *blocksum, u64 *C, double *q,
+                    int *flag_or, hipStream_t s);
+
+// radix sort of u64 keys with optional u32 payload, device-resident count --
+size_t sort_scratch_bytes(i64 cap, bool with_vals);
+void sort_keys(u64 *keys, unsigned *vals, u64 *tmp_keys, unsigned *tmp_vals, void *scratch,
+               i64 cap, const i64 *count_dev, i64 count_host, int bits, hipStream_t s);
+
+// generic exclusive scan of u32 -> u64 with total -----------------------------
+void scan_u32_to_u64(const unsigned *in, u64 *out, i64 n, u64 *total, void *scratch,
+                     hipStream_t s);
+size_t scan_scratch_bytes(i64 n);
+
+}  // namespace cpal

@@ -1,0 +1,576 @@
+// Sampled system of one mode update: KrpSamp (rows of the KRP as Hadamard
+// products of factor rows, eq. (2.1)), TnsrSamp (fibers of the sampled rows,
+// Sec. 6.3) and the weighted normal equations of the sketched problem
+// (eq. (1.2)):  G_s = sum_j omega_j z_j z_j^T (FP64),
+//               M(i_k,:) += omega_j x z_j  over every nonzero (i_k, x) of
+//               fiber j (gather precision T),
+//               A_k = M G_s^{-1}.
+// Also the per-mode fiber index built once at init: nonzeros sorted by
+// (complement key, i_k) and an open-addressing hash table key -> fiber.
+#include "cpal_common.h"
+
+namespace cpal {
+
+// ------------------------------------------------------------- sample rows --
+// One thread per row j of the sampled system (deterministic rows first, then
+// the combined random rows).  Computes omega_j, w_j, z_j (FP64), the weighted
+// row omega_j z_j in T, probes the fiber hash and adds the block's part of
+// G_s.  Also clears M.
+#define ROWS_BLK 128
+template <typename T>
+__global__ void __launch_bounds__(ROWS_BLK) k_rows(
+    OtherModes om, DevState *st, int R, u64 *__restrict__ samp_idx, double *__restrict__ samp_om,
+    double *__restrict__ samp_w, const u64 *__restrict__ ukey, const u64 *__restrict__ ustart,
+    const FiberSlot *__restrict__ slots, u64 hmask, int hshift, T *__restrict__ zhat,
+    unsigned *__restrict__ foff, unsigned *__restrict__ flen, double *__restrict__ gpart,
+    T *__restrict__ M, i64 mlen) {
+  extern __shared__ double sz[];           // ROWS_BLK x (R+1)
+  __shared__ double som[ROWS_BLK];
+  const int tid = threadIdx.x;
+  const int ld = R + 1;
+  const i64 s_det = st->s_det, n_urnd = st->n_urnd, s_used = st->s_rnd_used;
+  const i64 s_bar = s_det + n_urnd;
+  const double p_det = st->p_det;
+  if (blockIdx.x == 0 && tid == 0) st->s_bar = s_bar;
+  for (i64 e = (i64)blockIdx.x * blockDim.x + tid; e < mlen; e += (i64)gridDim.x * blockDim.x)
+    M[e] = T(0);
+  const i64 j = (i64)blockIdx.x * ROWS_BLK + tid;
+  double omj = 0.0;
+  double *z = sz + tid * ld;
+  if (j < s_bar) {
+    u64 lin;
+    double wj;
+    if (j < s_det) {
+      lin = samp_idx[j];
+      omj = 1.0;
+      wj = 1.0;
+    } else {
+      const i64 u = j - s_det;
+      lin = ukey[u];
+      const u64 end = (u + 1 < n_urnd) ? ustart[u + 1] : (u64)s_used;
+      const double c = (double)(end - ustart[u]);
+      const double p = prob_of(om, lin);
+      omj = (c * (1.0 - p_det)) / ((double)s_used * p);
+      wj = sqrt(omj);
+    }
+    samp_idx[j] = lin;
+    samp_om[j] = omj;
+    samp_w[j] = wj;
+    i64 im[CPAL_MAXORDER];
+    u64 rem = lin;
+    for (int u = 0; u < om.d; ++u) {
+      im[u] = (i64)(rem % (u64)om.n[u]);
+      rem /= (u64)om.n[u];
+    }
+    for (int r = 0; r < R; ++r) {
+      double v = om.A[0][im[0] * R + r];
+      for (int u = 1; u < om.d; ++u) v = v * om.A[u][im[u] * R + r];
+      z[r] = v;
+      zhat[j * R + r] = (T)(omj * v);
+    }
+    u64 h = fiber_hash(lin, hshift);
+    unsigned off = 0, len = 0;
+    for (;;) {
+      const FiberSlot sl = slots[h];
+      if (sl.key == lin) { off = sl.off; len = sl.len; break; }
+      if (sl.key == CPAL_EMPTY_KEY) break;
+      h = (h + 1) & hmask;
+    }
+    foff[j] = off;
+    flen[j] = len;
+  } else {
+    for (int r = 0; r < R; ++r) z[r] = 0.0;
+  }
+  som[tid] = omj;
+  __syncthreads();
+  const int rows = (int)max((i64)0, min((i64)ROWS_BLK, s_bar - (i64)blockIdx.x * ROWS_BLK));
+  const int np = R * (R + 1) / 2;
+  for (int p = tid; p < np; p += ROWS_BLK) {
+    int a = 0, c = p;
+    while (c >= R - a) { c -= R - a; ++a; }
+    c += a;
+    double acc = 0.0;
+    for (int r = 0; r < rows; ++r) acc = acc + (som[r] * sz[r * ld + a]) * sz[r * ld + c];
+    gpart[(i64)blockIdx.x * np + p] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ gather --
+// The sampled fibers form one stream of nnz(X~) = sum_j len_j nonzeros; wave
+// w takes stream positions [64c, 64c+64) for c = w, w + #waves, ...  A lane
+// finds its row j in a 64-entry window of the fiber prefix sums (shuffles),
+// loads its (i_k, x) pair and the wave then adds x * omega_j z_j into
+// M(i_k,:), two nonzeros per instruction when R <= 32 (lanes = columns).
+template <typename T>
+struct NzLoad;
+template <>
+struct NzLoad<float> {
+  const uint2 *pairs;
+  __device__ __forceinline__ void get(u64 e, int &ik, float &x) const {
+    const uint2 v = pairs[e];
+    ik = (int)v.x;
+    x = __uint_as_float(v.y);
+  }
+};
+template <>
+struct NzLoad<double> {
+  const int *ik;
+  const double *val;
+  __device__ __forceinline__ void get(u64 e, int &i, double &x) const {
+    i = ik[e];
+    x = val[e];
+  }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
+                                                const u64 *__restrict__ fpos,
+                                                const unsigned *__restrict__ foff, NzLoad<T> nz,
+                                                const T *__restrict__ zhat, T *__restrict__ M) {
+  const i64 total = st->gathered;
+  const i64 s_bar = st->s_bar;
+  const int lane = threadIdx.x & 63;
+  const i64 gw = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const i64 nw = ((i64)gridDim.x * blockDim.x) >> 6;
+  const bool half = R <= 32;
+  const int col = half ? (lane & 31) : lane;
+  const int sub = half ? (lane >> 5) : 0;
+  for (i64 start = gw * 64; start < total; start += nw * 64) {
+    // last row j0 with fpos[j0] <= start
+    i64 lo = 0, hi = s_bar;
+    while (lo < hi) {
+      const i64 mid = (lo + hi) >> 1;
+      if (fpos[mid] > (u64)start) hi = mid; else lo = mid + 1;
+    }
+    const i64 j0 = lo - 1;
+    const u64 winv = (j0 + lane < s_bar) ? fpos[j0 + lane] : ~0ull;
+    const i64 p = start + lane;
+    const bool valid = p < total;
+    int wl = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      const int cand = wl + step;
+      const u64 v = __shfl(winv, cand < 64 ? cand : 63, 64);
+      if (cand < 64 && v <= (u64)p) wl = cand;
+    }
+    i64 j = j0 + wl;
+    u64 fp = __shfl(winv, wl, 64);
+    if (valid && wl == 63) {
+      // the row lies beyond the window: search the whole prefix array
+      i64 l2 = j0 + 63, h2 = s_bar;
+      while (l2 < h2) {
+        const i64 mid = (l2 + h2) >> 1;
+        if (fpos[mid] > (u64)p) h2 = mid; else l2 = mid + 1;
+      }
+      j = l2 - 1;
+      fp = fpos[j];
+    }
+    int ik = 0;
+    T x = T(0);
+    if (valid) nz.get((u64)foff[j] + (u64)(p - (i64)fp), ik, x);
+    for (int src = 0; src < 64; src += half ? 2 : 1) {
+      const int sl = src + sub;
+      const int ik_s = __shfl(ik, sl, 64);
+      const T x_s = __shfl(x, sl, 64);
+      const i64 j_s = __shfl(j, sl, 64);
+      const bool v_s = __shfl((int)valid, sl, 64) != 0;
+      if (v_s && col < R) unsafeAtomicAdd(&M[(i64)ik_s * R + col], x_s * zhat[j_s * R + col]);
+    }
+  }
+}
+
+// Gather with per-workgroup accumulation in shared memory.  The stream of
+// gathered nonzeros is cut into chunks of GT_CHUNK positions; workgroup g of
+// row tile y takes chunks g, g+G, ...  For a chunk the workgroup finds the
+// first and last sampled rows by two binary searches, stages their fiber
+// prefix sums in shared memory (GT_WIN entries) and every position finds its
+// row there.  Contributions x * omega_j z_j with i_k inside the tile go to a
+// shared accumulator (tile_rows x R) with shared-memory atomics; at the end
+// the workgroup writes its partial M tile to P[g] (no global atomics).  The
+// partials are summed by k_reduce_partials.
+#define GT_THREADS 512
+#define GT_PER_THREAD 4
+#define GT_CHUNK (GT_THREADS * GT_PER_THREAD)
+#define GT_WIN 4096
+template <typename T>
+__global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
+    const DevState *st, int R, const u64 *__restrict__ fpos, const unsigned *__restrict__ foff,
+    NzLoad<T> nz, const T *__restrict__ zhat, T *__restrict__ P, i64 nk, int tile_rows) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  u64 *win = (u64 *)smem_raw;                          // GT_WIN fiber prefix sums
+  T *acc = (T *)(smem_raw + sizeof(u64) * GT_WIN);      // tile_rows x R
+  __shared__ i64 sh_jlo, sh_jhi;
+  const i64 total = st->gathered;
+  const i64 s_bar = st->s_bar;
+  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
+  const int g = blockIdx.x, G = gridDim.x;
+  if (g >= nch) return;
+  const i64 r0 = (i64)blockIdx.y * tile_rows;
+  const int rows = (int)min((i64)tile_rows, nk - r0);
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int e = tid; e < rows * R; e += GT_THREADS) acc[e] = T(0);
+  const bool half = R <= 32;
+  const int col = half ? (lane & 31) : lane;
+  const int sub = half ? (lane >> 5) : 0;
+  for (i64 c = g; c < nch; c += G) {
+    const i64 base = c * GT_CHUNK;
+    const i64 last = min(total, base + GT_CHUNK) - 1;
+    if (tid == 0 || tid == 64) {
+      // last row j with fpos[j] <= position
+      const i64 pos = tid == 0 ? base : last;
+      i64 lo = 0, hi = s_bar;
+      while (lo < hi) {
+        const i64 mid = (lo + hi) >> 1;
+        if (fpos[mid] > (u64)pos) hi = mid; else lo = mid + 1;
+      }
+      if (tid == 0) sh_jlo = lo - 1; else sh_jhi = lo - 1;
+    }
+    __syncthreads();
+    const i64 jlo = sh_jlo, jhi = sh_jhi;
+    const i64 nwin = jhi - jlo + 1;
+    const bool in_win = nwin <= GT_WIN;
+    if (in_win)
+      for (i64 e = tid; e < nwin; e += GT_THREADS) win[e] = fpos[jlo + e];
+    __syncthreads();
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      const i64 p = base + (i64)u * GT_THREADS + tid;
+      const bool valid = p <= last;
+      i64 j = jlo;
+      u64 fp = 0;
+      int ik = 0;
+      T x = T(0);
+      if (valid) {
+        if (in_win) {
+          int lo = 0, hi = (int)nwin;   // last index with win[idx] <= p
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (win[mid] <= (u64)p) lo = mid; else hi = mid;
+          }
+          j = jlo + lo;
+          fp = win[lo];
+        } else {
+          i64 lo = jlo, hi = jhi + 1;
+          while (hi - lo > 1) {
+            const i64 mid = (lo + hi) >> 1;
+            if (fpos[mid] <= (u64)p) lo = mid; else hi = mid;
+          }
+          j = lo;
+          fp = fpos[lo];
+        }
+        nz.get((u64)foff[j] + (u64)(p - (i64)fp), ik, x);
+      }
+      const bool mine = valid && ik >= r0 && ik < r0 + rows;
+      for (int src = 0; src < 64; src += half ? 2 : 1) {
+        const int sl = src + sub;
+        const int ik_s = __shfl(ik, sl, 64);
+        const T x_s = __shfl(x, sl, 64);
+        const i64 j_s = __shfl(j, sl, 64);
+        const bool m_s = __shfl((int)mine, sl, 64) != 0;
+        if (m_s && col < R)
+          unsafeAtomicAdd(&acc[(i64)(ik_s - r0) * R + col], x_s * zhat[j_s * R + col]);
+      }
+    }
+    __syncthreads();
+  }
+  T *out = P + (i64)g * nk * R + r0 * R;
+  for (int e = tid; e < rows * R; e += GT_THREADS) out[e] = acc[e];
+}
+
+// M = sum over the workgroups that had work of their partials.
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduce_partials(const DevState *st, const T *__restrict__ P,
+                                                         i64 nkR, int G, T *__restrict__ M) {
+  const i64 total = st->gathered;
+  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
+  const int nwg = (int)min((i64)G, nch);
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < nkR; e += (i64)gridDim.x * blockDim.x) {
+    T a = T(0);
+    for (int g = 0; g < nwg; ++g) a += P[(i64)g * nkR + e];
+    M[e] = a;
+  }
+}
+
+// ------------------------------------------------------------------- solve --
+// A_k(i,:) = M(i,:) G_s^{-1}: forward and back substitution with the Cholesky
+// factor, or the pseudo-inverse from the eigendecomposition.  Rows are
+// independent; FP64 throughout.  Skipped when the update hit a state error.
+#define SOLVE_BLK 128
+template <typename T>
+__global__ void __launch_bounds__(SOLVE_BLK) k_solve_rows(const DevState *st, i64 n, int R,
+                                                          const T *__restrict__ M,
+                                                          const Decomp *__restrict__ dc,
+                                                          double *__restrict__ A,
+                                                          float *__restrict__ A32) {
+  extern __shared__ double sy[];   // SOLVE_BLK x (R+1)
+  if (st->flags & CPAL_FLAG_STATE) return;
+  const i64 i = (i64)blockIdx.x * SOLVE_BLK + threadIdx.x;
+  if (i >= n) return;
+  const int ld = R + 1;
+  double *y = sy + threadIdx.x * ld;
+  for (int r = 0; r < R; ++r) y[r] = (double)M[i * R + r];
+  if (!dc->pinv) {
+    const double *L = dc->L;
+    for (int j = 0; j < R; ++j) {
+      double v = y[j];
+      for (int p = 0; p < j; ++p) v = v - L[j * R + p] * y[p];
+      y[j] = v / L[j * R + j];
+    }
+    for (int j = R - 1; j >= 0; --j) {
+      double v = y[j];
+      for (int p = j + 1; p < R; ++p) v = v - L[p * R + j] * y[p];
+      y[j] = v / L[j * R + j];
+    }
+    for (int r = 0; r < R; ++r) {
+      A[i * R + r] = y[r];
+      A32[i * R + r] = (float)y[r];
+    }
+  } else {
+    const double *V = dc->V;
+    double c[CPAL_MAXR];
+    for (int j = 0; j < R; ++j) {
+      c[j] = 0.0;
+      if (!(dc->lam[j] > dc->etol)) continue;
+      double v = 0.0;
+      for (int p = 0; p < R; ++p) v = v + V[p * R + j] * y[p];
+      c[j] = v / dc->lam[j];
+    }
+    for (int r = 0; r < R; ++r) {
+      double v = 0.0;
+      for (int j = 0; j < R; ++j) {
+        if (!(dc->lam[j] > dc->etol)) continue;
+        v = v + c[j] * V[r * R + j];
+      }
+      A[i * R + r] = v;
+      A32[i * R + r] = (float)v;
+    }
+  }
+}
+
+__global__ void k_stats(const DevState *st, int k, int D, cpal_mode_stats *out) {
+  int fl = st->flags;
+  for (int m = 0; m < D; ++m)
+    if (m != k && st->lev_pinv[m]) fl |= CPAL_FLAG_PINV;
+  out->s_det = st->s_det;
+  out->s_rnd = st->s_rnd_used;
+  out->s_bar = st->s_bar;
+  out->draws = st->draws;
+  out->gathered_nnz = st->gathered;
+  out->p_det = st->p_det;
+  out->flags = fl;
+  out->pad = 0;
+}
+
+__global__ void k_to_f32(const double *__restrict__ a, float *__restrict__ b, i64 n) {
+  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+// ------------------------------------------------------------- fiber index --
+// comp = lin(other coords) * n_k + i_k; err bit 1 = coordinate out of range.
+__global__ void k_mode_keys(const int *__restrict__ coords, i64 nnz, int D, OtherModes om,
+                            i64 nk, u64 *__restrict__ comp, unsigned *__restrict__ ids,
+                            int *err) {
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (i64)gridDim.x * blockDim.x) {
+    u64 key = 0;
+    bool bad = false;
+    for (int u = 0; u < om.d; ++u) {
+      const int c = coords[(i64)om.mode[u] * nnz + e];
+      bad |= c < 0 || c >= om.n[u];
+      key += (u64)(unsigned)c * om.stride[u];
+    }
+    const int ck = coords[(i64)om.k * nnz + e];
+    bad |= ck < 0 || ck >= nk;
+    if (bad) atomicOr(err, 1);
+    comp[e] = key * (u64)nk + (u64)(unsigned)ck;
+    ids[e] = (unsigned)e;
+  }
+}
+
+// fiber starts; err bit 2 = duplicate coordinate
+__global__ void k_fiber_mark(const u64 *__restrict__ comp, i64 nnz, i64 nk,
+                             unsigned *__restrict__ flag, int *err) {
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (i64)gridDim.x * blockDim.x) {
+    unsigned f = 1;
+    if (e > 0) {
+      const u64 a = comp[e - 1], b = comp[e];
+      if (a == b) atomicOr(err, 2);
+      f = (a / (u64)nk) != (b / (u64)nk);
+    }
+    flag[e] = f;
+  }
+}
+
+__global__ void k_fiber_starts(const unsigned *__restrict__ flag, const u64 *__restrict__ fid,
+                               i64 nnz, unsigned *__restrict__ fstart) {
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (i64)gridDim.x * blockDim.x)
+    if (flag[e]) fstart[fid[e]] = (unsigned)e;
+}
+
+__global__ void k_hash_insert(const u64 *__restrict__ comp, i64 nnz, i64 nk,
+                              const unsigned *__restrict__ fstart, u64 nfib,
+                              FiberSlot *__restrict__ slots, u64 hmask, int hshift) {
+  for (u64 f = (u64)blockIdx.x * blockDim.x + threadIdx.x; f < nfib; f += (u64)gridDim.x * blockDim.x) {
+    const unsigned off = fstart[f];
+    const unsigned end = (f + 1 < nfib) ? fstart[f + 1] : (unsigned)nnz;
+    const u64 key = comp[off] / (u64)nk;
+    u64 h = fiber_hash(key, hshift);
+    for (;;) {
+      const u64 old = atomicCAS(&slots[h].key, CPAL_EMPTY_KEY, key);
+      if (old == CPAL_EMPTY_KEY) {
+        slots[h].off = off;
+        slots[h].len = end - off;
+        break;
+      }
+      h = (h + 1) & hmask;
+    }
+  }
+}
+
+__global__ void k_slots_clear(FiberSlot *__restrict__ slots, u64 n) {
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
+    slots[i].key = CPAL_EMPTY_KEY;
+    slots[i].off = 0;
+    slots[i].len = 0;
+  }
+}
+
+// mode-sorted nonzeros in the gather layout
+__global__ void k_mode_pairs(const u64 *__restrict__ comp, const unsigned *__restrict__ ids, i64 nnz,
+                             i64 nk, const void *__restrict__ vals, int vdt,
+                             uint2 *__restrict__ pairs, int *__restrict__ ik32,
+                             double *__restrict__ v64) {
+  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (i64)gridDim.x * blockDim.x) {
+    const unsigned id = ids[e];
+    const int ik = (int)(comp[e] % (u64)nk);
+    const double v = vdt == CPAL_F64 ? ((const double *)vals)[id] : (double)((const float *)vals)[id];
+    if (pairs) pairs[e] = make_uint2((unsigned)ik, __float_as_uint((float)v));
+    if (ik32) { ik32[e] = ik; v64[e] = v; }
+  }
+}
+
+// ------------------------------------------------------------- launchers ---
+static int grid_for(i64 n, int blk, int maxg = 8192) {
+  i64 g = (n + blk - 1) / blk;
+  if (g < 1) g = 1;
+  if (g > maxg) g = maxg;
+  return (int)g;
+}
+
+void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
+                 double *samp_om, double *samp_w, const u64 *ukey, const u64 *ustart,
+                 const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
+                 unsigned *flen, double *gpart, void *M, i64 mlen, hipStream_t s) {
+  const int nb = (int)((cap + ROWS_BLK - 1) / ROWS_BLK);
+  const size_t sh = sizeof(double) * (size_t)ROWS_BLK * (R + 1);
+  if (f64)
+    hipLaunchKernelGGL(k_rows<double>, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx,
+                       samp_om, samp_w, ukey, ustart, slots, hmask, hshift, (double *)zhat, foff,
+                       flen, gpart, (double *)M, mlen);
+  else
+    hipLaunchKernelGGL(k_rows<float>, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx,
+                       samp_om, samp_w, ukey, ustart, slots, hmask, hshift, (float *)zhat, foff,
+                       flen, gpart, (float *)M, mlen);
+}
+
+int rows_blocks(i64 cap) { return (int)((cap + ROWS_BLK - 1) / ROWS_BLK); }
+
+// Shared-memory plan of the tiled gather: rows per tile and tile count.
+#define GT_LDS_BUDGET (120 * 1024)
+int gather_tile_rows(i64 nk, int R, bool f64) {
+  const size_t elem = f64 ? sizeof(double) : sizeof(float);
+  const size_t avail = GT_LDS_BUDGET - sizeof(u64) * GT_WIN;
+  i64 rows = (i64)(avail / (elem * (size_t)R));
+  return (int)std::min<i64>(rows, nk);
+}
+
+void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
+                         const uint2 *pairs, const int *ik, const double *v64, const void *zhat,
+                         void *P, void *M, i64 nk, int G, hipStream_t s) {
+  const int tr = gather_tile_rows(nk, R, f64);
+  const int ntiles = (int)((nk + tr - 1) / tr);
+  const size_t elem = f64 ? sizeof(double) : sizeof(float);
+  const size_t sh = sizeof(u64) * GT_WIN + elem * (size_t)tr * R;
+  const i64 nkR = nk * R;
+  const int rg = grid_for(nkR, 256, 4096);
+  if (f64) {
+    NzLoad<double> nz{ik, v64};
+    hipLaunchKernelGGL(k_gather_tile<double>, dim3(G, ntiles), dim3(GT_THREADS), sh, s, st, R, fpos,
+                       foff, nz, (const double *)zhat, (double *)P, nk, tr);
+    hipLaunchKernelGGL(k_reduce_partials<double>, dim3(rg), dim3(256), 0, s, st,
+                       (const double *)P, nkR, G, (double *)M);
+  } else {
+    NzLoad<float> nz{pairs};
+    hipLaunchKernelGGL(k_gather_tile<float>, dim3(G, ntiles), dim3(GT_THREADS), sh, s, st, R, fpos,
+                       foff, nz, (const float *)zhat, (float *)P, nk, tr);
+    hipLaunchKernelGGL(k_reduce_partials<float>, dim3(rg), dim3(256), 0, s, st, (const float *)P,
+                       nkR, G, (float *)M);
+  }
+}
+
+void launch_gather(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
+                   const uint2 *pairs, const int *ik, const double *v64, const void *zhat, void *M,
+                   int grid, hipStream_t s) {
+  if (f64) {
+    NzLoad<double> nz{ik, v64};
+    hipLaunchKernelGGL(k_gather<double>, dim3(grid), dim3(256), 0, s, st, R, fpos, foff, nz,
+                       (const double *)zhat, (double *)M);
+  } else {
+    NzLoad<float> nz{pairs};
+    hipLaunchKernelGGL(k_gather<float>, dim3(grid), dim3(256), 0, s, st, R, fpos, foff, nz,
+                       (const float *)zhat, (float *)M);
+  }
+}
+
+void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, const Decomp *dc,
+                       double *A, float *A32, hipStream_t s) {
+  const int nb = (int)((n + SOLVE_BLK - 1) / SOLVE_BLK);
+  const size_t sh = sizeof(double) * (size_t)SOLVE_BLK * (R + 1);
+  if (f64)
+    hipLaunchKernelGGL(k_solve_rows<double>, dim3(nb), dim3(SOLVE_BLK), sh, s, st, n, R,
+                       (const double *)M, dc, A, A32);
+  else
+    hipLaunchKernelGGL(k_solve_rows<float>, dim3(nb), dim3(SOLVE_BLK), sh, s, st, n, R,
+                       (const float *)M, dc, A, A32);
+}
+
+void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1), 0, s, st, k, D, out);
+}
+
+void launch_to_f32(const double *a, float *b, i64 n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, n);
+}
+
+void launch_mode_keys(const int *coords, i64 nnz, int D, const OtherModes &om, i64 nk, u64 *comp,
+                      unsigned *ids, int *err, hipStream_t s) {
+  hipLaunchKernelGGL(k_mode_keys, dim3(grid_for(nnz, 256)), dim3(256), 0, s, coords, nnz, D, om,
+                     nk, comp, ids, err);
+}
+
+void launch_fiber_mark(const u64 *comp, i64 nnz, i64 nk, unsigned *flag, int *err,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_fiber_mark, dim3(grid_for(nnz, 256)), dim3(256), 0, s, comp, nnz, nk, flag,
+                     err);
+}
+
+void launch_fiber_starts(const unsigned *flag, const u64 *fid, i64 nnz, unsigned *fstart,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_fiber_starts, dim3(grid_for(nnz, 256)), dim3(256), 0, s, flag, fid, nnz,
+                     fstart);
+}
+
+void launch_hash_build(const u64 *comp, i64 nnz, i64 nk, const unsigned *fstart, u64 nfib,
+                       FiberSlot *slots, u64 nslots, int hshift, hipStream_t s) {
+  hipLaunchKernelGGL(k_slots_clear, dim3(grid_for((i64)nslots, 256)), dim3(256), 0, s, slots,
+                     nslots);
+  hipLaunchKernelGGL(k_hash_insert, dim3(grid_for((i64)nfib, 256)), dim3(256), 0, s, comp, nnz,
+                     nk, fstart, nfib, slots, nslots - 1, hshift);
+}
+
+void launch_mode_pairs(const u64 *comp, const unsigned *ids, i64 nnz, i64 nk, const void *vals,
+                       int vdt, uint2 *pairs, int *ik32, double *v64, hipStream_t s) {
+  hipLaunchKernelGGL(k_mode_pairs, dim3(grid_for(nnz, 256)), dim3(256), 0, s, comp, ids, nnz, nk,
+                     vals, vdt, pairs, ik32, v64);
+}
+
+}  // namespace cpal

@@ -1,0 +1,333 @@
+// Leverage scores of a factor matrix (Def. 3.4) and its integer sampling
+// distribution (normalized leverage of Sec. 5.3 held as an integer CDF).
+//
+//   G = A^T A in blocks of 256 rows (rows ascending inside a block, blocks
+//   ascending), Cholesky G = L L^T column by column, l_i = ||L^{-1} a_i||^2;
+//   a pivot not above R*2^-52*max(diag G) switches to a Jacobi eigen-
+//   decomposition and l_i = a_i^T G^+ a_i.  w_i = floor(2^52 * l_i / R),
+//   C = inclusive prefix of w, q_i = w_i / W.
+//
+// Every multiply and add rounds separately (the library is built with
+// -ffp-contract=off), so these values are reproducible bit for bit.
+#include "cpal_common.h"
+
+namespace cpal {
+
+__device__ __forceinline__ void pair_of(int p, int R, int &a, int &c) {
+  int row = 0;
+  while (p >= R - row) { p -= R - row; ++row; }
+  a = row;
+  c = row + p;
+}
+
+// part[b][p]: sum over the rows of block b of A(r,a)*A(r,c), pair p = (a<=c).
+__global__ void __launch_bounds__(256) k_lev_gram_partial(const double *__restrict__ A, i64 n,
+                                                          int R, double *__restrict__ part) {
+  extern __shared__ double sA[];  // CPAL_GRAM_ROWS x R
+  const i64 r0 = (i64)blockIdx.x * CPAL_GRAM_ROWS;
+  const int rows = (int)min((i64)CPAL_GRAM_ROWS, n - r0);
+  for (int e = threadIdx.x; e < rows * R; e += blockDim.x) sA[e] = A[r0 * R + e];
+  __syncthreads();
+  const int np = R * (R + 1) / 2;
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    int a, c;
+    pair_of(p, R, a, c);
+    double acc = 0.0;
+    for (int r = 0; r < rows; ++r) acc = acc + sA[r * R + a] * sA[r * R + c];
+    part[(i64)blockIdx.x * np + p] = acc;
+  }
+}
+
+// Cyclic Jacobi eigendecomposition of the symmetric matrix S (R x R, shared
+// memory), one wavefront.  Pairs (p,q) are visited row by row; the rotation
+// for (p,q): theta = (S_qq - S_pp) / (2 S_pq), t = sign(theta) / (|theta| +
+// sqrt(theta^2 + 1)), c = 1/sqrt(t^2+1), s = t c; an entry with |S_pq| <=
+// 2^-53 sqrt|S_pp S_qq| is set to zero without rotating; stop after a sweep
+// without rotations or after 64 sweeps.  Every lane derives (t, c, s) from the
+// same three entries, then lane r updates row/column r of S and row r of V;
+// these updates touch disjoint entries, so the result equals the sequential
+// sweep element for element.
+__device__ void jacobi_wave(double *S, double *V, int R, Decomp *out) {
+  const int lane = threadIdx.x;
+  for (int e = lane; e < R * R; e += 64) V[e] = (e / R == e % R) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    bool any = false;
+    for (int p = 0; p + 1 < R; ++p) {
+      for (int q = p + 1; q < R; ++q) {
+        const double spq = S[p * R + q];
+        if (spq == 0.0) continue;
+        const double spp = S[p * R + p], sqq = S[q * R + q];
+        if (fabs(spq) <= 0x1p-53 * sqrt(fabs(spp * sqq))) {
+          __syncthreads();
+          if (lane == 0) { S[p * R + q] = 0.0; S[q * R + p] = 0.0; }
+          __syncthreads();
+          continue;
+        }
+        const double theta = (sqq - spp) / (2.0 * spq);
+        double t;
+        if (fabs(theta) > 0x1p500) {
+          t = 0.5 / theta;
+        } else {
+          t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+          if (theta < 0.0) t = -t;
+        }
+        const double c = 1.0 / sqrt(t * t + 1.0);
+        const double s = t * c;
+        __syncthreads();  // every lane has read S_pp, S_qq, S_pq
+        if (lane < R && lane != p && lane != q) {
+          const double x = S[lane * R + p], y = S[lane * R + q];
+          const double xp = c * x - s * y;
+          const double yq = s * x + c * y;
+          S[lane * R + p] = xp; S[p * R + lane] = xp;
+          S[lane * R + q] = yq; S[q * R + lane] = yq;
+        }
+        if (lane < R) {
+          const double x = V[lane * R + p], y = V[lane * R + q];
+          V[lane * R + p] = c * x - s * y;
+          V[lane * R + q] = s * x + c * y;
+        }
+        if (lane == 0) {
+          S[p * R + p] = spp - t * spq;
+          S[q * R + q] = sqq + t * spq;
+          S[p * R + q] = 0.0;
+          S[q * R + p] = 0.0;
+        }
+        __syncthreads();
+        any = true;
+      }
+    }
+    if (!any) break;
+  }
+  double mx = 0.0;
+  for (int j = 0; j < R; ++j) mx = fmax(mx, fabs(S[j * R + j]));
+  for (int e = lane; e < R * R; e += 64) out->V[e] = V[e];
+  if (lane < R) out->lam[lane] = S[lane * R + lane];
+  if (lane == 0) out->etol = ((double)R * 0x1p-52) * mx;
+}
+
+// Sum the block partials in block order into G, then factor G.  One block of
+// 64 threads (one wavefront); lane i owns row i during the Cholesky sweep.
+// nrows_dev (nullable) gives the number of partial blocks at run time as
+// ceil(*nrows_dev / rows_per_blk).  Partials are staged through shared
+// memory in slabs so that each pair's sum stays in block order.
+#define DECOMP_SLAB 4096
+__global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, int nblk,
+                                               const i64 *nrows_dev, int rows_per_blk, int R,
+                                               Decomp *__restrict__ out, int *flag_or,
+                                               int *flag_store) {
+  __shared__ double G[CPAL_MAXR * CPAL_MAXR];
+  __shared__ double L[CPAL_MAXR * CPAL_MAXR];
+  __shared__ double slab[DECOMP_SLAB];
+  __shared__ int fail;
+  const int lane = threadIdx.x;
+  if (nrows_dev) nblk = (int)((*nrows_dev + rows_per_blk - 1) / rows_per_blk);
+  const int np = R * (R + 1) / 2;
+  for (int p = lane; p < np; p += 64) G[p] = 0.0;   // running sums, packed by pair
+  const int per = max(1, DECOMP_SLAB / np);          // blocks per slab
+  for (int b0 = 0; b0 < nblk; b0 += per) {
+    const int nb = min(per, nblk - b0);
+    __syncthreads();
+    for (int e = lane; e < nb * np; e += 64) slab[e] = part[(i64)b0 * np + e];
+    __syncthreads();
+    for (int p = lane; p < np; p += 64) {
+      double tot = G[p];
+      for (int b = 0; b < nb; ++b) tot = tot + slab[b * np + p];
+      G[p] = tot;
+    }
+  }
+  __syncthreads();
+  // unpack the pair sums into the full symmetric matrix (L as staging)
+  for (int p = lane; p < np; p += 64) L[p] = G[p];
+  __syncthreads();
+  for (int p = lane; p < np; p += 64) {
+    int a, c;
+    pair_of(p, R, a, c);
+    G[a * R + c] = L[p];
+    G[c * R + a] = L[p];
+  }
+  __syncthreads();
+  for (int e = lane; e < R * R; e += 64) L[e] = 0.0;
+  if (lane == 0) fail = 0;
+  __syncthreads();
+  double maxdiag = 0.0;
+  for (int j = 0; j < R; ++j) maxdiag = fmax(maxdiag, G[j * R + j]);
+  const double tol = ((double)R * 0x1p-52) * maxdiag;
+  for (int j = 0; j < R; ++j) {
+    if (lane == 0) {
+      double v = G[j * R + j];
+      for (int p = 0; p < j; ++p) v = v - L[j * R + p] * L[j * R + p];
+      if (!(v > tol)) fail = 1;
+      else L[j * R + j] = sqrt(v);
+    }
+    __syncthreads();
+    if (fail) break;
+    const double ljj = L[j * R + j];
+    if (lane > j && lane < R) {
+      double u = G[lane * R + j];
+      for (int p = 0; p < j; ++p) u = u - L[lane * R + p] * L[j * R + p];
+      L[lane * R + j] = u / ljj;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (!fail) {
+    for (int e = lane; e < R * R; e += 64) out->L[e] = L[e];
+    if (lane == 0) {
+      out->pinv = 0;
+      out->R = R;
+      if (flag_store) *flag_store = 0;
+    }
+  } else {
+    jacobi_wave(G, L, R, out);
+    if (lane == 0) {
+      out->pinv = 1;
+      out->R = R;
+      if (flag_or) atomicOr(flag_or, CPAL_FLAG_PINV);
+      if (flag_store) *flag_store = 1;
+    }
+  }
+}
+
+// Parallel reduction of Gram partials (any order; used for the sampled G_s,
+// which is not part of the reproducible sampling state): out[p] = sum_b
+// part[b][p] for b < ceil(*nrows_dev / rows_per_blk).
+__global__ void __launch_bounds__(256) k_gram_reduce(const double *__restrict__ part,
+                                                     const i64 *nrows_dev, int rows_per_blk,
+                                                     int np, double *__restrict__ out) {
+  __shared__ double red[256];
+  const int nblk = (int)((*nrows_dev + rows_per_blk - 1) / rows_per_blk);
+  const int p = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) acc += part[(i64)b * np + p];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[p] = red[0];
+}
+
+// Per row: l_i, w_i; per block of 128 rows: sum of w.
+#define LEV_ROWS 128
+__global__ void __launch_bounds__(LEV_ROWS) k_lev_rows(const double *__restrict__ A, i64 n, int R,
+                                                      const Decomp *__restrict__ dc,
+                                                      double *__restrict__ lev,
+                                                      u64 *__restrict__ w,
+                                                      u64 *__restrict__ blocksum) {
+  extern __shared__ double sm[];
+  double *sL = sm;                       // R*R (L, or V)
+  double *sy = sm + R * R;               // LEV_ROWS x (R+1), padded rows
+  const int pinv = dc->pinv;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = pinv ? dc->V[e] : dc->L[e];
+  const i64 r0 = (i64)blockIdx.x * LEV_ROWS;
+  const int rows = (int)min((i64)LEV_ROWS, n - r0);
+  const int ld = R + 1;
+  for (int e = threadIdx.x; e < rows * R; e += blockDim.x) {
+    const int r = e / R, c = e - r * R;
+    sy[r * ld + c] = A[r0 * R + e];
+  }
+  __syncthreads();
+  u64 wi = 0;
+  if (threadIdx.x < rows) {
+    double *y = sy + threadIdx.x * ld;
+    double acc = 0.0;
+    if (!pinv) {
+      for (int j = 0; j < R; ++j) {
+        double v = y[j];
+        for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * y[p];
+        y[j] = v / sL[j * R + j];
+      }
+      for (int j = 0; j < R; ++j) acc = acc + y[j] * y[j];
+    } else {
+      const double etol = dc->etol;
+      for (int j = 0; j < R; ++j) {
+        const double lam = dc->lam[j];
+        if (!(lam > etol)) continue;
+        double t = 0.0;
+        for (int p = 0; p < R; ++p) t = t + sL[p * R + j] * y[p];
+        acc = acc + (t * t) / lam;
+      }
+    }
+    const double l = acc > 0.0 ? acc : 0.0;
+    lev[r0 + threadIdx.x] = l;
+    double v = l / (double)R;
+    if (!(v > 0.0)) v = 0.0;
+    if (v > 1.0) v = 1.0;
+    wi = (u64)(v * 0x1p52);
+    w[r0 + threadIdx.x] = wi;
+  }
+  u64 tot;
+  (void)block_excl_scan<u64>(wi, &tot);
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
+}
+
+// C = inclusive prefix of w, q = w / W.  Block b of LEV_ROWS rows.
+__global__ void __launch_bounds__(LEV_ROWS) k_lev_cdf(const u64 *__restrict__ w, i64 n,
+                                                     const u64 *__restrict__ blocksum, int nblk,
+                                                     u64 *__restrict__ C, double *__restrict__ q,
+                                                     int *flag_or) {
+  __shared__ u64 red[2][LEV_ROWS / 64];
+  u64 before = 0, all = 0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const u64 v = blocksum[b];
+    all += v;
+    if (b < (int)blockIdx.x) before += v;
+  }
+  before = wave_sum(before);
+  all = wave_sum(all);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = before; red[1][threadIdx.x >> 6] = all; }
+  __syncthreads();
+  before = 0; all = 0;
+  for (int i = 0; i < LEV_ROWS / 64; ++i) { before += red[0][i]; all += red[1][i]; }
+  const i64 i = (i64)blockIdx.x * LEV_ROWS + threadIdx.x;
+  const u64 wi = i < n ? w[i] : 0;
+  u64 tot;
+  const u64 ex = block_excl_scan<u64>(wi, &tot);
+  if (i < n) {
+    C[i] = before + ex + wi;
+    q[i] = all ? (double)wi / (double)all : 0.0;
+  }
+  if (i == 0 && all == 0 && flag_or) atomicOr(flag_or, CPAL_FLAG_STATE);
+}
+
+void launch_lev_gram_partial(const double *A, i64 n, int R, double *part, hipStream_t s) {
+  const int nblk = (int)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
+  const size_t sh = sizeof(double) * CPAL_GRAM_ROWS * R;
+  hipLaunchKernelGGL(k_lev_gram_partial, dim3(nblk), dim3(256), sh, s, A, n, R, part);
+}
+
+void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_store,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_decomp, dim3(1), dim3(64), 0, s, part, nblk, (const i64 *)nullptr, 1, R,
+                     out, (int *)nullptr, flag_store);
+}
+
+void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_blk, int R,
+                       Decomp *out, int *flag_or, double *gram_tmp, hipStream_t s) {
+  const int np = R * (R + 1) / 2;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(np), dim3(256), 0, s, part, nrows_dev, rows_per_blk, np,
+                     gram_tmp);
+  hipLaunchKernelGGL(k_decomp, dim3(1), dim3(64), 0, s, (const double *)gram_tmp, 1,
+                     (const i64 *)nullptr, 1, R, out, flag_or, (int *)nullptr);
+}
+
+void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *lev, u64 *w,
+                     u64 *blocksum, hipStream_t s) {
+  const int nblk = (int)((n + LEV_ROWS - 1) / LEV_ROWS);
+  const size_t sh = sizeof(double) * ((size_t)R * R + (size_t)LEV_ROWS * (R + 1));
+  hipLaunchKernelGGL(k_lev_rows, dim3(nblk), dim3(LEV_ROWS), sh, s, A, n, R, dc, lev, w,
+                     blocksum);
+}
+
+void launch_lev_cdf(const u64 *w, i64 n, const u64 *blocksum, u64 *C, double *q, int *flag_or,
+                    hipStream_t s) {
+  const int nblk = (int)((n + LEV_ROWS - 1) / LEV_ROWS);
+  hipLaunchKernelGGL(k_lev_cdf, dim3(nblk), dim3(LEV_ROWS), 0, s, w, n, blocksum, nblk, C, q,
+                     flag_or);
+}
+
+int lev_row_blocks(i64 n) { return (int)((n + LEV_ROWS - 1) / LEV_ROWS); }
+
+}  // namespace cpal

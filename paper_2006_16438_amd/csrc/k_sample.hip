@@ -1,0 +1,407 @@
+// SkrpLev on the device (Alg. 1): deterministic rows (Sec. 5.3), random rows
+// by per-mode draws (Lemma 5.3) with rejection of p > tau (Alg. 2), and the
+// bookkeeping of the combined rows (Sec. 4.1, 4.3).
+//
+// Canonical choices shared with the CPU reference by specification only:
+//  * p of a multi-index = product of the per-mode q in ascending mode order;
+//  * draw j of mode m at step t uses Philox4x64-10 with counter
+//    (j, m | k<<8, t, 0) and key (seed, stream_id); v = floor(U W_m / 2^128)
+//    with U = word1*2^64 + word0; the row is the smallest i with C_m(i) > v;
+//  * the random rows are the first s_rnd accepted draws in draw order;
+//  * the deterministic set is sorted by linear index; if it holds >= s rows
+//    the s most probable are kept (ties: smaller linear index);
+//  * p_det sums the kept p in linear-index order in blocks of 256.
+#include "cpal_common.h"
+
+namespace cpal {
+
+__device__ __forceinline__ double block_max_d(double v) {
+  __shared__ double red[16];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < nw; ++w) r = fmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v) {
+  __shared__ T red[16];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  T r = 0;
+  for (int w = 0; w < nw; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
+// Reset of the per-update state, maxima alpha_m, candidate lists (Sec. 5.3):
+// row i of mode o_t is a candidate iff the product with every other mode at
+// its maximum exceeds tau.  One block of 1024 threads.
+__global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u64 cap,
+                                                   DevState *st, int *__restrict__ cand) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    st->det_count = 0; st->combos = 0; st->s_det = 0; st->s_rnd = 0; st->s_rnd_used = 0;
+    st->s_bar = 0; st->n_urnd = 0; st->draws = 0; st->chunk_next = 0; st->accepted = 0;
+    st->nchunks = 0; st->gathered = 0; st->p_det = 0.0; st->tau_eff = 1.0; st->flags = 0;
+    for (int u = 0; u < CPAL_MAXORDER; ++u) st->ncand[u] = 0;
+  }
+  // a probability vector with no mass cannot be sampled: the update is void
+  __shared__ int bad;
+  if (tid == 0) {
+    bad = 0;
+    for (int u = 0; u < om.d; ++u) bad |= om.C[u][om.n[u] - 1] == 0;
+    if (bad) st->flags |= CPAL_FLAG_STATE;
+  }
+  __syncthreads();
+  if (bad || !(tau < 1.0)) return;
+  __shared__ double alpha[CPAL_MAXORDER];
+  for (int u = 0; u < om.d; ++u) {
+    double m = 0.0;
+    for (i64 i = tid; i < om.n[u]; i += blockDim.x) m = fmax(m, om.q[u][i]);
+    m = block_max_d(m);
+    if (tid == 0) alpha[u] = m;
+  }
+  __syncthreads();
+  double combos = 1.0;
+  u64 combos_u = 1;
+  for (int t = 0; t < om.d; ++t) {
+    const i64 n = om.n[t];
+    const double *q = om.q[t];
+    int *out = cand + om.cand_off[t];
+    u64 count = 0;
+    for (i64 base = 0; base < n; base += blockDim.x) {
+      const i64 i = base + tid;
+      unsigned pred = 0;
+      if (i < n) {
+        const double qi = q[i];
+        double b = (t == 0) ? qi : alpha[0];
+        for (int u = 1; u < om.d; ++u) b = b * ((u == t) ? qi : alpha[u]);
+        pred = b > tau;
+      }
+      unsigned tot;
+      const unsigned ex = block_excl_scan<unsigned>(pred, &tot);
+      if (pred) out[count + ex] = (int)i;
+      count += tot;
+    }
+    if (tid == 0) st->ncand[t] = count;
+    combos *= (double)count;
+    combos_u *= count;
+  }
+  if (tid == 0) {
+    if (combos > (double)cap) {
+      st->flags |= CPAL_FLAG_DETCAP;
+      st->combos = 0;
+      st->tau_eff = 1.0;
+    } else {
+      st->combos = combos_u;
+      st->tau_eff = tau;
+    }
+  }
+}
+
+// Enumerate the candidate product set; rows with p > tau are appended.
+__global__ void __launch_bounds__(256) k_det_enum(OtherModes om, double tau, DevState *st,
+                                                  const int *__restrict__ cand,
+                                                  u64 *__restrict__ det_keys, u64 det_cap) {
+  const u64 combos = st->combos;
+  if (combos == 0) return;
+  unsigned nc[CPAL_MAXORDER];
+  for (int u = 0; u < om.d; ++u) nc[u] = (unsigned)st->ncand[u];
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x; e < combos; e += stride) {
+    unsigned rem = (unsigned)e;
+    double p = 0.0;
+    u64 lin = 0;
+    for (int u = 0; u < om.d; ++u) {
+      const unsigned c = rem % nc[u];
+      rem /= nc[u];
+      const int i = cand[om.cand_off[u] + c];
+      const double qv = om.q[u][i];
+      p = (u == 0) ? qv : p * qv;
+      lin += (u64)i * om.stride[u];
+    }
+    if (p > tau) {
+      const u64 pos = atomicAdd(&st->det_count, 1ull);
+      if (pos < det_cap) det_keys[pos] = lin;
+    }
+  }
+}
+
+// Deterministic rows: truncation to the s most probable when needed, output
+// to samp_idx[0..s_det), p_det, s_rnd.  One block of 1024 threads.
+__global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st,
+                                                     const u64 *__restrict__ det_keys,
+                                                     double *__restrict__ det_p,
+                                                     double *__restrict__ kept_p,
+                                                     double *__restrict__ psum, u64 det_cap,
+                                                     i64 s, u64 *__restrict__ samp_idx,
+                                                     unsigned char *__restrict__ keep) {
+  const int tid = threadIdx.x;
+  if (st->flags & CPAL_FLAG_STATE) {
+    if (tid == 0) { st->s_det = 0; st->s_rnd = 0; st->p_det = 0.0; }
+    return;
+  }
+  const u64 cnt = st->det_count;
+  i64 n = (i64)min(cnt, det_cap);
+  if (tid == 0 && cnt > det_cap) st->flags |= CPAL_FLAG_OVERFLOW;
+  for (i64 i = tid; i < n; i += blockDim.x) det_p[i] = prob_of(om, det_keys[i]);
+  __syncthreads();
+  if (n >= s) {
+    // threshold theta: the largest bit pattern with #{p >= theta} >= s
+    u64 lo = 0, hi = 1ull << 63;
+    while (hi - lo > 1) {
+      const u64 mid = lo + (hi - lo) / 2;
+      u64 c = 0;
+      for (i64 i = tid; i < n; i += blockDim.x) c += (u64)(__double_as_longlong(det_p[i]) >= (i64)mid);
+      c = block_sum<u64>(c);
+      if (c >= (u64)s) lo = mid; else hi = mid;
+    }
+    const i64 theta = (i64)lo;
+    u64 gt = 0;
+    for (i64 i = tid; i < n; i += blockDim.x) gt += (u64)(__double_as_longlong(det_p[i]) > theta);
+    gt = block_sum<u64>(gt);
+    const u64 need = (u64)s - gt;
+    // first `need` rows equal to theta in linear-index order
+    u64 eq_seen = 0, out_pos = 0;
+    for (i64 base = 0; base < n; base += blockDim.x) {
+      const i64 i = base + tid;
+      i64 bits = 0;
+      unsigned is_eq = 0;
+      if (i < n) { bits = __double_as_longlong(det_p[i]); is_eq = bits == theta; }
+      unsigned eqtot;
+      const unsigned eq_ex = block_excl_scan<unsigned>(is_eq, &eqtot);
+      unsigned kp = 0;
+      if (i < n) kp = (bits > theta) || (is_eq && eq_seen + eq_ex < need);
+      unsigned ktot;
+      const unsigned k_ex = block_excl_scan<unsigned>(kp, &ktot);
+      if (kp) {
+        samp_idx[out_pos + k_ex] = det_keys[i];
+        kept_p[out_pos + k_ex] = det_p[i];
+      }
+      eq_seen += eqtot;
+      out_pos += ktot;
+    }
+    n = s;
+    if (tid == 0) st->flags |= CPAL_FLAG_DET_TRUNC;
+  } else {
+    for (i64 i = tid; i < n; i += blockDim.x) { samp_idx[i] = det_keys[i]; kept_p[i] = det_p[i]; }
+  }
+  __syncthreads();
+  const i64 nb = (n + 255) / 256;
+  for (i64 b = tid; b < nb; b += blockDim.x) {
+    double part = 0.0;
+    const i64 e = min(n, (b + 1) * 256);
+    for (i64 i = b * 256; i < e; ++i) part = part + kept_p[i];
+    psum[b] = part;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (i64 b = 0; b < nb; ++b) tot = tot + psum[b];
+    st->s_det = n;
+    st->p_det = tot;
+    i64 s_rnd = s - n;
+    if (s_rnd > 0 && !(1.0 - tot > 0x1p-40)) {
+      s_rnd = 0;
+      st->flags |= CPAL_FLAG_PDET_ONE;
+    }
+    st->s_rnd = s_rnd;
+    st->chunk_next = 0;
+    st->accepted = 0;
+  }
+  (void)keep;
+}
+
+__device__ __forceinline__ i64 max_draws_of(i64 s_rnd) { return 64 * s_rnd + (1ll << 20); }
+
+// Persistent draw kernel (Alg. 2): blocks take chunks of 256 consecutive
+// draws in increasing order while fewer than s_rnd draws were accepted, so
+// the processed chunks always form a prefix of the draw sequence.  Each
+// chunk's accepted rows are compacted in draw order.
+__global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 seed,
+                                              u64 stream_id, u64 t, u64 *__restrict__ buf,
+                                              unsigned char *__restrict__ bpos,
+                                              unsigned *__restrict__ chunk_cnt) {
+  __shared__ u64 sh_c;
+  __shared__ int stop;
+  const int tid = threadIdx.x;
+  const i64 s_rnd = st->s_rnd;
+  const double tau = st->tau_eff;
+  const i64 max_draws = max_draws_of(s_rnd);
+  const u64 max_chunks = (u64)((max_draws + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK);
+  u64 W[CPAL_MAXORDER];
+  for (int u = 0; u < om.d; ++u) W[u] = om.C[u][om.n[u] - 1];
+  for (;;) {
+    if (tid == 0) {
+      const u64 acc = __hip_atomic_load(&st->accepted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      stop = 0;
+      if ((i64)acc >= s_rnd) {
+        stop = 1;
+      } else {
+        const u64 c = atomicAdd(&st->chunk_next, 1ull);
+        if (c >= max_chunks) stop = 1; else sh_c = c;
+      }
+    }
+    __syncthreads();
+    if (stop) break;
+    const u64 c = sh_c;
+    const i64 j = (i64)c * CPAL_DRAW_CHUNK + tid;
+    unsigned ok = 0;
+    u64 lin = 0;
+    if (j < max_draws) {
+      double p = 0.0;
+      for (int u = 0; u < om.d; ++u) {
+        u64 ctr[4] = {(u64)j, (u64)om.mode[u] | ((u64)om.k << 8), t, 0ull};
+        philox4x64_10(ctr, seed, stream_id);
+        const u64 v = scale128(ctr[0], ctr[1], W[u]);
+        const i64 i = upper_bound_u64(om.C[u], om.n[u], v);
+        const double qv = om.q[u][i];
+        p = (u == 0) ? qv : p * qv;
+        lin += (u64)i * om.stride[u];
+      }
+      ok = p <= tau;
+    }
+    unsigned tot;
+    const unsigned ex = block_excl_scan<unsigned>(ok, &tot);
+    if (ok) {
+      buf[c * CPAL_DRAW_CHUNK + ex] = lin;
+      bpos[c * CPAL_DRAW_CHUNK + ex] = (unsigned char)tid;
+    }
+    if (tid == 0) {
+      chunk_cnt[c] = tot;
+      atomicAdd(&st->accepted, (u64)tot);
+    }
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of the chunk counts, the number of rows used, the draw
+// count (index of the s_rnd-th accepted draw + 1).  One block.
+__global__ void __launch_bounds__(1024) k_chunk_scan(DevState *st,
+                                                     const unsigned *__restrict__ chunk_cnt,
+                                                     u64 *__restrict__ chunk_off,
+                                                     const unsigned char *__restrict__ bpos) {
+  __shared__ i64 sh_draws;
+  const int tid = threadIdx.x;
+  const i64 s_rnd = st->s_rnd;
+  const i64 max_draws = max_draws_of(s_rnd);
+  const u64 max_chunks = (u64)((max_draws + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK);
+  const u64 Q = min(st->chunk_next, max_chunks);
+  if (tid == 0) sh_draws = -1;
+  u64 carry = 0;
+  for (u64 b0 = 0; b0 < Q; b0 += blockDim.x) {
+    const u64 b = b0 + tid;
+    const u64 v = b < Q ? chunk_cnt[b] : 0;
+    u64 tot;
+    const u64 ex = block_excl_scan<u64>(v, &tot);
+    if (b < Q) {
+      const u64 off = carry + ex;
+      chunk_off[b] = off;
+      if (s_rnd > 0 && off <= (u64)(s_rnd - 1) && (u64)(s_rnd - 1) < off + v)
+        sh_draws = (i64)b * CPAL_DRAW_CHUNK + bpos[b * CPAL_DRAW_CHUNK + (s_rnd - 1 - off)] + 1;
+    }
+    carry += tot;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    st->nchunks = (i64)Q;
+    if (s_rnd == 0) {
+      st->s_rnd_used = 0;
+      st->draws = 0;
+    } else if ((i64)carry < s_rnd) {
+      st->s_rnd_used = (i64)carry;
+      st->draws = max_draws;
+      st->flags |= CPAL_FLAG_DRAWCAP;
+    } else {
+      st->s_rnd_used = s_rnd;
+      st->draws = sh_draws;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_compact(const DevState *st, const u64 *__restrict__ buf,
+                                                 const unsigned *__restrict__ chunk_cnt,
+                                                 const u64 *__restrict__ chunk_off,
+                                                 u64 *__restrict__ keys) {
+  const i64 Q = st->nchunks;
+  const u64 used = (u64)st->s_rnd_used;
+  for (i64 q = blockIdx.x; q < Q; q += gridDim.x) {
+    const u64 off = chunk_off[q];
+    if (off >= used) continue;
+    const unsigned c = chunk_cnt[q];
+    if (threadIdx.x < c && off + threadIdx.x < used)
+      keys[off + threadIdx.x] = buf[(u64)q * CPAL_DRAW_CHUNK + threadIdx.x];
+  }
+}
+
+// Run starts of the sorted accepted rows.
+__global__ void __launch_bounds__(256) k_unique_mark(const DevState *st, const u64 *__restrict__ keys,
+                                                     i64 cap, unsigned *__restrict__ flag) {
+  const i64 n = st->s_rnd_used;
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cap) return;
+  flag[i] = (i < n) && (i == 0 || keys[i] != keys[i - 1]);
+}
+
+__global__ void __launch_bounds__(256) k_unique_scatter(const DevState *st,
+                                                        const u64 *__restrict__ keys, i64 cap,
+                                                        const unsigned *__restrict__ flag,
+                                                        const u64 *__restrict__ upos,
+                                                        u64 *__restrict__ ukey,
+                                                        u64 *__restrict__ ustart) {
+  const i64 n = st->s_rnd_used;
+  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cap || i >= n) return;
+  if (flag[i]) {
+    ukey[upos[i]] = keys[i];
+    ustart[upos[i]] = (u64)i;
+  }
+}
+
+void launch_det_cand(const OtherModes &om, double tau, u64 cap, DevState *st, int *cand,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_det_cand, dim3(1), dim3(1024), 0, s, om, tau, cap, st, cand);
+}
+void launch_det_enum(const OtherModes &om, double tau, DevState *st, const int *cand,
+                     u64 *det_keys, u64 det_cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_det_enum, dim3(1024), dim3(256), 0, s, om, tau, st, cand, det_keys,
+                     det_cap);
+}
+void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, double *det_p,
+                       double *kept_p, double *psum, u64 det_cap, i64 s, u64 *samp_idx,
+                       hipStream_t st_) {
+  hipLaunchKernelGGL(k_det_finish, dim3(1), dim3(1024), 0, st_, om, st, det_keys, det_p, kept_p,
+                     psum, det_cap, s, samp_idx, (unsigned char *)nullptr);
+}
+void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
+                 unsigned char *bpos, unsigned *chunk_cnt, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_draw, dim3(grid), dim3(256), 0, s, om, st, seed, stream_id, t, buf, bpos,
+                     chunk_cnt);
+}
+void launch_chunk_scan(DevState *st, const unsigned *chunk_cnt, u64 *chunk_off,
+                       const unsigned char *bpos, hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(1024), 0, s, st, chunk_cnt, chunk_off, bpos);
+}
+void launch_compact(const DevState *st, const u64 *buf, const unsigned *chunk_cnt,
+                    const u64 *chunk_off, u64 *keys, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(grid), dim3(256), 0, s, st, buf, chunk_cnt, chunk_off, keys);
+}
+void launch_unique_mark(const DevState *st, const u64 *keys, i64 cap, unsigned *flag,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_unique_mark, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, st,
+                     keys, cap, flag);
+}
+void launch_unique_scatter(const DevState *st, const u64 *keys, i64 cap, const unsigned *flag,
+                           const u64 *upos, u64 *ukey, u64 *ustart, hipStream_t s) {
+  hipLaunchKernelGGL(k_unique_scatter, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, st,
+                     keys, cap, flag, upos, ukey, ustart);
+}
+
+}  // namespace cpal

@@ -1,0 +1,91 @@
+"""Helpers shared by the GPU tests: build a library context and run the
+per-update parity protocol against the CPU oracle.
+
+Protocol (per mode update, identical inputs): the current device factors
+are copied to the host, the oracle runs the same update (same step t, seed,
+stream id) from those copies, then the device runs it.  Sample indices,
+omega and weights, the statistics and the cached leverage scores must match
+bit for bit; the new factor within a stated relative tolerance."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_ctx(T, fac, R, s, tau=None, gather="f64", seed=0, stream_id=0, det_cap=0,
+             fit_samples=0, values_f32=False):
+    from paper_2006_16438_amd.api import CpArlsLev
+    dev = torch.device("cuda:0")
+    coords = torch.from_numpy(np.ascontiguousarray(T.coords)).to(dev)
+    vals = torch.from_numpy(np.ascontiguousarray(T.values)).to(dev)
+    if values_f32:
+        vals = vals.float()
+    F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float64).copy()).to(dev) for f in fac]
+    ctx = CpArlsLev(T.dims, coords, vals, F, R, s, tau=tau, seed=seed, stream_id=stream_id,
+                    gather_dtype=gather, det_enum_cap=det_cap, fit_samples=fit_samples)
+    return ctx, F
+
+
+def rel_err(a, b):
+    den = max(np.max(np.abs(b)), 1e-300)
+    return float(np.max(np.abs(a - b)) / den)
+
+
+def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, stream_id=0,
+               det_cap=0, OT=None, check_lev=True, label=""):
+    """Returns the list of (oracle stats, device stats) per update."""
+    OT = OT or oracle.Tensor.from_synth(T)
+    ctx, F = make_ctx(T, fac, R, s, tau, gather, seed, stream_id, det_cap)
+    D = len(T.dims)
+    cap = det_cap if det_cap else (1 << 26)
+    out = []
+    for u in range(updates):
+        k = u % D
+        host = [f.cpu().numpy().copy() for f in F]
+        if check_lev:
+            for m in range(D):
+                ref_lev, _ = oracle.leverage(host[m])
+                got = ctx.leverage(m).cpu().numpy()
+                assert np.array_equal(got, ref_lev), f"{label} update {u}: leverage of mode {m} differs"
+        t = ctx.step
+        try:
+            ref = oracle.mode_update(OT, host, k, t, R, s, tau, seed, stream_id, cap)
+        except RuntimeError:
+            # an all-zero probability vector: the oracle rejects the update; the
+            # device flags it and leaves the factor unchanged
+            before = F[k].cpu().numpy().copy()
+            ctx.mode_update(k)
+            st = ctx.last_stats()
+            assert st["flags"] & 64 and st["s_bar"] == 0, f"{label} update {u}: state not flagged"
+            assert np.array_equal(F[k].cpu().numpy(), before)
+            out.append((None, st, 0.0))
+            continue
+        ctx.mode_update(k)
+        st = ctx.last_stats()
+        idx, om, w = ctx.samples_view()
+        idx = idx.cpu().numpy().view(np.uint64)
+        om = om.cpu().numpy()
+        w = w.cpu().numpy()
+        rs = ref["stats"]
+        for key in ("s_det", "s_rnd", "s_bar", "draws", "gathered_nnz", "flags"):
+            assert st[key] == rs[key], f"{label} update {u} (mode {k}): {key} {st[key]} != {rs[key]}"
+        assert np.float64(st["p_det"]).tobytes() == np.float64(rs["p_det"]).tobytes(), \
+            f"{label} update {u}: p_det {st['p_det']!r} != {rs['p_det']!r}"
+        assert np.array_equal(idx, ref["idx"]), f"{label} update {u}: sample indices differ"
+        assert np.array_equal(om, ref["omega"]), f"{label} update {u}: omega differs"
+        assert np.array_equal(w, ref["wgt"]), f"{label} update {u}: weights differ"
+        got = F[k].cpu().numpy()
+        err = rel_err(got, host[k])
+        assert err <= ftol, f"{label} update {u} (mode {k}): factor rel err {err:.3e} > {ftol:.1e}"
+        out.append((rs, st, err))
+    ctx.close()
+    return out

@@ -1,0 +1,211 @@
+"""GPU parity: the HIP mode update against the FP64 CPU oracle, per update
+with identical inputs (see gpu_util.run_parity).  Sample indices, omega,
+weights, statistics and leverage scores are compared bit for bit; factors
+within 1e-10 relative (max-norm) in FP64 gather mode, 1e-4 in FP32 mode."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_16438_amd import synth
+from tests.gpu_util import log, make_ctx, rel_err, run_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def concentrated(dims, R, seed):
+    rng = np.random.default_rng(seed)
+    fac = []
+    for n in dims:
+        A = rng.standard_normal((n, R)) * 0.05
+        hot = rng.choice(n, size=min(n, R), replace=False)
+        for j, h in enumerate(hot):
+            A[h, j % R] += 3.0 + j
+        fac.append(A)
+    return fac
+
+
+def test_small3_fp64_hybrid_ten_iterations():
+    """100x80x60, 20,000 nnz, R=5, s=1024, tau=1/s, 10 iterations, FP64."""
+    T, _, R = synth.small3(0)
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    log("small3 fp64 hybrid: 30 updates")
+    res = run_parity(T, fac, R, 1024, 1 / 1024, 30, "f64", 1e-10, label="small3")
+    assert all(r[0] is not None for r in res)
+    assert sum(r[0]["s_det"] for r in res) > 0, "hybrid sampling never found a deterministic row"
+
+
+def test_small3_fp32_gather():
+    T, _, R = synth.small3(0)
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    log("small3 fp32 gather: 9 updates")
+    run_parity(T, fac, R, 1024, 1 / 1024, 9, "f32", 1e-4, label="small3-f32")
+
+
+def test_small3_random_only():
+    T, _, R = synth.small3(0)
+    fac = synth.gaussian_factors(T.dims, R, 1)
+    log("small3 tau=1: 6 updates")
+    res = run_parity(T, fac, R, 1024, 1.0, 6, "f64", 1e-10, seed=5, stream_id=3, label="tau1")
+    assert all(r[0]["s_det"] == 0 and r[0]["draws"] == 1024 for r in res)
+
+
+def test_multi_tile_ragged():
+    """Several Gram blocks (700 = 2*256 + 188 rows), sort tiles, draw chunks."""
+    dims = (700, 300, 257)
+    T = synth.random_sparse(dims, 150_000, seed=21)
+    R = 8
+    fac = concentrated(dims, R, 22)
+    log("multi-tile 700x300x257: 6 updates")
+    run_parity(T, fac, R, 8192 + 77, 1 / 8192, 6, "f64", 1e-10, label="multitile")
+
+
+def test_rank_above_mode_size_uses_pinv():
+    """Uber shape with 200k nnz: mode 1 has 24 rows < R = 25, so its leverage
+    takes the pseudo-inverse path on both sides."""
+    T = synth.uber4(0, nnz=200_000)
+    R = 25
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    log("uber-shape 200k nnz R=25: 8 updates")
+    res = run_parity(T, fac, R, 1 << 14, 2.0 ** -14, 8, "f64", 1e-10, label="uber200k")
+    assert any(r[1]["flags"] & oracle.FLAG_PINV for r in res)
+
+
+def test_all_rows_matches_cp_als():
+    dims = (9, 7, 5)
+    T = synth.random_sparse(dims, 120, seed=7)
+    R = 3
+    fac = synth.gaussian_factors(dims, R, 8)
+    log("all rows (tau=0)")
+    res = run_parity(T, fac, R, 80, 0.0, 3, "f64", 1e-10, det_cap=1000, label="allrows")
+    for rs, st, _ in res:
+        assert rs is not None and st["flags"] & oracle.FLAG_PDET_ONE and st["s_rnd"] == 0
+
+
+def test_detcap_and_truncation():
+    dims = (12, 10, 9)
+    T = synth.random_sparse(dims, 300, seed=9)
+    R = 3
+    fac = concentrated(dims, R, 10)
+    log("det cap")
+    res = run_parity(T, fac, R, 64, 1e-6, 3, "f64", 1e-10, det_cap=5, label="detcap")
+    assert all(r[1]["flags"] & oracle.FLAG_DETCAP for r in res)
+    log("det truncation")
+    res = run_parity(T, fac, R, 16, 1e-9, 3, "f64", 1e-10, det_cap=100000, label="trunc")
+    assert all(r[1]["flags"] & oracle.FLAG_DET_TRUNC for r in res)
+
+
+@pytest.mark.parametrize("dims,R,s,nnz", [
+    ((40, 30), 4, 64, 500),          # order 2: the KRP is one factor
+    ((6, 5, 4, 3, 2), 2, 50, 200),   # order 5
+    ((50, 40, 30), 1, 256, 2000),    # R = 1
+    ((300, 200, 100), 64, 4096, 60_000),  # R = 64 (maximum)
+    ((20, 20, 20), 4, 1, 800),       # s = 1
+    ((20, 20, 20), 3, 32, 1),        # a single nonzero
+])
+def test_shapes_and_edges(dims, R, s, nnz):
+    T = synth.random_sparse(dims, nnz, seed=sum(dims) + R)
+    fac = synth.gaussian_factors(dims, R, R + s)
+    log(f"edge case dims={dims} R={R} s={s} nnz={nnz}")
+    run_parity(T, fac, R, s, 1.0 / s if s > 1 else 1.0, 2 * len(dims), "f64", 1e-9,
+               label=f"edge{dims}")
+
+
+def test_values_given_in_fp32():
+    T, _, R = synth.small3(3)
+    T.values = T.values.astype(np.float32).astype(np.float64)
+    fac = synth.gaussian_factors(T.dims, R, 3)
+    from paper_2006_16438_amd._lib import CpalError  # noqa: F401
+    log("fp32 input values")
+    OT = oracle.Tensor.from_synth(T)
+    ctx, F = make_ctx(T, fac, R, 512, values_f32=True)
+    host = [f.copy() for f in fac]
+    ref = oracle.mode_update(OT, host, 0, 0, R, 512)
+    ctx.mode_update(0)
+    assert np.array_equal(ctx.samples_view()[0].cpu().numpy().view(np.uint64), ref["idx"])
+    assert rel_err(F[0].cpu().numpy(), host[0]) < 1e-10
+    ctx.close()
+
+
+def test_init_errors():
+    import torch
+    from paper_2006_16438_amd._lib import CpalError
+    dims = (5, 4, 3)
+    T = synth.random_sparse(dims, 20, seed=1)
+    fac = synth.gaussian_factors(dims, 2, 1)
+    log("init errors")
+    # duplicate coordinate
+    T2 = synth.SparseTensor(dims, np.concatenate([T.coords, T.coords[:, :1]], axis=1),
+                            np.concatenate([T.values, T.values[:1]]))
+    with pytest.raises(CpalError) as e:
+        make_ctx(T2, fac, 2, 8)
+    assert e.value.code == 1
+    # coordinate out of range
+    T3 = synth.SparseTensor(dims, T.coords.copy(), T.values)
+    T3.coords[1, 0] = 4
+    with pytest.raises(CpalError) as e:
+        make_ctx(T3, fac, 2, 8)
+    assert e.value.code == 1
+    # all-zero factor
+    f0 = [f.copy() for f in fac]
+    f0[2][:] = 0
+    with pytest.raises(CpalError) as e:
+        make_ctx(T, f0, 2, 8)
+    assert e.value.code == 4
+    # bad options
+    with pytest.raises(CpalError):
+        make_ctx(T, fac, 2, 0)
+    with pytest.raises(CpalError):
+        make_ctx(T, fac, 2, 8, tau=1.5)
+    torch.cuda.synchronize()
+
+
+def test_uber4_full_size_fp32():
+    """The benchmark workload at full size: 183x24x1140x1717, 3.3e6 nnz,
+    R = 25, s = 2^17, tau = 2^-17, FP32 gather: one outer iteration."""
+    T = synth.uber4(0)
+    R = 25
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    log("uber4 full size fp32: 4 updates")
+    res = run_parity(T, fac, R, 1 << 17, 2.0 ** -17, 4, "f32", 1e-4, label="uber4")
+    for rs, st, err in res:
+        assert rs is not None
+        log(f"  s_bar={st['s_bar']} nnz(X~)={st['gathered_nnz']} err={err:.2e}")
+
+
+@pytest.mark.parametrize("which", ["small3", "uber4"])
+def test_fit_estimate_matches_oracle(which):
+    """Sec. 6.4 stratified estimate: the device draws the same sample as the
+    oracle (same Philox counters), so the estimates agree to rounding."""
+    if which == "small3":
+        T, _, R = synth.small3(0)
+        s_fit, s = 4096, 1024
+    else:
+        T = synth.uber4(0)
+        R, s_fit, s = 25, 1 << 20, 1 << 17
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    log(f"fit estimate {which} s_fit={s_fit}")
+    OT = oracle.Tensor.from_synth(T)
+    fs = oracle.FitSample(OT, s_fit, 0.5, seed=0, stream_id=0)
+    ctx, F = make_ctx(T, fac, R, s, gather="f32", fit_samples=s_fit)
+    for it in range(2):
+        host = [f.cpu().numpy().copy() for f in F]
+        ref = fs.estimate(host)
+        got = float(ctx.fit_estimate().item())
+        log(f"  fit gpu={got!r} oracle={ref!r}")
+        assert abs(got - ref) <= 1e-10 * max(1.0, abs(ref))
+        for k in range(len(T.dims)):
+            ctx.mode_update(k)
+    ctx.close()
+
+
+@pytest.mark.parametrize("gather", ["f64", "f32"])
+def test_large_mode_gather_paths(gather):
+    """Mode 0 with 5000 rows needs more than four shared-memory row tiles, so
+    its gather takes the global-atomic path; modes 1-2 use one tile."""
+    dims = (5000, 60, 50)
+    T = synth.random_sparse(dims, 300_000, seed=31)
+    R = 16
+    fac = concentrated(dims, R, 32)
+    log(f"large mode gather paths ({gather})")
+    run_parity(T, fac, R, 4096, 1 / 4096, 6, gather, 1e-10 if gather == "f64" else 1e-4,
+               label=f"large-{gather}")
