@@ -251,8 +251,47 @@ static void solve_row(const decomp *d, const double *m, double *x) {
   }
 }
 
+/* Fewer rows than columns (n < R): range(A) is all of R^n exactly when A has
+ * full row rank, and then every leverage score is 1 (Def. 3.4 with Q = I_n).
+ * Full row rank is decided by a Cholesky of K = A A^T (n x n, entries summed
+ * over the R columns in ascending order) with the same pivot test as for
+ * A^T A.  Returns 1 when that holds. */
+static int full_row_rank(const double *A, int64_t n, int32_t R) {
+  double K[MAXR * MAXR];
+  for (int i = 0; i < n; ++i) {
+    for (int j = i; j < n; ++j) {
+      double acc = 0.0;
+      for (int r = 0; r < R; ++r) acc = acc + A[(int64_t)i * R + r] * A[(int64_t)j * R + r];
+      K[i * n + j] = acc;
+      K[j * n + i] = acc;
+    }
+  }
+  double maxdiag = 0.0;
+  for (int j = 0; j < n; ++j) if (K[j * n + j] > maxdiag) maxdiag = K[j * n + j];
+  const double tol = ((double)n * 0x1p-52) * maxdiag;
+  double L[MAXR * MAXR];
+  memset(L, 0, sizeof(L));
+  for (int j = 0; j < n; ++j) {
+    double v = K[j * n + j];
+    for (int p = 0; p < j; ++p) v = v - L[j * n + p] * L[j * n + p];
+    if (!(v > tol)) return 0;
+    double ljj = sqrt(v);
+    L[j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double u = K[i * n + j];
+      for (int p = 0; p < j; ++p) u = u - L[i * n + p] * L[j * n + p];
+      L[i * n + j] = u / ljj;
+    }
+  }
+  return 1;
+}
+
 int32_t orc_leverage(const double *A, int64_t n, int32_t R, double *lev) {
   double G[MAXR * MAXR];
+  if (n < R && full_row_rank(A, n, R)) {
+    for (int64_t i = 0; i < n; ++i) lev[i] = 1.0;
+    return ORC_FLAG_PINV;   /* A^T A is singular */
+  }
   decomp *d = (decomp *)malloc(sizeof(decomp));
   orc_gram(A, n, R, G);
   factorize(G, R, d);

@@ -19,7 +19,7 @@ void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_bl
 int gather_tile_rows(i64 nk, int R, bool f64);
 void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
                          const uint2 *pairs, const int *ik, const double *v64, const void *zhat,
-                         void *P, void *M, i64 nk, int G, hipStream_t s);
+                         int ldz, void *P, void *M, i64 nk, int G, hipStream_t s);
 int lev_row_blocks(i64 n);
 void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
                   void *scratch, hipStream_t s);
@@ -43,11 +43,11 @@ void launch_unique_scatter(const DevState *st, const u64 *keys, i64 cap, const u
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
                  double *samp_om, double *samp_w, const u64 *ukey, const u64 *ustart,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
-                 unsigned *flen, double *gpart, void *M, i64 mlen, hipStream_t s);
+                 unsigned *flen, double *gpart, void *M, i64 mlen, int ldz, hipStream_t s);
 int rows_blocks(i64 cap);
 void launch_gather(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
                    const uint2 *pairs, const int *ik, const double *v64, const void *zhat, void *M,
-                   int grid, hipStream_t s);
+                   int ldz, int grid, hipStream_t s);
 void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, const Decomp *dc,
                        double *A, float *A32, hipStream_t s);
 void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s);
@@ -156,6 +156,7 @@ struct cpal_ctx {
   int draw_grid = 1024;
   int gather_grid = 2048;
   int tile_grid = 256;          // workgroups per row tile of the shared-memory gather
+  int ldz = 0;                  // row stride of the weighted KRP rows (16-byte multiple)
   void *Ppart = nullptr;        // their partial accumulators
   double *gram_tmp = nullptr;
   // fit sample (Sec. 6.4)
@@ -256,10 +257,17 @@ OtherModes others_of(const cpal_ctx *c, int k) {
 // Leverage of mode m from the current factor (Def. 3.4), cached.
 void refresh_leverage(cpal_ctx *c, int m) {
   Mode &md = c->mode[m];
-  launch_lev_gram_partial(md.A, md.n, c->R, c->lev_part, c->stream);
+  const int *skip = nullptr;
+  if (md.n < c->R) {
+    // fewer rows than columns: all scores are 1 when A has full row rank
+    launch_lev_rowspace(md.A, (int)md.n, c->R, md.lev, md.w, c->lev_bsum, &c->st->lev_skip[m],
+                        &c->st->lev_pinv[m], c->stream);
+    skip = &c->st->lev_skip[m];
+  }
+  launch_lev_gram_partial(md.A, md.n, c->R, c->lev_part, skip, c->stream);
   const int nblk = (int)((md.n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
-  launch_decomp(c->lev_part, nblk, c->R, c->dc, &c->st->lev_pinv[m], c->stream);
-  launch_lev_rows(md.A, md.n, c->R, c->dc, md.lev, md.w, c->lev_bsum, c->stream);
+  launch_decomp(c->lev_part, nblk, c->R, c->dc, &c->st->lev_pinv[m], skip, c->stream);
+  launch_lev_rows(md.A, md.n, c->R, c->dc, md.lev, md.w, c->lev_bsum, skip, c->stream);
   launch_lev_cdf(md.w, md.n, c->lev_bsum, md.C, md.q, nullptr, c->stream);
 }
 
@@ -398,7 +406,8 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->samp_om = c->alloc<double>(s);
     c->samp_w = c->alloc<double>(s);
     const size_t tsz = c->f64 ? sizeof(double) : sizeof(float);
-    c->zhat = c->alloc<char>((size_t)s * R * tsz);
+    c->ldz = c->f64 ? ((R + 1) & ~1) : ((R + 3) & ~3);
+    c->zhat = c->alloc<char>((size_t)s * c->ldz * tsz);
     c->foff = c->alloc<unsigned>(s);
     c->flen = c->alloc<unsigned>(s);
     c->fpos = c->alloc<u64>(s + 1);
@@ -560,7 +569,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
   launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->ukey, c->ustart,
               md.slots, md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->M,
-              md.n * R, s);
+              md.n * R, c->ldz, s);
   scan_u32_dev(c->flen, c->fpos, c->s, &c->st->s_bar, (u64 *)&c->st->gathered, c->scan_scratch,
                s);
   c->stage_end(CPAL_STAGE_ROWS, tb);
@@ -570,10 +579,10 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
     const i64 ntiles = (md.n + tr - 1) / tr;
     if (ntiles <= 4)
       launch_gather_tiled(c->f64, c->st, R, c->fpos, c->foff, md.pairs, md.ik, md.v64, c->zhat,
-                          c->Ppart, c->M, md.n, c->tile_grid, s);
+                          c->ldz, c->Ppart, c->M, md.n, c->tile_grid, s);
     else
       launch_gather(c->f64, c->st, R, c->fpos, c->foff, md.pairs, md.ik, md.v64, c->zhat, c->M,
-                    c->gather_grid, s);
+                    c->ldz, c->gather_grid, s);
   }
   c->stage_end(CPAL_STAGE_GATHER, tb);
   // solve A_k = M G_s^{-1}, then the leverage of the new A_k

@@ -38,6 +38,7 @@ struct DevState {
   i64 fit_z;          // fit sample: zero entries (accepted)
   u64 ncand[CPAL_MAXORDER];   // candidate rows per other mode (Sec. 5.3)
   int lev_pinv[CPAL_MAXORDER];  // pseudo-inverse used for a mode's leverage
+  int lev_skip[CPAL_MAXORDER];  // leverage settled by the full-row-rank test
   double fit;
   double normX2;
 };
@@ -180,11 +181,14 @@ namespace cpal {
 struct Sorter;   // radix sort scratch
 
 // leverage pipeline for one factor matrix (n x R) ---------------------------
-void launch_lev_gram_partial(const double *A, i64 n, int R, double *part, hipStream_t s);
+void launch_lev_gram_partial(const double *A, i64 n, int R, double *part, const int *skip,
+                             hipStream_t s);
+void launch_lev_rowspace(const double *A, int n, int R, double *lev, u64 *w, u64 *blocksum,
+                         int *skip, int *pinv_store, hipStream_t s);
 void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_store,
-                   hipStream_t s);
+                   const int *skip, hipStream_t s);
 void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *lev, u64 *w,
-                     u64 *blocksum, hipStream_t s);
+                     u64 *blocksum, const int *skip, hipStream_t s);
 void launch_lev_cdf(const u64 *w, i64 n, const u64 *blocksum, u64 *C, double *q,
                     int *flag_or, hipStream_t s);
 

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     double *__restrict__ samp_w, const u64 *__restrict__ ukey, const u64 *__restrict__ ustart,
     const FiberSlot *__restrict__ slots, u64 hmask, int hshift, T *__restrict__ zhat,
     unsigned *__restrict__ foff, unsigned *__restrict__ flen, double *__restrict__ gpart,
-    T *__restrict__ M, i64 mlen) {
+    T *__restrict__ M, i64 mlen, int ldz) {
   extern __shared__ double sz[];           // ROWS_BLK x (R+1)
   __shared__ double som[ROWS_BLK];
   const int tid = threadIdx.x;
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
       double v = om.A[0][im[0] * R + r];
       for (int u = 1; u < om.d; ++u) v = v * om.A[u][im[u] * R + r];
       z[r] = v;
-      zhat[j * R + r] = (T)(omj * v);
+      zhat[j * ldz + r] = (T)(omj * v);
     }
     u64 h = fiber_hash(lin, hshift);
     unsigned off = 0, len = 0;
@@ -126,7 +126,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
                                                 const u64 *__restrict__ fpos,
                                                 const unsigned *__restrict__ foff, NzLoad<T> nz,
-                                                const T *__restrict__ zhat, T *__restrict__ M) {
+                                                const T *__restrict__ zhat, T *__restrict__ M,
+                                                int ldz) {
   const i64 total = st->gathered;
   const i64 s_bar = st->s_bar;
   const int lane = threadIdx.x & 63;
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
       const T x_s = __shfl(x, sl, 64);
       const i64 j_s = __shfl(j, sl, 64);
       const bool v_s = __shfl((int)valid, sl, 64) != 0;
-      if (v_s && col < R) unsafeAtomicAdd(&M[(i64)ik_s * R + col], x_s * zhat[j_s * R + col]);
+      if (v_s && col < R) unsafeAtomicAdd(&M[(i64)ik_s * R + col], x_s * zhat[j_s * ldz + col]);
     }
   }
 }
@@ -192,10 +193,10 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
 #define GT_PER_THREAD 4
 #define GT_CHUNK (GT_THREADS * GT_PER_THREAD)
 #define GT_WIN 4096
-template <typename T>
+template <typename T, int RM>
 __global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
     const DevState *st, int R, const u64 *__restrict__ fpos, const unsigned *__restrict__ foff,
-    NzLoad<T> nz, const T *__restrict__ zhat, T *__restrict__ P, i64 nk, int tile_rows) {
+    NzLoad<T> nz, const T *__restrict__ zhat, int ldz, T *__restrict__ P, i64 nk, int tile_rows) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   u64 *win = (u64 *)smem_raw;                          // GT_WIN fiber prefix sums
   T *acc = (T *)(smem_raw + sizeof(u64) * GT_WIN);      // tile_rows x R
@@ -207,11 +208,8 @@ __global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
   if (g >= nch) return;
   const i64 r0 = (i64)blockIdx.y * tile_rows;
   const int rows = (int)min((i64)tile_rows, nk - r0);
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x;
   for (int e = tid; e < rows * R; e += GT_THREADS) acc[e] = T(0);
-  const bool half = R <= 32;
-  const int col = half ? (lane & 31) : lane;
-  const int sub = half ? (lane >> 5) : 0;
   for (i64 c = g; c < nch; c += G) {
     const i64 base = c * GT_CHUNK;
     const i64 last = min(total, base + GT_CHUNK) - 1;
@@ -234,41 +232,35 @@ __global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
     __syncthreads();
     for (int u = 0; u < GT_PER_THREAD; ++u) {
       const i64 p = base + (i64)u * GT_THREADS + tid;
-      const bool valid = p <= last;
-      i64 j = jlo;
-      u64 fp = 0;
-      int ik = 0;
-      T x = T(0);
-      if (valid) {
-        if (in_win) {
-          int lo = 0, hi = (int)nwin;   // last index with win[idx] <= p
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (win[mid] <= (u64)p) lo = mid; else hi = mid;
-          }
-          j = jlo + lo;
-          fp = win[lo];
-        } else {
-          i64 lo = jlo, hi = jhi + 1;
-          while (hi - lo > 1) {
-            const i64 mid = (lo + hi) >> 1;
-            if (fpos[mid] <= (u64)p) lo = mid; else hi = mid;
-          }
-          j = lo;
-          fp = fpos[lo];
+      if (p > last) continue;
+      i64 j;
+      u64 fp;
+      if (in_win) {
+        int lo = 0, hi = (int)nwin;   // last index with win[idx] <= p
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (win[mid] <= (u64)p) lo = mid; else hi = mid;
         }
-        nz.get((u64)foff[j] + (u64)(p - (i64)fp), ik, x);
+        j = jlo + lo;
+        fp = win[lo];
+      } else {
+        i64 lo = jlo, hi = jhi + 1;
+        while (hi - lo > 1) {
+          const i64 mid = (lo + hi) >> 1;
+          if (fpos[mid] <= (u64)p) lo = mid; else hi = mid;
+        }
+        j = lo;
+        fp = fpos[lo];
       }
-      const bool mine = valid && ik >= r0 && ik < r0 + rows;
-      for (int src = 0; src < 64; src += half ? 2 : 1) {
-        const int sl = src + sub;
-        const int ik_s = __shfl(ik, sl, 64);
-        const T x_s = __shfl(x, sl, 64);
-        const i64 j_s = __shfl(j, sl, 64);
-        const bool m_s = __shfl((int)mine, sl, 64) != 0;
-        if (m_s && col < R)
-          unsafeAtomicAdd(&acc[(i64)(ik_s - r0) * R + col], x_s * zhat[j_s * R + col]);
-      }
+      int ik;
+      T x;
+      nz.get((u64)foff[j] + (u64)(p - (i64)fp), ik, x);
+      if (ik < r0 || ik >= r0 + rows) continue;
+      const T *zr = zhat + j * ldz;
+      T *ar = acc + (i64)(ik - r0) * R;
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+        if (r < R) unsafeAtomicAdd(&ar[r], x * zr[r]);
     }
     __syncthreads();
   }
@@ -295,54 +287,96 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const DevState *st, con
 // factor, or the pseudo-inverse from the eigendecomposition.  Rows are
 // independent; FP64 throughout.  Skipped when the update hit a state error.
 #define SOLVE_BLK 128
-template <typename T>
+template <typename T, int RM>
 __global__ void __launch_bounds__(SOLVE_BLK) k_solve_rows(const DevState *st, i64 n, int R,
                                                           const T *__restrict__ M,
                                                           const Decomp *__restrict__ dc,
                                                           double *__restrict__ A,
                                                           float *__restrict__ A32) {
-  extern __shared__ double sy[];   // SOLVE_BLK x (R+1)
+  extern __shared__ double sm[];   // R*R factor, R lambdas, then SOLVE_BLK x (2R+1) rows
   if (st->flags & CPAL_FLAG_STATE) return;
-  const i64 i = (i64)blockIdx.x * SOLVE_BLK + threadIdx.x;
-  if (i >= n) return;
-  const int ld = R + 1;
-  double *y = sy + threadIdx.x * ld;
-  for (int r = 0; r < R; ++r) y[r] = (double)M[i * R + r];
-  if (!dc->pinv) {
-    const double *L = dc->L;
-    for (int j = 0; j < R; ++j) {
-      double v = y[j];
-      for (int p = 0; p < j; ++p) v = v - L[j * R + p] * y[p];
-      y[j] = v / L[j * R + j];
-    }
-    for (int j = R - 1; j >= 0; --j) {
-      double v = y[j];
-      for (int p = j + 1; p < R; ++p) v = v - L[p * R + j] * y[p];
-      y[j] = v / L[j * R + j];
-    }
-    for (int r = 0; r < R; ++r) {
-      A[i * R + r] = y[r];
-      A32[i * R + r] = (float)y[r];
-    }
-  } else {
-    const double *V = dc->V;
-    double c[CPAL_MAXR];
-    for (int j = 0; j < R; ++j) {
-      c[j] = 0.0;
-      if (!(dc->lam[j] > dc->etol)) continue;
-      double v = 0.0;
-      for (int p = 0; p < R; ++p) v = v + V[p * R + j] * y[p];
-      c[j] = v / dc->lam[j];
-    }
-    for (int r = 0; r < R; ++r) {
-      double v = 0.0;
-      for (int j = 0; j < R; ++j) {
-        if (!(dc->lam[j] > dc->etol)) continue;
-        v = v + c[j] * V[r * R + j];
+  const int pinv = dc->pinv;
+  double *sL = sm;
+  double *slam = sm + R * R;
+  const int ld = 2 * R + 1;
+  double *sy = slam + R;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = pinv ? dc->V[e] : dc->L[e];
+  for (int e = threadIdx.x; e < R; e += blockDim.x)
+    slam[e] = (pinv && dc->lam[e] > dc->etol) ? dc->lam[e] : 0.0;
+  const i64 r0 = (i64)blockIdx.x * blockDim.x;
+  const int rows = (int)min((i64)blockDim.x, n - r0);
+  for (int e = threadIdx.x; e < rows * R; e += blockDim.x) {
+    const int r = e / R, c = e - r * R;
+    sy[r * ld + c] = (double)M[r0 * R + e];
+  }
+  __syncthreads();
+  if (threadIdx.x < rows) {
+    double *ys = sy + threadIdx.x * ld;
+    if (!pinv) {
+      if constexpr (RM > 0) {
+        double y[RM];
+#pragma unroll
+        for (int j = 0; j < RM; ++j) y[j] = (j < R) ? ys[j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < RM; ++j) {
+          if (j < R) {
+            double v = y[j];
+#pragma unroll
+            for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * y[p];
+            y[j] = v / sL[j * R + j];
+          }
+        }
+#pragma unroll
+        for (int j = RM - 1; j >= 0; --j) {
+          if (j < R) {
+            double v = y[j];
+#pragma unroll
+            for (int p = j + 1; p < RM; ++p)
+              if (p < R) v = v - sL[p * R + j] * y[p];
+            y[j] = v / sL[j * R + j];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < RM; ++j)
+          if (j < R) ys[j] = y[j];
+      } else {
+        for (int j = 0; j < R; ++j) {
+          double v = ys[j];
+          for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * ys[p];
+          ys[j] = v / sL[j * R + j];
+        }
+        for (int j = R - 1; j >= 0; --j) {
+          double v = ys[j];
+          for (int p = j + 1; p < R; ++p) v = v - sL[p * R + j] * ys[p];
+          ys[j] = v / sL[j * R + j];
+        }
       }
-      A[i * R + r] = v;
-      A32[i * R + r] = (float)v;
+    } else {
+      // x = sum_j (v_j . m / lam_j) v_j over the kept eigenpairs
+      double *cs = ys + R;
+      for (int j = 0; j < R; ++j) {
+        double c = 0.0;
+        if (slam[j] > 0.0) {
+          double v = 0.0;
+          for (int p = 0; p < R; ++p) v = v + sL[p * R + j] * ys[p];
+          c = v / slam[j];
+        }
+        cs[j] = c;
+      }
+      for (int r = 0; r < R; ++r) {
+        double v = 0.0;
+        for (int j = 0; j < R; ++j)
+          if (slam[j] > 0.0) v = v + cs[j] * sL[r * R + j];
+        ys[r] = v;
+      }
     }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < rows * R; e += blockDim.x) {
+    const int r = e / R, c = e - r * R;
+    const double v = sy[r * ld + c];
+    A[r0 * R + e] = v;
+    A32[r0 * R + e] = (float)v;
   }
 }
 
@@ -459,17 +493,17 @@ static int grid_for(i64 n, int blk, int maxg = 8192) {
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
                  double *samp_om, double *samp_w, const u64 *ukey, const u64 *ustart,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
-                 unsigned *flen, double *gpart, void *M, i64 mlen, hipStream_t s) {
+                 unsigned *flen, double *gpart, void *M, i64 mlen, int ldz, hipStream_t s) {
   const int nb = (int)((cap + ROWS_BLK - 1) / ROWS_BLK);
   const size_t sh = sizeof(double) * (size_t)ROWS_BLK * (R + 1);
   if (f64)
     hipLaunchKernelGGL(k_rows<double>, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx,
                        samp_om, samp_w, ukey, ustart, slots, hmask, hshift, (double *)zhat, foff,
-                       flen, gpart, (double *)M, mlen);
+                       flen, gpart, (double *)M, mlen, ldz);
   else
     hipLaunchKernelGGL(k_rows<float>, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx,
                        samp_om, samp_w, ukey, ustart, slots, hmask, hshift, (float *)zhat, foff,
-                       flen, gpart, (float *)M, mlen);
+                       flen, gpart, (float *)M, mlen, ldz);
 }
 
 int rows_blocks(i64 cap) { return (int)((cap + ROWS_BLK - 1) / ROWS_BLK); }
@@ -485,23 +519,32 @@ int gather_tile_rows(i64 nk, int R, bool f64) {
 
 void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
                          const uint2 *pairs, const int *ik, const double *v64, const void *zhat,
-                         void *P, void *M, i64 nk, int G, hipStream_t s) {
+                         int ldz, void *P, void *M, i64 nk, int G, hipStream_t s) {
   const int tr = gather_tile_rows(nk, R, f64);
   const int ntiles = (int)((nk + tr - 1) / tr);
   const size_t elem = f64 ? sizeof(double) : sizeof(float);
   const size_t sh = sizeof(u64) * GT_WIN + elem * (size_t)tr * R;
   const i64 nkR = nk * R;
   const int rg = grid_for(nkR, 256, 4096);
+  const dim3 grid(G, ntiles), blk(GT_THREADS);
   if (f64) {
     NzLoad<double> nz{ik, v64};
-    hipLaunchKernelGGL(k_gather_tile<double>, dim3(G, ntiles), dim3(GT_THREADS), sh, s, st, R, fpos,
-                       foff, nz, (const double *)zhat, (double *)P, nk, tr);
+    if (R <= 32)
+      hipLaunchKernelGGL((k_gather_tile<double, 32>), grid, blk, sh, s, st, R, fpos, foff, nz,
+                         (const double *)zhat, ldz, (double *)P, nk, tr);
+    else
+      hipLaunchKernelGGL((k_gather_tile<double, 64>), grid, blk, sh, s, st, R, fpos, foff, nz,
+                         (const double *)zhat, ldz, (double *)P, nk, tr);
     hipLaunchKernelGGL(k_reduce_partials<double>, dim3(rg), dim3(256), 0, s, st,
                        (const double *)P, nkR, G, (double *)M);
   } else {
     NzLoad<float> nz{pairs};
-    hipLaunchKernelGGL(k_gather_tile<float>, dim3(G, ntiles), dim3(GT_THREADS), sh, s, st, R, fpos,
-                       foff, nz, (const float *)zhat, (float *)P, nk, tr);
+    if (R <= 32)
+      hipLaunchKernelGGL((k_gather_tile<float, 32>), grid, blk, sh, s, st, R, fpos, foff, nz,
+                         (const float *)zhat, ldz, (float *)P, nk, tr);
+    else
+      hipLaunchKernelGGL((k_gather_tile<float, 64>), grid, blk, sh, s, st, R, fpos, foff, nz,
+                         (const float *)zhat, ldz, (float *)P, nk, tr);
     hipLaunchKernelGGL(k_reduce_partials<float>, dim3(rg), dim3(256), 0, s, st, (const float *)P,
                        nkR, G, (float *)M);
   }
@@ -509,28 +552,32 @@ void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *fpos, c
 
 void launch_gather(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
                    const uint2 *pairs, const int *ik, const double *v64, const void *zhat, void *M,
-                   int grid, hipStream_t s) {
+                   int ldz, int grid, hipStream_t s) {
   if (f64) {
     NzLoad<double> nz{ik, v64};
     hipLaunchKernelGGL(k_gather<double>, dim3(grid), dim3(256), 0, s, st, R, fpos, foff, nz,
-                       (const double *)zhat, (double *)M);
+                       (const double *)zhat, (double *)M, ldz);
   } else {
     NzLoad<float> nz{pairs};
     hipLaunchKernelGGL(k_gather<float>, dim3(grid), dim3(256), 0, s, st, R, fpos, foff, nz,
-                       (const float *)zhat, (float *)M);
+                       (const float *)zhat, (float *)M, ldz);
   }
 }
 
 void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, const Decomp *dc,
                        double *A, float *A32, hipStream_t s) {
-  const int nb = (int)((n + SOLVE_BLK - 1) / SOLVE_BLK);
-  const size_t sh = sizeof(double) * (size_t)SOLVE_BLK * (R + 1);
-  if (f64)
-    hipLaunchKernelGGL(k_solve_rows<double>, dim3(nb), dim3(SOLVE_BLK), sh, s, st, n, R,
-                       (const double *)M, dc, A, A32);
-  else
-    hipLaunchKernelGGL(k_solve_rows<float>, dim3(nb), dim3(SOLVE_BLK), sh, s, st, n, R,
-                       (const float *)M, dc, A, A32);
+  const int bs = R > 32 ? 64 : SOLVE_BLK;   // rows per block (shared memory <= 100 KB)
+  const int nb = (int)((n + bs - 1) / bs);
+  const size_t sh = sizeof(double) * ((size_t)R * R + R + (size_t)bs * (2 * R + 1));
+#define CPAL_SOLVE(TT, RMV)                                                                       \
+  hipLaunchKernelGGL((k_solve_rows<TT, RMV>), dim3(nb), dim3(bs), sh, s, st, n, R,                \
+                     (const TT *)M, dc, A, A32)
+  if (f64) {
+    if (R <= 16) CPAL_SOLVE(double, 16); else if (R <= 32) CPAL_SOLVE(double, 32); else CPAL_SOLVE(double, 0);
+  } else {
+    if (R <= 16) CPAL_SOLVE(float, 16); else if (R <= 32) CPAL_SOLVE(float, 32); else CPAL_SOLVE(float, 0);
+  }
+#undef CPAL_SOLVE
 }
 
 void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s) {

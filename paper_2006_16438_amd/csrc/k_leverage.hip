@@ -22,8 +22,10 @@ __device__ __forceinline__ void pair_of(int p, int R, int &a, int &c) {
 
 // part[b][p]: sum over the rows of block b of A(r,a)*A(r,c), pair p = (a<=c).
 __global__ void __launch_bounds__(256) k_lev_gram_partial(const double *__restrict__ A, i64 n,
-                                                          int R, double *__restrict__ part) {
+                                                          int R, double *__restrict__ part,
+                                                          const int *skip) {
   extern __shared__ double sA[];  // CPAL_GRAM_ROWS x R
+  if (skip && *skip) return;
   const i64 r0 = (i64)blockIdx.x * CPAL_GRAM_ROWS;
   const int rows = (int)min((i64)CPAL_GRAM_ROWS, n - r0);
   for (int e = threadIdx.x; e < rows * R; e += blockDim.x) sA[e] = A[r0 * R + e];
@@ -106,6 +108,80 @@ __device__ void jacobi_wave(double *S, double *V, int R, Decomp *out) {
   if (lane == 0) out->etol = ((double)R * 0x1p-52) * mx;
 }
 
+// Right-looking Cholesky of the symmetric matrix S (R x R in shared memory;
+// its lower triangle is overwritten by the trailing updates) into L.  Entry
+// (i,j) receives the subtractions L(i,p) L(j,p) for p = 0, 1, ..., j-1 in
+// that order, then one division by L(j,j) -- the same operations as the
+// column-by-column form -- so the factor is identical bit for bit, while
+// each column's updates run in parallel.  Returns false when a pivot is not
+// above tol.
+__device__ bool chol_right(double *S, double *L, int R, double tol, int *fail_sh) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < R * R; e += nt) L[e] = 0.0;
+  if (tid == 0) *fail_sh = 0;
+  __syncthreads();
+  for (int j = 0; j < R; ++j) {
+    if (tid == 0) {
+      const double v = S[j * R + j];
+      if (!(v > tol)) *fail_sh = 1;
+      else L[j * R + j] = sqrt(v);
+    }
+    __syncthreads();
+    if (*fail_sh) return false;
+    const double ljj = L[j * R + j];
+    for (int i = j + 1 + tid; i < R; i += nt) L[i * R + j] = S[i * R + j] / ljj;
+    __syncthreads();
+    const int m = R - j - 1;
+    const int cnt = m * (m + 1) / 2;
+    for (int e = tid; e < cnt; e += nt) {
+      int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while (a > 0 && a * (a + 1) / 2 > e) --a;
+      while ((a + 1) * (a + 2) / 2 <= e) ++a;
+      const int b = e - a * (a + 1) / 2;
+      const int i = j + 1 + a, l = j + 1 + b;
+      S[i * R + l] = S[i * R + l] - L[i * R + j] * L[l * R + j];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// Leverage of a factor with fewer rows than columns (n < R <= 64): if A A^T
+// (n x n, each entry summed over the R columns in ascending order) passes the
+// Cholesky pivot test, A has full row rank, range(A) = R^n and every
+// leverage score is exactly 1; the generic kernels are then skipped (*skip =
+// 1).  Otherwise *skip = 0 and the Gram / eigen path runs.  One block.
+__global__ void __launch_bounds__(64) k_lev_rowspace(const double *__restrict__ A, int n, int R,
+                                                     double *__restrict__ lev, u64 *__restrict__ w,
+                                                     u64 *__restrict__ blocksum, int *skip,
+                                                     int *pinv_store) {
+  __shared__ double K[CPAL_MAXR * CPAL_MAXR];
+  __shared__ double L[CPAL_MAXR * CPAL_MAXR];
+  __shared__ int fail;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += 64) {
+    const int i = e / n, j = e - i * n;
+    if (j > i) continue;
+    double acc = 0.0;
+    for (int r = 0; r < R; ++r) acc = acc + A[(i64)i * R + r] * A[(i64)j * R + r];
+    K[i * n + j] = acc;
+    K[j * n + i] = acc;
+  }
+  __syncthreads();
+  double maxdiag = 0.0;
+  for (int j = 0; j < n; ++j) maxdiag = fmax(maxdiag, K[j * n + j]);
+  const double tol = ((double)n * 0x1p-52) * maxdiag;
+  const bool ok = chol_right(K, L, n, tol, &fail);
+  if (ok) {
+    double v = 1.0 / (double)R;
+    if (v > 1.0) v = 1.0;
+    const u64 wi = (u64)(v * 0x1p52);
+    for (int i = tid; i < n; i += 64) { lev[i] = 1.0; w[i] = wi; }
+    if (tid == 0) { blocksum[0] = wi * (u64)n; *pinv_store = 1; }
+  }
+  if (tid == 0) *skip = ok ? 1 : 0;
+}
+
 // Sum the block partials in block order into G, then factor G.  One block of
 // 64 threads (one wavefront); lane i owns row i during the Cholesky sweep.
 // nrows_dev (nullable) gives the number of partial blocks at run time as
@@ -115,11 +191,12 @@ __device__ void jacobi_wave(double *S, double *V, int R, Decomp *out) {
 __global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, int nblk,
                                                const i64 *nrows_dev, int rows_per_blk, int R,
                                                Decomp *__restrict__ out, int *flag_or,
-                                               int *flag_store) {
+                                               int *flag_store, const int *skip) {
   __shared__ double G[CPAL_MAXR * CPAL_MAXR];
   __shared__ double L[CPAL_MAXR * CPAL_MAXR];
   __shared__ double slab[DECOMP_SLAB];
   __shared__ int fail;
+  if (skip && *skip) return;
   const int lane = threadIdx.x;
   if (nrows_dev) nblk = (int)((*nrows_dev + rows_per_blk - 1) / rows_per_blk);
   const int np = R * (R + 1) / 2;
@@ -147,29 +224,12 @@ __global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, 
     G[c * R + a] = L[p];
   }
   __syncthreads();
-  for (int e = lane; e < R * R; e += 64) L[e] = 0.0;
-  if (lane == 0) fail = 0;
-  __syncthreads();
   double maxdiag = 0.0;
   for (int j = 0; j < R; ++j) maxdiag = fmax(maxdiag, G[j * R + j]);
   const double tol = ((double)R * 0x1p-52) * maxdiag;
-  for (int j = 0; j < R; ++j) {
-    if (lane == 0) {
-      double v = G[j * R + j];
-      for (int p = 0; p < j; ++p) v = v - L[j * R + p] * L[j * R + p];
-      if (!(v > tol)) fail = 1;
-      else L[j * R + j] = sqrt(v);
-    }
-    __syncthreads();
-    if (fail) break;
-    const double ljj = L[j * R + j];
-    if (lane > j && lane < R) {
-      double u = G[lane * R + j];
-      for (int p = 0; p < j; ++p) u = u - L[lane * R + p] * L[j * R + p];
-      L[lane * R + j] = u / ljj;
-    }
-    __syncthreads();
-  }
+  for (int e = lane; e < R * R; e += 64) slab[e] = G[e];   // working copy
+  __syncthreads();
+  chol_right(slab, L, R, tol, &fail);
   __syncthreads();
   if (!fail) {
     for (int e = lane; e < R * R; e += 64) out->L[e] = L[e];
@@ -209,14 +269,20 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double *__restrict__ 
   if (threadIdx.x == 0) out[p] = red[0];
 }
 
-// Per row: l_i, w_i; per block of 128 rows: sum of w.
+// Per row: l_i, w_i; per block of 128 rows: sum of w.  The row is staged
+// through shared memory (coalesced).  For RM > 0 (R <= RM <= 32) it is held
+// in registers and the substitution loops are unrolled; RM = 0 works on the
+// shared-memory copy.  Both run the canonical operation order.
 #define LEV_ROWS 128
+template <int RM>
 __global__ void __launch_bounds__(LEV_ROWS) k_lev_rows(const double *__restrict__ A, i64 n, int R,
                                                       const Decomp *__restrict__ dc,
                                                       double *__restrict__ lev,
                                                       u64 *__restrict__ w,
-                                                      u64 *__restrict__ blocksum) {
+                                                      u64 *__restrict__ blocksum,
+                                                      const int *skip) {
   extern __shared__ double sm[];
+  if (skip && *skip) return;
   double *sL = sm;                       // R*R (L, or V)
   double *sy = sm + R * R;               // LEV_ROWS x (R+1), padded rows
   const int pinv = dc->pinv;
@@ -231,23 +297,54 @@ __global__ void __launch_bounds__(LEV_ROWS) k_lev_rows(const double *__restrict_
   __syncthreads();
   u64 wi = 0;
   if (threadIdx.x < rows) {
-    double *y = sy + threadIdx.x * ld;
     double acc = 0.0;
-    if (!pinv) {
-      for (int j = 0; j < R; ++j) {
-        double v = y[j];
-        for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * y[p];
-        y[j] = v / sL[j * R + j];
+    double *ys = sy + threadIdx.x * ld;
+    if constexpr (RM > 0) {
+      double y[RM];
+#pragma unroll
+      for (int j = 0; j < RM; ++j) y[j] = (j < R) ? ys[j] : 0.0;
+      if (!pinv) {
+#pragma unroll
+        for (int j = 0; j < RM; ++j) {
+          if (j < R) {
+            double v = y[j];
+#pragma unroll
+            for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * y[p];
+            y[j] = v / sL[j * R + j];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < RM; ++j)
+          if (j < R) acc = acc + y[j] * y[j];
+      } else {
+        const double etol = dc->etol;
+        for (int j = 0; j < R; ++j) {
+          const double lam = dc->lam[j];
+          if (!(lam > etol)) continue;
+          double t = 0.0;
+#pragma unroll
+          for (int p = 0; p < RM; ++p)
+            if (p < R) t = t + sL[p * R + j] * y[p];
+          acc = acc + (t * t) / lam;
+        }
       }
-      for (int j = 0; j < R; ++j) acc = acc + y[j] * y[j];
     } else {
-      const double etol = dc->etol;
-      for (int j = 0; j < R; ++j) {
-        const double lam = dc->lam[j];
-        if (!(lam > etol)) continue;
-        double t = 0.0;
-        for (int p = 0; p < R; ++p) t = t + sL[p * R + j] * y[p];
-        acc = acc + (t * t) / lam;
+      if (!pinv) {
+        for (int j = 0; j < R; ++j) {
+          double v = ys[j];
+          for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * ys[p];
+          ys[j] = v / sL[j * R + j];
+        }
+        for (int j = 0; j < R; ++j) acc = acc + ys[j] * ys[j];
+      } else {
+        const double etol = dc->etol;
+        for (int j = 0; j < R; ++j) {
+          const double lam = dc->lam[j];
+          if (!(lam > etol)) continue;
+          double t = 0.0;
+          for (int p = 0; p < R; ++p) t = t + sL[p * R + j] * ys[p];
+          acc = acc + (t * t) / lam;
+        }
       }
     }
     const double l = acc > 0.0 ? acc : 0.0;
@@ -292,16 +389,23 @@ __global__ void __launch_bounds__(LEV_ROWS) k_lev_cdf(const u64 *__restrict__ w,
   if (i == 0 && all == 0 && flag_or) atomicOr(flag_or, CPAL_FLAG_STATE);
 }
 
-void launch_lev_gram_partial(const double *A, i64 n, int R, double *part, hipStream_t s) {
+void launch_lev_gram_partial(const double *A, i64 n, int R, double *part, const int *skip,
+                             hipStream_t s) {
   const int nblk = (int)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
   const size_t sh = sizeof(double) * CPAL_GRAM_ROWS * R;
-  hipLaunchKernelGGL(k_lev_gram_partial, dim3(nblk), dim3(256), sh, s, A, n, R, part);
+  hipLaunchKernelGGL(k_lev_gram_partial, dim3(nblk), dim3(256), sh, s, A, n, R, part, skip);
+}
+
+void launch_lev_rowspace(const double *A, int n, int R, double *lev, u64 *w, u64 *blocksum,
+                         int *skip, int *pinv_store, hipStream_t s) {
+  hipLaunchKernelGGL(k_lev_rowspace, dim3(1), dim3(64), 0, s, A, n, R, lev, w, blocksum, skip,
+                     pinv_store);
 }
 
 void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_store,
-                   hipStream_t s) {
+                   const int *skip, hipStream_t s) {
   hipLaunchKernelGGL(k_decomp, dim3(1), dim3(64), 0, s, part, nblk, (const i64 *)nullptr, 1, R,
-                     out, (int *)nullptr, flag_store);
+                     out, (int *)nullptr, flag_store, skip);
 }
 
 void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_blk, int R,
@@ -310,15 +414,22 @@ void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_bl
   hipLaunchKernelGGL(k_gram_reduce, dim3(np), dim3(256), 0, s, part, nrows_dev, rows_per_blk, np,
                      gram_tmp);
   hipLaunchKernelGGL(k_decomp, dim3(1), dim3(64), 0, s, (const double *)gram_tmp, 1,
-                     (const i64 *)nullptr, 1, R, out, flag_or, (int *)nullptr);
+                     (const i64 *)nullptr, 1, R, out, flag_or, (int *)nullptr, (const int *)nullptr);
 }
 
 void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *lev, u64 *w,
-                     u64 *blocksum, hipStream_t s) {
+                     u64 *blocksum, const int *skip, hipStream_t s) {
   const int nblk = (int)((n + LEV_ROWS - 1) / LEV_ROWS);
   const size_t sh = sizeof(double) * ((size_t)R * R + (size_t)LEV_ROWS * (R + 1));
-  hipLaunchKernelGGL(k_lev_rows, dim3(nblk), dim3(LEV_ROWS), sh, s, A, n, R, dc, lev, w,
-                     blocksum);
+  if (R <= 16)
+    hipLaunchKernelGGL(k_lev_rows<16>, dim3(nblk), dim3(LEV_ROWS), sh, s, A, n, R, dc, lev, w,
+                       blocksum, skip);
+  else if (R <= 32)
+    hipLaunchKernelGGL(k_lev_rows<32>, dim3(nblk), dim3(LEV_ROWS), sh, s, A, n, R, dc, lev, w,
+                       blocksum, skip);
+  else
+    hipLaunchKernelGGL(k_lev_rows<0>, dim3(nblk), dim3(LEV_ROWS), sh, s, A, n, R, dc, lev, w,
+                       blocksum, skip);
 }
 
 void launch_lev_cdf(const u64 *w, i64 n, const u64 *blocksum, u64 *C, double *q, int *flag_or,

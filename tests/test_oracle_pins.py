@@ -475,3 +475,24 @@ def test_single_row_krp_is_always_accepted():
     st = out["stats"]
     assert st["draws"] == 7 and st["s_rnd"] == 7 and st["s_bar"] == 1
     assert out["omega"][0] == 1.0 and st["flags"] == 0
+
+
+def test_leverage_fewer_rows_than_rank():
+    """n < R with full row rank: range(A) = R^n, so every leverage score is
+    exactly 1 (the projector is the identity); with a repeated row the rank
+    drops and the projector from the SVD applies."""
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((24, 25))
+    lev, fl = oracle.leverage(A)
+    assert fl & oracle.FLAG_PINV
+    assert np.all(lev == 1.0)
+    U, S, _ = np.linalg.svd(A, full_matrices=False)
+    assert np.allclose((U * U).sum(axis=1), 1.0, atol=1e-12)
+    B = A.copy()
+    B[5] = B[3]                      # rank 23
+    lev, fl = oracle.leverage(B)
+    U, S, _ = np.linalg.svd(B, full_matrices=False)
+    ref = (U[:, :23] ** 2).sum(axis=1)
+    assert fl & oracle.FLAG_PINV
+    assert np.max(np.abs(lev - ref)) < 1e-10
+    assert abs(lev.sum() - 23) < 1e-9
