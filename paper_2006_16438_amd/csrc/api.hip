@@ -26,7 +26,7 @@ void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *
 void launch_det_cand(const OtherModes &om, double tau, u64 cap, DevState *st, int *cand,
                      hipStream_t s);
 void launch_det_enum(const OtherModes &om, double tau, DevState *st, const int *cand,
-                     u64 *det_keys, u64 det_cap, hipStream_t s);
+                     unsigned *blk_cnt, u64 *det_keys, u64 det_cap, hipStream_t s);
 void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, double *det_p,
                        double *kept_p, double *psum, u64 det_cap, i64 s, u64 *samp_idx,
                        hipStream_t st_);
@@ -135,6 +135,7 @@ struct cpal_ctx {
   i64 cand_off[CPAL_MAXORDER] = {0};
   u64 det_cap = 0;
   u64 *det_keys = nullptr, *det_tmp = nullptr;
+  unsigned *det_blk = nullptr;
   double *det_p = nullptr, *kept_p = nullptr, *psum = nullptr;
   u64 *dbuf = nullptr;
   unsigned char *dpos = nullptr;
@@ -387,6 +388,7 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->det_cap = 4 * (u64)s + 4096;
     c->det_keys = c->alloc<u64>(c->det_cap);
     c->det_tmp = c->alloc<u64>(c->det_cap);
+    c->det_blk = c->alloc<unsigned>(256);
     c->det_p = c->alloc<double>(c->det_cap);
     c->kept_p = c->alloc<double>(s);
     c->psum = c->alloc<double>(c->det_cap / 256 + 2);
@@ -546,11 +548,8 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   // SkrpLev (Alg. 1): deterministic rows
   hipEvent_t tb = c->stage_begin();
   launch_det_cand(om, c->tau, c->enum_cap, c->st, c->cand, s);
-  if (c->tau < 1.0) {
-    launch_det_enum(om, c->tau, c->st, c->cand, c->det_keys, c->det_cap, s);
-    sort_keys(c->det_keys, nullptr, c->det_tmp, nullptr, c->sort_scratch, (i64)c->det_cap,
-              (const i64 *)&c->st->det_count, 0, md.key_bits, s);
-  }
+  if (c->tau < 1.0)
+    launch_det_enum(om, c->tau, c->st, c->cand, c->det_blk, c->det_keys, c->det_cap, s);
   launch_det_finish(om, c->st, c->det_keys, c->det_p, c->kept_p, c->psum, c->det_cap, c->s,
                     c->samp_idx, s);
   // random rows (Alg. 2) and combining repeats (Sec. 4.1, 4.3)

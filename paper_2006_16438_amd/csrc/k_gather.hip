@@ -276,9 +276,16 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const DevState *st, con
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
   const int nwg = (int)min((i64)G, nch);
   for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < nkR; e += (i64)gridDim.x * blockDim.x) {
-    T a = T(0);
-    for (int g = 0; g < nwg; ++g) a += P[(i64)g * nkR + e];
-    M[e] = a;
+    T a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = T(0);
+    int g = 0;
+    for (; g + 8 <= nwg; g += 8) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[k] += P[(i64)(g + k) * nkR + e];
+    }
+    for (; g < nwg; ++g) a[0] += P[(i64)g * nkR + e];
+    M[e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
 }
 

@@ -106,31 +106,83 @@ __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u6
   }
 }
 
-// Enumerate the candidate product set; rows with p > tau are appended.
-__global__ void __launch_bounds__(256) k_det_enum(OtherModes om, double tau, DevState *st,
-                                                  const int *__restrict__ cand,
-                                                  u64 *__restrict__ det_keys, u64 det_cap) {
+// Enumeration of the candidate product set in mixed-radix order (first other
+// mode fastest).  The candidate lists are ascending, so this order is
+// ascending in the linear index, and an order-preserving compaction of the
+// rows with p > tau yields the deterministic set already sorted.  Block b
+// owns the contiguous range [b*per, (b+1)*per) of combinations; pass 1
+// counts, pass 2 writes at the block's prefix offset.
+#define DET_BLOCKS 256
+__device__ __forceinline__ bool det_row(const OtherModes &om, const int *__restrict__ cand,
+                                        const unsigned *nc, u64 e, double tau, u64 &lin) {
+  unsigned rem = (unsigned)e;
+  double p = 0.0;
+  lin = 0;
+  for (int u = 0; u < om.d; ++u) {
+    const unsigned c = rem % nc[u];
+    rem /= nc[u];
+    const int i = cand[om.cand_off[u] + c];
+    const double qv = om.q[u][i];
+    p = (u == 0) ? qv : p * qv;
+    lin += (u64)i * om.stride[u];
+  }
+  return p > tau;
+}
+
+__global__ void __launch_bounds__(256) k_det_count(OtherModes om, double tau, DevState *st,
+                                                   const int *__restrict__ cand,
+                                                   unsigned *__restrict__ blk_cnt) {
   const u64 combos = st->combos;
-  if (combos == 0) return;
   unsigned nc[CPAL_MAXORDER];
   for (int u = 0; u < om.d; ++u) nc[u] = (unsigned)st->ncand[u];
-  const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 e = (u64)blockIdx.x * blockDim.x + threadIdx.x; e < combos; e += stride) {
-    unsigned rem = (unsigned)e;
-    double p = 0.0;
+  const u64 per = (combos + DET_BLOCKS - 1) / DET_BLOCKS;
+  const u64 b0 = (u64)blockIdx.x * per, b1 = min(combos, b0 + per);
+  unsigned cnt = 0;
+  for (u64 e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
+    u64 lin;
+    cnt += det_row(om, cand, nc, e, tau, lin) ? 1u : 0u;
+  }
+  cnt = wave_sum(cnt);
+  __shared__ unsigned ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) blk_cnt[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ void __launch_bounds__(256) k_det_scatter(OtherModes om, double tau, DevState *st,
+                                                     const int *__restrict__ cand,
+                                                     const unsigned *__restrict__ blk_cnt,
+                                                     u64 *__restrict__ det_keys, u64 det_cap) {
+  const u64 combos = st->combos;
+  unsigned nc[CPAL_MAXORDER];
+  for (int u = 0; u < om.d; ++u) nc[u] = (unsigned)st->ncand[u];
+  const u64 per = (combos + DET_BLOCKS - 1) / DET_BLOCKS;
+  const u64 b0 = (u64)blockIdx.x * per, b1 = min(combos, b0 + per);
+  __shared__ u64 sh_off;
+  if (threadIdx.x < 64) {
+    u64 before = 0, all = 0;
+    for (int b = threadIdx.x; b < DET_BLOCKS; b += 64) {
+      const u64 v = blk_cnt[b];
+      all += v;
+      if (b < (int)blockIdx.x) before += v;
+    }
+    before = wave_sum(before);
+    all = wave_sum(all);
+    if (threadIdx.x == 0) {
+      sh_off = before;
+      if (blockIdx.x == 0) st->det_count = all;
+    }
+  }
+  __syncthreads();
+  u64 off = sh_off;
+  for (u64 base = b0; base < b1; base += blockDim.x) {
+    const u64 e = base + threadIdx.x;
     u64 lin = 0;
-    for (int u = 0; u < om.d; ++u) {
-      const unsigned c = rem % nc[u];
-      rem /= nc[u];
-      const int i = cand[om.cand_off[u] + c];
-      const double qv = om.q[u][i];
-      p = (u == 0) ? qv : p * qv;
-      lin += (u64)i * om.stride[u];
-    }
-    if (p > tau) {
-      const u64 pos = atomicAdd(&st->det_count, 1ull);
-      if (pos < det_cap) det_keys[pos] = lin;
-    }
+    const unsigned pass = (e < b1 && det_row(om, cand, nc, e, tau, lin)) ? 1u : 0u;
+    unsigned tot;
+    const unsigned ex = block_excl_scan<unsigned>(pass, &tot);
+    if (pass && off + ex < det_cap) det_keys[off + ex] = lin;
+    off += tot;
   }
 }
 
@@ -225,10 +277,14 @@ __device__ __forceinline__ i64 max_draws_of(i64 s_rnd) { return 64 * s_rnd + (1l
 // draws in increasing order while fewer than s_rnd draws were accepted, so
 // the processed chunks always form a prefix of the draw sequence.  Each
 // chunk's accepted rows are compacted in draw order.
+// When the other modes' CDFs and probabilities fit (stage_n > 0 entries in
+// total), every block first copies them to shared memory and the per-draw
+// binary searches run there.
 __global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 seed,
                                               u64 stream_id, u64 t, u64 *__restrict__ buf,
                                               unsigned char *__restrict__ bpos,
-                                              unsigned *__restrict__ chunk_cnt) {
+                                              unsigned *__restrict__ chunk_cnt, int stage_n) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
   __shared__ u64 sh_c;
   __shared__ int stop;
   const int tid = threadIdx.x;
@@ -237,7 +293,28 @@ __global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 s
   const i64 max_draws = max_draws_of(s_rnd);
   const u64 max_chunks = (u64)((max_draws + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK);
   u64 W[CPAL_MAXORDER];
-  for (int u = 0; u < om.d; ++u) W[u] = om.C[u][om.n[u] - 1];
+  const u64 *Cp[CPAL_MAXORDER];
+  const double *qp[CPAL_MAXORDER];
+  for (int u = 0; u < om.d; ++u) {
+    W[u] = om.C[u][om.n[u] - 1];
+    Cp[u] = om.C[u];
+    qp[u] = om.q[u];
+  }
+  if (stage_n > 0) {   // block-uniform: every thread reaches the barrier below
+    u64 *sC = (u64 *)dsm;
+    double *sq = (double *)(dsm + sizeof(u64) * stage_n);
+    int off = 0;
+    for (int u = 0; u < om.d; ++u) {
+      for (int i = tid; i < om.n[u]; i += blockDim.x) {
+        sC[off + i] = om.C[u][i];
+        sq[off + i] = om.q[u][i];
+      }
+      Cp[u] = sC + off;
+      qp[u] = sq + off;
+      off += (int)om.n[u];
+    }
+    __syncthreads();
+  }
   for (;;) {
     if (tid == 0) {
       const u64 acc = __hip_atomic_load(&st->accepted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -261,8 +338,8 @@ __global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 s
         u64 ctr[4] = {(u64)j, (u64)om.mode[u] | ((u64)om.k << 8), t, 0ull};
         philox4x64_10(ctr, seed, stream_id);
         const u64 v = scale128(ctr[0], ctr[1], W[u]);
-        const i64 i = upper_bound_u64(om.C[u], om.n[u], v);
-        const double qv = om.q[u][i];
+        const i64 i = upper_bound_u64(Cp[u], om.n[u], v);
+        const double qv = qp[u][i];
         p = (u == 0) ? qv : p * qv;
         lin += (u64)i * om.stride[u];
       }
@@ -370,9 +447,10 @@ void launch_det_cand(const OtherModes &om, double tau, u64 cap, DevState *st, in
   hipLaunchKernelGGL(k_det_cand, dim3(1), dim3(1024), 0, s, om, tau, cap, st, cand);
 }
 void launch_det_enum(const OtherModes &om, double tau, DevState *st, const int *cand,
-                     u64 *det_keys, u64 det_cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_det_enum, dim3(1024), dim3(256), 0, s, om, tau, st, cand, det_keys,
-                     det_cap);
+                     unsigned *blk_cnt, u64 *det_keys, u64 det_cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_det_count, dim3(DET_BLOCKS), dim3(256), 0, s, om, tau, st, cand, blk_cnt);
+  hipLaunchKernelGGL(k_det_scatter, dim3(DET_BLOCKS), dim3(256), 0, s, om, tau, st, cand, blk_cnt,
+                     det_keys, det_cap);
 }
 void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, double *det_p,
                        double *kept_p, double *psum, u64 det_cap, i64 s, u64 *samp_idx,
@@ -382,8 +460,12 @@ void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, 
 }
 void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
                  unsigned char *bpos, unsigned *chunk_cnt, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_draw, dim3(grid), dim3(256), 0, s, om, st, seed, stream_id, t, buf, bpos,
-                     chunk_cnt);
+  i64 tot = 0;
+  for (int u = 0; u < om.d; ++u) tot += om.n[u];
+  const int stage_n = tot <= 4096 ? (int)tot : 0;   // <= 64 KB of shared memory
+  const size_t sh = (size_t)stage_n * (sizeof(u64) + sizeof(double));
+  hipLaunchKernelGGL(k_draw, dim3(grid), dim3(256), sh, s, om, st, seed, stream_id, t, buf, bpos,
+                     chunk_cnt, stage_n);
 }
 void launch_chunk_scan(DevState *st, const unsigned *chunk_cnt, u64 *chunk_off,
                        const unsigned char *bpos, hipStream_t s) {
