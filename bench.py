@@ -54,6 +54,9 @@ def main():
     ap.add_argument("--cpu-updates", type=int, default=80,
                     help="mode updates of the CPU oracle baseline (20 iterations = 80)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="first run a plain device copy of MB mebibytes (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -67,6 +70,13 @@ def main():
     from paper_2006_16438_amd.api import CpArlsLev
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     R, s, tau, s_fit = 25, 1 << 17, 2.0 ** -17, 1 << 20
     t0 = time.time()
     T = synth.uber4(0)

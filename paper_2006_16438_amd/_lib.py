@@ -49,11 +49,12 @@ STATS_BYTES = C.sizeof(cpal_mode_stats)
 _lib = None
 
 
-def load(path: str = LIB_PATH):
+def load(path: str | None = None):
     """Load libcpal.so and declare the C signatures; raises if it is missing."""
     global _lib
     if _lib is not None:
         return _lib
+    path = LIB_PATH if path is None else path
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
     L = C.CDLL(path)

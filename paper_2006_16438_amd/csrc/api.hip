@@ -17,9 +17,19 @@ namespace cpal {
 void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_blk, int R,
                        Decomp *out, int *flag_or, double *gram_tmp, hipStream_t s);
 int gather_tile_rows(i64 nk, int R, bool f64);
-void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
-                         const uint2 *pairs, const int *ik, const double *v64, const void *zhat,
-                         int ldz, void *P, void *M, i64 nk, int G, hipStream_t s);
+void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                         const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
+                         const int *ik, const double *v64, const void *zhat, int ldz, void *P,
+                         i64 nk, int G, hipStream_t s);
+void launch_gather_prep(const DevState *st, DevState *stw, const unsigned *flen,
+                        const unsigned *foff, i64 cap, u64 *part_len, unsigned *part_cnt,
+                        u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
+                        hipStream_t s);
+int gather_prep_blocks(i64 cap);
+int gather_row_width(int R);
+i64 gather_chunks_cap(i64 nnz);
+void launch_reduce_partials(bool f64, const DevState *st, int R, const void *P, void *M, i64 nk,
+                            int G, hipStream_t s);
 int lev_row_blocks(i64 n);
 void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
                   void *scratch, hipStream_t s);
@@ -31,9 +41,9 @@ void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, 
                        double *kept_p, double *psum, u64 det_cap, i64 s, u64 *samp_idx,
                        hipStream_t st_);
 void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
-                 unsigned char *bpos, unsigned *chunk_cnt, int grid, hipStream_t s);
+                 unsigned short *bpos, unsigned *chunk_cnt, int grid, hipStream_t s);
 void launch_chunk_scan(DevState *st, const unsigned *chunk_cnt, u64 *chunk_off,
-                       const unsigned char *bpos, hipStream_t s);
+                       const unsigned short *bpos, hipStream_t s);
 void launch_compact(const DevState *st, const u64 *buf, const unsigned *chunk_cnt,
                     const u64 *chunk_off, u64 *keys, int grid, hipStream_t s);
 void launch_unique_mark(const DevState *st, const u64 *keys, i64 cap, unsigned *flag,
@@ -45,9 +55,9 @@ void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
                  unsigned *flen, double *gpart, void *M, i64 mlen, int ldz, hipStream_t s);
 int rows_blocks(i64 cap);
-void launch_gather(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
-                   const uint2 *pairs, const int *ik, const double *v64, const void *zhat, void *M,
-                   int ldz, int grid, hipStream_t s);
+void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                   const unsigned *cidx, const uint2 *pairs, const int *ik, const double *v64,
+                   const void *zhat, void *M, int ldz, int grid, hipStream_t s);
 void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, const Decomp *dc,
                        double *A, float *A32, hipStream_t s);
 void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s);
@@ -138,7 +148,7 @@ struct cpal_ctx {
   unsigned *det_blk = nullptr;
   double *det_p = nullptr, *kept_p = nullptr, *psum = nullptr;
   u64 *dbuf = nullptr;
-  unsigned char *dpos = nullptr;
+  unsigned short *dpos = nullptr;
   unsigned *chunk_cnt = nullptr;
   u64 *chunk_off = nullptr;
   i64 max_chunks = 0;
@@ -154,11 +164,17 @@ struct cpal_ctx {
   void *M = nullptr;
   void *sort_scratch = nullptr;
   void *scan_scratch = nullptr;
-  int draw_grid = 1024;
+  int draw_grid = 256;
   int gather_grid = 2048;
   int tile_grid = 256;          // workgroups per row tile of the shared-memory gather
   int ldz = 0;                  // row stride of the weighted KRP rows (16-byte multiple)
   void *Ppart = nullptr;        // their partial accumulators
+  unsigned *chunk_first = nullptr;  // first nonempty fiber of each gather chunk
+  u64 *cpos = nullptr;              // nonempty fibers: stream position,
+  unsigned *coff = nullptr;         //   offset in the mode-sorted nonzeros,
+  unsigned *cidx = nullptr;         //   sampled row
+  u64 *gp_len = nullptr;
+  unsigned *gp_cnt = nullptr;
   double *gram_tmp = nullptr;
   // fit sample (Sec. 6.4)
   i64 fit_nz = 0, fit_n = 0, fit_ld = 0;
@@ -393,9 +409,9 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->kept_p = c->alloc<double>(s);
     c->psum = c->alloc<double>(c->det_cap / 256 + 2);
     const i64 max_draws = 64 * s + (1ll << 20);
-    c->max_chunks = (max_draws + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK;
-    c->dbuf = c->alloc<u64>((size_t)c->max_chunks * CPAL_DRAW_CHUNK);
-    c->dpos = c->alloc<unsigned char>((size_t)c->max_chunks * CPAL_DRAW_CHUNK);
+    c->max_chunks = (max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK;
+    c->dbuf = c->alloc<u64>((size_t)c->max_chunks * CPAL_KRP_CHUNK);
+    c->dpos = c->alloc<unsigned short>((size_t)c->max_chunks * CPAL_KRP_CHUNK);
     c->chunk_cnt = c->alloc<unsigned>(c->max_chunks);
     c->chunk_off = c->alloc<u64>(c->max_chunks);
     c->keys = c->alloc<u64>(s);
@@ -408,7 +424,7 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->samp_om = c->alloc<double>(s);
     c->samp_w = c->alloc<double>(s);
     const size_t tsz = c->f64 ? sizeof(double) : sizeof(float);
-    c->ldz = c->f64 ? ((R + 1) & ~1) : ((R + 3) & ~3);
+    c->ldz = gather_row_width(R);   // rows padded to the gather's unrolled width
     c->zhat = c->alloc<char>((size_t)s * c->ldz * tsz);
     c->foff = c->alloc<unsigned>(s);
     c->flen = c->alloc<unsigned>(s);
@@ -417,6 +433,12 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->M = c->alloc<char>((size_t)maxn * R * tsz);
     c->Ppart = c->alloc<char>((size_t)c->tile_grid * maxn * R * tsz);
     c->gram_tmp = c->alloc<double>(np);
+    c->chunk_first = c->alloc<unsigned>(gather_chunks_cap(c->nnz));
+    c->cpos = c->alloc<u64>(s);
+    c->coff = c->alloc<unsigned>(s);
+    c->cidx = c->alloc<unsigned>(s);
+    c->gp_len = c->alloc<u64>(gather_prep_blocks(s) + 1);
+    c->gp_cnt = c->alloc<unsigned>(gather_prep_blocks(s) + 1);
     const i64 sort_cap = std::max<i64>((i64)c->det_cap, c->nnz);
     c->sort_scratch = c->alloc<char>(sort_scratch_bytes(sort_cap, true));
     c->scan_scratch = c->alloc<char>(scan_scratch_bytes(std::max<i64>(sort_cap, s)));
@@ -569,23 +591,22 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->ukey, c->ustart,
               md.slots, md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->M,
               md.n * R, c->ldz, s);
-  scan_u32_dev(c->flen, c->fpos, c->s, &c->st->s_bar, (u64 *)&c->st->gathered, c->scan_scratch,
-               s);
+  launch_gather_prep(c->st, c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->cpos, c->coff,
+                     c->cidx, c->chunk_first, s);
+  const int tr = gather_tile_rows(md.n, R, c->f64);
+  const bool tiled = (md.n + tr - 1) / tr <= 4;
   c->stage_end(CPAL_STAGE_ROWS, tb);
   tb = c->stage_begin();
-  {
-    const int tr = gather_tile_rows(md.n, R, c->f64);
-    const i64 ntiles = (md.n + tr - 1) / tr;
-    if (ntiles <= 4)
-      launch_gather_tiled(c->f64, c->st, R, c->fpos, c->foff, md.pairs, md.ik, md.v64, c->zhat,
-                          c->ldz, c->Ppart, c->M, md.n, c->tile_grid, s);
-    else
-      launch_gather(c->f64, c->st, R, c->fpos, c->foff, md.pairs, md.ik, md.v64, c->zhat, c->M,
-                    c->ldz, c->gather_grid, s);
-  }
+  if (tiled)
+    launch_gather_tiled(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
+                        md.ik, md.v64, c->zhat, c->ldz, c->Ppart, md.n, c->tile_grid, s);
+  else
+    launch_gather(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, c->zhat,
+                  c->M, c->ldz, c->gather_grid, s);
   c->stage_end(CPAL_STAGE_GATHER, tb);
   // solve A_k = M G_s^{-1}, then the leverage of the new A_k
   tb = c->stage_begin();
+  if (tiled) launch_reduce_partials(c->f64, c->st, R, c->Ppart, c->M, md.n, c->tile_grid, s);
   launch_decomp_dev(c->gpart, &c->st->s_bar, 128, R, c->dc, &c->st->flags, c->gram_tmp, s);
   launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->dc, md.A, md.A32, s);
   c->stage_end(CPAL_STAGE_SOLVE, tb);

@@ -10,7 +10,8 @@
 #define CPAL_MAXR 64
 #define CPAL_MAXORDER 8
 #define CPAL_GRAM_ROWS 256      // rows per block of the canonical Gram summation
-#define CPAL_DRAW_CHUNK 256     // draws per chunk of the persistent draw kernel
+#define CPAL_DRAW_CHUNK 256     // draws per chunk of the persistent fit-sample draw kernel
+#define CPAL_KRP_CHUNK 1024     // draws per chunk of the KRP row draw kernel (4 per thread)
 
 typedef unsigned long long u64;
 typedef long long i64;
@@ -30,6 +31,7 @@ struct DevState {
   u64 accepted;       // accepted draws so far (atomic)
   i64 nchunks;        // chunks handed out (a prefix of the chunk sequence)
   i64 gathered;       // nnz of the sampled fibers
+  i64 n_fib;          // nonempty sampled fibers
   double p_det;
   double tau_eff;     // 1.0 when the enumeration was skipped or capped
   int flags;

@@ -68,6 +68,7 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
       z[r] = v;
       zhat[j * ldz + r] = (T)(omj * v);
     }
+    for (int r = R; r < ldz; ++r) zhat[j * ldz + r] = T(0);
     u64 h = fiber_hash(lin, hshift);
     unsigned off = 0, len = 0;
     for (;;) {
@@ -124,12 +125,13 @@ struct NzLoad<double> {
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
-                                                const u64 *__restrict__ fpos,
-                                                const unsigned *__restrict__ foff, NzLoad<T> nz,
+                                                const u64 *__restrict__ cpos,
+                                                const unsigned *__restrict__ coff,
+                                                const unsigned *__restrict__ cidx, NzLoad<T> nz,
                                                 const T *__restrict__ zhat, T *__restrict__ M,
                                                 int ldz) {
   const i64 total = st->gathered;
-  const i64 s_bar = st->s_bar;
+  const i64 nf = st->n_fib;
   const int lane = threadIdx.x & 63;
   const i64 gw = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const i64 nw = ((i64)gridDim.x * blockDim.x) >> 6;
@@ -137,14 +139,14 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
   const int col = half ? (lane & 31) : lane;
   const int sub = half ? (lane >> 5) : 0;
   for (i64 start = gw * 64; start < total; start += nw * 64) {
-    // last row j0 with fpos[j0] <= start
-    i64 lo = 0, hi = s_bar;
+    // last nonempty fiber j0 with cpos[j0] <= start; 64 positions span <= 64 fibers
+    i64 lo = 0, hi = nf;
     while (lo < hi) {
       const i64 mid = (lo + hi) >> 1;
-      if (fpos[mid] > (u64)start) hi = mid; else lo = mid + 1;
+      if (cpos[mid] > (u64)start) hi = mid; else lo = mid + 1;
     }
     const i64 j0 = lo - 1;
-    const u64 winv = (j0 + lane < s_bar) ? fpos[j0 + lane] : ~0ull;
+    const u64 winv = (j0 + lane < nf) ? cpos[j0 + lane] : ~0ull;
     const i64 p = start + lane;
     const bool valid = p < total;
     int wl = 0;
@@ -154,55 +156,156 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
       const u64 v = __shfl(winv, cand < 64 ? cand : 63, 64);
       if (cand < 64 && v <= (u64)p) wl = cand;
     }
-    i64 j = j0 + wl;
-    u64 fp = __shfl(winv, wl, 64);
-    if (valid && wl == 63) {
-      // the row lies beyond the window: search the whole prefix array
-      i64 l2 = j0 + 63, h2 = s_bar;
-      while (l2 < h2) {
-        const i64 mid = (l2 + h2) >> 1;
-        if (fpos[mid] > (u64)p) h2 = mid; else l2 = mid + 1;
-      }
-      j = l2 - 1;
-      fp = fpos[j];
-    }
+    const i64 j = j0 + wl;
+    const u64 fp = __shfl(winv, wl, 64);
     int ik = 0;
     T x = T(0);
-    if (valid) nz.get((u64)foff[j] + (u64)(p - (i64)fp), ik, x);
+    i64 zr = 0;
+    if (valid) {
+      nz.get((u64)coff[j] + (u64)(p - (i64)fp), ik, x);
+      zr = cidx[j];
+    }
     for (int src = 0; src < 64; src += half ? 2 : 1) {
       const int sl = src + sub;
       const int ik_s = __shfl(ik, sl, 64);
       const T x_s = __shfl(x, sl, 64);
-      const i64 j_s = __shfl(j, sl, 64);
+      const i64 z_s = __shfl(zr, sl, 64);
       const bool v_s = __shfl((int)valid, sl, 64) != 0;
-      if (v_s && col < R) unsafeAtomicAdd(&M[(i64)ik_s * R + col], x_s * zhat[j_s * ldz + col]);
+      if (v_s && col < R) unsafeAtomicAdd(&M[(i64)ik_s * R + col], x_s * zhat[z_s * ldz + col]);
     }
   }
 }
 
 // Gather with per-workgroup accumulation in shared memory.  The stream of
 // gathered nonzeros is cut into chunks of GT_CHUNK positions; workgroup g of
-// row tile y takes chunks g, g+G, ...  For a chunk the workgroup finds the
-// first and last sampled rows by two binary searches, stages their fiber
-// prefix sums in shared memory (GT_WIN entries) and every position finds its
-// row there.  Contributions x * omega_j z_j with i_k inside the tile go to a
-// shared accumulator (tile_rows x R) with shared-memory atomics; at the end
-// the workgroup writes its partial M tile to P[g] (no global atomics).  The
+// row tile y takes chunks g, g+G, ...  For a chunk the workgroup reads the
+// first and last nonempty fibers from chunk_first, stages their stream
+// positions in shared memory and every position finds its fiber there.
+// Contributions x * omega_j z_j with i_k inside the tile go to a shared
+// accumulator (tile_rows x R) with shared-memory atomics; at the end the
+// workgroup writes its partial M tile to P[g] (no global atomics).  The
 // partials are summed by k_reduce_partials.
 #define GT_THREADS 512
 #define GT_PER_THREAD 4
 #define GT_CHUNK (GT_THREADS * GT_PER_THREAD)
 #define GT_WIN 4096
+
+// Gather preparation: one scan over the sampled rows computes the stream
+// position of every fiber (exclusive prefix of the lengths) and compacts the
+// nonempty fibers: for the c-th nonempty fiber, cpos = first stream position,
+// coff = offset in the mode-sorted nonzeros, cidx = its sampled row (for the
+// weighted KRP row).  Empty fibers add nothing to M (they still enter G_s),
+// and with only nonempty fibers a chunk of GT_CHUNK positions spans at most
+// GT_CHUNK + 1 of them.
+#define GP_TILE 4096
+__global__ void __launch_bounds__(256) k_gp_part(const DevState *st, const unsigned *__restrict__ flen,
+                                                 u64 *__restrict__ part_len,
+                                                 unsigned *__restrict__ part_cnt) {
+  const i64 n = st->s_bar;
+  const i64 base = (i64)blockIdx.x * GP_TILE;
+  u64 sl = 0;
+  unsigned sc = 0;
+  for (int r = 0; r < GP_TILE / 256; ++r) {
+    const i64 i = base + r * 256 + threadIdx.x;
+    if (i < n) {
+      const unsigned l = flen[i];
+      sl += l;
+      sc += l > 0 ? 1u : 0u;
+    }
+  }
+  sl = wave_sum(sl);
+  sc = wave_sum(sc);
+  __shared__ u64 wl[4];
+  __shared__ unsigned wc[4];
+  if ((threadIdx.x & 63) == 0) { wl[threadIdx.x >> 6] = sl; wc[threadIdx.x >> 6] = sc; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part_len[blockIdx.x] = wl[0] + wl[1] + wl[2] + wl[3];
+    part_cnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_gp_top(DevState *st, u64 *__restrict__ part_len,
+                                                 unsigned *__restrict__ part_cnt) {
+  const i64 n = st->s_bar;
+  const int nb = (int)((n + GP_TILE - 1) / GP_TILE);
+  u64 carry_l = 0, carry_c = 0;
+  for (int b0 = 0; b0 < nb; b0 += 1024) {
+    const int b = b0 + threadIdx.x;
+    const u64 vl = b < nb ? part_len[b] : 0;
+    const u64 vc = b < nb ? part_cnt[b] : 0;
+    u64 tl, tc;
+    const u64 el = block_excl_scan<u64>(vl, &tl);
+    const u64 ec = block_excl_scan<u64>(vc, &tc);
+    if (b < nb) { part_len[b] = carry_l + el; part_cnt[b] = (unsigned)(carry_c + ec); }
+    carry_l += tl;
+    carry_c += tc;
+  }
+  if (threadIdx.x == 0) {
+    st->gathered = (i64)carry_l;
+    st->n_fib = (i64)carry_c;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gp_apply(const DevState *st, const unsigned *__restrict__ flen,
+                                                  const unsigned *__restrict__ foff,
+                                                  const u64 *__restrict__ part_len,
+                                                  const unsigned *__restrict__ part_cnt,
+                                                  u64 *__restrict__ cpos, unsigned *__restrict__ coff,
+                                                  unsigned *__restrict__ cidx) {
+  const i64 n = st->s_bar;
+  const i64 base = (i64)blockIdx.x * GP_TILE;
+  if (base >= n) return;
+  u64 cl = part_len[blockIdx.x];
+  u64 cc = part_cnt[blockIdx.x];
+  for (int r = 0; r < GP_TILE / 256; ++r) {
+    const i64 i = base + r * 256 + threadIdx.x;
+    const unsigned l = i < n ? flen[i] : 0u;
+    u64 tl, tc;
+    const u64 el = block_excl_scan<u64>((u64)l, &tl);
+    const u64 ec = block_excl_scan<u64>((u64)(l > 0), &tc);
+    if (l > 0) {
+      const u64 c = cc + ec;
+      cpos[c] = cl + el;
+      coff[c] = foff[i];
+      cidx[c] = (unsigned)i;
+    }
+    cl += tl;
+    cc += tc;
+  }
+}
+
+// chunk_first[ch] = the nonempty fiber holding stream position ch*GT_CHUNK.
+__global__ void __launch_bounds__(256) k_chunk_first(const DevState *st, const u64 *__restrict__ cpos,
+                                                     unsigned *__restrict__ chunk_first) {
+  const i64 nf = st->n_fib;
+  const u64 total = (u64)st->gathered;
+  for (i64 c = (i64)blockIdx.x * blockDim.x + threadIdx.x; c < nf; c += (i64)gridDim.x * blockDim.x) {
+    const u64 a = cpos[c];
+    const u64 b = (c + 1 < nf) ? cpos[c + 1] : total;
+    const u64 c0 = (a + GT_CHUNK - 1) / GT_CHUNK, c1 = (b - 1) / GT_CHUNK;
+    for (u64 ch = c0; ch <= c1; ++ch) chunk_first[ch] = (unsigned)c;
+  }
+}
+
+// Vector type of 16 bytes holding 16/sizeof(T) elements of T.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+
 template <typename T, int RM>
 __global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
-    const DevState *st, int R, const u64 *__restrict__ fpos, const unsigned *__restrict__ foff,
-    NzLoad<T> nz, const T *__restrict__ zhat, int ldz, T *__restrict__ P, i64 nk, int tile_rows) {
+    const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
+    const T *__restrict__ zhat, int ldz, T *__restrict__ P, i64 nk, int tile_rows) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VN = Vec16<T>::n;
+  constexpr int NV = RM / VN;                           // 16-byte loads per KRP row
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  u64 *win = (u64 *)smem_raw;                          // GT_WIN fiber prefix sums
+  u64 *win = (u64 *)smem_raw;                          // GT_WIN fiber start positions
   T *acc = (T *)(smem_raw + sizeof(u64) * GT_WIN);      // tile_rows x R
-  __shared__ i64 sh_jlo, sh_jhi;
   const i64 total = st->gathered;
-  const i64 s_bar = st->s_bar;
+  const i64 nf = st->n_fib;
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
   const int g = blockIdx.x, G = gridDim.x;
   if (g >= nch) return;
@@ -213,57 +316,58 @@ __global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
   for (i64 c = g; c < nch; c += G) {
     const i64 base = c * GT_CHUNK;
     const i64 last = min(total, base + GT_CHUNK) - 1;
-    if (tid == 0 || tid == 64) {
-      // last row j with fpos[j] <= position
-      const i64 pos = tid == 0 ? base : last;
-      i64 lo = 0, hi = s_bar;
-      while (lo < hi) {
-        const i64 mid = (lo + hi) >> 1;
-        if (fpos[mid] > (u64)pos) hi = mid; else lo = mid + 1;
-      }
-      if (tid == 0) sh_jlo = lo - 1; else sh_jhi = lo - 1;
-    }
+    const i64 jlo = chunk_first[c];
+    const i64 jhi = (c + 1 < nch) ? (i64)chunk_first[c + 1] : nf - 1;
+    const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
+    __syncthreads();   // previous chunk's readers of win are done
+    for (int e = tid; e < nwin; e += GT_THREADS) win[e] = cpos[jlo + e];
     __syncthreads();
-    const i64 jlo = sh_jlo, jhi = sh_jhi;
-    const i64 nwin = jhi - jlo + 1;
-    const bool in_win = nwin <= GT_WIN;
-    if (in_win)
-      for (i64 e = tid; e < nwin; e += GT_THREADS) win[e] = fpos[jlo + e];
-    __syncthreads();
+    // Every load below is unconditional (positions past the chunk are clamped
+    // to its last position and masked at the end), so the loads of all
+    // GT_PER_THREAD positions are in flight together.
+    int jw[GT_PER_THREAD];
+    u64 ee[GT_PER_THREAD];
+    bool vv[GT_PER_THREAD];
+#pragma unroll
     for (int u = 0; u < GT_PER_THREAD; ++u) {
-      const i64 p = base + (i64)u * GT_THREADS + tid;
-      if (p > last) continue;
-      i64 j;
-      u64 fp;
-      if (in_win) {
-        int lo = 0, hi = (int)nwin;   // last index with win[idx] <= p
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (win[mid] <= (u64)p) lo = mid; else hi = mid;
-        }
-        j = jlo + lo;
-        fp = win[lo];
-      } else {
-        i64 lo = jlo, hi = jhi + 1;
-        while (hi - lo > 1) {
-          const i64 mid = (lo + hi) >> 1;
-          if (fpos[mid] <= (u64)p) lo = mid; else hi = mid;
-        }
-        j = lo;
-        fp = fpos[lo];
+      const i64 pu = base + (i64)u * GT_THREADS + tid;
+      vv[u] = pu <= last;
+      const u64 p = (u64)min(pu, last);
+      int lo = 0, hi = nwin;   // last index with win[idx] <= p
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (win[mid] <= p) lo = mid; else hi = mid;
       }
-      int ik;
-      T x;
-      nz.get((u64)foff[j] + (u64)(p - (i64)fp), ik, x);
-      if (ik < r0 || ik >= r0 + rows) continue;
-      const T *zr = zhat + j * ldz;
-      T *ar = acc + (i64)(ik - r0) * R;
+      jw[u] = lo;
+      ee[u] = p - win[lo];
+    }
+    unsigned zrow[GT_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      ee[u] += coff[jlo + jw[u]];
+      zrow[u] = cidx[jlo + jw[u]];
+    }
+    int ik[GT_PER_THREAD];
+    T xx[GT_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) nz.get(ee[u], ik[u], xx[u]);
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      V zv[NV];
+      const V *zr = (const V *)(zhat + (i64)zrow[u] * ldz);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) zv[v] = zr[v];
+      const bool mine = vv[u] && ik[u] >= r0 && ik[u] < r0 + rows;
+      if (!mine) continue;
+      T *ar = acc + (i64)(ik[u] - r0) * R;
+      const T x = xx[u];
+      const T *zs = (const T *)zv;
 #pragma unroll
       for (int r = 0; r < RM; ++r)
-        if (r < R) unsafeAtomicAdd(&ar[r], x * zr[r]);
+        if (r < R) unsafeAtomicAdd(&ar[r], x * zs[r]);
     }
-    __syncthreads();
   }
+  __syncthreads();
   T *out = P + (i64)g * nk * R + r0 * R;
   for (int e = tid; e < rows * R; e += GT_THREADS) out[e] = acc[e];
 }
@@ -524,49 +628,70 @@ int gather_tile_rows(i64 nk, int R, bool f64) {
   return (int)std::min<i64>(rows, nk);
 }
 
-void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
-                         const uint2 *pairs, const int *ik, const double *v64, const void *zhat,
-                         int ldz, void *P, void *M, i64 nk, int G, hipStream_t s) {
+void launch_gather_prep(const DevState *st, DevState *stw, const unsigned *flen,
+                        const unsigned *foff, i64 cap, u64 *part_len, unsigned *part_cnt,
+                        u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
+                        hipStream_t s) {
+  const int nb = (int)((cap + GP_TILE - 1) / GP_TILE);
+  hipLaunchKernelGGL(k_gp_part, dim3(nb), dim3(256), 0, s, st, flen, part_len, part_cnt);
+  hipLaunchKernelGGL(k_gp_top, dim3(1), dim3(1024), 0, s, stw, part_len, part_cnt);
+  hipLaunchKernelGGL(k_gp_apply, dim3(nb), dim3(256), 0, s, st, flen, foff, part_len, part_cnt,
+                     cpos, coff, cidx);
+  hipLaunchKernelGGL(k_chunk_first, dim3(grid_for(cap, 256, 2048)), dim3(256), 0, s, st, cpos,
+                     chunk_first);
+}
+
+int gather_prep_blocks(i64 cap) { return (int)((cap + GP_TILE - 1) / GP_TILE); }
+
+i64 gather_chunks_cap(i64 nnz) { return nnz / GT_CHUNK + 2; }
+
+int gather_row_width(int R) { return R <= 16 ? 16 : (R <= 32 ? 32 : 64); }
+
+void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                         const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
+                         const int *ik, const double *v64, const void *zhat, int ldz, void *P,
+                         i64 nk, int G, hipStream_t s) {
   const int tr = gather_tile_rows(nk, R, f64);
   const int ntiles = (int)((nk + tr - 1) / tr);
   const size_t elem = f64 ? sizeof(double) : sizeof(float);
   const size_t sh = sizeof(u64) * GT_WIN + elem * (size_t)tr * R;
-  const i64 nkR = nk * R;
-  const int rg = grid_for(nkR, 256, 4096);
   const dim3 grid(G, ntiles), blk(GT_THREADS);
+  const int rm = gather_row_width(R);
+#define CPAL_GT(TT, RMV, NZ)                                                                      \
+  hipLaunchKernelGGL((k_gather_tile<TT, RMV>), grid, blk, sh, s, st, R, cpos, coff, cidx,        \
+                     chunk_first, NZ, (const TT *)zhat, ldz, (TT *)P, nk, tr)
   if (f64) {
     NzLoad<double> nz{ik, v64};
-    if (R <= 32)
-      hipLaunchKernelGGL((k_gather_tile<double, 32>), grid, blk, sh, s, st, R, fpos, foff, nz,
-                         (const double *)zhat, ldz, (double *)P, nk, tr);
-    else
-      hipLaunchKernelGGL((k_gather_tile<double, 64>), grid, blk, sh, s, st, R, fpos, foff, nz,
-                         (const double *)zhat, ldz, (double *)P, nk, tr);
-    hipLaunchKernelGGL(k_reduce_partials<double>, dim3(rg), dim3(256), 0, s, st,
-                       (const double *)P, nkR, G, (double *)M);
+    if (rm == 16) CPAL_GT(double, 16, nz); else if (rm == 32) CPAL_GT(double, 32, nz); else CPAL_GT(double, 64, nz);
   } else {
     NzLoad<float> nz{pairs};
-    if (R <= 32)
-      hipLaunchKernelGGL((k_gather_tile<float, 32>), grid, blk, sh, s, st, R, fpos, foff, nz,
-                         (const float *)zhat, ldz, (float *)P, nk, tr);
-    else
-      hipLaunchKernelGGL((k_gather_tile<float, 64>), grid, blk, sh, s, st, R, fpos, foff, nz,
-                         (const float *)zhat, ldz, (float *)P, nk, tr);
-    hipLaunchKernelGGL(k_reduce_partials<float>, dim3(rg), dim3(256), 0, s, st, (const float *)P,
-                       nkR, G, (float *)M);
+    if (rm == 16) CPAL_GT(float, 16, nz); else if (rm == 32) CPAL_GT(float, 32, nz); else CPAL_GT(float, 64, nz);
   }
+#undef CPAL_GT
 }
 
-void launch_gather(bool f64, const DevState *st, int R, const u64 *fpos, const unsigned *foff,
-                   const uint2 *pairs, const int *ik, const double *v64, const void *zhat, void *M,
-                   int ldz, int grid, hipStream_t s) {
+void launch_reduce_partials(bool f64, const DevState *st, int R, const void *P, void *M, i64 nk,
+                            int G, hipStream_t s) {
+  const i64 nkR = nk * R;
+  const int rg = grid_for(nkR, 256, 4096);
+  if (f64)
+    hipLaunchKernelGGL(k_reduce_partials<double>, dim3(rg), dim3(256), 0, s, st,
+                       (const double *)P, nkR, G, (double *)M);
+  else
+    hipLaunchKernelGGL(k_reduce_partials<float>, dim3(rg), dim3(256), 0, s, st, (const float *)P,
+                       nkR, G, (float *)M);
+}
+
+void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                   const unsigned *cidx, const uint2 *pairs, const int *ik, const double *v64,
+                   const void *zhat, void *M, int ldz, int grid, hipStream_t s) {
   if (f64) {
     NzLoad<double> nz{ik, v64};
-    hipLaunchKernelGGL(k_gather<double>, dim3(grid), dim3(256), 0, s, st, R, fpos, foff, nz,
+    hipLaunchKernelGGL(k_gather<double>, dim3(grid), dim3(256), 0, s, st, R, cpos, coff, cidx, nz,
                        (const double *)zhat, (double *)M, ldz);
   } else {
     NzLoad<float> nz{pairs};
-    hipLaunchKernelGGL(k_gather<float>, dim3(grid), dim3(256), 0, s, st, R, fpos, foff, nz,
+    hipLaunchKernelGGL(k_gather<float>, dim3(grid), dim3(256), 0, s, st, R, cpos, coff, cidx, nz,
                        (const float *)zhat, (float *)M, ldz);
   }
 }

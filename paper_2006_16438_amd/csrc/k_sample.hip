@@ -277,12 +277,18 @@ __device__ __forceinline__ i64 max_draws_of(i64 s_rnd) { return 64 * s_rnd + (1l
 // draws in increasing order while fewer than s_rnd draws were accepted, so
 // the processed chunks always form a prefix of the draw sequence.  Each
 // chunk's accepted rows are compacted in draw order.
-// When the other modes' CDFs and probabilities fit (stage_n > 0 entries in
-// total), every block first copies them to shared memory and the per-draw
-// binary searches run there.
+// Persistent draw kernel (Alg. 2): blocks take chunks of CPAL_KRP_CHUNK
+// consecutive draws in increasing order while fewer than s_rnd draws were
+// accepted, so the processed chunks always form a prefix of the draw
+// sequence.  Thread t makes draws 4t..4t+3 of a chunk (four independent
+// Philox streams), and the chunk's accepted rows are compacted in draw
+// order.  When the other modes' CDFs and probabilities fit (stage_n > 0
+// entries), every block first copies them to shared memory and the binary
+// searches run there.
+#define DRAWS_PER_THREAD (CPAL_KRP_CHUNK / 256)
 __global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 seed,
                                               u64 stream_id, u64 t, u64 *__restrict__ buf,
-                                              unsigned char *__restrict__ bpos,
+                                              unsigned short *__restrict__ bpos,
                                               unsigned *__restrict__ chunk_cnt, int stage_n) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
   __shared__ u64 sh_c;
@@ -291,7 +297,8 @@ __global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 s
   const i64 s_rnd = st->s_rnd;
   const double tau = st->tau_eff;
   const i64 max_draws = max_draws_of(s_rnd);
-  const u64 max_chunks = (u64)((max_draws + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK);
+  const u64 max_chunks = (u64)((max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK);
+  if (s_rnd == 0) return;
   u64 W[CPAL_MAXORDER];
   const u64 *Cp[CPAL_MAXORDER];
   const double *qp[CPAL_MAXORDER];
@@ -329,27 +336,46 @@ __global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 s
     __syncthreads();
     if (stop) break;
     const u64 c = sh_c;
-    const i64 j = (i64)c * CPAL_DRAW_CHUNK + tid;
-    unsigned ok = 0;
-    u64 lin = 0;
-    if (j < max_draws) {
-      double p = 0.0;
-      for (int u = 0; u < om.d; ++u) {
-        u64 ctr[4] = {(u64)j, (u64)om.mode[u] | ((u64)om.k << 8), t, 0ull};
-        philox4x64_10(ctr, seed, stream_id);
-        const u64 v = scale128(ctr[0], ctr[1], W[u]);
-        const i64 i = upper_bound_u64(Cp[u], om.n[u], v);
-        const double qv = qp[u][i];
-        p = (u == 0) ? qv : p * qv;
-        lin += (u64)i * om.stride[u];
+    const i64 j0 = (i64)c * CPAL_KRP_CHUNK + (i64)DRAWS_PER_THREAD * tid;
+    u64 lin[DRAWS_PER_THREAD];
+    double p[DRAWS_PER_THREAD];
+#pragma unroll
+    for (int v = 0; v < DRAWS_PER_THREAD; ++v) { lin[v] = 0; p[v] = 0.0; }
+    for (int u = 0; u < om.d; ++u) {
+      u64 ctr[DRAWS_PER_THREAD][4];
+#pragma unroll
+      for (int v = 0; v < DRAWS_PER_THREAD; ++v) {
+        ctr[v][0] = (u64)(j0 + v);
+        ctr[v][1] = (u64)om.mode[u] | ((u64)om.k << 8);
+        ctr[v][2] = t;
+        ctr[v][3] = 0ull;
+        philox4x64_10(ctr[v], seed, stream_id);
       }
-      ok = p <= tau;
+#pragma unroll
+      for (int v = 0; v < DRAWS_PER_THREAD; ++v) {
+        const u64 x = scale128(ctr[v][0], ctr[v][1], W[u]);
+        const i64 i = upper_bound_u64(Cp[u], om.n[u], x);
+        const double qv = qp[u][i];
+        p[v] = (u == 0) ? qv : p[v] * qv;
+        lin[v] += (u64)i * om.stride[u];
+      }
+    }
+    unsigned mine = 0, okm = 0;
+#pragma unroll
+    for (int v = 0; v < DRAWS_PER_THREAD; ++v) {
+      const bool ok = (j0 + v < max_draws) && p[v] <= tau;
+      okm |= (ok ? 1u : 0u) << v;
+      mine += ok ? 1u : 0u;
     }
     unsigned tot;
-    const unsigned ex = block_excl_scan<unsigned>(ok, &tot);
-    if (ok) {
-      buf[c * CPAL_DRAW_CHUNK + ex] = lin;
-      bpos[c * CPAL_DRAW_CHUNK + ex] = (unsigned char)tid;
+    unsigned pos = block_excl_scan<unsigned>(mine, &tot);
+#pragma unroll
+    for (int v = 0; v < DRAWS_PER_THREAD; ++v) {
+      if (okm & (1u << v)) {
+        buf[c * CPAL_KRP_CHUNK + pos] = lin[v];
+        bpos[c * CPAL_KRP_CHUNK + pos] = (unsigned short)(DRAWS_PER_THREAD * tid + v);
+        ++pos;
+      }
     }
     if (tid == 0) {
       chunk_cnt[c] = tot;
@@ -364,12 +390,12 @@ __global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 s
 __global__ void __launch_bounds__(1024) k_chunk_scan(DevState *st,
                                                      const unsigned *__restrict__ chunk_cnt,
                                                      u64 *__restrict__ chunk_off,
-                                                     const unsigned char *__restrict__ bpos) {
+                                                     const unsigned short *__restrict__ bpos) {
   __shared__ i64 sh_draws;
   const int tid = threadIdx.x;
   const i64 s_rnd = st->s_rnd;
   const i64 max_draws = max_draws_of(s_rnd);
-  const u64 max_chunks = (u64)((max_draws + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK);
+  const u64 max_chunks = (u64)((max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK);
   const u64 Q = min(st->chunk_next, max_chunks);
   if (tid == 0) sh_draws = -1;
   u64 carry = 0;
@@ -382,7 +408,7 @@ __global__ void __launch_bounds__(1024) k_chunk_scan(DevState *st,
       const u64 off = carry + ex;
       chunk_off[b] = off;
       if (s_rnd > 0 && off <= (u64)(s_rnd - 1) && (u64)(s_rnd - 1) < off + v)
-        sh_draws = (i64)b * CPAL_DRAW_CHUNK + bpos[b * CPAL_DRAW_CHUNK + (s_rnd - 1 - off)] + 1;
+        sh_draws = (i64)b * CPAL_KRP_CHUNK + bpos[b * CPAL_KRP_CHUNK + (s_rnd - 1 - off)] + 1;
     }
     carry += tot;
   }
@@ -413,8 +439,8 @@ __global__ void __launch_bounds__(256) k_compact(const DevState *st, const u64 *
     const u64 off = chunk_off[q];
     if (off >= used) continue;
     const unsigned c = chunk_cnt[q];
-    if (threadIdx.x < c && off + threadIdx.x < used)
-      keys[off + threadIdx.x] = buf[(u64)q * CPAL_DRAW_CHUNK + threadIdx.x];
+    for (unsigned i = threadIdx.x; i < c && off + i < used; i += blockDim.x)
+      keys[off + i] = buf[(u64)q * CPAL_KRP_CHUNK + i];
   }
 }
 
@@ -459,7 +485,7 @@ void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, 
                      psum, det_cap, s, samp_idx, (unsigned char *)nullptr);
 }
 void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
-                 unsigned char *bpos, unsigned *chunk_cnt, int grid, hipStream_t s) {
+                 unsigned short *bpos, unsigned *chunk_cnt, int grid, hipStream_t s) {
   i64 tot = 0;
   for (int u = 0; u < om.d; ++u) tot += om.n[u];
   const int stage_n = tot <= 4096 ? (int)tot : 0;   // <= 64 KB of shared memory
@@ -468,7 +494,7 @@ void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u6
                      chunk_cnt, stage_n);
 }
 void launch_chunk_scan(DevState *st, const unsigned *chunk_cnt, u64 *chunk_off,
-                       const unsigned char *bpos, hipStream_t s) {
+                       const unsigned short *bpos, hipStream_t s) {
   hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(1024), 0, s, st, chunk_cnt, chunk_off, bpos);
 }
 void launch_compact(const DevState *st, const u64 *buf, const unsigned *chunk_cnt,
