@@ -42,14 +42,12 @@ void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, 
                        hipStream_t st_);
 void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
                  unsigned short *bpos, unsigned *chunk_cnt, int grid, hipStream_t s);
-void launch_chunk_scan(DevState *st, const unsigned *chunk_cnt, u64 *chunk_off,
-                       const unsigned short *bpos, hipStream_t s);
-void launch_compact(const DevState *st, const u64 *buf, const unsigned *chunk_cnt,
-                    const u64 *chunk_off, u64 *keys, int grid, hipStream_t s);
-void launch_unique_mark(const DevState *st, const u64 *keys, i64 cap, unsigned *flag,
-                        hipStream_t s);
-void launch_unique_scatter(const DevState *st, const u64 *keys, i64 cap, const unsigned *flag,
-                           const u64 *upos, u64 *ukey, u64 *ustart, hipStream_t s);
+void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
+                    const unsigned short *bpos, u64 *keys, int grid, hipStream_t s);
+u64 *sort_keys_pp(u64 *keys, unsigned *vals, u64 *tmp_keys, unsigned *tmp_vals, void *scratch,
+                  i64 cap, const i64 *count_dev, i64 count_host, int bits, hipStream_t s);
+void unique_runs(const u64 *keys, i64 cap, const i64 *n_dev, u64 *n_runs, u64 *ukey, u64 *ustart,
+                 void *scratch, hipStream_t s);
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
                  double *samp_om, double *samp_w, const u64 *ukey, const u64 *ustart,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
@@ -150,11 +148,9 @@ struct cpal_ctx {
   u64 *dbuf = nullptr;
   unsigned short *dpos = nullptr;
   unsigned *chunk_cnt = nullptr;
-  u64 *chunk_off = nullptr;
   i64 max_chunks = 0;
   u64 *keys = nullptr, *keys_tmp = nullptr;
-  unsigned *uflag = nullptr;
-  u64 *upos = nullptr, *ukey = nullptr, *ustart = nullptr;
+  u64 *ukey = nullptr, *ustart = nullptr;
   u64 *samp_idx = nullptr;
   double *samp_om = nullptr, *samp_w = nullptr;
   void *zhat = nullptr;
@@ -413,11 +409,8 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->dbuf = c->alloc<u64>((size_t)c->max_chunks * CPAL_KRP_CHUNK);
     c->dpos = c->alloc<unsigned short>((size_t)c->max_chunks * CPAL_KRP_CHUNK);
     c->chunk_cnt = c->alloc<unsigned>(c->max_chunks);
-    c->chunk_off = c->alloc<u64>(c->max_chunks);
     c->keys = c->alloc<u64>(s);
     c->keys_tmp = c->alloc<u64>(s);
-    c->uflag = c->alloc<unsigned>(s);
-    c->upos = c->alloc<u64>(s);
     c->ukey = c->alloc<u64>(s);
     c->ustart = c->alloc<u64>(s + 1);
     c->samp_idx = c->alloc<u64>(s);
@@ -577,14 +570,11 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   // random rows (Alg. 2) and combining repeats (Sec. 4.1, 4.3)
   launch_draw(om, c->st, c->seed, c->stream_id, c->t, c->dbuf, c->dpos, c->chunk_cnt,
               c->draw_grid, s);
-  launch_chunk_scan(c->st, c->chunk_cnt, c->chunk_off, c->dpos, s);
-  launch_compact(c->st, c->dbuf, c->chunk_cnt, c->chunk_off, c->keys, c->draw_grid, s);
-  sort_keys(c->keys, nullptr, c->keys_tmp, nullptr, c->sort_scratch, c->s,
-            &c->st->s_rnd_used, 0, md.key_bits, s);
-  launch_unique_mark(c->st, c->keys, c->s, c->uflag, s);
-  scan_u32_dev(c->uflag, c->upos, c->s, &c->st->s_rnd_used, (u64 *)&c->st->n_urnd,
-               c->scan_scratch, s);
-  launch_unique_scatter(c->st, c->keys, c->s, c->uflag, c->upos, c->ukey, c->ustart, s);
+  launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->draw_grid, s);
+  const u64 *sorted = sort_keys_pp(c->keys, nullptr, c->keys_tmp, nullptr, c->sort_scratch, c->s,
+                                   &c->st->s_rnd_used, 0, md.key_bits, s);
+  unique_runs(sorted, c->s, &c->st->s_rnd_used, (u64 *)&c->st->n_urnd, c->ukey, c->ustart,
+              c->scan_scratch, s);
   c->stage_end(CPAL_STAGE_SAMPLE, tb);
   tb = c->stage_begin();
   // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M

@@ -146,6 +146,49 @@ __device__ bool chol_right(double *S, double *L, int R, double tol, int *fail_sh
   return true;
 }
 
+// Register form of the same right-looking Cholesky for R <= RM <= 32: lane
+// i holds row i of the lower triangle of S in registers; column j's pivot is
+// broadcast from lane j, and the column entries L(l,j) from lane l.  Every
+// entry sees the same operations in the same order as chol_right.  S and L
+// are shared-memory R x R arrays (S read, L written).  One wavefront.
+template <int RM>
+__device__ bool chol_regs(const double *S, double *L, int R, double tol) {
+  const int lane = threadIdx.x;
+  double g[RM];
+#pragma unroll
+  for (int l = 0; l < RM; ++l) g[l] = (lane < R && l < R) ? S[lane * R + l] : 0.0;
+  double lcol[RM];   // this lane's entries L(lane, j)
+#pragma unroll
+  for (int j = 0; j < RM; ++j) lcol[j] = 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    if (j < R && ok) {
+      const double piv = __shfl(g[j], j, 64);
+      if (!(piv > tol)) {
+        ok = false;
+      } else {
+        const double ljj = sqrt(piv);
+        const double lij = (lane == j) ? ljj : ((lane > j && lane < R) ? g[j] / ljj : 0.0);
+        lcol[j] = lij;
+#pragma unroll
+        for (int l = j + 1; l < RM; ++l) {
+          if (l < R) {
+            const double llj = __shfl(lij, l, 64);
+            if (lane >= l && lane < R) g[l] = g[l] - lij * llj;
+          }
+        }
+      }
+    }
+  }
+  if (ok) {
+#pragma unroll
+    for (int j = 0; j < RM; ++j)
+      if (lane < R && j < R) L[lane * R + j] = lcol[j];
+  }
+  return ok;
+}
+
 // Leverage of a factor with fewer rows than columns (n < R <= 64): if A A^T
 // (n x n, each entry summed over the R columns in ascending order) passes the
 // Cholesky pivot test, A has full row rank, range(A) = R^n and every
@@ -227,9 +270,21 @@ __global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, 
   double maxdiag = 0.0;
   for (int j = 0; j < R; ++j) maxdiag = fmax(maxdiag, G[j * R + j]);
   const double tol = ((double)R * 0x1p-52) * maxdiag;
-  for (int e = lane; e < R * R; e += 64) slab[e] = G[e];   // working copy
-  __syncthreads();
-  chol_right(slab, L, R, tol, &fail);
+  if (R <= 16) {
+    for (int e = lane; e < R * R; e += 64) L[e] = 0.0;
+    __syncthreads();
+    const bool ok = chol_regs<16>(G, L, R, tol);
+    if (lane == 0) fail = ok ? 0 : 1;
+  } else if (R <= 32) {
+    for (int e = lane; e < R * R; e += 64) L[e] = 0.0;
+    __syncthreads();
+    const bool ok = chol_regs<32>(G, L, R, tol);
+    if (lane == 0) fail = ok ? 0 : 1;
+  } else {
+    for (int e = lane; e < R * R; e += 64) slab[e] = G[e];   // working copy
+    __syncthreads();
+    chol_right(slab, L, R, tol, &fail);
+  }
   __syncthreads();
   if (!fail) {
     for (int e = lane; e < R * R; e += 64) out->L[e] = L[e];

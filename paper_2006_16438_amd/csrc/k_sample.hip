@@ -186,6 +186,7 @@ __global__ void __launch_bounds__(256) k_det_scatter(OtherModes om, double tau, 
   }
 }
 
+#define DET_STAGE 8192
 // Deterministic rows: truncation to the s most probable when needed, output
 // to samp_idx[0..s_det), p_det, s_rnd.  One block of 1024 threads.
 __global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st,
@@ -246,11 +247,23 @@ __global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st
     for (i64 i = tid; i < n; i += blockDim.x) { samp_idx[i] = det_keys[i]; kept_p[i] = det_p[i]; }
   }
   __syncthreads();
+  // p_det in blocks of 256 (ascending linear index), partials summed in
+  // order; the probabilities are staged in shared memory when they fit
+  __shared__ double sp[DET_STAGE];
   const i64 nb = (n + 255) / 256;
+  const bool staged = n <= DET_STAGE;
+  if (staged)
+    for (i64 i = tid; i < n; i += blockDim.x) sp[i] = kept_p[i];
+  __syncthreads();
   for (i64 b = tid; b < nb; b += blockDim.x) {
     double part = 0.0;
     const i64 e = min(n, (b + 1) * 256);
-    for (i64 i = b * 256; i < e; ++i) part = part + kept_p[i];
+    if (staged) {
+      for (i64 i = b * 256; i < e; ++i) part = part + sp[i];
+    } else {
+#pragma unroll 16
+      for (i64 i = b * 256; i < e; ++i) part = part + kept_p[i];
+    }
     psum[b] = part;
   }
   __syncthreads();
@@ -385,13 +398,18 @@ __global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 s
   }
 }
 
-// Exclusive scan of the chunk counts, the number of rows used, the draw
-// count (index of the s_rnd-th accepted draw + 1).  One block.
-__global__ void __launch_bounds__(1024) k_chunk_scan(DevState *st,
-                                                     const unsigned *__restrict__ chunk_cnt,
-                                                     u64 *__restrict__ chunk_off,
-                                                     const unsigned short *__restrict__ bpos) {
+// The first s_rnd accepted draws in draw order: every block scans the chunk
+// counts (a prefix of the chunk sequence) itself, window by window of 256
+// chunks, and copies the accepted rows of the chunks it owns to their place;
+// block 0 also records the number of rows used and the draw count (index of
+// the s_rnd-th accepted draw + 1).  Launched with 256 threads.
+__global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__restrict__ buf,
+                                                 const unsigned *__restrict__ chunk_cnt,
+                                                 const unsigned short *__restrict__ bpos,
+                                                 u64 *__restrict__ keys) {
   __shared__ i64 sh_draws;
+  __shared__ u64 soff[256];
+  __shared__ unsigned scnt[256];
   const int tid = threadIdx.x;
   const i64 s_rnd = st->s_rnd;
   const i64 max_draws = max_draws_of(s_rnd);
@@ -399,21 +417,29 @@ __global__ void __launch_bounds__(1024) k_chunk_scan(DevState *st,
   const u64 Q = min(st->chunk_next, max_chunks);
   if (tid == 0) sh_draws = -1;
   u64 carry = 0;
-  for (u64 b0 = 0; b0 < Q; b0 += blockDim.x) {
-    const u64 b = b0 + tid;
-    const u64 v = b < Q ? chunk_cnt[b] : 0;
+  for (u64 b0 = 0; b0 < Q; b0 += 256) {
+    const u64 q = b0 + tid;
+    const unsigned v = q < Q ? chunk_cnt[q] : 0u;
     u64 tot;
-    const u64 ex = block_excl_scan<u64>(v, &tot);
-    if (b < Q) {
-      const u64 off = carry + ex;
-      chunk_off[b] = off;
-      if (s_rnd > 0 && off <= (u64)(s_rnd - 1) && (u64)(s_rnd - 1) < off + v)
-        sh_draws = (i64)b * CPAL_KRP_CHUNK + bpos[b * CPAL_KRP_CHUNK + (s_rnd - 1 - off)] + 1;
+    const u64 off = carry + block_excl_scan<u64>((u64)v, &tot);
+    soff[tid] = off;
+    scnt[tid] = v;
+    if (q < Q && s_rnd > 0 && off <= (u64)(s_rnd - 1) && (u64)(s_rnd - 1) < off + v)
+      sh_draws = (i64)q * CPAL_KRP_CHUNK + bpos[q * CPAL_KRP_CHUNK + (s_rnd - 1 - off)] + 1;
+    __syncthreads();
+    // chunks of this window owned by this block (q = b0 + j, j = blockIdx mod grid)
+    for (u64 j = blockIdx.x; j < 256 && b0 + j < Q; j += gridDim.x) {
+      const u64 o = soff[j];
+      if (o >= (u64)s_rnd) continue;
+      const u64 cnt = min((u64)scnt[j], (u64)s_rnd - o);
+      const u64 *src = buf + (b0 + j) * CPAL_KRP_CHUNK;
+      for (u64 i = tid; i < cnt; i += 256) keys[o + i] = src[i];
     }
+    __syncthreads();
     carry += tot;
   }
   __syncthreads();
-  if (tid == 0) {
+  if (blockIdx.x == 0 && tid == 0) {
     st->nchunks = (i64)Q;
     if (s_rnd == 0) {
       st->s_rnd_used = 0;
@@ -426,45 +452,6 @@ __global__ void __launch_bounds__(1024) k_chunk_scan(DevState *st,
       st->s_rnd_used = s_rnd;
       st->draws = sh_draws;
     }
-  }
-}
-
-__global__ void __launch_bounds__(256) k_compact(const DevState *st, const u64 *__restrict__ buf,
-                                                 const unsigned *__restrict__ chunk_cnt,
-                                                 const u64 *__restrict__ chunk_off,
-                                                 u64 *__restrict__ keys) {
-  const i64 Q = st->nchunks;
-  const u64 used = (u64)st->s_rnd_used;
-  for (i64 q = blockIdx.x; q < Q; q += gridDim.x) {
-    const u64 off = chunk_off[q];
-    if (off >= used) continue;
-    const unsigned c = chunk_cnt[q];
-    for (unsigned i = threadIdx.x; i < c && off + i < used; i += blockDim.x)
-      keys[off + i] = buf[(u64)q * CPAL_KRP_CHUNK + i];
-  }
-}
-
-// Run starts of the sorted accepted rows.
-__global__ void __launch_bounds__(256) k_unique_mark(const DevState *st, const u64 *__restrict__ keys,
-                                                     i64 cap, unsigned *__restrict__ flag) {
-  const i64 n = st->s_rnd_used;
-  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cap) return;
-  flag[i] = (i < n) && (i == 0 || keys[i] != keys[i - 1]);
-}
-
-__global__ void __launch_bounds__(256) k_unique_scatter(const DevState *st,
-                                                        const u64 *__restrict__ keys, i64 cap,
-                                                        const unsigned *__restrict__ flag,
-                                                        const u64 *__restrict__ upos,
-                                                        u64 *__restrict__ ukey,
-                                                        u64 *__restrict__ ustart) {
-  const i64 n = st->s_rnd_used;
-  const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cap || i >= n) return;
-  if (flag[i]) {
-    ukey[upos[i]] = keys[i];
-    ustart[upos[i]] = (u64)i;
   }
 }
 
@@ -493,23 +480,9 @@ void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u6
   hipLaunchKernelGGL(k_draw, dim3(grid), dim3(256), sh, s, om, st, seed, stream_id, t, buf, bpos,
                      chunk_cnt, stage_n);
 }
-void launch_chunk_scan(DevState *st, const unsigned *chunk_cnt, u64 *chunk_off,
-                       const unsigned short *bpos, hipStream_t s) {
-  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(1024), 0, s, st, chunk_cnt, chunk_off, bpos);
-}
-void launch_compact(const DevState *st, const u64 *buf, const unsigned *chunk_cnt,
-                    const u64 *chunk_off, u64 *keys, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_compact, dim3(grid), dim3(256), 0, s, st, buf, chunk_cnt, chunk_off, keys);
-}
-void launch_unique_mark(const DevState *st, const u64 *keys, i64 cap, unsigned *flag,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_unique_mark, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, st,
-                     keys, cap, flag);
-}
-void launch_unique_scatter(const DevState *st, const u64 *keys, i64 cap, const unsigned *flag,
-                           const u64 *upos, u64 *ukey, u64 *ustart, hipStream_t s) {
-  hipLaunchKernelGGL(k_unique_scatter, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, st,
-                     keys, cap, flag, upos, ukey, ustart);
+void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
+                    const unsigned short *bpos, u64 *keys, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(grid), dim3(256), 0, s, st, buf, chunk_cnt, bpos, keys);
 }
 
 }  // namespace cpal
