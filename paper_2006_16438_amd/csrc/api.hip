@@ -41,7 +41,8 @@ void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, 
                        double *kept_p, double *psum, u64 det_cap, i64 s, u64 *samp_idx,
                        hipStream_t st_);
 void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
-                 unsigned short *bpos, unsigned *chunk_cnt, int grid, hipStream_t s);
+                 unsigned short *bpos, unsigned *chunk_cnt, int grid_first, int grid_more,
+                 hipStream_t s);
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
                     const unsigned short *bpos, u64 *keys, int grid, hipStream_t s);
 u64 *sort_keys_pp(u64 *keys, unsigned *vals, u64 *tmp_keys, unsigned *tmp_vals, void *scratch,
@@ -53,6 +54,7 @@ void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
                  unsigned *flen, double *gpart, void *M, i64 mlen, int ldz, hipStream_t s);
 int rows_blocks(i64 cap);
+int rows_per_block();
 void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                    const unsigned *cidx, const uint2 *pairs, const int *ik, const double *v64,
                    const void *zhat, void *M, int ldz, int grid, hipStream_t s);
@@ -160,7 +162,9 @@ struct cpal_ctx {
   void *M = nullptr;
   void *sort_scratch = nullptr;
   void *scan_scratch = nullptr;
-  int draw_grid = 256;
+  int draw_grid = 0;        // first draw pass: blocks for 1.5 s draws (the unneeded exit)
+  int draw_more_grid = 256; // top-up draw pass
+  int compact_grid = 256;
   int gather_grid = 2048;
   int tile_grid = 256;          // workgroups per row tile of the shared-memory gather
   int ldz = 0;                  // row stride of the weighted KRP rows (16-byte multiple)
@@ -263,6 +267,7 @@ OtherModes others_of(const cpal_ctx *c, int k) {
     om.A[u] = c->mode[m].A;
     om.A32[u] = c->mode[m].A32;
     om.cand_off[u] = c->cand_off[m];
+    om.rcp[u] = 1.0 / (double)c->dims[m];
   }
   return om;
 }
@@ -409,6 +414,8 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->dbuf = c->alloc<u64>((size_t)c->max_chunks * CPAL_KRP_CHUNK);
     c->dpos = c->alloc<unsigned short>((size_t)c->max_chunks * CPAL_KRP_CHUNK);
     c->chunk_cnt = c->alloc<unsigned>(c->max_chunks);
+    c->draw_grid = (int)std::min<i64>(c->max_chunks,
+                                      (i64)std::ceil(1.5 * (double)s / CPAL_KRP_CHUNK) + 2);
     c->keys = c->alloc<u64>(s);
     c->keys_tmp = c->alloc<u64>(s);
     c->ukey = c->alloc<u64>(s);
@@ -569,8 +576,8 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
                     c->samp_idx, s);
   // random rows (Alg. 2) and combining repeats (Sec. 4.1, 4.3)
   launch_draw(om, c->st, c->seed, c->stream_id, c->t, c->dbuf, c->dpos, c->chunk_cnt,
-              c->draw_grid, s);
-  launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->draw_grid, s);
+              c->draw_grid, c->draw_more_grid, s);
+  launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->compact_grid, s);
   const u64 *sorted = sort_keys_pp(c->keys, nullptr, c->keys_tmp, nullptr, c->sort_scratch, c->s,
                                    &c->st->s_rnd_used, 0, md.key_bits, s);
   unique_runs(sorted, c->s, &c->st->s_rnd_used, (u64 *)&c->st->n_urnd, c->ukey, c->ustart,
@@ -597,7 +604,8 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   // solve A_k = M G_s^{-1}, then the leverage of the new A_k
   tb = c->stage_begin();
   if (tiled) launch_reduce_partials(c->f64, c->st, R, c->Ppart, c->M, md.n, c->tile_grid, s);
-  launch_decomp_dev(c->gpart, &c->st->s_bar, 128, R, c->dc, &c->st->flags, c->gram_tmp, s);
+  launch_decomp_dev(c->gpart, &c->st->s_bar, rows_per_block(), R, c->dc, &c->st->flags,
+                    c->gram_tmp, s);
   launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->dc, md.A, md.A32, s);
   c->stage_end(CPAL_STAGE_SOLVE, tb);
   tb = c->stage_begin();

@@ -11,7 +11,7 @@
 #define CPAL_MAXORDER 8
 #define CPAL_GRAM_ROWS 256      // rows per block of the canonical Gram summation
 #define CPAL_DRAW_CHUNK 256     // draws per chunk of the persistent fit-sample draw kernel
-#define CPAL_KRP_CHUNK 1024     // draws per chunk of the KRP row draw kernel (4 per thread)
+#define CPAL_KRP_CHUNK 256      // draws per chunk of the KRP row draw kernel (one per thread)
 
 typedef unsigned long long u64;
 typedef long long i64;
@@ -28,7 +28,8 @@ struct DevState {
   i64 n_urnd;         // unique random rows
   i64 draws;
   u64 chunk_next;     // next draw chunk (atomic ticket)
-  u64 accepted;       // accepted draws so far (atomic)
+  u64 accepted;       // accepted draws of the top-up pass so far (atomic)
+  u64 first_chunks;   // chunks of the first draw pass
   i64 nchunks;        // chunks handed out (a prefix of the chunk sequence)
   i64 gathered;       // nnz of the sampled fibers
   i64 n_fib;          // nonempty sampled fibers
@@ -69,6 +70,7 @@ struct OtherModes {
   const double *A[CPAL_MAXORDER];
   const float *A32[CPAL_MAXORDER];
   i64 cand_off[CPAL_MAXORDER];
+  double rcp[CPAL_MAXORDER];   // 1 / n[u], rounded
 };
 
 // One hash slot of a per-mode fiber index: complement key -> [off, off+len)
@@ -118,13 +120,29 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // p of the KRP row encoded in lin (other modes ascending, first fastest):
 // product of the per-mode q in ascending mode order.
+// x / n and x % n (n >= 1, rcp = 1/n rounded).  For x < 2^53 a
+// floating-point quotient estimate (off by at most a few units) is corrected
+// by whole steps; larger x use the integer division.
+__device__ __forceinline__ u64 div_rcp(u64 x, u64 n, double rcp, u64 *rem) {
+  if (x >= (1ull << 53)) {
+    const u64 q = x / n;
+    *rem = x - q * n;
+    return q;
+  }
+  i64 q = (i64)((double)x * rcp);
+  i64 r = (i64)x - q * (i64)n;
+  while (r < 0) { --q; r += (i64)n; }
+  while (r >= (i64)n) { ++q; r -= (i64)n; }
+  *rem = (u64)r;
+  return (u64)q;
+}
+
 __device__ __forceinline__ double prob_of(const OtherModes &om, u64 lin) {
   double p = 0.0;
   u64 rem = lin;
   for (int u = 0; u < om.d; ++u) {
-    const u64 n = (u64)om.n[u];
-    const u64 i = rem % n;
-    rem /= n;
+    u64 i;
+    rem = div_rcp(rem, (u64)om.n[u], om.rcp[u], &i);
     const double qv = om.q[u][i];
     p = (u == 0) ? qv : p * qv;
   }

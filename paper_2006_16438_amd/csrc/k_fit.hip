@@ -135,33 +135,69 @@ __global__ void __launch_bounds__(1024) k_fit_zero_finish(FullModes fm, i64 n_z,
 }
 
 // Per-sample squared residual, weighted; one partial per block of FIT_BLK
-// samples (samples ascending inside a block), the partials summed in block
-// order by k_fit_final.
-__global__ void __launch_bounds__(FIT_BLK) k_fit_eval(FullModes fm, int R, i64 n_nz, i64 n_fit,
-                                                     double phi_nz, double phi_z,
-                                                     const int *__restrict__ sc, i64 ld,
-                                                     const double *__restrict__ sx,
-                                                     double *__restrict__ part) {
-  __shared__ double red[FIT_BLK];
-  const i64 j = (i64)blockIdx.x * FIT_BLK + threadIdx.x;
-  double term = 0.0;
-  if (j < n_fit) {
-    double m = 0.0;
-    for (int r = 0; r < R; ++r) {
-      double v = fm.A[0][(i64)sc[j] * R + r];
-      for (int u = 1; u < fm.D; ++u) v = v * fm.A[u][(i64)sc[(i64)u * ld + j] * R + r];
-      m = m + v;
+// samples.  Lanes = columns: a group of LPS lanes (R <= LPS) evaluates one
+// sample, lane r forming the product over the DD modes of the factor rows'
+// entries r (rows read contiguously), the model value being the group's
+// tree sum; each group takes FIT_BLK / (256 / LPS) consecutive samples,
+// FIT_UNR in flight, and sums its terms in sample order; the block partial is
+// the sum of its groups in order.  DD = 0: any order (runtime loop).
+#define FIT_UNR 4
+template <int LPS, int DD>
+__global__ void __launch_bounds__(256) k_fit_eval(FullModes fm, int R, i64 n_nz, i64 n_fit,
+                                                  double phi_nz, double phi_z,
+                                                  const int *__restrict__ sc, i64 ld,
+                                                  const double *__restrict__ sx,
+                                                  double *__restrict__ part) {
+  constexpr int G = 256 / LPS;
+  constexpr int PER = FIT_BLK / G;
+  __shared__ double gsum[G];
+  const int tid = threadIdx.x, g = tid / LPS, r = tid % LPS;
+  const int D = DD > 0 ? DD : fm.D;
+  const int rc = r < R ? r : R - 1;   // lanes past R read column R-1, weight 0
+  const i64 j0 = (i64)blockIdx.x * FIT_BLK + (i64)g * PER;
+  double acc = 0.0;
+  for (int s0 = 0; s0 < PER; s0 += FIT_UNR) {
+    double v[FIT_UNR];
+#pragma unroll
+    for (int q = 0; q < FIT_UNR; ++q) {
+      const i64 j = min(j0 + s0 + q, n_fit - 1);
+      if (DD > 0) {
+        int idx[DD > 0 ? DD : 1];
+#pragma unroll
+        for (int u = 0; u < (DD > 0 ? DD : 1); ++u) idx[u] = sc[(i64)u * ld + j];
+        double f[DD > 0 ? DD : 1];
+#pragma unroll
+        for (int u = 0; u < (DD > 0 ? DD : 1); ++u) f[u] = fm.A[u][(i64)idx[u] * R + rc];
+        double p = f[0];
+#pragma unroll
+        for (int u = 1; u < (DD > 0 ? DD : 1); ++u) p = p * f[u];
+        v[q] = p;
+      } else {
+        double p = fm.A[0][(i64)sc[j] * R + rc];
+        for (int u = 1; u < D; ++u) p = p * fm.A[u][(i64)sc[(i64)u * ld + j] * R + rc];
+        v[q] = p;
+      }
+      if (r >= R) v[q] = 0.0;
     }
-    const double d = m - sx[j];
-    term = (j < n_nz ? phi_nz : phi_z) * (d * d);
+#pragma unroll
+    for (int q = 0; q < FIT_UNR; ++q) {
+      double m = v[q];
+#pragma unroll
+      for (int off = LPS / 2; off > 0; off >>= 1) m = m + __shfl_xor(m, off, LPS);
+      const i64 j = j0 + s0 + q;
+      if (r == 0 && j < n_fit) {
+        const double d = m - sx[j];
+        acc = acc + (j < n_nz ? phi_nz : phi_z) * (d * d);
+      }
+    }
   }
-  red[threadIdx.x] = term;
+  if (r == 0) gsum[g] = acc;
   __syncthreads();
-  for (int off = FIT_BLK / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
-    __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int q = 0; q < G; ++q) t = t + gsum[q];
+    part[blockIdx.x] = t;
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 __global__ void __launch_bounds__(256) k_fit_final(const double *__restrict__ part, int nb,
@@ -244,8 +280,22 @@ void fit_eval(const FullModes &fm, int R, i64 n_nz, i64 n_fit, double phi_nz, do
               const int *sc, i64 ld, const double *sx, double *part, const DevState *st,
               double *fit_out, hipStream_t s) {
   const int nb = (int)((n_fit + FIT_BLK - 1) / FIT_BLK);
-  hipLaunchKernelGGL(k_fit_eval, dim3(nb), dim3(FIT_BLK), 0, s, fm, R, n_nz, n_fit, phi_nz, phi_z,
-                     sc, ld, sx, part);
+  const int dd = (fm.D >= 2 && fm.D <= 5) ? fm.D : 0;
+  auto pick = [dd](auto k2, auto k3, auto k4, auto k5, auto k0) {
+    return dd == 2 ? k2 : dd == 3 ? k3 : dd == 4 ? k4 : dd == 5 ? k5 : k0;
+  };
+  decltype(&k_fit_eval<16, 0>) k;
+  if (R <= 16)
+    k = pick(k_fit_eval<16, 2>, k_fit_eval<16, 3>, k_fit_eval<16, 4>, k_fit_eval<16, 5>,
+             k_fit_eval<16, 0>);
+  else if (R <= 32)
+    k = pick(k_fit_eval<32, 2>, k_fit_eval<32, 3>, k_fit_eval<32, 4>, k_fit_eval<32, 5>,
+             k_fit_eval<32, 0>);
+  else
+    k = pick(k_fit_eval<64, 2>, k_fit_eval<64, 3>, k_fit_eval<64, 4>, k_fit_eval<64, 5>,
+             k_fit_eval<64, 0>);
+  hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, fm, R, n_nz, n_fit, phi_nz, phi_z, sc, ld, sx,
+                     part);
   hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(256), 0, s, part, nb, st, fit_out);
 }
 

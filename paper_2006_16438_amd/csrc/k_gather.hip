@@ -12,63 +12,138 @@
 namespace cpal {
 
 // ------------------------------------------------------------- sample rows --
-// One thread per row j of the sampled system (deterministic rows first, then
-// the combined random rows).  Computes omega_j, w_j, z_j (FP64), the weighted
-// row omega_j z_j in T, probes the fiber hash and adds the block's part of
-// G_s.  Also clears M.
-#define ROWS_BLK 128
-template <typename T>
+// Rows j of the sampled system (deterministic rows first, then the combined
+// random rows), ROWS_BLK rows per block in three phases:
+//  1. thread per row: omega_j, w_j, the other-mode indices of row j and the
+//     fiber hash probe;
+//  2. lanes = columns: z_j (FP64, Hadamard product of the other factors' rows
+//     in ascending mode order) into shared memory and the weighted row
+//     omega_j z_j in T (zero-padded to ldz) to zhat, rows read and written
+//     contiguously, ROWS_UNR rows per lane group in flight;
+//  3. the block's part of G_s (pairs a <= c, packed row by row) on the
+//     matrix cores.
+// Blocks past s_bar only clear their share of M.  DD = number of other modes
+// (0: any, runtime loops).
+#define ROWS_BLK 256
+#define ROWS_UNR 4
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Phase 3 for NT = ceil(R/16) column blocks.  Wave w multiplies the rows
+// [64w, 64w+64) of the block: tiles (ta <= tc) of 16 x 16, D += A B with
+// A(i,k) = omega_k z_k(16 ta + i), B(k,j) = z_k(16 tc + j); lane l holds
+// A(l%16, l/16), B(l/16, l%16) and D(l/16 + 4v, l%16).  The four waves'
+// tiles are then summed in wave order through shared memory (red aliases z).
+template <int NT>
+__device__ __forceinline__ void gs_tiles(const double *sz, const double *som, int ld, int R,
+                                         int rows, double *red, double *__restrict__ gp) {
+  constexpr int NTL = NT * (NT + 1) / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  d4 acc[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+  const int kb = wid * (ROWS_BLK / 4), ke = min(rows, kb + ROWS_BLK / 4);
+  for (int k0 = kb; k0 < ke; k0 += 4) {
+    const int k = k0 + k4;
+    const bool ok = k < ke;
+    const double w = ok ? som[k] : 0.0;
+    double z[NT];
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      const int col = 16 * b + i16;
+      z[b] = (ok && col < R) ? sz[k * ld + col] : 0.0;
+    }
+    int t = 0;
+#pragma unroll
+    for (int ta = 0; ta < NT; ++ta) {
+      const double av = w * z[ta];
+#pragma unroll
+      for (int tc = ta; tc < NT; ++tc) {
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, z[tc], acc[t], 0, 0, 0);
+        ++t;
+      }
+    }
+  }
+  __syncthreads();   // every wave is done with sz before red overwrites it
+#pragma unroll
+  for (int t = 0; t < NTL; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[((wid * NTL + t) * 64 + lane) * 4 + v] = acc[t][v];
+  __syncthreads();
+  const int np = R * (R + 1) / 2;
+  for (int p = tid; p < np; p += ROWS_BLK) {
+    int a = 0, c = p;
+    while (c >= R - a) { c -= R - a; ++a; }
+    c += a;
+    const int ta = a >> 4, tc = c >> 4, i = a & 15, j = c & 15;
+    const int t = ta * NT - (ta * (ta - 1)) / 2 + (tc - ta);
+    const int l = j + 16 * (i & 3), v = i >> 2;
+    double sum = 0.0;
+    for (int w = 0; w < 4; ++w) sum = sum + red[((w * NTL + t) * 64 + l) * 4 + v];
+    gp[p] = sum;
+  }
+}
+
+template <typename T, int DD>
 __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     OtherModes om, DevState *st, int R, u64 *__restrict__ samp_idx, double *__restrict__ samp_om,
     double *__restrict__ samp_w, const u64 *__restrict__ ukey, const u64 *__restrict__ ustart,
     const FiberSlot *__restrict__ slots, u64 hmask, int hshift, T *__restrict__ zhat,
     unsigned *__restrict__ foff, unsigned *__restrict__ flen, double *__restrict__ gpart,
     T *__restrict__ M, i64 mlen, int ldz) {
-  extern __shared__ double sz[];           // ROWS_BLK x (R+1)
+  extern __shared__ double sz[];           // ROWS_BLK x (R+1); phase 3 reuses it
   __shared__ double som[ROWS_BLK];
+  __shared__ unsigned sim[CPAL_MAXORDER][ROWS_BLK];
   const int tid = threadIdx.x;
   const int ld = R + 1;
+  const int d = DD > 0 ? DD : om.d;
   const i64 s_det = st->s_det, n_urnd = st->n_urnd, s_used = st->s_rnd_used;
   const i64 s_bar = s_det + n_urnd;
   const double p_det = st->p_det;
   if (blockIdx.x == 0 && tid == 0) st->s_bar = s_bar;
   for (i64 e = (i64)blockIdx.x * blockDim.x + tid; e < mlen; e += (i64)gridDim.x * blockDim.x)
     M[e] = T(0);
-  const i64 j = (i64)blockIdx.x * ROWS_BLK + tid;
+  const i64 base = (i64)blockIdx.x * ROWS_BLK;
+  if (base >= s_bar) return;   // uniform per block
+  const int rows = (int)min((i64)ROWS_BLK, s_bar - base);
+  // phase 1
   double omj = 0.0;
-  double *z = sz + tid * ld;
-  if (j < s_bar) {
+  if (tid < rows) {
+    const i64 j = base + tid;
     u64 lin;
     double wj;
+    bool rnd = false;
+    u64 cnt = 0;
     if (j < s_det) {
       lin = samp_idx[j];
-      omj = 1.0;
-      wj = 1.0;
     } else {
       const i64 u = j - s_det;
       lin = ukey[u];
       const u64 end = (u + 1 < n_urnd) ? ustart[u + 1] : (u64)s_used;
-      const double c = (double)(end - ustart[u]);
-      const double p = prob_of(om, lin);
-      omj = (c * (1.0 - p_det)) / ((double)s_used * p);
+      cnt = end - ustart[u];
+      rnd = true;
+    }
+    u64 rem = lin;
+    double p = 0.0;
+    for (int u = 0; u < d; ++u) {
+      u64 i;
+      rem = div_rcp(rem, (u64)om.n[u], om.rcp[u], &i);
+      sim[u][tid] = (unsigned)i;
+      if (rnd) {
+        const double qv = om.q[u][i];
+        p = (u == 0) ? qv : p * qv;
+      }
+    }
+    if (rnd) {
+      omj = ((double)cnt * (1.0 - p_det)) / ((double)s_used * p);
       wj = sqrt(omj);
+    } else {
+      omj = 1.0;
+      wj = 1.0;
     }
     samp_idx[j] = lin;
     samp_om[j] = omj;
     samp_w[j] = wj;
-    i64 im[CPAL_MAXORDER];
-    u64 rem = lin;
-    for (int u = 0; u < om.d; ++u) {
-      im[u] = (i64)(rem % (u64)om.n[u]);
-      rem /= (u64)om.n[u];
-    }
-    for (int r = 0; r < R; ++r) {
-      double v = om.A[0][im[0] * R + r];
-      for (int u = 1; u < om.d; ++u) v = v * om.A[u][im[u] * R + r];
-      z[r] = v;
-      zhat[j * ldz + r] = (T)(omj * v);
-    }
-    for (int r = R; r < ldz; ++r) zhat[j * ldz + r] = T(0);
     u64 h = fiber_hash(lin, hshift);
     unsigned off = 0, len = 0;
     for (;;) {
@@ -79,21 +154,70 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     }
     foff[j] = off;
     flen[j] = len;
-  } else {
-    for (int r = 0; r < R; ++r) z[r] = 0.0;
   }
   som[tid] = omj;
   __syncthreads();
-  const int rows = (int)max((i64)0, min((i64)ROWS_BLK, s_bar - (i64)blockIdx.x * ROWS_BLK));
-  const int np = R * (R + 1) / 2;
-  for (int p = tid; p < np; p += ROWS_BLK) {
-    int a = 0, c = p;
-    while (c >= R - a) { c -= R - a; ++a; }
-    c += a;
-    double acc = 0.0;
-    for (int r = 0; r < rows; ++r) acc = acc + (som[r] * sz[r * ld + a]) * sz[r * ld + c];
-    gpart[(i64)blockIdx.x * np + p] = acc;
+  // phase 2
+  const int lane = tid & 63, wid = tid >> 6;
+  const int nwav = ROWS_BLK / 64;
+  const int half = ldz <= 32 ? 1 : 0;          // two rows per wave when a row fits 32 lanes
+  const int rpw = 1 + half;
+  const int c = half ? (lane & 31) : lane;     // c < ldz covers the padded row
+  const int sub = half ? (lane >> 5) : 0;
+  const int cl = min(c, R - 1);                // column read (lanes past R discard it)
+  for (int r0 = wid * rpw * ROWS_UNR; r0 < rows; r0 += nwav * rpw * ROWS_UNR) {
+    double v[ROWS_UNR];
+    if (DD > 0) {
+      constexpr int DM = DD > 0 ? DD : 1;
+      unsigned idx[ROWS_UNR][DM];
+#pragma unroll
+      for (int q = 0; q < ROWS_UNR; ++q) {
+        const int rr = min(r0 + q * rpw + sub, rows - 1);
+#pragma unroll
+        for (int u = 0; u < DM; ++u) idx[q][u] = sim[u][rr];
+      }
+      double f[ROWS_UNR][DM];
+#pragma unroll
+      for (int q = 0; q < ROWS_UNR; ++q)
+#pragma unroll
+        for (int u = 0; u < DM; ++u) f[q][u] = om.A[u][(i64)idx[q][u] * R + cl];
+#pragma unroll
+      for (int q = 0; q < ROWS_UNR; ++q) {
+        double x = f[q][0];
+#pragma unroll
+        for (int u = 1; u < DM; ++u) x = x * f[q][u];
+        v[q] = x;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < ROWS_UNR; ++q) {
+        const int rr = min(r0 + q * rpw + sub, rows - 1);
+        double x = om.A[0][(i64)sim[0][rr] * R + cl];
+        for (int u = 1; u < d; ++u) x = x * om.A[u][(i64)sim[u][rr] * R + cl];
+        v[q] = x;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < ROWS_UNR; ++q) {
+      const int rr = r0 + q * rpw + sub;
+      if (rr < rows && c < ldz) {
+        T out = T(0);
+        if (c < R) {
+          sz[rr * ld + c] = v[q];
+          out = (T)(som[rr] * v[q]);
+        }
+        zhat[(base + rr) * ldz + c] = out;
+      }
+    }
   }
+  __syncthreads();
+  // phase 3
+  double *gp = gpart + (i64)blockIdx.x * (R * (R + 1) / 2);
+  const int nt = (R + 15) / 16;
+  if (nt == 1) gs_tiles<1>(sz, som, ld, R, rows, sz, gp);
+  else if (nt == 2) gs_tiles<2>(sz, som, ld, R, rows, sz, gp);
+  else if (nt == 3) gs_tiles<3>(sz, som, ld, R, rows, sz, gp);
+  else gs_tiles<4>(sz, som, ld, R, rows, sz, gp);
 }
 
 // ------------------------------------------------------------------ gather --
@@ -606,18 +730,28 @@ void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
                  unsigned *flen, double *gpart, void *M, i64 mlen, int ldz, hipStream_t s) {
   const int nb = (int)((cap + ROWS_BLK - 1) / ROWS_BLK);
-  const size_t sh = sizeof(double) * (size_t)ROWS_BLK * (R + 1);
-  if (f64)
-    hipLaunchKernelGGL(k_rows<double>, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx,
-                       samp_om, samp_w, ukey, ustart, slots, hmask, hshift, (double *)zhat, foff,
-                       flen, gpart, (double *)M, mlen, ldz);
-  else
-    hipLaunchKernelGGL(k_rows<float>, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx,
-                       samp_om, samp_w, ukey, ustart, slots, hmask, hshift, (float *)zhat, foff,
-                       flen, gpart, (float *)M, mlen, ldz);
+  // z rows, then the four waves' G_s tiles (4 x NTL x 256 doubles)
+  const int nt = (R + 15) / 16;
+  const size_t sh = sizeof(double) * std::max<size_t>((size_t)ROWS_BLK * (R + 1),
+                                                      (size_t)1024 * (nt * (nt + 1) / 2));
+  const int dd = (om.d >= 2 && om.d <= 4) ? om.d : 0;
+  if (f64) {
+    auto k = dd == 2 ? k_rows<double, 2> : dd == 3 ? k_rows<double, 3>
+           : dd == 4 ? k_rows<double, 4> : k_rows<double, 0>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
+                       ukey, ustart, slots, hmask, hshift, (double *)zhat, foff, flen, gpart,
+                       (double *)M, mlen, ldz);
+  } else {
+    auto k = dd == 2 ? k_rows<float, 2> : dd == 3 ? k_rows<float, 3>
+           : dd == 4 ? k_rows<float, 4> : k_rows<float, 0>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
+                       ukey, ustart, slots, hmask, hshift, (float *)zhat, foff, flen, gpart,
+                       (float *)M, mlen, ldz);
+  }
 }
 
 int rows_blocks(i64 cap) { return (int)((cap + ROWS_BLK - 1) / ROWS_BLK); }
+int rows_per_block() { return ROWS_BLK; }
 
 // Shared-memory plan of the tiled gather: rows per tile and tile count.
 #define GT_LDS_BUDGET (120 * 1024)

@@ -151,6 +151,14 @@ __device__ bool chol_right(double *S, double *L, int R, double tol, int *fail_sh
 // broadcast from lane j, and the column entries L(l,j) from lane l.  Every
 // entry sees the same operations in the same order as chol_right.  S and L
 // are shared-memory R x R arrays (S read, L written).  One wavefront.
+// Value of v in lane l (l wave-uniform) through two scalar lane reads.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <int RM>
 __device__ bool chol_regs(const double *S, double *L, int R, double tol) {
   const int lane = threadIdx.x;
@@ -164,18 +172,20 @@ __device__ bool chol_regs(const double *S, double *L, int R, double tol) {
 #pragma unroll
   for (int j = 0; j < RM; ++j) {
     if (j < R && ok) {
-      const double piv = __shfl(g[j], j, 64);
+      const double piv = lane_value(g[j], j);
       if (!(piv > tol)) {
         ok = false;
       } else {
         const double ljj = sqrt(piv);
         const double lij = (lane == j) ? ljj : ((lane > j && lane < R) ? g[j] / ljj : 0.0);
         lcol[j] = lij;
+        // trailing update of every lane's row: entries above the diagonal
+        // (lane < l) and rows past R (all zero) are updated too but never read
 #pragma unroll
         for (int l = j + 1; l < RM; ++l) {
           if (l < R) {
-            const double llj = __shfl(lij, l, 64);
-            if (lane >= l && lane < R) g[l] = g[l] - lij * llj;
+            const double llj = lane_value(lij, l);
+            g[l] = g[l] - lij * llj;
           }
         }
       }
@@ -248,6 +258,7 @@ __global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, 
   for (int b0 = 0; b0 < nblk; b0 += per) {
     const int nb = min(per, nblk - b0);
     __syncthreads();
+#pragma unroll 8
     for (int e = lane; e < nb * np; e += 64) slab[e] = part[(i64)b0 * np + e];
     __syncthreads();
     for (int p = lane; p < np; p += 64) {
@@ -257,14 +268,14 @@ __global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, 
     }
   }
   __syncthreads();
-  // unpack the pair sums into the full symmetric matrix (L as staging)
+  // unpack the pair sums into the full symmetric matrix (L as staging); pair
+  // (a <= c) sits at a*R - a*(a-1)/2 + (c - a)
   for (int p = lane; p < np; p += 64) L[p] = G[p];
   __syncthreads();
-  for (int p = lane; p < np; p += 64) {
-    int a, c;
-    pair_of(p, R, a, c);
-    G[a * R + c] = L[p];
-    G[c * R + a] = L[p];
+  for (int e = lane; e < R * R; e += 64) {
+    const int r = e / R, q = e - r * R;
+    const int a = min(r, q), c = max(r, q);
+    G[e] = L[a * R - (a * (a - 1)) / 2 + (c - a)];
   }
   __syncthreads();
   double maxdiag = 0.0;

@@ -286,60 +286,128 @@ __global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st
 
 __device__ __forceinline__ i64 max_draws_of(i64 s_rnd) { return 64 * s_rnd + (1ll << 20); }
 
-// Persistent draw kernel (Alg. 2): blocks take chunks of 256 consecutive
-// draws in increasing order while fewer than s_rnd draws were accepted, so
-// the processed chunks always form a prefix of the draw sequence.  Each
-// chunk's accepted rows are compacted in draw order.
-// Persistent draw kernel (Alg. 2): blocks take chunks of CPAL_KRP_CHUNK
-// consecutive draws in increasing order while fewer than s_rnd draws were
-// accepted, so the processed chunks always form a prefix of the draw
-// sequence.  Thread t makes draws 4t..4t+3 of a chunk (four independent
-// Philox streams), and the chunk's accepted rows are compacted in draw
-// order.  When the other modes' CDFs and probabilities fit (stage_n > 0
-// entries), every block first copies them to shared memory and the binary
-// searches run there.
-#define DRAWS_PER_THREAD (CPAL_KRP_CHUNK / 256)
-__global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 seed,
-                                              u64 stream_id, u64 t, u64 *__restrict__ buf,
-                                              unsigned short *__restrict__ bpos,
-                                              unsigned *__restrict__ chunk_cnt, int stage_n) {
+// Random rows (Alg. 2) in chunks of CPAL_KRP_CHUNK consecutive draws, one
+// draw per thread of a 256-thread block; a chunk's accepted rows (product
+// probability <= tau_eff, i.e. outside the deterministic set) are compacted
+// in draw order into buf, their positions in the chunk into bpos and their
+// number into chunk_cnt.  The chunks processed always form a prefix of the
+// draw sequence that holds at least s_rnd accepted draws (or all
+// max_draws draws):
+//  * first pass: chunk b for block b < the expected need, s_rnd / (1 - p_det)
+//    draws plus a margin; no atomics;
+//  * top-up pass: when the first pass fell short, blocks take further chunks
+//    in increasing order (atomic ticket) until enough were accepted.
+// When the other modes' CDFs fit (stage_n > 0 entries) every block first
+// copies them to shared memory and the binary searches run there.
+__device__ __forceinline__ i64 draw_need_chunks(const DevState *st, i64 s_rnd) {
+  const double rate = fmax(1.0 - st->p_det, 1.0 / 1024.0);
+  return (i64)ceil((double)s_rnd / rate * 1.02 / CPAL_KRP_CHUNK) + 2;
+}
+
+struct DrawModes {
+  u64 W[CPAL_MAXORDER];
+  const u64 *C[CPAL_MAXORDER];
+};
+
+__device__ __forceinline__ void draw_setup(const OtherModes &om, int stage_n, unsigned char *dsm,
+                                           DrawModes &dm) {
+  for (int u = 0; u < om.d; ++u) {
+    dm.W[u] = om.C[u][om.n[u] - 1];
+    dm.C[u] = om.C[u];
+  }
+  if (stage_n > 0) {   // block-uniform: every thread reaches the barrier below
+    u64 *sC = (u64 *)dsm;
+    int off = 0;
+    for (int u = 0; u < om.d; ++u) {
+      for (int i = threadIdx.x; i < om.n[u]; i += blockDim.x) sC[off + i] = om.C[u][i];
+      dm.C[u] = sC + off;
+      off += (int)om.n[u];
+    }
+    __syncthreads();
+  }
+}
+
+// Draws of chunk c; returns the chunk's accepted count (block-uniform).
+__device__ __forceinline__ unsigned draw_chunk(const OtherModes &om, const DrawModes &dm, u64 c,
+                                               double tau, i64 max_draws, u64 seed, u64 stream_id,
+                                               u64 t, u64 *__restrict__ buf,
+                                               unsigned short *__restrict__ bpos,
+                                               unsigned *__restrict__ chunk_cnt) {
+  const int tid = threadIdx.x;
+  const i64 j = (i64)c * CPAL_KRP_CHUNK + tid;
+  u64 lin = 0;
+  double p = 0.0;
+  for (int u = 0; u < om.d; ++u) {
+    u64 ctr[4] = {(u64)j, (u64)om.mode[u] | ((u64)om.k << 8), t, 0ull};
+    philox4x64_10(ctr, seed, stream_id);
+    const u64 x = scale128(ctr[0], ctr[1], dm.W[u]);
+    const i64 i = upper_bound_u64(dm.C[u], om.n[u], x);
+    const double qv = om.q[u][i];
+    p = (u == 0) ? qv : p * qv;
+    lin += (u64)i * om.stride[u];
+  }
+  const bool ok = (j < max_draws) && p <= tau;
+  unsigned tot;
+  const unsigned pos = block_excl_scan<unsigned>(ok ? 1u : 0u, &tot);
+  if (ok) {
+    buf[c * CPAL_KRP_CHUNK + pos] = lin;
+    bpos[c * CPAL_KRP_CHUNK + pos] = (unsigned short)tid;
+  }
+  if (tid == 0) chunk_cnt[c] = tot;
+  return tot;
+}
+
+__global__ void __launch_bounds__(256) k_draw_first(OtherModes om, DevState *st, u64 seed,
+                                                    u64 stream_id, u64 t, u64 *__restrict__ buf,
+                                                    unsigned short *__restrict__ bpos,
+                                                    unsigned *__restrict__ chunk_cnt,
+                                                    int stage_n) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
+  const i64 s_rnd = st->s_rnd;
+  const i64 max_draws = max_draws_of(s_rnd);
+  const i64 max_chunks = (max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK;
+  const i64 first = s_rnd == 0 ? 0 : min(min(draw_need_chunks(st, s_rnd), max_chunks),
+                                         (i64)gridDim.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->first_chunks = (u64)first;
+    st->chunk_next = (u64)first;
+  }
+  if ((i64)blockIdx.x >= first) return;   // uniform per block
+  DrawModes dm;
+  draw_setup(om, stage_n, dsm, dm);
+  draw_chunk(om, dm, blockIdx.x, st->tau_eff, max_draws, seed, stream_id, t, buf, bpos,
+             chunk_cnt);
+}
+
+__global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, u64 seed,
+                                                   u64 stream_id, u64 t, u64 *__restrict__ buf,
+                                                   unsigned short *__restrict__ bpos,
+                                                   unsigned *__restrict__ chunk_cnt,
+                                                   int stage_n) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
   __shared__ u64 sh_c;
   __shared__ int stop;
   const int tid = threadIdx.x;
   const i64 s_rnd = st->s_rnd;
-  const double tau = st->tau_eff;
+  if (s_rnd == 0) return;
   const i64 max_draws = max_draws_of(s_rnd);
   const u64 max_chunks = (u64)((max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK);
-  if (s_rnd == 0) return;
-  u64 W[CPAL_MAXORDER];
-  const u64 *Cp[CPAL_MAXORDER];
-  const double *qp[CPAL_MAXORDER];
-  for (int u = 0; u < om.d; ++u) {
-    W[u] = om.C[u][om.n[u] - 1];
-    Cp[u] = om.C[u];
-    qp[u] = om.q[u];
-  }
-  if (stage_n > 0) {   // block-uniform: every thread reaches the barrier below
-    u64 *sC = (u64 *)dsm;
-    double *sq = (double *)(dsm + sizeof(u64) * stage_n);
-    int off = 0;
-    for (int u = 0; u < om.d; ++u) {
-      for (int i = tid; i < om.n[u]; i += blockDim.x) {
-        sC[off + i] = om.C[u][i];
-        sq[off + i] = om.q[u][i];
-      }
-      Cp[u] = sC + off;
-      qp[u] = sq + off;
-      off += (int)om.n[u];
-    }
-    __syncthreads();
-  }
+  const u64 first = st->first_chunks;
+  u64 acc0 = 0;
+  for (u64 c = tid; c < first; c += blockDim.x) acc0 += chunk_cnt[c];
+  acc0 = wave_sum(acc0);
+  __shared__ u64 ws[4];
+  if ((tid & 63) == 0) ws[tid >> 6] = acc0;
+  __syncthreads();
+  acc0 = ws[0] + ws[1] + ws[2] + ws[3];
+  if ((i64)acc0 >= s_rnd || first >= max_chunks) return;   // uniform per block
+  DrawModes dm;
+  draw_setup(om, stage_n, dsm, dm);
   for (;;) {
     if (tid == 0) {
       const u64 acc = __hip_atomic_load(&st->accepted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       stop = 0;
-      if ((i64)acc >= s_rnd) {
+      if ((i64)(acc0 + acc) >= s_rnd) {
         stop = 1;
       } else {
         const u64 c = atomicAdd(&st->chunk_next, 1ull);
@@ -348,52 +416,9 @@ __global__ void __launch_bounds__(256) k_draw(OtherModes om, DevState *st, u64 s
     }
     __syncthreads();
     if (stop) break;
-    const u64 c = sh_c;
-    const i64 j0 = (i64)c * CPAL_KRP_CHUNK + (i64)DRAWS_PER_THREAD * tid;
-    u64 lin[DRAWS_PER_THREAD];
-    double p[DRAWS_PER_THREAD];
-#pragma unroll
-    for (int v = 0; v < DRAWS_PER_THREAD; ++v) { lin[v] = 0; p[v] = 0.0; }
-    for (int u = 0; u < om.d; ++u) {
-      u64 ctr[DRAWS_PER_THREAD][4];
-#pragma unroll
-      for (int v = 0; v < DRAWS_PER_THREAD; ++v) {
-        ctr[v][0] = (u64)(j0 + v);
-        ctr[v][1] = (u64)om.mode[u] | ((u64)om.k << 8);
-        ctr[v][2] = t;
-        ctr[v][3] = 0ull;
-        philox4x64_10(ctr[v], seed, stream_id);
-      }
-#pragma unroll
-      for (int v = 0; v < DRAWS_PER_THREAD; ++v) {
-        const u64 x = scale128(ctr[v][0], ctr[v][1], W[u]);
-        const i64 i = upper_bound_u64(Cp[u], om.n[u], x);
-        const double qv = qp[u][i];
-        p[v] = (u == 0) ? qv : p[v] * qv;
-        lin[v] += (u64)i * om.stride[u];
-      }
-    }
-    unsigned mine = 0, okm = 0;
-#pragma unroll
-    for (int v = 0; v < DRAWS_PER_THREAD; ++v) {
-      const bool ok = (j0 + v < max_draws) && p[v] <= tau;
-      okm |= (ok ? 1u : 0u) << v;
-      mine += ok ? 1u : 0u;
-    }
-    unsigned tot;
-    unsigned pos = block_excl_scan<unsigned>(mine, &tot);
-#pragma unroll
-    for (int v = 0; v < DRAWS_PER_THREAD; ++v) {
-      if (okm & (1u << v)) {
-        buf[c * CPAL_KRP_CHUNK + pos] = lin[v];
-        bpos[c * CPAL_KRP_CHUNK + pos] = (unsigned short)(DRAWS_PER_THREAD * tid + v);
-        ++pos;
-      }
-    }
-    if (tid == 0) {
-      chunk_cnt[c] = tot;
-      atomicAdd(&st->accepted, (u64)tot);
-    }
+    const unsigned tot = draw_chunk(om, dm, sh_c, st->tau_eff, max_draws, seed, stream_id, t, buf,
+                                    bpos, chunk_cnt);
+    if (tid == 0) atomicAdd(&st->accepted, (u64)tot);
     __syncthreads();
   }
 }
@@ -472,13 +497,16 @@ void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, 
                      psum, det_cap, s, samp_idx, (unsigned char *)nullptr);
 }
 void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
-                 unsigned short *bpos, unsigned *chunk_cnt, int grid, hipStream_t s) {
+                 unsigned short *bpos, unsigned *chunk_cnt, int grid_first, int grid_more,
+                 hipStream_t s) {
   i64 tot = 0;
   for (int u = 0; u < om.d; ++u) tot += om.n[u];
-  const int stage_n = tot <= 4096 ? (int)tot : 0;   // <= 64 KB of shared memory
-  const size_t sh = (size_t)stage_n * (sizeof(u64) + sizeof(double));
-  hipLaunchKernelGGL(k_draw, dim3(grid), dim3(256), sh, s, om, st, seed, stream_id, t, buf, bpos,
-                     chunk_cnt, stage_n);
+  const int stage_n = tot <= 8192 ? (int)tot : 0;   // <= 64 KB of shared memory
+  const size_t sh = (size_t)stage_n * sizeof(u64);
+  hipLaunchKernelGGL(k_draw_first, dim3(grid_first), dim3(256), sh, s, om, st, seed, stream_id, t,
+                     buf, bpos, chunk_cnt, stage_n);
+  hipLaunchKernelGGL(k_draw_more, dim3(grid_more), dim3(256), sh, s, om, st, seed, stream_id, t,
+                     buf, bpos, chunk_cnt, stage_n);
 }
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
                     const unsigned short *bpos, u64 *keys, int grid, hipStream_t s) {

@@ -2,7 +2,7 @@
 // radix sort of u64 keys (optional u32 payload) whose element count may live
 // in device memory (so that the pass sequence is fixed and capturable).
 //
-// Radix pass: 8-bit digits, tiles of 4096 keys (256 threads x 16 rounds).
+// Radix pass: 8-bit digits, tiles of 1024 keys (256 threads x 4 rounds).
 // Within a round each wavefront ranks its keys by digit with ballots (the
 // lanes sharing a digit form a mask), the waves of the block are ordered
 // through shared counters, and rounds follow each other, so the scatter is
@@ -13,7 +13,7 @@
 namespace cpal {
 
 #define RS_THREADS 256
-#define RS_ROUNDS 16
+#define RS_ROUNDS 4
 #define RS_TILE (RS_THREADS * RS_ROUNDS)
 #define SCAN_TILE 4096
 
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const u64 *__restrict__ 
 }
 
 // fused_offsets: when hist_off is null the block derives its digit offsets
-// from the raw histograms (small inputs: nb <= 64), otherwise hist_off holds
+// from the raw histograms (small inputs: nb <= 256), otherwise hist_off holds
 // the digit-major exclusive scan.
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(
     const u64 *__restrict__ keys, const unsigned *__restrict__ vals, i64 cap, const i64 *n_dev,
@@ -122,10 +122,25 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(
     goff[tid] = hist_off[(i64)tid * nb + blockIdx.x];
   } else {
     u64 tot = 0, before = 0;
-    for (int b = 0; b < nb; ++b) {
-      const unsigned v = hist[(i64)tid * nb + b];
-      tot += v;
-      if (b < (int)blockIdx.x) before += v;
+    const unsigned *row = hist + (i64)tid * nb;
+    const int me = (int)blockIdx.x;
+    if ((nb & 3) == 0) {   // rows start 16-byte aligned
+      const uint4 *r4 = (const uint4 *)row;
+#pragma unroll 8
+      for (int b4 = 0; b4 < nb / 4; ++b4) {
+        const uint4 v = r4[b4];
+        const int b = 4 * b4;
+        tot += (u64)v.x + v.y + v.z + v.w;
+        before += (u64)(b < me ? v.x : 0u) + (b + 1 < me ? v.y : 0u) + (b + 2 < me ? v.z : 0u) +
+                  (b + 3 < me ? v.w : 0u);
+      }
+    } else {
+#pragma unroll 8
+      for (int b = 0; b < nb; ++b) {
+        const unsigned v = row[b];
+        tot += v;
+        if (b < me) before += v;
+      }
     }
     u64 alltot;
     const u64 ex = block_excl_scan<u64>(tot, &alltot);
@@ -198,7 +213,7 @@ u64 *sort_keys_pp(u64 *keys, unsigned *vals, u64 *tmp_keys, unsigned *tmp_vals, 
   p += ((sizeof(u64) * (size_t)nh + 255) & ~(size_t)255);
   void *scan_scratch = p;
   const i64 capn = count_dev ? cap : min(cap, count_host);
-  const bool fused = nb <= 64;
+  const bool fused = nb <= 256;
   int passes = (bits + 7) / 8;
   if (passes < 1) passes = 1;
   u64 *src_k = keys, *dst_k = tmp_keys;
