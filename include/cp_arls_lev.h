@@ -150,9 +150,12 @@ enum {
   CPAL_NSTAGES = 5
 };
 
-/* Enable (1) or disable (0) recording of HIP events around every stage of
- * each mode update on the context's stream (profiling aid; off by default). */
-cpal_status cp_arls_lev_set_timing(cpal_ctx *ctx, int32_t enable);
+/* Record HIP events around the stages of each mode update on the context's
+ * stream: stage_mask bit s times stage s (CPAL_TIMING_ALL: every stage, 0:
+ * none, the default).  Each timed stage adds two event records per update.
+ * Profiling aid. */
+#define CPAL_TIMING_ALL ((1 << CPAL_NSTAGES) - 1)
+cpal_status cp_arls_lev_set_timing(cpal_ctx *ctx, int32_t stage_mask);
 
 /* Synchronizes the stream and returns, per stage, the summed duration in
  * milliseconds (ms_host[CPAL_NSTAGES]) and the number of timed updates

@@ -90,8 +90,16 @@ class CpArlsLev:
         return dict(s_det=int(v[0]), s_rnd=int(v[1]), s_bar=int(v[2]), draws=int(v[3]),
                     gathered_nnz=int(v[4]), p_det=float(f[5]), flags=int(i32[12]))
 
-    def set_timing(self, on=True):
-        _check(L.load().cp_arls_lev_set_timing(self._ctx, 1 if on else 0), self._ctx)
+    def set_timing(self, on=True, stages=None):
+        """Time every stage (on=True), none (on=False) or the named stages
+        (stages = iterable of names from STAGES)."""
+        if stages is not None:
+            mask = 0
+            for name in stages:
+                mask |= 1 << L.STAGES.index(name)
+        else:
+            mask = (1 << len(L.STAGES)) - 1 if on else 0
+        _check(L.load().cp_arls_lev_set_timing(self._ctx, mask), self._ctx)
 
     def stage_times(self, reset=True):
         """{stage: (ms_total, count)} of the timed updates (synchronizes)."""

@@ -28,6 +28,16 @@ void launch_gather_prep(const DevState *st, DevState *stw, const unsigned *flen,
 int gather_prep_blocks(i64 cap);
 int gather_row_width(int R);
 i64 gather_chunks_cap(i64 nnz);
+void launch_gather_sorted(bool f64, const DevState *st, int R, const u64 *cpos,
+                          const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
+                          const uint2 *pairs, const int *ik, const double *v64, i64 nk,
+                          int *g_ik, void *g_x, unsigned *g_z, unsigned *cnt, unsigned *rowptr,
+                          unsigned *cursor, unsigned *csr_r, void *csr_x, unsigned *csr_z,
+                          const void *zhat, int ldz, void *M, int grid, hipStream_t s);
+void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                       const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
+                       const int *ik, const double *v64, i64 nk, const void *zhat, int ldz, void *M,
+                       int grid, hipStream_t s);
 void launch_reduce_partials(bool f64, const DevState *st, int R, const void *P, void *M, i64 nk,
                             int G, hipStream_t s);
 int lev_row_blocks(i64 n);
@@ -47,10 +57,11 @@ void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
                     const unsigned short *bpos, u64 *keys, int grid, hipStream_t s);
 u64 *sort_keys_pp(u64 *keys, unsigned *vals, u64 *tmp_keys, unsigned *tmp_vals, void *scratch,
                   i64 cap, const i64 *count_dev, i64 count_host, int bits, hipStream_t s);
-void unique_runs(const u64 *keys, i64 cap, const i64 *n_dev, u64 *n_runs, u64 *ukey, u64 *ustart,
-                 void *scratch, hipStream_t s);
+void launch_samples_out(const DevState *st, const u64 *samp_idx, const double *samp_om,
+                        const double *samp_w, i64 cap, u64 *idx, double *om, double *w,
+                        i64 *count, hipStream_t s);
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
-                 double *samp_om, double *samp_w, const u64 *ukey, const u64 *ustart,
+                 double *samp_om, double *samp_w, const u64 *skeys,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
                  unsigned *flen, double *gpart, void *M, i64 mlen, int ldz, hipStream_t s);
 int rows_blocks(i64 cap);
@@ -152,7 +163,6 @@ struct cpal_ctx {
   unsigned *chunk_cnt = nullptr;
   i64 max_chunks = 0;
   u64 *keys = nullptr, *keys_tmp = nullptr;
-  u64 *ukey = nullptr, *ustart = nullptr;
   u64 *samp_idx = nullptr;
   double *samp_om = nullptr, *samp_w = nullptr;
   void *zhat = nullptr;
@@ -169,6 +179,12 @@ struct cpal_ctx {
   int tile_grid = 256;          // workgroups per row tile of the shared-memory gather
   int ldz = 0;                  // row stride of the weighted KRP rows (16-byte multiple)
   void *Ppart = nullptr;        // their partial accumulators
+  // row-sorted gather: stream-order and row-order copies of the gathered nonzeros
+  int *g_ik = nullptr;
+  void *g_x = nullptr, *csr_x = nullptr;
+  unsigned *g_z = nullptr, *gs_cnt = nullptr, *gs_rowptr = nullptr, *gs_cursor = nullptr;
+  unsigned *csr_r = nullptr, *csr_z = nullptr;
+  int gs_grid = 512;
   unsigned *chunk_first = nullptr;  // first nonempty fiber of each gather chunk
   u64 *cpos = nullptr;              // nonempty fibers: stream position,
   unsigned *coff = nullptr;         //   offset in the mode-sorted nonzeros,
@@ -184,7 +200,7 @@ struct cpal_ctx {
   double *fit_part = nullptr;
   int fit_flags = 0;
   // stage timing
-  bool timing = false;
+  unsigned timing = 0;          // mask of timed stages
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_rec;
 
@@ -198,14 +214,14 @@ struct cpal_ctx {
     hipEventCreate(&e);
     return e;
   }
-  hipEvent_t stage_begin() {
-    if (!timing) return nullptr;
+  hipEvent_t stage_begin(int stage) {
+    if (!(timing >> stage & 1u)) return nullptr;
     hipEvent_t e = take_event();
     hipEventRecord(e, stream);
     return e;
   }
   void stage_end(int stage, hipEvent_t b) {
-    if (!timing || !b) return;
+    if (!b) return;
     hipEvent_t e = take_event();
     hipEventRecord(e, stream);
     ev_rec.push_back({stage, {b, e}});
@@ -418,8 +434,6 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
                                       (i64)std::ceil(1.5 * (double)s / CPAL_KRP_CHUNK) + 2);
     c->keys = c->alloc<u64>(s);
     c->keys_tmp = c->alloc<u64>(s);
-    c->ukey = c->alloc<u64>(s);
-    c->ustart = c->alloc<u64>(s + 1);
     c->samp_idx = c->alloc<u64>(s);
     c->samp_om = c->alloc<double>(s);
     c->samp_w = c->alloc<double>(s);
@@ -433,6 +447,16 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->M = c->alloc<char>((size_t)maxn * R * tsz);
     c->Ppart = c->alloc<char>((size_t)c->tile_grid * maxn * R * tsz);
     c->gram_tmp = c->alloc<double>(np);
+    c->g_ik = c->alloc<int>(c->nnz);
+    c->g_x = c->alloc<char>((size_t)c->nnz * tsz);
+    c->g_z = c->alloc<unsigned>(c->nnz);
+    c->csr_r = c->alloc<unsigned>(c->nnz);
+    c->csr_x = c->alloc<char>((size_t)c->nnz * tsz);
+    c->csr_z = c->alloc<unsigned>(c->nnz);
+    c->gs_cnt = c->alloc<unsigned>(maxn);
+    c->gs_rowptr = c->alloc<unsigned>(maxn + 1);
+    c->gs_cursor = c->alloc<unsigned>(maxn);
+    hipMemsetAsync(c->gs_cnt, 0, sizeof(unsigned) * (size_t)maxn, c->stream);
     c->chunk_first = c->alloc<unsigned>(gather_chunks_cap(c->nnz));
     c->cpos = c->alloc<u64>(s);
     c->coff = c->alloc<unsigned>(s);
@@ -568,7 +592,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   const OtherModes om = others_of(c, k);
   const int R = c->R;
   // SkrpLev (Alg. 1): deterministic rows
-  hipEvent_t tb = c->stage_begin();
+  hipEvent_t tb = c->stage_begin(CPAL_STAGE_SAMPLE);
   launch_det_cand(om, c->tau, c->enum_cap, c->st, c->cand, s);
   if (c->tau < 1.0)
     launch_det_enum(om, c->tau, c->st, c->cand, c->det_blk, c->det_keys, c->det_cap, s);
@@ -580,35 +604,30 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->compact_grid, s);
   const u64 *sorted = sort_keys_pp(c->keys, nullptr, c->keys_tmp, nullptr, c->sort_scratch, c->s,
                                    &c->st->s_rnd_used, 0, md.key_bits, s);
-  unique_runs(sorted, c->s, &c->st->s_rnd_used, (u64 *)&c->st->n_urnd, c->ukey, c->ustart,
-              c->scan_scratch, s);
   c->stage_end(CPAL_STAGE_SAMPLE, tb);
-  tb = c->stage_begin();
+  tb = c->stage_begin(CPAL_STAGE_ROWS);
   // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
-  launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->ukey, c->ustart,
-              md.slots, md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->M,
-              md.n * R, c->ldz, s);
+  launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, sorted, md.slots,
+              md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->M, md.n * R,
+              c->ldz, s);
   launch_gather_prep(c->st, c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->cpos, c->coff,
                      c->cidx, c->chunk_first, s);
-  const int tr = gather_tile_rows(md.n, R, c->f64);
-  const bool tiled = (md.n + tr - 1) / tr <= 4;
   c->stage_end(CPAL_STAGE_ROWS, tb);
-  tb = c->stage_begin();
-  if (tiled)
-    launch_gather_tiled(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
-                        md.ik, md.v64, c->zhat, c->ldz, c->Ppart, md.n, c->tile_grid, s);
+  tb = c->stage_begin(CPAL_STAGE_GATHER);
+  if (md.n <= (1 << 20))
+    launch_gather_seg(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
+                      md.ik, md.v64, md.n, c->zhat, c->ldz, c->M, c->gs_grid, s);
   else
     launch_gather(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, c->zhat,
                   c->M, c->ldz, c->gather_grid, s);
   c->stage_end(CPAL_STAGE_GATHER, tb);
   // solve A_k = M G_s^{-1}, then the leverage of the new A_k
-  tb = c->stage_begin();
-  if (tiled) launch_reduce_partials(c->f64, c->st, R, c->Ppart, c->M, md.n, c->tile_grid, s);
-  launch_decomp_dev(c->gpart, &c->st->s_bar, rows_per_block(), R, c->dc, &c->st->flags,
+  tb = c->stage_begin(CPAL_STAGE_SOLVE);
+  launch_decomp_dev(c->gpart, &c->st->n_slots, rows_per_block(), R, c->dc, &c->st->flags,
                     c->gram_tmp, s);
   launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->dc, md.A, md.A32, s);
   c->stage_end(CPAL_STAGE_SOLVE, tb);
-  tb = c->stage_begin();
+  tb = c->stage_begin(CPAL_STAGE_LEVERAGE);
   refresh_leverage(c, k);
   c->stage_end(CPAL_STAGE_LEVERAGE, tb);
   if (stats_dev) launch_stats(c->st, k, c->D, stats_dev, s);
@@ -628,12 +647,8 @@ cpal_status cp_arls_lev_fit_estimate(cpal_ctx *c, double *fit_dev) {
 cpal_status cp_arls_lev_samples(const cpal_ctx *c, uint64_t *idx_dev, double *omega_dev,
                                 double *w_dev, int64_t cap, int64_t *count_dev) {
   if (!c || cap < 0) return CPAL_E_ARG;
-  const i64 n = std::min<i64>(cap, c->s);
-  // copy the full buffers up to cap; entries past s_bar are stale
-  if (idx_dev && n) hipMemcpyAsync(idx_dev, c->samp_idx, sizeof(u64) * n, hipMemcpyDeviceToDevice, c->stream);
-  if (omega_dev && n) hipMemcpyAsync(omega_dev, c->samp_om, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream);
-  if (w_dev && n) hipMemcpyAsync(w_dev, c->samp_w, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream);
-  if (count_dev) hipMemcpyAsync(count_dev, &c->st->s_bar, sizeof(i64), hipMemcpyDeviceToDevice, c->stream);
+  launch_samples_out(c->st, c->samp_idx, c->samp_om, c->samp_w, cap, (u64 *)idx_dev, omega_dev,
+                     w_dev, (i64 *)count_dev, c->stream);
   return CPAL_OK;
 }
 
@@ -665,7 +680,7 @@ cpal_status cp_arls_lev_set_step(cpal_ctx *c, uint64_t t) {
 
 cpal_status cp_arls_lev_set_timing(cpal_ctx *c, int32_t enable) {
   if (!c) return CPAL_E_ARG;
-  c->timing = enable != 0;
+  c->timing = (unsigned)enable & ((1u << CPAL_NSTAGES) - 1u);
   return CPAL_OK;
 }
 

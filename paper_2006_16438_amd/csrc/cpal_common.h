@@ -25,7 +25,7 @@ struct DevState {
   i64 s_rnd;          // random rows requested
   i64 s_rnd_used;     // accepted random draws used for the weights
   i64 s_bar;          // rows of the sampled system
-  i64 n_urnd;         // unique random rows
+  i64 n_slots;        // slots of the sampled system (deterministic rows + accepted draws)
   i64 draws;
   u64 chunk_next;     // next draw chunk (atomic ticket)
   u64 accepted;       // accepted draws of the top-up pass so far (atomic)

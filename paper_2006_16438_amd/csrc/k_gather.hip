@@ -12,9 +12,11 @@
 namespace cpal {
 
 // ------------------------------------------------------------- sample rows --
-// Rows j of the sampled system (deterministic rows first, then the combined
-// random rows), ROWS_BLK rows per block in three phases:
-//  1. thread per row: omega_j, w_j, the other-mode indices of row j and the
+// Slots j of the sampled system, ROWS_BLK per block: the deterministic rows
+// first, then one slot per accepted random draw in sorted order, of which
+// the first of every run of equal rows is the combined row (Sec. 4.1) and
+// the others stay empty (omega = 0, no fiber); three phases:
+//  1. thread per slot: omega_j, w_j, the other-mode indices of row j and the
 //     fiber hash probe;
 //  2. lanes = columns: z_j (FP64, Hadamard product of the other factors' rows
 //     in ascending mode order) into shared memory and the weighted row
@@ -22,7 +24,7 @@ namespace cpal {
 //     contiguously, ROWS_UNR rows per lane group in flight;
 //  3. the block's part of G_s (pairs a <= c, packed row by row) on the
 //     matrix cores.
-// Blocks past s_bar only clear their share of M.  DD = number of other modes
+// Blocks past the slots only clear their share of M.  DD = number of other modes
 // (0: any, runtime loops).
 #define ROWS_BLK 256
 #define ROWS_UNR 4
@@ -87,7 +89,7 @@ __device__ __forceinline__ void gs_tiles(const double *sz, const double *som, in
 template <typename T, int DD>
 __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     OtherModes om, DevState *st, int R, u64 *__restrict__ samp_idx, double *__restrict__ samp_om,
-    double *__restrict__ samp_w, const u64 *__restrict__ ukey, const u64 *__restrict__ ustart,
+    double *__restrict__ samp_w, const u64 *__restrict__ skeys,
     const FiberSlot *__restrict__ slots, u64 hmask, int hshift, T *__restrict__ zhat,
     unsigned *__restrict__ foff, unsigned *__restrict__ flen, double *__restrict__ gpart,
     T *__restrict__ M, i64 mlen, int ldz) {
@@ -97,31 +99,49 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
   const int tid = threadIdx.x;
   const int ld = R + 1;
   const int d = DD > 0 ? DD : om.d;
-  const i64 s_det = st->s_det, n_urnd = st->n_urnd, s_used = st->s_rnd_used;
-  const i64 s_bar = s_det + n_urnd;
+  const i64 s_det = st->s_det, s_used = st->s_rnd_used;
+  const i64 n_slots = s_det + s_used;
   const double p_det = st->p_det;
-  if (blockIdx.x == 0 && tid == 0) st->s_bar = s_bar;
+  if (blockIdx.x == 0 && tid == 0) st->n_slots = n_slots;
   for (i64 e = (i64)blockIdx.x * blockDim.x + tid; e < mlen; e += (i64)gridDim.x * blockDim.x)
     M[e] = T(0);
   const i64 base = (i64)blockIdx.x * ROWS_BLK;
-  if (base >= s_bar) return;   // uniform per block
-  const int rows = (int)min((i64)ROWS_BLK, s_bar - base);
+  if (base >= n_slots) return;   // uniform per block
+  const int rows = (int)min((i64)ROWS_BLK, n_slots - base);
   // phase 1
   double omj = 0.0;
+  bool active = false;
   if (tid < rows) {
     const i64 j = base + tid;
     u64 lin;
-    double wj;
+    double wj = 0.0;
     bool rnd = false;
     u64 cnt = 0;
+    active = true;
     if (j < s_det) {
       lin = samp_idx[j];
     } else {
-      const i64 u = j - s_det;
-      lin = ukey[u];
-      const u64 end = (u + 1 < n_urnd) ? ustart[u + 1] : (u64)s_used;
-      cnt = end - ustart[u];
+      // slot s_det + i of the sorted accepted draws: the first of a run of
+      // equal rows carries the run (its length by galloping then bisection)
+      const i64 i = j - s_det;
+      lin = skeys[i];
       rnd = true;
+      active = i == 0 || skeys[i - 1] != lin;
+      if (active) {
+        i64 lo = i, hi = s_used, step = 1;
+        for (;;) {
+          const i64 t = i + step;
+          if (t >= s_used) break;
+          if (skeys[t] != lin) { hi = t; break; }
+          lo = t;
+          step <<= 1;
+        }
+        while (hi - lo > 1) {
+          const i64 mid = (lo + hi) >> 1;
+          if (skeys[mid] == lin) lo = mid; else hi = mid;
+        }
+        cnt = (u64)(hi - i);
+      }
     }
     u64 rem = lin;
     double p = 0.0;
@@ -134,26 +154,39 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
         p = (u == 0) ? qv : p * qv;
       }
     }
-    if (rnd) {
-      omj = ((double)cnt * (1.0 - p_det)) / ((double)s_used * p);
-      wj = sqrt(omj);
-    } else {
+    if (!rnd) {
       omj = 1.0;
       wj = 1.0;
+    } else if (active) {
+      omj = ((double)cnt * (1.0 - p_det)) / ((double)s_used * p);
+      wj = sqrt(omj);
     }
     samp_idx[j] = lin;
     samp_om[j] = omj;
     samp_w[j] = wj;
-    u64 h = fiber_hash(lin, hshift);
     unsigned off = 0, len = 0;
-    for (;;) {
-      const FiberSlot sl = slots[h];
-      if (sl.key == lin) { off = sl.off; len = sl.len; break; }
-      if (sl.key == CPAL_EMPTY_KEY) break;
-      h = (h + 1) & hmask;
+    if (active) {
+      u64 h = fiber_hash(lin, hshift);
+      for (;;) {
+        const FiberSlot sl = slots[h];
+        if (sl.key == lin) { off = sl.off; len = sl.len; break; }
+        if (sl.key == CPAL_EMPTY_KEY) break;
+        h = (h + 1) & hmask;
+      }
     }
     foff[j] = off;
     flen[j] = len;
+  }
+  {   // rows of the sampled system (s_bar): one atomic add per workgroup
+    const unsigned na = (unsigned)__popcll(__ballot(active));
+    __shared__ unsigned wact[ROWS_BLK / 64];
+    if ((tid & 63) == 0) wact[tid >> 6] = na;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned t = 0;
+      for (int q = 0; q < ROWS_BLK / 64; ++q) t += wact[q];
+      atomicAdd((unsigned long long *)&st->s_bar, (unsigned long long)t);
+    }
   }
   som[tid] = omj;
   __syncthreads();
@@ -321,11 +354,11 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
 // weighted KRP row).  Empty fibers add nothing to M (they still enter G_s),
 // and with only nonempty fibers a chunk of GT_CHUNK positions spans at most
 // GT_CHUNK + 1 of them.
-#define GP_TILE 4096
+#define GP_TILE 1024
 __global__ void __launch_bounds__(256) k_gp_part(const DevState *st, const unsigned *__restrict__ flen,
                                                  u64 *__restrict__ part_len,
                                                  unsigned *__restrict__ part_cnt) {
-  const i64 n = st->s_bar;
+  const i64 n = st->n_slots;
   const i64 base = (i64)blockIdx.x * GP_TILE;
   u64 sl = 0;
   unsigned sc = 0;
@@ -351,7 +384,7 @@ __global__ void __launch_bounds__(256) k_gp_part(const DevState *st, const unsig
 
 __global__ void __launch_bounds__(1024) k_gp_top(DevState *st, u64 *__restrict__ part_len,
                                                  unsigned *__restrict__ part_cnt) {
-  const i64 n = st->s_bar;
+  const i64 n = st->n_slots;
   const int nb = (int)((n + GP_TILE - 1) / GP_TILE);
   u64 carry_l = 0, carry_c = 0;
   for (int b0 = 0; b0 < nb; b0 += 1024) {
@@ -377,7 +410,7 @@ __global__ void __launch_bounds__(256) k_gp_apply(const DevState *st, const unsi
                                                   const unsigned *__restrict__ part_cnt,
                                                   u64 *__restrict__ cpos, unsigned *__restrict__ coff,
                                                   unsigned *__restrict__ cidx) {
-  const i64 n = st->s_bar;
+  const i64 n = st->n_slots;
   const i64 base = (i64)blockIdx.x * GP_TILE;
   if (base >= n) return;
   u64 cl = part_len[blockIdx.x];
@@ -412,19 +445,27 @@ __global__ void __launch_bounds__(256) k_chunk_first(const DevState *st, const u
   }
 }
 
-// Vector type of 16 bytes holding 16/sizeof(T) elements of T.
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
-template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
 
-template <typename T, int RM>
+// Shared-memory tiled gather: workgroup g takes the chunks g, g + G, ... of
+// GT_CHUNK stream positions and adds into its tile of rows [r0, r0 + rows)
+// of its own partial M.
+//  * per thread, GT_PER_THREAD positions: the nonempty fiber holding the
+//    position (binary search in the chunk's window of fiber starts), then
+//    the nonzero (i_k, x) and the fiber's sampled row; every load is
+//    unconditional (positions past the chunk are clamped to its last one and
+//    masked), so all of them are in flight together;
+//  * then lanes = columns: groups of LPN lanes (LPN = padded row width ldz)
+//    take the wave's nonzeros in turn, lane c adding x * zhat(row, c) into
+//    the tile's row i_k, so the lanes of one shared-memory atomic hit
+//    distinct columns; GT_BATCH nonzeros per group are loaded before they are
+//    added.
+#define GT_BATCH 8
+template <typename T, int LPN>
 __global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
     const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
     const T *__restrict__ zhat, int ldz, T *__restrict__ P, i64 nk, int tile_rows) {
-  typedef typename Vec16<T>::type V;
-  constexpr int VN = Vec16<T>::n;
-  constexpr int NV = RM / VN;                           // 16-byte loads per KRP row
+  constexpr int NPW = 64 / LPN;                         // nonzeros per wave instruction
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   u64 *win = (u64 *)smem_raw;                          // GT_WIN fiber start positions
   T *acc = (T *)(smem_raw + sizeof(u64) * GT_WIN);      // tile_rows x R
@@ -435,20 +476,18 @@ __global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
   if (g >= nch) return;
   const i64 r0 = (i64)blockIdx.y * tile_rows;
   const int rows = (int)min((i64)tile_rows, nk - r0);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int c = lane % LPN, sub = lane / LPN;
   for (int e = tid; e < rows * R; e += GT_THREADS) acc[e] = T(0);
-  for (i64 c = g; c < nch; c += G) {
-    const i64 base = c * GT_CHUNK;
+  for (i64 ch = g; ch < nch; ch += G) {
+    const i64 base = ch * GT_CHUNK;
     const i64 last = min(total, base + GT_CHUNK) - 1;
-    const i64 jlo = chunk_first[c];
-    const i64 jhi = (c + 1 < nch) ? (i64)chunk_first[c + 1] : nf - 1;
+    const i64 jlo = chunk_first[ch];
+    const i64 jhi = (ch + 1 < nch) ? (i64)chunk_first[ch + 1] : nf - 1;
     const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
     __syncthreads();   // previous chunk's readers of win are done
     for (int e = tid; e < nwin; e += GT_THREADS) win[e] = cpos[jlo + e];
     __syncthreads();
-    // Every load below is unconditional (positions past the chunk are clamped
-    // to its last position and masked at the end), so the loads of all
-    // GT_PER_THREAD positions are in flight together.
     int jw[GT_PER_THREAD];
     u64 ee[GT_PER_THREAD];
     bool vv[GT_PER_THREAD];
@@ -474,26 +513,431 @@ __global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
     int ik[GT_PER_THREAD];
     T xx[GT_PER_THREAD];
 #pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) nz.get(ee[u], ik[u], xx[u]);
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      nz.get(ee[u], ik[u], xx[u]);
+      ik[u] = (vv[u] && ik[u] >= r0 && ik[u] < r0 + rows) ? (int)(ik[u] - r0) : -1;
+    }
 #pragma unroll
     for (int u = 0; u < GT_PER_THREAD; ++u) {
-      V zv[NV];
-      const V *zr = (const V *)(zhat + (i64)zrow[u] * ldz);
+      for (int i0 = 0; i0 < 64; i0 += NPW * GT_BATCH) {
+        int kk[GT_BATCH];
+        T xv[GT_BATCH], zv[GT_BATCH];
+        unsigned zr[GT_BATCH];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) zv[v] = zr[v];
-      const bool mine = vv[u] && ik[u] >= r0 && ik[u] < r0 + rows;
-      if (!mine) continue;
-      T *ar = acc + (i64)(ik[u] - r0) * R;
-      const T x = xx[u];
-      const T *zs = (const T *)zv;
+        for (int q = 0; q < GT_BATCH; ++q) {
+          const int src = i0 + q * NPW + sub;
+          kk[q] = __shfl(ik[u], src, 64);
+          xv[q] = __shfl(xx[u], src, 64);
+          zr[q] = __shfl(zrow[u], src, 64);
+        }
 #pragma unroll
-      for (int r = 0; r < RM; ++r)
-        if (r < R) unsafeAtomicAdd(&ar[r], x * zs[r]);
+        for (int q = 0; q < GT_BATCH; ++q) zv[q] = zhat[(i64)zr[q] * ldz + c];
+#pragma unroll
+        for (int q = 0; q < GT_BATCH; ++q)
+          if (kk[q] >= 0 && c < R) unsafeAtomicAdd(&acc[kk[q] * R + c], xv[q] * zv[q]);
+      }
     }
   }
   __syncthreads();
   T *out = P + (i64)g * nk * R + r0 * R;
   for (int e = tid; e < rows * R; e += GT_THREADS) out[e] = acc[e];
+}
+
+// Row-sorted gather: the gathered nonzeros are regrouped by output row i_k
+// (a counting sort), after which every lane group owns a run of one row and
+// accumulates it in registers; no shared-memory float atomics.
+//  1. k_gs_stream: per stream position (as in the tiled gather) the nonzero
+//     (i_k, x) and its KRP row index, written in stream order, and the row
+//     counts (shared-memory histogram flushed once per workgroup when
+//     nk <= GS_LBINS, else global counters);
+//  2. k_gs_scan: row pointers = exclusive scan of the counts (counts reset);
+//  3. k_gs_scatter: each nonzero to its row's range (rank inside the
+//     workgroup from a shared-memory histogram, one global ticket per row
+//     and workgroup);
+//  4. k_gs_rows: lane groups of LPN lanes take LPN consecutive entries,
+//     lane c summing x * zhat(row, c) while the row stays the same and
+//     adding the sum into M(i_k, c) when it changes or the run ends.
+#define GS_LBINS 8192
+template <typename T>
+__global__ void __launch_bounds__(GT_THREADS) k_gs_stream(
+    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
+    i64 nk, int *__restrict__ g_ik, T *__restrict__ g_x, unsigned *__restrict__ g_z,
+    unsigned *__restrict__ cnt) {
+  __shared__ u64 win[GT_WIN];
+  __shared__ unsigned lh[GS_LBINS];
+  const i64 total = st->gathered;
+  const i64 nf = st->n_fib;
+  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
+  const int g = blockIdx.x, G = gridDim.x;
+  if (g >= nch) return;
+  const int tid = threadIdx.x;
+  const bool local = nk <= GS_LBINS;
+  if (local)
+    for (int b = tid; b < nk; b += GT_THREADS) lh[b] = 0u;
+  for (i64 ch = g; ch < nch; ch += G) {
+    const i64 base = ch * GT_CHUNK;
+    const i64 last = min(total, base + GT_CHUNK) - 1;
+    const i64 jlo = chunk_first[ch];
+    const i64 jhi = (ch + 1 < nch) ? (i64)chunk_first[ch + 1] : nf - 1;
+    const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
+    __syncthreads();   // previous chunk's readers of win are done (and lh is cleared)
+    for (int e = tid; e < nwin; e += GT_THREADS) win[e] = cpos[jlo + e];
+    __syncthreads();
+    int jw[GT_PER_THREAD];
+    u64 ee[GT_PER_THREAD];
+    bool vv[GT_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      const i64 pu = base + (i64)u * GT_THREADS + tid;
+      vv[u] = pu <= last;
+      const u64 p = (u64)min(pu, last);
+      int lo = 0, hi = nwin;   // last index with win[idx] <= p
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (win[mid] <= p) lo = mid; else hi = mid;
+      }
+      jw[u] = lo;
+      ee[u] = p - win[lo];
+    }
+    unsigned zrow[GT_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      ee[u] += coff[jlo + jw[u]];
+      zrow[u] = cidx[jlo + jw[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      int ik;
+      T x;
+      nz.get(ee[u], ik, x);
+      if (vv[u]) {
+        const i64 p = base + (i64)u * GT_THREADS + tid;
+        g_ik[p] = ik;
+        g_x[p] = x;
+        g_z[p] = zrow[u];
+        if (local) atomicAdd(&lh[ik], 1u);
+        else atomicAdd(&cnt[ik], 1u);
+      }
+    }
+  }
+  if (local) {
+    __syncthreads();
+    for (int b = tid; b < nk; b += GT_THREADS)
+      if (lh[b]) atomicAdd(&cnt[b], lh[b]);
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_gs_scan(unsigned *__restrict__ cnt, i64 nk,
+                                                  unsigned *__restrict__ rowptr,
+                                                  unsigned *__restrict__ cursor) {
+  unsigned carry = 0;
+  for (i64 b0 = 0; b0 < nk; b0 += 1024) {
+    const i64 b = b0 + threadIdx.x;
+    const unsigned v = b < nk ? cnt[b] : 0u;
+    unsigned tot;
+    const unsigned ex = block_excl_scan<unsigned>(v, &tot);
+    if (b < nk) {
+      rowptr[b] = carry + ex;
+      cursor[b] = carry + ex;
+      cnt[b] = 0u;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) rowptr[nk] = carry;
+}
+
+// Scatter: workgroup b takes the contiguous range [b*per, (b+1)*per) of the
+// stream; pass 1 counts its rows in shared memory, one global ticket per row
+// and workgroup reserves each row's range (nk <= GS_LBINS), pass 2 hands out
+// positions inside the ranges.  Larger nk take one global ticket per nonzero.
+#define GS_SC_THREADS 1024
+template <typename T>
+__global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(
+    const DevState *st, const int *__restrict__ g_ik, const T *__restrict__ g_x,
+    const unsigned *__restrict__ g_z, i64 nk, unsigned *__restrict__ cursor,
+    unsigned *__restrict__ csr_r, T *__restrict__ csr_x, unsigned *__restrict__ csr_z) {
+  __shared__ unsigned lh[GS_LBINS];
+  const i64 total = st->gathered;
+  const i64 per = (total + gridDim.x - 1) / gridDim.x;
+  const i64 p0 = (i64)blockIdx.x * per, p1 = min(total, p0 + per);
+  if (p0 >= p1) return;   // uniform per block
+  const int tid = threadIdx.x;
+  if (nk <= GS_LBINS) {
+    for (int b = tid; b < nk; b += GS_SC_THREADS) lh[b] = 0u;
+    __syncthreads();
+#pragma unroll 4
+    for (i64 p = p0 + tid; p < p1; p += GS_SC_THREADS) atomicAdd(&lh[g_ik[p]], 1u);
+    __syncthreads();
+    for (int b = tid; b < nk; b += GS_SC_THREADS)
+      if (lh[b]) lh[b] = atomicAdd(&cursor[b], lh[b]);
+    __syncthreads();
+#pragma unroll 4
+    for (i64 p = p0 + tid; p < p1; p += GS_SC_THREADS) {
+      const int ik = g_ik[p];
+      const unsigned pos = atomicAdd(&lh[ik], 1u);
+      csr_r[pos] = (unsigned)ik;
+      csr_x[pos] = g_x[p];
+      csr_z[pos] = g_z[p];
+    }
+  } else {
+#pragma unroll 4
+    for (i64 p = p0 + tid; p < p1; p += GS_SC_THREADS) {
+      const int ik = g_ik[p];
+      const unsigned pos = atomicAdd(&cursor[ik], 1u);
+      csr_r[pos] = (unsigned)ik;
+      csr_x[pos] = g_x[p];
+      csr_z[pos] = g_z[p];
+    }
+  }
+}
+
+// Rows: a group of LPN lanes takes LPN consecutive row-sorted entries, lane
+// c loading entry c's (row, x, KRP row) and then, for every entry of the
+// group in order, x * zhat(row, c) (all LPN loads in flight); the running sum
+// goes to M(row, c) when the row changes and at the end.
+template <typename T, int LPN>
+__global__ void __launch_bounds__(256) k_gs_rows(const DevState *st, int R,
+                                                 const unsigned *__restrict__ csr_r,
+                                                 const T *__restrict__ csr_x,
+                                                 const unsigned *__restrict__ csr_z,
+                                                 const T *__restrict__ zhat, int ldz,
+                                                 T *__restrict__ M) {
+  const i64 total = st->gathered;
+  const int lane = threadIdx.x & 63;
+  const int c = lane % LPN, gb = lane - c;   // first lane of the group
+  const i64 grp = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / LPN;
+  const i64 ngrp = ((i64)gridDim.x * blockDim.x) / LPN;
+  const bool col = c < R;
+  for (i64 s0 = grp * LPN; s0 < total; s0 += ngrp * LPN) {
+    const int cnt = (int)min((i64)LPN, total - s0);
+    const i64 e = s0 + min(c, cnt - 1);
+    const unsigned my_r = csr_r[e];
+    const T my_x = csr_x[e];
+    const unsigned my_z = csr_z[e];
+    T zv[LPN];
+#pragma unroll
+    for (int q = 0; q < LPN; ++q) {
+      const unsigned zz = __shfl(my_z, gb + q, 64);
+      zv[q] = zhat[(i64)zz * ldz + c];
+    }
+    unsigned cur = __shfl(my_r, gb, 64);
+    T acc = T(0);
+#pragma unroll
+    for (int q = 0; q < LPN; ++q) {
+      const unsigned rr = __shfl(my_r, gb + q, 64);
+      const T xv = __shfl(my_x, gb + q, 64);
+      if (q < cnt) {
+        if (rr != cur) {
+          if (col) unsafeAtomicAdd(&M[(i64)cur * R + c], acc);
+          cur = rr;
+          acc = T(0);
+        }
+        acc += xv * zv[q];
+      }
+    }
+    if (col) unsafeAtomicAdd(&M[(i64)cur * R + c], acc);
+  }
+}
+
+// Segmented gather: workgroup g takes the chunks g, g + G, ... of GT_CHUNK
+// stream positions; for a chunk
+//  1. per thread, GT_PER_THREAD positions: the nonempty fiber holding the
+//     position (binary search in the chunk's window of fiber starts), the
+//     nonzero (i_k, x) and the fiber's sampled row, with every load
+//     unconditional (positions past the chunk are clamped and masked);
+//  2. the chunk's nonzeros are sorted by i_k in shared memory (stable LSD
+//     radix sort, 6-bit digits ranked with wave ballots, keys i_k << 12 |
+//     position in the chunk);
+//  3. lane groups of LPN lanes (LPN = padded row width ldz) take equal
+//     slices of the sorted list, lane c summing x * zhat(row, c) in a
+//     register while i_k stays the same; a run that ends inside the slice is
+//     added to M(i_k, c) at once, the first and last runs of every slice are
+//     merged across slices in shared memory first, so every row of the chunk
+//     costs one global atomic add per column (rows need i_k < 2^20).
+#define GS_DIG 6
+#define GS_BATCH 32
+template <typename T, int LPN>
+__global__ void __launch_bounds__(GT_THREADS) k_gather_seg(
+    const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
+    int ikbits, const T *__restrict__ zhat, int ldz, T *__restrict__ M) {
+  constexpr int NW = GT_THREADS / 64;
+  constexpr int NG = GT_THREADS / LPN;
+  constexpr int PER = GT_CHUNK / NG;
+  constexpr int NT = 64 * GT_PER_THREAD * NW;   // digit x round x wave counters
+  __shared__ u64 win[GT_WIN];
+  __shared__ unsigned ka[GT_CHUNK], kb[GT_CHUNK];
+  __shared__ T lx[GT_CHUNK];
+  __shared__ unsigned lz[GT_CHUNK];
+  __shared__ unsigned tab[NT];
+  __shared__ int srow[2 * NG];
+  __shared__ T svec[2 * NG][LPN];
+  const i64 total = st->gathered;
+  const i64 nf = st->n_fib;
+  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
+  const int g = blockIdx.x, G = gridDim.x;
+  if (g >= nch) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int gi = tid / LPN, c = tid % LPN;
+  const u64 lt = __lanemask_lt();
+  for (i64 ch = g; ch < nch; ch += G) {
+    const i64 base = ch * GT_CHUNK;
+    const i64 last = min(total, base + GT_CHUNK) - 1;
+    const i64 jlo = chunk_first[ch];
+    const i64 jhi = (ch + 1 < nch) ? (i64)chunk_first[ch + 1] : nf - 1;
+    const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
+    __syncthreads();   // the previous chunk is finished with every shared array
+    for (int e = tid; e < nwin; e += GT_THREADS) win[e] = cpos[jlo + e];
+    __syncthreads();
+    // 1
+    int jw[GT_PER_THREAD];
+    u64 ee[GT_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      const u64 p = (u64)min(base + (i64)u * GT_THREADS + tid, last);
+      int lo = 0, hi = nwin;   // last index with win[idx] <= p
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (win[mid] <= p) lo = mid; else hi = mid;
+      }
+      jw[u] = lo;
+      ee[u] = p - win[lo];
+    }
+    unsigned zrow[GT_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      ee[u] += coff[jlo + jw[u]];
+      zrow[u] = cidx[jlo + jw[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      int ik;
+      T x;
+      nz.get(ee[u], ik, x);
+      const int li = u * GT_THREADS + tid;   // = position - base
+      ka[li] = (base + li <= last) ? (((unsigned)ik << 12) | (unsigned)li) : 0xFFFFFFFFu;
+      lx[li] = x;
+      lz[li] = zrow[u];
+    }
+    // 2
+    unsigned *src = ka, *dst = kb;
+    for (int shift = 12; shift < 12 + ikbits; shift += GS_DIG) {
+      for (int e = tid; e < NT; e += GT_THREADS) tab[e] = 0u;
+      __syncthreads();
+      unsigned key[GT_PER_THREAD], dg[GT_PER_THREAD], rk[GT_PER_THREAD];
+#pragma unroll
+      for (int r = 0; r < GT_PER_THREAD; ++r) {
+        key[r] = src[r * GT_THREADS + tid];
+        dg[r] = (key[r] >> shift) & 63u;
+        u64 peers = ~0ull;
+#pragma unroll
+        for (int b = 0; b < GS_DIG; ++b) {
+          const bool bit = (dg[r] >> b) & 1u;
+          const u64 m = __ballot(bit);
+          peers &= bit ? m : ~m;
+        }
+        rk[r] = (unsigned)__popcll(peers & lt);
+        if (rk[r] == 0) tab[(dg[r] * GT_PER_THREAD + r) * NW + w] = (unsigned)__popcll(peers);
+      }
+      __syncthreads();
+      {   // exclusive scan of tab in (digit, round, wave) order
+        unsigned v[NT / GT_THREADS], sum = 0;
+#pragma unroll
+        for (int q = 0; q < NT / GT_THREADS; ++q) { v[q] = tab[tid * (NT / GT_THREADS) + q]; sum += v[q]; }
+        unsigned tot;
+        unsigned run = block_excl_scan<unsigned>(sum, &tot);
+#pragma unroll
+        for (int q = 0; q < NT / GT_THREADS; ++q) {
+          tab[tid * (NT / GT_THREADS) + q] = run;
+          run += v[q];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < GT_PER_THREAD; ++r)
+        dst[tab[(dg[r] * GT_PER_THREAD + r) * NW + w] + rk[r]] = key[r];
+      __syncthreads();
+      unsigned *t = src; src = dst; dst = t;
+    }
+    // 3
+    const int nvalid = (int)(last - base + 1);
+    const int q0 = gi * PER, q1 = min(nvalid, q0 + PER);
+    int cur = -1, first = -1;
+    T acc = T(0), facc = T(0);
+    if (q0 < q1) {
+      cur = (int)(src[q0] >> 12);
+      for (int q = q0; q < q1; q += GS_BATCH) {
+        unsigned kk[GS_BATCH];
+        T xv[GS_BATCH], zv[GS_BATCH];
+#pragma unroll
+        for (int b = 0; b < GS_BATCH; ++b) {
+          kk[b] = src[min(q + b, q1 - 1)];
+          const unsigned li = kk[b] & 4095u;
+          xv[b] = lx[li];
+          zv[b] = zhat[(i64)lz[li] * ldz + c];
+        }
+#pragma unroll
+        for (int b = 0; b < GS_BATCH; ++b) {
+          if (q + b < q1) {
+            const int r = (int)(kk[b] >> 12);
+            if (r != cur) {
+              if (first < 0) { first = cur; facc = acc; }
+              else if (c < R) unsafeAtomicAdd(&M[(i64)cur * R + c], acc);
+              cur = r;
+              acc = T(0);
+            }
+            acc += xv[b] * zv[b];
+          }
+        }
+      }
+    }
+    // slice ends: slot 2gi = first run, 2gi+1 = last run (-1: none)
+    if (first < 0) { first = cur; facc = acc; cur = -1; }
+    if (c == 0) { srow[2 * gi] = first; srow[2 * gi + 1] = cur; }
+    svec[2 * gi][c] = facc;
+    svec[2 * gi + 1][c] = acc;
+    __syncthreads();
+    if (gi == 0) {
+      int mr = -1;
+      T ma = T(0);
+      for (int sl = 0; sl < 2 * NG; ++sl) {
+        const int r = srow[sl];
+        if (r < 0) continue;
+        if (r != mr) {
+          if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * R + c], ma);
+          mr = r;
+          ma = T(0);
+        }
+        ma += svec[sl][c];
+      }
+      if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * R + c], ma);
+    }
+  }
+}
+
+int gather_row_width(int R);
+
+void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                       const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
+                       const int *ik, const double *v64, i64 nk, const void *zhat, int ldz, void *M,
+                       int grid, hipStream_t s) {
+  int ikbits = 1;
+  while ((1ll << ikbits) < nk) ++ikbits;
+  const int rm = gather_row_width(R);
+  if (f64) {
+    NzLoad<double> nz{ik, v64};
+    auto k = rm == 16 ? k_gather_seg<double, 16> : rm == 32 ? k_gather_seg<double, 32>
+                                                            : k_gather_seg<double, 64>;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
+                       chunk_first, nz, ikbits, (const double *)zhat, ldz, (double *)M);
+  } else {
+    NzLoad<float> nz{pairs};
+    auto k = rm == 16 ? k_gather_seg<float, 16> : rm == 32 ? k_gather_seg<float, 32>
+                                                           : k_gather_seg<float, 64>;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
+                       chunk_first, nz, ikbits, (const float *)zhat, ldz, (float *)M);
+  }
 }
 
 // M = sum over the workgroups that had work of their partials.
@@ -726,7 +1170,7 @@ static int grid_for(i64 n, int blk, int maxg = 8192) {
 }
 
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
-                 double *samp_om, double *samp_w, const u64 *ukey, const u64 *ustart,
+                 double *samp_om, double *samp_w, const u64 *skeys,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
                  unsigned *flen, double *gpart, void *M, i64 mlen, int ldz, hipStream_t s) {
   const int nb = (int)((cap + ROWS_BLK - 1) / ROWS_BLK);
@@ -739,13 +1183,13 @@ void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u
     auto k = dd == 2 ? k_rows<double, 2> : dd == 3 ? k_rows<double, 3>
            : dd == 4 ? k_rows<double, 4> : k_rows<double, 0>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
-                       ukey, ustart, slots, hmask, hshift, (double *)zhat, foff, flen, gpart,
+                       skeys, slots, hmask, hshift, (double *)zhat, foff, flen, gpart,
                        (double *)M, mlen, ldz);
   } else {
     auto k = dd == 2 ? k_rows<float, 2> : dd == 3 ? k_rows<float, 3>
            : dd == 4 ? k_rows<float, 4> : k_rows<float, 0>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
-                       ukey, ustart, slots, hmask, hshift, (float *)zhat, foff, flen, gpart,
+                       skeys, slots, hmask, hshift, (float *)zhat, foff, flen, gpart,
                        (float *)M, mlen, ldz);
   }
 }
@@ -791,17 +1235,19 @@ void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *cpos, c
   const size_t sh = sizeof(u64) * GT_WIN + elem * (size_t)tr * R;
   const dim3 grid(G, ntiles), blk(GT_THREADS);
   const int rm = gather_row_width(R);
-#define CPAL_GT(TT, RMV, NZ)                                                                      \
-  hipLaunchKernelGGL((k_gather_tile<TT, RMV>), grid, blk, sh, s, st, R, cpos, coff, cidx,        \
-                     chunk_first, NZ, (const TT *)zhat, ldz, (TT *)P, nk, tr)
   if (f64) {
     NzLoad<double> nz{ik, v64};
-    if (rm == 16) CPAL_GT(double, 16, nz); else if (rm == 32) CPAL_GT(double, 32, nz); else CPAL_GT(double, 64, nz);
+    auto k = rm == 16 ? k_gather_tile<double, 16> : rm == 32 ? k_gather_tile<double, 32>
+                                                             : k_gather_tile<double, 64>;
+    hipLaunchKernelGGL(k, grid, blk, sh, s, st, R, cpos, coff, cidx, chunk_first, nz,
+                       (const double *)zhat, ldz, (double *)P, nk, tr);
   } else {
     NzLoad<float> nz{pairs};
-    if (rm == 16) CPAL_GT(float, 16, nz); else if (rm == 32) CPAL_GT(float, 32, nz); else CPAL_GT(float, 64, nz);
+    auto k = rm == 16 ? k_gather_tile<float, 16> : rm == 32 ? k_gather_tile<float, 32>
+                                                            : k_gather_tile<float, 64>;
+    hipLaunchKernelGGL(k, grid, blk, sh, s, st, R, cpos, coff, cidx, chunk_first, nz,
+                       (const float *)zhat, ldz, (float *)P, nk, tr);
   }
-#undef CPAL_GT
 }
 
 void launch_reduce_partials(bool f64, const DevState *st, int R, const void *P, void *M, i64 nk,
@@ -828,6 +1274,73 @@ void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const u
     hipLaunchKernelGGL(k_gather<float>, dim3(grid), dim3(256), 0, s, st, R, cpos, coff, cidx, nz,
                        (const float *)zhat, (float *)M, ldz);
   }
+}
+
+void launch_gather_sorted(bool f64, const DevState *st, int R, const u64 *cpos,
+                          const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
+                          const uint2 *pairs, const int *ik, const double *v64, i64 nk,
+                          int *g_ik, void *g_x, unsigned *g_z, unsigned *cnt, unsigned *rowptr,
+                          unsigned *cursor, unsigned *csr_r, void *csr_x, unsigned *csr_z,
+                          const void *zhat, int ldz, void *M, int grid, hipStream_t s) {
+  const int rm = gather_row_width(R);
+  if (f64) {
+    NzLoad<double> nz{ik, v64};
+    hipLaunchKernelGGL(k_gs_stream<double>, dim3(grid), dim3(GT_THREADS), 0, s, st, cpos, coff,
+                       cidx, chunk_first, nz, nk, g_ik, (double *)g_x, g_z, cnt);
+  } else {
+    NzLoad<float> nz{pairs};
+    hipLaunchKernelGGL(k_gs_stream<float>, dim3(grid), dim3(GT_THREADS), 0, s, st, cpos, coff,
+                       cidx, chunk_first, nz, nk, g_ik, (float *)g_x, g_z, cnt);
+  }
+  hipLaunchKernelGGL(k_gs_scan, dim3(1), dim3(1024), 0, s, cnt, nk, rowptr, cursor);
+  if (f64) {
+    hipLaunchKernelGGL(k_gs_scatter<double>, dim3(64), dim3(GS_SC_THREADS), 0, s, st, g_ik,
+                       (const double *)g_x, g_z, nk, cursor, csr_r, (double *)csr_x, csr_z);
+    auto k = rm == 16 ? k_gs_rows<double, 16> : rm == 32 ? k_gs_rows<double, 32>
+                                                         : k_gs_rows<double, 64>;
+    hipLaunchKernelGGL(k, dim3(8 * grid), dim3(256), 0, s, st, R, csr_r, (const double *)csr_x,
+                       csr_z, (const double *)zhat, ldz, (double *)M);
+  } else {
+    hipLaunchKernelGGL(k_gs_scatter<float>, dim3(64), dim3(GS_SC_THREADS), 0, s, st, g_ik,
+                       (const float *)g_x, g_z, nk, cursor, csr_r, (float *)csr_x, csr_z);
+    auto k = rm == 16 ? k_gs_rows<float, 16> : rm == 32 ? k_gs_rows<float, 32>
+                                                        : k_gs_rows<float, 64>;
+    hipLaunchKernelGGL(k, dim3(8 * grid), dim3(256), 0, s, st, R, csr_r, (const float *)csr_x,
+                       csr_z, (const float *)zhat, ldz, (float *)M);
+  }
+}
+
+// Sampled rows in order (active slots only, s_bar of them) into the caller's
+// buffers, at most cap; *count = s_bar.  One workgroup (audit path).
+__global__ void __launch_bounds__(1024) k_samples_out(const DevState *st,
+                                                      const u64 *__restrict__ samp_idx,
+                                                      const double *__restrict__ samp_om,
+                                                      const double *__restrict__ samp_w, i64 cap,
+                                                      u64 *idx, double *om, double *w,
+                                                      i64 *count) {
+  const i64 n = st->n_slots, s_det = st->s_det;
+  i64 carry = 0;
+  for (i64 b0 = 0; b0 < n; b0 += 1024) {
+    const i64 j = b0 + threadIdx.x;
+    const unsigned a = (j < n && (j < s_det || samp_om[j] > 0.0)) ? 1u : 0u;
+    unsigned tot;
+    const unsigned ex = block_excl_scan<unsigned>(a, &tot);
+    const i64 o = carry + ex;
+    if (a && o < cap) {
+      if (idx) idx[o] = samp_idx[j];
+      if (om) om[o] = samp_om[j];
+      if (w) w[o] = samp_w[j];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && count) *count = st->s_bar;
+}
+
+void launch_samples_out(const DevState *st, const u64 *samp_idx, const double *samp_om,
+                        const double *samp_w, i64 cap, u64 *idx, double *om, double *w,
+                        i64 *count, hipStream_t s) {
+  hipLaunchKernelGGL(k_samples_out, dim3(1), dim3(1024), 0, s, st, samp_idx, samp_om, samp_w, cap,
+                     idx, om, w, count);
 }
 
 void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, const Decomp *dc,

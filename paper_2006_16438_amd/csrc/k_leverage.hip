@@ -146,11 +146,6 @@ __device__ bool chol_right(double *S, double *L, int R, double tol, int *fail_sh
   return true;
 }
 
-// Register form of the same right-looking Cholesky for R <= RM <= 32: lane
-// i holds row i of the lower triangle of S in registers; column j's pivot is
-// broadcast from lane j, and the column entries L(l,j) from lane l.  Every
-// entry sees the same operations in the same order as chol_right.  S and L
-// are shared-memory R x R arrays (S read, L written).  One wavefront.
 // Value of v in lane l (l wave-uniform) through two scalar lane reads.
 __device__ __forceinline__ double lane_value(double v, int l) {
   const long long b = __double_as_longlong(v);
@@ -159,8 +154,15 @@ __device__ __forceinline__ double lane_value(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Register form of the same right-looking Cholesky for R <= RM <= 32: lane
+// i holds row i of the lower triangle of S in registers; column j's pivot is
+// read from lane j, and the column entries L(l,j) from lane l.  Every entry
+// of the lower triangle sees the same operations in the same order as
+// chol_right.  S and L are shared-memory R x R arrays (S read, L written in
+// full when the factorization succeeds).  One wavefront.
+
 template <int RM>
-__device__ bool chol_regs(const double *S, double *L, int R, double tol) {
+__device__ __forceinline__ bool chol_regs(const double *S, double *L, int R, double tol) {
   const int lane = threadIdx.x;
   double g[RM];
 #pragma unroll
@@ -210,13 +212,17 @@ __global__ void __launch_bounds__(64) k_lev_rowspace(const double *__restrict__ 
                                                      int *pinv_store) {
   __shared__ double K[CPAL_MAXR * CPAL_MAXR];
   __shared__ double L[CPAL_MAXR * CPAL_MAXR];
+  __shared__ double sA[CPAL_MAXR * CPAL_MAXR];   // A, n x R with n < R
   __shared__ int fail;
   const int tid = threadIdx.x;
+#pragma unroll 8
+  for (int e = tid; e < n * R; e += 64) sA[e] = A[e];
+  __syncthreads();
   for (int e = tid; e < n * n; e += 64) {
     const int i = e / n, j = e - i * n;
     if (j > i) continue;
     double acc = 0.0;
-    for (int r = 0; r < R; ++r) acc = acc + A[(i64)i * R + r] * A[(i64)j * R + r];
+    for (int r = 0; r < R; ++r) acc = acc + sA[i * R + r] * sA[j * R + r];
     K[i * n + j] = acc;
     K[j * n + i] = acc;
   }
@@ -224,7 +230,10 @@ __global__ void __launch_bounds__(64) k_lev_rowspace(const double *__restrict__ 
   double maxdiag = 0.0;
   for (int j = 0; j < n; ++j) maxdiag = fmax(maxdiag, K[j * n + j]);
   const double tol = ((double)n * 0x1p-52) * maxdiag;
-  const bool ok = chol_right(K, L, n, tol, &fail);
+  bool ok;
+  if (n <= 16) ok = chol_regs<16>(K, L, n, tol);
+  else if (n <= 32) ok = chol_regs<32>(K, L, n, tol);
+  else ok = chol_right(K, L, n, tol, &fail);
   if (ok) {
     double v = 1.0 / (double)R;
     if (v > 1.0) v = 1.0;

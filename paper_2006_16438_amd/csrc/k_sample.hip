@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u6
   const int tid = threadIdx.x;
   if (tid == 0) {
     st->det_count = 0; st->combos = 0; st->s_det = 0; st->s_rnd = 0; st->s_rnd_used = 0;
-    st->s_bar = 0; st->n_urnd = 0; st->draws = 0; st->chunk_next = 0; st->accepted = 0;
+    st->s_bar = 0; st->n_slots = 0; st->draws = 0; st->chunk_next = 0; st->accepted = 0;
     st->nchunks = 0; st->gathered = 0; st->p_det = 0.0; st->tau_eff = 1.0; st->flags = 0;
     for (int u = 0; u < CPAL_MAXORDER; ++u) st->ncand[u] = 0;
   }

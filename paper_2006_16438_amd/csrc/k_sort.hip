@@ -15,7 +15,7 @@ namespace cpal {
 #define RS_THREADS 256
 #define RS_ROUNDS 4
 #define RS_TILE (RS_THREADS * RS_ROUNDS)
-#define SCAN_TILE 4096
+#define SCAN_TILE 1024
 
 // ------------------------------------------------------------------ scan ---
 __global__ void __launch_bounds__(256) k_scan_part(const unsigned *__restrict__ in, i64 cap,
@@ -244,56 +244,6 @@ void sort_keys(u64 *keys, unsigned *vals, u64 *tmp_keys, unsigned *tmp_vals, voi
     if (vals) hipMemcpyAsync(vals, tmp_vals, sizeof(unsigned) * (size_t)capn,
                              hipMemcpyDeviceToDevice, s);
   }
-}
-
-// ------------------------------------------------------------ unique runs ---
-// Run starts of a sorted key array (n = *n_dev): part counts the starts per
-// SCAN_TILE tile, k_scan_top scans the counts (total = number of runs),
-// apply writes ukey[r] = the run's key and ustart[r] = its first index.
-__global__ void __launch_bounds__(256) k_uq_part(const u64 *__restrict__ keys, i64 cap,
-                                                 const i64 *n_dev, u64 *__restrict__ part) {
-  const i64 n = min(*n_dev, cap);
-  const i64 base = (i64)blockIdx.x * SCAN_TILE;
-  u64 c = 0;
-  for (int r = 0; r < SCAN_TILE / 256; ++r) {
-    const i64 i = base + r * 256 + threadIdx.x;
-    if (i < n) c += (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
-  }
-  c = wave_sum(c);
-  __shared__ u64 ws[4];
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
-}
-
-__global__ void __launch_bounds__(256) k_uq_apply(const u64 *__restrict__ keys, i64 cap,
-                                                  const i64 *n_dev, const u64 *__restrict__ part,
-                                                  u64 *__restrict__ ukey, u64 *__restrict__ ustart) {
-  const i64 n = min(*n_dev, cap);
-  const i64 base = (i64)blockIdx.x * SCAN_TILE;
-  if (base >= n) return;
-  u64 carry = part[blockIdx.x];
-  for (int r = 0; r < SCAN_TILE / 256; ++r) {
-    const i64 i = base + r * 256 + threadIdx.x;
-    const unsigned f = (i < n && (i == 0 || keys[i] != keys[i - 1])) ? 1u : 0u;
-    unsigned tot;
-    const unsigned ex = block_excl_scan<unsigned>(f, &tot);
-    if (f) {
-      ukey[carry + ex] = keys[i];
-      ustart[carry + ex] = (u64)i;
-    }
-    carry += tot;
-  }
-}
-
-void unique_runs(const u64 *keys, i64 cap, const i64 *n_dev, u64 *n_runs, u64 *ukey, u64 *ustart,
-                 void *scratch, hipStream_t s) {
-  const int nb = (int)((cap + SCAN_TILE - 1) / SCAN_TILE);
-  u64 *part = (u64 *)scratch;
-  if (nb == 0) return;
-  hipLaunchKernelGGL(k_uq_part, dim3(nb), dim3(256), 0, s, keys, cap, n_dev, part);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, part, nb, n_runs);
-  hipLaunchKernelGGL(k_uq_apply, dim3(nb), dim3(256), 0, s, keys, cap, n_dev, part, ukey, ustart);
 }
 
 }  // namespace cpal
