@@ -302,7 +302,7 @@ void refresh_leverage(cpal_ctx *c, int m) {
   const int nblk = (int)((md.n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
   launch_decomp(c->lev_part, nblk, c->R, c->dc, &c->st->lev_pinv[m], skip, c->stream);
   launch_lev_rows(md.A, md.n, c->R, c->dc, md.lev, md.w, c->lev_bsum, skip, c->stream);
-  launch_lev_cdf(md.w, md.n, c->lev_bsum, md.C, md.q, nullptr, c->stream);
+  launch_lev_cdf(md.w, md.n, c->R, c->lev_bsum, md.C, md.q, nullptr, c->stream);
 }
 
 cpal_status check_hip(cpal_ctx *c, hipError_t e, const char *what) {

@@ -195,6 +195,28 @@ __device__ __forceinline__ T block_excl_scan(T v, T *total) {
   return res;
 }
 
+// Value of v in lane l (l wave-uniform) through two scalar lane reads.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Lanes = columns: a wave holds 64 / LPN rows, lane c of group g holding
+// column c of row g.  group_value(v, j) = column j of the caller's row.
+template <int LPN>
+__device__ __forceinline__ double group_value(double v, int j) {
+  const int g = (int)(threadIdx.x & 63) / LPN;
+  double r = lane_value(v, j);
+#pragma unroll
+  for (int q = 1; q < 64 / LPN; ++q) {
+    const double t = lane_value(v, q * LPN + j);
+    r = g == q ? t : r;
+  }
+  return r;
+}
+
 // ------------------------------------------------------------ launchers
 namespace cpal {
 
@@ -209,7 +231,7 @@ void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_s
                    const int *skip, hipStream_t s);
 void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *lev, u64 *w,
                      u64 *blocksum, const int *skip, hipStream_t s);
-void launch_lev_cdf(const u64 *w, i64 n, const u64 *blocksum, u64 *C, double *q,
+void launch_lev_cdf(const u64 *w, i64 n, int R, const u64 *blocksum, u64 *C, double *q,
                     int *flag_or, hipStream_t s);
 
 // radix sort of u64 keys with optional u32 payload, device-resident count --

@@ -962,100 +962,57 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const DevState *st, con
 }
 
 // ------------------------------------------------------------------- solve --
-// A_k(i,:) = M(i,:) G_s^{-1}: forward and back substitution with the Cholesky
-// factor, or the pseudo-inverse from the eigendecomposition.  Rows are
-// independent; FP64 throughout.  Skipped when the update hit a state error.
-#define SOLVE_BLK 128
-template <typename T, int RM>
-__global__ void __launch_bounds__(SOLVE_BLK) k_solve_rows(const DevState *st, i64 n, int R,
-                                                          const T *__restrict__ M,
-                                                          const Decomp *__restrict__ dc,
-                                                          double *__restrict__ A,
-                                                          float *__restrict__ A32) {
-  extern __shared__ double sm[];   // R*R factor, R lambdas, then SOLVE_BLK x (2R+1) rows
+// A_k(i,:) = M(i,:) G_s^{-1}: forward substitution with the Cholesky factor
+// (subtractions in ascending order), back substitution (right-looking:
+// subtractions in descending order), or the pseudo-inverse from the
+// eigendecomposition.  Lanes = columns, LPN lanes per row (R <= LPN); FP64
+// throughout.  Skipped when the update hit a state error.  256 threads.
+template <typename T, int LPN>
+__global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, int R,
+                                                    const T *__restrict__ M,
+                                                    const Decomp *__restrict__ dc,
+                                                    double *__restrict__ A,
+                                                    float *__restrict__ A32) {
+  extern __shared__ double sL[];   // R*R factor (L, or V)
   if (st->flags & CPAL_FLAG_STATE) return;
   const int pinv = dc->pinv;
-  double *sL = sm;
-  double *slam = sm + R * R;
-  const int ld = 2 * R + 1;
-  double *sy = slam + R;
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = pinv ? dc->V[e] : dc->L[e];
-  for (int e = threadIdx.x; e < R; e += blockDim.x)
-    slam[e] = (pinv && dc->lam[e] > dc->etol) ? dc->lam[e] : 0.0;
-  const i64 r0 = (i64)blockIdx.x * blockDim.x;
-  const int rows = (int)min((i64)blockDim.x, n - r0);
-  for (int e = threadIdx.x; e < rows * R; e += blockDim.x) {
-    const int r = e / R, c = e - r * R;
-    sy[r * ld + c] = (double)M[r0 * R + e];
-  }
   __syncthreads();
-  if (threadIdx.x < rows) {
-    double *ys = sy + threadIdx.x * ld;
-    if (!pinv) {
-      if constexpr (RM > 0) {
-        double y[RM];
-#pragma unroll
-        for (int j = 0; j < RM; ++j) y[j] = (j < R) ? ys[j] : 0.0;
-#pragma unroll
-        for (int j = 0; j < RM; ++j) {
-          if (j < R) {
-            double v = y[j];
-#pragma unroll
-            for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * y[p];
-            y[j] = v / sL[j * R + j];
-          }
-        }
-#pragma unroll
-        for (int j = RM - 1; j >= 0; --j) {
-          if (j < R) {
-            double v = y[j];
-#pragma unroll
-            for (int p = j + 1; p < RM; ++p)
-              if (p < R) v = v - sL[p * R + j] * y[p];
-            y[j] = v / sL[j * R + j];
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < RM; ++j)
-          if (j < R) ys[j] = y[j];
-      } else {
-        for (int j = 0; j < R; ++j) {
-          double v = ys[j];
-          for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * ys[p];
-          ys[j] = v / sL[j * R + j];
-        }
-        for (int j = R - 1; j >= 0; --j) {
-          double v = ys[j];
-          for (int p = j + 1; p < R; ++p) v = v - sL[p * R + j] * ys[p];
-          ys[j] = v / sL[j * R + j];
-        }
-      }
-    } else {
-      // x = sum_j (v_j . m / lam_j) v_j over the kept eigenpairs
-      double *cs = ys + R;
-      for (int j = 0; j < R; ++j) {
-        double c = 0.0;
-        if (slam[j] > 0.0) {
-          double v = 0.0;
-          for (int p = 0; p < R; ++p) v = v + sL[p * R + j] * ys[p];
-          c = v / slam[j];
-        }
-        cs[j] = c;
-      }
-      for (int r = 0; r < R; ++r) {
-        double v = 0.0;
-        for (int j = 0; j < R; ++j)
-          if (slam[j] > 0.0) v = v + cs[j] * sL[r * R + j];
-        ys[r] = v;
-      }
+  const int tid = threadIdx.x;
+  const int c = (tid & 63) % LPN;
+  const i64 row = ((i64)blockIdx.x * blockDim.x + tid) / LPN;
+  if (row >= n) return;   // uniform per lane group
+  const bool col = c < R;
+  const int cl = col ? c : R - 1;
+  double v = col ? (double)M[row * R + c] : 0.0;
+  if (!pinv) {
+    for (int j = 0; j < R; ++j) {
+      const double yj = group_value<LPN>(v, j) / sL[j * R + j];
+      if (c == j) v = yj;
+      else if (c > j && col) v = v - sL[c * R + j] * yj;
     }
+    for (int j = R - 1; j >= 0; --j) {
+      const double xj = group_value<LPN>(v, j) / sL[j * R + j];
+      if (c == j) v = xj;
+      else if (c < j) v = v - sL[j * R + c] * xj;
+    }
+  } else {
+    // x = sum over kept j of ((v_j . m) / lambda_j) v_j
+    const double etol = dc->etol;
+    double t = 0.0;
+    for (int p = 0; p < R; ++p) t = t + sL[p * R + cl] * group_value<LPN>(v, p);
+    const double lam = dc->lam[cl];
+    const double cj = lam > etol ? t / lam : 0.0;
+    double x = 0.0;
+    for (int j = 0; j < R; ++j) {
+      const double cv = group_value<LPN>(cj, j);
+      if (dc->lam[j] > etol) x = x + cv * sL[cl * R + j];
+    }
+    v = x;
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < rows * R; e += blockDim.x) {
-    const int r = e / R, c = e - r * R;
-    const double v = sy[r * ld + c];
-    A[r0 * R + e] = v;
-    A32[r0 * R + e] = (float)v;
+  if (col) {
+    A[row * R + c] = v;
+    A32[row * R + c] = (float)v;
   }
 }
 
@@ -1345,18 +1302,18 @@ void launch_samples_out(const DevState *st, const u64 *samp_idx, const double *s
 
 void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, const Decomp *dc,
                        double *A, float *A32, hipStream_t s) {
-  const int bs = R > 32 ? 64 : SOLVE_BLK;   // rows per block (shared memory <= 100 KB)
-  const int nb = (int)((n + bs - 1) / bs);
-  const size_t sh = sizeof(double) * ((size_t)R * R + R + (size_t)bs * (2 * R + 1));
-#define CPAL_SOLVE(TT, RMV)                                                                       \
-  hipLaunchKernelGGL((k_solve_rows<TT, RMV>), dim3(nb), dim3(bs), sh, s, st, n, R,                \
-                     (const TT *)M, dc, A, A32)
+  const int lpn = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
+  const int nb = (int)((n * lpn + 255) / 256);
+  const size_t sh = sizeof(double) * (size_t)R * R;
   if (f64) {
-    if (R <= 16) CPAL_SOLVE(double, 16); else if (R <= 32) CPAL_SOLVE(double, 32); else CPAL_SOLVE(double, 0);
+    auto k = lpn == 16 ? k_solve_rows<double, 16> : lpn == 32 ? k_solve_rows<double, 32>
+                                                              : k_solve_rows<double, 64>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const double *)M, dc, A, A32);
   } else {
-    if (R <= 16) CPAL_SOLVE(float, 16); else if (R <= 32) CPAL_SOLVE(float, 32); else CPAL_SOLVE(float, 0);
+    auto k = lpn == 16 ? k_solve_rows<float, 16> : lpn == 32 ? k_solve_rows<float, 32>
+                                                             : k_solve_rows<float, 64>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const float *)M, dc, A, A32);
   }
-#undef CPAL_SOLVE
 }
 
 void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s) {

@@ -21,7 +21,8 @@ __device__ __forceinline__ void pair_of(int p, int R, int &a, int &c) {
 }
 
 // part[b][p]: sum over the rows of block b of A(r,a)*A(r,c), pair p = (a<=c).
-__global__ void __launch_bounds__(256) k_lev_gram_partial(const double *__restrict__ A, i64 n,
+#define GRAM_THREADS 512
+__global__ void __launch_bounds__(GRAM_THREADS) k_lev_gram_partial(const double *__restrict__ A, i64 n,
                                                           int R, double *__restrict__ part,
                                                           const int *skip) {
   extern __shared__ double sA[];  // CPAL_GRAM_ROWS x R
@@ -35,7 +36,15 @@ __global__ void __launch_bounds__(256) k_lev_gram_partial(const double *__restri
     int a, c;
     pair_of(p, R, a, c);
     double acc = 0.0;
-    for (int r = 0; r < rows; ++r) acc = acc + sA[r * R + a] * sA[r * R + c];
+    int r = 0;
+    for (; r + 8 <= rows; r += 8) {   // products first, then added in row order
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = sA[(r + q) * R + a] * sA[(r + q) * R + c];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc = acc + t[q];
+    }
+    for (; r < rows; ++r) acc = acc + sA[r * R + a] * sA[r * R + c];
     part[(i64)blockIdx.x * np + p] = acc;
   }
 }
@@ -146,14 +155,6 @@ __device__ bool chol_right(double *S, double *L, int R, double tol, int *fail_sh
   return true;
 }
 
-// Value of v in lane l (l wave-uniform) through two scalar lane reads.
-__device__ __forceinline__ double lane_value(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Register form of the same right-looking Cholesky for R <= RM <= 32: lane
 // i holds row i of the lower triangle of S in registers; column j's pivot is
 // read from lane j, and the column entries L(l,j) from lane l.  Every entry
@@ -208,8 +209,8 @@ __device__ __forceinline__ bool chol_regs(const double *S, double *L, int R, dou
 // 1).  Otherwise *skip = 0 and the Gram / eigen path runs.  One block.
 __global__ void __launch_bounds__(64) k_lev_rowspace(const double *__restrict__ A, int n, int R,
                                                      double *__restrict__ lev, u64 *__restrict__ w,
-                                                     u64 *__restrict__ blocksum, int *skip,
-                                                     int *pinv_store) {
+                                                     u64 *__restrict__ blocksum, int rb,
+                                                     int *skip, int *pinv_store) {
   __shared__ double K[CPAL_MAXR * CPAL_MAXR];
   __shared__ double L[CPAL_MAXR * CPAL_MAXR];
   __shared__ double sA[CPAL_MAXR * CPAL_MAXR];   // A, n x R with n < R
@@ -239,7 +240,8 @@ __global__ void __launch_bounds__(64) k_lev_rowspace(const double *__restrict__ 
     if (v > 1.0) v = 1.0;
     const u64 wi = (u64)(v * 0x1p52);
     for (int i = tid; i < n; i += 64) { lev[i] = 1.0; w[i] = wi; }
-    if (tid == 0) { blocksum[0] = wi * (u64)n; *pinv_store = 1; }
+    for (int b = tid; b * rb < n; b += 64) blocksum[b] = wi * (u64)min(rb, n - b * rb);
+    if (tid == 0) *pinv_store = 1;
   }
   if (tid == 0) *skip = ok ? 1 : 0;
 }
@@ -344,116 +346,87 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double *__restrict__ 
   if (threadIdx.x == 0) out[p] = red[0];
 }
 
-// Per row: l_i, w_i; per block of 128 rows: sum of w.  The row is staged
-// through shared memory (coalesced).  For RM > 0 (R <= RM <= 32) it is held
-// in registers and the substitution loops are unrolled; RM = 0 works on the
-// shared-memory copy.  Both run the canonical operation order.
-#define LEV_ROWS 128
-template <int RM>
-__global__ void __launch_bounds__(LEV_ROWS) k_lev_rows(const double *__restrict__ A, i64 n, int R,
-                                                      const Decomp *__restrict__ dc,
-                                                      double *__restrict__ lev,
-                                                      u64 *__restrict__ w,
-                                                      u64 *__restrict__ blocksum,
-                                                      const int *skip) {
-  extern __shared__ double sm[];
+// Leverage of the rows of A (Def. 3.4): l_i = ||L^{-1} a_i||^2 with the
+// Cholesky factor (forward substitution, y_j subtracted in ascending order,
+// squares summed in ascending order), or sum over the kept eigenpairs of
+// (v_j . a_i)^2 / lambda_j; then w_i = floor(2^52 min(l_i/R, 1)) and the
+// block's sum of w.  Lanes = columns, LPN lanes per row (R <= LPN), every
+// operation of a row in the same order as the sequential form.  Blocks of
+// 256 threads = 256 / LPN rows.
+template <int LPN>
+__global__ void __launch_bounds__(256) k_lev_rows(const double *__restrict__ A, i64 n, int R,
+                                                  const Decomp *__restrict__ dc,
+                                                  double *__restrict__ lev,
+                                                  u64 *__restrict__ w,
+                                                  u64 *__restrict__ blocksum,
+                                                  const int *skip) {
+  extern __shared__ double sL[];          // R*R (L, or V)
+  __shared__ u64 wsum[4];
   if (skip && *skip) return;
-  double *sL = sm;                       // R*R (L, or V)
-  double *sy = sm + R * R;               // LEV_ROWS x (R+1), padded rows
   const int pinv = dc->pinv;
   for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = pinv ? dc->V[e] : dc->L[e];
-  const i64 r0 = (i64)blockIdx.x * LEV_ROWS;
-  const int rows = (int)min((i64)LEV_ROWS, n - r0);
-  const int ld = R + 1;
-  for (int e = threadIdx.x; e < rows * R; e += blockDim.x) {
-    const int r = e / R, c = e - r * R;
-    sy[r * ld + c] = A[r0 * R + e];
-  }
   __syncthreads();
-  u64 wi = 0;
-  if (threadIdx.x < rows) {
+  const int tid = threadIdx.x, wid = tid >> 6;
+  const int c = (tid & 63) % LPN;
+  const i64 row = (i64)blockIdx.x * (256 / LPN) + tid / LPN;
+  const double etol = dc->etol;
+  u64 wacc = 0;
+  {
+    const bool live = row < n;
+    double v = (live && c < R) ? A[row * R + c] : 0.0;
     double acc = 0.0;
-    double *ys = sy + threadIdx.x * ld;
-    if constexpr (RM > 0) {
-      double y[RM];
-#pragma unroll
-      for (int j = 0; j < RM; ++j) y[j] = (j < R) ? ys[j] : 0.0;
-      if (!pinv) {
-#pragma unroll
-        for (int j = 0; j < RM; ++j) {
-          if (j < R) {
-            double v = y[j];
-#pragma unroll
-            for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * y[p];
-            y[j] = v / sL[j * R + j];
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < RM; ++j)
-          if (j < R) acc = acc + y[j] * y[j];
-      } else {
-        const double etol = dc->etol;
-        for (int j = 0; j < R; ++j) {
-          const double lam = dc->lam[j];
-          if (!(lam > etol)) continue;
-          double t = 0.0;
-#pragma unroll
-          for (int p = 0; p < RM; ++p)
-            if (p < R) t = t + sL[p * R + j] * y[p];
-          acc = acc + (t * t) / lam;
-        }
+    if (!pinv) {
+      for (int j = 0; j < R; ++j) {
+        const double yj = group_value<LPN>(v, j) / sL[j * R + j];
+        if (c == j) v = yj;
+        else if (c > j && c < R) v = v - sL[c * R + j] * yj;
+        acc = acc + yj * yj;
       }
     } else {
-      if (!pinv) {
-        for (int j = 0; j < R; ++j) {
-          double v = ys[j];
-          for (int p = 0; p < j; ++p) v = v - sL[j * R + p] * ys[p];
-          ys[j] = v / sL[j * R + j];
-        }
-        for (int j = 0; j < R; ++j) acc = acc + ys[j] * ys[j];
-      } else {
-        const double etol = dc->etol;
-        for (int j = 0; j < R; ++j) {
-          const double lam = dc->lam[j];
-          if (!(lam > etol)) continue;
-          double t = 0.0;
-          for (int p = 0; p < R; ++p) t = t + sL[p * R + j] * ys[p];
-          acc = acc + (t * t) / lam;
-        }
+      // lane j: t_j = sum_p V(p,j) a_p in ascending p
+      double t = 0.0;
+      for (int p = 0; p < R; ++p) t = t + sL[p * R + min(c, R - 1)] * group_value<LPN>(v, p);
+      for (int j = 0; j < R; ++j) {
+        const double lam = dc->lam[j];
+        const double tj = group_value<LPN>(t, j);
+        if (lam > etol) acc = acc + (tj * tj) / lam;
       }
     }
-    const double l = acc > 0.0 ? acc : 0.0;
-    lev[r0 + threadIdx.x] = l;
-    double v = l / (double)R;
-    if (!(v > 0.0)) v = 0.0;
-    if (v > 1.0) v = 1.0;
-    wi = (u64)(v * 0x1p52);
-    w[r0 + threadIdx.x] = wi;
+    if (live && c == 0) {
+      const double l = acc > 0.0 ? acc : 0.0;
+      lev[row] = l;
+      double q = l / (double)R;
+      if (!(q > 0.0)) q = 0.0;
+      if (q > 1.0) q = 1.0;
+      const u64 wi = (u64)(q * 0x1p52);
+      w[row] = wi;
+      wacc = wi;
+    }
   }
-  u64 tot;
-  (void)block_excl_scan<u64>(wi, &tot);
-  if (threadIdx.x == 0) blocksum[blockIdx.x] = tot;
+  wacc = wave_sum(wacc);
+  if ((tid & 63) == 0) wsum[wid] = wacc;
+  __syncthreads();
+  if (tid == 0) blocksum[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-// C = inclusive prefix of w, q = w / W.  Block b of LEV_ROWS rows.
-__global__ void __launch_bounds__(LEV_ROWS) k_lev_cdf(const u64 *__restrict__ w, i64 n,
-                                                     const u64 *__restrict__ blocksum, int nblk,
-                                                     u64 *__restrict__ C, double *__restrict__ q,
-                                                     int *flag_or) {
-  __shared__ u64 red[2][LEV_ROWS / 64];
+// C = inclusive prefix of w, q = w / W.  Blocks of CDF_ROWS rows; blocksum
+// holds the sums of w over consecutive groups of rb rows (rb divides
+// CDF_ROWS), nbs of them.
+#define CDF_ROWS 64
+__global__ void __launch_bounds__(CDF_ROWS) k_lev_cdf(const u64 *__restrict__ w, i64 n,
+                                                     const u64 *__restrict__ blocksum, int nbs,
+                                                     int rb, u64 *__restrict__ C,
+                                                     double *__restrict__ q, int *flag_or) {
+  const int lim = (int)(blockIdx.x * (CDF_ROWS / rb));
   u64 before = 0, all = 0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nbs; b += blockDim.x) {
     const u64 v = blocksum[b];
     all += v;
-    if (b < (int)blockIdx.x) before += v;
+    if (b < lim) before += v;
   }
   before = wave_sum(before);
   all = wave_sum(all);
-  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = before; red[1][threadIdx.x >> 6] = all; }
-  __syncthreads();
-  before = 0; all = 0;
-  for (int i = 0; i < LEV_ROWS / 64; ++i) { before += red[0][i]; all += red[1][i]; }
-  const i64 i = (i64)blockIdx.x * LEV_ROWS + threadIdx.x;
+  const i64 i = (i64)blockIdx.x * CDF_ROWS + threadIdx.x;
   const u64 wi = i < n ? w[i] : 0;
   u64 tot;
   const u64 ex = block_excl_scan<u64>(wi, &tot);
@@ -464,17 +437,20 @@ __global__ void __launch_bounds__(LEV_ROWS) k_lev_cdf(const u64 *__restrict__ w,
   if (i == 0 && all == 0 && flag_or) atomicOr(flag_or, CPAL_FLAG_STATE);
 }
 
+int lev_rows_per_block(int R) { return 256 / (R <= 16 ? 16 : (R <= 32 ? 32 : 64)); }
+
 void launch_lev_gram_partial(const double *A, i64 n, int R, double *part, const int *skip,
                              hipStream_t s) {
   const int nblk = (int)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
   const size_t sh = sizeof(double) * CPAL_GRAM_ROWS * R;
-  hipLaunchKernelGGL(k_lev_gram_partial, dim3(nblk), dim3(256), sh, s, A, n, R, part, skip);
+  hipLaunchKernelGGL(k_lev_gram_partial, dim3(nblk), dim3(GRAM_THREADS), sh, s, A, n, R, part,
+                     skip);
 }
 
 void launch_lev_rowspace(const double *A, int n, int R, double *lev, u64 *w, u64 *blocksum,
                          int *skip, int *pinv_store, hipStream_t s) {
-  hipLaunchKernelGGL(k_lev_rowspace, dim3(1), dim3(64), 0, s, A, n, R, lev, w, blocksum, skip,
-                     pinv_store);
+  hipLaunchKernelGGL(k_lev_rowspace, dim3(1), dim3(64), 0, s, A, n, R, lev, w, blocksum,
+                     lev_rows_per_block(R), skip, pinv_store);
 }
 
 void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_store,
@@ -494,26 +470,22 @@ void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_bl
 
 void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *lev, u64 *w,
                      u64 *blocksum, const int *skip, hipStream_t s) {
-  const int nblk = (int)((n + LEV_ROWS - 1) / LEV_ROWS);
-  const size_t sh = sizeof(double) * ((size_t)R * R + (size_t)LEV_ROWS * (R + 1));
-  if (R <= 16)
-    hipLaunchKernelGGL(k_lev_rows<16>, dim3(nblk), dim3(LEV_ROWS), sh, s, A, n, R, dc, lev, w,
-                       blocksum, skip);
-  else if (R <= 32)
-    hipLaunchKernelGGL(k_lev_rows<32>, dim3(nblk), dim3(LEV_ROWS), sh, s, A, n, R, dc, lev, w,
-                       blocksum, skip);
-  else
-    hipLaunchKernelGGL(k_lev_rows<0>, dim3(nblk), dim3(LEV_ROWS), sh, s, A, n, R, dc, lev, w,
-                       blocksum, skip);
+  const int rb = lev_rows_per_block(R);
+  const int nblk = (int)((n + rb - 1) / rb);
+  const size_t sh = sizeof(double) * (size_t)R * R;
+  auto k = R <= 16 ? k_lev_rows<16> : R <= 32 ? k_lev_rows<32> : k_lev_rows<64>;
+  hipLaunchKernelGGL(k, dim3(nblk), dim3(256), sh, s, A, n, R, dc, lev, w, blocksum, skip);
 }
 
-void launch_lev_cdf(const u64 *w, i64 n, const u64 *blocksum, u64 *C, double *q, int *flag_or,
-                    hipStream_t s) {
-  const int nblk = (int)((n + LEV_ROWS - 1) / LEV_ROWS);
-  hipLaunchKernelGGL(k_lev_cdf, dim3(nblk), dim3(LEV_ROWS), 0, s, w, n, blocksum, nblk, C, q,
+void launch_lev_cdf(const u64 *w, i64 n, int R, const u64 *blocksum, u64 *C, double *q,
+                    int *flag_or, hipStream_t s) {
+  const int rb = lev_rows_per_block(R);
+  const int nbs = (int)((n + rb - 1) / rb);
+  const int nblk = (int)((n + CDF_ROWS - 1) / CDF_ROWS);
+  hipLaunchKernelGGL(k_lev_cdf, dim3(nblk), dim3(CDF_ROWS), 0, s, w, n, blocksum, nbs, rb, C, q,
                      flag_or);
 }
 
-int lev_row_blocks(i64 n) { return (int)((n + LEV_ROWS - 1) / LEV_ROWS); }
+int lev_row_blocks(i64 n) { return (int)((n + 3) / 4); }   // blocksums at 4 rows per block
 
 }  // namespace cpal
