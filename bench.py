@@ -41,6 +41,22 @@ def gather_bytes(st, R, nk, elem=4):
     return pair * st["gathered_nnz"] + (12 + elem * R) * st["s_bar"] + elem * R * nk
 
 
+def recorded_traffic(root):
+    """HBM bytes per launch of the gather kernel from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE runs), or None when the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(root, "profiles", "gather_seg_uber4_traffic.txt")
+    try:
+        rec = json.loads(open(path).read().strip().splitlines()[-1])
+        src = open(os.path.join(root, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError, IndexError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -162,13 +178,13 @@ def main():
         "gathered_nnz_per_s": nnz_g / elapsed,
         "stage_ms_per_update": {k: v[0] / max(v[1], 1) for k, v in stage_all.items()},
         "roofline": {
-            "kernel": "k_gather (fiber gather + sampled MTTKRP)",
+            "kernel": "k_gather_seg (fiber gather + sampled MTTKRP)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": recorded_traffic(ROOT),
             "algorithmic_bytes_per_launch": gbytes / updates,
             "avg_launch_us": 1e3 * g_ms / max(g_cnt, 1),
         },

@@ -16,11 +16,6 @@
 namespace cpal {
 void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_blk, int R,
                        Decomp *out, int *flag_or, double *gram_tmp, hipStream_t s);
-int gather_tile_rows(i64 nk, int R, bool f64);
-void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
-                         const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
-                         const int *ik, const double *v64, const void *zhat, int ldz, void *P,
-                         i64 nk, int G, hipStream_t s);
 void launch_gather_prep(const DevState *st, DevState *stw, const unsigned *flen,
                         const unsigned *foff, i64 cap, u64 *part_len, unsigned *part_cnt,
                         u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
@@ -28,18 +23,10 @@ void launch_gather_prep(const DevState *st, DevState *stw, const unsigned *flen,
 int gather_prep_blocks(i64 cap);
 int gather_row_width(int R);
 i64 gather_chunks_cap(i64 nnz);
-void launch_gather_sorted(bool f64, const DevState *st, int R, const u64 *cpos,
-                          const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
-                          const uint2 *pairs, const int *ik, const double *v64, i64 nk,
-                          int *g_ik, void *g_x, unsigned *g_z, unsigned *cnt, unsigned *rowptr,
-                          unsigned *cursor, unsigned *csr_r, void *csr_x, unsigned *csr_z,
-                          const void *zhat, int ldz, void *M, int grid, hipStream_t s);
 void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                        const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz, void *M,
                        int grid, hipStream_t s);
-void launch_reduce_partials(bool f64, const DevState *st, int R, const void *P, void *M, i64 nk,
-                            int G, hipStream_t s);
 int lev_row_blocks(i64 n);
 void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
                   void *scratch, hipStream_t s);
@@ -176,15 +163,8 @@ struct cpal_ctx {
   int draw_more_grid = 256; // top-up draw pass
   int compact_grid = 256;
   int gather_grid = 2048;
-  int tile_grid = 256;          // workgroups per row tile of the shared-memory gather
   int ldz = 0;                  // row stride of the weighted KRP rows (16-byte multiple)
-  void *Ppart = nullptr;        // their partial accumulators
-  // row-sorted gather: stream-order and row-order copies of the gathered nonzeros
-  int *g_ik = nullptr;
-  void *g_x = nullptr, *csr_x = nullptr;
-  unsigned *g_z = nullptr, *gs_cnt = nullptr, *gs_rowptr = nullptr, *gs_cursor = nullptr;
-  unsigned *csr_r = nullptr, *csr_z = nullptr;
-  int gs_grid = 512;
+  int gs_grid = 512;            // workgroups of the segmented gather
   unsigned *chunk_first = nullptr;  // first nonempty fiber of each gather chunk
   u64 *cpos = nullptr;              // nonempty fibers: stream position,
   unsigned *coff = nullptr;         //   offset in the mode-sorted nonzeros,
@@ -445,18 +425,7 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->fpos = c->alloc<u64>(s + 1);
     c->gpart = c->alloc<double>((size_t)rows_blocks(s) * np);
     c->M = c->alloc<char>((size_t)maxn * R * tsz);
-    c->Ppart = c->alloc<char>((size_t)c->tile_grid * maxn * R * tsz);
     c->gram_tmp = c->alloc<double>(np);
-    c->g_ik = c->alloc<int>(c->nnz);
-    c->g_x = c->alloc<char>((size_t)c->nnz * tsz);
-    c->g_z = c->alloc<unsigned>(c->nnz);
-    c->csr_r = c->alloc<unsigned>(c->nnz);
-    c->csr_x = c->alloc<char>((size_t)c->nnz * tsz);
-    c->csr_z = c->alloc<unsigned>(c->nnz);
-    c->gs_cnt = c->alloc<unsigned>(maxn);
-    c->gs_rowptr = c->alloc<unsigned>(maxn + 1);
-    c->gs_cursor = c->alloc<unsigned>(maxn);
-    hipMemsetAsync(c->gs_cnt, 0, sizeof(unsigned) * (size_t)maxn, c->stream);
     c->chunk_first = c->alloc<unsigned>(gather_chunks_cap(c->nnz));
     c->cpos = c->alloc<u64>(s);
     c->coff = c->alloc<unsigned>(s);

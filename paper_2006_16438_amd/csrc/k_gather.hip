@@ -333,15 +333,11 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
   }
 }
 
-// Gather with per-workgroup accumulation in shared memory.  The stream of
-// gathered nonzeros is cut into chunks of GT_CHUNK positions; workgroup g of
-// row tile y takes chunks g, g+G, ...  For a chunk the workgroup reads the
-// first and last nonempty fibers from chunk_first, stages their stream
-// positions in shared memory and every position finds its fiber there.
-// Contributions x * omega_j z_j with i_k inside the tile go to a shared
-// accumulator (tile_rows x R) with shared-memory atomics; at the end the
-// workgroup writes its partial M tile to P[g] (no global atomics).  The
-// partials are summed by k_reduce_partials.
+// The stream of gathered nonzeros (the sampled fibers one after the other)
+// is cut into chunks of GT_CHUNK positions; the chunk's first and last
+// nonempty fibers come from chunk_first, their stream positions are staged in
+// shared memory (GT_WIN >= GT_CHUNK + 1 entries) and every position finds its
+// fiber there.
 #define GT_THREADS 512
 #define GT_PER_THREAD 4
 #define GT_CHUNK (GT_THREADS * GT_PER_THREAD)
@@ -445,300 +441,6 @@ __global__ void __launch_bounds__(256) k_chunk_first(const DevState *st, const u
   }
 }
 
-
-// Shared-memory tiled gather: workgroup g takes the chunks g, g + G, ... of
-// GT_CHUNK stream positions and adds into its tile of rows [r0, r0 + rows)
-// of its own partial M.
-//  * per thread, GT_PER_THREAD positions: the nonempty fiber holding the
-//    position (binary search in the chunk's window of fiber starts), then
-//    the nonzero (i_k, x) and the fiber's sampled row; every load is
-//    unconditional (positions past the chunk are clamped to its last one and
-//    masked), so all of them are in flight together;
-//  * then lanes = columns: groups of LPN lanes (LPN = padded row width ldz)
-//    take the wave's nonzeros in turn, lane c adding x * zhat(row, c) into
-//    the tile's row i_k, so the lanes of one shared-memory atomic hit
-//    distinct columns; GT_BATCH nonzeros per group are loaded before they are
-//    added.
-#define GT_BATCH 8
-template <typename T, int LPN>
-__global__ void __launch_bounds__(GT_THREADS) k_gather_tile(
-    const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
-    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    const T *__restrict__ zhat, int ldz, T *__restrict__ P, i64 nk, int tile_rows) {
-  constexpr int NPW = 64 / LPN;                         // nonzeros per wave instruction
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  u64 *win = (u64 *)smem_raw;                          // GT_WIN fiber start positions
-  T *acc = (T *)(smem_raw + sizeof(u64) * GT_WIN);      // tile_rows x R
-  const i64 total = st->gathered;
-  const i64 nf = st->n_fib;
-  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
-  const int g = blockIdx.x, G = gridDim.x;
-  if (g >= nch) return;
-  const i64 r0 = (i64)blockIdx.y * tile_rows;
-  const int rows = (int)min((i64)tile_rows, nk - r0);
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int c = lane % LPN, sub = lane / LPN;
-  for (int e = tid; e < rows * R; e += GT_THREADS) acc[e] = T(0);
-  for (i64 ch = g; ch < nch; ch += G) {
-    const i64 base = ch * GT_CHUNK;
-    const i64 last = min(total, base + GT_CHUNK) - 1;
-    const i64 jlo = chunk_first[ch];
-    const i64 jhi = (ch + 1 < nch) ? (i64)chunk_first[ch + 1] : nf - 1;
-    const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
-    __syncthreads();   // previous chunk's readers of win are done
-    for (int e = tid; e < nwin; e += GT_THREADS) win[e] = cpos[jlo + e];
-    __syncthreads();
-    int jw[GT_PER_THREAD];
-    u64 ee[GT_PER_THREAD];
-    bool vv[GT_PER_THREAD];
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      const i64 pu = base + (i64)u * GT_THREADS + tid;
-      vv[u] = pu <= last;
-      const u64 p = (u64)min(pu, last);
-      int lo = 0, hi = nwin;   // last index with win[idx] <= p
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (win[mid] <= p) lo = mid; else hi = mid;
-      }
-      jw[u] = lo;
-      ee[u] = p - win[lo];
-    }
-    unsigned zrow[GT_PER_THREAD];
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      ee[u] += coff[jlo + jw[u]];
-      zrow[u] = cidx[jlo + jw[u]];
-    }
-    int ik[GT_PER_THREAD];
-    T xx[GT_PER_THREAD];
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      nz.get(ee[u], ik[u], xx[u]);
-      ik[u] = (vv[u] && ik[u] >= r0 && ik[u] < r0 + rows) ? (int)(ik[u] - r0) : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      for (int i0 = 0; i0 < 64; i0 += NPW * GT_BATCH) {
-        int kk[GT_BATCH];
-        T xv[GT_BATCH], zv[GT_BATCH];
-        unsigned zr[GT_BATCH];
-#pragma unroll
-        for (int q = 0; q < GT_BATCH; ++q) {
-          const int src = i0 + q * NPW + sub;
-          kk[q] = __shfl(ik[u], src, 64);
-          xv[q] = __shfl(xx[u], src, 64);
-          zr[q] = __shfl(zrow[u], src, 64);
-        }
-#pragma unroll
-        for (int q = 0; q < GT_BATCH; ++q) zv[q] = zhat[(i64)zr[q] * ldz + c];
-#pragma unroll
-        for (int q = 0; q < GT_BATCH; ++q)
-          if (kk[q] >= 0 && c < R) unsafeAtomicAdd(&acc[kk[q] * R + c], xv[q] * zv[q]);
-      }
-    }
-  }
-  __syncthreads();
-  T *out = P + (i64)g * nk * R + r0 * R;
-  for (int e = tid; e < rows * R; e += GT_THREADS) out[e] = acc[e];
-}
-
-// Row-sorted gather: the gathered nonzeros are regrouped by output row i_k
-// (a counting sort), after which every lane group owns a run of one row and
-// accumulates it in registers; no shared-memory float atomics.
-//  1. k_gs_stream: per stream position (as in the tiled gather) the nonzero
-//     (i_k, x) and its KRP row index, written in stream order, and the row
-//     counts (shared-memory histogram flushed once per workgroup when
-//     nk <= GS_LBINS, else global counters);
-//  2. k_gs_scan: row pointers = exclusive scan of the counts (counts reset);
-//  3. k_gs_scatter: each nonzero to its row's range (rank inside the
-//     workgroup from a shared-memory histogram, one global ticket per row
-//     and workgroup);
-//  4. k_gs_rows: lane groups of LPN lanes take LPN consecutive entries,
-//     lane c summing x * zhat(row, c) while the row stays the same and
-//     adding the sum into M(i_k, c) when it changes or the run ends.
-#define GS_LBINS 8192
-template <typename T>
-__global__ void __launch_bounds__(GT_THREADS) k_gs_stream(
-    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
-    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    i64 nk, int *__restrict__ g_ik, T *__restrict__ g_x, unsigned *__restrict__ g_z,
-    unsigned *__restrict__ cnt) {
-  __shared__ u64 win[GT_WIN];
-  __shared__ unsigned lh[GS_LBINS];
-  const i64 total = st->gathered;
-  const i64 nf = st->n_fib;
-  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
-  const int g = blockIdx.x, G = gridDim.x;
-  if (g >= nch) return;
-  const int tid = threadIdx.x;
-  const bool local = nk <= GS_LBINS;
-  if (local)
-    for (int b = tid; b < nk; b += GT_THREADS) lh[b] = 0u;
-  for (i64 ch = g; ch < nch; ch += G) {
-    const i64 base = ch * GT_CHUNK;
-    const i64 last = min(total, base + GT_CHUNK) - 1;
-    const i64 jlo = chunk_first[ch];
-    const i64 jhi = (ch + 1 < nch) ? (i64)chunk_first[ch + 1] : nf - 1;
-    const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
-    __syncthreads();   // previous chunk's readers of win are done (and lh is cleared)
-    for (int e = tid; e < nwin; e += GT_THREADS) win[e] = cpos[jlo + e];
-    __syncthreads();
-    int jw[GT_PER_THREAD];
-    u64 ee[GT_PER_THREAD];
-    bool vv[GT_PER_THREAD];
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      const i64 pu = base + (i64)u * GT_THREADS + tid;
-      vv[u] = pu <= last;
-      const u64 p = (u64)min(pu, last);
-      int lo = 0, hi = nwin;   // last index with win[idx] <= p
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (win[mid] <= p) lo = mid; else hi = mid;
-      }
-      jw[u] = lo;
-      ee[u] = p - win[lo];
-    }
-    unsigned zrow[GT_PER_THREAD];
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      ee[u] += coff[jlo + jw[u]];
-      zrow[u] = cidx[jlo + jw[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      int ik;
-      T x;
-      nz.get(ee[u], ik, x);
-      if (vv[u]) {
-        const i64 p = base + (i64)u * GT_THREADS + tid;
-        g_ik[p] = ik;
-        g_x[p] = x;
-        g_z[p] = zrow[u];
-        if (local) atomicAdd(&lh[ik], 1u);
-        else atomicAdd(&cnt[ik], 1u);
-      }
-    }
-  }
-  if (local) {
-    __syncthreads();
-    for (int b = tid; b < nk; b += GT_THREADS)
-      if (lh[b]) atomicAdd(&cnt[b], lh[b]);
-  }
-}
-
-__global__ void __launch_bounds__(1024) k_gs_scan(unsigned *__restrict__ cnt, i64 nk,
-                                                  unsigned *__restrict__ rowptr,
-                                                  unsigned *__restrict__ cursor) {
-  unsigned carry = 0;
-  for (i64 b0 = 0; b0 < nk; b0 += 1024) {
-    const i64 b = b0 + threadIdx.x;
-    const unsigned v = b < nk ? cnt[b] : 0u;
-    unsigned tot;
-    const unsigned ex = block_excl_scan<unsigned>(v, &tot);
-    if (b < nk) {
-      rowptr[b] = carry + ex;
-      cursor[b] = carry + ex;
-      cnt[b] = 0u;
-    }
-    carry += tot;
-  }
-  if (threadIdx.x == 0) rowptr[nk] = carry;
-}
-
-// Scatter: workgroup b takes the contiguous range [b*per, (b+1)*per) of the
-// stream; pass 1 counts its rows in shared memory, one global ticket per row
-// and workgroup reserves each row's range (nk <= GS_LBINS), pass 2 hands out
-// positions inside the ranges.  Larger nk take one global ticket per nonzero.
-#define GS_SC_THREADS 1024
-template <typename T>
-__global__ void __launch_bounds__(GS_SC_THREADS) k_gs_scatter(
-    const DevState *st, const int *__restrict__ g_ik, const T *__restrict__ g_x,
-    const unsigned *__restrict__ g_z, i64 nk, unsigned *__restrict__ cursor,
-    unsigned *__restrict__ csr_r, T *__restrict__ csr_x, unsigned *__restrict__ csr_z) {
-  __shared__ unsigned lh[GS_LBINS];
-  const i64 total = st->gathered;
-  const i64 per = (total + gridDim.x - 1) / gridDim.x;
-  const i64 p0 = (i64)blockIdx.x * per, p1 = min(total, p0 + per);
-  if (p0 >= p1) return;   // uniform per block
-  const int tid = threadIdx.x;
-  if (nk <= GS_LBINS) {
-    for (int b = tid; b < nk; b += GS_SC_THREADS) lh[b] = 0u;
-    __syncthreads();
-#pragma unroll 4
-    for (i64 p = p0 + tid; p < p1; p += GS_SC_THREADS) atomicAdd(&lh[g_ik[p]], 1u);
-    __syncthreads();
-    for (int b = tid; b < nk; b += GS_SC_THREADS)
-      if (lh[b]) lh[b] = atomicAdd(&cursor[b], lh[b]);
-    __syncthreads();
-#pragma unroll 4
-    for (i64 p = p0 + tid; p < p1; p += GS_SC_THREADS) {
-      const int ik = g_ik[p];
-      const unsigned pos = atomicAdd(&lh[ik], 1u);
-      csr_r[pos] = (unsigned)ik;
-      csr_x[pos] = g_x[p];
-      csr_z[pos] = g_z[p];
-    }
-  } else {
-#pragma unroll 4
-    for (i64 p = p0 + tid; p < p1; p += GS_SC_THREADS) {
-      const int ik = g_ik[p];
-      const unsigned pos = atomicAdd(&cursor[ik], 1u);
-      csr_r[pos] = (unsigned)ik;
-      csr_x[pos] = g_x[p];
-      csr_z[pos] = g_z[p];
-    }
-  }
-}
-
-// Rows: a group of LPN lanes takes LPN consecutive row-sorted entries, lane
-// c loading entry c's (row, x, KRP row) and then, for every entry of the
-// group in order, x * zhat(row, c) (all LPN loads in flight); the running sum
-// goes to M(row, c) when the row changes and at the end.
-template <typename T, int LPN>
-__global__ void __launch_bounds__(256) k_gs_rows(const DevState *st, int R,
-                                                 const unsigned *__restrict__ csr_r,
-                                                 const T *__restrict__ csr_x,
-                                                 const unsigned *__restrict__ csr_z,
-                                                 const T *__restrict__ zhat, int ldz,
-                                                 T *__restrict__ M) {
-  const i64 total = st->gathered;
-  const int lane = threadIdx.x & 63;
-  const int c = lane % LPN, gb = lane - c;   // first lane of the group
-  const i64 grp = ((i64)blockIdx.x * blockDim.x + threadIdx.x) / LPN;
-  const i64 ngrp = ((i64)gridDim.x * blockDim.x) / LPN;
-  const bool col = c < R;
-  for (i64 s0 = grp * LPN; s0 < total; s0 += ngrp * LPN) {
-    const int cnt = (int)min((i64)LPN, total - s0);
-    const i64 e = s0 + min(c, cnt - 1);
-    const unsigned my_r = csr_r[e];
-    const T my_x = csr_x[e];
-    const unsigned my_z = csr_z[e];
-    T zv[LPN];
-#pragma unroll
-    for (int q = 0; q < LPN; ++q) {
-      const unsigned zz = __shfl(my_z, gb + q, 64);
-      zv[q] = zhat[(i64)zz * ldz + c];
-    }
-    unsigned cur = __shfl(my_r, gb, 64);
-    T acc = T(0);
-#pragma unroll
-    for (int q = 0; q < LPN; ++q) {
-      const unsigned rr = __shfl(my_r, gb + q, 64);
-      const T xv = __shfl(my_x, gb + q, 64);
-      if (q < cnt) {
-        if (rr != cur) {
-          if (col) unsafeAtomicAdd(&M[(i64)cur * R + c], acc);
-          cur = rr;
-          acc = T(0);
-        }
-        acc += xv * zv[q];
-      }
-    }
-    if (col) unsafeAtomicAdd(&M[(i64)cur * R + c], acc);
-  }
-}
 
 // Segmented gather: workgroup g takes the chunks g, g + G, ... of GT_CHUNK
 // stream positions; for a chunk
@@ -940,27 +642,6 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
   }
 }
 
-// M = sum over the workgroups that had work of their partials.
-template <typename T>
-__global__ void __launch_bounds__(256) k_reduce_partials(const DevState *st, const T *__restrict__ P,
-                                                         i64 nkR, int G, T *__restrict__ M) {
-  const i64 total = st->gathered;
-  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
-  const int nwg = (int)min((i64)G, nch);
-  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < nkR; e += (i64)gridDim.x * blockDim.x) {
-    T a[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = T(0);
-    int g = 0;
-    for (; g + 8 <= nwg; g += 8) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) a[k] += P[(i64)(g + k) * nkR + e];
-    }
-    for (; g < nwg; ++g) a[0] += P[(i64)g * nkR + e];
-    M[e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  }
-}
-
 // ------------------------------------------------------------------- solve --
 // A_k(i,:) = M(i,:) G_s^{-1}: forward substitution with the Cholesky factor
 // (subtractions in ascending order), back substitution (right-looking:
@@ -1154,15 +835,6 @@ void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u
 int rows_blocks(i64 cap) { return (int)((cap + ROWS_BLK - 1) / ROWS_BLK); }
 int rows_per_block() { return ROWS_BLK; }
 
-// Shared-memory plan of the tiled gather: rows per tile and tile count.
-#define GT_LDS_BUDGET (120 * 1024)
-int gather_tile_rows(i64 nk, int R, bool f64) {
-  const size_t elem = f64 ? sizeof(double) : sizeof(float);
-  const size_t avail = GT_LDS_BUDGET - sizeof(u64) * GT_WIN;
-  i64 rows = (i64)(avail / (elem * (size_t)R));
-  return (int)std::min<i64>(rows, nk);
-}
-
 void launch_gather_prep(const DevState *st, DevState *stw, const unsigned *flen,
                         const unsigned *foff, i64 cap, u64 *part_len, unsigned *part_cnt,
                         u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
@@ -1182,43 +854,6 @@ i64 gather_chunks_cap(i64 nnz) { return nnz / GT_CHUNK + 2; }
 
 int gather_row_width(int R) { return R <= 16 ? 16 : (R <= 32 ? 32 : 64); }
 
-void launch_gather_tiled(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
-                         const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
-                         const int *ik, const double *v64, const void *zhat, int ldz, void *P,
-                         i64 nk, int G, hipStream_t s) {
-  const int tr = gather_tile_rows(nk, R, f64);
-  const int ntiles = (int)((nk + tr - 1) / tr);
-  const size_t elem = f64 ? sizeof(double) : sizeof(float);
-  const size_t sh = sizeof(u64) * GT_WIN + elem * (size_t)tr * R;
-  const dim3 grid(G, ntiles), blk(GT_THREADS);
-  const int rm = gather_row_width(R);
-  if (f64) {
-    NzLoad<double> nz{ik, v64};
-    auto k = rm == 16 ? k_gather_tile<double, 16> : rm == 32 ? k_gather_tile<double, 32>
-                                                             : k_gather_tile<double, 64>;
-    hipLaunchKernelGGL(k, grid, blk, sh, s, st, R, cpos, coff, cidx, chunk_first, nz,
-                       (const double *)zhat, ldz, (double *)P, nk, tr);
-  } else {
-    NzLoad<float> nz{pairs};
-    auto k = rm == 16 ? k_gather_tile<float, 16> : rm == 32 ? k_gather_tile<float, 32>
-                                                            : k_gather_tile<float, 64>;
-    hipLaunchKernelGGL(k, grid, blk, sh, s, st, R, cpos, coff, cidx, chunk_first, nz,
-                       (const float *)zhat, ldz, (float *)P, nk, tr);
-  }
-}
-
-void launch_reduce_partials(bool f64, const DevState *st, int R, const void *P, void *M, i64 nk,
-                            int G, hipStream_t s) {
-  const i64 nkR = nk * R;
-  const int rg = grid_for(nkR, 256, 4096);
-  if (f64)
-    hipLaunchKernelGGL(k_reduce_partials<double>, dim3(rg), dim3(256), 0, s, st,
-                       (const double *)P, nkR, G, (double *)M);
-  else
-    hipLaunchKernelGGL(k_reduce_partials<float>, dim3(rg), dim3(256), 0, s, st, (const float *)P,
-                       nkR, G, (float *)M);
-}
-
 void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                    const unsigned *cidx, const uint2 *pairs, const int *ik, const double *v64,
                    const void *zhat, void *M, int ldz, int grid, hipStream_t s) {
@@ -1230,40 +865,6 @@ void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const u
     NzLoad<float> nz{pairs};
     hipLaunchKernelGGL(k_gather<float>, dim3(grid), dim3(256), 0, s, st, R, cpos, coff, cidx, nz,
                        (const float *)zhat, (float *)M, ldz);
-  }
-}
-
-void launch_gather_sorted(bool f64, const DevState *st, int R, const u64 *cpos,
-                          const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
-                          const uint2 *pairs, const int *ik, const double *v64, i64 nk,
-                          int *g_ik, void *g_x, unsigned *g_z, unsigned *cnt, unsigned *rowptr,
-                          unsigned *cursor, unsigned *csr_r, void *csr_x, unsigned *csr_z,
-                          const void *zhat, int ldz, void *M, int grid, hipStream_t s) {
-  const int rm = gather_row_width(R);
-  if (f64) {
-    NzLoad<double> nz{ik, v64};
-    hipLaunchKernelGGL(k_gs_stream<double>, dim3(grid), dim3(GT_THREADS), 0, s, st, cpos, coff,
-                       cidx, chunk_first, nz, nk, g_ik, (double *)g_x, g_z, cnt);
-  } else {
-    NzLoad<float> nz{pairs};
-    hipLaunchKernelGGL(k_gs_stream<float>, dim3(grid), dim3(GT_THREADS), 0, s, st, cpos, coff,
-                       cidx, chunk_first, nz, nk, g_ik, (float *)g_x, g_z, cnt);
-  }
-  hipLaunchKernelGGL(k_gs_scan, dim3(1), dim3(1024), 0, s, cnt, nk, rowptr, cursor);
-  if (f64) {
-    hipLaunchKernelGGL(k_gs_scatter<double>, dim3(64), dim3(GS_SC_THREADS), 0, s, st, g_ik,
-                       (const double *)g_x, g_z, nk, cursor, csr_r, (double *)csr_x, csr_z);
-    auto k = rm == 16 ? k_gs_rows<double, 16> : rm == 32 ? k_gs_rows<double, 32>
-                                                         : k_gs_rows<double, 64>;
-    hipLaunchKernelGGL(k, dim3(8 * grid), dim3(256), 0, s, st, R, csr_r, (const double *)csr_x,
-                       csr_z, (const double *)zhat, ldz, (double *)M);
-  } else {
-    hipLaunchKernelGGL(k_gs_scatter<float>, dim3(64), dim3(GS_SC_THREADS), 0, s, st, g_ik,
-                       (const float *)g_x, g_z, nk, cursor, csr_r, (float *)csr_x, csr_z);
-    auto k = rm == 16 ? k_gs_rows<float, 16> : rm == 32 ? k_gs_rows<float, 32>
-                                                        : k_gs_rows<float, 64>;
-    hipLaunchKernelGGL(k, dim3(8 * grid), dim3(256), 0, s, st, R, csr_r, (const float *)csr_x,
-                       csr_z, (const float *)zhat, ldz, (float *)M);
   }
 }
 

@@ -200,8 +200,8 @@ def test_fit_estimate_matches_oracle(which):
 
 @pytest.mark.parametrize("gather", ["f64", "f32"])
 def test_large_mode_gather_paths(gather):
-    """Mode 0 with 5000 rows needs more than four shared-memory row tiles, so
-    its gather takes the global-atomic path; modes 1-2 use one tile."""
+    """A 5000-row mode: the chunk-local sort by output row takes two 6-bit
+    radix passes (13-bit row indices), the short modes one."""
     dims = (5000, 60, 50)
     T = synth.random_sparse(dims, 300_000, seed=31)
     R = 16
@@ -209,3 +209,16 @@ def test_large_mode_gather_paths(gather):
     log(f"large mode gather paths ({gather})")
     run_parity(T, fac, R, 4096, 1 / 4096, 6, gather, 1e-10 if gather == "f64" else 1e-4,
                label=f"large-{gather}")
+
+
+@pytest.mark.parametrize("gather", ["f64", "f32"])
+def test_tall_mode_atomic_gather(gather):
+    """A mode with more than 2^20 rows has row indices too wide for the
+    chunk-local sort keys; its gather adds straight into M (global atomics)."""
+    dims = ((1 << 20) + 4099, 7, 5)
+    T = synth.random_sparse(dims, 120_000, seed=41)
+    R = 8
+    fac = concentrated(dims, R, 43)
+    log(f"tall mode atomic gather ({gather})")
+    run_parity(T, fac, R, 2048, 1 / 2048, 3, gather, 1e-10 if gather == "f64" else 1e-4,
+               label=f"tall-{gather}")
