@@ -16,11 +16,9 @@
 namespace cpal {
 void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_blk, int R,
                        Decomp *out, int *flag_or, double *gram_tmp, hipStream_t s);
-void launch_gather_prep(const DevState *st, DevState *stw, const unsigned *flen,
-                        const unsigned *foff, i64 cap, u64 *part_len, unsigned *part_cnt,
-                        u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
-                        hipStream_t s);
-int gather_prep_blocks(i64 cap);
+void launch_gather_prep(DevState *st, const unsigned *flen, const unsigned *foff, i64 cap,
+                        const u64 *part_len, const unsigned *part_cnt, u64 *cpos, unsigned *coff,
+                        unsigned *cidx, unsigned *chunk_first, hipStream_t s);
 int gather_row_width(int R);
 i64 gather_chunks_cap(i64 nnz);
 void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
@@ -50,7 +48,8 @@ void launch_samples_out(const DevState *st, const u64 *samp_idx, const double *s
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
                  double *samp_om, double *samp_w, const u64 *skeys,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
-                 unsigned *flen, double *gpart, void *M, i64 mlen, int ldz, hipStream_t s);
+                 unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt, void *M,
+                 i64 mlen, int ldz, hipStream_t s);
 int rows_blocks(i64 cap);
 int rows_per_block();
 void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
@@ -430,8 +429,8 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->cpos = c->alloc<u64>(s);
     c->coff = c->alloc<unsigned>(s);
     c->cidx = c->alloc<unsigned>(s);
-    c->gp_len = c->alloc<u64>(gather_prep_blocks(s) + 1);
-    c->gp_cnt = c->alloc<unsigned>(gather_prep_blocks(s) + 1);
+    c->gp_len = c->alloc<u64>(rows_blocks(s) + 1);
+    c->gp_cnt = c->alloc<unsigned>(rows_blocks(s) + 1);
     const i64 sort_cap = std::max<i64>((i64)c->det_cap, c->nnz);
     c->sort_scratch = c->alloc<char>(sort_scratch_bytes(sort_cap, true));
     c->scan_scratch = c->alloc<char>(scan_scratch_bytes(std::max<i64>(sort_cap, s)));
@@ -577,9 +576,9 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   tb = c->stage_begin(CPAL_STAGE_ROWS);
   // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
   launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, sorted, md.slots,
-              md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->M, md.n * R,
-              c->ldz, s);
-  launch_gather_prep(c->st, c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->cpos, c->coff,
+              md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->gp_len, c->gp_cnt,
+              c->M, md.n * R, c->ldz, s);
+  launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->cpos, c->coff,
                      c->cidx, c->chunk_first, s);
   c->stage_end(CPAL_STAGE_ROWS, tb);
   tb = c->stage_begin(CPAL_STAGE_GATHER);

@@ -92,7 +92,8 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     double *__restrict__ samp_w, const u64 *__restrict__ skeys,
     const FiberSlot *__restrict__ slots, u64 hmask, int hshift, T *__restrict__ zhat,
     unsigned *__restrict__ foff, unsigned *__restrict__ flen, double *__restrict__ gpart,
-    T *__restrict__ M, i64 mlen, int ldz) {
+    u64 *__restrict__ part_len, unsigned *__restrict__ part_cnt, T *__restrict__ M, i64 mlen,
+    int ldz) {
   extern __shared__ double sz[];           // ROWS_BLK x (R+1); phase 3 reuses it
   __shared__ double som[ROWS_BLK];
   __shared__ unsigned sim[CPAL_MAXORDER][ROWS_BLK];
@@ -177,15 +178,22 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     foff[j] = off;
     flen[j] = len;
   }
-  {   // rows of the sampled system (s_bar): one atomic add per workgroup
+  {   // rows of the sampled system (s_bar, one atomic add per workgroup) and the
+      // workgroup's gathered length and nonempty-fiber count for the gather
     const unsigned na = (unsigned)__popcll(__ballot(active));
-    __shared__ unsigned wact[ROWS_BLK / 64];
-    if ((tid & 63) == 0) wact[tid >> 6] = na;
+    const u64 ln = wave_sum((u64)(tid < rows ? flen[base + tid] : 0u));
+    const unsigned nf = (unsigned)__popcll(__ballot(tid < rows && flen[base + tid] > 0u));
+    __shared__ unsigned wact[ROWS_BLK / 64], wnf[ROWS_BLK / 64];
+    __shared__ u64 wln[ROWS_BLK / 64];
+    if ((tid & 63) == 0) { wact[tid >> 6] = na; wnf[tid >> 6] = nf; wln[tid >> 6] = ln; }
     __syncthreads();
     if (tid == 0) {
-      unsigned t = 0;
-      for (int q = 0; q < ROWS_BLK / 64; ++q) t += wact[q];
+      unsigned t = 0, f = 0;
+      u64 l = 0;
+      for (int q = 0; q < ROWS_BLK / 64; ++q) { t += wact[q]; f += wnf[q]; l += wln[q]; }
       atomicAdd((unsigned long long *)&st->s_bar, (unsigned long long)t);
+      part_len[blockIdx.x] = l;
+      part_cnt[blockIdx.x] = f;
     }
   }
   som[tid] = omj;
@@ -343,104 +351,66 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
 #define GT_CHUNK (GT_THREADS * GT_PER_THREAD)
 #define GT_WIN 4096
 
-// Gather preparation: one scan over the sampled rows computes the stream
-// position of every fiber (exclusive prefix of the lengths) and compacts the
-// nonempty fibers: for the c-th nonempty fiber, cpos = first stream position,
-// coff = offset in the mode-sorted nonzeros, cidx = its sampled row (for the
-// weighted KRP row).  Empty fibers add nothing to M (they still enter G_s),
-// and with only nonempty fibers a chunk of GT_CHUNK positions spans at most
-// GT_CHUNK + 1 of them.
-#define GP_TILE 1024
-__global__ void __launch_bounds__(256) k_gp_part(const DevState *st, const unsigned *__restrict__ flen,
-                                                 u64 *__restrict__ part_len,
-                                                 unsigned *__restrict__ part_cnt) {
-  const i64 n = st->n_slots;
-  const i64 base = (i64)blockIdx.x * GP_TILE;
-  u64 sl = 0;
-  unsigned sc = 0;
-  for (int r = 0; r < GP_TILE / 256; ++r) {
-    const i64 i = base + r * 256 + threadIdx.x;
-    if (i < n) {
-      const unsigned l = flen[i];
-      sl += l;
-      sc += l > 0 ? 1u : 0u;
-    }
-  }
-  sl = wave_sum(sl);
-  sc = wave_sum(sc);
-  __shared__ u64 wl[4];
-  __shared__ unsigned wc[4];
-  if ((threadIdx.x & 63) == 0) { wl[threadIdx.x >> 6] = sl; wc[threadIdx.x >> 6] = sc; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    part_len[blockIdx.x] = wl[0] + wl[1] + wl[2] + wl[3];
-    part_cnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
-  }
-}
-
-__global__ void __launch_bounds__(1024) k_gp_top(DevState *st, u64 *__restrict__ part_len,
-                                                 unsigned *__restrict__ part_cnt) {
-  const i64 n = st->n_slots;
-  const int nb = (int)((n + GP_TILE - 1) / GP_TILE);
-  u64 carry_l = 0, carry_c = 0;
-  for (int b0 = 0; b0 < nb; b0 += 1024) {
-    const int b = b0 + threadIdx.x;
-    const u64 vl = b < nb ? part_len[b] : 0;
-    const u64 vc = b < nb ? part_cnt[b] : 0;
-    u64 tl, tc;
-    const u64 el = block_excl_scan<u64>(vl, &tl);
-    const u64 ec = block_excl_scan<u64>(vc, &tc);
-    if (b < nb) { part_len[b] = carry_l + el; part_cnt[b] = (unsigned)(carry_c + ec); }
-    carry_l += tl;
-    carry_c += tc;
-  }
-  if (threadIdx.x == 0) {
-    st->gathered = (i64)carry_l;
-    st->n_fib = (i64)carry_c;
-  }
-}
-
-__global__ void __launch_bounds__(256) k_gp_apply(const DevState *st, const unsigned *__restrict__ flen,
-                                                  const unsigned *__restrict__ foff,
-                                                  const u64 *__restrict__ part_len,
-                                                  const unsigned *__restrict__ part_cnt,
-                                                  u64 *__restrict__ cpos, unsigned *__restrict__ coff,
-                                                  unsigned *__restrict__ cidx) {
-  const i64 n = st->n_slots;
-  const i64 base = (i64)blockIdx.x * GP_TILE;
-  if (base >= n) return;
-  u64 cl = part_len[blockIdx.x];
-  u64 cc = part_cnt[blockIdx.x];
-  for (int r = 0; r < GP_TILE / 256; ++r) {
-    const i64 i = base + r * 256 + threadIdx.x;
-    const unsigned l = i < n ? flen[i] : 0u;
-    u64 tl, tc;
-    const u64 el = block_excl_scan<u64>((u64)l, &tl);
-    const u64 ec = block_excl_scan<u64>((u64)(l > 0), &tc);
-    if (l > 0) {
-      const u64 c = cc + ec;
-      cpos[c] = cl + el;
-      coff[c] = foff[i];
-      cidx[c] = (unsigned)i;
-    }
-    cl += tl;
-    cc += tc;
-  }
-}
-
+// Gather preparation: the stream position of every fiber (exclusive prefix
+// of the lengths over the slots) and the compacted nonempty fibers: for the
+// c-th nonempty fiber, cpos = first stream position, coff = offset in the
+// mode-sorted nonzeros, cidx = its slot (for the weighted KRP row); also
 // chunk_first[ch] = the nonempty fiber holding stream position ch*GT_CHUNK.
-__global__ void __launch_bounds__(256) k_chunk_first(const DevState *st, const u64 *__restrict__ cpos,
-                                                     unsigned *__restrict__ chunk_first) {
-  const i64 nf = st->n_fib;
-  const u64 total = (u64)st->gathered;
-  for (i64 c = (i64)blockIdx.x * blockDim.x + threadIdx.x; c < nf; c += (i64)gridDim.x * blockDim.x) {
-    const u64 a = cpos[c];
-    const u64 b = (c + 1 < nf) ? cpos[c + 1] : total;
-    const u64 c0 = (a + GT_CHUNK - 1) / GT_CHUNK, c1 = (b - 1) / GT_CHUNK;
+// Empty fibers add nothing to M (they still enter G_s), and with only
+// nonempty fibers a chunk of GT_CHUNK positions spans at most GT_CHUNK + 1 of
+// them.  Workgroup b covers the ROWS_BLK slots of the row kernel's
+// workgroup b, whose totals it takes from part_len / part_cnt; every
+// workgroup sums the totals before its own, workgroup 0 also stores the
+// grand totals.
+__global__ void __launch_bounds__(ROWS_BLK) k_gather_prep(DevState *st,
+                                                          const unsigned *__restrict__ flen,
+                                                          const unsigned *__restrict__ foff,
+                                                          const u64 *__restrict__ part_len,
+                                                          const unsigned *__restrict__ part_cnt,
+                                                          u64 *__restrict__ cpos,
+                                                          unsigned *__restrict__ coff,
+                                                          unsigned *__restrict__ cidx,
+                                                          unsigned *__restrict__ chunk_first) {
+  const i64 n = st->n_slots;
+  const int nb = (int)((n + ROWS_BLK - 1) / ROWS_BLK);
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (b >= nb && !(b == 0 && nb == 0)) return;   // uniform per block
+  u64 bl = 0, al = 0, bc = 0, ac = 0;
+  for (int q = tid; q < nb; q += ROWS_BLK) {
+    const u64 l = part_len[q], c = part_cnt[q];
+    al += l;
+    ac += c;
+    if (q < b) { bl += l; bc += c; }
+  }
+  bl = wave_sum(bl); al = wave_sum(al); bc = wave_sum(bc); ac = wave_sum(ac);
+  __shared__ u64 red[4][ROWS_BLK / 64];
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = bl; red[1][tid >> 6] = al; red[2][tid >> 6] = bc; red[3][tid >> 6] = ac;
+  }
+  __syncthreads();
+  bl = al = bc = ac = 0;
+  for (int q = 0; q < ROWS_BLK / 64; ++q) {
+    bl += red[0][q]; al += red[1][q]; bc += red[2][q]; ac += red[3][q];
+  }
+  if (b == 0 && tid == 0) {
+    st->gathered = (i64)al;
+    st->n_fib = (i64)ac;
+  }
+  if (b >= nb) return;
+  const i64 i = (i64)b * ROWS_BLK + tid;
+  const unsigned l = i < n ? flen[i] : 0u;
+  u64 tl, tc;
+  const u64 el = block_excl_scan<u64>((u64)l, &tl);
+  const u64 ec = block_excl_scan<u64>((u64)(l > 0), &tc);
+  if (l > 0) {
+    const u64 c = bc + ec, p0 = bl + el;
+    cpos[c] = p0;
+    coff[c] = foff[i];
+    cidx[c] = (unsigned)i;
+    const u64 c0 = (p0 + GT_CHUNK - 1) / GT_CHUNK, c1 = (p0 + l - 1) / GT_CHUNK;
     for (u64 ch = c0; ch <= c1; ++ch) chunk_first[ch] = (unsigned)c;
   }
 }
-
 
 // Segmented gather: workgroup g takes the chunks g, g + G, ... of GT_CHUNK
 // stream positions; for a chunk
@@ -810,7 +780,8 @@ static int grid_for(i64 n, int blk, int maxg = 8192) {
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
                  double *samp_om, double *samp_w, const u64 *skeys,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
-                 unsigned *flen, double *gpart, void *M, i64 mlen, int ldz, hipStream_t s) {
+                 unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt, void *M,
+                 i64 mlen, int ldz, hipStream_t s) {
   const int nb = (int)((cap + ROWS_BLK - 1) / ROWS_BLK);
   // z rows, then the four waves' G_s tiles (4 x NTL x 256 doubles)
   const int nt = (R + 15) / 16;
@@ -822,33 +793,27 @@ void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u
            : dd == 4 ? k_rows<double, 4> : k_rows<double, 0>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
                        skeys, slots, hmask, hshift, (double *)zhat, foff, flen, gpart,
-                       (double *)M, mlen, ldz);
+                       part_len, part_cnt, (double *)M, mlen, ldz);
   } else {
     auto k = dd == 2 ? k_rows<float, 2> : dd == 3 ? k_rows<float, 3>
            : dd == 4 ? k_rows<float, 4> : k_rows<float, 0>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
                        skeys, slots, hmask, hshift, (float *)zhat, foff, flen, gpart,
-                       (float *)M, mlen, ldz);
+                       part_len, part_cnt, (float *)M, mlen, ldz);
   }
 }
 
 int rows_blocks(i64 cap) { return (int)((cap + ROWS_BLK - 1) / ROWS_BLK); }
 int rows_per_block() { return ROWS_BLK; }
 
-void launch_gather_prep(const DevState *st, DevState *stw, const unsigned *flen,
-                        const unsigned *foff, i64 cap, u64 *part_len, unsigned *part_cnt,
-                        u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
-                        hipStream_t s) {
-  const int nb = (int)((cap + GP_TILE - 1) / GP_TILE);
-  hipLaunchKernelGGL(k_gp_part, dim3(nb), dim3(256), 0, s, st, flen, part_len, part_cnt);
-  hipLaunchKernelGGL(k_gp_top, dim3(1), dim3(1024), 0, s, stw, part_len, part_cnt);
-  hipLaunchKernelGGL(k_gp_apply, dim3(nb), dim3(256), 0, s, st, flen, foff, part_len, part_cnt,
-                     cpos, coff, cidx);
-  hipLaunchKernelGGL(k_chunk_first, dim3(grid_for(cap, 256, 2048)), dim3(256), 0, s, st, cpos,
-                     chunk_first);
+void launch_gather_prep(DevState *st, const unsigned *flen, const unsigned *foff, i64 cap,
+                        const u64 *part_len, const unsigned *part_cnt, u64 *cpos, unsigned *coff,
+                        unsigned *cidx, unsigned *chunk_first, hipStream_t s) {
+  const int nb = std::max(1, (int)((cap + ROWS_BLK - 1) / ROWS_BLK));
+  hipLaunchKernelGGL(k_gather_prep, dim3(nb), dim3(ROWS_BLK), 0, s, st, flen, foff, part_len,
+                     part_cnt, cpos, coff, cidx, chunk_first);
 }
 
-int gather_prep_blocks(i64 cap) { return (int)((cap + GP_TILE - 1) / GP_TILE); }
 
 i64 gather_chunks_cap(i64 nnz) { return nnz / GT_CHUNK + 2; }
 
