@@ -55,8 +55,8 @@ int rows_per_block();
 void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                    const unsigned *cidx, const uint2 *pairs, const int *ik, const double *v64,
                    const void *zhat, void *M, int ldz, int grid, hipStream_t s);
-void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, const Decomp *dc,
-                       double *A, float *A32, hipStream_t s);
+void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, int ncopies,
+                       const Decomp *dc, double *A, float *A32, hipStream_t s);
 void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s);
 void launch_to_f32(const double *a, float *b, i64 n, hipStream_t s);
 void launch_mode_keys(const int *coords, i64 nnz, int D, const OtherModes &om, i64 nk, u64 *comp,
@@ -245,6 +245,10 @@ FullModes full_modes(const cpal_ctx *c) {
   return fm;
 }
 
+// Copies of M a mode's gather adds into: one per XCD for the segmented
+// gather, a single one for the atomic gather of very tall modes.
+i64 m_copies(i64 n) { return n <= (1 << 20) ? CPAL_MCOPIES : 1; }
+
 OtherModes others_of(const cpal_ctx *c, int k) {
   OtherModes om;
   std::memset(&om, 0, sizeof(om));
@@ -423,7 +427,11 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->flen = c->alloc<unsigned>(s);
     c->fpos = c->alloc<u64>(s + 1);
     c->gpart = c->alloc<double>((size_t)rows_blocks(s) * np);
-    c->M = c->alloc<char>((size_t)maxn * R * tsz);
+    {
+      i64 mcap = 0;
+      for (int m = 0; m < c->D; ++m) mcap = std::max<i64>(mcap, m_copies(c->dims[m]) * c->dims[m]);
+      c->M = c->alloc<char>((size_t)mcap * R * tsz);
+    }
     c->gram_tmp = c->alloc<double>(np);
     c->chunk_first = c->alloc<unsigned>(gather_chunks_cap(c->nnz));
     c->cpos = c->alloc<u64>(s);
@@ -577,7 +585,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
   launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, sorted, md.slots,
               md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->gp_len, c->gp_cnt,
-              c->M, md.n * R, c->ldz, s);
+              c->M, m_copies(md.n) * md.n * R, c->ldz, s);
   launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->cpos, c->coff,
                      c->cidx, c->chunk_first, s);
   c->stage_end(CPAL_STAGE_ROWS, tb);
@@ -593,7 +601,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   tb = c->stage_begin(CPAL_STAGE_SOLVE);
   launch_decomp_dev(c->gpart, &c->st->n_slots, rows_per_block(), R, c->dc, &c->st->flags,
                     c->gram_tmp, s);
-  launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->dc, md.A, md.A32, s);
+  launch_solve_rows(c->f64, c->st, md.n, R, c->M, (int)m_copies(md.n), c->dc, md.A, md.A32, s);
   c->stage_end(CPAL_STAGE_SOLVE, tb);
   tb = c->stage_begin(CPAL_STAGE_LEVERAGE);
   refresh_leverage(c, k);

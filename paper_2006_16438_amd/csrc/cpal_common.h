@@ -12,6 +12,7 @@
 #define CPAL_GRAM_ROWS 256      // rows per block of the canonical Gram summation
 #define CPAL_DRAW_CHUNK 256     // draws per chunk of the persistent fit-sample draw kernel
 #define CPAL_KRP_CHUNK 256      // draws per chunk of the KRP row draw kernel (one per thread)
+#define CPAL_MCOPIES 8          // copies of M for the gather's adds, one per XCD (power of two)
 
 typedef unsigned long long u64;
 typedef long long i64;
@@ -193,6 +194,11 @@ __device__ __forceinline__ T block_excl_scan(T v, T *total) {
   *total = wsum[16];
   __syncthreads();
   return res;
+}
+
+// Index of the XCD (accelerator complex die) the calling wave runs on.
+__device__ __forceinline__ unsigned xcd_id() {
+  return (unsigned)__builtin_amdgcn_s_getreg((3 << 11) | 20);   // HW_REG_XCC_ID, bits [3:0]
 }
 
 // Value of v in lane l (l wave-uniform) through two scalar lane reads.

@@ -429,162 +429,199 @@ __global__ void __launch_bounds__(ROWS_BLK) k_gather_prep(DevState *st,
 //     costs one global atomic add per column (rows need i_k < 2^20).
 #define GS_DIG 6
 #define GS_BATCH 32
+
+// Steps 1 and 2 for chunk ch; returns the sorted keys (ka or kb).
+template <typename T>
+__device__ __forceinline__ unsigned *seg_load_sort(
+    i64 ch, i64 nch, i64 total, i64 nf, const u64 *__restrict__ cpos,
+    const unsigned *__restrict__ coff, const unsigned *__restrict__ cidx,
+    const unsigned *__restrict__ chunk_first, const NzLoad<T> &nz, int ikbits, u64 *win,
+    unsigned *ka, unsigned *kb, T *lx, unsigned *lz, unsigned *tab) {
+  constexpr int NW = GT_THREADS / 64;
+  constexpr int NT = 64 * GT_PER_THREAD * NW;   // digit x round x wave counters
+  const int tid = threadIdx.x, w = tid >> 6;
+  const u64 lt = __lanemask_lt();
+  const i64 base = ch * GT_CHUNK;
+  const i64 last = min(total, base + GT_CHUNK) - 1;
+  const i64 jlo = chunk_first[ch];
+  const i64 jhi = (ch + 1 < nch) ? (i64)chunk_first[ch + 1] : nf - 1;
+  const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
+  __syncthreads();   // the previous chunk is finished with every shared array
+  for (int e = tid; e < nwin; e += GT_THREADS) win[e] = cpos[jlo + e];
+  __syncthreads();
+  int jw[GT_PER_THREAD];
+  u64 ee[GT_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < GT_PER_THREAD; ++u) {
+    const u64 p = (u64)min(base + (i64)u * GT_THREADS + tid, last);
+    int lo = 0, hi = nwin;   // last index with win[idx] <= p
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (win[mid] <= p) lo = mid; else hi = mid;
+    }
+    jw[u] = lo;
+    ee[u] = p - win[lo];
+  }
+  unsigned zrow[GT_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < GT_PER_THREAD; ++u) {
+    ee[u] += coff[jlo + jw[u]];
+    zrow[u] = cidx[jlo + jw[u]];
+  }
+#pragma unroll
+  for (int u = 0; u < GT_PER_THREAD; ++u) {
+    int ik;
+    T x;
+    nz.get(ee[u], ik, x);
+    const int li = u * GT_THREADS + tid;   // = position - base
+    ka[li] = (base + li <= last) ? (((unsigned)ik << 12) | (unsigned)li) : 0xFFFFFFFFu;
+    lx[li] = x;
+    lz[li] = zrow[u];
+  }
+  unsigned *src = ka, *dst = kb;
+  for (int shift = 12; shift < 12 + ikbits; shift += GS_DIG) {
+    for (int e = tid; e < NT; e += GT_THREADS) tab[e] = 0u;
+    __syncthreads();
+    unsigned key[GT_PER_THREAD], dg[GT_PER_THREAD], rk[GT_PER_THREAD];
+#pragma unroll
+    for (int r = 0; r < GT_PER_THREAD; ++r) {
+      key[r] = src[r * GT_THREADS + tid];
+      dg[r] = (key[r] >> shift) & 63u;
+      u64 peers = ~0ull;
+#pragma unroll
+      for (int b = 0; b < GS_DIG; ++b) {
+        const bool bit = (dg[r] >> b) & 1u;
+        const u64 m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      rk[r] = (unsigned)__popcll(peers & lt);
+      if (rk[r] == 0) tab[(dg[r] * GT_PER_THREAD + r) * NW + w] = (unsigned)__popcll(peers);
+    }
+    __syncthreads();
+    {   // exclusive scan of tab in (digit, round, wave) order
+      unsigned v[NT / GT_THREADS], sum = 0;
+#pragma unroll
+      for (int q = 0; q < NT / GT_THREADS; ++q) { v[q] = tab[tid * (NT / GT_THREADS) + q]; sum += v[q]; }
+      unsigned tot;
+      unsigned run = block_excl_scan<unsigned>(sum, &tot);
+#pragma unroll
+      for (int q = 0; q < NT / GT_THREADS; ++q) {
+        tab[tid * (NT / GT_THREADS) + q] = run;
+        run += v[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < GT_PER_THREAD; ++r)
+      dst[tab[(dg[r] * GT_PER_THREAD + r) * NW + w] + rk[r]] = key[r];
+    __syncthreads();
+    unsigned *t = src; src = dst; dst = t;
+  }
+  return src;
+}
+
+// Step 3 over n row-sorted entries; entry q -> (row, x, KRP row) by get(q).
+template <typename T, int LPN, typename Get>
+__device__ __forceinline__ void seg_reduce(const Get &get, int n, int R,
+                                           const T *__restrict__ zhat, int ldz,
+                                           T *__restrict__ M, int *srow, T (*svec)[LPN]) {
+  constexpr int NG = GT_THREADS / LPN;
+  constexpr int PER = GT_CHUNK / NG;
+  const int tid = threadIdx.x, gi = tid / LPN, c = tid % LPN;
+  const int q0 = gi * PER, q1 = min(n, q0 + PER);
+  int cur = -1, first = -1;
+  T acc = T(0), facc = T(0);
+  if (q0 < q1) {
+    {
+      unsigned r0;
+      T x0;
+      unsigned z0;
+      get(q0, r0, x0, z0);
+      cur = (int)r0;
+    }
+    for (int q = q0; q < q1; q += GS_BATCH) {
+      unsigned rr[GS_BATCH];
+      T xv[GS_BATCH], zv[GS_BATCH];
+#pragma unroll
+      for (int b = 0; b < GS_BATCH; ++b) {
+        unsigned zr;
+        get(min(q + b, q1 - 1), rr[b], xv[b], zr);
+        zv[b] = zhat[(i64)zr * ldz + c];
+      }
+#pragma unroll
+      for (int b = 0; b < GS_BATCH; ++b) {
+        if (q + b < q1) {
+          const int r = (int)rr[b];
+          if (r != cur) {
+            if (first < 0) { first = cur; facc = acc; }
+            else if (c < R) unsafeAtomicAdd(&M[(i64)cur * R + c], acc);
+            cur = r;
+            acc = T(0);
+          }
+          acc += xv[b] * zv[b];
+        }
+      }
+    }
+  }
+  // slice ends: slot 2gi = first run, 2gi+1 = last run (-1: none)
+  if (first < 0) { first = cur; facc = acc; cur = -1; }
+  if (c == 0) { srow[2 * gi] = first; srow[2 * gi + 1] = cur; }
+  svec[2 * gi][c] = facc;
+  svec[2 * gi + 1][c] = acc;
+  __syncthreads();
+  if (gi == 0 && n > 0) {
+    int mr = -1;
+    T ma = T(0);
+    for (int sl = 0; sl < 2 * NG; ++sl) {
+      const int r = srow[sl];
+      if (r < 0) continue;
+      if (r != mr) {
+        if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * R + c], ma);
+        mr = r;
+        ma = T(0);
+      }
+      ma += svec[sl][c];
+    }
+    if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * R + c], ma);
+  }
+}
+
+template <typename T>
+struct LdsEntries {
+  const unsigned *keys;
+  const T *lx;
+  const unsigned *lz;
+  __device__ __forceinline__ void operator()(int q, unsigned &r, T &x, unsigned &z) const {
+    const unsigned k = keys[q];
+    r = k >> 12;
+    x = lx[k & 4095u];
+    z = lz[k & 4095u];
+  }
+};
+
 template <typename T, int LPN>
 __global__ void __launch_bounds__(GT_THREADS) k_gather_seg(
     const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    int ikbits, const T *__restrict__ zhat, int ldz, T *__restrict__ M) {
-  constexpr int NW = GT_THREADS / 64;
+    int ikbits, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
   constexpr int NG = GT_THREADS / LPN;
-  constexpr int PER = GT_CHUNK / NG;
-  constexpr int NT = 64 * GT_PER_THREAD * NW;   // digit x round x wave counters
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned ka[GT_CHUNK], kb[GT_CHUNK];
   __shared__ T lx[GT_CHUNK];
   __shared__ unsigned lz[GT_CHUNK];
-  __shared__ unsigned tab[NT];
+  __shared__ unsigned tab[64 * GT_PER_THREAD * (GT_THREADS / 64)];
   __shared__ int srow[2 * NG];
   __shared__ T svec[2 * NG][LPN];
   const i64 total = st->gathered;
   const i64 nf = st->n_fib;
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
-  const int g = blockIdx.x, G = gridDim.x;
-  if (g >= nch) return;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int gi = tid / LPN, c = tid % LPN;
-  const u64 lt = __lanemask_lt();
-  for (i64 ch = g; ch < nch; ch += G) {
-    const i64 base = ch * GT_CHUNK;
-    const i64 last = min(total, base + GT_CHUNK) - 1;
-    const i64 jlo = chunk_first[ch];
-    const i64 jhi = (ch + 1 < nch) ? (i64)chunk_first[ch + 1] : nf - 1;
-    const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
-    __syncthreads();   // the previous chunk is finished with every shared array
-    for (int e = tid; e < nwin; e += GT_THREADS) win[e] = cpos[jlo + e];
-    __syncthreads();
-    // 1
-    int jw[GT_PER_THREAD];
-    u64 ee[GT_PER_THREAD];
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      const u64 p = (u64)min(base + (i64)u * GT_THREADS + tid, last);
-      int lo = 0, hi = nwin;   // last index with win[idx] <= p
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (win[mid] <= p) lo = mid; else hi = mid;
-      }
-      jw[u] = lo;
-      ee[u] = p - win[lo];
-    }
-    unsigned zrow[GT_PER_THREAD];
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      ee[u] += coff[jlo + jw[u]];
-      zrow[u] = cidx[jlo + jw[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < GT_PER_THREAD; ++u) {
-      int ik;
-      T x;
-      nz.get(ee[u], ik, x);
-      const int li = u * GT_THREADS + tid;   // = position - base
-      ka[li] = (base + li <= last) ? (((unsigned)ik << 12) | (unsigned)li) : 0xFFFFFFFFu;
-      lx[li] = x;
-      lz[li] = zrow[u];
-    }
-    // 2
-    unsigned *src = ka, *dst = kb;
-    for (int shift = 12; shift < 12 + ikbits; shift += GS_DIG) {
-      for (int e = tid; e < NT; e += GT_THREADS) tab[e] = 0u;
-      __syncthreads();
-      unsigned key[GT_PER_THREAD], dg[GT_PER_THREAD], rk[GT_PER_THREAD];
-#pragma unroll
-      for (int r = 0; r < GT_PER_THREAD; ++r) {
-        key[r] = src[r * GT_THREADS + tid];
-        dg[r] = (key[r] >> shift) & 63u;
-        u64 peers = ~0ull;
-#pragma unroll
-        for (int b = 0; b < GS_DIG; ++b) {
-          const bool bit = (dg[r] >> b) & 1u;
-          const u64 m = __ballot(bit);
-          peers &= bit ? m : ~m;
-        }
-        rk[r] = (unsigned)__popcll(peers & lt);
-        if (rk[r] == 0) tab[(dg[r] * GT_PER_THREAD + r) * NW + w] = (unsigned)__popcll(peers);
-      }
-      __syncthreads();
-      {   // exclusive scan of tab in (digit, round, wave) order
-        unsigned v[NT / GT_THREADS], sum = 0;
-#pragma unroll
-        for (int q = 0; q < NT / GT_THREADS; ++q) { v[q] = tab[tid * (NT / GT_THREADS) + q]; sum += v[q]; }
-        unsigned tot;
-        unsigned run = block_excl_scan<unsigned>(sum, &tot);
-#pragma unroll
-        for (int q = 0; q < NT / GT_THREADS; ++q) {
-          tab[tid * (NT / GT_THREADS) + q] = run;
-          run += v[q];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < GT_PER_THREAD; ++r)
-        dst[tab[(dg[r] * GT_PER_THREAD + r) * NW + w] + rk[r]] = key[r];
-      __syncthreads();
-      unsigned *t = src; src = dst; dst = t;
-    }
-    // 3
-    const int nvalid = (int)(last - base + 1);
-    const int q0 = gi * PER, q1 = min(nvalid, q0 + PER);
-    int cur = -1, first = -1;
-    T acc = T(0), facc = T(0);
-    if (q0 < q1) {
-      cur = (int)(src[q0] >> 12);
-      for (int q = q0; q < q1; q += GS_BATCH) {
-        unsigned kk[GS_BATCH];
-        T xv[GS_BATCH], zv[GS_BATCH];
-#pragma unroll
-        for (int b = 0; b < GS_BATCH; ++b) {
-          kk[b] = src[min(q + b, q1 - 1)];
-          const unsigned li = kk[b] & 4095u;
-          xv[b] = lx[li];
-          zv[b] = zhat[(i64)lz[li] * ldz + c];
-        }
-#pragma unroll
-        for (int b = 0; b < GS_BATCH; ++b) {
-          if (q + b < q1) {
-            const int r = (int)(kk[b] >> 12);
-            if (r != cur) {
-              if (first < 0) { first = cur; facc = acc; }
-              else if (c < R) unsafeAtomicAdd(&M[(i64)cur * R + c], acc);
-              cur = r;
-              acc = T(0);
-            }
-            acc += xv[b] * zv[b];
-          }
-        }
-      }
-    }
-    // slice ends: slot 2gi = first run, 2gi+1 = last run (-1: none)
-    if (first < 0) { first = cur; facc = acc; cur = -1; }
-    if (c == 0) { srow[2 * gi] = first; srow[2 * gi + 1] = cur; }
-    svec[2 * gi][c] = facc;
-    svec[2 * gi + 1][c] = acc;
-    __syncthreads();
-    if (gi == 0) {
-      int mr = -1;
-      T ma = T(0);
-      for (int sl = 0; sl < 2 * NG; ++sl) {
-        const int r = srow[sl];
-        if (r < 0) continue;
-        if (r != mr) {
-          if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * R + c], ma);
-          mr = r;
-          ma = T(0);
-        }
-        ma += svec[sl][c];
-      }
-      if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * R + c], ma);
-    }
+  // this XCD's copy of M: the adds of workgroups on one XCD stay in its L2
+  T *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * R;
+  for (i64 ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const unsigned *keys = seg_load_sort<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz,
+                                            ikbits, win, ka, kb, lx, lz, tab);
+    const int nvalid = (int)(min(total, (ch + 1) * GT_CHUNK) - ch * GT_CHUNK);
+    seg_reduce<T, LPN>(LdsEntries<T>{keys, lx, lz}, nvalid, R, zhat, ldz, Mx, srow, svec);
   }
 }
 
@@ -602,13 +639,13 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
     auto k = rm == 16 ? k_gather_seg<double, 16> : rm == 32 ? k_gather_seg<double, 32>
                                                             : k_gather_seg<double, 64>;
     hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
-                       chunk_first, nz, ikbits, (const double *)zhat, ldz, (double *)M);
+                       chunk_first, nz, ikbits, (const double *)zhat, ldz, (double *)M, nk);
   } else {
     NzLoad<float> nz{pairs};
     auto k = rm == 16 ? k_gather_seg<float, 16> : rm == 32 ? k_gather_seg<float, 32>
                                                            : k_gather_seg<float, 64>;
     hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
-                       chunk_first, nz, ikbits, (const float *)zhat, ldz, (float *)M);
+                       chunk_first, nz, ikbits, (const float *)zhat, ldz, (float *)M, nk);
   }
 }
 
@@ -620,7 +657,7 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
 // throughout.  Skipped when the update hit a state error.  256 threads.
 template <typename T, int LPN>
 __global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, int R,
-                                                    const T *__restrict__ M,
+                                                    const T *__restrict__ M, int ncopies,
                                                     const Decomp *__restrict__ dc,
                                                     double *__restrict__ A,
                                                     float *__restrict__ A32) {
@@ -635,7 +672,9 @@ __global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, i
   if (row >= n) return;   // uniform per lane group
   const bool col = c < R;
   const int cl = col ? c : R - 1;
-  double v = col ? (double)M[row * R + c] : 0.0;
+  double v = 0.0;
+  if (col)
+    for (int x = 0; x < ncopies; ++x) v = v + (double)M[(i64)x * n * R + row * R + c];
   if (!pinv) {
     for (int j = 0; j < R; ++j) {
       const double yj = group_value<LPN>(v, j) / sL[j * R + j];
@@ -866,19 +905,21 @@ void launch_samples_out(const DevState *st, const u64 *samp_idx, const double *s
                      idx, om, w, count);
 }
 
-void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, const Decomp *dc,
-                       double *A, float *A32, hipStream_t s) {
+void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, int ncopies,
+                       const Decomp *dc, double *A, float *A32, hipStream_t s) {
   const int lpn = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
   const int nb = (int)((n * lpn + 255) / 256);
   const size_t sh = sizeof(double) * (size_t)R * R;
   if (f64) {
     auto k = lpn == 16 ? k_solve_rows<double, 16> : lpn == 32 ? k_solve_rows<double, 32>
                                                               : k_solve_rows<double, 64>;
-    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const double *)M, dc, A, A32);
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const double *)M, ncopies, dc, A,
+                       A32);
   } else {
     auto k = lpn == 16 ? k_solve_rows<float, 16> : lpn == 32 ? k_solve_rows<float, 32>
                                                              : k_solve_rows<float, 64>;
-    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const float *)M, dc, A, A32);
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const float *)M, ncopies, dc, A,
+                       A32);
   }
 }
 
