@@ -17,8 +17,9 @@ namespace cpal {
 void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_blk, int R,
                        Decomp *out, int *flag_or, double *gram_tmp, hipStream_t s);
 void launch_gather_prep(DevState *st, const unsigned *flen, const unsigned *foff, i64 cap,
-                        const u64 *part_len, const unsigned *part_cnt, u64 *cpos, unsigned *coff,
-                        unsigned *cidx, unsigned *chunk_first, hipStream_t s);
+                        const u64 *part_len, const unsigned *part_cnt, const unsigned *part_act,
+                        u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
+                        hipStream_t s);
 int gather_row_width(int R);
 i64 gather_chunks_cap(i64 nnz);
 void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
@@ -48,8 +49,8 @@ void launch_samples_out(const DevState *st, const u64 *samp_idx, const double *s
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
                  double *samp_om, double *samp_w, const u64 *skeys,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
-                 unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt, void *M,
-                 i64 mlen, int ldz, hipStream_t s);
+                 unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt,
+                 unsigned *part_act, void *M, i64 mlen, int ldz, hipStream_t s);
 int rows_blocks(i64 cap);
 int rows_per_block();
 void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
@@ -169,7 +170,7 @@ struct cpal_ctx {
   unsigned *coff = nullptr;         //   offset in the mode-sorted nonzeros,
   unsigned *cidx = nullptr;         //   sampled row
   u64 *gp_len = nullptr;
-  unsigned *gp_cnt = nullptr;
+  unsigned *gp_cnt = nullptr, *gp_act = nullptr;
   double *gram_tmp = nullptr;
   // fit sample (Sec. 6.4)
   i64 fit_nz = 0, fit_n = 0, fit_ld = 0;
@@ -439,6 +440,7 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->cidx = c->alloc<unsigned>(s);
     c->gp_len = c->alloc<u64>(rows_blocks(s) + 1);
     c->gp_cnt = c->alloc<unsigned>(rows_blocks(s) + 1);
+    c->gp_act = c->alloc<unsigned>(rows_blocks(s) + 1);
     const i64 sort_cap = std::max<i64>((i64)c->det_cap, c->nnz);
     c->sort_scratch = c->alloc<char>(sort_scratch_bytes(sort_cap, true));
     c->scan_scratch = c->alloc<char>(scan_scratch_bytes(std::max<i64>(sort_cap, s)));
@@ -585,9 +587,9 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
   launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, sorted, md.slots,
               md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->gp_len, c->gp_cnt,
-              c->M, m_copies(md.n) * md.n * R, c->ldz, s);
-  launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->cpos, c->coff,
-                     c->cidx, c->chunk_first, s);
+              c->gp_act, c->M, m_copies(md.n) * md.n * R, c->ldz, s);
+  launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
+                     c->coff, c->cidx, c->chunk_first, s);
   c->stage_end(CPAL_STAGE_ROWS, tb);
   tb = c->stage_begin(CPAL_STAGE_GATHER);
   if (md.n <= (1 << 20))

@@ -92,8 +92,8 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     double *__restrict__ samp_w, const u64 *__restrict__ skeys,
     const FiberSlot *__restrict__ slots, u64 hmask, int hshift, T *__restrict__ zhat,
     unsigned *__restrict__ foff, unsigned *__restrict__ flen, double *__restrict__ gpart,
-    u64 *__restrict__ part_len, unsigned *__restrict__ part_cnt, T *__restrict__ M, i64 mlen,
-    int ldz) {
+    u64 *__restrict__ part_len, unsigned *__restrict__ part_cnt, unsigned *__restrict__ part_act,
+    T *__restrict__ M, i64 mlen, int ldz) {
   extern __shared__ double sz[];           // ROWS_BLK x (R+1); phase 3 reuses it
   __shared__ double som[ROWS_BLK];
   __shared__ unsigned sim[CPAL_MAXORDER][ROWS_BLK];
@@ -178,8 +178,8 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     foff[j] = off;
     flen[j] = len;
   }
-  {   // rows of the sampled system (s_bar, one atomic add per workgroup) and the
-      // workgroup's gathered length and nonempty-fiber count for the gather
+  {   // the workgroup's rows of the sampled system (active slots), gathered
+      // length and nonempty-fiber count, totalled by the gather preparation
     const unsigned na = (unsigned)__popcll(__ballot(active));
     const u64 ln = wave_sum((u64)(tid < rows ? flen[base + tid] : 0u));
     const unsigned nf = (unsigned)__popcll(__ballot(tid < rows && flen[base + tid] > 0u));
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
       unsigned t = 0, f = 0;
       u64 l = 0;
       for (int q = 0; q < ROWS_BLK / 64; ++q) { t += wact[q]; f += wnf[q]; l += wln[q]; }
-      atomicAdd((unsigned long long *)&st->s_bar, (unsigned long long)t);
+      part_act[blockIdx.x] = t;
       part_len[blockIdx.x] = l;
       part_cnt[blockIdx.x] = f;
     }
@@ -367,6 +367,7 @@ __global__ void __launch_bounds__(ROWS_BLK) k_gather_prep(DevState *st,
                                                           const unsigned *__restrict__ foff,
                                                           const u64 *__restrict__ part_len,
                                                           const unsigned *__restrict__ part_cnt,
+                                                          const unsigned *__restrict__ part_act,
                                                           u64 *__restrict__ cpos,
                                                           unsigned *__restrict__ coff,
                                                           unsigned *__restrict__ cidx,
@@ -375,26 +376,29 @@ __global__ void __launch_bounds__(ROWS_BLK) k_gather_prep(DevState *st,
   const int nb = (int)((n + ROWS_BLK - 1) / ROWS_BLK);
   const int b = blockIdx.x, tid = threadIdx.x;
   if (b >= nb && !(b == 0 && nb == 0)) return;   // uniform per block
-  u64 bl = 0, al = 0, bc = 0, ac = 0;
+  u64 bl = 0, al = 0, bc = 0, ac = 0, aa = 0;
   for (int q = tid; q < nb; q += ROWS_BLK) {
     const u64 l = part_len[q], c = part_cnt[q];
     al += l;
     ac += c;
+    aa += part_act[q];
     if (q < b) { bl += l; bc += c; }
   }
-  bl = wave_sum(bl); al = wave_sum(al); bc = wave_sum(bc); ac = wave_sum(ac);
-  __shared__ u64 red[4][ROWS_BLK / 64];
+  bl = wave_sum(bl); al = wave_sum(al); bc = wave_sum(bc); ac = wave_sum(ac); aa = wave_sum(aa);
+  __shared__ u64 red[5][ROWS_BLK / 64];
   if ((tid & 63) == 0) {
     red[0][tid >> 6] = bl; red[1][tid >> 6] = al; red[2][tid >> 6] = bc; red[3][tid >> 6] = ac;
+    red[4][tid >> 6] = aa;
   }
   __syncthreads();
-  bl = al = bc = ac = 0;
+  bl = al = bc = ac = aa = 0;
   for (int q = 0; q < ROWS_BLK / 64; ++q) {
-    bl += red[0][q]; al += red[1][q]; bc += red[2][q]; ac += red[3][q];
+    bl += red[0][q]; al += red[1][q]; bc += red[2][q]; ac += red[3][q]; aa += red[4][q];
   }
   if (b == 0 && tid == 0) {
     st->gathered = (i64)al;
     st->n_fib = (i64)ac;
+    st->s_bar = (i64)aa;
   }
   if (b >= nb) return;
   const i64 i = (i64)b * ROWS_BLK + tid;
@@ -819,8 +823,8 @@ static int grid_for(i64 n, int blk, int maxg = 8192) {
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
                  double *samp_om, double *samp_w, const u64 *skeys,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
-                 unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt, void *M,
-                 i64 mlen, int ldz, hipStream_t s) {
+                 unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt,
+                 unsigned *part_act, void *M, i64 mlen, int ldz, hipStream_t s) {
   const int nb = (int)((cap + ROWS_BLK - 1) / ROWS_BLK);
   // z rows, then the four waves' G_s tiles (4 x NTL x 256 doubles)
   const int nt = (R + 15) / 16;
@@ -832,13 +836,13 @@ void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u
            : dd == 4 ? k_rows<double, 4> : k_rows<double, 0>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
                        skeys, slots, hmask, hshift, (double *)zhat, foff, flen, gpart,
-                       part_len, part_cnt, (double *)M, mlen, ldz);
+                       part_len, part_cnt, part_act, (double *)M, mlen, ldz);
   } else {
     auto k = dd == 2 ? k_rows<float, 2> : dd == 3 ? k_rows<float, 3>
            : dd == 4 ? k_rows<float, 4> : k_rows<float, 0>;
     hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
                        skeys, slots, hmask, hshift, (float *)zhat, foff, flen, gpart,
-                       part_len, part_cnt, (float *)M, mlen, ldz);
+                       part_len, part_cnt, part_act, (float *)M, mlen, ldz);
   }
 }
 
@@ -846,11 +850,12 @@ int rows_blocks(i64 cap) { return (int)((cap + ROWS_BLK - 1) / ROWS_BLK); }
 int rows_per_block() { return ROWS_BLK; }
 
 void launch_gather_prep(DevState *st, const unsigned *flen, const unsigned *foff, i64 cap,
-                        const u64 *part_len, const unsigned *part_cnt, u64 *cpos, unsigned *coff,
-                        unsigned *cidx, unsigned *chunk_first, hipStream_t s) {
+                        const u64 *part_len, const unsigned *part_cnt, const unsigned *part_act,
+                        u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
+                        hipStream_t s) {
   const int nb = std::max(1, (int)((cap + ROWS_BLK - 1) / ROWS_BLK));
   hipLaunchKernelGGL(k_gather_prep, dim3(nb), dim3(ROWS_BLK), 0, s, st, flen, foff, part_len,
-                     part_cnt, cpos, coff, cidx, chunk_first);
+                     part_cnt, part_act, cpos, coff, cidx, chunk_first);
 }
 
 
