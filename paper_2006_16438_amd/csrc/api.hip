@@ -19,7 +19,7 @@ void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_bl
 void launch_gather_prep(DevState *st, const unsigned *flen, const unsigned *foff, i64 cap,
                         const u64 *part_len, const unsigned *part_cnt, const unsigned *part_act,
                         u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
-                        hipStream_t s);
+                        const unsigned *tpos, DrawEntry *tab, hipStream_t s);
 int gather_row_width(int R);
 i64 gather_chunks_cap(i64 nnz);
 void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
@@ -40,14 +40,16 @@ void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u6
                  unsigned short *bpos, unsigned *chunk_cnt, int grid_first, int grid_more,
                  hipStream_t s);
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
-                    const unsigned short *bpos, u64 *keys, int grid, hipStream_t s);
-u64 *sort_keys_pp(u64 *keys, unsigned *vals, u64 *tmp_keys, unsigned *tmp_vals, void *scratch,
-                  i64 cap, const i64 *count_dev, i64 count_host, int bits, hipStream_t s);
-void launch_samples_out(const DevState *st, const u64 *samp_idx, const double *samp_om,
-                        const double *samp_w, i64 cap, u64 *idx, double *om, double *w,
-                        i64 *count, hipStream_t s);
+                    const unsigned short *bpos, u64 *keys, DrawEntry *tab, u64 tmask, int tshift,
+                    hipStream_t s);
+void launch_draw_table_clear(DrawEntry *tab, u64 n, hipStream_t s);
+void launch_samples_out(DevState *st, const u64 *samp_idx, const double *samp_om,
+                        const double *samp_w, i64 slots_cap, int key_bits, u64 *rkeys,
+                        u64 *rkeys_tmp, unsigned *rslot, unsigned *rslot_tmp, void *sort_scratch,
+                        i64 cap, u64 *idx, double *om, double *w, i64 *count, hipStream_t s);
 void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
-                 double *samp_om, double *samp_w, const u64 *skeys,
+                 double *samp_om, double *samp_w, const u64 *dkeys, const DrawEntry *tab,
+                 u64 tmask, int tshift, unsigned *tpos,
                  const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
                  unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt,
                  unsigned *part_act, void *M, i64 mlen, int ldz, hipStream_t s);
@@ -149,7 +151,13 @@ struct cpal_ctx {
   unsigned short *dpos = nullptr;
   unsigned *chunk_cnt = nullptr;
   i64 max_chunks = 0;
-  u64 *keys = nullptr, *keys_tmp = nullptr;
+  u64 *keys = nullptr, *keys_tmp = nullptr;   // accepted draws in draw order (+ sort buffer)
+  DrawEntry *dtab = nullptr;                  // draw table: row -> first draw, count
+  u64 dtab_n = 0;
+  int dtab_shift = 0;
+  unsigned *tpos = nullptr;                   // per draw: its table entry if it is a row's first
+  unsigned *ord = nullptr, *ord_tmp = nullptr;  // slots of the listed random rows (sort payload)
+  int last_key_bits = 0;                      // key width of the last updated mode
   u64 *samp_idx = nullptr;
   double *samp_om = nullptr, *samp_w = nullptr;
   void *zhat = nullptr;
@@ -161,7 +169,6 @@ struct cpal_ctx {
   void *scan_scratch = nullptr;
   int draw_grid = 0;        // first draw pass: blocks for 1.5 s draws (the unneeded exit)
   int draw_more_grid = 256; // top-up draw pass
-  int compact_grid = 256;
   int gather_grid = 2048;
   int ldz = 0;                  // row stride of the weighted KRP rows (16-byte multiple)
   int gs_grid = 512;            // workgroups of the segmented gather
@@ -418,6 +425,15 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
                                       (i64)std::ceil(1.5 * (double)s / CPAL_KRP_CHUNK) + 2);
     c->keys = c->alloc<u64>(s);
     c->keys_tmp = c->alloc<u64>(s);
+    c->dtab_n = 64;
+    while (c->dtab_n < 2 * (u64)s) c->dtab_n <<= 1;
+    c->dtab_shift = 64;
+    for (u64 v = c->dtab_n; v > 1; v >>= 1) --c->dtab_shift;
+    c->dtab = c->alloc<DrawEntry>(c->dtab_n);
+    launch_draw_table_clear(c->dtab, c->dtab_n, c->stream);
+    c->tpos = c->alloc<unsigned>(s);
+    c->ord = c->alloc<unsigned>(s);
+    c->ord_tmp = c->alloc<unsigned>(s);
     c->samp_idx = c->alloc<u64>(s);
     c->samp_om = c->alloc<double>(s);
     c->samp_w = c->alloc<double>(s);
@@ -579,17 +595,17 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   // random rows (Alg. 2) and combining repeats (Sec. 4.1, 4.3)
   launch_draw(om, c->st, c->seed, c->stream_id, c->t, c->dbuf, c->dpos, c->chunk_cnt,
               c->draw_grid, c->draw_more_grid, s);
-  launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->compact_grid, s);
-  const u64 *sorted = sort_keys_pp(c->keys, nullptr, c->keys_tmp, nullptr, c->sort_scratch, c->s,
-                                   &c->st->s_rnd_used, 0, md.key_bits, s);
+  launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->dtab, c->dtab_n - 1,
+                 c->dtab_shift, s);
+  c->last_key_bits = md.key_bits;
   c->stage_end(CPAL_STAGE_SAMPLE, tb);
   tb = c->stage_begin(CPAL_STAGE_ROWS);
   // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
-  launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, sorted, md.slots,
-              md.nslots - 1, md.hshift, c->zhat, c->foff, c->flen, c->gpart, c->gp_len, c->gp_cnt,
-              c->gp_act, c->M, m_copies(md.n) * md.n * R, c->ldz, s);
+  launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->keys, c->dtab,
+              c->dtab_n - 1, c->dtab_shift, c->tpos, md.slots, md.nslots - 1, md.hshift, c->zhat,
+              c->foff, c->flen, c->gpart, c->gp_len, c->gp_cnt, c->gp_act, c->M, m_copies(md.n) * md.n * R, c->ldz, s);
   launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
-                     c->coff, c->cidx, c->chunk_first, s);
+                     c->coff, c->cidx, c->chunk_first, c->tpos, c->dtab, s);
   c->stage_end(CPAL_STAGE_ROWS, tb);
   tb = c->stage_begin(CPAL_STAGE_GATHER);
   if (md.n <= (1 << 20))
@@ -625,8 +641,9 @@ cpal_status cp_arls_lev_fit_estimate(cpal_ctx *c, double *fit_dev) {
 cpal_status cp_arls_lev_samples(const cpal_ctx *c, uint64_t *idx_dev, double *omega_dev,
                                 double *w_dev, int64_t cap, int64_t *count_dev) {
   if (!c || cap < 0) return CPAL_E_ARG;
-  launch_samples_out(c->st, c->samp_idx, c->samp_om, c->samp_w, cap, (u64 *)idx_dev, omega_dev,
-                     w_dev, (i64 *)count_dev, c->stream);
+  launch_samples_out(c->st, c->samp_idx, c->samp_om, c->samp_w, c->s, c->last_key_bits, c->keys,
+                     c->keys_tmp, c->ord, c->ord_tmp, c->sort_scratch, cap, (u64 *)idx_dev,
+                     omega_dev, w_dev, (i64 *)count_dev, c->stream);
   return CPAL_OK;
 }
 

@@ -13,6 +13,7 @@
 #define CPAL_DRAW_CHUNK 256     // draws per chunk of the persistent fit-sample draw kernel
 #define CPAL_KRP_CHUNK 256      // draws per chunk of the KRP row draw kernel (one per thread)
 #define CPAL_MCOPIES 8          // copies of M for the gather's adds, one per XCD (power of two)
+#define CPAL_GATHER_CHUNK 2048  // stream positions per chunk of the segmented gather
 
 typedef unsigned long long u64;
 typedef long long i64;
@@ -34,6 +35,7 @@ struct DevState {
   i64 nchunks;        // chunks handed out (a prefix of the chunk sequence)
   i64 gathered;       // nnz of the sampled fibers
   i64 n_fib;          // nonempty sampled fibers
+  i64 n_rnd_rows;     // distinct random rows (set when the sampled rows are listed)
   double p_det;
   double tau_eff;     // 1.0 when the enumeration was skipped or capped
   int flags;
@@ -82,6 +84,16 @@ struct __attribute__((aligned(16))) FiberSlot {
   unsigned len;
 };
 #define CPAL_EMPTY_KEY (~0ull)
+
+// One entry of the table of an update's accepted random draws: KRP row ->
+// position of the draw that entered it (its slot carries the row) and the
+// number of its other draws.  An empty entry is {CPAL_EMPTY_KEY, ~0u, 0}; the
+// table is empty between updates.
+struct __attribute__((aligned(16))) DrawEntry {
+  u64 key;
+  unsigned first;
+  unsigned cnt;
+};
 
 // ------------------------------------------------------------ device helpers
 __device__ __forceinline__ void philox4x64_10(u64 c[4], u64 k0, u64 k1) {
@@ -150,8 +162,9 @@ __device__ __forceinline__ double prob_of(const OtherModes &om, u64 lin) {
   return p;
 }
 
-// Multiplicative hash of a fiber key into a table of 2^(64-shift) slots.
-__device__ __forceinline__ u64 fiber_hash(u64 key, int shift) {
+// Multiplicative hash of a key (fiber or KRP row) into a table of 2^(64-shift)
+// slots.
+__device__ __forceinline__ u64 key_hash(u64 key, int shift) {
   return (key * 0x9E3779B97F4A7C15ull) >> shift;
 }
 

@@ -28,7 +28,7 @@ __global__ void k_fullkey_insert(const int *__restrict__ coords, i64 nnz, FullMo
   for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (i64)gridDim.x * blockDim.x) {
     u64 key = 0;
     for (int m = 0; m < fm.D; ++m) key += (u64)(unsigned)coords[(i64)m * nnz + e] * fm.stride[m];
-    u64 h = fiber_hash(key, shift);
+    u64 h = key_hash(key, shift);
     for (;;) {
       const u64 old = atomicCAS(&set[h], CPAL_EMPTY_KEY, key);
       if (old == CPAL_EMPTY_KEY || old == key) break;
@@ -39,7 +39,7 @@ __global__ void k_fullkey_insert(const int *__restrict__ coords, i64 nnz, FullMo
 
 __device__ __forceinline__ bool fullkey_present(const u64 *__restrict__ set, u64 mask, int shift,
                                                 u64 key) {
-  u64 h = fiber_hash(key, shift);
+  u64 h = key_hash(key, shift);
   for (;;) {
     const u64 v = set[h];
     if (v == key) return true;

@@ -423,45 +423,92 @@ __global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, 
   }
 }
 
+// Finishes the entry of accepted draw `pos` of row `key` in the draw table
+// (linear probing from slot h, whose compare-and-swap returned old).  The
+// draw that enters a row stores its position (its slot carries the row); a
+// later draw of the same row only counts itself as a repeat.  The table has
+// at least twice as many entries as draws, so a free entry exists.
+__device__ __forceinline__ void draw_insert_from(DrawEntry *tab, u64 mask, u64 key, u64 h,
+                                                 u64 old, unsigned pos) {
+  for (u64 probe = 0; old != CPAL_EMPTY_KEY && old != key && probe < mask; ++probe) {
+    h = (h + 1) & mask;
+    old = atomicCAS(&tab[h].key, CPAL_EMPTY_KEY, key);
+  }
+  if (old == CPAL_EMPTY_KEY) tab[h].first = pos;
+  else if (old == key) atomicAdd(&tab[h].cnt, 1u);
+}
+
+#define CMP_WINS 64   // windows of 256 chunks whose owned chunk is kept at once
+
 // The first s_rnd accepted draws in draw order: every block scans the chunk
 // counts (a prefix of the chunk sequence) itself, window by window of 256
-// chunks, and copies the accepted rows of the chunks it owns to their place;
-// block 0 also records the number of rows used and the draw count (index of
-// the s_rnd-th accepted draw + 1).  Launched with 256 threads.
+// chunks, and keeps where the one chunk of each window that it owns (chunk
+// blockIdx.x of the window; launched with 256 blocks of 256 threads) goes;
+// then it copies the accepted rows of its chunks to their place and enters
+// them into the draw table, four chunks at a time with their first
+// compare-and-swaps in flight together.  The table so holds, per row, the
+// position of one of its draws and its number of further draws: the repeats
+// of Sec. 4.1 without sorting the draws (which draw represents the row
+// depends on timing; the row, its count and weight do not).  Block 0 also records the number of rows used and the
+// draw count (index of the s_rnd-th accepted draw + 1).
 __global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__restrict__ buf,
                                                  const unsigned *__restrict__ chunk_cnt,
                                                  const unsigned short *__restrict__ bpos,
-                                                 u64 *__restrict__ keys) {
+                                                 u64 *__restrict__ keys, DrawEntry *tab,
+                                                 u64 tmask, int tshift) {
   __shared__ i64 sh_draws;
   __shared__ u64 soff[256];
   __shared__ unsigned scnt[256];
+  __shared__ u64 own_off[CMP_WINS];
+  __shared__ unsigned own_cnt[CMP_WINS];
   const int tid = threadIdx.x;
   const i64 s_rnd = st->s_rnd;
   const i64 max_draws = max_draws_of(s_rnd);
   const u64 max_chunks = (u64)((max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK);
   const u64 Q = min(st->chunk_next, max_chunks);
+  const u64 nwin = (Q + 255) / 256;
   if (tid == 0) sh_draws = -1;
   u64 carry = 0;
-  for (u64 b0 = 0; b0 < Q; b0 += 256) {
-    const u64 q = b0 + tid;
-    const unsigned v = q < Q ? chunk_cnt[q] : 0u;
-    u64 tot;
-    const u64 off = carry + block_excl_scan<u64>((u64)v, &tot);
-    soff[tid] = off;
-    scnt[tid] = v;
-    if (q < Q && s_rnd > 0 && off <= (u64)(s_rnd - 1) && (u64)(s_rnd - 1) < off + v)
-      sh_draws = (i64)q * CPAL_KRP_CHUNK + bpos[q * CPAL_KRP_CHUNK + (s_rnd - 1 - off)] + 1;
-    __syncthreads();
-    // chunks of this window owned by this block (q = b0 + j, j = blockIdx mod grid)
-    for (u64 j = blockIdx.x; j < 256 && b0 + j < Q; j += gridDim.x) {
-      const u64 o = soff[j];
-      if (o >= (u64)s_rnd) continue;
-      const u64 cnt = min((u64)scnt[j], (u64)s_rnd - o);
-      const u64 *src = buf + (b0 + j) * CPAL_KRP_CHUNK;
-      for (u64 i = tid; i < cnt; i += 256) keys[o + i] = src[i];
+  for (u64 wb = 0; wb < nwin; wb += CMP_WINS) {
+    const int nw = (int)min((u64)CMP_WINS, nwin - wb);
+    for (int wi = 0; wi < nw; ++wi) {
+      const u64 b0 = (wb + wi) * 256;
+      const u64 q = b0 + tid;
+      const unsigned v = q < Q ? chunk_cnt[q] : 0u;
+      u64 tot;
+      const u64 off = carry + block_excl_scan<u64>((u64)v, &tot);
+      if (q < Q && s_rnd > 0 && off <= (u64)(s_rnd - 1) && (u64)(s_rnd - 1) < off + v)
+        sh_draws = (i64)q * CPAL_KRP_CHUNK + bpos[q * CPAL_KRP_CHUNK + (s_rnd - 1 - off)] + 1;
+      if (tid == (int)blockIdx.x) {
+        // rows of the owned chunk that fall among the first s_rnd
+        own_off[wi] = off;
+        own_cnt[wi] = off < (u64)s_rnd ? (unsigned)min((u64)v, (u64)s_rnd - off) : 0u;
+      }
+      carry += tot;
     }
     __syncthreads();
-    carry += tot;
+    for (int w0 = 0; w0 < nw; w0 += 4) {
+      u64 key[4], h[4], old[4];
+      unsigned pos[4];
+      bool has[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int wi = w0 + r;
+        has[r] = wi < nw && (unsigned)tid < own_cnt[wi];
+        if (has[r]) {
+          const u64 q = (wb + wi) * 256 + blockIdx.x;
+          key[r] = buf[q * CPAL_KRP_CHUNK + tid];
+          pos[r] = (unsigned)(own_off[wi] + tid);
+          keys[pos[r]] = key[r];
+          h[r] = key_hash(key[r], tshift);
+          old[r] = atomicCAS(&tab[h[r]].key, CPAL_EMPTY_KEY, key[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (has[r]) draw_insert_from(tab, tmask, key[r], h[r], old[r], pos[r]);
+    }
+    __syncthreads();   // own_off / own_cnt are refilled by the next batch
   }
   __syncthreads();
   if (blockIdx.x == 0 && tid == 0) {
@@ -509,8 +556,21 @@ void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u6
                      buf, bpos, chunk_cnt, stage_n);
 }
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
-                    const unsigned short *bpos, u64 *keys, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_compact, dim3(grid), dim3(256), 0, s, st, buf, chunk_cnt, bpos, keys);
+                    const unsigned short *bpos, u64 *keys, DrawEntry *tab, u64 tmask, int tshift,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(256), dim3(256), 0, s, st, buf, chunk_cnt, bpos, keys, tab,
+                     tmask, tshift);
+}
+
+__global__ void k_draw_table_clear(DrawEntry *__restrict__ tab, u64 n) {
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+    tab[i] = DrawEntry{CPAL_EMPTY_KEY, ~0u, 0u};
+}
+
+void launch_draw_table_clear(DrawEntry *tab, u64 n, hipStream_t s) {
+  const u64 g = std::min<u64>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_draw_table_clear, dim3((unsigned)std::max<u64>(g, 1)), dim3(256), 0, s, tab,
+                     n);
 }
 
 }  // namespace cpal

@@ -1,0 +1,115 @@
+// Solve of the sketched normal equations, A_k = M G_s^{-1} (eq. (1.2)), the
+// update statistics and the FP32 factor mirror.
+#include "cpal_common.h"
+
+namespace cpal {
+
+static int grid_for(i64 n, int blk, int maxg = 8192) {
+  i64 g = (n + blk - 1) / blk;
+  if (g < 1) g = 1;
+  if (g > maxg) g = maxg;
+  return (int)g;
+}
+
+// ------------------------------------------------------------------- solve --
+// A_k(i,:) = M(i,:) G_s^{-1}: forward substitution with the Cholesky factor
+// (subtractions in ascending order), back substitution (right-looking:
+// subtractions in descending order), or the pseudo-inverse from the
+// eigendecomposition.  Lanes = columns, LPN lanes per row (R <= LPN); FP64
+// throughout.  Skipped when the update hit a state error.  256 threads.
+template <typename T, int LPN>
+__global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, int R,
+                                                    const T *__restrict__ M, int ncopies,
+                                                    const Decomp *__restrict__ dc,
+                                                    double *__restrict__ A,
+                                                    float *__restrict__ A32) {
+  extern __shared__ double sL[];   // R*R factor (L, or V)
+  if (st->flags & CPAL_FLAG_STATE) return;
+  const int pinv = dc->pinv;
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = pinv ? dc->V[e] : dc->L[e];
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const int c = (tid & 63) % LPN;
+  const i64 row = ((i64)blockIdx.x * blockDim.x + tid) / LPN;
+  if (row >= n) return;   // uniform per lane group
+  const bool col = c < R;
+  const int cl = col ? c : R - 1;
+  double v = 0.0;
+  if (col)
+    for (int x = 0; x < ncopies; ++x) v = v + (double)M[(i64)x * n * R + row * R + c];
+  if (!pinv) {
+    for (int j = 0; j < R; ++j) {
+      const double yj = group_value<LPN>(v, j) / sL[j * R + j];
+      if (c == j) v = yj;
+      else if (c > j && col) v = v - sL[c * R + j] * yj;
+    }
+    for (int j = R - 1; j >= 0; --j) {
+      const double xj = group_value<LPN>(v, j) / sL[j * R + j];
+      if (c == j) v = xj;
+      else if (c < j) v = v - sL[j * R + c] * xj;
+    }
+  } else {
+    // x = sum over kept j of ((v_j . m) / lambda_j) v_j
+    const double etol = dc->etol;
+    double t = 0.0;
+    for (int p = 0; p < R; ++p) t = t + sL[p * R + cl] * group_value<LPN>(v, p);
+    const double lam = dc->lam[cl];
+    const double cj = lam > etol ? t / lam : 0.0;
+    double x = 0.0;
+    for (int j = 0; j < R; ++j) {
+      const double cv = group_value<LPN>(cj, j);
+      if (dc->lam[j] > etol) x = x + cv * sL[cl * R + j];
+    }
+    v = x;
+  }
+  if (col) {
+    A[row * R + c] = v;
+    A32[row * R + c] = (float)v;
+  }
+}
+
+__global__ void k_stats(const DevState *st, int k, int D, cpal_mode_stats *out) {
+  int fl = st->flags;
+  for (int m = 0; m < D; ++m)
+    if (m != k && st->lev_pinv[m]) fl |= CPAL_FLAG_PINV;
+  out->s_det = st->s_det;
+  out->s_rnd = st->s_rnd_used;
+  out->s_bar = st->s_bar;
+  out->draws = st->draws;
+  out->gathered_nnz = st->gathered;
+  out->p_det = st->p_det;
+  out->flags = fl;
+  out->pad = 0;
+}
+
+__global__ void k_to_f32(const double *__restrict__ a, float *__restrict__ b, i64 n) {
+  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, int ncopies,
+                       const Decomp *dc, double *A, float *A32, hipStream_t s) {
+  const int lpn = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
+  const int nb = (int)((n * lpn + 255) / 256);
+  const size_t sh = sizeof(double) * (size_t)R * R;
+  if (f64) {
+    auto k = lpn == 16 ? k_solve_rows<double, 16> : lpn == 32 ? k_solve_rows<double, 32>
+                                                              : k_solve_rows<double, 64>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const double *)M, ncopies, dc, A,
+                       A32);
+  } else {
+    auto k = lpn == 16 ? k_solve_rows<float, 16> : lpn == 32 ? k_solve_rows<float, 32>
+                                                             : k_solve_rows<float, 64>;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const float *)M, ncopies, dc, A,
+                       A32);
+  }
+}
+
+void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1), 0, s, st, k, D, out);
+}
+
+void launch_to_f32(const double *a, float *b, i64 n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, n);
+}
+}  // namespace cpal
