@@ -202,6 +202,95 @@ __device__ __forceinline__ bool chol_regs(const double *S, double *L, int R, dou
   return ok;
 }
 
+// Branch-free register Cholesky for R <= RM: lane i holds row i of S in
+// g[0..RM) with every entry past R (rows and columns) zero, and receives its
+// row of L in lcol.  The padded columns see zero pivots and zero updates, so
+// every entry of the R x R factor gets the same operations in the same order
+// as chol_right (bit for bit), while the straight-line code lets column j's
+// trailing update overlap the square root and divisions of column j + 1.
+// Returns false when a pivot of the first R columns is not above tol.  One
+// wavefront.
+template <int RM>
+__device__ __forceinline__ bool chol_pad(double (&g)[RM], double (&lcol)[RM], int R, double tol) {
+  const int lane = threadIdx.x & 63;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    const double piv = lane_value(g[j], j);
+    ok = ok & ((j >= R) | (piv > tol));
+    const double ljj = sqrt(piv);
+    const double q = g[j] / ljj;
+    const double lij = (lane == j) ? ljj : ((lane > j && lane < R) ? q : 0.0);
+    lcol[j] = lij;
+#pragma unroll
+    for (int l = j + 1; l < RM; ++l) g[l] = g[l] - lij * lane_value(lij, l);
+  }
+  return ok;
+}
+
+// Pair sums of the block partials in block order (pair p of lane + 64 k),
+// straight from global memory.  Returns them packed in sG.
+template <int KP>
+__device__ __forceinline__ void pair_sums(const double *__restrict__ part, int nblk, int np,
+                                          double *sG) {
+  const int lane = threadIdx.x & 63;
+  double acc[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) acc[k] = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    const double *pb = part + (i64)b * np;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const int p = lane + 64 * k;
+      if (p < np) acc[k] = acc[k] + pb[p];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int p = lane + 64 * k;
+    if (p < np) sG[p] = acc[k];
+  }
+}
+
+// k_decomp for R <= RM <= 32 (one wavefront): pair sums, lane i's row of G
+// from the packed sums, the pivot tolerance from the diagonal, chol_pad, and
+// the factor written from registers.  On a failed pivot G is unpacked into
+// the shared square matrix Gsq for the eigen-decomposition; returns whether
+// the Cholesky succeeded.
+template <int RM>
+__device__ bool decomp_regs(const double *__restrict__ part, int nblk, int R,
+                            Decomp *__restrict__ out, double *sG, double *Gsq) {
+  const int lane = threadIdx.x & 63;
+  const int np = R * (R + 1) / 2;
+  pair_sums<(RM * (RM + 1) / 2 + 63) / 64>(part, nblk, np, sG);
+  __syncthreads();
+  double g[RM];
+#pragma unroll
+  for (int l = 0; l < RM; ++l) {
+    const int a = min(lane, l), c = max(lane, l);
+    g[l] = (lane < R && l < R) ? sG[a * R - (a * (a - 1)) / 2 + (c - a)] : 0.0;
+  }
+  double md = lane < R ? sG[lane * R - (lane * (lane - 1)) / 2] : 0.0;
+  for (int off = 32; off > 0; off >>= 1) md = fmax(md, __shfl_xor(md, off, 64));
+  const double tol = ((double)R * 0x1p-52) * md;
+  double lcol[RM];
+  const bool ok = chol_pad<RM>(g, lcol, R, tol);
+  if (ok) {
+    if (lane < R)
+#pragma unroll
+      for (int j = 0; j < RM; ++j)
+        if (j < R) out->L[lane * R + j] = lcol[j];
+  } else {
+    for (int e = lane; e < R * R; e += 64) {
+      const int r = e / R, q = e - r * R;
+      const int a = min(r, q), c = max(r, q);
+      Gsq[e] = sG[a * R - (a * (a - 1)) / 2 + (c - a)];
+    }
+    __syncthreads();
+  }
+  return ok;
+}
+
 // Leverage of a factor with fewer rows than columns (n < R <= 64): if A A^T
 // (n x n, each entry summed over the R columns in ascending order) passes the
 // Cholesky pivot test, A has full row rank, range(A) = R^n and every
@@ -264,6 +353,29 @@ __global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, 
   const int lane = threadIdx.x;
   if (nrows_dev) nblk = (int)((*nrows_dev + rows_per_blk - 1) / rows_per_blk);
   const int np = R * (R + 1) / 2;
+  if (R <= 32) {
+    bool ok;
+    if (R <= 8) ok = decomp_regs<8>(part, nblk, R, out, slab, G);
+    else if (R <= 16) ok = decomp_regs<16>(part, nblk, R, out, slab, G);
+    else if (R <= 24) ok = decomp_regs<24>(part, nblk, R, out, slab, G);
+    else ok = decomp_regs<32>(part, nblk, R, out, slab, G);
+    if (ok) {
+      if (lane == 0) {
+        out->pinv = 0;
+        out->R = R;
+        if (flag_store) *flag_store = 0;
+      }
+    } else {
+      jacobi_wave(G, L, R, out);
+      if (lane == 0) {
+        out->pinv = 1;
+        out->R = R;
+        if (flag_or) atomicOr(flag_or, CPAL_FLAG_PINV);
+        if (flag_store) *flag_store = 1;
+      }
+    }
+    return;
+  }
   for (int p = lane; p < np; p += 64) G[p] = 0.0;   // running sums, packed by pair
   const int per = max(1, DECOMP_SLAB / np);          // blocks per slab
   for (int b0 = 0; b0 < nblk; b0 += per) {

@@ -27,7 +27,7 @@ namespace cpal {
 // Blocks past the slots only clear their share of M.  DD = number of other modes
 // (0: any, runtime loops).
 #define ROWS_BLK 256
-#define ROWS_UNR 4
+#define ROWS_UNR 8
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Phase 3 for NT = ceil(R/16) column blocks.  Wave w multiplies the rows
@@ -45,6 +45,7 @@ __device__ __forceinline__ void gs_tiles(const double *sz, const double *som, in
 #pragma unroll
   for (int t = 0; t < NTL; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
   const int kb = wid * (ROWS_BLK / 4), ke = min(rows, kb + ROWS_BLK / 4);
+#pragma unroll 4
   for (int k0 = kb; k0 < ke; k0 += 4) {
     const int k = k0 + k4;
     const bool ok = k < ke;
@@ -110,73 +111,80 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
   const i64 base = (i64)blockIdx.x * ROWS_BLK;
   if (base >= n_slots) return;   // uniform per block
   const int rows = (int)min((i64)ROWS_BLK, n_slots - base);
-  // phase 1
+  // phase 1: the first draw-table probe, the first fiber probe and the q
+  // loads are all issued before any of them is used
   double omj = 0.0;
   bool active = false;
+  unsigned len = 0;
   if (tid < rows) {
     const i64 j = base + tid;
-    u64 lin;
-    double wj = 0.0;
-    bool rnd = false;
-    u64 cnt = 0;
+    const bool rnd = j >= s_det;
+    const i64 i = j - s_det;   // accepted draw of a random slot
+    const u64 lin = rnd ? dkeys[i] : samp_idx[j];
+    u64 hd = key_hash(lin, tshift), hf = key_hash(lin, hshift);
+    DrawEntry e{lin, 0u, 0u};
+    if (rnd) e = tab[hd];
+    FiberSlot sl = slots[hf];
+    constexpr int MO = CPAL_MAXORDER - 1;
+    unsigned ix[MO];
+    double qv[MO];
+    u64 rem = lin;
+#pragma unroll
+    for (int u = 0; u < MO; ++u) {
+      ix[u] = 0;
+      if (u < d) {
+        u64 iu;
+        rem = div_rcp(rem, (u64)om.n[u], om.rcp[u], &iu);
+        ix[u] = (unsigned)iu;
+        sim[u][tid] = ix[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < MO; ++u) qv[u] = (rnd && u < d) ? om.q[u][ix[u]] : 1.0;
+    // the row's table entry says whether this draw carries the row and how
+    // many draws it has
+    u64 cnt = 1;
     active = true;
-    if (j < s_det) {
-      lin = samp_idx[j];
-    } else {
-      // slot s_det + i: accepted draw i; the row's table entry says whether
-      // this draw carries the row and how many draws it has
-      const i64 i = j - s_det;
-      lin = dkeys[i];
-      rnd = true;
-      u64 h = key_hash(lin, tshift);
-      DrawEntry e = tab[h];
+    if (rnd) {
       for (u64 probe = 0; e.key != lin && e.key != CPAL_EMPTY_KEY && probe < tmask; ++probe) {
-        h = (h + 1) & tmask;
-        e = tab[h];
+        hd = (hd + 1) & tmask;
+        e = tab[hd];
       }
       active = e.key == lin && e.first == (unsigned)i;
       cnt = 1 + (u64)e.cnt;
-      tpos[i] = active ? (unsigned)h : ~0u;
+      tpos[i] = active ? (unsigned)hd : ~0u;
     }
-    u64 rem = lin;
-    double p = 0.0;
-    for (int u = 0; u < d; ++u) {
-      u64 i;
-      rem = div_rcp(rem, (u64)om.n[u], om.rcp[u], &i);
-      sim[u][tid] = (unsigned)i;
-      if (rnd) {
-        const double qv = om.q[u][i];
-        p = (u == 0) ? qv : p * qv;
-      }
+    unsigned off = 0;
+    for (;;) {
+      if (sl.key == lin) { off = sl.off; len = sl.len; break; }
+      if (sl.key == CPAL_EMPTY_KEY) break;
+      hf = (hf + 1) & hmask;
+      sl = slots[hf];
     }
+    if (!active) { off = 0; len = 0; }
+    double wj = 0.0;
     if (!rnd) {
       omj = 1.0;
       wj = 1.0;
     } else if (active) {
+      double p = qv[0];
+#pragma unroll
+      for (int u = 1; u < MO; ++u)
+        if (u < d) p = p * qv[u];
       omj = ((double)cnt * (1.0 - p_det)) / ((double)s_used * p);
       wj = sqrt(omj);
     }
     samp_idx[j] = lin;
     samp_om[j] = omj;
     samp_w[j] = wj;
-    unsigned off = 0, len = 0;
-    if (active) {
-      u64 h = key_hash(lin, hshift);
-      for (;;) {
-        const FiberSlot sl = slots[h];
-        if (sl.key == lin) { off = sl.off; len = sl.len; break; }
-        if (sl.key == CPAL_EMPTY_KEY) break;
-        h = (h + 1) & hmask;
-      }
-    }
     foff[j] = off;
     flen[j] = len;
   }
   {   // the workgroup's rows of the sampled system (active slots), gathered
       // length and nonempty-fiber count, totalled by the gather preparation
     const unsigned na = (unsigned)__popcll(__ballot(active));
-    const u64 ln = wave_sum((u64)(tid < rows ? flen[base + tid] : 0u));
-    const unsigned nf = (unsigned)__popcll(__ballot(tid < rows && flen[base + tid] > 0u));
+    const u64 ln = wave_sum((u64)len);
+    const unsigned nf = (unsigned)__popcll(__ballot(len > 0u));
     __shared__ unsigned wact[ROWS_BLK / 64], wnf[ROWS_BLK / 64];
     __shared__ u64 wln[ROWS_BLK / 64];
     if ((tid & 63) == 0) { wact[tid >> 6] = na; wnf[tid >> 6] = nf; wln[tid >> 6] = ln; }

@@ -40,12 +40,18 @@ __device__ __forceinline__ T block_sum(T v) {
   return r;
 }
 
+#define DET_STAGE 8192
 // Reset of the per-update state, maxima alpha_m, candidate lists (Sec. 5.3):
 // row i of mode o_t is a candidate iff the product with every other mode at
-// its maximum exceeds tau.  One block of 1024 threads.
+// its maximum exceeds tau.  One block of 1024 threads; the other modes' q
+// are read once (into shared memory, at the candidate-list offsets, when
+// those end within DET_STAGE entries).
 __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u64 cap,
                                                    DevState *st, int *__restrict__ cand) {
-  const int tid = threadIdx.x;
+  __shared__ double sq[DET_STAGE];
+  __shared__ double red[16][CPAL_MAXORDER];
+  __shared__ double alpha[CPAL_MAXORDER];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) {
     st->det_count = 0; st->combos = 0; st->s_det = 0; st->s_rnd = 0; st->s_rnd_used = 0;
     st->s_bar = 0; st->n_slots = 0; st->draws = 0; st->chunk_next = 0; st->accepted = 0;
@@ -53,20 +59,38 @@ __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u6
     for (int u = 0; u < CPAL_MAXORDER; ++u) st->ncand[u] = 0;
   }
   // a probability vector with no mass cannot be sampled: the update is void
-  __shared__ int bad;
-  if (tid == 0) {
-    bad = 0;
-    for (int u = 0; u < om.d; ++u) bad |= om.C[u][om.n[u] - 1] == 0;
-    if (bad) st->flags |= CPAL_FLAG_STATE;
+  int bad0 = 0;
+  if (tid == 0)
+    for (int u = 0; u < om.d; ++u) bad0 |= om.C[u][om.n[u] - 1] == 0;
+  const int bad = __syncthreads_or(bad0);
+  if (bad) {
+    if (tid == 0) st->flags |= CPAL_FLAG_STATE;
+    return;
+  }
+  if (!(tau < 1.0)) return;
+  i64 lim = 0;   // staged at the candidate-list offsets
+  for (int u = 0; u < om.d; ++u) lim = max(lim, om.cand_off[u] + om.n[u]);
+  const bool staged = lim <= DET_STAGE;
+  // maxima alpha_u (and the staging copy)
+  double m[CPAL_MAXORDER];
+#pragma unroll
+  for (int u = 0; u < CPAL_MAXORDER; ++u) {
+    m[u] = 0.0;
+    if (u < om.d) {
+      for (i64 i = tid; i < om.n[u]; i += blockDim.x) {
+        const double v = om.q[u][i];
+        if (staged) sq[om.cand_off[u] + i] = v;
+        m[u] = fmax(m[u], v);
+      }
+      for (int off = 32; off > 0; off >>= 1) m[u] = fmax(m[u], __shfl_xor(m[u], off, 64));
+      if (lane == 0) red[wid][u] = m[u];
+    }
   }
   __syncthreads();
-  if (bad || !(tau < 1.0)) return;
-  __shared__ double alpha[CPAL_MAXORDER];
-  for (int u = 0; u < om.d; ++u) {
-    double m = 0.0;
-    for (i64 i = tid; i < om.n[u]; i += blockDim.x) m = fmax(m, om.q[u][i]);
-    m = block_max_d(m);
-    if (tid == 0) alpha[u] = m;
+  if (tid < om.d) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w][tid]);
+    alpha[tid] = r;
   }
   __syncthreads();
   double combos = 1.0;
@@ -74,13 +98,14 @@ __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u6
   for (int t = 0; t < om.d; ++t) {
     const i64 n = om.n[t];
     const double *q = om.q[t];
+    const double *qs = sq + om.cand_off[t];
     int *out = cand + om.cand_off[t];
     u64 count = 0;
     for (i64 base = 0; base < n; base += blockDim.x) {
       const i64 i = base + tid;
       unsigned pred = 0;
       if (i < n) {
-        const double qi = q[i];
+        const double qi = staged ? qs[i] : q[i];
         double b = (t == 0) ? qi : alpha[0];
         for (int u = 1; u < om.d; ++u) b = b * ((u == t) ? qi : alpha[u]);
         pred = b > tau;
@@ -186,9 +211,24 @@ __global__ void __launch_bounds__(256) k_det_scatter(OtherModes om, double tau, 
   }
 }
 
-#define DET_STAGE 8192
+// Sizes of the sampled system once p_det (tot) is known.
+__device__ __forceinline__ void det_finish_state(DevState *st, i64 n, i64 s, double tot) {
+  st->s_det = n;
+  st->p_det = tot;
+  i64 s_rnd = s - n;
+  if (s_rnd > 0 && !(1.0 - tot > 0x1p-40)) {
+    s_rnd = 0;
+    st->flags |= CPAL_FLAG_PDET_ONE;
+  }
+  st->s_rnd = s_rnd;
+  st->chunk_next = 0;
+  st->accepted = 0;
+}
+
 // Deterministic rows: truncation to the s most probable when needed, output
-// to samp_idx[0..s_det), p_det, s_rnd.  One block of 1024 threads.
+// to samp_idx[0..s_det), p_det, s_rnd.  One block of 1024 threads.  Fewer
+// than s rows that fit in shared memory (the usual case) stay there: p, the
+// partial sums and the total never leave the block.
 __global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st,
                                                      const u64 *__restrict__ det_keys,
                                                      double *__restrict__ det_p,
@@ -204,6 +244,30 @@ __global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st
   const u64 cnt = st->det_count;
   i64 n = (i64)min(cnt, det_cap);
   if (tid == 0 && cnt > det_cap) st->flags |= CPAL_FLAG_OVERFLOW;
+  __shared__ double sp[DET_STAGE];
+  __shared__ double spart[DET_STAGE / 256];
+  if (n < s && n <= DET_STAGE) {
+    for (i64 i = tid; i < n; i += blockDim.x) {
+      const u64 key = det_keys[i];
+      samp_idx[i] = key;
+      sp[i] = prob_of(om, key);
+    }
+    __syncthreads();
+    const i64 nb = (n + 255) / 256;
+    if (tid < nb) {
+      double part = 0.0;
+      const i64 e = min(n, (i64)(tid + 1) * 256);
+      for (i64 i = (i64)tid * 256; i < e; ++i) part = part + sp[i];
+      spart[tid] = part;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (i64 b = 0; b < nb; ++b) tot = tot + spart[b];
+      det_finish_state(st, n, s, tot);
+    }
+    return;
+  }
   for (i64 i = tid; i < n; i += blockDim.x) det_p[i] = prob_of(om, det_keys[i]);
   __syncthreads();
   if (n >= s) {
@@ -249,7 +313,6 @@ __global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st
   __syncthreads();
   // p_det in blocks of 256 (ascending linear index), partials summed in
   // order; the probabilities are staged in shared memory when they fit
-  __shared__ double sp[DET_STAGE];
   const i64 nb = (n + 255) / 256;
   const bool staged = n <= DET_STAGE;
   if (staged)
@@ -270,16 +333,7 @@ __global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st
   if (tid == 0) {
     double tot = 0.0;
     for (i64 b = 0; b < nb; ++b) tot = tot + psum[b];
-    st->s_det = n;
-    st->p_det = tot;
-    i64 s_rnd = s - n;
-    if (s_rnd > 0 && !(1.0 - tot > 0x1p-40)) {
-      s_rnd = 0;
-      st->flags |= CPAL_FLAG_PDET_ONE;
-    }
-    st->s_rnd = s_rnd;
-    st->chunk_next = 0;
-    st->accepted = 0;
+    det_finish_state(st, n, s, tot);
   }
   (void)keep;
 }
