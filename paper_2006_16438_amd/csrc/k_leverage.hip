@@ -237,6 +237,7 @@ __device__ __forceinline__ void pair_sums(const double *__restrict__ part, int n
   double acc[KP];
 #pragma unroll
   for (int k = 0; k < KP; ++k) acc[k] = 0.0;
+#pragma unroll 4
   for (int b = 0; b < nblk; ++b) {
     const double *pb = part + (i64)b * np;
 #pragma unroll

@@ -59,15 +59,10 @@ __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u6
     for (int u = 0; u < CPAL_MAXORDER; ++u) st->ncand[u] = 0;
   }
   // a probability vector with no mass cannot be sampled: the update is void
+  // (checked at the first barrier, so its loads overlap the staging below)
   int bad0 = 0;
   if (tid == 0)
     for (int u = 0; u < om.d; ++u) bad0 |= om.C[u][om.n[u] - 1] == 0;
-  const int bad = __syncthreads_or(bad0);
-  if (bad) {
-    if (tid == 0) st->flags |= CPAL_FLAG_STATE;
-    return;
-  }
-  if (!(tau < 1.0)) return;
   i64 lim = 0;   // staged at the candidate-list offsets
   for (int u = 0; u < om.d; ++u) lim = max(lim, om.cand_off[u] + om.n[u]);
   const bool staged = lim <= DET_STAGE;
@@ -86,7 +81,11 @@ __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u6
       if (lane == 0) red[wid][u] = m[u];
     }
   }
-  __syncthreads();
+  if (__syncthreads_or(bad0)) {
+    if (tid == 0) st->flags |= CPAL_FLAG_STATE;
+    return;
+  }
+  if (!(tau < 1.0)) return;
   if (tid < om.d) {
     double r = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w][tid]);
@@ -257,6 +256,7 @@ __global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st
     if (tid < nb) {
       double part = 0.0;
       const i64 e = min(n, (i64)(tid + 1) * 256);
+#pragma unroll 16
       for (i64 i = (i64)tid * 256; i < e; ++i) part = part + sp[i];
       spart[tid] = part;
     }
@@ -361,18 +361,24 @@ __device__ __forceinline__ i64 draw_need_chunks(const DevState *st, i64 s_rnd) {
 struct DrawModes {
   u64 W[CPAL_MAXORDER];
   const u64 *C[CPAL_MAXORDER];
+  bool staged;
 };
 
+template <int DD>
 __device__ __forceinline__ void draw_setup(const OtherModes &om, int stage_n, unsigned char *dsm,
                                            DrawModes &dm) {
-  for (int u = 0; u < om.d; ++u) {
+  const int d = DD > 0 ? DD : om.d;
+#pragma unroll
+  for (int u = 0; u < d; ++u) {
     dm.W[u] = om.C[u][om.n[u] - 1];
     dm.C[u] = om.C[u];
   }
+  dm.staged = stage_n > 0;
   if (stage_n > 0) {   // block-uniform: every thread reaches the barrier below
     u64 *sC = (u64 *)dsm;
     int off = 0;
-    for (int u = 0; u < om.d; ++u) {
+#pragma unroll
+    for (int u = 0; u < d; ++u) {
       for (int i = threadIdx.x; i < om.n[u]; i += blockDim.x) sC[off + i] = om.C[u][i];
       dm.C[u] = sC + off;
       off += (int)om.n[u];
@@ -382,6 +388,8 @@ __device__ __forceinline__ void draw_setup(const OtherModes &om, int stage_n, un
 }
 
 // Draws of chunk c; returns the chunk's accepted count (block-uniform).
+// DD = number of other modes (0: any, runtime loop).
+template <int DD>
 __device__ __forceinline__ unsigned draw_chunk(const OtherModes &om, const DrawModes &dm, u64 c,
                                                double tau, i64 max_draws, u64 seed, u64 stream_id,
                                                u64 t, u64 *__restrict__ buf,
@@ -391,12 +399,18 @@ __device__ __forceinline__ unsigned draw_chunk(const OtherModes &om, const DrawM
   const i64 j = (i64)c * CPAL_KRP_CHUNK + tid;
   u64 lin = 0;
   double p = 0.0;
-  for (int u = 0; u < om.d; ++u) {
+  const int d = DD > 0 ? DD : om.d;
+#pragma unroll
+  for (int u = 0; u < d; ++u) {
     u64 ctr[4] = {(u64)j, (u64)om.mode[u] | ((u64)om.k << 8), t, 0ull};
     philox4x64_10(ctr, seed, stream_id);
     const u64 x = scale128(ctr[0], ctr[1], dm.W[u]);
     const i64 i = upper_bound_u64(dm.C[u], om.n[u], x);
-    const double qv = om.q[u][i];
+    // q_i = w_i / W, recomputed from the CDF when it is staged in shared
+    // memory (the same operations, so the same value)
+    const double qv = dm.staged ? (double)(dm.C[u][i] - (i > 0 ? dm.C[u][i - 1] : 0ull)) /
+                                      (double)dm.W[u]
+                                : om.q[u][i];
     p = (u == 0) ? qv : p * qv;
     lin += (u64)i * om.stride[u];
   }
@@ -411,6 +425,7 @@ __device__ __forceinline__ unsigned draw_chunk(const OtherModes &om, const DrawM
   return tot;
 }
 
+template <int DD>
 __global__ void __launch_bounds__(256) k_draw_first(OtherModes om, DevState *st, u64 seed,
                                                     u64 stream_id, u64 t, u64 *__restrict__ buf,
                                                     unsigned short *__restrict__ bpos,
@@ -428,11 +443,12 @@ __global__ void __launch_bounds__(256) k_draw_first(OtherModes om, DevState *st,
   }
   if ((i64)blockIdx.x >= first) return;   // uniform per block
   DrawModes dm;
-  draw_setup(om, stage_n, dsm, dm);
-  draw_chunk(om, dm, blockIdx.x, st->tau_eff, max_draws, seed, stream_id, t, buf, bpos,
+  draw_setup<DD>(om, stage_n, dsm, dm);
+  draw_chunk<DD>(om, dm, blockIdx.x, st->tau_eff, max_draws, seed, stream_id, t, buf, bpos,
              chunk_cnt);
 }
 
+template <int DD>
 __global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, u64 seed,
                                                    u64 stream_id, u64 t, u64 *__restrict__ buf,
                                                    unsigned short *__restrict__ bpos,
@@ -456,7 +472,7 @@ __global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, 
   acc0 = ws[0] + ws[1] + ws[2] + ws[3];
   if ((i64)acc0 >= s_rnd || first >= max_chunks) return;   // uniform per block
   DrawModes dm;
-  draw_setup(om, stage_n, dsm, dm);
+  draw_setup<DD>(om, stage_n, dsm, dm);
   for (;;) {
     if (tid == 0) {
       const u64 acc = __hip_atomic_load(&st->accepted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -470,7 +486,7 @@ __global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, 
     }
     __syncthreads();
     if (stop) break;
-    const unsigned tot = draw_chunk(om, dm, sh_c, st->tau_eff, max_draws, seed, stream_id, t, buf,
+    const unsigned tot = draw_chunk<DD>(om, dm, sh_c, st->tau_eff, max_draws, seed, stream_id, t, buf,
                                     bpos, chunk_cnt);
     if (tid == 0) atomicAdd(&st->accepted, (u64)tot);
     __syncthreads();
@@ -604,10 +620,15 @@ void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u6
   for (int u = 0; u < om.d; ++u) tot += om.n[u];
   const int stage_n = tot <= 8192 ? (int)tot : 0;   // <= 64 KB of shared memory
   const size_t sh = (size_t)stage_n * sizeof(u64);
-  hipLaunchKernelGGL(k_draw_first, dim3(grid_first), dim3(256), sh, s, om, st, seed, stream_id, t,
-                     buf, bpos, chunk_cnt, stage_n);
-  hipLaunchKernelGGL(k_draw_more, dim3(grid_more), dim3(256), sh, s, om, st, seed, stream_id, t,
-                     buf, bpos, chunk_cnt, stage_n);
+  const int dd = om.d <= 4 ? om.d : 0;
+  auto kf = dd == 1 ? k_draw_first<1> : dd == 2 ? k_draw_first<2> : dd == 3 ? k_draw_first<3>
+          : dd == 4 ? k_draw_first<4> : k_draw_first<0>;
+  auto km = dd == 1 ? k_draw_more<1> : dd == 2 ? k_draw_more<2> : dd == 3 ? k_draw_more<3>
+          : dd == 4 ? k_draw_more<4> : k_draw_more<0>;
+  hipLaunchKernelGGL(kf, dim3(grid_first), dim3(256), sh, s, om, st, seed, stream_id, t, buf, bpos,
+                     chunk_cnt, stage_n);
+  hipLaunchKernelGGL(km, dim3(grid_more), dim3(256), sh, s, om, st, seed, stream_id, t, buf, bpos,
+                     chunk_cnt, stage_n);
 }
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
                     const unsigned short *bpos, u64 *keys, DrawEntry *tab, u64 tmask, int tshift,
