@@ -14,9 +14,11 @@ static int grid_for(i64 n, int blk, int maxg = 8192) {
 // ------------------------------------------------------------------- solve --
 // A_k(i,:) = M(i,:) G_s^{-1}: forward substitution with the Cholesky factor
 // (subtractions in ascending order), back substitution (right-looking:
-// subtractions in descending order), or the pseudo-inverse from the
-// eigendecomposition.  Lanes = columns, LPN lanes per row (R <= LPN); FP64
-// throughout.  Skipped when the update hit a state error.  256 threads.
+// subtractions in descending order), both multiplying by the reciprocals of
+// the pivots; or the pseudo-inverse from the eigendecomposition.  Lanes =
+// columns, LPN lanes per row (R <= LPN); FP64 throughout.  The rows of M
+// (the copies summed in copy order) are loaded before the factor is staged.
+// Skipped when the update hit a state error.  256 threads.
 template <typename T, int LPN>
 __global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, int R,
                                                     const T *__restrict__ M, int ncopies,
@@ -24,27 +26,40 @@ __global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, i
                                                     double *__restrict__ A,
                                                     float *__restrict__ A32) {
   extern __shared__ double sL[];   // R*R factor (L, or V)
+  __shared__ double rdiag[CPAL_MAXR];
   if (st->flags & CPAL_FLAG_STATE) return;
-  const int pinv = dc->pinv;
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) sL[e] = pinv ? dc->V[e] : dc->L[e];
-  __syncthreads();
   const int tid = threadIdx.x;
   const int c = (tid & 63) % LPN;
   const i64 row = ((i64)blockIdx.x * blockDim.x + tid) / LPN;
-  if (row >= n) return;   // uniform per lane group
+  const bool live = row < n;
   const bool col = c < R;
   const int cl = col ? c : R - 1;
+  T mv[CPAL_MCOPIES];
+#pragma unroll
+  for (int x = 0; x < CPAL_MCOPIES; ++x)
+    mv[x] = (live && col && x < ncopies) ? M[(i64)x * n * R + row * R + c] : T(0);
+  const int pinv = dc->pinv;
+  for (int e = tid; e < R * R; e += blockDim.x) {
+    const double lv = dc->L[e], vv = dc->V[e];
+    sL[e] = pinv ? vv : lv;
+  }
+  __syncthreads();
+  if (!pinv)
+    for (int jj = tid; jj < R; jj += blockDim.x) rdiag[jj] = 1.0 / sL[jj * R + jj];
+  __syncthreads();
+  if (!live) return;   // uniform per lane group
   double v = 0.0;
-  if (col)
-    for (int x = 0; x < ncopies; ++x) v = v + (double)M[(i64)x * n * R + row * R + c];
+#pragma unroll
+  for (int x = 0; x < CPAL_MCOPIES; ++x)
+    if (x < ncopies) v = v + (double)mv[x];
   if (!pinv) {
     for (int j = 0; j < R; ++j) {
-      const double yj = group_value<LPN>(v, j) / sL[j * R + j];
+      const double yj = group_value<LPN>(v, j) * rdiag[j];
       if (c == j) v = yj;
       else if (c > j && col) v = v - sL[c * R + j] * yj;
     }
     for (int j = R - 1; j >= 0; --j) {
-      const double xj = group_value<LPN>(v, j) / sL[j * R + j];
+      const double xj = group_value<LPN>(v, j) * rdiag[j];
       if (c == j) v = xj;
       else if (c < j) v = v - sL[j * R + c] * xj;
     }
