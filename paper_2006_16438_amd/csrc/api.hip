@@ -58,7 +58,8 @@ int rows_per_block();
 void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                    const unsigned *cidx, const uint2 *pairs, const int *ik, const double *v64,
                    const void *zhat, void *M, int ldz, int grid, hipStream_t s);
-void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, int ncopies,
+void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, int ldm,
+                       int ncopies,
                        const Decomp *dc, double *A, float *A32, hipStream_t s);
 void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s);
 void launch_to_f32(const double *a, float *b, i64 n, hipStream_t s);
@@ -447,7 +448,7 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     {
       i64 mcap = 0;
       for (int m = 0; m < c->D; ++m) mcap = std::max<i64>(mcap, m_copies(c->dims[m]) * c->dims[m]);
-      c->M = c->alloc<char>((size_t)mcap * R * tsz);
+      c->M = c->alloc<char>((size_t)mcap * c->ldz * tsz);   // rows padded to ldz
     }
     c->gram_tmp = c->alloc<double>(np);
     c->chunk_first = c->alloc<unsigned>(gather_chunks_cap(c->nnz));
@@ -603,7 +604,8 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
   launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->keys, c->dtab,
               c->dtab_n - 1, c->dtab_shift, c->tpos, md.slots, md.nslots - 1, md.hshift, c->zhat,
-              c->foff, c->flen, c->gpart, c->gp_len, c->gp_cnt, c->gp_act, c->M, m_copies(md.n) * md.n * R, c->ldz, s);
+              c->foff, c->flen, c->gpart, c->gp_len, c->gp_cnt, c->gp_act, c->M,
+              m_copies(md.n) * md.n * c->ldz, c->ldz, s);
   launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
                      c->coff, c->cidx, c->chunk_first, c->tpos, c->dtab, s);
   c->stage_end(CPAL_STAGE_ROWS, tb);
@@ -619,7 +621,8 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   tb = c->stage_begin(CPAL_STAGE_SOLVE);
   launch_decomp_dev(c->gpart, &c->st->n_slots, rows_per_block(), R, c->dc, &c->st->flags,
                     c->gram_tmp, s);
-  launch_solve_rows(c->f64, c->st, md.n, R, c->M, (int)m_copies(md.n), c->dc, md.A, md.A32, s);
+  launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->ldz, (int)m_copies(md.n), c->dc, md.A,
+                    md.A32, s);
   c->stage_end(CPAL_STAGE_SOLVE, tb);
   tb = c->stage_begin(CPAL_STAGE_LEVERAGE);
   refresh_leverage(c, k);

@@ -1,5 +1,8 @@
 // TnsrSamp and the sampled MTTKRP (Sec. 6.3, eq. (1.2)): every nonzero (i_k, x)
 // of sampled fiber j adds omega_j x z_j to M(i_k,:) (gather precision T).
+// M's rows have the padded stride ldz of the weighted KRP rows, so that a
+// row's adds touch whole aligned lines (one 128-byte line for R <= 32 in
+// FP32): atomic adds write through to memory line by line.
 #include "cpal_common.h"
 
 namespace cpal {
@@ -79,7 +82,7 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
       const T x_s = __shfl(x, sl, 64);
       const i64 z_s = __shfl(zr, sl, 64);
       const bool v_s = __shfl((int)valid, sl, 64) != 0;
-      if (v_s && col < R) unsafeAtomicAdd(&M[(i64)ik_s * R + col], x_s * zhat[z_s * ldz + col]);
+      if (v_s && col < R) unsafeAtomicAdd(&M[(i64)ik_s * ldz + col], x_s * zhat[z_s * ldz + col]);
     }
   }
 }
@@ -237,7 +240,7 @@ __device__ __forceinline__ void seg_reduce(const Get &get, int n, int R,
           const int r = (int)rr[b];
           if (r != cur) {
             if (first < 0) { first = cur; facc = acc; }
-            else if (c < R) unsafeAtomicAdd(&M[(i64)cur * R + c], acc);
+            else if (c < R) unsafeAtomicAdd(&M[(i64)cur * ldz + c], acc);
             cur = r;
             acc = T(0);
           }
@@ -259,13 +262,13 @@ __device__ __forceinline__ void seg_reduce(const Get &get, int n, int R,
       const int r = srow[sl];
       if (r < 0) continue;
       if (r != mr) {
-        if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * R + c], ma);
+        if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * ldz + c], ma);
         mr = r;
         ma = T(0);
       }
       ma += svec[sl][c];
     }
-    if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * R + c], ma);
+    if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * ldz + c], ma);
   }
 }
 
@@ -299,7 +302,7 @@ __global__ void __launch_bounds__(GT_THREADS) k_gather_seg(
   const i64 nf = st->n_fib;
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
   // this XCD's copy of M: the adds of workgroups on one XCD stay in its L2
-  T *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * R;
+  T *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * ldz;
   for (i64 ch = blockIdx.x; ch < nch; ch += gridDim.x) {
     const unsigned *keys = seg_load_sort<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz,
                                             ikbits, win, ka, kb, lx, lz, tab);

@@ -17,11 +17,13 @@ static int grid_for(i64 n, int blk, int maxg = 8192) {
 // subtractions in descending order), both multiplying by the reciprocals of
 // the pivots; or the pseudo-inverse from the eigendecomposition.  Lanes =
 // columns, LPN lanes per row (R <= LPN); FP64 throughout.  The rows of M
-// (the copies summed in copy order) are loaded before the factor is staged.
+// (row stride ldm; the copies summed in copy order) are loaded before the
+// factor is staged.
 // Skipped when the update hit a state error.  256 threads.
 template <typename T, int LPN>
 __global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, int R,
-                                                    const T *__restrict__ M, int ncopies,
+                                                    const T *__restrict__ M, int ldm,
+                                                    int ncopies,
                                                     const Decomp *__restrict__ dc,
                                                     double *__restrict__ A,
                                                     float *__restrict__ A32) {
@@ -37,7 +39,7 @@ __global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, i
   T mv[CPAL_MCOPIES];
 #pragma unroll
   for (int x = 0; x < CPAL_MCOPIES; ++x)
-    mv[x] = (live && col && x < ncopies) ? M[(i64)x * n * R + row * R + c] : T(0);
+    mv[x] = (live && col && x < ncopies) ? M[(i64)x * n * ldm + row * ldm + c] : T(0);
   const int pinv = dc->pinv;
   for (int e = tid; e < R * R; e += blockDim.x) {
     const double lv = dc->L[e], vv = dc->V[e];
@@ -102,7 +104,8 @@ __global__ void k_to_f32(const double *__restrict__ a, float *__restrict__ b, i6
     b[i] = (float)a[i];
 }
 
-void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, int ncopies,
+void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, int ldm,
+                       int ncopies,
                        const Decomp *dc, double *A, float *A32, hipStream_t s) {
   const int lpn = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
   const int nb = (int)((n * lpn + 255) / 256);
@@ -110,12 +113,12 @@ void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M
   if (f64) {
     auto k = lpn == 16 ? k_solve_rows<double, 16> : lpn == 32 ? k_solve_rows<double, 32>
                                                               : k_solve_rows<double, 64>;
-    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const double *)M, ncopies, dc, A,
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const double *)M, ldm, ncopies, dc, A,
                        A32);
   } else {
     auto k = lpn == 16 ? k_solve_rows<float, 16> : lpn == 32 ? k_solve_rows<float, 32>
                                                              : k_solve_rows<float, 64>;
-    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const float *)M, ncopies, dc, A,
+    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const float *)M, ldm, ncopies, dc, A,
                        A32);
   }
 }
