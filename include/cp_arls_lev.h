@@ -59,10 +59,14 @@ enum {
 typedef struct {
   int32_t order;             /* D >= 2, <= 8                                           */
   const int64_t *dims;       /* host, order entries; prod(dims) < 2^62                 */
-  int64_t nnz;               /* >= 1, < 2^32                                           */
-  const int32_t *coords;     /* device, [order][nnz], distinct coordinates             */
-  const void *values;        /* device, nnz values of value_dtype                      */
+  int64_t nnz;               /* sparse: >= 1, < 2^32; ignored when dense               */
+  const int32_t *coords;     /* device, [order][nnz], distinct coordinates; ignored
+                                (may be NULL) when dense                             */
+  const void *values;        /* device, value_dtype: nnz values (sparse), or
+                                prod(dims) values with mode 0 fastest (dense)        */
   int32_t value_dtype;       /* CPAL_F32 or CPAL_F64                                   */
+  int32_t dense;             /* 0: COO sparse; 1: every entry stored (the fibers of
+                                the sampled rows are whole columns, Sec. 6.3)        */
 } cpal_tensor;
 
 typedef struct {
@@ -73,8 +77,11 @@ typedef struct {
   uint64_t stream_id;        /* Philox key word 1 (e.g. the restart number)            */
   int32_t gather_dtype;      /* CPAL_F64 (parity) or CPAL_F32: precision of the fiber
                                 values, the weighted KRP rows and the sampled MTTKRP;
+                                CPAL_BF16 (dense tensors only): BF16 fiber values and
+                                KRP rows on the matrix cores, FP32 accumulation.
                                 Gram matrices, solves and leverage are always FP64   */
-  int64_t fit_samples;       /* s_fit for cp_arls_lev_fit_estimate; 0 = no fit sample  */
+  int64_t fit_samples;       /* s_fit for cp_arls_lev_fit_estimate; 0 = no fit sample
+                                (must be 0 for a dense tensor)                       */
   double fit_nnz_fraction;   /* alpha in [0,1] (Sec. 6.4), default 0.5                 */
   int64_t det_enum_cap;      /* max candidate combinations examined by the
                                 deterministic enumeration; 0 = 2^26                  */
@@ -93,7 +100,9 @@ typedef struct {
 
 /* Create a context (Alg. 3 setup): copies X into per-mode fiber indexes
  * (Sec. 6.3: every nonzero keyed by the linear index of its other-mode
- * coordinates, sorted, with a hash table key -> fiber), computes the
+ * coordinates, sorted, with a hash table key -> fiber; for a dense X one
+ * copy per mode in the gather precision with every mode-m fiber
+ * contiguous, prod(dims) * (element size) bytes each), computes the
  * leverage scores of every initial factor (Alg. 3, first loop) and, if
  * fit_samples > 0, draws the stratified fit sample once (Sec. 6.4).
  * factors: host array of `order` device pointers, each n_m x R FP64,

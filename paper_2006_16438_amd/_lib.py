@@ -29,7 +29,8 @@ STAGES = ("sample", "rows", "gather", "solve", "leverage")
 
 class cpal_tensor(C.Structure):
     _fields_ = [("order", C.c_int32), ("dims", C.POINTER(C.c_int64)), ("nnz", C.c_int64),
-                ("coords", C.c_void_p), ("values", C.c_void_p), ("value_dtype", C.c_int32)]
+                ("coords", C.c_void_p), ("values", C.c_void_p), ("value_dtype", C.c_int32),
+                ("dense", C.c_int32)]
 
 
 class cpal_options(C.Structure):

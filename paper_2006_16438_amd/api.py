@@ -1,6 +1,6 @@
 """Python face of the gfx950 CP-ARLS-LEV library (thin wrapper over the C ABI).
 
-A :class:`CpArlsLev` owns one library context: a COO tensor, FP64 factor
+A :class:`CpArlsLev` owns one library context: a COO (or dense) tensor, FP64 factor
 matrices on the device, and the options of Alg. 3 (rank R, samples s,
 threshold tau, seed).  ``mode_update(k)`` runs one sampled least-squares
 update of factor k entirely in the library's HIP kernels.
@@ -39,13 +39,23 @@ class CpArlsLev:
         self.rank = int(rank)
         self.samples = int(samples)
         self.tau = (1.0 / samples if samples > 0 else 1.0) if tau is None else float(tau)
-        if coords.dtype != torch.int32 or not coords.is_cuda or coords.shape[0] != self.order:
-            raise ValueError("coords must be an int32 CUDA tensor of shape [order, nnz]")
         if values.dtype not in (torch.float32, torch.float64) or not values.is_cuda:
             raise ValueError("values must be a float32/float64 CUDA tensor")
-        self.coords = coords.contiguous()
-        self.values = values.contiguous()
-        self.nnz = int(self.coords.shape[1])
+        self.dense = coords is None
+        if self.dense:
+            # every entry stored: values[i_0, ..., i_{D-1}] handed over with mode 0 fastest
+            if tuple(values.shape) != self.dims:
+                raise ValueError("a dense tensor (coords=None) must have shape dims")
+            self.coords = None
+            self.values = values.permute(*reversed(range(self.order))).contiguous().reshape(-1)
+            self.nnz = 0
+        else:
+            if (coords.dtype != torch.int32 or not coords.is_cuda
+                    or coords.shape[0] != self.order):
+                raise ValueError("coords must be an int32 CUDA tensor of shape [order, nnz]")
+            self.coords = coords.contiguous()
+            self.values = values.contiguous()
+            self.nnz = int(self.coords.shape[1])
         if len(factors) != self.order:
             raise ValueError("one factor matrix per mode")
         for m, f in enumerate(factors):
@@ -56,10 +66,12 @@ class CpArlsLev:
         self.factors = list(factors)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._dims_c = (C.c_int64 * self.order)(*self.dims)
-        t = L.cpal_tensor(self.order, self._dims_c, self.nnz, self.coords.data_ptr(),
+        t = L.cpal_tensor(self.order, self._dims_c, self.nnz,
+                          self.coords.data_ptr() if self.coords is not None else None,
                           self.values.data_ptr(),
-                          L.CPAL_F64 if self.values.dtype == torch.float64 else L.CPAL_F32)
-        gdt = {"f64": L.CPAL_F64, "f32": L.CPAL_F32}[gather_dtype]
+                          L.CPAL_F64 if self.values.dtype == torch.float64 else L.CPAL_F32,
+                          1 if self.dense else 0)
+        gdt = {"f64": L.CPAL_F64, "f32": L.CPAL_F32, "bf16": L.CPAL_BF16}[gather_dtype]
         self.gather_dtype = gather_dtype
         o = L.cpal_options(self.rank, self.samples, self.tau, seed, stream_id, gdt,
                            int(fit_samples), float(fit_alpha), int(det_enum_cap))
@@ -68,7 +80,8 @@ class CpArlsLev:
         code = lib.cp_arls_lev_init(C.byref(t), C.byref(o), fp, _stream_ptr(self.stream),
                                     C.byref(self._ctx))
         _check(code)
-        self._stats = torch.zeros(L.STATS_BYTES // 8, dtype=torch.int64, device=self.coords.device)
+        self._stats = torch.zeros(L.STATS_BYTES // 8, dtype=torch.int64,
+                                  device=self.values.device)
 
     # ---------------------------------------------------------------- calls
     def mode_update(self, k, stats=True, stats_buf=None):
@@ -114,7 +127,7 @@ class CpArlsLev:
 
     def samples_view(self):
         """(idx uint64 as int64, omega, w) of the last update, s_bar rows (synchronizes)."""
-        dev = self.coords.device
+        dev = self.values.device
         idx = torch.empty(self.samples, dtype=torch.int64, device=dev)
         om = torch.empty(self.samples, dtype=torch.float64, device=dev)
         w = torch.empty(self.samples, dtype=torch.float64, device=dev)
@@ -125,7 +138,7 @@ class CpArlsLev:
         return idx[:n], om[:n], w[:n]
 
     def leverage(self, m):
-        out = torch.empty(self.dims[m], dtype=torch.float64, device=self.coords.device)
+        out = torch.empty(self.dims[m], dtype=torch.float64, device=self.values.device)
         _check(L.load().cp_arls_lev_leverage(self._ctx, int(m), out.data_ptr()), self._ctx)
         return out
 
@@ -134,7 +147,7 @@ class CpArlsLev:
 
     def fit_estimate(self, out=None):
         if out is None:
-            out = torch.empty(1, dtype=torch.float64, device=self.coords.device)
+            out = torch.empty(1, dtype=torch.float64, device=self.values.device)
         _check(L.load().cp_arls_lev_fit_estimate(self._ctx, out.data_ptr()), self._ctx)
         return out
 

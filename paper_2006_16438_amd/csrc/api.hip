@@ -47,10 +47,17 @@ void launch_samples_out(DevState *st, const u64 *samp_idx, const double *samp_om
                         const double *samp_w, i64 slots_cap, int key_bits, u64 *rkeys,
                         u64 *rkeys_tmp, unsigned *rslot, unsigned *rslot_tmp, void *sort_scratch,
                         i64 cap, u64 *idx, double *om, double *w, i64 *count, hipStream_t s);
-void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
+void launch_dense_copy(const void *vals, int vdt, const i64 *dims, int D, int k, int xdt,
+                       void *out, i64 ldx, hipStream_t s);
+void launch_dense_mttkrp(int xdt, const DevState *st, i64 nk, int R, int ldz, i64 ldx,
+                         const unsigned *cidx, const u64 *samp_idx, const void *X,
+                         const void *zhat, void *part, int kc, int nchunks, void *M,
+                         hipStream_t s);
+void launch_rows(int zdt, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
                  double *samp_om, double *samp_w, const u64 *dkeys, const DrawEntry *tab,
                  u64 tmask, int tshift, unsigned *tpos,
-                 const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
+                 const FiberSlot *slots, u64 hmask, int hshift, unsigned dense_len, void *zhat,
+                 unsigned *foff,
                  unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt,
                  unsigned *part_act, void *M, i64 mlen, int ldz, hipStream_t s);
 int rows_blocks(i64 cap);
@@ -117,6 +124,8 @@ struct Mode {
   uint2 *pairs = nullptr;
   int *ik = nullptr;
   double *v64 = nullptr;
+  void *dX = nullptr;   // dense tensor: copy with every mode-m fiber contiguous
+  i64 dld = 0;          //   fiber stride (n_m rounded up to 8)
 };
 
 }  // namespace
@@ -129,6 +138,11 @@ struct cpal_ctx {
   double tau = 1.0;
   u64 seed = 0, stream_id = 0;
   bool f64 = true;
+  int zdt = CPAL_F64;    // gather precision (CPAL_F64, CPAL_F32, CPAL_BF16 for dense)
+  bool dense = false;    // every entry stored (mode 0 fastest)
+  void *dpart = nullptr; // dense: partial M per workgroup of sampled fibers
+  int dkc = 64;          // dense: sampled fibers per workgroup
+  int dnch = 1;          // dense: workgroups along the sampled fibers
   i64 nnz = 0;
   u64 enum_cap = 1ull << 26;
   hipStream_t stream = nullptr;
@@ -350,14 +364,17 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
   if (!out) return CPAL_E_ARG;
   *out = nullptr;
   if (!X || !opt || !factors) return CPAL_E_ARG;
-  if (X->order < 2 || X->order > CPAL_MAXORDER || !X->dims || !X->coords || !X->values)
-    return CPAL_E_ARG;
-  if (X->nnz < 1 || X->nnz >= (1ll << 32)) return CPAL_E_ARG;
+  const bool dense = X->dense != 0;
+  if (X->order < 2 || X->order > CPAL_MAXORDER || !X->dims || !X->values) return CPAL_E_ARG;
+  if (!dense && (!X->coords || X->nnz < 1 || X->nnz >= (1ll << 32))) return CPAL_E_ARG;
   if (X->value_dtype != CPAL_F32 && X->value_dtype != CPAL_F64) return CPAL_E_ARG;
   if (opt->rank < 1 || opt->rank > CPAL_MAXR || opt->samples < 1) return CPAL_E_ARG;
   if (opt->samples > (1ll << 28)) return CPAL_E_ARG;
   if (!(opt->tau >= 0.0 && opt->tau <= 1.0)) return CPAL_E_ARG;
-  if (opt->gather_dtype != CPAL_F64 && opt->gather_dtype != CPAL_F32) return CPAL_E_ARG;
+  if (opt->gather_dtype != CPAL_F64 && opt->gather_dtype != CPAL_F32 &&
+      !(dense && opt->gather_dtype == CPAL_BF16))
+    return CPAL_E_ARG;
+  if (dense && opt->fit_samples != 0) return CPAL_E_ARG;   // the Sec. 6.4 sample is over nonzeros
   if (opt->det_enum_cap < 0 || opt->det_enum_cap > (1ll << 31)) return CPAL_E_ARG;
   if (opt->fit_samples < 0) return CPAL_E_ARG;
   long double fulld = 1;
@@ -379,7 +396,9 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
   c->seed = opt->seed;
   c->stream_id = opt->stream_id;
   c->f64 = opt->gather_dtype == CPAL_F64;
-  c->nnz = X->nnz;
+  c->zdt = opt->gather_dtype;
+  c->dense = dense;
+  c->nnz = dense ? 0 : X->nnz;
   c->enum_cap = opt->det_enum_cap ? (u64)opt->det_enum_cap : (1ull << 26);
   c->stream = (hipStream_t)hip_stream;
   try {
@@ -447,11 +466,20 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->gpart = c->alloc<double>((size_t)rows_blocks(s) * np);
     {
       i64 mcap = 0;
-      for (int m = 0; m < c->D; ++m) mcap = std::max<i64>(mcap, m_copies(c->dims[m]) * c->dims[m]);
+      for (int m = 0; m < c->D; ++m)
+        mcap = std::max<i64>(mcap, (dense ? 1 : m_copies(c->dims[m])) * c->dims[m]);
       c->M = c->alloc<char>((size_t)mcap * c->ldz * tsz);   // rows padded to ldz
     }
     c->gram_tmp = c->alloc<double>(np);
-    c->chunk_first = c->alloc<unsigned>(gather_chunks_cap(c->nnz));
+    // gather stream length: at most nnz (sparse), s * max n_m (dense)
+    c->chunk_first = c->alloc<unsigned>(gather_chunks_cap(dense ? s * maxn : c->nnz));
+    if (dense) {   // sampled fibers per workgroup of the dense contraction: <= 256 partials
+      i64 kc = ((s + 255) / 256 + 15) / 16 * 16;
+      kc = std::min<i64>(std::max<i64>(kc, 64), 1024);
+      c->dkc = (int)kc;
+      c->dnch = (int)((s + kc - 1) / kc);
+      c->dpart = c->alloc<char>((size_t)c->dnch * maxn * c->ldz * tsz);
+    }
     c->cpos = c->alloc<u64>(s);
     c->coff = c->alloc<unsigned>(s);
     c->cidx = c->alloc<unsigned>(s);
@@ -462,7 +490,7 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     c->sort_scratch = c->alloc<char>(sort_scratch_bytes(sort_cap, true));
     c->scan_scratch = c->alloc<char>(scan_scratch_bytes(std::max<i64>(sort_cap, s)));
 
-    // per-mode fiber indexes (Sec. 6.3)
+    // per-mode fiber indexes (Sec. 6.3), or per-mode copies of a dense tensor
     const i64 nnz = c->nnz;
     u64 *comp = nullptr, *comp_t = nullptr, *fid = nullptr, *nfib_dev = nullptr;
     unsigned *ids = nullptr, *ids_t = nullptr, *flag = nullptr, *fstart = nullptr;
@@ -477,63 +505,84 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
       tmp.push_back(p);
       return p;
     };
-    comp = (u64 *)talloc(sizeof(u64) * nnz);
-    comp_t = (u64 *)talloc(sizeof(u64) * nnz);
-    fid = (u64 *)talloc(sizeof(u64) * nnz);
-    ids = (unsigned *)talloc(sizeof(unsigned) * nnz);
-    ids_t = (unsigned *)talloc(sizeof(unsigned) * nnz);
-    flag = (unsigned *)talloc(sizeof(unsigned) * nnz);
-    fstart = (unsigned *)talloc(sizeof(unsigned) * nnz);
-    nfib_dev = (u64 *)talloc(sizeof(u64));
-    err_dev = (int *)talloc(sizeof(int));
-    hipMemsetAsync(err_dev, 0, sizeof(int), c->stream);
-    for (int k = 0; k < c->D; ++k)
-      build_index(c, k, X, comp, ids, comp_t, ids_t, flag, fid, fstart, c->sort_scratch,
-                  c->scan_scratch, err_dev, nfib_dev);
     int err_host = 0;
-    hipMemcpyAsync(&err_host, err_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream);
-    // ||X||^2 (uses fid as scratch for the block partials)
-    fit_norm(X->values, X->value_dtype, nnz, (double *)fid, c->st, c->stream);
-    hipError_t e = hipStreamSynchronize(c->stream);
-    for (void *q : tmp) hipFree(q);
-    tmp.clear();
-    if (e == hipSuccess && !err_host && opt->fit_samples > 0) {
-      // stratified fit sample, drawn once (Sec. 6.4)
-      const double alpha = opt->fit_nnz_fraction;
-      if (!(alpha >= 0.0 && alpha <= 1.0)) throw cpal_status(CPAL_E_ARG);
-      const i64 n_nz = (i64)std::ceil(alpha * (double)opt->fit_samples);
-      i64 n_z = (i64)std::floor((1.0 - alpha) * (double)opt->fit_samples);
-      const u64 zeros = (u64)full - (u64)nnz;
-      if (zeros == 0) n_z = 0;
-      c->fit_ld = n_nz + n_z;
-      c->fit_nz = n_nz;
-      c->phi_nz = n_nz ? (double)nnz / (double)n_nz : 0.0;
-      c->phi_z = n_z ? (double)zeros / (double)n_z : 0.0;
-      c->fit_sc = c->alloc<int>((size_t)c->D * std::max<i64>(c->fit_ld, 1));
-      c->fit_x = c->alloc<double>(std::max<i64>(c->fit_ld, 1));
-      c->fit_part = c->alloc<double>(c->fit_ld / 256 + 2);
-      u64 ns = 64;
-      while (ns < 2 * (u64)nnz) ns <<= 1;
-      int lg = 0;
-      while ((1ull << lg) < ns) ++lg;
-      const i64 zd = 64 * n_z + (1ll << 20);
-      const i64 zchunks = (zd + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK;
-      u64 *set = (u64 *)talloc(sizeof(u64) * ns);
-      u64 *ctl = (u64 *)talloc(sizeof(u64) * 4);
-      u64 *zbuf = (u64 *)talloc(sizeof(u64) * (size_t)zchunks * CPAL_DRAW_CHUNK);
-      unsigned *zcnt = (unsigned *)talloc(sizeof(unsigned) * zchunks);
-      hipMemsetAsync(ctl, 0, sizeof(u64) * 4, c->stream);
-      const FullModes fm = full_modes(c);
-      fit_build_set(X->coords, nnz, fm, set, ns, 64 - lg, c->stream);
-      fit_draw(X->coords, X->values, X->value_dtype, nnz, fm, n_nz, n_z, c->seed, c->stream_id,
-               set, ns, 64 - lg, ctl, zbuf, zcnt, c->fit_sc, c->fit_ld, c->fit_x, c->stream);
-      u64 got = 0;
-      if (n_z > 0) hipMemcpyAsync(&got, ctl + 2, sizeof(u64), hipMemcpyDeviceToHost, c->stream);
+    hipError_t e = hipSuccess;
+    if (dense) {
+      const size_t xsz = c->zdt == CPAL_F64 ? 8 : c->zdt == CPAL_F32 ? 4 : 2;
+      const i64 N = (i64)full;
+      for (int k = 0; k < c->D; ++k) {
+        Mode &md = c->mode[k];
+        md.dld = (md.n + 7) / 8 * 8;
+        const size_t bytes = (size_t)(N / md.n) * (size_t)md.dld * xsz;
+        md.dX = c->alloc<char>(bytes);
+        hipMemsetAsync(md.dX, 0, bytes, c->stream);
+        launch_dense_copy(X->values, X->value_dtype, c->dims, c->D, k, c->zdt, md.dX, md.dld,
+                          c->stream);
+      }
+      // ||X||^2
+      double *part = (double *)talloc(sizeof(double) * (size_t)(N / 256 + 2));
+      fit_norm(X->values, X->value_dtype, N, part, c->st, c->stream);
       e = hipStreamSynchronize(c->stream);
       for (void *q : tmp) hipFree(q);
       tmp.clear();
-      c->fit_n = n_nz + (i64)got;
-      if ((i64)got < n_z) c->fit_flags |= CPAL_FLAG_DRAWCAP;
+    } else {
+      comp = (u64 *)talloc(sizeof(u64) * nnz);
+      comp_t = (u64 *)talloc(sizeof(u64) * nnz);
+      fid = (u64 *)talloc(sizeof(u64) * nnz);
+      ids = (unsigned *)talloc(sizeof(unsigned) * nnz);
+      ids_t = (unsigned *)talloc(sizeof(unsigned) * nnz);
+      flag = (unsigned *)talloc(sizeof(unsigned) * nnz);
+      fstart = (unsigned *)talloc(sizeof(unsigned) * nnz);
+      nfib_dev = (u64 *)talloc(sizeof(u64));
+      err_dev = (int *)talloc(sizeof(int));
+      hipMemsetAsync(err_dev, 0, sizeof(int), c->stream);
+      for (int k = 0; k < c->D; ++k)
+        build_index(c, k, X, comp, ids, comp_t, ids_t, flag, fid, fstart, c->sort_scratch,
+                    c->scan_scratch, err_dev, nfib_dev);
+      hipMemcpyAsync(&err_host, err_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+      // ||X||^2 (uses fid as scratch for the block partials)
+      fit_norm(X->values, X->value_dtype, nnz, (double *)fid, c->st, c->stream);
+      e = hipStreamSynchronize(c->stream);
+      for (void *q : tmp) hipFree(q);
+      tmp.clear();
+      if (e == hipSuccess && !err_host && opt->fit_samples > 0) {
+        // stratified fit sample, drawn once (Sec. 6.4)
+        const double alpha = opt->fit_nnz_fraction;
+        if (!(alpha >= 0.0 && alpha <= 1.0)) throw cpal_status(CPAL_E_ARG);
+        const i64 n_nz = (i64)std::ceil(alpha * (double)opt->fit_samples);
+        i64 n_z = (i64)std::floor((1.0 - alpha) * (double)opt->fit_samples);
+        const u64 zeros = (u64)full - (u64)nnz;
+        if (zeros == 0) n_z = 0;
+        c->fit_ld = n_nz + n_z;
+        c->fit_nz = n_nz;
+        c->phi_nz = n_nz ? (double)nnz / (double)n_nz : 0.0;
+        c->phi_z = n_z ? (double)zeros / (double)n_z : 0.0;
+        c->fit_sc = c->alloc<int>((size_t)c->D * std::max<i64>(c->fit_ld, 1));
+        c->fit_x = c->alloc<double>(std::max<i64>(c->fit_ld, 1));
+        c->fit_part = c->alloc<double>(c->fit_ld / 256 + 2);
+        u64 ns = 64;
+        while (ns < 2 * (u64)nnz) ns <<= 1;
+        int lg = 0;
+        while ((1ull << lg) < ns) ++lg;
+        const i64 zd = 64 * n_z + (1ll << 20);
+        const i64 zchunks = (zd + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK;
+        u64 *set = (u64 *)talloc(sizeof(u64) * ns);
+        u64 *ctl = (u64 *)talloc(sizeof(u64) * 4);
+        u64 *zbuf = (u64 *)talloc(sizeof(u64) * (size_t)zchunks * CPAL_DRAW_CHUNK);
+        unsigned *zcnt = (unsigned *)talloc(sizeof(unsigned) * zchunks);
+        hipMemsetAsync(ctl, 0, sizeof(u64) * 4, c->stream);
+        const FullModes fm = full_modes(c);
+        fit_build_set(X->coords, nnz, fm, set, ns, 64 - lg, c->stream);
+        fit_draw(X->coords, X->values, X->value_dtype, nnz, fm, n_nz, n_z, c->seed, c->stream_id,
+                 set, ns, 64 - lg, ctl, zbuf, zcnt, c->fit_sc, c->fit_ld, c->fit_x, c->stream);
+        u64 got = 0;
+        if (n_z > 0) hipMemcpyAsync(&got, ctl + 2, sizeof(u64), hipMemcpyDeviceToHost, c->stream);
+        e = hipStreamSynchronize(c->stream);
+        for (void *q : tmp) hipFree(q);
+        tmp.clear();
+        c->fit_n = n_nz + (i64)got;
+        if ((i64)got < n_z) c->fit_flags |= CPAL_FLAG_DRAWCAP;
+      }
     }
     if (e != hipSuccess) {
       cpal_status st = check_hip(c, e, "init (fiber index)");
@@ -602,15 +651,20 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   c->stage_end(CPAL_STAGE_SAMPLE, tb);
   tb = c->stage_begin(CPAL_STAGE_ROWS);
   // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
-  launch_rows(c->f64, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->keys, c->dtab,
-              c->dtab_n - 1, c->dtab_shift, c->tpos, md.slots, md.nslots - 1, md.hshift, c->zhat,
-              c->foff, c->flen, c->gpart, c->gp_len, c->gp_cnt, c->gp_act, c->M,
-              m_copies(md.n) * md.n * c->ldz, c->ldz, s);
+  const int ncopies = c->dense ? 1 : (int)m_copies(md.n);
+  launch_rows(c->zdt, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->keys, c->dtab,
+              c->dtab_n - 1, c->dtab_shift, c->tpos, c->dense ? nullptr : md.slots,
+              md.nslots - 1, md.hshift, (unsigned)md.n, c->zhat, c->foff, c->flen, c->gpart,
+              c->gp_len, c->gp_cnt, c->gp_act, c->M, c->dense ? 0 : ncopies * md.n * c->ldz,
+              c->ldz, s);
   launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
                      c->coff, c->cidx, c->chunk_first, c->tpos, c->dtab, s);
   c->stage_end(CPAL_STAGE_ROWS, tb);
   tb = c->stage_begin(CPAL_STAGE_GATHER);
-  if (md.n <= (1 << 20))
+  if (c->dense)   // M = X~^T diag(omega) Z on the matrix cores
+    launch_dense_mttkrp(c->zdt, c->st, md.n, R, c->ldz, md.dld, c->cidx, c->samp_idx, md.dX,
+                        c->zhat, c->dpart, c->dkc, c->dnch, c->M, s);
+  else if (md.n <= (1 << 20))
     launch_gather_seg(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                       md.ik, md.v64, md.n, c->zhat, c->ldz, c->M, c->gs_grid, s);
   else
@@ -621,7 +675,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   tb = c->stage_begin(CPAL_STAGE_SOLVE);
   launch_decomp_dev(c->gpart, &c->st->n_slots, rows_per_block(), R, c->dc, &c->st->flags,
                     c->gram_tmp, s);
-  launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->ldz, (int)m_copies(md.n), c->dc, md.A,
+  launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->ldz, ncopies, c->dc, md.A,
                     md.A32, s);
   c->stage_end(CPAL_STAGE_SOLVE, tb);
   tb = c->stage_begin(CPAL_STAGE_LEVERAGE);

@@ -162,6 +162,23 @@ __device__ __forceinline__ double prob_of(const OtherModes &om, u64 lin) {
   return p;
 }
 
+// bfloat16 values are kept as their bit patterns.  Conversion from FP64
+// rounds to FP32 first, then to the nearest bfloat16 (ties to even; the
+// values here are finite).
+typedef unsigned short bf16s;
+__device__ __forceinline__ bf16s bf16_from_float(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (bf16s)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(bf16s b) {
+  return __uint_as_float((unsigned)b << 16);
+}
+template <typename T>
+__device__ __forceinline__ T cvt_from(double x) { return (T)x; }
+template <>
+__device__ __forceinline__ bf16s cvt_from<bf16s>(double x) { return bf16_from_float((float)x); }
+
 // Multiplicative hash of a key (fiber or KRP row) into a table of 2^(64-shift)
 // slots.
 __device__ __forceinline__ u64 key_hash(u64 key, int shift) {

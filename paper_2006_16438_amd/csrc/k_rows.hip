@@ -87,15 +87,15 @@ __device__ __forceinline__ void gs_tiles(const double *sz, const double *som, in
   }
 }
 
-template <typename T, int DD>
+template <typename TZ, typename TM, int DD>
 __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     OtherModes om, DevState *st, int R, u64 *__restrict__ samp_idx, double *__restrict__ samp_om,
     double *__restrict__ samp_w, const u64 *__restrict__ dkeys, const DrawEntry *__restrict__ tab,
     u64 tmask, int tshift, unsigned *__restrict__ tpos,
-    const FiberSlot *__restrict__ slots, u64 hmask, int hshift, T *__restrict__ zhat,
-    unsigned *__restrict__ foff, unsigned *__restrict__ flen, double *__restrict__ gpart,
-    u64 *__restrict__ part_len, unsigned *__restrict__ part_cnt, unsigned *__restrict__ part_act,
-    T *__restrict__ M, i64 mlen, int ldz) {
+    const FiberSlot *__restrict__ slots, u64 hmask, int hshift, unsigned dense_len,
+    TZ *__restrict__ zhat, unsigned *__restrict__ foff, unsigned *__restrict__ flen,
+    double *__restrict__ gpart, u64 *__restrict__ part_len, unsigned *__restrict__ part_cnt,
+    unsigned *__restrict__ part_act, TM *__restrict__ M, i64 mlen, int ldz) {
   extern __shared__ double sz[];           // ROWS_BLK x (R+1); phase 3 reuses it
   __shared__ double som[ROWS_BLK];
   __shared__ unsigned sim[CPAL_MAXORDER][ROWS_BLK];
@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
   const double p_det = st->p_det;
   if (blockIdx.x == 0 && tid == 0) st->n_slots = n_slots;
   for (i64 e = (i64)blockIdx.x * blockDim.x + tid; e < mlen; e += (i64)gridDim.x * blockDim.x)
-    M[e] = T(0);
+    M[e] = TM(0);
   const i64 base = (i64)blockIdx.x * ROWS_BLK;
   if (base >= n_slots) return;   // uniform per block
   const int rows = (int)min((i64)ROWS_BLK, n_slots - base);
@@ -124,7 +124,9 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     u64 hd = key_hash(lin, tshift), hf = key_hash(lin, hshift);
     DrawEntry e{lin, 0u, 0u};
     if (rnd) e = tab[hd];
-    FiberSlot sl = slots[hf];
+    const bool dense = slots == nullptr;   // every fiber: the whole mode-k column
+    FiberSlot sl{dense ? lin : CPAL_EMPTY_KEY, 0u, dense_len};
+    if (!dense) sl = slots[hf];
     constexpr int MO = CPAL_MAXORDER - 1;
     unsigned ix[MO];
     double qv[MO];
@@ -244,10 +246,10 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
     for (int q = 0; q < ROWS_UNR; ++q) {
       const int rr = r0 + q * rpw + sub;
       if (rr < rows && c < ldz) {
-        T out = T(0);
+        TZ out = TZ(0);
         if (c < R) {
           sz[rr * ld + c] = v[q];
-          out = (T)(som[rr] * v[q]);
+          out = cvt_from<TZ>(som[rr] * v[q]);
         }
         zhat[(base + rr) * ldz + c] = out;
       }
@@ -339,33 +341,47 @@ __global__ void __launch_bounds__(ROWS_BLK) k_gather_prep(DevState *st,
 }
 
 // ------------------------------------------------------------- launchers ---
-void launch_rows(bool f64, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
+template <typename TZ, typename TM>
+static void launch_rows_t(const OtherModes &om, DevState *st, int R, int nb, size_t sh, u64 *samp_idx,
+                          double *samp_om, double *samp_w, const u64 *dkeys, const DrawEntry *tab,
+                          u64 tmask, int tshift, unsigned *tpos, const FiberSlot *slots, u64 hmask,
+                          int hshift, unsigned dense_len, void *zhat, unsigned *foff,
+                          unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt,
+                          unsigned *part_act, void *M, i64 mlen, int ldz, hipStream_t s) {
+  const int dd = (om.d >= 2 && om.d <= 4) ? om.d : 0;
+  auto k = dd == 2 ? k_rows<TZ, TM, 2> : dd == 3 ? k_rows<TZ, TM, 3>
+         : dd == 4 ? k_rows<TZ, TM, 4> : k_rows<TZ, TM, 0>;
+  hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
+                     dkeys, tab, tmask, tshift, tpos, slots, hmask, hshift, dense_len, (TZ *)zhat,
+                     foff, flen, gpart, part_len, part_cnt, part_act, (TM *)M, mlen, ldz);
+}
+
+// zdt: precision of the weighted KRP rows (CPAL_F64, CPAL_F32 or CPAL_BF16);
+// M is FP64 for CPAL_F64, else FP32.  slots == nullptr: dense tensor, every
+// fiber has dense_len entries and no index is probed.
+void launch_rows(int zdt, const OtherModes &om, DevState *st, int R, i64 cap, u64 *samp_idx,
                  double *samp_om, double *samp_w, const u64 *dkeys, const DrawEntry *tab,
                  u64 tmask, int tshift, unsigned *tpos,
-                 const FiberSlot *slots, u64 hmask, int hshift, void *zhat, unsigned *foff,
-                 unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt,
+                 const FiberSlot *slots, u64 hmask, int hshift, unsigned dense_len, void *zhat,
+                 unsigned *foff, unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt,
                  unsigned *part_act, void *M, i64 mlen, int ldz, hipStream_t s) {
   const int nb = (int)((cap + ROWS_BLK - 1) / ROWS_BLK);
   // z rows, then the four waves' G_s tiles (4 x NTL x 256 doubles)
   const int nt = (R + 15) / 16;
   const size_t sh = sizeof(double) * std::max<size_t>((size_t)ROWS_BLK * (R + 1),
                                                       (size_t)1024 * (nt * (nt + 1) / 2));
-  const int dd = (om.d >= 2 && om.d <= 4) ? om.d : 0;
-  if (f64) {
-    auto k = dd == 2 ? k_rows<double, 2> : dd == 3 ? k_rows<double, 3>
-           : dd == 4 ? k_rows<double, 4> : k_rows<double, 0>;
-    hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
-                       dkeys, tab, tmask, tshift, tpos, slots, hmask, hshift, (double *)zhat,
-                       foff, flen, gpart,
-                       part_len, part_cnt, part_act, (double *)M, mlen, ldz);
-  } else {
-    auto k = dd == 2 ? k_rows<float, 2> : dd == 3 ? k_rows<float, 3>
-           : dd == 4 ? k_rows<float, 4> : k_rows<float, 0>;
-    hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
-                       dkeys, tab, tmask, tshift, tpos, slots, hmask, hshift, (float *)zhat,
-                       foff, flen, gpart,
-                       part_len, part_cnt, part_act, (float *)M, mlen, ldz);
-  }
+  if (zdt == CPAL_F64)
+    launch_rows_t<double, double>(om, st, R, nb, sh, samp_idx, samp_om, samp_w, dkeys, tab, tmask,
+                                  tshift, tpos, slots, hmask, hshift, dense_len, zhat, foff, flen,
+                                  gpart, part_len, part_cnt, part_act, M, mlen, ldz, s);
+  else if (zdt == CPAL_F32)
+    launch_rows_t<float, float>(om, st, R, nb, sh, samp_idx, samp_om, samp_w, dkeys, tab, tmask,
+                                tshift, tpos, slots, hmask, hshift, dense_len, zhat, foff, flen,
+                                gpart, part_len, part_cnt, part_act, M, mlen, ldz, s);
+  else
+    launch_rows_t<bf16s, float>(om, st, R, nb, sh, samp_idx, samp_om, samp_w, dkeys, tab, tmask,
+                                tshift, tpos, slots, hmask, hshift, dense_len, zhat, foff, flen,
+                                gpart, part_len, part_cnt, part_act, M, mlen, ldz, s);
 }
 
 int rows_blocks(i64 cap) { return (int)((cap + ROWS_BLK - 1) / ROWS_BLK); }

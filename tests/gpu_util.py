@@ -21,12 +21,28 @@ def log(msg):
     sys.stdout.flush()
 
 
+def dense_values(T):
+    """A fully stored tensor (every coordinate, linear order with mode 0
+    fastest, as synth.planted(..., density=1.0) makes it) as an array of
+    shape dims."""
+    assert T.coords.shape[1] == int(np.prod(T.dims)), "every entry must be stored"
+    return np.reshape(np.asarray(T.values), tuple(T.dims), order="F")
+
+
 def make_ctx(T, fac, R, s, tau=None, gather="f64", seed=0, stream_id=0, det_cap=0,
-             fit_samples=0, values_f32=False):
+             fit_samples=0, values_f32=False, dense=False, dense_values_gpu=None):
+    """dense_values_gpu: a dense CUDA tensor of shape T.dims handed over as is."""
     from paper_2006_16438_amd.api import CpArlsLev
     dev = torch.device("cuda:0")
-    coords = torch.from_numpy(np.ascontiguousarray(T.coords)).to(dev)
-    vals = torch.from_numpy(np.ascontiguousarray(T.values)).to(dev)
+    if dense_values_gpu is not None:
+        coords = None
+        vals = dense_values_gpu
+    elif dense:
+        coords = None
+        vals = torch.from_numpy(np.ascontiguousarray(dense_values(T))).to(dev)
+    else:
+        coords = torch.from_numpy(np.ascontiguousarray(T.coords)).to(dev)
+        vals = torch.from_numpy(np.ascontiguousarray(T.values)).to(dev)
     if values_f32:
         vals = vals.float()
     F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float64).copy()).to(dev) for f in fac]
@@ -41,10 +57,12 @@ def rel_err(a, b):
 
 
 def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, stream_id=0,
-               det_cap=0, OT=None, check_lev=True, label=""):
-    """Returns the list of (oracle stats, device stats) per update."""
+               det_cap=0, OT=None, check_lev=True, label="", dense=False):
+    """Returns the list of (oracle stats, device stats) per update.  dense:
+    hand the (fully stored) tensor to the library as a dense array; the
+    oracle keeps the equivalent COO form with every entry."""
     OT = OT or oracle.Tensor.from_synth(T)
-    ctx, F = make_ctx(T, fac, R, s, tau, gather, seed, stream_id, det_cap)
+    ctx, F = make_ctx(T, fac, R, s, tau, gather, seed, stream_id, det_cap, dense=dense)
     D = len(T.dims)
     cap = det_cap if det_cap else (1 << 26)
     out = []
