@@ -226,32 +226,44 @@ __global__ void __launch_bounds__(DN_THREADS) k_dense_mttkrp(
       }
 }
 
-// M(row, col) = sum of the workgroup partials in workgroup order (col < R;
-// the padding columns are cleared).
+// M(row, col) = the sum of the workgroup partials (col < R; the padding
+// columns are cleared).  A workgroup takes 16 entries; its 16 thread groups
+// sum 16 consecutive slices of the partials each, and the slice sums are
+// added in slice order, so the result does not depend on timing.
 template <typename TA>
 __global__ void __launch_bounds__(256) k_dense_reduce(const DevState *st, i64 nk, int R, int ldz,
                                                      const TA *__restrict__ part, int kc,
                                                      TA *__restrict__ M) {
+  __shared__ TA red[16][17];
   const i64 nch = (st->n_fib + kc - 1) / kc;
   const i64 stride = nk * ldz;
-  for (i64 e = (i64)blockIdx.x * blockDim.x + threadIdx.x; e < stride;
-       e += (i64)gridDim.x * blockDim.x) {
-    const int col = (int)(e % ldz);
-    TA sum = TA(0);
-    if (col < R) {
-#pragma unroll 8
-      for (i64 c = 0; c < nch; ++c) sum = sum + part[c * stride + e];
-    }
-    M[e] = sum;
+  const int el = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const i64 e = (i64)blockIdx.x * 16 + el;
+  const i64 per = (nch + 15) / 16;
+  const i64 c0 = sl * per, c1 = min(nch, c0 + per);
+  TA sum = TA(0);
+  if (e < stride) {
+#pragma unroll 4
+    for (i64 c = c0; c < c1; ++c) sum = sum + part[c * stride + e];
+  }
+  red[sl][el] = sum;
+  __syncthreads();
+  if (sl == 0 && e < stride) {
+    TA tot = TA(0);
+    for (int q = 0; q < 16; ++q) tot = tot + red[q][el];
+    M[e] = (int)(e % ldz) < R ? tot : TA(0);
   }
 }
 
 // Tile shape per precision: rows per workgroup = 64 TW (TW row tiles per
-// wave, a power of two), limited by the shared-memory staging of 16 fibers.
+// wave, a power of two): short row blocks give several workgroups per CU
+// (memory parallelism for the fiber stream) at no cost in partials, which
+// are kept per row.
 static int dense_tw(int xdt, int nr) {
-  int tw = (xdt == CPAL_F64 ? 8 : 16) / nr;
-  while (tw & (tw - 1)) tw &= tw - 1;   // a power of two, so 16 fibers tile the staging
-  return std::max(1, tw);
+  int tw = (xdt == CPAL_F64 ? 2 : 4) / nr;
+  while (tw & (tw - 1)) tw &= tw - 1;
+  const int tw_min = xdt == CPAL_BF16 ? 2 : 1;   // 16 fibers x 64 TW rows >= one load per thread
+  return std::max(tw_min, tw);
 }
 
 int dense_rows_per_block(int xdt, int R) { return 64 * dense_tw(xdt, (R + 15) / 16); }
@@ -270,17 +282,22 @@ static void launch_dense_p(const DevState *st, i64 nk, int R, int ldz, i64 ldx,
   const TX *x = (const TX *)X;
   const TX *z = (const TX *)zhat;
   TA *p = (TA *)part;
-  // TW follows dense_tw(): 16 / NR (BF16, FP32) or 8 / NR (FP64), rounded down to 2^j
+  // TW follows dense_tw()
   if constexpr (sizeof(TX) == 8) {
-    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 8>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 4>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+  } else if constexpr (sizeof(TX) == 4) {
+    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 4>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+  } else {
+    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 4>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
     else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
     else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-  } else {
-    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 16>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 8>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 4>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 4>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
   }
 }
 
@@ -301,7 +318,7 @@ void launch_dense_mttkrp(int xdt, const DevState *st, i64 nk, int R, int ldz, i6
     launch_dense_p<DenseF64>(st, nk, R, ldz, ldx, cidx, samp_idx, X, zhat, part, kc, nchunks,
                              xdt, s);
   const i64 total = nk * ldz;
-  const unsigned g = (unsigned)std::min<i64>((total + 255) / 256, 4096);
+  const unsigned g = (unsigned)((total + 15) / 16);
   if (xdt == CPAL_F64)
     hipLaunchKernelGGL(k_dense_reduce<double>, dim3(g), dim3(256), 0, s, st, nk, R, ldz,
                        (const double *)part, kc, (double *)M);
