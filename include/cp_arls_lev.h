@@ -178,6 +178,40 @@ const char *cp_arls_lev_last_error(const cpal_ctx *ctx);
 /* Free everything the library allocated for the context (synchronizes). */
 void cp_arls_lev_destroy(cpal_ctx *ctx);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent decompositions (random restarts, tensors of different
+ * shape, order and rank): n decompositions over m tensors, decomposition i
+ * of tensor tensor_of[i] with options opts[i] and factors factors[i] (host
+ * array of that tensor's order device pointers, as for cp_arls_lev_init).
+ * Decompositions of one tensor with the same gather precision share its
+ * per-mode fiber index (or dense copies), built once.  The batch runs its
+ * decompositions on a few streams of its own (default priority) so that
+ * their kernels overlap; every batch call is ordered after the work already
+ * enqueued on hip_stream and work enqueued on hip_stream afterwards runs
+ * after it.  Errors as for cp_arls_lev_init; on error nothing is created. */
+typedef struct cpal_batch cpal_batch;
+
+cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
+                                   const int32_t *tensor_of, const cpal_options *opts,
+                                   double *const *const *factors, void *hip_stream,
+                                   cpal_batch **out);
+
+/* One mode update (cp_arls_lev_mode_update) of mode `mode` in every
+ * decomposition whose tensor has more than `mode` modes.  stats_dev: device
+ * array of n cpal_mode_stats, or NULL.  Returns the first error met. */
+cpal_status cp_arls_lev_mode_step_batch(cpal_batch *batch, int32_t mode,
+                                        cpal_mode_stats *stats_dev);
+
+/* cp_arls_lev_fit_estimate of every decomposition into fits_dev[0..n). */
+cpal_status cp_arls_lev_fit_estimate_batch(cpal_batch *batch, double *fits_dev);
+
+/* The context of decomposition i (for samples, leverage, step counter and
+ * error text); owned by the batch, valid until cp_arls_lev_destroy_batch. */
+cpal_status cp_arls_lev_batch_ctx(const cpal_batch *batch, int32_t i, cpal_ctx **ctx);
+
+/* Synchronize the batch's streams and free everything it allocated. */
+void cp_arls_lev_destroy_batch(cpal_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,6 +23,8 @@ SYMBOLS = (
     "cp_arls_lev_samples", "cp_arls_lev_leverage", "cp_arls_lev_refresh",
     "cp_arls_lev_get_step", "cp_arls_lev_set_step", "cp_arls_lev_set_timing",
     "cp_arls_lev_stage_times", "cp_arls_lev_last_error", "cp_arls_lev_destroy",
+    "cp_arls_lev_init_batch", "cp_arls_lev_mode_step_batch", "cp_arls_lev_fit_estimate_batch",
+    "cp_arls_lev_batch_ctx", "cp_arls_lev_destroy_batch",
 )
 STAGES = ("sample", "rows", "gather", "solve", "leverage")
 
@@ -85,6 +87,17 @@ def load(path: str | None = None):
     L.cp_arls_lev_last_error.restype = C.c_char_p
     L.cp_arls_lev_destroy.argtypes = [vp]
     L.cp_arls_lev_destroy.restype = None
+    L.cp_arls_lev_init_batch.argtypes = [C.c_int32, P(cpal_tensor), C.c_int32, P(C.c_int32),
+                                         P(cpal_options), P(vp), vp, P(vp)]
+    L.cp_arls_lev_init_batch.restype = C.c_int
+    L.cp_arls_lev_mode_step_batch.argtypes = [vp, C.c_int32, vp]
+    L.cp_arls_lev_mode_step_batch.restype = C.c_int
+    L.cp_arls_lev_fit_estimate_batch.argtypes = [vp, vp]
+    L.cp_arls_lev_fit_estimate_batch.restype = C.c_int
+    L.cp_arls_lev_batch_ctx.argtypes = [vp, C.c_int32, P(vp)]
+    L.cp_arls_lev_batch_ctx.restype = C.c_int
+    L.cp_arls_lev_destroy_batch.argtypes = [vp]
+    L.cp_arls_lev_destroy_batch.restype = None
     _lib = L
     return L
 

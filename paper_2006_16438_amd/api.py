@@ -171,3 +171,130 @@ class CpArlsLev:
             self.close()
         except Exception:
             pass
+
+
+class _Member(CpArlsLev):
+    """One decomposition of a CpArlsLevBatch (samples, leverage, step
+    counter); the batch owns the context."""
+
+    def __init__(self, ptr, dims, rank, samples, device):
+        self._ctx = C.c_void_p(ptr)
+        self.order = len(dims)
+        self.dims = tuple(dims)
+        self.rank = rank
+        self.samples = samples
+        self.values = torch.empty(0, device=device)
+        self._stats = torch.zeros(L.STATS_BYTES // 8, dtype=torch.int64, device=device)
+
+    # the context's work runs on one of the batch's streams: synchronize the
+    # device before reading what the library wrote
+    def samples_view(self):
+        dev = self.values.device
+        idx = torch.empty(self.samples, dtype=torch.int64, device=dev)
+        om = torch.empty(self.samples, dtype=torch.float64, device=dev)
+        w = torch.empty(self.samples, dtype=torch.float64, device=dev)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        _check(L.load().cp_arls_lev_samples(self._ctx, idx.data_ptr(), om.data_ptr(), w.data_ptr(),
+                                            self.samples, cnt.data_ptr()), self._ctx)
+        torch.cuda.synchronize()
+        n = int(cnt.item())
+        return idx[:n], om[:n], w[:n]
+
+    def leverage(self, m):
+        out = torch.empty(self.dims[m], dtype=torch.float64, device=self.values.device)
+        torch.cuda.synchronize()
+        _check(L.load().cp_arls_lev_leverage(self._ctx, int(m), out.data_ptr()), self._ctx)
+        torch.cuda.synchronize()
+        return out
+
+    def close(self):
+        self._ctx = C.c_void_p()
+
+
+class CpArlsLevBatch:
+    """Many independent decompositions (restarts, tensors of different shape
+    and rank) stepped together: ``mode_step(k)`` updates mode k of every
+    decomposition whose tensor has more than k modes.
+
+    tensors: list of (dims, coords or None, values) as for CpArlsLev;
+    tensor_of[i]: the tensor of decomposition i; factors[i]: its FP64 factor
+    matrices; ranks, samples, taus, seeds, stream_ids: per decomposition
+    (scalars broadcast)."""
+
+    def __init__(self, tensors, tensor_of, factors, ranks, samples, taus=None, seeds=0,
+                 stream_ids=0, gather_dtype="f32", fit_samples=0, fit_alpha=0.5,
+                 det_enum_cap=0, stream=None):
+        lib = L.load()
+        n = len(tensor_of)
+        per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * n
+        ranks, samples, seeds, stream_ids = per(ranks), per(samples), per(seeds), per(stream_ids)
+        taus = [1.0 / s for s in samples] if taus is None else per(taus)
+        self._keep = []
+        tens = (L.cpal_tensor * len(tensors))()
+        self.tdims = []
+        for t, (dims, coords, values) in enumerate(tensors):
+            dims = tuple(int(x) for x in dims)
+            self.tdims.append(dims)
+            if coords is None:
+                vals = values.permute(*reversed(range(len(dims)))).contiguous().reshape(-1)
+                crd, nnz, dense = None, 0, 1
+            else:
+                crd, vals = coords.contiguous(), values.contiguous()
+                nnz, dense = int(crd.shape[1]), 0
+            dc = (C.c_int64 * len(dims))(*dims)
+            self._keep += [dc, crd, vals]
+            tens[t] = L.cpal_tensor(len(dims), dc, nnz, crd.data_ptr() if crd is not None else None,
+                                    vals.data_ptr(),
+                                    L.CPAL_F64 if vals.dtype == torch.float64 else L.CPAL_F32,
+                                    dense)
+            self.device = vals.device
+        gdt = {"f64": L.CPAL_F64, "f32": L.CPAL_F32, "bf16": L.CPAL_BF16}[gather_dtype]
+        opts = (L.cpal_options * n)()
+        fptrs = (C.c_void_p * n)()
+        self.factors = [list(f) for f in factors]
+        for i in range(n):
+            opts[i] = L.cpal_options(int(ranks[i]), int(samples[i]), float(taus[i]), int(seeds[i]),
+                                     int(stream_ids[i]), gdt, int(fit_samples), float(fit_alpha),
+                                     int(det_enum_cap))
+            arr = (C.c_void_p * len(self.factors[i]))(*[f.data_ptr() for f in self.factors[i]])
+            self._keep.append(arr)
+            fptrs[i] = C.cast(arr, C.c_void_p)
+        tof = (C.c_int32 * n)(*[int(t) for t in tensor_of])
+        self.tensor_of = list(tensor_of)
+        self.ranks, self.samples = ranks, samples
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._b = C.c_void_p()
+        _check(lib.cp_arls_lev_init_batch(len(tensors), tens, n, tof, opts, fptrs,
+                                          _stream_ptr(self.stream), C.byref(self._b)))
+        self.n = n
+        self._stats = torch.zeros((n, L.STATS_BYTES // 8), dtype=torch.int64, device=self.device)
+
+    def mode_step(self, k, stats_buf=None):
+        """Update mode k of every decomposition (whose tensor has > k modes);
+        stats_buf: optional int64 CUDA tensor (n, >= 7) for the statistics."""
+        buf = stats_buf if stats_buf is not None else self._stats
+        _check(L.load().cp_arls_lev_mode_step_batch(self._b, int(k), C.c_void_p(buf.data_ptr())))
+
+    def fit_estimate(self, out=None):
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(L.load().cp_arls_lev_fit_estimate_batch(self._b, C.c_void_p(out.data_ptr())))
+        return out
+
+    def member(self, i):
+        p = C.c_void_p()
+        _check(L.load().cp_arls_lev_batch_ctx(self._b, int(i), C.byref(p)))
+        return _Member(p.value, self.tdims[self.tensor_of[i]], self.ranks[i], self.samples[i],
+                       self.device)
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            L.load().cp_arls_lev_destroy_batch(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -359,8 +359,16 @@ void build_index(cpal_ctx *c, int k, const cpal_tensor *X, u64 *comp, unsigned *
 
 extern "C" {
 
-cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
-                             double *const *factors, void *hip_stream, cpal_ctx **out) {
+}  // extern "C"
+
+namespace {
+
+// Context creation; `share`, when given and built from a tensor of the same
+// shape, storage and gather precision, lends its per-mode index (or dense
+// copies) and ||X||^2 instead of building them again (restarts of one tensor
+// in a batch).  The lender must outlive the borrower.
+cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *const *factors,
+                      void *hip_stream, const cpal_ctx *share, cpal_ctx **out) {
   if (!out) return CPAL_E_ARG;
   *out = nullptr;
   if (!X || !opt || !factors) return CPAL_E_ARG;
@@ -399,6 +407,12 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
   c->zdt = opt->gather_dtype;
   c->dense = dense;
   c->nnz = dense ? 0 : X->nnz;
+  if (share) {
+    bool same = share->D == c->D && share->dense == dense && share->zdt == c->zdt &&
+                share->nnz == c->nnz;
+    for (int m = 0; same && m < c->D; ++m) same = share->dims[m] == c->dims[m];
+    if (!same) share = nullptr;
+  }
   c->enum_cap = opt->det_enum_cap ? (u64)opt->det_enum_cap : (1ull << 26);
   c->stream = (hipStream_t)hip_stream;
   try {
@@ -507,7 +521,20 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
     };
     int err_host = 0;
     hipError_t e = hipSuccess;
-    if (dense) {
+    if (share) {   // borrow the index (or dense copies) and ||X||^2
+      for (int k = 0; k < c->D; ++k) {
+        Mode &md = c->mode[k];
+        const Mode &sm = share->mode[k];
+        md.slots = sm.slots; md.nslots = sm.nslots; md.hshift = sm.hshift; md.nfib = sm.nfib;
+        md.pairs = sm.pairs; md.ik = sm.ik; md.v64 = sm.v64; md.dX = sm.dX; md.dld = sm.dld;
+      }
+      hipMemcpyAsync(&c->st->normX2, &share->st->normX2, sizeof(double),
+                     hipMemcpyDeviceToDevice, c->stream);
+      e = hipStreamSynchronize(c->stream);
+    }
+    if (share) {
+      // nothing to build
+    } else if (dense) {
       const size_t xsz = c->zdt == CPAL_F64 ? 8 : c->zdt == CPAL_F32 ? 4 : 2;
       const i64 N = (i64)full;
       for (int k = 0; k < c->D; ++k) {
@@ -545,44 +572,44 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
       e = hipStreamSynchronize(c->stream);
       for (void *q : tmp) hipFree(q);
       tmp.clear();
-      if (e == hipSuccess && !err_host && opt->fit_samples > 0) {
-        // stratified fit sample, drawn once (Sec. 6.4)
-        const double alpha = opt->fit_nnz_fraction;
-        if (!(alpha >= 0.0 && alpha <= 1.0)) throw cpal_status(CPAL_E_ARG);
-        const i64 n_nz = (i64)std::ceil(alpha * (double)opt->fit_samples);
-        i64 n_z = (i64)std::floor((1.0 - alpha) * (double)opt->fit_samples);
-        const u64 zeros = (u64)full - (u64)nnz;
-        if (zeros == 0) n_z = 0;
-        c->fit_ld = n_nz + n_z;
-        c->fit_nz = n_nz;
-        c->phi_nz = n_nz ? (double)nnz / (double)n_nz : 0.0;
-        c->phi_z = n_z ? (double)zeros / (double)n_z : 0.0;
-        c->fit_sc = c->alloc<int>((size_t)c->D * std::max<i64>(c->fit_ld, 1));
-        c->fit_x = c->alloc<double>(std::max<i64>(c->fit_ld, 1));
-        c->fit_part = c->alloc<double>(c->fit_ld / 256 + 2);
-        u64 ns = 64;
-        while (ns < 2 * (u64)nnz) ns <<= 1;
-        int lg = 0;
-        while ((1ull << lg) < ns) ++lg;
-        const i64 zd = 64 * n_z + (1ll << 20);
-        const i64 zchunks = (zd + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK;
-        u64 *set = (u64 *)talloc(sizeof(u64) * ns);
-        u64 *ctl = (u64 *)talloc(sizeof(u64) * 4);
-        u64 *zbuf = (u64 *)talloc(sizeof(u64) * (size_t)zchunks * CPAL_DRAW_CHUNK);
-        unsigned *zcnt = (unsigned *)talloc(sizeof(unsigned) * zchunks);
-        hipMemsetAsync(ctl, 0, sizeof(u64) * 4, c->stream);
-        const FullModes fm = full_modes(c);
-        fit_build_set(X->coords, nnz, fm, set, ns, 64 - lg, c->stream);
-        fit_draw(X->coords, X->values, X->value_dtype, nnz, fm, n_nz, n_z, c->seed, c->stream_id,
-                 set, ns, 64 - lg, ctl, zbuf, zcnt, c->fit_sc, c->fit_ld, c->fit_x, c->stream);
-        u64 got = 0;
-        if (n_z > 0) hipMemcpyAsync(&got, ctl + 2, sizeof(u64), hipMemcpyDeviceToHost, c->stream);
-        e = hipStreamSynchronize(c->stream);
-        for (void *q : tmp) hipFree(q);
-        tmp.clear();
-        c->fit_n = n_nz + (i64)got;
-        if ((i64)got < n_z) c->fit_flags |= CPAL_FLAG_DRAWCAP;
-      }
+    }
+    if (!dense && e == hipSuccess && !err_host && opt->fit_samples > 0) {
+      // stratified fit sample, drawn once (Sec. 6.4)
+      const double alpha = opt->fit_nnz_fraction;
+      if (!(alpha >= 0.0 && alpha <= 1.0)) throw cpal_status(CPAL_E_ARG);
+      const i64 n_nz = (i64)std::ceil(alpha * (double)opt->fit_samples);
+      i64 n_z = (i64)std::floor((1.0 - alpha) * (double)opt->fit_samples);
+      const u64 zeros = (u64)full - (u64)nnz;
+      if (zeros == 0) n_z = 0;
+      c->fit_ld = n_nz + n_z;
+      c->fit_nz = n_nz;
+      c->phi_nz = n_nz ? (double)nnz / (double)n_nz : 0.0;
+      c->phi_z = n_z ? (double)zeros / (double)n_z : 0.0;
+      c->fit_sc = c->alloc<int>((size_t)c->D * std::max<i64>(c->fit_ld, 1));
+      c->fit_x = c->alloc<double>(std::max<i64>(c->fit_ld, 1));
+      c->fit_part = c->alloc<double>(c->fit_ld / 256 + 2);
+      u64 ns = 64;
+      while (ns < 2 * (u64)nnz) ns <<= 1;
+      int lg = 0;
+      while ((1ull << lg) < ns) ++lg;
+      const i64 zd = 64 * n_z + (1ll << 20);
+      const i64 zchunks = (zd + CPAL_DRAW_CHUNK - 1) / CPAL_DRAW_CHUNK;
+      u64 *set = (u64 *)talloc(sizeof(u64) * ns);
+      u64 *ctl = (u64 *)talloc(sizeof(u64) * 4);
+      u64 *zbuf = (u64 *)talloc(sizeof(u64) * (size_t)zchunks * CPAL_DRAW_CHUNK);
+      unsigned *zcnt = (unsigned *)talloc(sizeof(unsigned) * zchunks);
+      hipMemsetAsync(ctl, 0, sizeof(u64) * 4, c->stream);
+      const FullModes fm = full_modes(c);
+      fit_build_set(X->coords, nnz, fm, set, ns, 64 - lg, c->stream);
+      fit_draw(X->coords, X->values, X->value_dtype, nnz, fm, n_nz, n_z, c->seed, c->stream_id,
+               set, ns, 64 - lg, ctl, zbuf, zcnt, c->fit_sc, c->fit_ld, c->fit_x, c->stream);
+      u64 got = 0;
+      if (n_z > 0) hipMemcpyAsync(&got, ctl + 2, sizeof(u64), hipMemcpyDeviceToHost, c->stream);
+      e = hipStreamSynchronize(c->stream);
+      for (void *q : tmp) hipFree(q);
+      tmp.clear();
+      c->fit_n = n_nz + (i64)got;
+      if ((i64)got < n_z) c->fit_flags |= CPAL_FLAG_DRAWCAP;
     }
     if (e != hipSuccess) {
       cpal_status st = check_hip(c, e, "init (fiber index)");
@@ -625,6 +652,15 @@ cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
   }
   *out = c;
   return CPAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
+                             double *const *factors, void *hip_stream, cpal_ctx **out) {
+  return init_impl(X, opt, factors, hip_stream, nullptr, out);
 }
 
 cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *stats_dev) {
@@ -768,6 +804,131 @@ void cp_arls_lev_destroy(cpal_ctx *c) {
   hipStreamSynchronize(c->stream);
   c->release();
   delete c;
+}
+
+// ------------------------------------------------------------------ batches
+}  // extern "C"
+
+struct cpal_batch {
+  std::vector<cpal_ctx *> ctx;
+  hipStream_t user = nullptr;
+  std::vector<hipStream_t> streams;
+  hipEvent_t start = nullptr;
+  std::vector<hipEvent_t> done;
+};
+
+namespace {
+
+constexpr int kBatchStreams = 4;   // hardware queues a process gets by default
+
+void batch_free(cpal_batch *b) {
+  for (cpal_ctx *c : b->ctx)
+    if (c) cp_arls_lev_destroy(c);
+  for (hipStream_t s : b->streams) hipStreamDestroy(s);
+  for (hipEvent_t e : b->done) hipEventDestroy(e);
+  if (b->start) hipEventDestroy(b->start);
+  delete b;
+}
+
+// The batch's streams wait for the caller's stream; afterwards the caller's
+// stream waits for every batch stream.
+void batch_fork(cpal_batch *b) {
+  hipEventRecord(b->start, b->user);
+  for (hipStream_t s : b->streams) hipStreamWaitEvent(s, b->start, 0);
+}
+void batch_join(cpal_batch *b) {
+  for (size_t j = 0; j < b->streams.size(); ++j) {
+    hipEventRecord(b->done[j], b->streams[j]);
+    hipStreamWaitEvent(b->user, b->done[j], 0);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
+                                   const int32_t *tensor_of, const cpal_options *opts,
+                                   double *const *const *factors, void *hip_stream,
+                                   cpal_batch **out) {
+  if (!out) return CPAL_E_ARG;
+  *out = nullptr;
+  if (m < 1 || n < 1 || !Xs || !tensor_of || !opts || !factors) return CPAL_E_ARG;
+  for (int i = 0; i < n; ++i)
+    if (tensor_of[i] < 0 || tensor_of[i] >= m || !factors[i]) return CPAL_E_ARG;
+  cpal_batch *b = new cpal_batch();
+  b->user = (hipStream_t)hip_stream;
+  const int ns = std::min(n, kBatchStreams);
+  for (int j = 0; j < ns; ++j) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      if (s) hipStreamDestroy(s);
+      batch_free(b);
+      return CPAL_E_DEVICE;
+    }
+    b->streams.push_back(s);
+    b->done.push_back(e);
+  }
+  if (hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess) {
+    batch_free(b);
+    return CPAL_E_DEVICE;
+  }
+  // init runs on the batch streams after the caller's pending work
+  batch_fork(b);
+  std::vector<cpal_ctx *> owner(m, nullptr);
+  b->ctx.assign(n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    const int t = tensor_of[i];
+    const cpal_status st = init_impl(&Xs[t], &opts[i], factors[i], b->streams[i % ns], owner[t],
+                                     &b->ctx[i]);
+    if (st != CPAL_OK) {
+      batch_free(b);
+      return st;
+    }
+    if (!owner[t]) owner[t] = b->ctx[i];
+  }
+  *out = b;
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_mode_step_batch(cpal_batch *b, int32_t mode, cpal_mode_stats *stats_dev) {
+  if (!b || mode < 0) return CPAL_E_ARG;
+  batch_fork(b);
+  cpal_status res = CPAL_OK;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    cpal_ctx *c = b->ctx[i];
+    if (mode >= c->D) continue;
+    const cpal_status st = cp_arls_lev_mode_update(c, mode, stats_dev ? stats_dev + i : nullptr);
+    if (st != CPAL_OK && res == CPAL_OK) res = st;
+  }
+  batch_join(b);
+  return res;
+}
+
+cpal_status cp_arls_lev_fit_estimate_batch(cpal_batch *b, double *fits_dev) {
+  if (!b || !fits_dev) return CPAL_E_ARG;
+  batch_fork(b);
+  cpal_status res = CPAL_OK;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    const cpal_status st = cp_arls_lev_fit_estimate(b->ctx[i], fits_dev + i);
+    if (st != CPAL_OK && res == CPAL_OK) res = st;
+  }
+  batch_join(b);
+  return res;
+}
+
+cpal_status cp_arls_lev_batch_ctx(const cpal_batch *b, int32_t i, cpal_ctx **ctx) {
+  if (!b || !ctx || i < 0 || i >= (int32_t)b->ctx.size()) return CPAL_E_ARG;
+  *ctx = b->ctx[i];
+  return CPAL_OK;
+}
+
+void cp_arls_lev_destroy_batch(cpal_batch *b) {
+  if (!b) return;
+  for (hipStream_t s : b->streams) hipStreamSynchronize(s);
+  batch_free(b);
 }
 
 }  // extern "C"
