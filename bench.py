@@ -460,6 +460,18 @@ def bench_batch(args):
     torch.cuda.synchronize()
     el_b = time.perf_counter() - t2
     rows_b = int(stats[:, :, 2].sum())
+    # the same batched steps replayed from captured HIP graphs (one per mode)
+    b.set_graphs(True)
+    for k in range(3):   # captures
+        b.mode_step(k)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for it in range(K):
+        for k in range(3):
+            b.mode_step(k, stats_buf=stats[it * 3 + k])
+    torch.cuda.synchronize()
+    el_g = time.perf_counter() - t2
+    log(f"batched {K} iterations: eager {el_b * 1e3:.1f} ms, graphs {el_g * 1e3:.1f} ms")
     members = [b.member(i) for i in range(n)]
     torch.cuda.synchronize()
     t3 = time.perf_counter()
@@ -498,6 +510,8 @@ def bench_batch(args):
                              "note": "the same 256 decompositions run one after another "
                                      "(continuing from the batched run's state)"},
         "batched_speedup": el_p / el_b,
+        "graph_replay": {"value": updates / el_g, "unit": "mode-updates/s",
+                         "speedup_over_eager_batched": el_b / el_g},
         "roofline": None,
         "cpu_baseline": None,
     }

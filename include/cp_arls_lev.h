@@ -205,6 +205,14 @@ cpal_status cp_arls_lev_mode_step_batch(cpal_batch *batch, int32_t mode,
 /* cp_arls_lev_fit_estimate of every decomposition into fits_dev[0..n). */
 cpal_status cp_arls_lev_fit_estimate_batch(cpal_batch *batch, double *fits_dev);
 
+/* on != 0: from now on every cp_arls_lev_mode_step_batch of a mode replays
+ * one HIP graph holding that mode's update of every decomposition, captured
+ * on the first such call (the step counter t lives in device memory, so a
+ * replay samples with the next t; statistics are copied to stats_dev after
+ * the replay; stage timing is not recorded in replays).  Changing a
+ * decomposition's options afterwards is not supported. */
+cpal_status cp_arls_lev_batch_set_graphs(cpal_batch *batch, int32_t on);
+
 /* The context of decomposition i (for samples, leverage, step counter and
  * error text); owned by the batch, valid until cp_arls_lev_destroy_batch. */
 cpal_status cp_arls_lev_batch_ctx(const cpal_batch *batch, int32_t i, cpal_ctx **ctx);

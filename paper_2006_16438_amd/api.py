@@ -224,7 +224,7 @@ class CpArlsLevBatch:
 
     def __init__(self, tensors, tensor_of, factors, ranks, samples, taus=None, seeds=0,
                  stream_ids=0, gather_dtype="f32", fit_samples=0, fit_alpha=0.5,
-                 det_enum_cap=0, stream=None):
+                 det_enum_cap=0, stream=None, use_graphs=False):
         lib = L.load()
         n = len(tensor_of)
         per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * n
@@ -269,6 +269,13 @@ class CpArlsLevBatch:
                                           _stream_ptr(self.stream), C.byref(self._b)))
         self.n = n
         self._stats = torch.zeros((n, L.STATS_BYTES // 8), dtype=torch.int64, device=self.device)
+        if use_graphs:
+            self.set_graphs(True)
+
+    def set_graphs(self, on):
+        """on: each later mode step replays the HIP graph captured for that
+        mode on its first step (kernels of all decompositions in one launch)."""
+        _check(L.load().cp_arls_lev_batch_set_graphs(self._b, 1 if on else 0))
 
     def mode_step(self, k, stats_buf=None):
         """Update mode k of every decomposition (whose tensor has > k modes);

@@ -36,7 +36,8 @@ void launch_det_enum(const OtherModes &om, double tau, DevState *st, const int *
 void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, double *det_p,
                        double *kept_p, double *psum, u64 det_cap, i64 s, u64 *samp_idx,
                        hipStream_t st_);
-void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
+void launch_set_step(DevState *st, u64 t, hipStream_t s);
+void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 *buf,
                  unsigned short *bpos, unsigned *chunk_cnt, int grid_first, int grid_more,
                  hipStream_t s);
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
@@ -679,7 +680,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   launch_det_finish(om, c->st, c->det_keys, c->det_p, c->kept_p, c->psum, c->det_cap, c->s,
                     c->samp_idx, s);
   // random rows (Alg. 2) and combining repeats (Sec. 4.1, 4.3)
-  launch_draw(om, c->st, c->seed, c->stream_id, c->t, c->dbuf, c->dpos, c->chunk_cnt,
+  launch_draw(om, c->st, c->seed, c->stream_id, c->dbuf, c->dpos, c->chunk_cnt,
               c->draw_grid, c->draw_more_grid, s);
   launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->dtab, c->dtab_n - 1,
                  c->dtab_shift, s);
@@ -763,7 +764,8 @@ cpal_status cp_arls_lev_get_step(const cpal_ctx *c, uint64_t *t) {
 cpal_status cp_arls_lev_set_step(cpal_ctx *c, uint64_t t) {
   if (!c) return CPAL_E_ARG;
   c->t = t;
-  return CPAL_OK;
+  launch_set_step(c->st, t, c->stream);   // the kernels read the counter on the device
+  return check_hip(c, hipGetLastError(), "set_step");
 }
 
 cpal_status cp_arls_lev_set_timing(cpal_ctx *c, int32_t enable) {
@@ -815,6 +817,9 @@ struct cpal_batch {
   std::vector<hipStream_t> streams;
   hipEvent_t start = nullptr;
   std::vector<hipEvent_t> done;
+  bool graphs = false;                              // replay captured mode steps
+  hipGraphExec_t exec[CPAL_MAXORDER] = {nullptr};   // one captured step per mode
+  cpal_mode_stats *stats = nullptr;                 // statistics written by the graphs
 };
 
 namespace {
@@ -822,6 +827,9 @@ namespace {
 constexpr int kBatchStreams = 4;   // hardware queues a process gets by default
 
 void batch_free(cpal_batch *b) {
+  for (hipGraphExec_t g : b->exec)
+    if (g) hipGraphExecDestroy(g);
+  if (b->stats) hipFree(b->stats);
   for (cpal_ctx *c : b->ctx)
     if (c) cp_arls_lev_destroy(c);
   for (hipStream_t s : b->streams) hipStreamDestroy(s);
@@ -841,6 +849,41 @@ void batch_join(cpal_batch *b) {
     hipEventRecord(b->done[j], b->streams[j]);
     hipStreamWaitEvent(b->user, b->done[j], 0);
   }
+}
+
+// Capture mode step `mode` of every decomposition into one graph: the
+// decompositions' kernels are recorded on the batch's streams (forked from
+// and joined back into streams[0]); each writes its statistics to b->stats.
+// Stage timing is off while capturing; the host step counters are restored
+// (a capture runs no kernel).
+cpal_status batch_capture(cpal_batch *b, int mode) {
+  hipStream_t s0 = b->streams[0];
+  if (hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed) != hipSuccess) return CPAL_E_DEVICE;
+  hipEventRecord(b->start, s0);
+  for (size_t j = 1; j < b->streams.size(); ++j) hipStreamWaitEvent(b->streams[j], b->start, 0);
+  cpal_status res = CPAL_OK;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    cpal_ctx *c = b->ctx[i];
+    if (mode >= c->D) continue;
+    const u64 t = c->t;
+    const unsigned timing = c->timing;
+    c->timing = 0;
+    const cpal_status st = cp_arls_lev_mode_update(c, mode, b->stats + i);
+    c->timing = timing;
+    c->t = t;
+    if (st != CPAL_OK && res == CPAL_OK) res = st;
+  }
+  for (size_t j = 1; j < b->streams.size(); ++j) {
+    hipEventRecord(b->done[j], b->streams[j]);
+    hipStreamWaitEvent(s0, b->done[j], 0);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s0, &g);
+  if (e != hipSuccess || !g) return CPAL_E_DEVICE;
+  if (res == CPAL_OK && hipGraphInstantiate(&b->exec[mode], g, nullptr, nullptr, 0) != hipSuccess)
+    res = CPAL_E_DEVICE;
+  hipGraphDestroy(g);
+  return res;
 }
 
 }  // namespace
@@ -871,7 +914,8 @@ cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
     b->streams.push_back(s);
     b->done.push_back(e);
   }
-  if (hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&b->stats, sizeof(cpal_mode_stats) * (size_t)n) != hipSuccess) {
     batch_free(b);
     return CPAL_E_DEVICE;
   }
@@ -894,7 +938,27 @@ cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
 }
 
 cpal_status cp_arls_lev_mode_step_batch(cpal_batch *b, int32_t mode, cpal_mode_stats *stats_dev) {
-  if (!b || mode < 0) return CPAL_E_ARG;
+  if (!b || mode < 0 || mode >= CPAL_MAXORDER) return CPAL_E_ARG;
+  if (b->graphs) {
+    if (!b->exec[mode]) {
+      const cpal_status st = batch_capture(b, mode);
+      if (st != CPAL_OK) return st;
+    }
+    hipEventRecord(b->start, b->user);
+    hipStreamWaitEvent(b->streams[0], b->start, 0);
+    if (hipGraphLaunch(b->exec[mode], b->streams[0]) != hipSuccess) return CPAL_E_DEVICE;
+    for (cpal_ctx *c : b->ctx)
+      if (mode < c->D) {   // host state an eager step would have left
+        c->t += 1;
+        c->last_key_bits = c->mode[mode].key_bits;
+      }
+    hipEventRecord(b->done[0], b->streams[0]);
+    hipStreamWaitEvent(b->user, b->done[0], 0);
+    if (stats_dev)
+      hipMemcpyAsync(stats_dev, b->stats, sizeof(cpal_mode_stats) * b->ctx.size(),
+                     hipMemcpyDeviceToDevice, b->user);
+    return hipGetLastError() == hipSuccess ? CPAL_OK : CPAL_E_DEVICE;
+  }
   batch_fork(b);
   cpal_status res = CPAL_OK;
   for (size_t i = 0; i < b->ctx.size(); ++i) {
@@ -917,6 +981,12 @@ cpal_status cp_arls_lev_fit_estimate_batch(cpal_batch *b, double *fits_dev) {
   }
   batch_join(b);
   return res;
+}
+
+cpal_status cp_arls_lev_batch_set_graphs(cpal_batch *b, int32_t on) {
+  if (!b) return CPAL_E_ARG;
+  b->graphs = on != 0;
+  return CPAL_OK;
 }
 
 cpal_status cp_arls_lev_batch_ctx(const cpal_batch *b, int32_t i, cpal_ctx **ctx) {

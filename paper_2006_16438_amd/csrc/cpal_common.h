@@ -36,6 +36,8 @@ struct DevState {
   i64 gathered;       // nnz of the sampled fibers
   i64 n_fib;          // nonempty sampled fibers
   i64 n_rnd_rows;     // distinct random rows (set when the sampled rows are listed)
+  u64 t_next;         // step counter of the next update (third Philox counter word)
+  u64 t_cur;          // step counter of the update in progress
   double p_det;
   double tau_eff;     // 1.0 when the enumeration was skipped or capped
   int flags;

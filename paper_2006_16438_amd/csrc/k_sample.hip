@@ -53,6 +53,10 @@ __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u6
   __shared__ double alpha[CPAL_MAXORDER];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) {
+    // this update's step counter (device-side, so that a captured update
+    // replays with the next value)
+    st->t_cur = st->t_next;
+    st->t_next = st->t_cur + 1;
     st->det_count = 0; st->combos = 0; st->s_det = 0; st->s_rnd = 0; st->s_rnd_used = 0;
     st->s_bar = 0; st->n_slots = 0; st->draws = 0; st->chunk_next = 0; st->accepted = 0;
     st->nchunks = 0; st->gathered = 0; st->p_det = 0.0; st->tau_eff = 1.0; st->flags = 0;
@@ -427,12 +431,13 @@ __device__ __forceinline__ unsigned draw_chunk(const OtherModes &om, const DrawM
 
 template <int DD>
 __global__ void __launch_bounds__(256) k_draw_first(OtherModes om, DevState *st, u64 seed,
-                                                    u64 stream_id, u64 t, u64 *__restrict__ buf,
+                                                    u64 stream_id, u64 *__restrict__ buf,
                                                     unsigned short *__restrict__ bpos,
                                                     unsigned *__restrict__ chunk_cnt,
                                                     int stage_n) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
   const i64 s_rnd = st->s_rnd;
+  const u64 t = st->t_cur;
   const i64 max_draws = max_draws_of(s_rnd);
   const i64 max_chunks = (max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK;
   const i64 first = s_rnd == 0 ? 0 : min(min(draw_need_chunks(st, s_rnd), max_chunks),
@@ -450,7 +455,7 @@ __global__ void __launch_bounds__(256) k_draw_first(OtherModes om, DevState *st,
 
 template <int DD>
 __global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, u64 seed,
-                                                   u64 stream_id, u64 t, u64 *__restrict__ buf,
+                                                   u64 stream_id, u64 *__restrict__ buf,
                                                    unsigned short *__restrict__ bpos,
                                                    unsigned *__restrict__ chunk_cnt,
                                                    int stage_n) {
@@ -459,6 +464,7 @@ __global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, 
   __shared__ int stop;
   const int tid = threadIdx.x;
   const i64 s_rnd = st->s_rnd;
+  const u64 t = st->t_cur;
   if (s_rnd == 0) return;
   const i64 max_draws = max_draws_of(s_rnd);
   const u64 max_chunks = (u64)((max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK);
@@ -533,7 +539,7 @@ __global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__rest
   __shared__ unsigned own_cnt[CMP_WINS];
   const int tid = threadIdx.x;
   const i64 s_rnd = st->s_rnd;
-  const i64 max_draws = max_draws_of(s_rnd);
+    const i64 max_draws = max_draws_of(s_rnd);
   const u64 max_chunks = (u64)((max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK);
   const u64 Q = min(st->chunk_next, max_chunks);
   const u64 nwin = (Q + 255) / 256;
@@ -597,6 +603,12 @@ __global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__rest
   }
 }
 
+__global__ void k_set_step(DevState *st, u64 t) { st->t_next = t; }
+
+void launch_set_step(DevState *st, u64 t, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, st, t);
+}
+
 void launch_det_cand(const OtherModes &om, double tau, u64 cap, DevState *st, int *cand,
                      hipStream_t s) {
   hipLaunchKernelGGL(k_det_cand, dim3(1), dim3(1024), 0, s, om, tau, cap, st, cand);
@@ -613,7 +625,7 @@ void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, 
   hipLaunchKernelGGL(k_det_finish, dim3(1), dim3(1024), 0, st_, om, st, det_keys, det_p, kept_p,
                      psum, det_cap, s, samp_idx, (unsigned char *)nullptr);
 }
-void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 t, u64 *buf,
+void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 *buf,
                  unsigned short *bpos, unsigned *chunk_cnt, int grid_first, int grid_more,
                  hipStream_t s) {
   i64 tot = 0;
@@ -625,9 +637,9 @@ void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u6
           : dd == 4 ? k_draw_first<4> : k_draw_first<0>;
   auto km = dd == 1 ? k_draw_more<1> : dd == 2 ? k_draw_more<2> : dd == 3 ? k_draw_more<3>
           : dd == 4 ? k_draw_more<4> : k_draw_more<0>;
-  hipLaunchKernelGGL(kf, dim3(grid_first), dim3(256), sh, s, om, st, seed, stream_id, t, buf, bpos,
+  hipLaunchKernelGGL(kf, dim3(grid_first), dim3(256), sh, s, om, st, seed, stream_id, buf, bpos,
                      chunk_cnt, stage_n);
-  hipLaunchKernelGGL(km, dim3(grid_more), dim3(256), sh, s, om, st, seed, stream_id, t, buf, bpos,
+  hipLaunchKernelGGL(km, dim3(grid_more), dim3(256), sh, s, om, st, seed, stream_id, buf, bpos,
                      chunk_cnt, stage_n);
 }
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,

@@ -18,7 +18,10 @@ from tests.gpu_util import dense_values, log, rel_err
 pytestmark = pytest.mark.gpu
 
 
-def test_batch_mixed_parity():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batch_mixed_parity(graphs):
+    """graphs=True: every mode step after the first replays the captured
+    graph of that mode; each replay is checked against the oracle."""
     from paper_2006_16438_amd.api import CpArlsLevBatch
     dev = torch.device("cuda:0")
     A = synth.random_sparse((30, 25, 20), 3000, seed=5)
@@ -41,11 +44,11 @@ def test_batch_mixed_parity():
                 for f in synth.gaussian_factors(tensors_np[t].dims, ranks[i], 10 + i)]
                for i, t in enumerate(tensor_of)]
     b = CpArlsLevBatch(tensors, tensor_of, factors, ranks, samples, seeds=3,
-                       stream_ids=stream_ids, gather_dtype="f64")
+                       stream_ids=stream_ids, gather_dtype="f64", use_graphs=graphs)
     OTs = [oracle.Tensor.from_synth(T) for T in tensors_np]
     members = [b.member(i) for i in range(len(tensor_of))]
     max_order = max(len(T.dims) for T in tensors_np)
-    for it in range(2):
+    for it in range(3):
         for k in range(max_order):
             refs = {}
             for i, t in enumerate(tensor_of):
@@ -69,5 +72,5 @@ def test_batch_mixed_parity():
                 assert np.array_equal(w.cpu().numpy(), ref["wgt"])
                 err = rel_err(factors[i][k].cpu().numpy(), new)
                 assert err <= 1e-10, f"decomposition {i} mode {k}: factor rel err {err:.3e}"
-            log(f"iteration {it} mode {k}: {len(refs)} decompositions match")
+            log(f"iteration {it} mode {k}: {len(refs)} decompositions match (graphs={graphs})")
     b.close()
