@@ -69,17 +69,26 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--gather", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--workload", default="uber4", choices=["uber4", "dense1000", "batch256"],
+    ap.add_argument("--workload", default="uber4",
+                    choices=["uber4", "dense1000", "batch256", "large1e9"],
                     help="uber4: the sparse 4-way benchmark (default); dense1000: dense "
                          "1000^3, BF16 on the matrix cores vs the plain FP32 path; batch256: "
-                         "64 sparse tensors x 4 restarts stepped together vs one at a time")
+                         "64 sparse tensors x 4 restarts stepped together vs one at a time; "
+                         "large1e9: sparse 8211x176962x8116 with 1e9 nonzeros")
+    ap.add_argument("--large-nnz", type=int, default=1_000_000_000,
+                    help="nonzeros of the large1e9 workload")
     ap.add_argument("--cpu-updates", type=int, default=80,
                     help="mode updates of the CPU oracle baseline (20 iterations = 80)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", choices=["on", "off"], default=None,
+                    help="time the gather launch shapes first (cp_arls_lev_autotune); default "
+                         "on for batch256, off for the single decompositions (whose default "
+                         "shapes measured as fast as the tuned ones)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB mebibytes (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    args.tune = (args.autotune or ("on" if args.workload == "batch256" else "off")) == "on"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(every box has one MI355X)", file=sys.stderr)
@@ -90,6 +99,9 @@ def main():
         return
     if args.workload == "batch256":
         bench_batch(args)
+        return
+    if args.workload == "large1e9":
+        bench_large(args)
         return
 
     import numpy as np
@@ -119,6 +131,8 @@ def main():
         F = [torch.from_numpy(f.copy()).to(dev) for f in fac0]
         ctx = CpArlsLev(T.dims, coords, vals, F, R, s, tau=tau, seed=0, stream_id=0,
                         gather_dtype=args.gather, fit_samples=s_fit)
+        if args.tune:   # launch shapes timed on this state; state unchanged
+            ctx.autotune()
         return ctx, F
 
     # warm-up run (kernels, allocator, caches)
@@ -165,6 +179,7 @@ def main():
     gbytes = sum(gather_bytes(x, R, T.dims[i % D], elem) for i, x in enumerate(sts))
     g_ms, g_cnt = stage["gather"]
     achieved = gbytes / (g_ms * 1e-3) / 1e9 if g_ms > 0 else 0.0
+    gcfg = [ctx.gather_config(k) for k in range(D)]
     ctx.close()
 
     result = {
@@ -202,6 +217,8 @@ def main():
             "avg_launch_us": 1e3 * g_ms / max(g_cnt, 1),
         },
         "fit_estimated": fit_est,
+        "gather_launch": {"autotuned": args.tune,
+                          "grid_sort_min_per_mode": gcfg},
     }
 
     if not args.no_cpu_baseline:
@@ -255,7 +272,7 @@ def bench_dense(args):
     the plain path, in FP32; an FP64-gather run gives the reference fit."""
     import torch
 
-    from paper_2006_16438_amd import synth
+    from paper_2006_16438_amd import synth, synth_gpu
     from paper_2006_16438_amd.api import CpArlsLev
 
     dev = torch.device("cuda:0")
@@ -263,13 +280,7 @@ def bench_dense(args):
     tau = 1.0 / s
     dims = (n, n, n)
     t0 = time.time()
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(0)
-    P = [torch.randn(n, planted_rank, generator=gen, device=dev) for _ in range(3)]
-    X = torch.einsum("ir,jr,kr->ijk", P[0], P[1], P[2])
-    E = torch.randn(X.shape, generator=gen, device=dev)
-    X.add_(E, alpha=0.01 * (X.norm() / E.norm()).item())
-    del E, P
+    X = synth_gpu.dense_planted(n, planted_rank, seed=0)
     torch.cuda.synchronize()
     log(f"generated dense 1000^3 in {time.time() - t0:.1f}s")
     fac0 = synth.gaussian_factors(dims, R, 0)
@@ -375,62 +386,20 @@ def bench_dense(args):
     print(json.dumps(result), flush=True)
 
 
-def gen_batch_tensors(n_tensors, seed, nnz_lo=100_000, nnz_hi=500_000):
-    """Sparse 3-way tensors generated on the GPU: dims uniform in [200, 5000],
-    nnz uniform in [nnz_lo, nnz_hi] capped at 5% of the entries, per-mode
-    Zipf(1.1) coordinates (hot indices scattered by a seeded permutation,
-    duplicates removed), planted rank uniform in 8..32 with U(0,1)
-    unit-norm-column factors, values = model + 1% relative Gaussian noise."""
-    import torch
-    dev = torch.device("cuda:0")
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
-    out = []
-    for _ in range(n_tensors):
-        dims = [int(x) for x in torch.randint(200, 5001, (3,), generator=g, device=dev)]
-        total = dims[0] * dims[1] * dims[2]
-        want = int(torch.randint(nnz_lo, nnz_hi + 1, (1,), generator=g, device=dev))
-        want = min(want, total // 20)
-        idx = []
-        for n in dims:
-            p = torch.arange(1, n + 1, device=dev, dtype=torch.float64).pow(-1.1)
-            cdf = torch.cumsum(p / p.sum(), 0)
-            u = torch.rand(int(want * 1.6), generator=g, device=dev, dtype=torch.float64)
-            i = torch.searchsorted(cdf, u).clamp_(max=n - 1)
-            perm = torch.randperm(n, generator=g, device=dev)
-            idx.append(perm[i])
-        key = idx[0] + dims[0] * (idx[1] + dims[1] * idx[2])
-        key = torch.unique(key)[:want]
-        c0 = key % dims[0]
-        c1 = (key // dims[0]) % dims[1]
-        c2 = key // (dims[0] * dims[1])
-        coords = torch.stack([c0, c1, c2]).to(torch.int32).contiguous()
-        rank = int(torch.randint(8, 33, (1,), generator=g, device=dev))
-        fac = []
-        for n in dims:
-            a = torch.rand(n, rank, generator=g, device=dev, dtype=torch.float64)
-            fac.append(a / a.norm(dim=0, keepdim=True))
-        model = (fac[0][c0] * fac[1][c1] * fac[2][c2]).sum(1)
-        noise = torch.randn(model.shape, generator=g, device=dev, dtype=torch.float64)
-        vals = (model + 0.01 * (model.norm() / noise.norm()) * noise).float().contiguous()
-        out.append((tuple(dims), coords, vals, rank))
-    return out
-
-
 def bench_batch(args):
-    """64 sparse 3-way tensors (gen_batch_tensors), 4 restarts each = 256
+    """64 sparse 3-way tensors (synth_gpu.batch_tensors), 4 restarts each = 256
     decompositions, R = the planted rank, s = 2^15, tau = 1/s, FP32 gather and
     FP64 solve: K iterations of batched mode steps (the decompositions spread
     over the batch's streams) against K iterations of the same decompositions
     run one after another (plain)."""
     import torch
 
-    from paper_2006_16438_amd import synth
+    from paper_2006_16438_amd import synth, synth_gpu
     from paper_2006_16438_amd.api import CpArlsLevBatch
 
     dev = torch.device("cuda:0")
     t0 = time.time()
-    tens = gen_batch_tensors(64, seed=0)
+    tens = synth_gpu.batch_tensors(64, seed=0)
     torch.cuda.synchronize()
     log(f"generated 64 tensors in {time.time() - t0:.1f}s, "
         f"nnz total {sum(int(c.shape[1]) for _, c, _, _ in tens)}")
@@ -452,6 +421,13 @@ def bench_batch(args):
         for k in range(3):
             b.mode_step(k)
     torch.cuda.synchronize()
+    if args.tune:   # on the state after the warm-up iterations
+        t1 = time.time()
+        b.autotune()
+        torch.cuda.synchronize()
+        from collections import Counter
+        shapes = Counter(b.member(i).gather_config(k) for i in range(n) for k in range(3))
+        log(f"gather launch shapes autotuned in {time.time() - t1:.1f}s: {shapes.most_common(8)}")
     stats = torch.zeros((K * 3, n, 7), dtype=torch.int64, device=dev)
     t2 = time.perf_counter()
     for it in range(K):
@@ -471,6 +447,7 @@ def bench_batch(args):
             b.mode_step(k, stats_buf=stats[it * 3 + k])
     torch.cuda.synchronize()
     el_g = time.perf_counter() - t2
+    rows_g = int(stats[:, :, 2].sum())
     log(f"batched {K} iterations: eager {el_b * 1e3:.1f} ms, graphs {el_g * 1e3:.1f} ms")
     members = [b.member(i) for i in range(n)]
     torch.cuda.synchronize()
@@ -485,35 +462,194 @@ def bench_batch(args):
     updates = K * 3 * n
     result = {
         "metric": METRIC,
-        "value": updates / el_b,
+        "value": updates / el_g,
         "unit": "mode-updates/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * el_b / K,
+        "ms_per_step": 1e3 * el_g / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": "batched: 64 sparse 3-way tensors, dims U[200,5000], nnz U[1e5,5e5] "
+            "workload": "batched: 64 sparse 3-way tensors, dims U[200,5000], nnz U[1e5,5e6] "
                         "capped at 5% of the entries, Zipf(1.1) coordinates, planted ranks "
                         "8-32 + 1% noise, 4 restarts each (256 decompositions); R = planted "
                         "rank, s=2^15, tau=2^-15, FP32 gather, FP64 solve; a step = one "
                         "iteration (3 batched mode steps)",
             "decompositions": n, "samples": s, "iterations": K,
-            "parallelism": "single GPU, 4 streams",
+            "parallelism": "single GPU; one captured HIP graph per mode step (kernels of all "
+                           "decompositions on 4 streams as parallel branches)",
+            "autotuned_gather": args.tune,
         },
-        "gathered_rows_per_s": rows_b / el_b,
+        "gathered_rows_per_s": rows_g / el_g,
+        "eager_batched": {"value": updates / el_b, "unit": "mode-updates/s",
+                          "gathered_rows_per_s": rows_b / el_b,
+                          "note": "the same batched steps launched kernel by kernel"},
         "plain_sequential": {"value": updates / el_p, "unit": "mode-updates/s",
                              "note": "the same 256 decompositions run one after another "
-                                     "(continuing from the batched run's state)"},
-        "batched_speedup": el_p / el_b,
-        "graph_replay": {"value": updates / el_g, "unit": "mode-updates/s",
-                         "speedup_over_eager_batched": el_b / el_g},
+                                     "(continuing from the batched runs' state)"},
+        "speedup_over_sequential": el_p / el_g,
         "roofline": None,
+        "roofline_note": "thousands of small gathers per step (one per decomposition); the "
+                         "single-decomposition workloads carry the gather's roofline",
         "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
+def exact_fit_sparse(coords, vals, F, chunk=1 << 23):
+    """1 - ||X - [[A_0, ..., A_{D-1}]]|| / ||X|| in FP64 for a sparse X on
+    the GPU (stored entries only contribute to <X, model>)."""
+    import torch
+    nnz = vals.numel()
+    norm_x2 = float((vals.double() ** 2).sum())
+    inner = 0.0
+    for a in range(0, nnz, chunk):
+        b = min(nnz, a + chunk)
+        m = F[0][coords[0, a:b].long()]
+        for k in range(1, len(F)):
+            m = m * F[k][coords[k, a:b].long()]
+        inner += float((m.sum(1) * vals[a:b].double()).sum())
+        del m
+    g = F[0].T @ F[0]
+    for k in range(1, len(F)):
+        g = g * (F[k].T @ F[k])
+    res2 = max(norm_x2 - 2.0 * inner + float(g.sum()), 0.0)
+    return 1.0 - math.sqrt(res2) / math.sqrt(norm_x2)
+
+
+def bench_large(args):
+    """Sparse 3-way 8211 x 176962 x 8116 with 1e9 distinct Zipf(1.2)
+    coordinates (synth_gpu.large3), values log(1 + Geometric(0.3)); R = 25,
+    s = 2^17, tau = 2^-17.  The FP32-gather path is timed over K iterations
+    from fresh factors (after W warm-up iterations whose state is reset);
+    an FP64-gather run of the same decomposition gives the reference fit."""
+    import torch
+
+    from paper_2006_16438_amd import synth, synth_gpu
+    from paper_2006_16438_amd.api import CpArlsLev
+
+    dev = torch.device("cuda:0")
+    R, s = 25, 1 << 17
+    tau = 1.0 / s
+    t0 = time.time()
+    dims, coords, vals = synth_gpu.large3(0, nnz=args.large_nnz)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()   # the library allocates outside torch's cache
+    t_gen = time.time() - t0
+    nnz = int(vals.numel())
+    log(f"generated {dims} with {nnz} nonzeros in {t_gen:.1f}s")
+    fac0 = synth.gaussian_factors(dims, R, 0)
+    K = args.steps
+
+    def run(gather, timed):
+        F = [torch.from_numpy(f.copy()).to(dev) for f in fac0]
+        torch.cuda.synchronize()
+        t1 = time.time()
+        ctx = CpArlsLev(dims, coords, vals, F, R, s, tau=tau, seed=0, stream_id=0,
+                        gather_dtype=gather)
+        torch.cuda.synchronize()
+        t_init = time.time() - t1
+        if args.tune:
+            t1 = time.time()
+            cfg = ctx.autotune()
+            log(f"{gather}: autotuned gather shapes {cfg} in {time.time() - t1:.1f}s")
+        log(f"{gather}: context initialised in {t_init:.1f}s "
+            f"(device memory in use {torch.cuda.memory_allocated() / 2**30:.1f} GiB by torch)")
+        if timed and args.warmup > 0:
+            for _ in range(args.warmup):
+                for k in range(3):
+                    ctx.mode_update(k, stats=False)
+            torch.cuda.synchronize()
+            for m in range(3):   # back to the initial state
+                F[m].copy_(torch.from_numpy(fac0[m]))
+                ctx.refresh(m)
+            ctx.step = 0
+            torch.cuda.synchronize()
+        stats = torch.zeros((K * 3, 7), dtype=torch.int64, device=dev)
+        if timed:
+            ctx.set_timing(stages=["gather"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for it in range(K):
+            for k in range(3):
+                ctx.mode_update(k, stats_buf=stats[it * 3 + k])
+            if not timed:
+                torch.cuda.synchronize()
+                log(f"{gather}: iteration {it} done")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        stage = ctx.stage_times(reset=True) if timed else None
+        stage_all = None
+        if timed:   # per-stage breakdown from one more (untimed) iteration
+            ctx.set_timing(True)
+            for k in range(3):
+                ctx.mode_update(k, stats=False)
+            stage_all = ctx.stage_times(reset=True)
+            ctx.set_timing(False)
+        cfg = [ctx.gather_config(k) for k in range(3)]
+        ctx.close()
+        sts = [CpArlsLev.parse_stats(stats[i]) for i in range(K * 3)]
+        fit = exact_fit_sparse(coords, vals, F)
+        log(f"{gather}: {K} iterations in {el:.3f}s, exact fit {fit:.6f}")
+        return el, stage, stage_all, sts, F, fit, t_init, cfg
+
+    el, stage, stage_all, sts, F32, fit32, t_init, gcfg = run("f32", True)
+    updates = K * 3
+    gbytes = sum(gather_bytes(x, R, dims[i % 3], 4) for i, x in enumerate(sts))
+    g_ms, g_cnt = stage["gather"]
+    achieved = gbytes / (g_ms * 1e-3) / 1e9 if g_ms > 0 else 0.0
+    _, _, _, _, F64, fit64, _, _ = run("f64", False)
+    fac_err = max(float((a - b).norm() / b.norm()) for a, b in zip(F32, F64))
+    result = {
+        "metric": METRIC,
+        "value": updates / el,
+        "unit": "mode-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"sparse 3-way {dims[0]}x{dims[1]}x{dims[2]}, {nnz} distinct Zipf(1.2) "
+                        "coordinates, log1p(Geometric(0.3)) FP32 values; R=25, s=2^17, "
+                        "tau=2^-17, FP32 gather, FP64 Gram/solve; a step = one iteration "
+                        "(3 mode updates)",
+            "rank": R, "samples": s, "tau": tau, "iterations": K, "nnz": nnz,
+            "parallelism": "single GPU",
+        },
+        "gathered_rows_per_s": sum(x["s_bar"] for x in sts) / el,
+        "gathered_nnz_per_s": sum(x["gathered_nnz"] for x in sts) / el,
+        "gathered_nnz_per_update": [x["gathered_nnz"] for x in sts[:3]],
+        "stage_ms_per_update": {k: v[0] / max(v[1], 1) for k, v in stage_all.items()},
+        "roofline": {
+            "kernel": "k_gather_seg (fiber gather + sampled MTTKRP)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": gbytes / updates,
+            "avg_launch_us": 1e3 * g_ms / max(g_cnt, 1),
+        },
+        "init_s": t_init,
+        "generate_s": t_gen,
+        "gather_launch": {"autotuned": args.tune,
+                          "grid_sort_min_per_mode": gcfg},
+        "fit_exact": {"f32": fit32, "f64_reference": fit64},
+        "fit_delta": abs(fit32 - fit64),
+        "factor_rel_err_f32_vs_f64": fac_err,
+        "cpu_baseline": None,
+        "cpu_baseline_note": "the FP64 oracle cannot hold 1e9 nonzeros; the FP64-gather GPU "
+                             "path (oracle parity 1e-10) is the reference",
     }
     print(json.dumps(result), flush=True)
 

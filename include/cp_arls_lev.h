@@ -172,6 +172,30 @@ cpal_status cp_arls_lev_set_timing(cpal_ctx *ctx, int32_t stage_mask);
 cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *count_host,
                                     int32_t reset);
 
+/* Launch shape of the fiber gather + sampled MTTKRP of mode k (Sec. 6.3):
+ * grid = workgroups (0: the library's default), sort_min = the segmented
+ * gather (modes of at most 2^20 rows) keeps the nonzeros of a 2048-position
+ * chunk in stream order instead of sorting them by row when the chunk spans
+ * at most sort_min sampled fibers (0: always sort).  Results do not depend
+ * on either beyond the rounding order of the FP32/FP64 sums.  Host-side
+ * setting, takes effect at the next mode update; grid in [0, 2^20],
+ * sort_min >= 0, else CPAL_E_ARG. */
+cpal_status cp_arls_lev_set_gather_config(cpal_ctx *ctx, int32_t k, int32_t grid,
+                                          int32_t sort_min);
+/* The launch shape mode k uses (grid_host: the effective workgroup count). */
+cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_t *grid_host,
+                                          int32_t *sort_min_host);
+
+/* Autotuner of the gather launch shapes: for every mode, builds the sampled
+ * system of an update of that mode at the current step (sampling, KRP rows,
+ * fiber probes; the factors, leverage scores and step counter are left as
+ * they were), times the gather over a fixed set of grids (and, for the
+ * segmented gather, sort thresholds) with HIP events, best of `reps` runs
+ * each (0: 2, at most 16), and keeps the fastest shape for the mode.
+ * Synchronizes the stream and is not graph-capturable.  Dense tensors have
+ * one launch shape per rank: returns CPAL_OK without timing. */
+cpal_status cp_arls_lev_autotune(cpal_ctx *ctx, int32_t reps);
+
 /* Text of the last error on this context (never NULL). */
 const char *cp_arls_lev_last_error(const cpal_ctx *ctx);
 
@@ -212,6 +236,12 @@ cpal_status cp_arls_lev_fit_estimate_batch(cpal_batch *batch, double *fits_dev);
  * the replay; stage timing is not recorded in replays).  Changing a
  * decomposition's options afterwards is not supported. */
 cpal_status cp_arls_lev_batch_set_graphs(cpal_batch *batch, int32_t on);
+
+/* cp_arls_lev_autotune for the first decomposition of every tensor; the
+ * other decompositions of that tensor take its launch shapes.  Graphs
+ * captured earlier are dropped (the next graph step captures again).
+ * Synchronizes the batch's streams. */
+cpal_status cp_arls_lev_autotune_batch(cpal_batch *batch, int32_t reps);
 
 /* The context of decomposition i (for samples, leverage, step counter and
  * error text); owned by the batch, valid until cp_arls_lev_destroy_batch. */

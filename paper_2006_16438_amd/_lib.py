@@ -25,6 +25,8 @@ SYMBOLS = (
     "cp_arls_lev_stage_times", "cp_arls_lev_last_error", "cp_arls_lev_destroy",
     "cp_arls_lev_init_batch", "cp_arls_lev_mode_step_batch", "cp_arls_lev_fit_estimate_batch",
     "cp_arls_lev_batch_set_graphs", "cp_arls_lev_batch_ctx", "cp_arls_lev_destroy_batch",
+    "cp_arls_lev_set_gather_config", "cp_arls_lev_get_gather_config", "cp_arls_lev_autotune",
+    "cp_arls_lev_autotune_batch",
 )
 STAGES = ("sample", "rows", "gather", "solve", "leverage")
 
@@ -94,6 +96,14 @@ def load(path: str | None = None):
     L.cp_arls_lev_mode_step_batch.restype = C.c_int
     L.cp_arls_lev_fit_estimate_batch.argtypes = [vp, vp]
     L.cp_arls_lev_fit_estimate_batch.restype = C.c_int
+    L.cp_arls_lev_set_gather_config.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+    L.cp_arls_lev_set_gather_config.restype = C.c_int
+    L.cp_arls_lev_get_gather_config.argtypes = [vp, C.c_int32, P(C.c_int32), P(C.c_int32)]
+    L.cp_arls_lev_get_gather_config.restype = C.c_int
+    L.cp_arls_lev_autotune.argtypes = [vp, C.c_int32]
+    L.cp_arls_lev_autotune.restype = C.c_int
+    L.cp_arls_lev_autotune_batch.argtypes = [vp, C.c_int32]
+    L.cp_arls_lev_autotune_batch.restype = C.c_int
     L.cp_arls_lev_batch_set_graphs.argtypes = [vp, C.c_int32]
     L.cp_arls_lev_batch_set_graphs.restype = C.c_int
     L.cp_arls_lev_batch_ctx.argtypes = [vp, C.c_int32, P(vp)]

@@ -145,6 +145,25 @@ class CpArlsLev:
     def refresh(self, m):
         _check(L.load().cp_arls_lev_refresh(self._ctx, int(m)), self._ctx)
 
+    def set_gather_config(self, k, grid=0, sort_min=0):
+        """Launch shape of mode k's gather (grid 0: default; sort_min: chunks
+        spanning at most this many fibers skip the row sort)."""
+        _check(L.load().cp_arls_lev_set_gather_config(self._ctx, int(k), int(grid),
+                                                       int(sort_min)), self._ctx)
+
+    def gather_config(self, k):
+        g, sm = C.c_int32(0), C.c_int32(0)
+        _check(L.load().cp_arls_lev_get_gather_config(self._ctx, int(k), C.byref(g),
+                                                       C.byref(sm)), self._ctx)
+        return g.value, sm.value
+
+    def autotune(self, reps=2):
+        """Time the gather launch shapes of every mode on this decomposition's
+        current state and keep the fastest (factors and step unchanged).
+        Returns [(grid, sort_min)] per mode."""
+        _check(L.load().cp_arls_lev_autotune(self._ctx, int(reps)), self._ctx)
+        return [self.gather_config(k) for k in range(self.order)]
+
     def fit_estimate(self, out=None):
         if out is None:
             out = torch.empty(1, dtype=torch.float64, device=self.values.device)
@@ -271,6 +290,11 @@ class CpArlsLevBatch:
         self._stats = torch.zeros((n, L.STATS_BYTES // 8), dtype=torch.int64, device=self.device)
         if use_graphs:
             self.set_graphs(True)
+
+    def autotune(self, reps=2):
+        """cp_arls_lev_autotune_batch: tune the first decomposition of every
+        tensor, the restarts take its launch shapes."""
+        _check(L.load().cp_arls_lev_autotune_batch(self._b, int(reps)))
 
     def set_graphs(self, on):
         """on: each later mode step replays the HIP graph captured for that

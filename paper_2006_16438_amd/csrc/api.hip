@@ -25,7 +25,8 @@ i64 gather_chunks_cap(i64 nnz);
 void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                        const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz, void *M,
-                       int grid, hipStream_t s);
+                       int grid, int sort_min, hipStream_t s);
+void launch_zero_words(void *p, i64 nwords, hipStream_t s);
 int lev_row_blocks(i64 n);
 void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
                   void *scratch, hipStream_t s);
@@ -127,6 +128,8 @@ struct Mode {
   double *v64 = nullptr;
   void *dX = nullptr;   // dense tensor: copy with every mode-m fiber contiguous
   i64 dld = 0;          //   fiber stride (n_m rounded up to 8)
+  int g_grid = 0;       // gather launch: workgroups (0: the default)
+  int g_sort_min = 0;   //   segmented gather: chunks of <= this many fibers skip the sort
 };
 
 }  // namespace
@@ -657,6 +660,80 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
 
 }  // namespace
 
+namespace {
+
+int default_gather_grid(const cpal_ctx *c, int k) {
+  return c->mode[k].n <= (1 << 20) ? c->gs_grid : c->gather_grid;
+}
+
+// Steps of one mode update before the gather: SkrpLev's deterministic and
+// random rows with repeats combined (Alg. 1, 2; Sec. 4.1, 4.3), the sampled
+// KRP rows, fiber probes and G_s partials, and the gather stream layout.
+void update_front(cpal_ctx *c, int k) {
+  hipStream_t s = c->stream;
+  Mode &md = c->mode[k];
+  const OtherModes om = others_of(c, k);
+  const int R = c->R;
+  hipEvent_t tb = c->stage_begin(CPAL_STAGE_SAMPLE);
+  launch_det_cand(om, c->tau, c->enum_cap, c->st, c->cand, s);
+  if (c->tau < 1.0)
+    launch_det_enum(om, c->tau, c->st, c->cand, c->det_blk, c->det_keys, c->det_cap, s);
+  launch_det_finish(om, c->st, c->det_keys, c->det_p, c->kept_p, c->psum, c->det_cap, c->s,
+                    c->samp_idx, s);
+  launch_draw(om, c->st, c->seed, c->stream_id, c->dbuf, c->dpos, c->chunk_cnt,
+              c->draw_grid, c->draw_more_grid, s);
+  launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->dtab, c->dtab_n - 1,
+                 c->dtab_shift, s);
+  c->last_key_bits = md.key_bits;
+  c->stage_end(CPAL_STAGE_SAMPLE, tb);
+  tb = c->stage_begin(CPAL_STAGE_ROWS);
+  const int ncopies = c->dense ? 1 : (int)m_copies(md.n);
+  launch_rows(c->zdt, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->keys, c->dtab,
+              c->dtab_n - 1, c->dtab_shift, c->tpos, c->dense ? nullptr : md.slots,
+              md.nslots - 1, md.hshift, (unsigned)md.n, c->zhat, c->foff, c->flen, c->gpart,
+              c->gp_len, c->gp_cnt, c->gp_act, c->M, c->dense ? 0 : ncopies * md.n * c->ldz,
+              c->ldz, s);
+  launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
+                     c->coff, c->cidx, c->chunk_first, c->tpos, c->dtab, s);
+  c->stage_end(CPAL_STAGE_ROWS, tb);
+}
+
+// TnsrSamp + sampled MTTKRP (Sec. 6.3, eq. (1.2)) into M.
+void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
+  hipStream_t s = c->stream;
+  Mode &md = c->mode[k];
+  const int R = c->R;
+  if (grid <= 0) grid = default_gather_grid(c, k);
+  if (c->dense)   // M = X~^T diag(omega) Z on the matrix cores
+    launch_dense_mttkrp(c->zdt, c->st, md.n, R, c->ldz, md.dld, c->cidx, c->samp_idx, md.dX,
+                        c->zhat, c->dpart, c->dkc, c->dnch, c->M, s);
+  else if (md.n <= (1 << 20))
+    launch_gather_seg(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
+                      md.ik, md.v64, md.n, c->zhat, c->ldz, c->M, grid, sort_min, s);
+  else
+    launch_gather(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, c->zhat,
+                  c->M, c->ldz, grid, s);
+}
+
+// Solve A_k = M G_s^{-1}, the leverage of the new A_k, statistics.
+void update_back(cpal_ctx *c, int k, cpal_mode_stats *stats_dev) {
+  hipStream_t s = c->stream;
+  Mode &md = c->mode[k];
+  const int R = c->R;
+  const int ncopies = c->dense ? 1 : (int)m_copies(md.n);
+  hipEvent_t tb = c->stage_begin(CPAL_STAGE_SOLVE);
+  launch_decomp_dev(c->gpart, &c->st->n_slots, rows_per_block(), R, c->dc, &c->st->flags,
+                    c->gram_tmp, s);
+  launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->ldz, ncopies, c->dc, md.A, md.A32, s);
+  c->stage_end(CPAL_STAGE_SOLVE, tb);
+  tb = c->stage_begin(CPAL_STAGE_LEVERAGE);
+  refresh_leverage(c, k);
+  c->stage_end(CPAL_STAGE_LEVERAGE, tb);
+  if (stats_dev) launch_stats(c->st, k, c->D, stats_dev, s);
+}
+
+}  // namespace
+
 extern "C" {
 
 cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
@@ -668,59 +745,87 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   if (!c) return CPAL_E_ARG;
   if (k < 0 || k >= c->D) return fail(c, CPAL_E_ARG, "mode out of range");
   if (c->failed) return fail(c, CPAL_E_STATE, "context failed earlier");
-  hipStream_t s = c->stream;
-  Mode &md = c->mode[k];
-  const OtherModes om = others_of(c, k);
-  const int R = c->R;
-  // SkrpLev (Alg. 1): deterministic rows
-  hipEvent_t tb = c->stage_begin(CPAL_STAGE_SAMPLE);
-  launch_det_cand(om, c->tau, c->enum_cap, c->st, c->cand, s);
-  if (c->tau < 1.0)
-    launch_det_enum(om, c->tau, c->st, c->cand, c->det_blk, c->det_keys, c->det_cap, s);
-  launch_det_finish(om, c->st, c->det_keys, c->det_p, c->kept_p, c->psum, c->det_cap, c->s,
-                    c->samp_idx, s);
-  // random rows (Alg. 2) and combining repeats (Sec. 4.1, 4.3)
-  launch_draw(om, c->st, c->seed, c->stream_id, c->dbuf, c->dpos, c->chunk_cnt,
-              c->draw_grid, c->draw_more_grid, s);
-  launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->dtab, c->dtab_n - 1,
-                 c->dtab_shift, s);
-  c->last_key_bits = md.key_bits;
-  c->stage_end(CPAL_STAGE_SAMPLE, tb);
-  tb = c->stage_begin(CPAL_STAGE_ROWS);
-  // KrpSamp + fiber probes + G_s partials, then TnsrSamp + M
-  const int ncopies = c->dense ? 1 : (int)m_copies(md.n);
-  launch_rows(c->zdt, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->keys, c->dtab,
-              c->dtab_n - 1, c->dtab_shift, c->tpos, c->dense ? nullptr : md.slots,
-              md.nslots - 1, md.hshift, (unsigned)md.n, c->zhat, c->foff, c->flen, c->gpart,
-              c->gp_len, c->gp_cnt, c->gp_act, c->M, c->dense ? 0 : ncopies * md.n * c->ldz,
-              c->ldz, s);
-  launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
-                     c->coff, c->cidx, c->chunk_first, c->tpos, c->dtab, s);
-  c->stage_end(CPAL_STAGE_ROWS, tb);
-  tb = c->stage_begin(CPAL_STAGE_GATHER);
-  if (c->dense)   // M = X~^T diag(omega) Z on the matrix cores
-    launch_dense_mttkrp(c->zdt, c->st, md.n, R, c->ldz, md.dld, c->cidx, c->samp_idx, md.dX,
-                        c->zhat, c->dpart, c->dkc, c->dnch, c->M, s);
-  else if (md.n <= (1 << 20))
-    launch_gather_seg(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
-                      md.ik, md.v64, md.n, c->zhat, c->ldz, c->M, c->gs_grid, s);
-  else
-    launch_gather(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, c->zhat,
-                  c->M, c->ldz, c->gather_grid, s);
+  update_front(c, k);
+  hipEvent_t tb = c->stage_begin(CPAL_STAGE_GATHER);
+  update_gather(c, k, c->mode[k].g_grid, c->mode[k].g_sort_min);
   c->stage_end(CPAL_STAGE_GATHER, tb);
-  // solve A_k = M G_s^{-1}, then the leverage of the new A_k
-  tb = c->stage_begin(CPAL_STAGE_SOLVE);
-  launch_decomp_dev(c->gpart, &c->st->n_slots, rows_per_block(), R, c->dc, &c->st->flags,
-                    c->gram_tmp, s);
-  launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->ldz, ncopies, c->dc, md.A,
-                    md.A32, s);
-  c->stage_end(CPAL_STAGE_SOLVE, tb);
-  tb = c->stage_begin(CPAL_STAGE_LEVERAGE);
-  refresh_leverage(c, k);
-  c->stage_end(CPAL_STAGE_LEVERAGE, tb);
-  if (stats_dev) launch_stats(c->st, k, c->D, stats_dev, s);
+  update_back(c, k, stats_dev);
   c->t += 1;
   return check_hip(c, hipGetLastError(), "mode_update launch");
+}
+
+cpal_status cp_arls_lev_set_gather_config(cpal_ctx *c, int32_t k, int32_t grid, int32_t sort_min) {
+  if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < 0)
+    return CPAL_E_ARG;
+  c->mode[k].g_grid = grid;
+  c->mode[k].g_sort_min = sort_min;
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *c, int32_t k, int32_t *grid,
+                                          int32_t *sort_min) {
+  if (!c || k < 0 || k >= c->D || !grid || !sort_min) return CPAL_E_ARG;
+  *grid = c->mode[k].g_grid ? c->mode[k].g_grid : default_gather_grid(c, k);
+  *sort_min = c->mode[k].g_sort_min;
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
+  if (!c || reps < 0 || reps > 16) return CPAL_E_ARG;
+  if (c->failed) return fail(c, CPAL_E_STATE, "context failed earlier");
+  if (c->dense) return CPAL_OK;   // the dense contraction has one launch shape per rank
+  if (reps == 0) reps = 2;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return fail(c, CPAL_E_DEVICE, "autotune: event creation");
+  }
+  const unsigned timing = c->timing;
+  c->timing = 0;
+  cpal_status res = CPAL_OK;
+  for (int k = 0; k < c->D && res == CPAL_OK; ++k) {
+    Mode &md = c->mode[k];
+    // the sampled system of an update of mode k at the current step, as
+    // mode_update would build it; the factors are not touched
+    update_front(c, k);
+    const bool seg = md.n <= (1 << 20);
+    static const int seg_grids[] = {256, 512, 1024, 2048};
+    static const int seg_sort[] = {0, 4, 32, 1 << 30};
+    static const int flat_grids[] = {1024, 2048, 4096, 8192};
+    const i64 mwords = (i64)m_copies(md.n) * md.n * c->ldz * (c->f64 ? 2 : 1);
+    float best = 1e30f;
+    int best_grid = 0, best_sort = 0;
+    const int ng = 4, ns = seg ? 4 : 1;
+    for (int gi = 0; gi < ng && res == CPAL_OK; ++gi)
+      for (int si = 0; si < ns && res == CPAL_OK; ++si) {
+        const int grid = seg ? seg_grids[gi] : flat_grids[gi];
+        const int smin = seg ? seg_sort[si] : 0;
+        float tmin = 1e30f;
+        for (int r = 0; r < reps; ++r) {
+          launch_zero_words(c->M, mwords, c->stream);
+          hipEventRecord(e0, c->stream);
+          update_gather(c, k, grid, smin);
+          hipEventRecord(e1, c->stream);
+          if (hipEventSynchronize(e1) != hipSuccess) {
+            res = check_hip(c, hipGetLastError(), "autotune trial");
+            break;
+          }
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, e0, e1);
+          tmin = std::min(tmin, ms);
+        }
+        if (tmin < best) { best = tmin; best_grid = grid; best_sort = smin; }
+      }
+    md.g_grid = best_grid;
+    md.g_sort_min = best_sort;
+  }
+  c->timing = timing;
+  // the trials consumed no step: the next update samples with the same t
+  launch_set_step(c->st, c->t, c->stream);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (res != CPAL_OK) return res;
+  return check_hip(c, hipStreamSynchronize(c->stream), "autotune");
 }
 
 cpal_status cp_arls_lev_fit_estimate(cpal_ctx *c, double *fit_dev) {
@@ -820,6 +925,7 @@ struct cpal_batch {
   bool graphs = false;                              // replay captured mode steps
   hipGraphExec_t exec[CPAL_MAXORDER] = {nullptr};   // one captured step per mode
   cpal_mode_stats *stats = nullptr;                 // statistics written by the graphs
+  std::vector<int> tensor_of;                       // tensor of each decomposition
 };
 
 namespace {
@@ -919,6 +1025,7 @@ cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
     batch_free(b);
     return CPAL_E_DEVICE;
   }
+  b->tensor_of.assign(tensor_of, tensor_of + n);
   // init runs on the batch streams after the caller's pending work
   batch_fork(b);
   std::vector<cpal_ctx *> owner(m, nullptr);
@@ -981,6 +1088,35 @@ cpal_status cp_arls_lev_fit_estimate_batch(cpal_batch *b, double *fits_dev) {
   }
   batch_join(b);
   return res;
+}
+
+cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
+  if (!b) return CPAL_E_ARG;
+  for (hipStream_t s : b->streams) hipStreamSynchronize(s);
+  // tune the first decomposition of every tensor; the others of that tensor
+  // (restarts: same shapes and sampled-fiber statistics) take its choice
+  std::vector<int> tuned(b->ctx.size(), -1);
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    int src = -1;
+    for (size_t j = 0; j < i; ++j)
+      if (b->tensor_of[j] == b->tensor_of[i] && tuned[j] == (int)j) { src = (int)j; break; }
+    cpal_ctx *c = b->ctx[i];
+    if (src < 0) {
+      const cpal_status st = cp_arls_lev_autotune(c, reps);
+      if (st != CPAL_OK) return st;
+      tuned[i] = (int)i;
+    } else {
+      for (int k = 0; k < c->D; ++k) {
+        c->mode[k].g_grid = b->ctx[src]->mode[k].g_grid;
+        c->mode[k].g_sort_min = b->ctx[src]->mode[k].g_sort_min;
+      }
+      tuned[i] = src;
+    }
+  }
+  // captured graphs hold the old launch shapes
+  for (hipGraphExec_t &g : b->exec)
+    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+  return CPAL_OK;
 }
 
 cpal_status cp_arls_lev_batch_set_graphs(cpal_batch *b, int32_t on) {

@@ -106,7 +106,9 @@ static_assert(GT_CHUNK == CPAL_GATHER_CHUNK, "gather chunk must match the prepar
 //     unconditional (positions past the chunk are clamped and masked);
 //  2. the chunk's nonzeros are sorted by i_k in shared memory (stable LSD
 //     radix sort, 6-bit digits ranked with wave ballots, keys i_k << 12 |
-//     position in the chunk);
+//     position in the chunk), unless the chunk spans at most sort_min
+//     fibers (then they stay in stream order: long fibers have distinct
+//     rows, and a sort would only delay the adds);
 //  3. lane groups of LPN lanes (LPN = padded row width ldz) take equal
 //     slices of the sorted list, lane c summing x * zhat(row, c) in a
 //     register while i_k stays the same; a run that ends inside the slice is
@@ -114,15 +116,15 @@ static_assert(GT_CHUNK == CPAL_GATHER_CHUNK, "gather chunk must match the prepar
 //     merged across slices in shared memory first, so every row of the chunk
 //     costs one global atomic add per column (rows need i_k < 2^20).
 #define GS_DIG 6
-#define GS_BATCH 32
+#define GS_BATCH 16   // sorted entries a lane group loads ahead (fits 128 VGPRs)
 
 // Steps 1 and 2 for chunk ch; returns the sorted keys (ka or kb).
 template <typename T>
 __device__ __forceinline__ unsigned *seg_load_sort(
     i64 ch, i64 nch, i64 total, i64 nf, const u64 *__restrict__ cpos,
     const unsigned *__restrict__ coff, const unsigned *__restrict__ cidx,
-    const unsigned *__restrict__ chunk_first, const NzLoad<T> &nz, int ikbits, u64 *win,
-    unsigned *ka, unsigned *kb, T *lx, unsigned *lz, unsigned *tab) {
+    const unsigned *__restrict__ chunk_first, const NzLoad<T> &nz, int ikbits, int sort_min,
+    u64 *win, unsigned *ka, unsigned *kb, T *lx, unsigned *lz, unsigned *tab) {
   constexpr int NW = GT_THREADS / 64;
   constexpr int NT = 64 * GT_PER_THREAD * NW;   // digit x round x wave counters
   const int tid = threadIdx.x, w = tid >> 6;
@@ -164,8 +166,13 @@ __device__ __forceinline__ unsigned *seg_load_sort(
     lx[li] = x;
     lz[li] = zrow[u];
   }
+  __syncthreads();   // every entry is written before any group reads it
+  // a chunk spanning at most sort_min fibers stays in stream order (rows are
+  // distinct within a fiber, so sorting would merge little); the branch is
+  // uniform over the workgroup
+  const int bits = nwin > sort_min ? ikbits : 0;
   unsigned *src = ka, *dst = kb;
-  for (int shift = 12; shift < 12 + ikbits; shift += GS_DIG) {
+  for (int shift = 12; shift < 12 + bits; shift += GS_DIG) {
     for (int e = tid; e < NT; e += GT_THREADS) tab[e] = 0u;
     __syncthreads();
     unsigned key[GT_PER_THREAD], dg[GT_PER_THREAD], rk[GT_PER_THREAD];
@@ -285,11 +292,13 @@ struct LdsEntries {
   }
 };
 
+// Two workgroups per CU (4 waves per SIMD: at most 128 VGPRs; the FP32
+// kernel's 78 KB of shared memory fits twice).
 template <typename T, int LPN>
-__global__ void __launch_bounds__(GT_THREADS) k_gather_seg(
+__global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
     const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    int ikbits, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+    int ikbits, int sort_min, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
   constexpr int NG = GT_THREADS / LPN;
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned ka[GT_CHUNK], kb[GT_CHUNK];
@@ -305,7 +314,7 @@ __global__ void __launch_bounds__(GT_THREADS) k_gather_seg(
   T *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * ldz;
   for (i64 ch = blockIdx.x; ch < nch; ch += gridDim.x) {
     const unsigned *keys = seg_load_sort<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz,
-                                            ikbits, win, ka, kb, lx, lz, tab);
+                                            ikbits, sort_min, win, ka, kb, lx, lz, tab);
     const int nvalid = (int)(min(total, (ch + 1) * GT_CHUNK) - ch * GT_CHUNK);
     seg_reduce<T, LPN>(LdsEntries<T>{keys, lx, lz}, nvalid, R, zhat, ldz, Mx, srow, svec);
   }
@@ -316,7 +325,7 @@ int gather_row_width(int R);
 void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                        const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz, void *M,
-                       int grid, hipStream_t s) {
+                       int grid, int sort_min, hipStream_t s) {
   int ikbits = 1;
   while ((1ll << ikbits) < nk) ++ikbits;
   const int rm = gather_row_width(R);
@@ -325,14 +334,28 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
     auto k = rm == 16 ? k_gather_seg<double, 16> : rm == 32 ? k_gather_seg<double, 32>
                                                             : k_gather_seg<double, 64>;
     hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
-                       chunk_first, nz, ikbits, (const double *)zhat, ldz, (double *)M, nk);
+                       chunk_first, nz, ikbits, sort_min, (const double *)zhat, ldz, (double *)M,
+                       nk);
   } else {
     NzLoad<float> nz{pairs};
     auto k = rm == 16 ? k_gather_seg<float, 16> : rm == 32 ? k_gather_seg<float, 32>
                                                            : k_gather_seg<float, 64>;
     hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
-                       chunk_first, nz, ikbits, (const float *)zhat, ldz, (float *)M, nk);
+                       chunk_first, nz, ikbits, sort_min, (const float *)zhat, ldz, (float *)M,
+                       nk);
   }
+}
+
+__global__ void k_zero_words(unsigned *__restrict__ p, i64 n) {
+  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+void launch_zero_words(void *p, i64 nwords, hipStream_t s) {
+  if (nwords <= 0) return;
+  i64 g = (nwords + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_zero_words, dim3((int)g), dim3(256), 0, s, (unsigned *)p, nwords);
 }
 
 i64 gather_chunks_cap(i64 nnz) { return nnz / GT_CHUNK + 2; }

@@ -57,13 +57,30 @@ def rel_err(a, b):
 
 
 def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, stream_id=0,
-               det_cap=0, OT=None, check_lev=True, label="", dense=False):
+               det_cap=0, OT=None, check_lev=True, label="", dense=False, gather_config=None,
+               autotune=False):
     """Returns the list of (oracle stats, device stats) per update.  dense:
     hand the (fully stored) tensor to the library as a dense array; the
-    oracle keeps the equivalent COO form with every entry."""
+    oracle keeps the equivalent COO form with every entry.  gather_config:
+    (grid, sort_min) set for every mode; autotune: run the autotuner first
+    and check that it left factors, leverage and step as they were."""
     OT = OT or oracle.Tensor.from_synth(T)
     ctx, F = make_ctx(T, fac, R, s, tau, gather, seed, stream_id, det_cap, dense=dense)
     D = len(T.dims)
+    if gather_config is not None:
+        for m in range(D):
+            ctx.set_gather_config(m, *gather_config)
+    if autotune:
+        before = [f.cpu().numpy().copy() for f in F]
+        lev0 = [ctx.leverage(m).cpu().numpy() for m in range(D)]
+        t0 = ctx.step
+        cfg = ctx.autotune()
+        log(f"  {label}: autotuned gather shapes {cfg}")
+        assert ctx.step == t0, "autotune changed the step counter"
+        for m in range(D):
+            assert np.array_equal(F[m].cpu().numpy(), before[m]), "autotune changed a factor"
+            assert np.array_equal(ctx.leverage(m).cpu().numpy(), lev0[m]), \
+                "autotune changed a leverage vector"
     cap = det_cap if det_cap else (1 << 26)
     out = []
     for u in range(updates):
@@ -107,3 +124,40 @@ def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, str
         out.append((rs, st, err))
     ctx.close()
     return out
+
+
+def sampled_solve_torch(dims, coords, vals, F, k, idx, om):
+    """FP64 solve of a sampled system built directly from its definition,
+    with plain torch operations on the GPU: the fiber of sampled row j is
+    every stored entry whose coordinates on the other modes equal those of
+    lin(j) (first other mode fastest); M = sum_j omega_j sum_{(i_k, x) in
+    fiber j} x e_{i_k} z_j^T, G_s = sum_j omega_j z_j z_j^T, A_k = M G_s^{-1}."""
+    D = len(dims)
+    others = [m for m in range(D) if m != k]
+    key = torch.zeros(coords.shape[1], dtype=torch.int64, device=coords.device)
+    stride = 1
+    strides = []
+    for m in others:
+        key += coords[m].long() * stride
+        strides.append(stride)
+        stride *= dims[m]
+    sk, perm = torch.sort(key)
+    del key
+    lo = torch.searchsorted(sk, idx)
+    hi = torch.searchsorted(sk, idx, right=True)
+    del sk
+    lens = hi - lo
+    R = F[0].shape[1]
+    Z = torch.ones((idx.numel(), R), dtype=torch.float64, device=idx.device)
+    for m, st in zip(others, strides):
+        Z *= F[m][(idx // st) % dims[m]]
+    rep = torch.repeat_interleave(torch.arange(idx.numel(), device=idx.device), lens)
+    start = torch.cumsum(lens, 0) - lens
+    pos = lo[rep] + (torch.arange(rep.numel(), device=idx.device) - start[rep])
+    e = perm[pos]
+    ik = coords[k][e].long()
+    x = vals[e].double()
+    M = torch.zeros((dims[k], R), dtype=torch.float64, device=idx.device)
+    M.index_add_(0, ik, (om[rep] * x)[:, None] * Z[rep])
+    G = Z.T @ (om[:, None] * Z)
+    return torch.linalg.solve(G, M.T).T, int(rep.numel())

@@ -64,20 +64,6 @@ def test_dense_ragged_rank20(gather):
     log(f"  factor rel errors {['%.2e' % e for _, _, e in out]}")
 
 
-def _planted_dense_gpu(n, rank, seed, noise=0.01):
-    """n^3 FP32 tensor on the GPU: planted rank-`rank` CP model with N(0,1)
-    factors plus `noise` relative Gaussian noise (seeded)."""
-    g = torch.Generator(device="cuda:0")
-    g.manual_seed(seed)
-    dev = torch.device("cuda:0")
-    A = [torch.randn(n, rank, generator=g, device=dev) for _ in range(3)]
-    X = torch.einsum("ir,jr,kr->ijk", A[0], A[1], A[2])
-    E = torch.randn(X.shape, generator=g, device=dev)
-    X.add_(E, alpha=noise * (X.norm() / E.norm()).item())
-    del E
-    return X
-
-
 @pytest.mark.parametrize("gather", ["bf16", "f32"])
 def test_dense_1000cube_full_size(gather):
     """Dense 1000^3 FP32, planted rank 10 + 1% noise, R = 10, s = 2^14, in the
@@ -89,7 +75,8 @@ def test_dense_1000cube_full_size(gather):
     tolerance."""
     n, R, s = 1000, 10, 1 << 14
     dims = (n, n, n)
-    X = _planted_dense_gpu(n, 10, seed=4)
+    from paper_2006_16438_amd import synth_gpu
+    X = synth_gpu.dense_planted(n, 10, seed=4)
     fac = synth.gaussian_factors(dims, R, 4)
     log(f"dense 1000^3 R={R} s={s} gather={gather}: init")
     ctx, F = make_ctx(_Shape(dims), fac, R, s, 1.0 / s, gather, dense_values_gpu=X)

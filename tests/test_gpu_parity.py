@@ -222,3 +222,33 @@ def test_tall_mode_atomic_gather(gather):
     log(f"tall mode atomic gather ({gather})")
     run_parity(T, fac, R, 2048, 1 / 2048, 3, gather, 1e-10 if gather == "f64" else 1e-4,
                label=f"tall-{gather}")
+
+
+@pytest.mark.parametrize("grid,sort_min", [(64, 0), (1024, 1 << 30), (300, 4)])
+def test_gather_launch_shapes(grid, sort_min):
+    """Results do not depend on the gather's launch shape: a tensor whose
+    mode-0 fibers are long (a 2048-position chunk spans one or two fibers,
+    the case that skips the row sort) and whose other modes have short ones
+    (many fibers per chunk, sorted), FP64, under grids smaller and larger
+    than the chip and every sort threshold."""
+    dims = (3000, 4, 3)
+    T = synth.random_sparse(dims, 30_000, seed=51)
+    R = 3
+    fac = concentrated(dims, R, 52)
+    log(f"gather launch shape grid={grid} sort_min={sort_min}")
+    run_parity(T, fac, R, 256, 1 / 256, 6, "f64", 1e-10, label=f"shape-{grid}-{sort_min}",
+               gather_config=(grid, sort_min))
+
+
+@pytest.mark.parametrize("gather", ["f64", "f32"])
+def test_autotune_then_parity(gather):
+    """The autotuner times the launch shapes on the decomposition's own state
+    and leaves factors, leverage and step unchanged; the updates after it
+    match the oracle."""
+    dims = (700, 300, 257)
+    T = synth.random_sparse(dims, 150_000, seed=21)
+    R = 8
+    fac = concentrated(dims, R, 22)
+    log(f"autotune then parity ({gather})")
+    run_parity(T, fac, R, 8192, 1 / 8192, 6, gather, 1e-10 if gather == "f64" else 1e-4,
+               label=f"autotune-{gather}", autotune=True)
