@@ -96,7 +96,9 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
 #define GT_PER_THREAD 4
 #define GT_CHUNK (GT_THREADS * GT_PER_THREAD)
 static_assert(GT_CHUNK == CPAL_GATHER_CHUNK, "gather chunk must match the preparation's");
-#define GT_WIN 4096
+// A chunk's window holds the fibers starting inside it (at most GT_CHUNK)
+// and the one overlapping its first position.
+#define GT_WIN (GT_CHUNK + 8)
 
 // Segmented gather: workgroup g takes the chunks g, g + G, ... of GT_CHUNK
 // stream positions; for a chunk
@@ -214,16 +216,24 @@ __device__ __forceinline__ unsigned *seg_load_sort(
 }
 
 // Step 3 over n row-sorted entries; entry q -> (row, x, KRP row) by get(q).
-template <typename T, int LPN, typename Get>
+// A lane group of LPN lanes takes one entry at a time, lane c holding the
+// columns c, c + LPN, ..., c + (CPL-1) LPN of the row (LPN * CPL = the
+// padded row width): with CPL = 2 a wave instruction serves four entries,
+// halving the per-entry bookkeeping.
+template <typename T, int LPN, int CPL, typename Get>
 __device__ __forceinline__ void seg_reduce(const Get &get, int n, int R,
                                            const T *__restrict__ zhat, int ldz,
-                                           T *__restrict__ M, int *srow, T (*svec)[LPN]) {
+                                           T *__restrict__ M, int *srow,
+                                           T (*svec)[LPN * CPL]) {
   constexpr int NG = GT_THREADS / LPN;
   constexpr int PER = GT_CHUNK / NG;
+  constexpr int B = GS_BATCH / CPL;
   const int tid = threadIdx.x, gi = tid / LPN, c = tid % LPN;
   const int q0 = gi * PER, q1 = min(n, q0 + PER);
   int cur = -1, first = -1;
-  T acc = T(0), facc = T(0);
+  T acc[CPL], facc[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) { acc[j] = T(0); facc[j] = T(0); }
   if (q0 < q1) {
     {
       unsigned r0;
@@ -232,50 +242,80 @@ __device__ __forceinline__ void seg_reduce(const Get &get, int n, int R,
       get(q0, r0, x0, z0);
       cur = (int)r0;
     }
-    for (int q = q0; q < q1; q += GS_BATCH) {
-      unsigned rr[GS_BATCH];
-      T xv[GS_BATCH], zv[GS_BATCH];
+    for (int q = q0; q < q1; q += B) {
+      unsigned rr[B];
+      T xv[B], zv[B][CPL];
 #pragma unroll
-      for (int b = 0; b < GS_BATCH; ++b) {
+      for (int b = 0; b < B; ++b) {
         unsigned zr;
         get(min(q + b, q1 - 1), rr[b], xv[b], zr);
-        zv[b] = zhat[(i64)zr * ldz + c];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) zv[b][j] = zhat[(i64)zr * ldz + c + j * LPN];
       }
 #pragma unroll
-      for (int b = 0; b < GS_BATCH; ++b) {
+      for (int b = 0; b < B; ++b) {
         if (q + b < q1) {
           const int r = (int)rr[b];
           if (r != cur) {
-            if (first < 0) { first = cur; facc = acc; }
-            else if (c < R) unsafeAtomicAdd(&M[(i64)cur * ldz + c], acc);
+            if (first < 0) {
+              first = cur;
+#pragma unroll
+              for (int j = 0; j < CPL; ++j) facc[j] = acc[j];
+            } else {
+#pragma unroll
+              for (int j = 0; j < CPL; ++j)
+                if (c + j * LPN < R) unsafeAtomicAdd(&M[(i64)cur * ldz + c + j * LPN], acc[j]);
+            }
             cur = r;
-            acc = T(0);
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) acc[j] = T(0);
           }
-          acc += xv[b] * zv[b];
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) acc[j] += xv[b] * zv[b][j];
         }
       }
     }
   }
   // slice ends: slot 2gi = first run, 2gi+1 = last run (-1: none)
-  if (first < 0) { first = cur; facc = acc; cur = -1; }
+  if (first < 0) {
+    first = cur;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) facc[j] = acc[j];
+    cur = -1;
+  }
   if (c == 0) { srow[2 * gi] = first; srow[2 * gi + 1] = cur; }
-  svec[2 * gi][c] = facc;
-  svec[2 * gi + 1][c] = acc;
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    svec[2 * gi][c + j * LPN] = facc[j];
+    svec[2 * gi + 1][c + j * LPN] = acc[j];
+  }
   __syncthreads();
   if (gi == 0 && n > 0) {
     int mr = -1;
-    T ma = T(0);
+    T ma[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) ma[j] = T(0);
     for (int sl = 0; sl < 2 * NG; ++sl) {
       const int r = srow[sl];
       if (r < 0) continue;
       if (r != mr) {
-        if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * ldz + c], ma);
+        if (mr >= 0) {
+#pragma unroll
+          for (int j = 0; j < CPL; ++j)
+            if (c + j * LPN < R) unsafeAtomicAdd(&M[(i64)mr * ldz + c + j * LPN], ma[j]);
+        }
         mr = r;
-        ma = T(0);
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) ma[j] = T(0);
       }
-      ma += svec[sl][c];
+#pragma unroll
+      for (int j = 0; j < CPL; ++j) ma[j] += svec[sl][c + j * LPN];
     }
-    if (mr >= 0 && c < R) unsafeAtomicAdd(&M[(i64)mr * ldz + c], ma);
+    if (mr >= 0) {
+#pragma unroll
+      for (int j = 0; j < CPL; ++j)
+        if (c + j * LPN < R) unsafeAtomicAdd(&M[(i64)mr * ldz + c + j * LPN], ma[j]);
+    }
   }
 }
 
@@ -293,8 +333,9 @@ struct LdsEntries {
 };
 
 // Two workgroups per CU (4 waves per SIMD: at most 128 VGPRs; the FP32
-// kernel's 78 KB of shared memory fits twice).
-template <typename T, int LPN>
+// kernel's shared memory fits twice).  Lane groups of LPN lanes, CPL columns
+// per lane (LPN * CPL = the padded row width ldz).
+template <typename T, int LPN, int CPL>
 __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
     const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
@@ -306,7 +347,7 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
   __shared__ unsigned lz[GT_CHUNK];
   __shared__ unsigned tab[64 * GT_PER_THREAD * (GT_THREADS / 64)];
   __shared__ int srow[2 * NG];
-  __shared__ T svec[2 * NG][LPN];
+  __shared__ T svec[2 * NG][LPN * CPL];
   const i64 total = st->gathered;
   const i64 nf = st->n_fib;
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
@@ -316,7 +357,7 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
     const unsigned *keys = seg_load_sort<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz,
                                             ikbits, sort_min, win, ka, kb, lx, lz, tab);
     const int nvalid = (int)(min(total, (ch + 1) * GT_CHUNK) - ch * GT_CHUNK);
-    seg_reduce<T, LPN>(LdsEntries<T>{keys, lx, lz}, nvalid, R, zhat, ldz, Mx, srow, svec);
+    seg_reduce<T, LPN, CPL>(LdsEntries<T>{keys, lx, lz}, nvalid, R, zhat, ldz, Mx, srow, svec);
   }
 }
 
@@ -331,15 +372,15 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
   const int rm = gather_row_width(R);
   if (f64) {
     NzLoad<double> nz{ik, v64};
-    auto k = rm == 16 ? k_gather_seg<double, 16> : rm == 32 ? k_gather_seg<double, 32>
-                                                            : k_gather_seg<double, 64>;
+    auto k = rm == 16 ? k_gather_seg<double, 16, 1>
+                      : rm == 32 ? k_gather_seg<double, 16, 2> : k_gather_seg<double, 32, 2>;
     hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
                        chunk_first, nz, ikbits, sort_min, (const double *)zhat, ldz, (double *)M,
                        nk);
   } else {
     NzLoad<float> nz{pairs};
-    auto k = rm == 16 ? k_gather_seg<float, 16> : rm == 32 ? k_gather_seg<float, 32>
-                                                           : k_gather_seg<float, 64>;
+    auto k = rm == 16 ? k_gather_seg<float, 16, 1>
+                      : rm == 32 ? k_gather_seg<float, 16, 2> : k_gather_seg<float, 32, 2>;
     hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
                        chunk_first, nz, ikbits, sort_min, (const float *)zhat, ldz, (float *)M,
                        nk);
