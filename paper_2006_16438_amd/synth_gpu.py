@@ -35,12 +35,13 @@ def _zipf_draw(cdf, perm, count, g, dev):
     return perm[i]
 
 
-def zipf_distinct(dims, nnz, a, seed, value_fn, chunk=1 << 28, max_chunks=64, verbose=False):
+def zipf_distinct(dims, nnz, a, seed, value_fn, chunk=1 << 28, max_chunks=64, verbose=False,
+                  device="cuda:0"):
     """First `nnz` distinct coordinates of a stream of per-mode Zipf(a) draws
     (mode 0 fastest in the linear key), with value_fn(count, g) drawing one
     value per draw.  Returns (coords int32 [D, nnz], values float32 [nnz]) on
-    cuda:0, ordered by linear key."""
-    dev = torch.device("cuda:0")
+    `device`, ordered by linear key."""
+    dev = torch.device(device)
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
     tables = [_zipf_table(n, a, g, dev) for n in dims]
