@@ -31,7 +31,9 @@ if ROOT not in sys.path:
 
 METRIC = "sampled ALS mode-updates/s + gathered rows/s, mixed/batched vs plain, fit Δ≤1e-3"
 HBM_PEAK_GBS = 8000.0
-CONV_ITERS = 100   # dense workload: iterations of the fit comparison between precisions
+CONV_ITERS = 400   # dense workload: iterations of the fit comparison between precisions
+                   # (from the seed-0 start every precision passes two swamps, fits 0.564 and
+                   # 0.689, and reaches the 1% noise floor, 0.990, by about 400 iterations)
 
 
 def gather_bytes(st, R, nk, elem=4):
@@ -43,12 +45,12 @@ def gather_bytes(st, R, nk, elem=4):
     return pair * st["gathered_nnz"] + (12 + elem * R) * st["s_bar"] + elem * R * nk
 
 
-def recorded_traffic(root):
-    """HBM bytes per launch of the gather kernel from the committed counter
-    summary (FETCH_SIZE / WRITE_SIZE runs), or None when the kernel source has
-    changed since the counters were taken."""
+def recorded_counters(root, name):
+    """The JSON record closing a committed counter summary under profiles/,
+    or None when the kernel source it names has changed since the counters
+    were taken."""
     import hashlib
-    path = os.path.join(root, "profiles", "gather_seg_uber4_traffic.txt")
+    path = os.path.join(root, "profiles", name)
     try:
         rec = json.loads(open(path).read().strip().splitlines()[-1])
         src = open(os.path.join(root, rec["source"]), "rb").read()
@@ -56,7 +58,14 @@ def recorded_traffic(root):
         return None
     if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec
+
+
+def recorded_traffic(root):
+    """HBM bytes per launch of the gather kernel (FETCH_SIZE / WRITE_SIZE
+    runs), or None when its source has changed since."""
+    rec = recorded_counters(root, "gather_seg_uber4_traffic.txt")
+    return rec.get("traffic_bytes_per_launch") if rec else None
 
 
 def log(msg):
@@ -75,6 +84,9 @@ def main():
                          "1000^3, BF16 on the matrix cores vs the plain FP32 path; batch256: "
                          "64 sparse tensors x 4 restarts stepped together vs one at a time; "
                          "large1e9: sparse 8211x176962x8116 with 1e9 nonzeros")
+    ap.add_argument("--conv-iters", type=int, default=CONV_ITERS,
+                    help="dense1000: iterations of the fit comparison between precisions "
+                         "(0: skip it)")
     ap.add_argument("--large-nnz", type=int, default=1_000_000_000,
                     help="nonzeros of the large1e9 workload")
     ap.add_argument("--cpu-updates", type=int, default=80,
@@ -94,6 +106,14 @@ def main():
               "(every box has one MI355X)", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration > 0:   # a plain device copy of known size for the counters
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "dense1000":
         bench_dense(args)
         return
@@ -111,13 +131,6 @@ def main():
     from paper_2006_16438_amd.api import CpArlsLev
 
     dev = torch.device("cuda:0")
-    if args.copy_calibration > 0:
-        n = args.copy_calibration * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     R, s, tau, s_fit = 25, 1 << 17, 2.0 ** -17, 1 << 20
     t0 = time.time()
     T = synth.uber4(0)
@@ -217,6 +230,10 @@ def main():
             "avg_launch_us": 1e3 * g_ms / max(g_cnt, 1),
         },
         "fit_estimated": fit_est,
+        "paper_context": "the paper gives no numeric times for the Uber tensor (figures only); "
+                         "its closest per-update figures are for Amazon (1.7e9 nonzeros, R=25, "
+                         "s=2^17: about 15-17 s per mode update, MATLAB FP64 on 2x AMD EPYC "
+                         "7452); context only",
         "gather_launch": {"autotuned": args.tune,
                           "grid_sort_min_per_mode": gcfg},
     }
@@ -322,8 +339,9 @@ def bench_dense(args):
     updates = K * 3
     # the sampled rows follow the factors, so runs in different precisions take
     # different paths; compare their fits again after CONV iterations
-    K_timed, K = K, CONV_ITERS
-    conv = {g: exact_fit_dense(X, run(g, False)[3]) for g in ("bf16", "f32", "f64")}
+    K_timed, K = K, args.conv_iters
+    conv = ({g: exact_fit_dense(X, run(g, False)[3]) for g in ("bf16", "f32", "f64")}
+            if K > 0 else {"bf16": math.nan, "f32": math.nan, "f64": math.nan})
     K = K_timed
 
     def roof(stage, sts, b):
@@ -334,6 +352,7 @@ def bench_dense(args):
         return byts / t / 1e9, flops / t / 1e12, byts / updates, 1e3 * g_ms / max(g_cnt, 1)
 
     gb, tf, bpl, us = roof(stage_b, sts_b, 2)
+    dense_rec = recorded_counters(ROOT, "dense1000_mfma_traffic.txt")
     gbf, tff, _, usf = roof(stage_f, sts_f, 4)
     result = {
         "metric": METRIC,
@@ -363,20 +382,21 @@ def bench_dense(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": gb / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (dense_rec or {}).get("bf16_update_traffic_bytes"),
             "algorithmic_bytes_per_launch": bpl,
             "avg_launch_us": us,
             "mfma_tflops": tf,
             "mfma_peak_tflops": 2500.0,
+            "mfma_busy_counter": (dense_rec or {}).get("bf16_mfma_busy"),
         },
         "plain_f32": {"value": updates / el_f, "unit": "mode-updates/s",
                       "contraction_gbs": gbf, "contraction_us": usf},
         "fit_exact": {"bf16": fit_b, "f32": fit_f, "f64_reference": fit_d},
         "fit_delta_bf16": abs(fit_b - fit_d),
         "fit_delta_f32": abs(fit_f - fit_d),
-        f"fit_exact_after_{CONV_ITERS}_iterations": conv,
-        f"fit_delta_bf16_after_{CONV_ITERS}": abs(conv["bf16"] - conv["f64"]),
-        f"fit_delta_f32_after_{CONV_ITERS}": abs(conv["f32"] - conv["f64"]),
+        f"fit_exact_after_{args.conv_iters}_iterations": conv,
+        f"fit_delta_bf16_after_{args.conv_iters}": abs(conv["bf16"] - conv["f64"]),
+        f"fit_delta_f32_after_{args.conv_iters}": abs(conv["f32"] - conv["f64"]),
         "factor_rel_err_bf16": fac_err(F_b),
         "factor_rel_err_f32": fac_err(F_f),
         "cpu_baseline": None,
@@ -650,6 +670,10 @@ def bench_large(args):
         "cpu_baseline": None,
         "cpu_baseline_note": "the FP64 oracle cannot hold 1e9 nonzeros; the FP64-gather GPU "
                              "path (oracle parity 1e-10) is the reference",
+        "paper_context": "Sec. 7 (Reddit tensor 8.2e6 x 176962 x 8.1e6, 4.7e9 nonzeros, R=25, "
+                         "hybrid s=2^17): 2231 s per epoch of 15 mode updates, about 149 s per "
+                         "update, MATLAB FP64 on 2x AMD EPYC 7601 (64 cores); a 4.7x larger "
+                         "tensor on other hardware, context only",
     }
     print(json.dumps(result), flush=True)
 
