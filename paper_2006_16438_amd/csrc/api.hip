@@ -70,7 +70,6 @@ void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const u
 void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, int ldm,
                        int ncopies,
                        const Decomp *dc, double *A, float *A32, hipStream_t s);
-void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s);
 void launch_to_f32(const double *a, float *b, i64 n, hipStream_t s);
 void launch_mode_keys(const int *coords, i64 nnz, int D, const OtherModes &om, i64 nk, u64 *comp,
                       unsigned *ids, int *err, hipStream_t s);
@@ -299,7 +298,9 @@ OtherModes others_of(const cpal_ctx *c, int k) {
 }
 
 // Leverage of mode m from the current factor (Def. 3.4), cached.
-void refresh_leverage(cpal_ctx *c, int m) {
+// Leverage scores, weights and CDF of factor m (Def. 3.4); stats (nullable)
+// receives the statistics of the update of mode m that produced the factor.
+void refresh_leverage(cpal_ctx *c, int m, cpal_mode_stats *stats = nullptr) {
   Mode &md = c->mode[m];
   const int *skip = nullptr;
   if (md.n < c->R) {
@@ -312,7 +313,8 @@ void refresh_leverage(cpal_ctx *c, int m) {
   const int nblk = (int)((md.n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
   launch_decomp(c->lev_part, nblk, c->R, c->dc, &c->st->lev_pinv[m], skip, c->stream);
   launch_lev_rows(md.A, md.n, c->R, c->dc, md.lev, md.w, c->lev_bsum, skip, c->stream);
-  launch_lev_cdf(md.w, md.n, c->R, c->lev_bsum, md.C, md.q, nullptr, c->stream);
+  launch_lev_cdf(md.w, md.n, c->R, c->lev_bsum, md.C, md.q, nullptr, c->st, m, c->D, stats,
+                 c->stream);
 }
 
 cpal_status check_hip(cpal_ctx *c, hipError_t e, const char *what) {
@@ -727,9 +729,8 @@ void update_back(cpal_ctx *c, int k, cpal_mode_stats *stats_dev) {
   launch_solve_rows(c->f64, c->st, md.n, R, c->M, c->ldz, ncopies, c->dc, md.A, md.A32, s);
   c->stage_end(CPAL_STAGE_SOLVE, tb);
   tb = c->stage_begin(CPAL_STAGE_LEVERAGE);
-  refresh_leverage(c, k);
+  refresh_leverage(c, k, stats_dev);   // its last kernel also writes the statistics
   c->stage_end(CPAL_STAGE_LEVERAGE, tb);
-  if (stats_dev) launch_stats(c->st, k, c->D, stats_dev, s);
 }
 
 }  // namespace

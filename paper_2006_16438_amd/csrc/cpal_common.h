@@ -270,7 +270,8 @@ void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_s
 void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *lev, u64 *w,
                      u64 *blocksum, const int *skip, hipStream_t s);
 void launch_lev_cdf(const u64 *w, i64 n, int R, const u64 *blocksum, u64 *C, double *q,
-                    int *flag_or, hipStream_t s);
+                    int *flag_or, const DevState *st, int k, int D, cpal_mode_stats *stats,
+                    hipStream_t s);
 
 // radix sort of u64 keys with optional u32 payload, device-resident count --
 size_t sort_scratch_bytes(i64 cap, bool with_vals);

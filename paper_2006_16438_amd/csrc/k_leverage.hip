@@ -529,7 +529,24 @@ __global__ void __launch_bounds__(256) k_lev_rows(const double *__restrict__ A, 
 __global__ void __launch_bounds__(CDF_ROWS) k_lev_cdf(const u64 *__restrict__ w, i64 n,
                                                      const u64 *__restrict__ blocksum, int nbs,
                                                      int rb, u64 *__restrict__ C,
-                                                     double *__restrict__ q, int *flag_or) {
+                                                     double *__restrict__ q, int *flag_or,
+                                                     const DevState *st, int k, int D,
+                                                     cpal_mode_stats *stats) {
+  // the update's statistics, when asked for (this is the update's last kernel;
+  // every count and flag is final by now)
+  if (stats && blockIdx.x == 0 && threadIdx.x == 0) {
+    int fl = st->flags;
+    for (int m = 0; m < D; ++m)
+      if (m != k && st->lev_pinv[m]) fl |= CPAL_FLAG_PINV;
+    stats->s_det = st->s_det;
+    stats->s_rnd = st->s_rnd_used;
+    stats->s_bar = st->s_bar;
+    stats->draws = st->draws;
+    stats->gathered_nnz = st->gathered;
+    stats->p_det = st->p_det;
+    stats->flags = fl;
+    stats->pad = 0;
+  }
   const int lim = (int)(blockIdx.x * (CDF_ROWS / rb));
   u64 before = 0, all = 0;
   for (int b = threadIdx.x; b < nbs; b += blockDim.x) {
@@ -591,12 +608,13 @@ void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *le
 }
 
 void launch_lev_cdf(const u64 *w, i64 n, int R, const u64 *blocksum, u64 *C, double *q,
-                    int *flag_or, hipStream_t s) {
+                    int *flag_or, const DevState *st, int k, int D, cpal_mode_stats *stats,
+                    hipStream_t s) {
   const int rb = lev_rows_per_block(R);
   const int nbs = (int)((n + rb - 1) / rb);
   const int nblk = (int)((n + CDF_ROWS - 1) / CDF_ROWS);
   hipLaunchKernelGGL(k_lev_cdf, dim3(nblk), dim3(CDF_ROWS), 0, s, w, n, blocksum, nbs, rb, C, q,
-                     flag_or);
+                     flag_or, st, k, D, stats);
 }
 
 int lev_row_blocks(i64 n) { return (int)((n + 3) / 4); }   // blocksums at 4 rows per block

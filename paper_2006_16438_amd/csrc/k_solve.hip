@@ -1,5 +1,5 @@
-// Solve of the sketched normal equations, A_k = M G_s^{-1} (eq. (1.2)), the
-// update statistics and the FP32 factor mirror.
+// Solve of the sketched normal equations, A_k = M G_s^{-1} (eq. (1.2)), and
+// the FP32 factor mirror.
 #include "cpal_common.h"
 
 namespace cpal {
@@ -85,20 +85,6 @@ __global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, i
   }
 }
 
-__global__ void k_stats(const DevState *st, int k, int D, cpal_mode_stats *out) {
-  int fl = st->flags;
-  for (int m = 0; m < D; ++m)
-    if (m != k && st->lev_pinv[m]) fl |= CPAL_FLAG_PINV;
-  out->s_det = st->s_det;
-  out->s_rnd = st->s_rnd_used;
-  out->s_bar = st->s_bar;
-  out->draws = st->draws;
-  out->gathered_nnz = st->gathered;
-  out->p_det = st->p_det;
-  out->flags = fl;
-  out->pad = 0;
-}
-
 __global__ void k_to_f32(const double *__restrict__ a, float *__restrict__ b, i64 n) {
   for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
     b[i] = (float)a[i];
@@ -121,10 +107,6 @@ void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M
     hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const float *)M, ldm, ncopies, dc, A,
                        A32);
   }
-}
-
-void launch_stats(const DevState *st, int k, int D, cpal_mode_stats *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1), 0, s, st, k, D, out);
 }
 
 void launch_to_f32(const double *a, float *b, i64 n, hipStream_t s) {

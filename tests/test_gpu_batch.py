@@ -18,10 +18,13 @@ from tests.gpu_util import dense_values, log, rel_err
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("graphs", [False, True])
+@pytest.mark.parametrize("graphs", [False, True, "autotune"])
 def test_batch_mixed_parity(graphs):
     """graphs=True: every mode step after the first replays the captured
-    graph of that mode; each replay is checked against the oracle."""
+    graph of that mode; each replay is checked against the oracle.
+    graphs="autotune": as True, and after the first iteration the autotuner
+    changes the launch shapes, which drops the captured graphs (the next
+    steps capture again with the new shapes)."""
     from paper_2006_16438_amd.api import CpArlsLevBatch
     dev = torch.device("cuda:0")
     A = synth.random_sparse((30, 25, 20), 3000, seed=5)
@@ -44,11 +47,15 @@ def test_batch_mixed_parity(graphs):
                 for f in synth.gaussian_factors(tensors_np[t].dims, ranks[i], 10 + i)]
                for i, t in enumerate(tensor_of)]
     b = CpArlsLevBatch(tensors, tensor_of, factors, ranks, samples, seeds=3,
-                       stream_ids=stream_ids, gather_dtype="f64", use_graphs=graphs)
+                       stream_ids=stream_ids, gather_dtype="f64", use_graphs=bool(graphs))
     OTs = [oracle.Tensor.from_synth(T) for T in tensors_np]
     members = [b.member(i) for i in range(len(tensor_of))]
     max_order = max(len(T.dims) for T in tensors_np)
     for it in range(3):
+        if graphs == "autotune" and it == 1:
+            b.autotune()
+            log("autotuned: " + str([members[i].gather_config(k) for i in range(len(tensor_of))
+                                     for k in range(len(tensors_np[tensor_of[i]].dims))]))
         for k in range(max_order):
             refs = {}
             for i, t in enumerate(tensor_of):
