@@ -306,8 +306,11 @@ def bench_dense(args):
     def run(gather, timed):
         def new_ctx():
             F = [torch.from_numpy(f.copy()).to(dev) for f in fac0]
-            return CpArlsLev(dims, None, X, F, R, s, tau=tau, seed=0, stream_id=0,
-                             gather_dtype=gather), F
+            ctx = CpArlsLev(dims, None, X, F, R, s, tau=tau, seed=0, stream_id=0,
+                            gather_dtype=gather)
+            if args.tune:   # split of the sampled fibers, timed on this state
+                ctx.autotune()
+            return ctx, F
         if timed and args.warmup > 0:
             ctx, F = new_ctx()
             for _ in range(args.warmup):

@@ -176,10 +176,13 @@ cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *cou
  * grid = workgroups (0: the library's default), sort_min = the segmented
  * gather (modes of at most 2^20 rows) keeps the nonzeros of a 2048-position
  * chunk in stream order instead of sorting them by row when the chunk spans
- * at most sort_min sampled fibers (0: always sort).  Results do not depend
- * on either beyond the rounding order of the FP32/FP64 sums.  Host-side
- * setting, takes effect at the next mode update; grid in [0, 2^20],
- * sort_min >= 0, else CPAL_E_ARG. */
+ * at most sort_min sampled fibers (0: always sort).  Dense tensors: grid =
+ * workgroups along the sampled fibers of the split contraction (each writes
+ * one partial M; at most the default, which get_gather_config reports;
+ * sort_min unused).  Results do not depend on either beyond the rounding
+ * order of the FP32/FP64 sums.  Host-side setting, takes effect at the next
+ * mode update; grid in [0, 2^20] (dense: [0, default]), sort_min >= 0, else
+ * CPAL_E_ARG. */
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *ctx, int32_t k, int32_t grid,
                                           int32_t sort_min);
 /* The launch shape mode k uses (grid_host: the effective workgroup count). */
@@ -190,10 +193,10 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_
  * system of an update of that mode at the current step (sampling, KRP rows,
  * fiber probes; the factors, leverage scores and step counter are left as
  * they were), times the gather over a fixed set of grids (and, for the
- * segmented gather, sort thresholds) with HIP events, best of `reps` runs
- * each (0: 2, at most 16), and keeps the fastest shape for the mode.
- * Synchronizes the stream and is not graph-capturable.  Dense tensors have
- * one launch shape per rank: returns CPAL_OK without timing. */
+ * segmented gather, sort thresholds; for dense tensors the default split of
+ * the sampled fibers and 1/2, 1/4, 1/8 of it) with HIP events, best of
+ * `reps` runs each (0: 2, at most 16), and keeps the fastest shape for the
+ * mode.  Synchronizes the stream and is not graph-capturable. */
 cpal_status cp_arls_lev_autotune(cpal_ctx *ctx, int32_t reps);
 
 /* Text of the last error on this context (never NULL). */

@@ -665,7 +665,17 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
 namespace {
 
 int default_gather_grid(const cpal_ctx *c, int k) {
+  if (c->dense) return c->dnch;
   return c->mode[k].n <= (1 << 20) ? c->gs_grid : c->gather_grid;
+}
+
+// Dense contraction with `nch` workgroups along the sampled fibers (at most
+// the c->dnch the partials are sized for): sampled fibers per workgroup, a
+// multiple of 16.
+int dense_kc(const cpal_ctx *c, int nch) {
+  if (nch <= 0 || nch > c->dnch) nch = c->dnch;
+  i64 kc = ((c->s + nch - 1) / nch + 15) / 16 * 16;
+  return (int)std::min<i64>(std::max<i64>(kc, c->dkc), 1024);
 }
 
 // Steps of one mode update before the gather: SkrpLev's deterministic and
@@ -706,9 +716,11 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
   Mode &md = c->mode[k];
   const int R = c->R;
   if (grid <= 0) grid = default_gather_grid(c, k);
-  if (c->dense)   // M = X~^T diag(omega) Z on the matrix cores
+  if (c->dense) {   // M = X~^T diag(omega) Z on the matrix cores
+    const int kc = dense_kc(c, grid);
     launch_dense_mttkrp(c->zdt, c->st, md.n, R, c->ldz, md.dld, c->cidx, c->samp_idx, md.dX,
-                        c->zhat, c->dpart, c->dkc, c->dnch, c->M, s);
+                        c->zhat, c->dpart, kc, (int)((c->s + kc - 1) / kc), c->M, s);
+  }
   else if (md.n <= (1 << 20))
     launch_gather_seg(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                       md.ik, md.v64, md.n, c->zhat, c->ldz, c->M, grid, sort_min, s);
@@ -758,6 +770,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *c, int32_t k, int32_t grid, int32_t sort_min) {
   if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < 0)
     return CPAL_E_ARG;
+  if (c->dense && grid > c->dnch) return CPAL_E_ARG;
   c->mode[k].g_grid = grid;
   c->mode[k].g_sort_min = sort_min;
   return CPAL_OK;
@@ -767,6 +780,10 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *c, int32_t k, int32_t 
                                           int32_t *sort_min) {
   if (!c || k < 0 || k >= c->D || !grid || !sort_min) return CPAL_E_ARG;
   *grid = c->mode[k].g_grid ? c->mode[k].g_grid : default_gather_grid(c, k);
+  if (c->dense) {   // the effective workgroups along the sampled fibers
+    const int kc = dense_kc(c, *grid);
+    *grid = (int)((c->s + kc - 1) / kc);
+  }
   *sort_min = c->mode[k].g_sort_min;
   return CPAL_OK;
 }
@@ -774,7 +791,6 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *c, int32_t k, int32_t 
 cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
   if (!c || reps < 0 || reps > 16) return CPAL_E_ARG;
   if (c->failed) return fail(c, CPAL_E_STATE, "context failed earlier");
-  if (c->dense) return CPAL_OK;   // the dense contraction has one launch shape per rank
   if (reps == 0) reps = 2;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -789,17 +805,21 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
     // the sampled system of an update of mode k at the current step, as
     // mode_update would build it; the factors are not touched
     update_front(c, k);
-    const bool seg = md.n <= (1 << 20);
+    const bool seg = !c->dense && md.n <= (1 << 20);
     static const int seg_grids[] = {256, 512, 1024, 2048};
     static const int seg_sort[] = {0, 4, 32, 1 << 30};
     static const int flat_grids[] = {1024, 2048, 4096, 8192};
-    const i64 mwords = (i64)m_copies(md.n) * md.n * c->ldz * (c->f64 ? 2 : 1);
+    // dense: workgroups along the sampled fibers (fewer, longer ones write
+    // fewer partials of M); the contraction writes M itself (nothing to clear)
+    const int dense_grids[] = {c->dnch, std::max(1, c->dnch / 2), std::max(1, c->dnch / 4),
+                               std::max(1, c->dnch / 8)};
+    const i64 mwords = c->dense ? 0 : (i64)m_copies(md.n) * md.n * c->ldz * (c->f64 ? 2 : 1);
     float best = 1e30f;
     int best_grid = 0, best_sort = 0;
     const int ng = 4, ns = seg ? 4 : 1;
     for (int gi = 0; gi < ng && res == CPAL_OK; ++gi)
       for (int si = 0; si < ns && res == CPAL_OK; ++si) {
-        const int grid = seg ? seg_grids[gi] : flat_grids[gi];
+        const int grid = c->dense ? dense_grids[gi] : seg ? seg_grids[gi] : flat_grids[gi];
         const int smin = seg ? seg_sort[si] : 0;
         float tmin = 1e30f;
         for (int r = 0; r < reps; ++r) {

@@ -123,3 +123,24 @@ def test_dense_1000cube_full_size(gather):
 class _Shape:
     def __init__(self, dims):
         self.dims = dims
+
+
+@pytest.mark.parametrize("split", ["quarter", "autotune"])
+def test_dense_split_shapes(split):
+    """The split of the sampled fibers over workgroups (one partial M each)
+    changes only the rounding order: FP64 parity under a quarter of the
+    default split, and after the autotuner (which leaves factors, leverage
+    and step unchanged)."""
+    T, _ = synth.planted((40, 30, 20), 4, seed=0, density=1.0, law="normal")
+    R, s = 6, 4096
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    if split == "quarter":
+        ctx, _ = make_ctx(T, fac, R, s, 1.0 / s, "f64", dense=True)
+        default = ctx.gather_config(0)[0]
+        ctx.close()
+        log(f"dense split: default {default} workgroups along the fibers, running {default // 4}")
+        run_parity(T, fac, R, s, 1.0 / s, 3, gather="f64", ftol=FTOL["f64"],
+                   label="dense-split", dense=True, gather_config=(max(1, default // 4), 0))
+    else:
+        run_parity(T, fac, R, s, 1.0 / s, 3, gather="f64", ftol=FTOL["f64"],
+                   label="dense-autotune", dense=True, autotune=True)
