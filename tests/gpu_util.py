@@ -153,11 +153,13 @@ def sampled_solve_torch(dims, coords, vals, F, k, idx, om):
         Z *= F[m][(idx // st) % dims[m]]
     rep = torch.repeat_interleave(torch.arange(idx.numel(), device=idx.device), lens)
     start = torch.cumsum(lens, 0) - lens
-    pos = lo[rep] + (torch.arange(rep.numel(), device=idx.device) - start[rep])
-    e = perm[pos]
-    ik = coords[k][e].long()
-    x = vals[e].double()
     M = torch.zeros((dims[k], R), dtype=torch.float64, device=idx.device)
-    M.index_add_(0, ik, (om[rep] * x)[:, None] * Z[rep])
+    step = 1 << 24   # entries per accumulation chunk (bounded temporaries)
+    for a in range(0, rep.numel(), step):
+        r = rep[a:a + step]
+        pos = lo[r] + (torch.arange(a, a + r.numel(), device=idx.device) - start[r])
+        e = perm[pos]
+        M.index_add_(0, coords[k][e].long(), (om[r] * vals[e].double())[:, None] * Z[r])
+        del r, pos, e
     G = Z.T @ (om[:, None] * Z)
     return torch.linalg.solve(G, M.T).T, int(rep.numel())

@@ -69,3 +69,46 @@ def test_large3_shape_parity(large_tensor, gather):
         del A_ref, Fh
     ctx.close()
     torch.cuda.empty_cache()
+
+
+def test_large3_full_size_fp32():
+    """The benchmark's 10^9-nonzero tensor in the benchmark's launch
+    configuration (FP32 gather, default launch shapes), one iteration from
+    the benchmark's initial factors: per mode the sample equals the
+    oracle's and the factor an FP64 solve of the same sampled system built
+    with torch from its definition (1e-4)."""
+    from paper_2006_16438_amd import synth_gpu
+    from paper_2006_16438_amd.api import CpArlsLev
+    torch.cuda.empty_cache()
+    log("generating the 1e9-nonzero tensor")
+    dims, coords, vals = synth_gpu.large3(0, verbose=False)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    R, s = 25, 1 << 17
+    dev = coords.device
+    fac = synth.gaussian_factors(dims, R, 0)
+    F = [torch.from_numpy(f.copy()).to(dev) for f in fac]
+    ctx = CpArlsLev(dims, coords, vals, F, R, s, tau=1.0 / s, seed=0, stream_id=0,
+                    gather_dtype="f32")
+    OT = oracle.Tensor(np.array(dims), np.zeros((3, 1), dtype=np.int32), np.ones(1))
+    for k in range(3):
+        host = [f.cpu().numpy().copy() for f in F]
+        ref = oracle.mode_update(OT, [h.copy() for h in host], k, ctx.step, R, s, 1.0 / s)
+        ctx.mode_update(k)
+        st = ctx.last_stats()
+        idx, om, w = ctx.samples_view()
+        assert np.array_equal(idx.cpu().numpy().view(np.uint64), ref["idx"]), \
+            f"mode {k}: sample indices differ"
+        assert np.array_equal(om.cpu().numpy(), ref["omega"]), f"mode {k}: omega differs"
+        assert np.array_equal(w.cpu().numpy(), ref["wgt"]), f"mode {k}: weights differ"
+        Fh = [torch.from_numpy(h).to(dev) for h in host]
+        A_ref, nnz_g = sampled_solve_torch(dims, coords, vals, Fh, k, idx, om)
+        assert nnz_g == st["gathered_nnz"]
+        err = rel_err(F[k].cpu().numpy(), A_ref.cpu().numpy())
+        log(f"  mode {k}: s_bar={idx.numel()} gathered nnz={nnz_g} factor rel err {err:.3e}")
+        assert err <= FTOL["f32"], f"mode {k}: factor rel err {err:.3e}"
+        del A_ref, Fh
+        torch.cuda.empty_cache()
+    ctx.close()
+    del coords, vals, F
+    torch.cuda.empty_cache()
