@@ -93,14 +93,16 @@ def main():
                     help="mode updates of the CPU oracle baseline (20 iterations = 80)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", choices=["on", "off"], default=None,
-                    help="time the gather launch shapes first (cp_arls_lev_autotune); default "
-                         "on for batch256, off for the single decompositions (whose default "
-                         "shapes measured as fast as the tuned ones)")
+                    help="time the gather launch shapes after the warm-up (cp_arls_lev_autotune); "
+                         "default on for batch256 and large1e9 (where the bucketed gather wins), "
+                         "off for uber4 and dense1000 (whose default shapes measured as fast as "
+                         "the tuned ones)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB mebibytes (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
-    args.tune = (args.autotune or ("on" if args.workload == "batch256" else "off")) == "on"
+    args.tune = (args.autotune or ("on" if args.workload in ("batch256", "large1e9")
+                                   else "off")) == "on"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(every box has one MI355X)", file=sys.stderr)
@@ -576,10 +578,6 @@ def bench_large(args):
                         gather_dtype=gather)
         torch.cuda.synchronize()
         t_init = time.time() - t1
-        if args.tune:
-            t1 = time.time()
-            cfg = ctx.autotune()
-            log(f"{gather}: autotuned gather shapes {cfg} in {time.time() - t1:.1f}s")
         log(f"{gather}: context initialised in {t_init:.1f}s "
             f"(device memory in use {torch.cuda.memory_allocated() / 2**30:.1f} GiB by torch)")
         if timed and args.warmup > 0:
@@ -587,6 +585,10 @@ def bench_large(args):
                 for k in range(3):
                     ctx.mode_update(k, stats=False)
             torch.cuda.synchronize()
+            if args.tune:   # launch shapes timed on the warmed-up state
+                t1 = time.time()
+                cfg = ctx.autotune()
+                log(f"{gather}: autotuned gather shapes {cfg} in {time.time() - t1:.1f}s")
             for m in range(3):   # back to the initial state
                 F[m].copy_(torch.from_numpy(fac0[m]))
                 ctx.refresh(m)
@@ -621,6 +623,10 @@ def bench_large(args):
         return el, stage, stage_all, sts, F, fit, t_init, cfg
 
     el, stage, stage_all, sts, F32, fit32, t_init, gcfg = run("f32", True)
+    gather_label = ("fiber gather + sampled MTTKRP, whole stage per update: "
+                    + ", ".join(f"mode {k} " + ("bucketed (k_bkt_count, scan, k_bkt_scatter, "
+                                                "k_gather_bkt)" if sm < 0 else "k_gather_seg")
+                                for k, (g, sm) in enumerate(gcfg)))
     updates = K * 3
     gbytes = sum(gather_bytes(x, R, dims[i % 3], 4) for i, x in enumerate(sts))
     g_ms, g_cnt = stage["gather"]
@@ -653,7 +659,7 @@ def bench_large(args):
         "gathered_nnz_per_update": [x["gathered_nnz"] for x in sts[:3]],
         "stage_ms_per_update": {k: v[0] / max(v[1], 1) for k, v in stage_all.items()},
         "roofline": {
-            "kernel": "k_gather_seg (fiber gather + sampled MTTKRP)",
+            "kernel": gather_label,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

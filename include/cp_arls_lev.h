@@ -176,13 +176,19 @@ cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *cou
  * grid = workgroups (0: the library's default), sort_min = the segmented
  * gather (modes of at most 2^20 rows) keeps the nonzeros of a 2048-position
  * chunk in stream order instead of sorting them by row when the chunk spans
- * at most sort_min sampled fibers (0: always sort).  Dense tensors: grid =
+ * at most sort_min sampled fibers (0: always sort); sort_min = -1 selects the
+ * bucketed gather instead (FP32 gather, modes of at most 2^20 rows): the
+ * sampled nonzeros are first moved into 4096 buckets of consecutive output
+ * rows, so that the adds of different fibers to one row are summed on chip
+ * (it allocates 12 bytes per stored nonzero plus 48 MB on first use; its
+ * sums are in a timing-dependent order).  Dense tensors: grid =
  * workgroups along the sampled fibers of the split contraction (each writes
  * one partial M; at most the default, which get_gather_config reports;
  * sort_min unused).  Results do not depend on either beyond the rounding
  * order of the FP32/FP64 sums.  Host-side setting, takes effect at the next
- * mode update; grid in [0, 2^20] (dense: [0, default]), sort_min >= 0, else
- * CPAL_E_ARG. */
+ * mode update; grid in [0, 2^20] (dense: [0, default]), sort_min >= -1 (-1
+ * only where the bucketed gather applies), else CPAL_E_ARG; CPAL_E_NOMEM if
+ * the bucketed gather's buffers cannot be allocated. */
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *ctx, int32_t k, int32_t grid,
                                           int32_t sort_min);
 /* The launch shape mode k uses (grid_host: the effective workgroup count). */
@@ -193,7 +199,8 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_
  * system of an update of that mode at the current step (sampling, KRP rows,
  * fiber probes; the factors, leverage scores and step counter are left as
  * they were), times the gather over a fixed set of grids (and, for the
- * segmented gather, sort thresholds; for dense tensors the default split of
+ * segmented gather, sort thresholds and the bucketed gather, whose buffers
+ * it allocates where they fit; for dense tensors the default split of
  * the sampled fibers and 1/2, 1/4, 1/8 of it) with HIP events, best of
  * `reps` runs each (0: 2, at most 16), and keeps the fastest shape for the
  * mode.  Synchronizes the stream and is not graph-capturable. */

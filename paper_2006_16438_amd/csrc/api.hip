@@ -27,6 +27,12 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz, void *M,
                        int grid, int sort_min, hipStream_t s);
 void launch_zero_words(void *p, i64 nwords, hipStream_t s);
+size_t gather_bkt_count_words();
+void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                       const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
+                       i64 nk, const float *zhat, int ldz, float *M, int grid, unsigned *cnt,
+                       u64 *off, void *scan_scratch, uint2 *bpair, unsigned *bz,
+                       hipStream_t s);
 int lev_row_blocks(i64 n);
 void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
                   void *scratch, hipStream_t s);
@@ -191,6 +197,13 @@ struct cpal_ctx {
   int ldz = 0;                  // row stride of the weighted KRP rows (16-byte multiple)
   int gs_grid = 512;            // workgroups of the segmented gather
   unsigned *chunk_first = nullptr;  // first nonempty fiber of each gather chunk
+  // bucketed gather (allocated when a mode first uses it): counts and offsets
+  // per (bucket, workgroup), scan scratch, nonzeros moved into buckets
+  unsigned *bk_cnt = nullptr;
+  u64 *bk_off = nullptr;
+  void *bk_scan = nullptr;
+  uint2 *bk_pair = nullptr;
+  unsigned *bk_z = nullptr;
   u64 *cpos = nullptr;              // nonempty fibers: stream position,
   unsigned *coff = nullptr;         //   offset in the mode-sorted nonzeros,
   unsigned *cidx = nullptr;         //   sampled row
@@ -710,7 +723,28 @@ void update_front(cpal_ctx *c, int k) {
   c->stage_end(CPAL_STAGE_ROWS, tb);
 }
 
-// TnsrSamp + sampled MTTKRP (Sec. 6.3, eq. (1.2)) into M.
+// The bucketed gather's buffers (FP32 sparse contexts; nonzeros up to nnz).
+cpal_status ensure_bucket_buffers(cpal_ctx *c) {
+  if (c->bk_pair) return CPAL_OK;
+  try {
+    const size_t nw = gather_bkt_count_words();
+    c->bk_cnt = c->alloc<unsigned>(nw);
+    c->bk_off = c->alloc<u64>(nw);
+    c->bk_scan = c->alloc<char>(scan_scratch_bytes((i64)nw));
+    c->bk_z = c->alloc<unsigned>((size_t)c->nnz);
+    c->bk_pair = c->alloc<uint2>((size_t)c->nnz);
+  } catch (cpal_status st) {
+    return st;
+  }
+  return CPAL_OK;
+}
+
+bool bucket_capable(const cpal_ctx *c, int k) {
+  return !c->dense && !c->f64 && c->mode[k].n <= (1 << 20);
+}
+
+// TnsrSamp + sampled MTTKRP (Sec. 6.3, eq. (1.2)) into M.  sort_min < 0
+// selects the bucketed gather (bucket_capable modes).
 void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
   hipStream_t s = c->stream;
   Mode &md = c->mode[k];
@@ -721,9 +755,13 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
     launch_dense_mttkrp(c->zdt, c->st, md.n, R, c->ldz, md.dld, c->cidx, c->samp_idx, md.dX,
                         c->zhat, c->dpart, kc, (int)((c->s + kc - 1) / kc), c->M, s);
   }
+  else if (sort_min < 0 && c->bk_pair && bucket_capable(c, k))
+    launch_gather_bkt(c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs, md.n,
+                      (const float *)c->zhat, c->ldz, (float *)c->M, grid, c->bk_cnt, c->bk_off,
+                      c->bk_scan, c->bk_pair, c->bk_z, s);
   else if (md.n <= (1 << 20))
     launch_gather_seg(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
-                      md.ik, md.v64, md.n, c->zhat, c->ldz, c->M, grid, sort_min, s);
+                      md.ik, md.v64, md.n, c->zhat, c->ldz, c->M, grid, std::max(sort_min, 0), s);
   else
     launch_gather(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, c->zhat,
                   c->M, c->ldz, grid, s);
@@ -768,9 +806,14 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
 }
 
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *c, int32_t k, int32_t grid, int32_t sort_min) {
-  if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < 0)
+  if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < -1)
     return CPAL_E_ARG;
   if (c->dense && grid > c->dnch) return CPAL_E_ARG;
+  if (sort_min < 0) {   // the bucketed gather
+    if (!bucket_capable(c, k)) return CPAL_E_ARG;
+    const cpal_status st = ensure_bucket_buffers(c);
+    if (st != CPAL_OK) return fail(c, st, "bucketed gather: buffers");
+  }
   c->mode[k].g_grid = grid;
   c->mode[k].g_sort_min = sort_min;
   return CPAL_OK;
@@ -816,11 +859,13 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
     const i64 mwords = c->dense ? 0 : (i64)m_copies(md.n) * md.n * c->ldz * (c->f64 ? 2 : 1);
     float best = 1e30f;
     int best_grid = 0, best_sort = 0;
-    const int ng = 4, ns = seg ? 4 : 1;
+    // the bucketed gather (sort threshold -1) when its buffers can be had
+    const bool bkt = bucket_capable(c, k) && ensure_bucket_buffers(c) == CPAL_OK;
+    const int ng = 4, ns = seg ? (bkt ? 5 : 4) : 1;
     for (int gi = 0; gi < ng && res == CPAL_OK; ++gi)
       for (int si = 0; si < ns && res == CPAL_OK; ++si) {
         const int grid = c->dense ? dense_grids[gi] : seg ? seg_grids[gi] : flat_grids[gi];
-        const int smin = seg ? seg_sort[si] : 0;
+        const int smin = !seg ? 0 : si < 4 ? seg_sort[si] : -1;
         float tmin = 1e30f;
         for (int r = 0; r < reps; ++r) {
           launch_zero_words(c->M, mwords, c->stream);

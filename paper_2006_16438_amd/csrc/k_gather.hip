@@ -7,6 +7,10 @@
 
 namespace cpal {
 
+void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
+                  void *scratch, hipStream_t s);
+int gather_row_width(int R);
+
 // ------------------------------------------------------------------ gather --
 // The sampled fibers form one stream of nnz(X~) = sum_j len_j nonzeros; wave
 // w takes stream positions [64c, 64c+64) for c = w, w + #waves, ...  A lane
@@ -120,6 +124,57 @@ static_assert(GT_CHUNK == CPAL_GATHER_CHUNK, "gather chunk must match the prepar
 #define GS_DIG 6
 #define GS_BATCH 16   // sorted entries a lane group loads ahead (fits 128 VGPRs)
 
+// Stable LSD radix sort of the chunk's GT_CHUNK keys ka (row << 12 |
+// position) on key bits [12, 12 + bits), 6-bit digits ranked with wave
+// ballots; returns the buffer holding the result (ka or kb).
+__device__ __forceinline__ unsigned *chunk_radix(unsigned *ka, unsigned *kb, unsigned *tab,
+                                                 int bits) {
+  constexpr int NW = GT_THREADS / 64;
+  constexpr int NT = 64 * GT_PER_THREAD * NW;   // digit x round x wave counters
+  const int tid = threadIdx.x, w = tid >> 6;
+  const u64 lt = __lanemask_lt();
+  unsigned *src = ka, *dst = kb;
+  for (int shift = 12; shift < 12 + bits; shift += GS_DIG) {
+    for (int e = tid; e < NT; e += GT_THREADS) tab[e] = 0u;
+    __syncthreads();
+    unsigned key[GT_PER_THREAD], dg[GT_PER_THREAD], rk[GT_PER_THREAD];
+#pragma unroll
+    for (int r = 0; r < GT_PER_THREAD; ++r) {
+      key[r] = src[r * GT_THREADS + tid];
+      dg[r] = (key[r] >> shift) & 63u;
+      u64 peers = ~0ull;
+#pragma unroll
+      for (int b = 0; b < GS_DIG; ++b) {
+        const bool bit = (dg[r] >> b) & 1u;
+        const u64 m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      rk[r] = (unsigned)__popcll(peers & lt);
+      if (rk[r] == 0) tab[(dg[r] * GT_PER_THREAD + r) * NW + w] = (unsigned)__popcll(peers);
+    }
+    __syncthreads();
+    {   // exclusive scan of tab in (digit, round, wave) order
+      unsigned v[NT / GT_THREADS], sum = 0;
+#pragma unroll
+      for (int q = 0; q < NT / GT_THREADS; ++q) { v[q] = tab[tid * (NT / GT_THREADS) + q]; sum += v[q]; }
+      unsigned tot;
+      unsigned run = block_excl_scan<unsigned>(sum, &tot);
+#pragma unroll
+      for (int q = 0; q < NT / GT_THREADS; ++q) {
+        tab[tid * (NT / GT_THREADS) + q] = run;
+        run += v[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < GT_PER_THREAD; ++r)
+      dst[tab[(dg[r] * GT_PER_THREAD + r) * NW + w] + rk[r]] = key[r];
+    __syncthreads();
+    unsigned *t = src; src = dst; dst = t;
+  }
+  return src;
+}
+
 // Steps 1 and 2 for chunk ch; returns the sorted keys (ka or kb).
 template <typename T>
 __device__ __forceinline__ unsigned *seg_load_sort(
@@ -127,10 +182,7 @@ __device__ __forceinline__ unsigned *seg_load_sort(
     const unsigned *__restrict__ coff, const unsigned *__restrict__ cidx,
     const unsigned *__restrict__ chunk_first, const NzLoad<T> &nz, int ikbits, int sort_min,
     u64 *win, unsigned *ka, unsigned *kb, T *lx, unsigned *lz, unsigned *tab) {
-  constexpr int NW = GT_THREADS / 64;
-  constexpr int NT = 64 * GT_PER_THREAD * NW;   // digit x round x wave counters
-  const int tid = threadIdx.x, w = tid >> 6;
-  const u64 lt = __lanemask_lt();
+  const int tid = threadIdx.x;
   const i64 base = ch * GT_CHUNK;
   const i64 last = min(total, base + GT_CHUNK) - 1;
   const i64 jlo = chunk_first[ch];
@@ -172,47 +224,7 @@ __device__ __forceinline__ unsigned *seg_load_sort(
   // a chunk spanning at most sort_min fibers stays in stream order (rows are
   // distinct within a fiber, so sorting would merge little); the branch is
   // uniform over the workgroup
-  const int bits = nwin > sort_min ? ikbits : 0;
-  unsigned *src = ka, *dst = kb;
-  for (int shift = 12; shift < 12 + bits; shift += GS_DIG) {
-    for (int e = tid; e < NT; e += GT_THREADS) tab[e] = 0u;
-    __syncthreads();
-    unsigned key[GT_PER_THREAD], dg[GT_PER_THREAD], rk[GT_PER_THREAD];
-#pragma unroll
-    for (int r = 0; r < GT_PER_THREAD; ++r) {
-      key[r] = src[r * GT_THREADS + tid];
-      dg[r] = (key[r] >> shift) & 63u;
-      u64 peers = ~0ull;
-#pragma unroll
-      for (int b = 0; b < GS_DIG; ++b) {
-        const bool bit = (dg[r] >> b) & 1u;
-        const u64 m = __ballot(bit);
-        peers &= bit ? m : ~m;
-      }
-      rk[r] = (unsigned)__popcll(peers & lt);
-      if (rk[r] == 0) tab[(dg[r] * GT_PER_THREAD + r) * NW + w] = (unsigned)__popcll(peers);
-    }
-    __syncthreads();
-    {   // exclusive scan of tab in (digit, round, wave) order
-      unsigned v[NT / GT_THREADS], sum = 0;
-#pragma unroll
-      for (int q = 0; q < NT / GT_THREADS; ++q) { v[q] = tab[tid * (NT / GT_THREADS) + q]; sum += v[q]; }
-      unsigned tot;
-      unsigned run = block_excl_scan<unsigned>(sum, &tot);
-#pragma unroll
-      for (int q = 0; q < NT / GT_THREADS; ++q) {
-        tab[tid * (NT / GT_THREADS) + q] = run;
-        run += v[q];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < GT_PER_THREAD; ++r)
-      dst[tab[(dg[r] * GT_PER_THREAD + r) * NW + w] + rk[r]] = key[r];
-    __syncthreads();
-    unsigned *t = src; src = dst; dst = t;
-  }
-  return src;
+  return chunk_radix(ka, kb, tab, nwin > sort_min ? ikbits : 0);
 }
 
 // Step 3 over n row-sorted entries; entry q -> (row, x, KRP row) by get(q).
@@ -359,6 +371,158 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
     const int nvalid = (int)(min(total, (ch + 1) * GT_CHUNK) - ch * GT_CHUNK);
     seg_reduce<T, LPN, CPL>(LdsEntries<T>{keys, lx, lz}, nvalid, R, zhat, ldz, Mx, srow, svec);
   }
+}
+
+// ----------------------------------------------------------- bucketed gather --
+// For modes whose sampled fibers are long, a stream chunk spans one or two
+// fibers, its rows are all distinct and every nonzero costs a global row add
+// (two 64-byte atomic requests for a 25-column FP32 row, and the gather runs
+// at the chip's atomic request rate).  Here the gathered nonzeros are first
+// moved into BK_BUCKETS buckets of 2^bshift consecutive output rows (count,
+// scan, scatter), then reduced chunk by chunk like the stream: a chunk of a
+// bucket holds many nonzeros of each of its rows, which are summed in
+// registers before their one add.  FP32 gather; the order inside a bucket
+// depends on timing (rounding order only).
+#define BK_BUCKETS 4096
+#define BK_THREADS 256
+#define BK_PER (GT_CHUNK / BK_THREADS)
+#define BK_GRID 1024
+
+// Calls f(ik, x bits, KRP row) for every position of stream chunk ch (the
+// chunk's fiber starts are staged in win; positions find their fiber there).
+template <typename F>
+__device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
+                                         const u64 *__restrict__ cpos,
+                                         const unsigned *__restrict__ coff,
+                                         const unsigned *__restrict__ cidx,
+                                         const unsigned *__restrict__ chunk_first,
+                                         const uint2 *__restrict__ pairs, u64 *win, F &&f) {
+  const int tid = threadIdx.x;
+  const i64 base = ch * GT_CHUNK;
+  const i64 last = min(total, base + GT_CHUNK) - 1;
+  const i64 jlo = chunk_first[ch];
+  const i64 jhi = (ch + 1 < nch) ? (i64)chunk_first[ch + 1] : nf - 1;
+  const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
+  __syncthreads();   // the previous chunk is finished with win
+  for (int e = tid; e < nwin; e += BK_THREADS) win[e] = cpos[jlo + e];
+  __syncthreads();
+#pragma unroll 2
+  for (int u = 0; u < BK_PER; ++u) {
+    const i64 p = base + (i64)u * BK_THREADS + tid;
+    if (p > last) break;   // positions grow with u
+    int lo = 0, hi = nwin;   // last index with win[idx] <= p
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (win[mid] <= (u64)p) lo = mid; else hi = mid;
+    }
+    const uint2 v = pairs[(u64)coff[jlo + lo] + ((u64)p - win[lo])];
+    f(v.x, v.y, cidx[jlo + lo]);
+  }
+}
+
+// Workgroup w takes the consecutive chunks [w cpw, (w + 1) cpw) of the stream
+// in both passes, so its counts and its scatter see the same nonzeros.
+__global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
+    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
+    const uint2 *__restrict__ pairs, int bshift, unsigned *__restrict__ cnt) {
+  __shared__ u64 win[GT_WIN];
+  __shared__ unsigned h[BK_BUCKETS];
+  const i64 total = st->gathered, nf = st->n_fib;
+  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
+  const i64 cpw = (nch + gridDim.x - 1) / gridDim.x;
+  const i64 c0 = (i64)blockIdx.x * cpw, c1 = min(nch, c0 + cpw);
+  for (int b = threadIdx.x; b < BK_BUCKETS; b += BK_THREADS) h[b] = 0u;
+  for (i64 ch = c0; ch < c1; ++ch)
+    bk_chunk(ch, nch, total, nf, cpos, coff, cidx, chunk_first, pairs, win,
+             [&](unsigned ik, unsigned, unsigned) { atomicAdd(&h[ik >> bshift], 1u); });
+  __syncthreads();
+  for (int b = threadIdx.x; b < BK_BUCKETS; b += BK_THREADS)
+    cnt[(i64)b * gridDim.x + blockIdx.x] = h[b];
+}
+
+// off = exclusive scan of cnt in (bucket, workgroup) order.
+__global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
+    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
+    const uint2 *__restrict__ pairs, int bshift, const u64 *__restrict__ off,
+    uint2 *__restrict__ bpair, unsigned *__restrict__ bz) {
+  __shared__ u64 win[GT_WIN];
+  __shared__ unsigned cur[BK_BUCKETS];
+  const i64 total = st->gathered, nf = st->n_fib;
+  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
+  const i64 cpw = (nch + gridDim.x - 1) / gridDim.x;
+  const i64 c0 = (i64)blockIdx.x * cpw, c1 = min(nch, c0 + cpw);
+  for (int b = threadIdx.x; b < BK_BUCKETS; b += BK_THREADS)
+    cur[b] = (unsigned)off[(i64)b * gridDim.x + blockIdx.x];
+  for (i64 ch = c0; ch < c1; ++ch)
+    bk_chunk(ch, nch, total, nf, cpos, coff, cidx, chunk_first, pairs, win,
+             [&](unsigned ik, unsigned xb, unsigned zr) {
+               const unsigned pos = atomicAdd(&cur[ik >> bshift], 1u);
+               bpair[pos] = make_uint2(ik, xb);
+               bz[pos] = zr;
+             });
+}
+
+// The bucketed nonzeros in chunks of GT_CHUNK: loaded directly, sorted on
+// the low `sortbits` bits of the row (rows of one bucket differ only there;
+// a chunk crossing a bucket boundary merges a little less, nothing else),
+// then reduced as in the segmented gather.
+template <int LPN, int CPL>
+__global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
+    const DevState *st, int R, const uint2 *__restrict__ bpair, const unsigned *__restrict__ bz,
+    int sortbits, const float *__restrict__ zhat, int ldz, float *__restrict__ M, i64 nk) {
+  constexpr int NG = GT_THREADS / LPN;
+  __shared__ unsigned ka[GT_CHUNK], kb[GT_CHUNK];
+  __shared__ float lx[GT_CHUNK];
+  __shared__ unsigned lz[GT_CHUNK];
+  __shared__ unsigned tab[64 * GT_PER_THREAD * (GT_THREADS / 64)];
+  __shared__ int srow[2 * NG];
+  __shared__ float svec[2 * NG][LPN * CPL];
+  const i64 total = st->gathered;
+  const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
+  float *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * ldz;
+  const int tid = threadIdx.x;
+  for (i64 ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const i64 base = ch * GT_CHUNK;
+    const i64 last = min(total, base + GT_CHUNK) - 1;
+    __syncthreads();   // the previous chunk is finished with every shared array
+#pragma unroll
+    for (int u = 0; u < GT_PER_THREAD; ++u) {
+      const int li = u * GT_THREADS + tid;
+      const bool valid = base + li <= last;
+      const uint2 v = valid ? bpair[base + li] : make_uint2(0u, 0u);
+      ka[li] = valid ? ((v.x << 12) | (unsigned)li) : 0xFFFFFFFFu;
+      lx[li] = __uint_as_float(v.y);
+      lz[li] = valid ? bz[base + li] : 0u;
+    }
+    __syncthreads();
+    const unsigned *keys = chunk_radix(ka, kb, tab, sortbits);
+    const int nvalid = (int)(last - base + 1);
+    seg_reduce<float, LPN, CPL>(LdsEntries<float>{keys, lx, lz}, nvalid, R, zhat, ldz, Mx, srow,
+                                svec);
+  }
+}
+
+size_t gather_bkt_count_words() { return (size_t)BK_BUCKETS * BK_GRID; }
+
+void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                       const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
+                       i64 nk, const float *zhat, int ldz, float *M, int grid, unsigned *cnt,
+                       u64 *off, void *scan_scratch, uint2 *bpair, unsigned *bz,
+                       hipStream_t s) {
+  int ikbits = 1;
+  while ((1ll << ikbits) < nk) ++ikbits;
+  const int bshift = ikbits > 12 ? ikbits - 12 : 0;   // row >> bshift < BK_BUCKETS
+  hipLaunchKernelGGL(k_bkt_count, dim3(BK_GRID), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                     chunk_first, pairs, bshift, cnt);
+  scan_u32_dev(cnt, off, (i64)BK_BUCKETS * BK_GRID, nullptr, nullptr, scan_scratch, s);
+  hipLaunchKernelGGL(k_bkt_scatter, dim3(BK_GRID), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                     chunk_first, pairs, bshift, off, bpair, bz);
+  const int rm = gather_row_width(R);
+  auto k = rm == 16 ? k_gather_bkt<16, 1> : rm == 32 ? k_gather_bkt<16, 2> : k_gather_bkt<32, 2>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, bpair, bz, bshift, zhat, ldz, M,
+                     nk);
 }
 
 int gather_row_width(int R);

@@ -35,7 +35,7 @@ def large_tensor():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("gather", ["f64", "f32"])
+@pytest.mark.parametrize("gather", ["f64", "f32", "f32-bucketed"])
 def test_large3_shape_parity(large_tensor, gather):
     from paper_2006_16438_amd.api import CpArlsLev
     dims, coords, vals = large_tensor
@@ -44,9 +44,14 @@ def test_large3_shape_parity(large_tensor, gather):
     fac = synth.gaussian_factors(dims, R, 3)
     F = [torch.from_numpy(f.copy()).to(dev) for f in fac]
     log(f"large3 {dims} nnz={NNZ} R={R} s={s} gather={gather}: init")
+    bucketed = gather == "f32-bucketed"
+    gather = "f32" if bucketed else gather
     ctx = CpArlsLev(dims, coords, vals, F, R, s, tau=1.0 / s, seed=0, stream_id=0,
                     gather_dtype=gather)
-    if gather == "f32":   # the tuned launch shapes (long fibers skip the row sort)
+    if bucketed:   # nonzeros moved into row buckets before the reduction
+        for k in range(3):
+            ctx.set_gather_config(k, 512, -1)
+    elif gather == "f32":   # the tuned launch shapes
         log(f"  autotuned gather shapes {ctx.autotune()}")
     OT = oracle.Tensor(np.array(dims), np.zeros((3, 1), dtype=np.int32), np.ones(1))
     for k in range(3):

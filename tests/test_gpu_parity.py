@@ -252,3 +252,28 @@ def test_autotune_then_parity(gather):
     log(f"autotune then parity ({gather})")
     run_parity(T, fac, R, 8192, 1 / 8192, 6, gather, 1e-10 if gather == "f64" else 1e-4,
                label=f"autotune-{gather}", autotune=True)
+
+
+@pytest.mark.parametrize("case", ["long_short", "multitile", "uber4"])
+def test_bucketed_gather_fp32(case):
+    """The bucketed gather (sampled nonzeros moved into 4096 buckets of
+    output rows before the chunked reduction), FP32: bucket widths of one
+    row (modes up to 4096 rows) and more, long-fiber and short-fiber modes,
+    the benchmark workload at full size."""
+    if case == "long_short":
+        dims = (3000, 4, 3)
+        T = synth.random_sparse(dims, 30_000, seed=51)
+        R, s, tau, n = 3, 256, 1 / 256, 6
+        fac = concentrated(dims, R, 52)
+    elif case == "multitile":
+        dims = (700, 300, 257)
+        T = synth.random_sparse(dims, 150_000, seed=21)
+        R, s, tau, n = 8, 8192 + 77, 1 / 8192, 6
+        fac = concentrated(dims, R, 22)
+    else:
+        T = synth.uber4(0)
+        R, s, tau, n = 25, 1 << 17, 2.0 ** -17, 4
+        fac = synth.gaussian_factors(T.dims, R, 0)
+    log(f"bucketed gather, {case}")
+    run_parity(T, fac, R, s, tau, n, "f32", 1e-4, label=f"bucketed-{case}",
+               gather_config=(512, -1))
