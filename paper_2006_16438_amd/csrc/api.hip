@@ -30,8 +30,8 @@ void launch_zero_words(void *p, i64 nwords, hipStream_t s);
 size_t gather_bkt_count_words();
 void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                        const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
-                       i64 nk, const float *zhat, int ldz, float *M, int grid, unsigned *cnt,
-                       u64 *off, void *scan_scratch, uint2 *bpair, unsigned *bz,
+                       i64 nk, i64 max_total, const float *zhat, int ldz, float *M, int grid,
+                       unsigned *cnt, u64 *off, void *scan_scratch, uint2 *bpair, unsigned *bz,
                        hipStream_t s);
 int lev_row_blocks(i64 n);
 void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
@@ -757,8 +757,8 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
   }
   else if (sort_min < 0 && c->bk_pair && bucket_capable(c, k))
     launch_gather_bkt(c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs, md.n,
-                      (const float *)c->zhat, c->ldz, (float *)c->M, grid, c->bk_cnt, c->bk_off,
-                      c->bk_scan, c->bk_pair, c->bk_z, s);
+                      c->nnz, (const float *)c->zhat, c->ldz, (float *)c->M, grid, c->bk_cnt,
+                      c->bk_off, c->bk_scan, c->bk_pair, c->bk_z, s);
   else if (md.n <= (1 << 20))
     launch_gather_seg(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                       md.ik, md.v64, md.n, c->zhat, c->ldz, c->M, grid, std::max(sort_min, 0), s);

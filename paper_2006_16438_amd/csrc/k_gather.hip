@@ -383,10 +383,10 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
 // bucket holds many nonzeros of each of its rows, which are summed in
 // registers before their one add.  FP32 gather; the order inside a bucket
 // depends on timing (rounding order only).
-#define BK_BUCKETS 4096
+#define BK_BUCKETS 4096   // at most
 #define BK_THREADS 256
 #define BK_PER (GT_CHUNK / BK_THREADS)
-#define BK_GRID 1024
+#define BK_GRID 1024      // at most
 
 // Calls f(ik, x bits, KRP row) for every position of stream chunk ch (the
 // chunk's fiber starts are staged in win; positions find their fiber there).
@@ -425,19 +425,19 @@ __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
 __global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
-    const uint2 *__restrict__ pairs, int bshift, unsigned *__restrict__ cnt) {
+    const uint2 *__restrict__ pairs, int bshift, int nb, unsigned *__restrict__ cnt) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned h[BK_BUCKETS];
   const i64 total = st->gathered, nf = st->n_fib;
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
   const i64 cpw = (nch + gridDim.x - 1) / gridDim.x;
   const i64 c0 = (i64)blockIdx.x * cpw, c1 = min(nch, c0 + cpw);
-  for (int b = threadIdx.x; b < BK_BUCKETS; b += BK_THREADS) h[b] = 0u;
+  for (int b = threadIdx.x; b < nb; b += BK_THREADS) h[b] = 0u;
   for (i64 ch = c0; ch < c1; ++ch)
     bk_chunk(ch, nch, total, nf, cpos, coff, cidx, chunk_first, pairs, win,
              [&](unsigned ik, unsigned, unsigned) { atomicAdd(&h[ik >> bshift], 1u); });
   __syncthreads();
-  for (int b = threadIdx.x; b < BK_BUCKETS; b += BK_THREADS)
+  for (int b = threadIdx.x; b < nb; b += BK_THREADS)
     cnt[(i64)b * gridDim.x + blockIdx.x] = h[b];
 }
 
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
 __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
-    const uint2 *__restrict__ pairs, int bshift, const u64 *__restrict__ off,
+    const uint2 *__restrict__ pairs, int bshift, int nb, const u64 *__restrict__ off,
     uint2 *__restrict__ bpair, unsigned *__restrict__ bz) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned cur[BK_BUCKETS];
@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
   const i64 cpw = (nch + gridDim.x - 1) / gridDim.x;
   const i64 c0 = (i64)blockIdx.x * cpw, c1 = min(nch, c0 + cpw);
-  for (int b = threadIdx.x; b < BK_BUCKETS; b += BK_THREADS)
+  for (int b = threadIdx.x; b < nb; b += BK_THREADS)
     cur[b] = (unsigned)off[(i64)b * gridDim.x + blockIdx.x];
   for (i64 ch = c0; ch < c1; ++ch)
     bk_chunk(ch, nch, total, nf, cpos, coff, cidx, chunk_first, pairs, win,
@@ -506,19 +506,26 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
 
 size_t gather_bkt_count_words() { return (size_t)BK_BUCKETS * BK_GRID; }
 
+// max_total bounds the stream length (the context's nonzeros): the count and
+// scatter grids are sized from it (about 8 chunks per workgroup, 64 to
+// BK_GRID workgroups) and the buckets from n_k, so that small gathers do not
+// pay for a scan of BK_BUCKETS x BK_GRID counts.
 void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                        const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
-                       i64 nk, const float *zhat, int ldz, float *M, int grid, unsigned *cnt,
-                       u64 *off, void *scan_scratch, uint2 *bpair, unsigned *bz,
+                       i64 nk, i64 max_total, const float *zhat, int ldz, float *M, int grid,
+                       unsigned *cnt, u64 *off, void *scan_scratch, uint2 *bpair, unsigned *bz,
                        hipStream_t s) {
   int ikbits = 1;
   while ((1ll << ikbits) < nk) ++ikbits;
   const int bshift = ikbits > 12 ? ikbits - 12 : 0;   // row >> bshift < BK_BUCKETS
-  hipLaunchKernelGGL(k_bkt_count, dim3(BK_GRID), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, pairs, bshift, cnt);
-  scan_u32_dev(cnt, off, (i64)BK_BUCKETS * BK_GRID, nullptr, nullptr, scan_scratch, s);
-  hipLaunchKernelGGL(k_bkt_scatter, dim3(BK_GRID), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, pairs, bshift, off, bpair, bz);
+  const int nb = (int)((nk + (1ll << bshift) - 1) >> bshift);
+  const i64 chunks = (max_total + GT_CHUNK - 1) / GT_CHUNK;
+  const int gb = (int)std::min<i64>(BK_GRID, std::max<i64>(64, (chunks + 7) / 8));
+  hipLaunchKernelGGL(k_bkt_count, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                     chunk_first, pairs, bshift, nb, cnt);
+  scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, nullptr, scan_scratch, s);
+  hipLaunchKernelGGL(k_bkt_scatter, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                     chunk_first, pairs, bshift, nb, off, bpair, bz);
   const int rm = gather_row_width(R);
   auto k = rm == 16 ? k_gather_bkt<16, 1> : rm == 32 ? k_gather_bkt<16, 2> : k_gather_bkt<32, 2>;
   hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, bpair, bz, bshift, zhat, ldz, M,
