@@ -506,7 +506,7 @@ def bench_batch(args):
                         "iteration (3 batched mode steps)",
             "decompositions": n, "samples": s, "iterations": K,
             "parallelism": "single GPU; one captured HIP graph per mode step (kernels of all "
-                           "decompositions on 4 streams as parallel branches)",
+                           "decompositions on 16 streams as parallel branches)",
             "autotuned_gather": args.tune,
         },
         "gathered_rows_per_s": rows_g / el_g,
