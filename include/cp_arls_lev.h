@@ -180,7 +180,7 @@ cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *cou
  * bucketed gather instead (FP32 gather, modes of at most 2^20 rows): the
  * sampled nonzeros are first moved into 4096 buckets of consecutive output
  * rows, so that the adds of different fibers to one row are summed on chip
- * (it allocates 12 bytes per stored nonzero plus 48 MB on first use; its
+ * (it allocates 16 bytes per stored nonzero plus 48 MB on first use; its
  * sums are in a timing-dependent order).  Dense tensors: grid =
  * workgroups along the sampled fibers of the split contraction (each writes
  * one partial M; at most the default, which get_gather_config reports;

@@ -31,8 +31,7 @@ size_t gather_bkt_count_words();
 void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                        const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
                        i64 nk, i64 max_total, const float *zhat, int ldz, float *M, int grid,
-                       unsigned *cnt, u64 *off, void *scan_scratch, uint2 *bpair, unsigned *bz,
-                       hipStream_t s);
+                       unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s);
 int lev_row_blocks(i64 n);
 void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
                   void *scratch, hipStream_t s);
@@ -202,8 +201,7 @@ struct cpal_ctx {
   unsigned *bk_cnt = nullptr;
   u64 *bk_off = nullptr;
   void *bk_scan = nullptr;
-  uint2 *bk_pair = nullptr;
-  unsigned *bk_z = nullptr;
+  uint4 *bk_ent = nullptr;
   u64 *cpos = nullptr;              // nonempty fibers: stream position,
   unsigned *coff = nullptr;         //   offset in the mode-sorted nonzeros,
   unsigned *cidx = nullptr;         //   sampled row
@@ -725,14 +723,13 @@ void update_front(cpal_ctx *c, int k) {
 
 // The bucketed gather's buffers (FP32 sparse contexts; nonzeros up to nnz).
 cpal_status ensure_bucket_buffers(cpal_ctx *c) {
-  if (c->bk_pair) return CPAL_OK;
+  if (c->bk_ent) return CPAL_OK;
   try {
     const size_t nw = gather_bkt_count_words();
     c->bk_cnt = c->alloc<unsigned>(nw);
     c->bk_off = c->alloc<u64>(nw);
     c->bk_scan = c->alloc<char>(scan_scratch_bytes((i64)nw));
-    c->bk_z = c->alloc<unsigned>((size_t)c->nnz);
-    c->bk_pair = c->alloc<uint2>((size_t)c->nnz);
+    c->bk_ent = c->alloc<uint4>((size_t)c->nnz);
   } catch (cpal_status st) {
     return st;
   }
@@ -755,10 +752,10 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
     launch_dense_mttkrp(c->zdt, c->st, md.n, R, c->ldz, md.dld, c->cidx, c->samp_idx, md.dX,
                         c->zhat, c->dpart, kc, (int)((c->s + kc - 1) / kc), c->M, s);
   }
-  else if (sort_min < 0 && c->bk_pair && bucket_capable(c, k))
+  else if (sort_min < 0 && c->bk_ent && bucket_capable(c, k))
     launch_gather_bkt(c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs, md.n,
                       c->nnz, (const float *)c->zhat, c->ldz, (float *)c->M, grid, c->bk_cnt,
-                      c->bk_off, c->bk_scan, c->bk_pair, c->bk_z, s);
+                      c->bk_off, c->bk_scan, c->bk_ent, s);
   else if (md.n <= (1 << 20))
     launch_gather_seg(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                       md.ik, md.v64, md.n, c->zhat, c->ldz, c->M, grid, std::max(sort_min, 0), s);

@@ -381,7 +381,8 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
 // moved into BK_BUCKETS buckets of 2^bshift consecutive output rows (count,
 // scan, scatter), then reduced chunk by chunk like the stream: a chunk of a
 // bucket holds many nonzeros of each of its rows, which are summed in
-// registers before their one add.  FP32 gather; the order inside a bucket
+// registers before their one add.  A bucketed nonzero is one 16-byte record
+// {row, value bits, KRP row, 0}.  FP32 gather; the order inside a bucket
 // depends on timing (rounding order only).
 #define BK_BUCKETS 4096   // at most
 #define BK_THREADS 256
@@ -446,7 +447,7 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
     const uint2 *__restrict__ pairs, int bshift, int nb, const u64 *__restrict__ off,
-    uint2 *__restrict__ bpair, unsigned *__restrict__ bz) {
+    uint4 *__restrict__ bent) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned cur[BK_BUCKETS];
   const i64 total = st->gathered, nf = st->n_fib;
@@ -459,8 +460,7 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
     bk_chunk(ch, nch, total, nf, cpos, coff, cidx, chunk_first, pairs, win,
              [&](unsigned ik, unsigned xb, unsigned zr) {
                const unsigned pos = atomicAdd(&cur[ik >> bshift], 1u);
-               bpair[pos] = make_uint2(ik, xb);
-               bz[pos] = zr;
+               bent[pos] = make_uint4(ik, xb, zr, 0u);   // one 16-byte store
              });
 }
 
@@ -470,8 +470,8 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
 // then reduced as in the segmented gather.
 template <int LPN, int CPL>
 __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
-    const DevState *st, int R, const uint2 *__restrict__ bpair, const unsigned *__restrict__ bz,
-    int sortbits, const float *__restrict__ zhat, int ldz, float *__restrict__ M, i64 nk) {
+    const DevState *st, int R, const uint4 *__restrict__ bent, int sortbits,
+    const float *__restrict__ zhat, int ldz, float *__restrict__ M, i64 nk) {
   constexpr int NG = GT_THREADS / LPN;
   __shared__ unsigned ka[GT_CHUNK], kb[GT_CHUNK];
   __shared__ float lx[GT_CHUNK];
@@ -491,10 +491,10 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
     for (int u = 0; u < GT_PER_THREAD; ++u) {
       const int li = u * GT_THREADS + tid;
       const bool valid = base + li <= last;
-      const uint2 v = valid ? bpair[base + li] : make_uint2(0u, 0u);
+      const uint4 v = valid ? bent[base + li] : make_uint4(0u, 0u, 0u, 0u);
       ka[li] = valid ? ((v.x << 12) | (unsigned)li) : 0xFFFFFFFFu;
       lx[li] = __uint_as_float(v.y);
-      lz[li] = valid ? bz[base + li] : 0u;
+      lz[li] = v.z;
     }
     __syncthreads();
     const unsigned *keys = chunk_radix(ka, kb, tab, sortbits);
@@ -513,8 +513,7 @@ size_t gather_bkt_count_words() { return (size_t)BK_BUCKETS * BK_GRID; }
 void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                        const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
                        i64 nk, i64 max_total, const float *zhat, int ldz, float *M, int grid,
-                       unsigned *cnt, u64 *off, void *scan_scratch, uint2 *bpair, unsigned *bz,
-                       hipStream_t s) {
+                       unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s) {
   int ikbits = 1;
   while ((1ll << ikbits) < nk) ++ikbits;
   const int bshift = ikbits > 12 ? ikbits - 12 : 0;   // row >> bshift < BK_BUCKETS
@@ -525,11 +524,10 @@ void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigne
                      chunk_first, pairs, bshift, nb, cnt);
   scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, nullptr, scan_scratch, s);
   hipLaunchKernelGGL(k_bkt_scatter, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, pairs, bshift, nb, off, bpair, bz);
+                     chunk_first, pairs, bshift, nb, off, bent);
   const int rm = gather_row_width(R);
   auto k = rm == 16 ? k_gather_bkt<16, 1> : rm == 32 ? k_gather_bkt<16, 2> : k_gather_bkt<32, 2>;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, bpair, bz, bshift, zhat, ldz, M,
-                     nk);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, bent, bshift, zhat, ldz, M, nk);
 }
 
 int gather_row_width(int R);
