@@ -277,3 +277,31 @@ def test_bucketed_gather_fp32(case):
     log(f"bucketed gather, {case}")
     run_parity(T, fac, R, s, tau, n, "f32", 1e-4, label=f"bucketed-{case}",
                gather_config=(512, -1))
+
+
+def test_gather_config_errors():
+    """Argument checks of the launch-shape calls: negative grids, sort
+    thresholds below -1, the bucketed gather (-1) in FP64 mode, a dense
+    split beyond the default, modes out of range."""
+    from paper_2006_16438_amd._lib import CpalError
+    T, _, R = synth.small3(0)
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    ctx, _ = make_ctx(T, fac, R, 1024, gather="f64")
+    for args in ((0, -1, 0), (0, 64, -2), (0, 64, -1), (3, 64, 0), (-1, 64, 0)):
+        with pytest.raises(CpalError):
+            ctx.set_gather_config(*args)
+    ctx.set_gather_config(0, 64, 4)
+    assert ctx.gather_config(0) == (64, 4)
+    ctx.close()
+    ctx, _ = make_ctx(T, fac, R, 1024, gather="f32")
+    ctx.set_gather_config(1, 256, -1)   # the bucketed gather exists in FP32 mode
+    assert ctx.gather_config(1) == (256, -1)
+    ctx.close()
+    D, _ = synth.planted((12, 10, 8), 3, seed=8, density=1.0, law="normal")
+    ctx, _ = make_ctx(D, synth.gaussian_factors(D.dims, 3, 0), 3, 256, gather="f32", dense=True)
+    default = ctx.gather_config(0)[0]
+    with pytest.raises(CpalError):
+        ctx.set_gather_config(0, default + 1, 0)
+    with pytest.raises(CpalError):
+        ctx.set_gather_config(0, 1, -1)   # no bucketed gather for dense tensors
+    ctx.close()
