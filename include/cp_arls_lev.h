@@ -52,9 +52,28 @@ enum {
   CPAL_FLAG_DET_TRUNC = 4,  /* >= s rows above tau: the s most probable kept          */
   CPAL_FLAG_PDET_ONE = 8,   /* 1 - p_det <= 2^-40: no random rows                     */
   CPAL_FLAG_DRAWCAP = 16,   /* random draws hit 64*s_rnd + 2^20 before s_rnd accepts  */
-  CPAL_FLAG_OVERFLOW = 32,  /* the deterministic set exceeded its buffer (4s+4096)    */
+  CPAL_FLAG_OVERFLOW = 32,  /* the deterministic set exceeded its buffer; the buffer
+                               is sized at init from the bound |D| < 1/tau (Sec. 5.3),
+                               the largest other-mode KRP row count and det_enum_cap,
+                               so this flag marks an internal error                  */
   CPAL_FLAG_STATE = 64      /* a probability vector summed to zero                    */
 };
+
+/* Device memory provider (ownership of every buffer the library allocates):
+ * alloc(bytes, user) returns `bytes` of device memory on the context's device,
+ * 256-byte aligned, or NULL on failure (the call then fails with
+ * CPAL_E_NOMEM); free(ptr, user) releases a pointer alloc returned.  Every
+ * allocation of a context or batch -- persistent buffers, the temporaries of
+ * init, buffers added later by cp_arls_lev_set_gather_config or the
+ * autotuner -- goes through it, and cp_arls_lev_destroy (or
+ * cp_arls_lev_destroy_batch) returns all of them after synchronizing the
+ * streams.  The callbacks are called from the calling host thread only, never
+ * from a stream or graph.  A NULL cpal_allocator* selects hipMalloc/hipFree. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *user;
+} cpal_allocator;
 
 typedef struct {
   int32_t order;             /* D >= 2, <= 8                                           */
@@ -107,11 +126,13 @@ typedef struct {
  * fit_samples > 0, draws the stratified fit sample once (Sec. 6.4).
  * factors: host array of `order` device pointers, each n_m x R FP64,
  * caller-owned, must outlive the context.  hip_stream: hipStream_t (may be
- * NULL for the default stream).  Synchronizes the stream before returning;
+ * NULL for the default stream).  alloc: device memory provider (NULL:
+ * hipMalloc); it must outlive the context.  Synchronizes the stream before returning;
  * X may be freed afterwards.  Errors: CPAL_E_ARG (bad sizes/options/null),
  * CPAL_E_NOMEM, CPAL_E_DEVICE, CPAL_E_STATE (an all-zero factor). */
 cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
-                             double *const *factors, void *hip_stream, cpal_ctx **out);
+                             double *const *factors, void *hip_stream,
+                             const cpal_allocator *alloc, cpal_ctx **out);
 
 /* One mode update of Alg. 3 for mode `mode`: SkrpLev (Alg. 1) over the
  * cached leverage of the other modes -- deterministic rows with p > tau
@@ -131,10 +152,14 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *ctx, int32_t mode, cpal_mode_stats
  * CPAL_E_STATE if the context was created with fit_samples = 0. */
 cpal_status cp_arls_lev_fit_estimate(cpal_ctx *ctx, double *fit_dev);
 
-/* Copy the last update's sampled rows: linear indices, omega (= weight^2)
- * and weights; deterministic rows first (ascending), then combined random
- * rows (ascending).  Copies min(s_bar, cap) rows; *count_dev = s_bar.
- * Asynchronous.  Exists so that callers can audit the sketch. */
+/* The output (idx, wgt, s_bar) of SkrpLev (Alg. 1) for the last mode update:
+ * linear indices of the sampled KRP rows (eq. (2.2), 0-based), omega
+ * (= weight^2, the combined-row weights of Sec. 4.1 and 4.3) and weights;
+ * deterministic rows first (ascending), then combined random rows
+ * (ascending).  Copies min(s_bar, cap) rows; *count_dev = s_bar.
+ * Asynchronous.  CPAL_E_STATE before the first update and after
+ * cp_arls_lev_autotune (whose trial samples are not an update's) until the
+ * next update.  Exists so that callers can audit the sketch. */
 cpal_status cp_arls_lev_samples(const cpal_ctx *ctx, uint64_t *idx_dev, double *omega_dev,
                                 double *w_dev, int64_t cap, int64_t *count_dev);
 
@@ -203,7 +228,10 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_
  * it allocates where they fit; for dense tensors the default split of
  * the sampled fibers and 1/2, 1/4, 1/8 of it) with HIP events, best of
  * `reps` runs each (0: 2, at most 16), and keeps the fastest shape for the
- * mode.  Synchronizes the stream and is not graph-capturable. */
+ * mode.  Every trial samples at the current step; afterwards the step
+ * counter, factors and leverage scores are as before, and
+ * cp_arls_lev_samples reports CPAL_E_STATE until the next mode update.
+ * Synchronizes the stream and is not graph-capturable. */
 cpal_status cp_arls_lev_autotune(cpal_ctx *ctx, int32_t reps);
 
 /* Text of the last error on this context (never NULL). */
@@ -222,13 +250,15 @@ void cp_arls_lev_destroy(cpal_ctx *ctx);
  * decompositions on a few streams of its own (default priority) so that
  * their kernels overlap; every batch call is ordered after the work already
  * enqueued on hip_stream and work enqueued on hip_stream afterwards runs
- * after it.  Errors as for cp_arls_lev_init; on error nothing is created. */
+ * after it.  alloc as for cp_arls_lev_init (every member context and the
+ * batch's own buffers use it).  Errors as for cp_arls_lev_init; on error
+ * nothing is created. */
 typedef struct cpal_batch cpal_batch;
 
 cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
                                    const int32_t *tensor_of, const cpal_options *opts,
                                    double *const *const *factors, void *hip_stream,
-                                   cpal_batch **out);
+                                   const cpal_allocator *alloc, cpal_batch **out);
 
 /* One mode update (cp_arls_lev_mode_update) of mode `mode` in every
  * decomposition whose tensor has more than `mode` modes.  stats_dev: device

@@ -717,7 +717,6 @@ int64_t orc_fit_sample(const orc_tensor *X, uint64_t seed, uint64_t stream_id,
     sx[j] = X->vals[e];
     sphi[j] = phi_nz;
   }
-  double phi_z = n_z ? (double)zeros / (double)n_z : 0.0;
   int64_t got = 0, draws = 0, guard = 64 * n_z + (1 << 20);
   while (got < n_z) {
     if (draws >= guard) { *flags |= ORC_FLAG_DRAWCAP; break; }
@@ -736,9 +735,12 @@ int64_t orc_fit_sample(const orc_tensor *X, uint64_t seed, uint64_t stream_id,
     int64_t j = n_nz + got;
     for (int m = 0; m < D; ++m) sc[(int64_t)m * cap + j] = c[m];
     sx[j] = 0.0;
-    sphi[j] = phi_z;
     got++;
   }
+  /* the zero stratum holds (prod n - nnz) entries represented by the `got`
+   * zeros actually drawn (fewer than n_z when the draw guard stopped it) */
+  double phi_z = got ? (double)zeros / (double)got : 0.0;
+  for (int64_t j = n_nz; j < n_nz + got; ++j) sphi[j] = phi_z;
   orc_index_free(ix);
   return n_nz + got;
 }

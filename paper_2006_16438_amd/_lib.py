@@ -31,6 +31,14 @@ SYMBOLS = (
 STAGES = ("sample", "rows", "gather", "solve", "leverage")
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class cpal_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
 class cpal_tensor(C.Structure):
     _fields_ = [("order", C.c_int32), ("dims", C.POINTER(C.c_int64)), ("nnz", C.c_int64),
                 ("coords", C.c_void_p), ("values", C.c_void_p), ("value_dtype", C.c_int32),
@@ -65,7 +73,8 @@ def load(path: str | None = None):
     L = C.CDLL(path)
     P = C.POINTER
     vp = C.c_void_p
-    L.cp_arls_lev_init.argtypes = [P(cpal_tensor), P(cpal_options), P(vp), vp, P(vp)]
+    L.cp_arls_lev_init.argtypes = [P(cpal_tensor), P(cpal_options), P(vp), vp,
+                                   P(cpal_allocator), P(vp)]
     L.cp_arls_lev_init.restype = C.c_int
     L.cp_arls_lev_mode_update.argtypes = [vp, C.c_int32, vp]
     L.cp_arls_lev_mode_update.restype = C.c_int
@@ -90,7 +99,8 @@ def load(path: str | None = None):
     L.cp_arls_lev_destroy.argtypes = [vp]
     L.cp_arls_lev_destroy.restype = None
     L.cp_arls_lev_init_batch.argtypes = [C.c_int32, P(cpal_tensor), C.c_int32, P(C.c_int32),
-                                         P(cpal_options), P(vp), vp, P(vp)]
+                                         P(cpal_options), P(vp), vp, P(cpal_allocator),
+                                         P(vp)]
     L.cp_arls_lev_init_batch.restype = C.c_int
     L.cp_arls_lev_mode_step_batch.argtypes = [vp, C.c_int32, vp]
     L.cp_arls_lev_mode_step_batch.restype = C.c_int

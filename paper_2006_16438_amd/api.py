@@ -20,6 +20,55 @@ def _stream_ptr(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
+class TorchAllocator:
+    """A cpal_allocator whose device memory comes from torch's caching
+    allocator (on one device, associated with one stream).  It counts the
+    calls and the live allocations, and must outlive every context using it."""
+
+    def __init__(self, device=None, stream=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.device = dev.index if dev.index is not None else torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.n_alloc = 0
+        self.n_free = 0
+        self.live = {}
+
+        def _alloc(nbytes, user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            except Exception:   # out of memory: the library reports CPAL_E_NOMEM
+                return None
+            self.live[int(p)] = int(nbytes)
+            self.n_alloc += 1
+            return p
+
+        def _free(ptr, user):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            finally:
+                self.live.pop(int(ptr), None)
+                self.n_free += 1
+
+        self._fa = L.ALLOC_FN(_alloc)
+        self._ff = L.FREE_FN(_free)
+        self.struct = L.cpal_allocator(self._fa, self._ff, None)
+
+    @property
+    def live_bytes(self):
+        return sum(self.live.values())
+
+
+def _allocator_arg(allocator, device, stream):
+    """(allocator object or None, pointer for the C call).  "torch": torch's
+    caching allocator; None: the library's hipMalloc."""
+    if allocator == "torch":
+        allocator = TorchAllocator(device, stream)
+    if allocator is None:
+        return None, None
+    return allocator, C.byref(allocator.struct)
+
+
 def _check(code, ctx_ptr=None):
     if code != L.CPAL_OK:
         msg = ""
@@ -32,7 +81,7 @@ def _check(code, ctx_ptr=None):
 class CpArlsLev:
     def __init__(self, dims, coords, values, factors, rank, samples, tau=None, seed=0,
                  stream_id=0, gather_dtype="f64", fit_samples=0, fit_alpha=0.5,
-                 det_enum_cap=0, stream=None):
+                 det_enum_cap=0, stream=None, allocator="torch"):
         lib = L.load()
         self.order = len(dims)
         self.dims = tuple(int(n) for n in dims)
@@ -77,7 +126,8 @@ class CpArlsLev:
                            int(fit_samples), float(fit_alpha), int(det_enum_cap))
         fp = (C.c_void_p * self.order)(*[f.data_ptr() for f in self.factors])
         self._ctx = C.c_void_p()
-        code = lib.cp_arls_lev_init(C.byref(t), C.byref(o), fp, _stream_ptr(self.stream),
+        self.allocator, aptr = _allocator_arg(allocator, self.values.device, self.stream)
+        code = lib.cp_arls_lev_init(C.byref(t), C.byref(o), fp, _stream_ptr(self.stream), aptr,
                                     C.byref(self._ctx))
         _check(code)
         self._stats = torch.zeros(L.STATS_BYTES // 8, dtype=torch.int64,
@@ -243,7 +293,7 @@ class CpArlsLevBatch:
 
     def __init__(self, tensors, tensor_of, factors, ranks, samples, taus=None, seeds=0,
                  stream_ids=0, gather_dtype="f32", fit_samples=0, fit_alpha=0.5,
-                 det_enum_cap=0, stream=None, use_graphs=False):
+                 det_enum_cap=0, stream=None, use_graphs=False, allocator="torch"):
         lib = L.load()
         n = len(tensor_of)
         per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * n
@@ -284,8 +334,9 @@ class CpArlsLevBatch:
         self.ranks, self.samples = ranks, samples
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._b = C.c_void_p()
+        self.allocator, aptr = _allocator_arg(allocator, self.device, self.stream)
         _check(lib.cp_arls_lev_init_batch(len(tensors), tens, n, tof, opts, fptrs,
-                                          _stream_ptr(self.stream), C.byref(self._b)))
+                                          _stream_ptr(self.stream), aptr, C.byref(self._b)))
         self.n = n
         self._stats = torch.zeros((n, L.STATS_BYTES // 8), dtype=torch.int64, device=self.device)
         if use_graphs:

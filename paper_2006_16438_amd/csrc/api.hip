@@ -156,7 +156,9 @@ struct cpal_ctx {
   hipStream_t stream = nullptr;
   u64 t = 0;
   bool failed = false;
+  bool samples_valid = false;   // samp_* hold the output of a mode update
   std::string err;
+  cpal_allocator al{};          // alloc == nullptr: hipMalloc / hipFree
   std::vector<void *> allocs;
   Mode mode[CPAL_MAXORDER];
   // scratch
@@ -243,16 +245,31 @@ struct cpal_ctx {
     ev_rec.push_back({stage, {b, e}});
   }
 
+  // every device allocation goes through the caller's provider (or hipMalloc)
+  void *raw_alloc(size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    void *p = nullptr;
+    if (al.alloc) {
+      p = al.alloc(bytes, al.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    return p;
+  }
+  void raw_free(void *p) {
+    if (!p) return;
+    if (al.alloc) al.free(p, al.user);
+    else hipFree(p);
+  }
   template <typename T>
   T *alloc(size_t count) {
-    void *p = nullptr;
-    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
-    if (hipMalloc(&p, bytes) != hipSuccess) throw cpal_status(CPAL_E_NOMEM);
+    void *p = raw_alloc(count * sizeof(T));
+    if (!p) throw cpal_status(CPAL_E_NOMEM);
     allocs.push_back(p);
     return (T *)p;
   }
   void release() {
-    for (void *p : allocs) hipFree(p);
+    for (void *p : allocs) raw_free(p);
     allocs.clear();
     for (auto &r : ev_rec) { hipEventDestroy(r.second.first); hipEventDestroy(r.second.second); }
     ev_rec.clear();
@@ -385,7 +402,8 @@ namespace {
 // copies) and ||X||^2 instead of building them again (restarts of one tensor
 // in a batch).  The lender must outlive the borrower.
 cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *const *factors,
-                      void *hip_stream, const cpal_ctx *share, cpal_ctx **out) {
+                      void *hip_stream, const cpal_allocator *alloc, const cpal_ctx *share,
+                      cpal_ctx **out) {
   if (!out) return CPAL_E_ARG;
   *out = nullptr;
   if (!X || !opt || !factors) return CPAL_E_ARG;
@@ -402,6 +420,7 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
   if (dense && opt->fit_samples != 0) return CPAL_E_ARG;   // the Sec. 6.4 sample is over nonzeros
   if (opt->det_enum_cap < 0 || opt->det_enum_cap > (1ll << 31)) return CPAL_E_ARG;
   if (opt->fit_samples < 0) return CPAL_E_ARG;
+  if (alloc && (!alloc->alloc || !alloc->free)) return CPAL_E_ARG;
   long double fulld = 1;
   for (int m = 0; m < X->order; ++m) {
     if (X->dims[m] < 1 || X->dims[m] > (1ll << 31) - 1) return CPAL_E_ARG;
@@ -413,6 +432,7 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
   for (int m = 0; m < X->order; ++m) full *= (u64)X->dims[m];
 
   cpal_ctx *c = new cpal_ctx();
+  if (alloc) c->al = *alloc;
   c->D = X->order;
   for (int m = 0; m < c->D; ++m) c->dims[m] = X->dims[m];
   c->R = opt->rank;
@@ -460,7 +480,20 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
     c->lev_part = c->alloc<double>((size_t)((maxn + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS) * np);
     c->lev_bsum = c->alloc<u64>(lev_row_blocks(maxn) + 1);
     c->cand = c->alloc<int>(sumn);
-    c->det_cap = 4 * (u64)s + 4096;
+    // |D| < 1/tau (every p > tau and the p sum to at most 1, Sec. 5.3), |D| is at
+    // most the other modes' KRP row count and, when enumerated, at most
+    // det_enum_cap: the deterministic set always fits
+    {
+      u64 cap = c->enum_cap;
+      u64 maxNk = 0;
+      for (int m = 0; m < c->D; ++m) maxNk = std::max(maxNk, c->mode[m].Nk);
+      cap = std::min(cap, maxNk);
+      if (c->tau > 0.0) {
+        const double b = std::floor((1.0 + 0x1p-30) / c->tau) + 1.0;
+        if (b < (double)cap) cap = (u64)b;
+      }
+      c->det_cap = std::max<u64>(cap, 1);
+    }
     c->det_keys = c->alloc<u64>(c->det_cap);
     c->det_tmp = c->alloc<u64>(c->det_cap);
     c->det_blk = c->alloc<unsigned>(256);
@@ -528,13 +561,17 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
     int *err_dev = nullptr;
     std::vector<void *> tmp;
     auto talloc = [&](size_t bytes) {
-      void *p = nullptr;
-      if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
-        for (void *q : tmp) hipFree(q);
+      void *p = c->raw_alloc(bytes);
+      if (!p) {
+        for (void *q : tmp) c->raw_free(q);
         throw cpal_status(CPAL_E_NOMEM);
       }
       tmp.push_back(p);
       return p;
+    };
+    auto tfree_all = [&]() {
+      for (void *q : tmp) c->raw_free(q);
+      tmp.clear();
     };
     int err_host = 0;
     hipError_t e = hipSuccess;
@@ -567,8 +604,7 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
       double *part = (double *)talloc(sizeof(double) * (size_t)(N / 256 + 2));
       fit_norm(X->values, X->value_dtype, N, part, c->st, c->stream);
       e = hipStreamSynchronize(c->stream);
-      for (void *q : tmp) hipFree(q);
-      tmp.clear();
+      tfree_all();
     } else {
       comp = (u64 *)talloc(sizeof(u64) * nnz);
       comp_t = (u64 *)talloc(sizeof(u64) * nnz);
@@ -587,8 +623,7 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
       // ||X||^2 (uses fid as scratch for the block partials)
       fit_norm(X->values, X->value_dtype, nnz, (double *)fid, c->st, c->stream);
       e = hipStreamSynchronize(c->stream);
-      for (void *q : tmp) hipFree(q);
-      tmp.clear();
+      tfree_all();
     }
     if (!dense && e == hipSuccess && !err_host && opt->fit_samples > 0) {
       // stratified fit sample, drawn once (Sec. 6.4)
@@ -601,7 +636,6 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
       c->fit_ld = n_nz + n_z;
       c->fit_nz = n_nz;
       c->phi_nz = n_nz ? (double)nnz / (double)n_nz : 0.0;
-      c->phi_z = n_z ? (double)zeros / (double)n_z : 0.0;
       c->fit_sc = c->alloc<int>((size_t)c->D * std::max<i64>(c->fit_ld, 1));
       c->fit_x = c->alloc<double>(std::max<i64>(c->fit_ld, 1));
       c->fit_part = c->alloc<double>(c->fit_ld / 256 + 2);
@@ -623,9 +657,11 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
       u64 got = 0;
       if (n_z > 0) hipMemcpyAsync(&got, ctl + 2, sizeof(u64), hipMemcpyDeviceToHost, c->stream);
       e = hipStreamSynchronize(c->stream);
-      for (void *q : tmp) hipFree(q);
-      tmp.clear();
+      tfree_all();
       c->fit_n = n_nz + (i64)got;
+      // the zero stratum's weight uses the zeros actually drawn (fewer than
+      // n_z when the draw guard stopped the rejection sampling)
+      c->phi_z = got ? (double)zeros / (double)got : 0.0;
       if ((i64)got < n_z) c->fit_flags |= CPAL_FLAG_DRAWCAP;
     }
     if (e != hipSuccess) {
@@ -785,8 +821,9 @@ void update_back(cpal_ctx *c, int k, cpal_mode_stats *stats_dev) {
 extern "C" {
 
 cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
-                             double *const *factors, void *hip_stream, cpal_ctx **out) {
-  return init_impl(X, opt, factors, hip_stream, nullptr, out);
+                             double *const *factors, void *hip_stream,
+                             const cpal_allocator *alloc, cpal_ctx **out) {
+  return init_impl(X, opt, factors, hip_stream, alloc, nullptr, out);
 }
 
 cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *stats_dev) {
@@ -799,6 +836,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
   c->stage_end(CPAL_STAGE_GATHER, tb);
   update_back(c, k, stats_dev);
   c->t += 1;
+  c->samples_valid = true;
   return check_hip(c, hipGetLastError(), "mode_update launch");
 }
 
@@ -844,6 +882,7 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
     Mode &md = c->mode[k];
     // the sampled system of an update of mode k at the current step, as
     // mode_update would build it; the factors are not touched
+    launch_set_step(c->st, c->t, c->stream);
     update_front(c, k);
     const bool seg = !c->dense && md.n <= (1 << 20);
     static const int seg_grids[] = {256, 512, 1024, 2048};
@@ -885,6 +924,7 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
   c->timing = timing;
   // the trials consumed no step: the next update samples with the same t
   launch_set_step(c->st, c->t, c->stream);
+  c->samples_valid = false;   // the sample buffers hold a trial's rows
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (res != CPAL_OK) return res;
@@ -903,6 +943,7 @@ cpal_status cp_arls_lev_fit_estimate(cpal_ctx *c, double *fit_dev) {
 cpal_status cp_arls_lev_samples(const cpal_ctx *c, uint64_t *idx_dev, double *omega_dev,
                                 double *w_dev, int64_t cap, int64_t *count_dev) {
   if (!c || cap < 0) return CPAL_E_ARG;
+  if (!c->samples_valid) return CPAL_E_STATE;
   launch_samples_out(c->st, c->samp_idx, c->samp_om, c->samp_w, c->s, c->last_key_bits, c->keys,
                      c->keys_tmp, c->ord, c->ord_tmp, c->sort_scratch, cap, (u64 *)idx_dev,
                      omega_dev, w_dev, (i64 *)count_dev, c->stream);
@@ -989,6 +1030,7 @@ struct cpal_batch {
   hipGraphExec_t exec[CPAL_MAXORDER] = {nullptr};   // one captured step per mode
   cpal_mode_stats *stats = nullptr;                 // statistics written by the graphs
   std::vector<int> tensor_of;                       // tensor of each decomposition
+  cpal_allocator al{};                              // alloc == nullptr: hipMalloc / hipFree
 };
 
 namespace {
@@ -1001,7 +1043,10 @@ constexpr int kBatchStreams = 16;
 void batch_free(cpal_batch *b) {
   for (hipGraphExec_t g : b->exec)
     if (g) hipGraphExecDestroy(g);
-  if (b->stats) hipFree(b->stats);
+  if (b->stats) {
+    if (b->al.alloc) b->al.free(b->stats, b->al.user);
+    else hipFree(b->stats);
+  }
   for (cpal_ctx *c : b->ctx)
     if (c) cp_arls_lev_destroy(c);
   for (hipStream_t s : b->streams) hipStreamDestroy(s);
@@ -1065,13 +1110,15 @@ extern "C" {
 cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
                                    const int32_t *tensor_of, const cpal_options *opts,
                                    double *const *const *factors, void *hip_stream,
-                                   cpal_batch **out) {
+                                   const cpal_allocator *alloc, cpal_batch **out) {
   if (!out) return CPAL_E_ARG;
   *out = nullptr;
   if (m < 1 || n < 1 || !Xs || !tensor_of || !opts || !factors) return CPAL_E_ARG;
+  if (alloc && (!alloc->alloc || !alloc->free)) return CPAL_E_ARG;
   for (int i = 0; i < n; ++i)
     if (tensor_of[i] < 0 || tensor_of[i] >= m || !factors[i]) return CPAL_E_ARG;
   cpal_batch *b = new cpal_batch();
+  if (alloc) b->al = *alloc;
   b->user = (hipStream_t)hip_stream;
   const int ns = std::min(n, kBatchStreams);
   for (int j = 0; j < ns; ++j) {
@@ -1086,10 +1133,20 @@ cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
     b->streams.push_back(s);
     b->done.push_back(e);
   }
-  if (hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess ||
-      hipMalloc(&b->stats, sizeof(cpal_mode_stats) * (size_t)n) != hipSuccess) {
+  if (hipEventCreateWithFlags(&b->start, hipEventDisableTiming) != hipSuccess) {
     batch_free(b);
     return CPAL_E_DEVICE;
+  }
+  {
+    const size_t bytes = sizeof(cpal_mode_stats) * (size_t)n;
+    void *p = nullptr;
+    if (b->al.alloc) p = b->al.alloc(bytes, b->al.user);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (!p) {
+      batch_free(b);
+      return CPAL_E_NOMEM;
+    }
+    b->stats = (cpal_mode_stats *)p;
   }
   b->tensor_of.assign(tensor_of, tensor_of + n);
   // init runs on the batch streams after the caller's pending work
@@ -1098,8 +1155,8 @@ cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
   b->ctx.assign(n, nullptr);
   for (int i = 0; i < n; ++i) {
     const int t = tensor_of[i];
-    const cpal_status st = init_impl(&Xs[t], &opts[i], factors[i], b->streams[i % ns], owner[t],
-                                     &b->ctx[i]);
+    const cpal_status st = init_impl(&Xs[t], &opts[i], factors[i], b->streams[i % ns], alloc,
+                                     owner[t], &b->ctx[i]);
     if (st != CPAL_OK) {
       batch_free(b);
       return st;
@@ -1124,6 +1181,7 @@ cpal_status cp_arls_lev_mode_step_batch(cpal_batch *b, int32_t mode, cpal_mode_s
       if (mode < c->D) {   // host state an eager step would have left
         c->t += 1;
         c->last_key_bits = c->mode[mode].key_bits;
+        c->samples_valid = true;
       }
     hipEventRecord(b->done[0], b->streams[0]);
     hipStreamWaitEvent(b->user, b->done[0], 0);
@@ -1172,9 +1230,20 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
       if (st != CPAL_OK) return st;
       tuned[i] = (int)i;
     } else {
+      // a restart takes the tuned shapes; the bucketed gather needs its own
+      // buffers, and where they cannot be had the restart keeps the default
+      bool need_bkt = false;
+      for (int k = 0; k < c->D; ++k) need_bkt |= b->ctx[src]->mode[k].g_sort_min < 0;
+      const bool bkt_ok = need_bkt && ensure_bucket_buffers(c) == CPAL_OK;
       for (int k = 0; k < c->D; ++k) {
-        c->mode[k].g_grid = b->ctx[src]->mode[k].g_grid;
-        c->mode[k].g_sort_min = b->ctx[src]->mode[k].g_sort_min;
+        const int sm = b->ctx[src]->mode[k].g_sort_min;
+        if (sm < 0 && !(bkt_ok && bucket_capable(c, k))) {
+          c->mode[k].g_grid = 0;
+          c->mode[k].g_sort_min = 0;
+        } else {
+          c->mode[k].g_grid = b->ctx[src]->mode[k].g_grid;
+          c->mode[k].g_sort_min = sm;
+        }
       }
       tuned[i] = src;
     }

@@ -56,6 +56,80 @@ def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / den)
 
 
+# unit roundoff of the operands the gather rounds (fiber value and weighted
+# KRP row, each rounded once) and of one accumulation step
+_U_IN = {"f64": 2.0 ** -52, "f32": 2.0 ** -23, "bf16": 2.0 ** -8}
+_U_ACC = {"f64": 2.0 ** -52, "f32": 2.0 ** -24, "bf16": 2.0 ** -24}
+
+
+def sampled_system(OT, fac, k, idx, om):
+    """The explicit sampled system of one update from the oracle's output:
+    Z (s_bar x R), G_s = Z^T Omega Z, M = X~^T Omega Z, the same with
+    absolute values (|X~|^T Omega |Z|, |Z|^T Omega |Z|), and the largest
+    number of terms summed into one entry of M."""
+    dims = [int(d) for d in OT.dims]
+    others = [m for m in range(len(dims)) if m != k]
+    idx = np.asarray(idx, dtype=np.uint64).astype(np.int64)
+    om = np.asarray(om, dtype=np.float64)
+    R = fac[0].shape[1]
+    Z = np.ones((idx.size, R))
+    stride = 1
+    key = np.zeros(OT.nnz, dtype=np.int64)
+    for m in others:
+        Z *= fac[m][(idx // stride) % dims[m]]
+        key += OT.coords[m].astype(np.int64) * stride
+        stride *= dims[m]
+    order = np.argsort(idx, kind="stable")
+    sidx = idx[order]
+    pos = np.searchsorted(sidx, key)
+    pos_c = np.minimum(pos, max(idx.size - 1, 0))
+    hit = (idx.size > 0) & (sidx[pos_c] == key) if idx.size else np.zeros(OT.nnz, bool)
+    j = order[pos_c[hit]]
+    ik = OT.coords[k][hit].astype(np.int64)
+    x = OT.vals[hit]
+    n_k = dims[k]
+    M = np.zeros((n_k, R))
+    Ma = np.zeros((n_k, R))
+    np.add.at(M, ik, (om[j] * x)[:, None] * Z[j])
+    np.add.at(Ma, ik, (om[j] * np.abs(x))[:, None] * np.abs(Z[j]))
+    G = Z.T @ (om[:, None] * Z)
+    Ga = np.abs(Z).T @ (om[:, None] * np.abs(Z))
+    n_terms = int(np.bincount(ik, minlength=n_k).max()) if ik.size else 0
+    return dict(Z=Z, G=G, Ga=Ga, M=M, Ma=Ma, n_terms=n_terms)
+
+
+def derived_tolerance(OT, fac, k, ref, gather):
+    """First-order bound on the relative Frobenius-norm difference of the new
+    factor between the device and the FP64 oracle, from the arithmetic:
+    A = M G_s^+ with M = X~^T Omega Z.  The device rounds each fiber value
+    and each weighted KRP row once to the gather precision and sums in that
+    precision (FP32 for BF16 operands), so every term of M carries a
+    relative error of at most u_in + n u_acc (n = terms in the entry):
+    ||dM||_F <= (u_in + n u_acc) || |X~|^T Omega |Z| ||_F.  G_s is FP64 on
+    both sides, in different orders: ||dG||_F <= 2 n_G 2^-53 || |Z|^T Omega |Z| ||_F.
+    With ||A||_F >= ||M||_F / ||G||_2 and dA = dM G^+ - A dG G^+,
+      ||dA||_F / ||A||_F <= kappa(G_s) (||dM||_F/||M||_F + ||dG||_F/||G||_2),
+    kappa over the nonzero spectrum (the pseudo-inverse when G_s is singular)."""
+    sy = sampled_system(OT, fac, k, ref["idx"], ref["omega"])
+    ev = np.linalg.eigvalsh(sy["G"])
+    top = ev.max() if ev.size else 0.0
+    keep = ev > top * sy["G"].shape[0] * 2.0 ** -52
+    if not np.any(keep):
+        return np.inf
+    kappa = ev[keep].max() / ev[keep].min()
+    n_g = len(ref["idx"])
+    eps_m = _U_IN[gather] + sy["n_terms"] * _U_ACC[gather]
+    mnorm = np.linalg.norm(sy["M"])
+    rel_m = eps_m * np.linalg.norm(sy["Ma"]) / mnorm if mnorm > 0 else 0.0
+    rel_g = 2 * n_g * 2.0 ** -53 * np.linalg.norm(sy["Ga"]) / top
+    return float(kappa * (rel_m + rel_g))
+
+
+def fro_rel_err(a, b):
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a))
+
+
 def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, stream_id=0,
                det_cap=0, OT=None, check_lev=True, label="", dense=False, gather_config=None,
                autotune=False):
@@ -86,6 +160,7 @@ def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, str
     for u in range(updates):
         k = u % D
         host = [f.cpu().numpy().copy() for f in F]
+        inputs = [h.copy() for h in host]   # the update's input factors
         if check_lev:
             for m in range(D):
                 ref_lev, _ = oracle.leverage(host[m])
@@ -119,6 +194,17 @@ def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, str
         assert np.array_equal(om, ref["omega"]), f"{label} update {u}: omega differs"
         assert np.array_equal(w, ref["wgt"]), f"{label} update {u}: weights differ"
         got = F[k].cpu().numpy()
+        if ftol == "derived":
+            # the bound of derived_tolerance on the Frobenius-norm error; in
+            # FP64 the 1e-10 parity bar applies unless the bound is larger
+            # (an ill-conditioned G_s), and then the bound does
+            bound = derived_tolerance(OT, inputs, k, ref, gather)
+            tol = max(bound, 1e-10) if gather == "f64" else bound
+            err = fro_rel_err(got, host[k])
+            assert err <= tol, (f"{label} update {u} (mode {k}): factor rel err {err:.3e} > "
+                                f"derived bound {tol:.2e}")
+            out.append((rs, st, err))
+            continue
         err = rel_err(got, host[k])
         assert err <= ftol, f"{label} update {u} (mode {k}): factor rel err {err:.3e} > {ftol:.1e}"
         out.append((rs, st, err))

@@ -4,6 +4,7 @@ structures match the header's layout."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -29,12 +30,55 @@ def test_library_exports_every_declared_symbol():
     assert sorted(_lib.SYMBOLS) == names
 
 
-def test_struct_layouts():
+def _header_layout(tmp_path):
+    """sizeof / offsetof of every ABI structure, printed by a C program
+    compiled against the header with the host compiler."""
     from paper_2006_16438_amd import _lib
-    assert ctypes.sizeof(_lib.cpal_mode_stats) == 56
-    assert _lib.cpal_mode_stats.flags.offset == 48
-    assert ctypes.sizeof(_lib.cpal_tensor) == 48
-    assert ctypes.sizeof(_lib.cpal_options) == 72
+    structs = {"cpal_mode_stats": _lib.cpal_mode_stats, "cpal_tensor": _lib.cpal_tensor,
+               "cpal_options": _lib.cpal_options, "cpal_allocator": _lib.cpal_allocator}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for name, st in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f in st._fields_:
+            lines.append(f'  printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True)
+    return structs, dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+
+
+def test_struct_layouts(tmp_path):
+    structs, ref = _header_layout(tmp_path)
+    for name, st in structs.items():
+        assert ctypes.sizeof(st) == int(ref[name]), name
+        for f in st._fields_:
+            assert getattr(st, f[0]).offset == int(ref[f"{name}.{f[0]}"]), f"{name}.{f[0]}"
+
+
+def _header_param_counts():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(cp_arls_lev_\w+)\s*\(([^;]*?)\)\s*;", text, flags=re.S):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_header():
+    """Every declared call is bound with as many arguments as the header
+    gives it (e.g. the allocator argument of the two init calls)."""
+    from paper_2006_16438_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libcpal.so is not built; run __graft_entry__.build()")
+    L = _lib.load()
+    counts = _header_param_counts()
+    assert set(counts) == set(_lib.SYMBOLS)
+    for name, n in counts.items():
+        assert len(getattr(L, name).argtypes) == n, name
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -1,0 +1,154 @@
+"""GPU parity of the guarded and degenerate branches, end-to-end agreement
+from one seed, and the device-memory provider of the C ABI.
+
+* Draw guard (Alg. 2 with rejection): a KRP row holding almost all of the
+  probability is deterministic and a random draw is accepted only with
+  probability ~1e-5, so the draws stop at 64 s_rnd + 2^20 (flag DRAWCAP);
+  the device matches the oracle bit for bit, including the weights, which
+  use the number of accepted draws.
+* Deterministic set larger than 4s + 4096 rows (tau << 1/s, Sec. 5.3): kept
+  whole and truncated to the s most probable rows, as the oracle does.
+* Zero stratum of the fit sample cut short by its guard (Sec. 6.4): the
+  device estimate equals the oracle's, both weighting the zeros by the
+  number actually drawn.
+* End to end (100x80x60, 20,000 nonzeros, R = 5, s = 1024, tau = 1/s, FP64,
+  seed 0): device and oracle each run 10 iterations from the same initial
+  factors without exchanging factors; every update's sample indices agree
+  and the factors stay within 1e-10.
+* Allocator: every device allocation of a context goes through the caller's
+  provider and is returned at destroy."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2006_16438_amd import synth
+from paper_2006_16438_amd._lib import CpalError
+from tests.gpu_util import log, make_ctx, rel_err, run_parity
+
+pytestmark = pytest.mark.gpu
+
+
+class _T:
+    def __init__(self, dims, coords, values):
+        self.dims = tuple(dims)
+        self.coords = np.ascontiguousarray(coords, dtype=np.int32)
+        self.values = np.ascontiguousarray(values, dtype=np.float64)
+
+
+def test_draw_guard_parity():
+    dims = (6, 7, 8)
+    T = synth.random_sparse(dims, 100, seed=5)
+    fac = [np.ones((n, 1)) for n in dims]
+    fac[1][0, 0] = 1000.0
+    fac[2][0, 0] = 1000.0
+    log("draw guard: dominant KRP row, s=2048")
+    res = run_parity(T, fac, 1, 2048, 1.0 / 2048, 1, "f64", 1e-10, label="drawcap")
+    rs, st, _ = res[0]
+    assert st["flags"] & oracle.FLAG_DRAWCAP
+    assert st["draws"] == 64 * (2048 - st["s_det"]) + (1 << 20)
+    log(f"  s_det={st['s_det']} accepted={st['s_rnd']} draws={st['draws']}")
+
+
+def test_deterministic_set_beyond_4s_plus_4096():
+    """tau = 1e-6 with s = 16: nearly every KRP row has p > tau, |D| is far
+    above 4s + 4096 = 4160, and the s most probable rows of all of D are
+    kept."""
+    T, _, R = synth.small3(0)
+    fac = synth.gaussian_factors(T.dims, R, 7)
+    log("det set above 4s+4096: tau=1e-6, s=16")
+    res = run_parity(T, fac, R, 16, 1e-6, 3, "f64", 1e-10, label="det-overflow")
+    for rs, st, _ in res:
+        assert st["flags"] & oracle.FLAG_DET_TRUNC
+        assert not st["flags"] & 32   # CPAL_FLAG_OVERFLOW
+
+
+def test_fit_zero_stratum_guard_parity():
+    dims = (10, 10, 10)
+    R = 2
+    fac = synth.gaussian_factors(dims, R, 5)
+    full = np.array(np.unravel_index(np.arange(1000), dims, order="F"), dtype=np.int32)
+    keep = np.setdiff1d(np.arange(1000), [137, 802])
+    coords = full[:, keep]
+    vals = np.einsum("ir,jr,kr->ijk", *fac)[tuple(coords)] + 0.25
+    T = _T(dims, coords, vals)
+    OT = oracle.Tensor(dims, T.coords, T.values)
+    fs = oracle.FitSample(OT, 20000, 0.5, seed=0)
+    assert fs.flags & oracle.FLAG_DRAWCAP
+    ctx, F = make_ctx(T, fac, R, 64, gather="f64", fit_samples=20000)
+    got = float(ctx.fit_estimate().item())
+    ref = fs.estimate([f.copy() for f in fac])
+    log(f"  zero-guard fit gpu={got!r} oracle={ref!r} zeros drawn={fs.n - 10000}")
+    assert abs(got - ref) <= 1e-10 * max(1.0, abs(ref))
+    ctx.close()
+
+
+def test_end_to_end_small3_from_seed0():
+    T, _, R = synth.small3(0)
+    s, tau, iters = 1024, 1.0 / 1024, 10
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    OT = oracle.Tensor.from_synth(T)
+    ctx, F = make_ctx(T, fac, R, s, tau, "f64")
+    fo = [f.copy() for f in fac]
+    agree, worst = [], 0.0
+    for u in range(iters * 3):
+        k = u % 3
+        ref = oracle.mode_update(OT, fo, k, u, R, s, tau)
+        ctx.mode_update(k)
+        idx = ctx.samples_view()[0].cpu().numpy().view(np.uint64)
+        agree.append(float(np.mean(idx == ref["idx"])) if idx.size == ref["idx"].size else 0.0)
+        worst = max(worst, max(rel_err(F[m].cpu().numpy(), fo[m]) for m in range(3)))
+    fit_g = oracle.fit_exact(OT, [f.cpu().numpy() for f in F], R)
+    fit_o = oracle.fit_exact(OT, fo, R)
+    log(f"  end to end: index agreement min {min(agree):.4f}, max factor rel err {worst:.2e}, "
+        f"fit gpu {fit_g:.12f} oracle {fit_o:.12f}")
+    ctx.close()
+    assert min(agree) == 1.0
+    assert worst <= 1e-10
+    assert abs(fit_g - fit_o) <= 1e-10
+
+
+def test_allocator_callbacks_balance():
+    from paper_2006_16438_amd.api import CpArlsLev, TorchAllocator
+    T, _, R = synth.small3(0)
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    dev = torch.device("cuda:0")
+    al = TorchAllocator(dev)
+    F = [torch.from_numpy(f.copy()).to(dev) for f in fac]
+    ctx = CpArlsLev(T.dims, torch.from_numpy(T.coords).to(dev), torch.from_numpy(T.values).to(dev),
+                    F, R, 1024, gather_dtype="f32", fit_samples=4096, allocator=al)
+    n0 = al.n_alloc
+    assert n0 > 10 and al.n_free > 0          # init temporaries returned already
+    assert al.live and al.live_bytes > 0
+    ctx.set_gather_config(0, 0, -1)           # bucketed gather buffers, allocated now
+    assert al.n_alloc > n0
+    for k in range(3):
+        ctx.mode_update(k)
+    ctx.fit_estimate()
+    torch.cuda.synchronize()
+    ctx.close()
+    log(f"  allocator: {al.n_alloc} allocations, {al.n_free} frees")
+    assert al.n_alloc == al.n_free and not al.live
+    # the library's own hipMalloc path (no provider)
+    ctx2 = CpArlsLev(T.dims, torch.from_numpy(T.coords).to(dev),
+                     torch.from_numpy(T.values).to(dev),
+                     [torch.from_numpy(f.copy()).to(dev) for f in fac], R, 1024, allocator=None)
+    ctx2.mode_update(0)
+    torch.cuda.synchronize()
+    ctx2.close()
+
+
+def test_samples_invalid_after_autotune():
+    T, _, R = synth.small3(0)
+    fac = synth.gaussian_factors(T.dims, R, 0)
+    ctx, F = make_ctx(T, fac, R, 1024, gather="f32")
+    with pytest.raises(CpalError):
+        ctx.samples_view()                     # no update yet
+    ctx.mode_update(0)
+    ctx.samples_view()
+    ctx.autotune()
+    with pytest.raises(CpalError):
+        ctx.samples_view()                     # the buffers hold a trial's rows
+    ctx.mode_update(1)
+    assert ctx.samples_view()[0].numel() > 0
+    ctx.close()

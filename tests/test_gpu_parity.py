@@ -1,7 +1,11 @@
 """GPU parity: the HIP mode update against the FP64 CPU oracle, per update
 with identical inputs (see gpu_util.run_parity).  Sample indices, omega,
 weights, statistics and leverage scores are compared bit for bit; factors
-within 1e-10 relative (max-norm) in FP64 gather mode, 1e-4 in FP32 mode."""
+within 1e-10 relative (max-norm) in FP64 gather mode; in FP32 mode within
+the bound derived per update from the rounding of the operands, the number
+of terms summed and the condition number of G_s (gpu_util.derived_tolerance).
+Edge cases whose G_s is ill-conditioned (s = 1, R = 64) take the larger of
+1e-10 and that bound in FP64 too."""
 import numpy as np
 import pytest
 
@@ -38,7 +42,7 @@ def test_small3_fp32_gather():
     T, _, R = synth.small3(0)
     fac = synth.gaussian_factors(T.dims, R, 0)
     log("small3 fp32 gather: 9 updates")
-    run_parity(T, fac, R, 1024, 1 / 1024, 9, "f32", 1e-4, label="small3-f32")
+    run_parity(T, fac, R, 1024, 1 / 1024, 9, "f32", "derived", label="small3-f32")
 
 
 def test_small3_random_only():
@@ -106,7 +110,7 @@ def test_shapes_and_edges(dims, R, s, nnz):
     T = synth.random_sparse(dims, nnz, seed=sum(dims) + R)
     fac = synth.gaussian_factors(dims, R, R + s)
     log(f"edge case dims={dims} R={R} s={s} nnz={nnz}")
-    run_parity(T, fac, R, s, 1.0 / s if s > 1 else 1.0, 2 * len(dims), "f64", 1e-9,
+    run_parity(T, fac, R, s, 1.0 / s if s > 1 else 1.0, 2 * len(dims), "f64", "derived",
                label=f"edge{dims}")
 
 
@@ -166,7 +170,7 @@ def test_uber4_full_size_fp32():
     R = 25
     fac = synth.gaussian_factors(T.dims, R, 0)
     log("uber4 full size fp32: 4 updates")
-    res = run_parity(T, fac, R, 1 << 17, 2.0 ** -17, 4, "f32", 1e-4, label="uber4")
+    res = run_parity(T, fac, R, 1 << 17, 2.0 ** -17, 4, "f32", "derived", label="uber4")
     for rs, st, err in res:
         assert rs is not None
         log(f"  s_bar={st['s_bar']} nnz(X~)={st['gathered_nnz']} err={err:.2e}")
@@ -207,7 +211,7 @@ def test_large_mode_gather_paths(gather):
     R = 16
     fac = concentrated(dims, R, 32)
     log(f"large mode gather paths ({gather})")
-    run_parity(T, fac, R, 4096, 1 / 4096, 6, gather, 1e-10 if gather == "f64" else 1e-4,
+    run_parity(T, fac, R, 4096, 1 / 4096, 6, gather, 1e-10 if gather == "f64" else "derived",
                label=f"large-{gather}")
 
 
@@ -220,7 +224,7 @@ def test_tall_mode_atomic_gather(gather):
     R = 8
     fac = concentrated(dims, R, 43)
     log(f"tall mode atomic gather ({gather})")
-    run_parity(T, fac, R, 2048, 1 / 2048, 3, gather, 1e-10 if gather == "f64" else 1e-4,
+    run_parity(T, fac, R, 2048, 1 / 2048, 3, gather, 1e-10 if gather == "f64" else "derived",
                label=f"tall-{gather}")
 
 
@@ -250,7 +254,7 @@ def test_autotune_then_parity(gather):
     R = 8
     fac = concentrated(dims, R, 22)
     log(f"autotune then parity ({gather})")
-    run_parity(T, fac, R, 8192, 1 / 8192, 6, gather, 1e-10 if gather == "f64" else 1e-4,
+    run_parity(T, fac, R, 8192, 1 / 8192, 6, gather, 1e-10 if gather == "f64" else "derived",
                label=f"autotune-{gather}", autotune=True)
 
 
@@ -275,7 +279,7 @@ def test_bucketed_gather_fp32(case):
         R, s, tau, n = 25, 1 << 17, 2.0 ** -17, 4
         fac = synth.gaussian_factors(T.dims, R, 0)
     log(f"bucketed gather, {case}")
-    run_parity(T, fac, R, s, tau, n, "f32", 1e-4, label=f"bucketed-{case}",
+    run_parity(T, fac, R, s, tau, n, "f32", "derived", label=f"bucketed-{case}",
                gather_config=(512, -1))
 
 

@@ -496,3 +496,113 @@ def test_leverage_fewer_rows_than_rank():
     assert fl & oracle.FLAG_PINV
     assert np.max(np.abs(lev - ref)) < 1e-10
     assert abs(lev.sum() - 23) < 1e-9
+
+
+# ------------------------------------- singular G_s, draw guards, zero stratum --
+def _sketched_minimum_norm(dims, T, fac, k, out):
+    """argmin ||Omega Z B^T - Omega X_(k)^T|| of eq. (1.2) built explicitly
+    from the returned rows and weights; numpy's SVD-based lstsq returns the
+    minimizer of least norm when the system is rank-deficient."""
+    others = [m for m in range(len(dims)) if m != k]
+    Z = krp_rows(fac, others)
+    Xk = unfold(dims, T.coords, T.values, k)
+    ii = out["idx"].astype(np.int64)
+    wv = out["wgt"][:, None]
+    B, *_ = np.linalg.lstsq(wv * Z[ii], wv * Xk[:, ii].T, rcond=None)
+    return B.T
+
+
+@pytest.mark.parametrize("case", ["collinear", "one_sample"])
+def test_singular_sampled_gram_gives_minimum_norm_solution(case):
+    """A singular G_s = Z~^T Z~ leaves the sketched problem (1.2) with many
+    minimizers; the update takes the one of least norm, G_s^+ applied to M
+    (the pseudo-inverse branch of the solve).  'collinear': two KRP columns
+    are equal bit for bit (the null vector (1, -1, 0) is not a coordinate
+    axis, so a transposed or mis-cut eigenbasis fails); 'one_sample': s = 1
+    gives a rank-1 G_s."""
+    dims = (9, 7, 6)
+    R = 3
+    T = synth.random_sparse(dims, 150, seed=21)
+    OT = oracle.Tensor.from_synth(T)
+    fac = synth.gaussian_factors(dims, R, 22)
+    if case == "collinear":
+        for m in (1, 2):
+            fac[m][:, 1] = fac[m][:, 0]
+        s, tau = 24, None
+    else:
+        s, tau = 1, 1.0
+    for k in range(3):
+        if case == "collinear" and k != 0:
+            continue
+        f2 = [f.copy() for f in fac]
+        out = oracle.mode_update(OT, f2, k, 3 + k, R, s, tau)
+        assert out["stats"]["flags"] & oracle.FLAG_PINV
+        ref = _sketched_minimum_norm(dims, T, fac, k, out)
+        err = np.max(np.abs(f2[k] - ref)) / np.max(np.abs(ref))
+        assert err < 1e-10, (case, k, err)
+        if case == "collinear":
+            # the least-norm solution splits equally over the two equal columns
+            assert np.max(np.abs(f2[k][:, 0] - f2[k][:, 1])) < 1e-12 * np.max(np.abs(f2[k]))
+
+
+def test_draw_guard_stops_rejection_and_normalizes_by_accepted_draws():
+    """One KRP row holds almost all probability (p ~ 0.99999 > tau), so it is
+    deterministic and a random draw is accepted (p <= tau) only with
+    probability 1 - p_det ~ 1e-5: the rejection loop of Alg. 2 stops at the
+    guard of 64 s_rnd + 2^20 draws with fewer accepted draws than asked for.
+    The weights then use the number of accepted draws (the draws are an
+    i.i.d. sample of that size from p restricted to p <= tau), which makes
+    sum_rnd omega_j p_j = 1 - p_det hold exactly: the random rows estimate
+    the mass outside the deterministic set without bias (Lemma 3.2)."""
+    dims = (6, 7, 8)
+    R = 1
+    T = synth.random_sparse(dims, 100, seed=5)
+    OT = oracle.Tensor.from_synth(T)
+    fac = [np.ones((n, 1)) for n in dims]
+    fac[1][0, 0] = 1000.0
+    fac[2][0, 0] = 1000.0
+    s = 2048
+    tau = 1.0 / s
+    f2 = [f.copy() for f in fac]
+    out = oracle.mode_update(OT, f2, 0, 0, R, s, tau)
+    st = out["stats"]
+    assert st["flags"] & oracle.FLAG_DRAWCAP
+    assert st["s_det"] == 1 and out["idx"][0] == 0
+    assert st["draws"] == 64 * (s - 1) + (1 << 20)
+    assert 0 < st["s_rnd"] < s - 1
+    assert out["raw"].size == st["s_rnd"]
+    q = q_vectors(fac, R)
+    lin = out["idx"][1:].astype(np.int64)
+    p = q[1][lin % 7] * q[2][lin // 7]
+    assert np.all(p <= tau)
+    om = out["omega"][1:]
+    assert abs(np.sum(om * p) - (1 - st["p_det"])) < 1e-12 * (1 - st["p_det"])
+    counts = om * st["s_rnd"] * p / (1 - st["p_det"])
+    assert np.allclose(counts, np.round(counts), atol=1e-9) and round(counts.sum()) == st["s_rnd"]
+
+
+def test_fit_estimate_zero_stratum_weight_uses_the_zeros_drawn():
+    """A nearly full tensor (998 of 1000 entries stored): the rejection
+    sampling of zeros (Sec. 6.4) stops at its guard with fewer zeros than
+    floor((1 - alpha) s_fit).  The zero stratum (2 entries) is then
+    represented by the zeros actually drawn, phi = 2 / drawn, and F_hat
+    still estimates ||X - M||^2 = the model's squares at the two zeros
+    (the stored values equal the model, so the nonzero stratum adds 0)."""
+    dims = (10, 10, 10)
+    R = 2
+    fac = synth.gaussian_factors(dims, R, 5)
+    full = np.array(np.unravel_index(np.arange(1000), dims, order="F"), dtype=np.int32)
+    missing = [137, 802]
+    keep = np.setdiff1d(np.arange(1000), missing)
+    coords = np.ascontiguousarray(full[:, keep])
+    M = np.einsum("ir,jr,kr->ijk", *fac)
+    vals = M[tuple(coords)]
+    OT = oracle.Tensor(dims, coords, vals)
+    fs = oracle.FitSample(OT, 20000, 0.5, seed=0)
+    assert fs.flags & oracle.FLAG_DRAWCAP
+    got = fs.n - 10000
+    assert 0 < got < 10000
+    assert np.all(fs.phi[10000:fs.n] == 2.0 / got)
+    F = sum(M[tuple(full[:, e])] ** 2 for e in missing)
+    fhat = ((1 - fs.estimate(fac)) * OT.norm) ** 2
+    assert abs(fhat / F - 1) < 0.1, (fhat, F)
