@@ -44,6 +44,15 @@ typedef enum {
 
 typedef enum { CPAL_F64 = 0, CPAL_F32 = 1, CPAL_BF16 = 2 } cpal_dtype;
 
+/* Probability of row i of factor m used to sample KRP rows; a KRP row's
+ * probability is the product over the other modes (Sec. 5.3 for leverage,
+ * App. B for the other two). */
+typedef enum {
+  CPAL_SAMPLE_LEVERAGE = 0,        /* l_i(A_m) / R (Def. 3.4; the method)              */
+  CPAL_SAMPLE_UNIFORM = 1,         /* 1 / n_m                                          */
+  CPAL_SAMPLE_LENGTH_SQUARED = 2   /* ||A_m(i,:)||^2 / ||A_m||_F^2                      */
+} cpal_sampling;
+
 /* Bits of cpal_mode_stats.flags. */
 enum {
   CPAL_FLAG_PINV = 1,       /* a Gram matrix was singular: pseudo-inverse used        */
@@ -104,6 +113,11 @@ typedef struct {
   double fit_nnz_fraction;   /* alpha in [0,1] (Sec. 6.4), default 0.5                 */
   int64_t det_enum_cap;      /* max candidate combinations examined by the
                                 deterministic enumeration; 0 = 2^26                  */
+  int32_t sampling;          /* cpal_sampling: CPAL_SAMPLE_LEVERAGE (0, the method),
+                                CPAL_SAMPLE_UNIFORM or CPAL_SAMPLE_LENGTH_SQUARED;
+                                the scores behind the probabilities are what
+                                cp_arls_lev_leverage returns                         */
+  int32_t pad;
 } cpal_options;
 
 typedef struct {
@@ -162,6 +176,49 @@ cpal_status cp_arls_lev_fit_estimate(cpal_ctx *ctx, double *fit_dev);
  * next update.  Exists so that callers can audit the sketch. */
 cpal_status cp_arls_lev_samples(const cpal_ctx *ctx, uint64_t *idx_dev, double *omega_dev,
                                 double *w_dev, int64_t cap, int64_t *count_dev);
+
+/* Exact fit 1 - ||X - M|| / ||X|| (eq. (6.1)) of the current factors, with
+ * ||X - M||^2 = ||X||^2 - 2 <X, M> + sum_{r,r'} prod_m (A_m^T A_m)(r,r'):
+ * <X, M> is summed over every stored entry (dense: every entry) from the
+ * per-mode copy of the mode with the fewest rows (a dense BF16 context holds
+ * only BF16 copies, so its exact fit is that of the BF16-rounded tensor).
+ * The sums are blocked in a fixed order, so the result does not vary from
+ * run to run.  fit_dev: device pointer to one double.  Asynchronous. */
+cpal_status cp_arls_lev_fit_exact(cpal_ctx *ctx, double *fit_dev);
+
+/* Options of the full CP-ARLS-LEV loop (Alg. 3). */
+typedef struct {
+  int32_t eta;          /* outer iterations per epoch, >= 1 (Alg. 3 default 5)           */
+  int32_t pi;           /* consecutive epochs without improvement that end the run, >= 1
+                           (default 3)                                                   */
+  double tol;           /* an epoch improves when its fit exceeds the best earlier fit by
+                           more than tol (>= 0; default 1e-4)                            */
+  int32_t max_epochs;   /* upper bound on the epochs run, >= 1                           */
+  int32_t exact_fit;    /* 0: the estimated fit of Sec. 6.4 (needs fit_samples > 0);
+                           1: the exact fit (cp_arls_lev_fit_exact)                      */
+} cpal_run_options;
+
+typedef struct {
+  int32_t epochs;          /* epochs run (entries of the fit trace)                      */
+  int32_t stopped;         /* 1: pi epochs in a row did not improve; 0: max_epochs hit   */
+  double best_fit;         /* largest fit in the trace                                   */
+  double final_exact_fit;  /* exact fit of the final factors; with exact_fit = 0, the
+                              trace minus (last trace entry - this) is the bias-corrected
+                              fit trace of Sec. 7                                        */
+} cpal_run_result;
+
+/* CP-ARLS-LEV (Alg. 3) from the context's current state: epochs of eta outer
+ * iterations, each iteration one mode update of every mode in ascending
+ * order; after each epoch the fit (estimated or exact) is taken and copied to
+ * the host; the run ends when pi consecutive epochs fail to improve on the
+ * best earlier fit by more than tol, or after max_epochs.  fit_trace_host:
+ * host array of max_epochs doubles (the fit after each epoch); res_host: the
+ * outcome.  Factors are updated in place; the step counter advances by one
+ * per mode update.  Synchronizes the stream once per epoch.  Errors:
+ * CPAL_E_ARG (bad options or null pointers), CPAL_E_STATE (estimated fit
+ * without a fit sample, or a failed context), CPAL_E_DEVICE. */
+cpal_status cp_arls_lev_run(cpal_ctx *ctx, const cpal_run_options *opts, double *fit_trace_host,
+                            cpal_run_result *res_host);
 
 /* Copy the cached leverage scores (Def. 3.4) of a mode: n_mode doubles. */
 cpal_status cp_arls_lev_leverage(const cpal_ctx *ctx, int32_t mode, double *lev_dev);

@@ -38,7 +38,10 @@ class _Tensor(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("rank", C.c_int32), ("samples", C.c_int64), ("tau", C.c_double),
-                ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("det_cap", C.c_int64)]
+                ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("det_cap", C.c_int64),
+                ("sampling", C.c_int32), ("pad", C.c_int32)]
+
+SAMPLING = {"leverage": 0, "uniform": 1, "length_squared": 2}
 
 
 class _Stats(C.Structure):
@@ -64,6 +67,11 @@ def lib():
         L.orc_sampling_vectors.argtypes = [P(C.c_double), C.c_int64, C.c_int32,
                                            P(C.c_uint64), P(C.c_uint64), P(C.c_double)]
         L.orc_sampling_vectors.restype = C.c_uint64
+        L.orc_scores.argtypes = [P(C.c_double), C.c_int64, C.c_int32, C.c_int32, P(C.c_double)]
+        L.orc_scores.restype = C.c_double
+        L.orc_sampling_vectors_norm.argtypes = [P(C.c_double), C.c_int64, C.c_double,
+                                                P(C.c_uint64), P(C.c_uint64), P(C.c_double)]
+        L.orc_sampling_vectors_norm.restype = C.c_uint64
         L.orc_index_build.argtypes = [P(_Tensor)]
         L.orc_index_build.restype = C.c_void_p
         L.orc_index_free.argtypes = [C.c_void_p]
@@ -141,6 +149,28 @@ def sampling_vectors(lev, R):
     return w, Cdf, q, int(W)
 
 
+def scores(A, kind):
+    """Row scores of App. B's distributions: returns (score, total)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n, R = A.shape
+    sc = np.zeros(n)
+    S = lib().orc_scores(_p(A, C.c_double), n, R, SAMPLING[kind] if isinstance(kind, str) else kind,
+                         _p(sc, C.c_double))
+    return sc, float(S)
+
+
+def sampling_vectors_norm(score, S):
+    """(w, C, q, W) with the scores normalised by S."""
+    score = np.ascontiguousarray(score, dtype=np.float64)
+    n = score.size
+    w = np.zeros(n, dtype=np.uint64)
+    Cdf = np.zeros(n, dtype=np.uint64)
+    q = np.zeros(n)
+    W = lib().orc_sampling_vectors_norm(_p(score, C.c_double), n, S, _p(w, C.c_uint64),
+                                        _p(Cdf, C.c_uint64), _p(q, C.c_double))
+    return w, Cdf, q, int(W)
+
+
 def det_set(dims, qs, k, s, tau, det_cap=1 << 26, cap=None):
     """Returns (idx, p, p_det, flags)."""
     order = len(dims)
@@ -204,13 +234,13 @@ def _fac_ptrs(factors):
 
 
 def mode_update(T: Tensor, factors, k, t, rank, samples, tau=None, seed=0, stream_id=0,
-                det_cap=1 << 26):
+                det_cap=1 << 26, sampling="leverage"):
     """One mode update, in place on factors[k].  Returns a dict with idx, omega,
     wgt (the s_bar sampled rows), raw (accepted random draws, draw order) and
     the stats."""
     if tau is None:
         tau = 1.0 / samples
-    opts = _Opts(rank, samples, tau, seed, stream_id, det_cap)
+    opts = _Opts(rank, samples, tau, seed, stream_id, det_cap, SAMPLING[sampling], 0)
     idx = np.zeros(samples, dtype=np.uint64)
     om = np.zeros(samples)
     wg = np.zeros(samples)
@@ -276,3 +306,34 @@ def cp_arls_lev(T: Tensor, factors, rank, samples, iters, tau=None, seed=0, stre
             log.append(out["stats"])
             t += 1
     return log
+
+
+def cp_arls_lev_run(T: Tensor, factors, rank, samples, eta=5, pi=3, tol=1e-4, max_epochs=100,
+                    tau=None, seed=0, stream_id=0, fit_sample=None, det_cap=1 << 26, t0=0):
+    """The full loop of Alg. 3: epochs of eta outer iterations (every mode
+    once per iteration, ascending), the fit after each epoch -- the estimate
+    of Sec. 6.4 from `fit_sample` (a FitSample drawn once), or the exact fit
+    when it is None -- and the stop when pi consecutive epochs fail to beat
+    the best earlier fit by more than tol (or after max_epochs).  Factors are
+    updated in place; the step counter starts at t0 and advances by one per
+    mode update.  Returns dict(trace, epochs, stopped, best_fit,
+    final_exact_fit)."""
+    t = t0
+    trace = []
+    best = -np.inf
+    fails = 0
+    stopped = False
+    while len(trace) < max_epochs:
+        for _ in range(eta):
+            for k in range(T.order):
+                mode_update(T, factors, k, t, rank, samples, tau, seed, stream_id, det_cap)
+                t += 1
+        fit = fit_sample.estimate(factors) if fit_sample is not None else fit_exact(T, factors, rank)
+        trace.append(fit)
+        fails = 0 if fit > best + tol else fails + 1
+        best = max(best, fit)
+        if fails >= pi:
+            stopped = True
+            break
+    return dict(trace=np.array(trace), epochs=len(trace), stopped=stopped, best_fit=best,
+                final_exact_fit=fit_exact(T, factors, rank))

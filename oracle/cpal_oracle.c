@@ -308,9 +308,33 @@ int32_t orc_leverage(const double *A, int64_t n, int32_t R, double *lev) {
  * floor(2^52 * l_i / R), W = sum w, C = inclusive prefix, q_i = w_i / W. */
 uint64_t orc_sampling_vectors(const double *lev, int64_t n, int32_t R,
                               uint64_t *w, uint64_t *C, double *q) {
+  return orc_sampling_vectors_norm(lev, n, (double)R, w, C, q);
+}
+
+/* The other row distributions of App. B: uniform, and length squared, whose
+ * total ||A||_F^2 is the trace of the Gram matrix in orc_gram's order. */
+double orc_scores(const double *A, int64_t n, int32_t R, int32_t kind, double *score) {
+  if (kind == 1) {
+    for (int64_t i = 0; i < n; ++i) score[i] = 1.0;
+    return (double)n;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int c = 0; c < R; ++c) acc = acc + A[i * R + c] * A[i * R + c];
+    score[i] = acc;
+  }
+  double G[MAXR * MAXR];
+  orc_gram(A, n, R, G);
+  double S = 0.0;
+  for (int j = 0; j < R; ++j) S = S + G[j * R + j];
+  return S;
+}
+
+uint64_t orc_sampling_vectors_norm(const double *lev, int64_t n, double S,
+                                   uint64_t *w, uint64_t *C, double *q) {
   uint64_t W = 0;
   for (int64_t i = 0; i < n; ++i) {
-    double v = lev[i] / (double)R;
+    double v = S > 0.0 ? lev[i] / S : 0.0;
     if (!(v > 0.0)) v = 0.0;
     if (v > 1.0) v = 1.0;
     w[i] = (uint64_t)(v * 0x1p52);
@@ -523,6 +547,7 @@ int32_t orc_mode_update(const orc_tensor *X, const orc_index *ix,
   const int64_t s = opt->samples;
   if (D < 2 || D > 16 || R < 1 || R > MAXR || s < 1 || k < 0 || k >= D) return 1;
   if (!(opt->tau >= 0.0 && opt->tau <= 1.0)) return 1;
+  if (opt->sampling < 0 || opt->sampling > 2) return 1;
   memset(st, 0, sizeof(*st));
 
   /* leverage and sampling vectors of every other mode (Alg. 3 setup) */
@@ -536,8 +561,13 @@ int32_t orc_mode_update(const orc_tensor *X, const orc_index *ix,
     uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * n);
     q[m] = (double *)malloc(sizeof(double) * n);
     C[m] = (uint64_t *)malloc(sizeof(uint64_t) * n);
-    st->flags |= orc_leverage(factors[m], n, R, lev);
-    W[m] = orc_sampling_vectors(lev, n, R, w, C[m], q[m]);
+    if (opt->sampling == 0) {
+      st->flags |= orc_leverage(factors[m], n, R, lev);
+      W[m] = orc_sampling_vectors(lev, n, R, w, C[m], q[m]);
+    } else {
+      double S = orc_scores(factors[m], n, R, opt->sampling, lev);
+      W[m] = orc_sampling_vectors_norm(lev, n, S, w, C[m], q[m]);
+    }
     free(lev);
     free(w);
   }

@@ -36,6 +36,8 @@ typedef struct {
   uint64_t seed;
   uint64_t stream_id;
   int64_t det_cap;
+  int32_t sampling;   /* 0 leverage scores, 1 uniform, 2 length squared (App. B) */
+  int32_t pad;
 } orc_opts;
 
 typedef struct {
@@ -62,6 +64,14 @@ int32_t orc_leverage(const double *A, int64_t n, int32_t R, double *lev);
 /* Integer sampling weights, inclusive CDF and probabilities; returns W. */
 uint64_t orc_sampling_vectors(const double *lev, int64_t n, int32_t R,
                               uint64_t *w, uint64_t *C, double *q);
+
+/* Row scores of the sampling distributions of App. B: kind 1 uniform (every
+ * score 1), kind 2 length squared (||A(i,:)||^2); returns their total
+ * (n, or the trace of orc_gram's blocked Gram matrix). */
+double orc_scores(const double *A, int64_t n, int32_t R, int32_t kind, double *score);
+/* As orc_sampling_vectors with the scores normalised by S instead of R. */
+uint64_t orc_sampling_vectors_norm(const double *score, int64_t n, double S,
+                                   uint64_t *w, uint64_t *C, double *q);
 
 /* Per-mode fiber index (sorted complement keys). */
 orc_index *orc_index_build(const orc_tensor *X);

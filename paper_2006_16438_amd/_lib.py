@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libcpal.so")
 
 CPAL_OK, CPAL_E_ARG, CPAL_E_NOMEM, CPAL_E_DEVICE, CPAL_E_STATE = 0, 1, 2, 3, 4
 CPAL_F64, CPAL_F32, CPAL_BF16 = 0, 1, 2
+SAMPLING = {"leverage": 0, "uniform": 1, "length_squared": 2}
 FLAG_PINV, FLAG_DETCAP, FLAG_DET_TRUNC, FLAG_PDET_ONE, FLAG_DRAWCAP, FLAG_OVERFLOW, FLAG_STATE = (
     1, 2, 4, 8, 16, 32, 64)
 
@@ -26,7 +27,7 @@ SYMBOLS = (
     "cp_arls_lev_init_batch", "cp_arls_lev_mode_step_batch", "cp_arls_lev_fit_estimate_batch",
     "cp_arls_lev_batch_set_graphs", "cp_arls_lev_batch_ctx", "cp_arls_lev_destroy_batch",
     "cp_arls_lev_set_gather_config", "cp_arls_lev_get_gather_config", "cp_arls_lev_autotune",
-    "cp_arls_lev_autotune_batch",
+    "cp_arls_lev_autotune_batch", "cp_arls_lev_fit_exact", "cp_arls_lev_run",
 )
 STAGES = ("sample", "rows", "gather", "solve", "leverage")
 
@@ -49,13 +50,23 @@ class cpal_options(C.Structure):
     _fields_ = [("rank", C.c_int32), ("samples", C.c_int64), ("tau", C.c_double),
                 ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("gather_dtype", C.c_int32),
                 ("fit_samples", C.c_int64), ("fit_nnz_fraction", C.c_double),
-                ("det_enum_cap", C.c_int64)]
+                ("det_enum_cap", C.c_int64), ("sampling", C.c_int32), ("pad", C.c_int32)]
 
 
 class cpal_mode_stats(C.Structure):
     _fields_ = [("s_det", C.c_int64), ("s_rnd", C.c_int64), ("s_bar", C.c_int64),
                 ("draws", C.c_int64), ("gathered_nnz", C.c_int64), ("p_det", C.c_double),
                 ("flags", C.c_int32), ("pad", C.c_int32)]
+
+
+class cpal_run_options(C.Structure):
+    _fields_ = [("eta", C.c_int32), ("pi", C.c_int32), ("tol", C.c_double),
+                ("max_epochs", C.c_int32), ("exact_fit", C.c_int32)]
+
+
+class cpal_run_result(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("stopped", C.c_int32), ("best_fit", C.c_double),
+                ("final_exact_fit", C.c_double)]
 
 
 STATS_BYTES = C.sizeof(cpal_mode_stats)
@@ -80,6 +91,10 @@ def load(path: str | None = None):
     L.cp_arls_lev_mode_update.restype = C.c_int
     L.cp_arls_lev_fit_estimate.argtypes = [vp, vp]
     L.cp_arls_lev_fit_estimate.restype = C.c_int
+    L.cp_arls_lev_fit_exact.argtypes = [vp, vp]
+    L.cp_arls_lev_fit_exact.restype = C.c_int
+    L.cp_arls_lev_run.argtypes = [vp, P(cpal_run_options), P(C.c_double), P(cpal_run_result)]
+    L.cp_arls_lev_run.restype = C.c_int
     L.cp_arls_lev_samples.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
     L.cp_arls_lev_samples.restype = C.c_int
     L.cp_arls_lev_leverage.argtypes = [vp, C.c_int32, vp]

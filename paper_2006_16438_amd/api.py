@@ -81,7 +81,7 @@ def _check(code, ctx_ptr=None):
 class CpArlsLev:
     def __init__(self, dims, coords, values, factors, rank, samples, tau=None, seed=0,
                  stream_id=0, gather_dtype="f64", fit_samples=0, fit_alpha=0.5,
-                 det_enum_cap=0, stream=None, allocator="torch"):
+                 det_enum_cap=0, stream=None, allocator="torch", sampling="leverage"):
         lib = L.load()
         self.order = len(dims)
         self.dims = tuple(int(n) for n in dims)
@@ -122,8 +122,10 @@ class CpArlsLev:
                           1 if self.dense else 0)
         gdt = {"f64": L.CPAL_F64, "f32": L.CPAL_F32, "bf16": L.CPAL_BF16}[gather_dtype]
         self.gather_dtype = gather_dtype
+        self.sampling = sampling
         o = L.cpal_options(self.rank, self.samples, self.tau, seed, stream_id, gdt,
-                           int(fit_samples), float(fit_alpha), int(det_enum_cap))
+                           int(fit_samples), float(fit_alpha), int(det_enum_cap),
+                           L.SAMPLING[sampling], 0)
         fp = (C.c_void_p * self.order)(*[f.data_ptr() for f in self.factors])
         self._ctx = C.c_void_p()
         self.allocator, aptr = _allocator_arg(allocator, self.values.device, self.stream)
@@ -220,6 +222,32 @@ class CpArlsLev:
         _check(L.load().cp_arls_lev_fit_estimate(self._ctx, out.data_ptr()), self._ctx)
         return out
 
+    def fit_exact(self, out=None):
+        """Exact fit of the current factors (eq. (6.1)), on the device."""
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.values.device)
+        _check(L.load().cp_arls_lev_fit_exact(self._ctx, out.data_ptr()), self._ctx)
+        return out
+
+    def run(self, eta=5, pi=3, tol=1e-4, max_epochs=100, exact_fit=False):
+        """CP-ARLS-LEV (Alg. 3) until pi epochs of eta iterations fail to
+        improve the fit by more than tol.  Returns a dict: trace (fit after
+        each epoch), epochs, stopped, best_fit, final_exact_fit and, for the
+        estimated fit, the bias-corrected trace (shifted so that its last
+        entry equals the final exact fit)."""
+        import numpy as np
+        ro = L.cpal_run_options(int(eta), int(pi), float(tol), int(max_epochs),
+                                1 if exact_fit else 0)
+        trace = (C.c_double * int(max_epochs))()
+        res = L.cpal_run_result()
+        _check(L.load().cp_arls_lev_run(self._ctx, C.byref(ro), trace, C.byref(res)), self._ctx)
+        tr = np.array(trace[:res.epochs])
+        out = dict(trace=tr, epochs=res.epochs, stopped=bool(res.stopped), best_fit=res.best_fit,
+                   final_exact_fit=res.final_exact_fit)
+        if not exact_fit and res.epochs > 0:
+            out["trace_bias_corrected"] = tr - (tr[-1] - res.final_exact_fit)
+        return out
+
     @property
     def step(self):
         t = C.c_uint64(0)
@@ -293,7 +321,8 @@ class CpArlsLevBatch:
 
     def __init__(self, tensors, tensor_of, factors, ranks, samples, taus=None, seeds=0,
                  stream_ids=0, gather_dtype="f32", fit_samples=0, fit_alpha=0.5,
-                 det_enum_cap=0, stream=None, use_graphs=False, allocator="torch"):
+                 det_enum_cap=0, stream=None, use_graphs=False, allocator="torch",
+                 sampling="leverage"):
         lib = L.load()
         n = len(tensor_of)
         per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * n
@@ -325,7 +354,7 @@ class CpArlsLevBatch:
         for i in range(n):
             opts[i] = L.cpal_options(int(ranks[i]), int(samples[i]), float(taus[i]), int(seeds[i]),
                                      int(stream_ids[i]), gdt, int(fit_samples), float(fit_alpha),
-                                     int(det_enum_cap))
+                                     int(det_enum_cap), L.SAMPLING[sampling], 0)
             arr = (C.c_void_p * len(self.factors[i]))(*[f.data_ptr() for f in self.factors[i]])
             self._keep.append(arr)
             fptrs[i] = C.cast(arr, C.c_void_p)

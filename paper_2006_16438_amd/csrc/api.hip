@@ -101,6 +101,11 @@ void fit_norm(const void *vals, int vdt, i64 nnz, double *part, DevState *st, hi
 void fit_eval(const FullModes &fm, int R, i64 n_nz, i64 n_fit, double phi_nz, double phi_z,
               const int *sc, i64 ld, const double *sx, double *part, const DevState *st,
               double *fit_out, hipStream_t s);
+size_t fit_exact_scratch_doubles(int R, i64 maxn);
+void launch_fit_exact(int D, const i64 *dims, double *const *A, int R, int k, int kind,
+                      const FiberSlot *slots, u64 nslots, const uint2 *pairs, const int *ik,
+                      const double *v64, const void *dX, i64 ldx, const DevState *st,
+                      double *scratch, double *fit_out, hipStream_t s);
 }  // namespace cpal
 
 using namespace cpal;
@@ -144,6 +149,7 @@ struct cpal_ctx {
   int R = 0;
   i64 s = 0;
   double tau = 1.0;
+  int sampling = CPAL_SAMPLE_LEVERAGE;   // probability of a factor row (App. B)
   u64 seed = 0, stream_id = 0;
   bool f64 = true;
   int zdt = CPAL_F64;    // gather precision (CPAL_F64, CPAL_F32, CPAL_BF16 for dense)
@@ -217,6 +223,8 @@ struct cpal_ctx {
   double *fit_x = nullptr;
   double *fit_part = nullptr;
   int fit_flags = 0;
+  double *fitx_scratch = nullptr;   // exact fit: block partials, Hadamard of Grams
+  double *fit_host_buf = nullptr;   // one device double the driver reads back
   // stage timing
   unsigned timing = 0;          // mask of timed stages
   std::vector<hipEvent_t> ev_pool;
@@ -330,6 +338,13 @@ OtherModes others_of(const cpal_ctx *c, int k) {
 // receives the statistics of the update of mode m that produced the factor.
 void refresh_leverage(cpal_ctx *c, int m, cpal_mode_stats *stats = nullptr) {
   Mode &md = c->mode[m];
+  if (c->sampling != CPAL_SAMPLE_LEVERAGE) {
+    launch_scores(md.A, md.n, c->R, c->sampling, c->lev_part, &c->st->score_norm[m],
+                  &c->st->lev_pinv[m], md.lev, md.w, c->lev_bsum, c->stream);
+    launch_lev_cdf(md.w, md.n, c->R, c->lev_bsum, md.C, md.q, nullptr, c->st, m, c->D, stats,
+                   c->stream);
+    return;
+  }
   const int *skip = nullptr;
   if (md.n < c->R) {
     // fewer rows than columns: all scores are 1 when A has full row rank
@@ -420,6 +435,8 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
   if (dense && opt->fit_samples != 0) return CPAL_E_ARG;   // the Sec. 6.4 sample is over nonzeros
   if (opt->det_enum_cap < 0 || opt->det_enum_cap > (1ll << 31)) return CPAL_E_ARG;
   if (opt->fit_samples < 0) return CPAL_E_ARG;
+  if (opt->sampling < CPAL_SAMPLE_LEVERAGE || opt->sampling > CPAL_SAMPLE_LENGTH_SQUARED)
+    return CPAL_E_ARG;
   if (alloc && (!alloc->alloc || !alloc->free)) return CPAL_E_ARG;
   long double fulld = 1;
   for (int m = 0; m < X->order; ++m) {
@@ -438,6 +455,7 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
   c->R = opt->rank;
   c->s = opt->samples;
   c->tau = opt->tau;
+  c->sampling = opt->sampling;
   c->seed = opt->seed;
   c->stream_id = opt->stream_id;
   c->f64 = opt->gather_dtype == CPAL_F64;
@@ -535,6 +553,8 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
       c->M = c->alloc<char>((size_t)mcap * c->ldz * tsz);   // rows padded to ldz
     }
     c->gram_tmp = c->alloc<double>(np);
+    c->fitx_scratch = c->alloc<double>(fit_exact_scratch_doubles(R, maxn));
+    c->fit_host_buf = c->alloc<double>(1);
     // gather stream length: at most nnz (sparse), s * max n_m (dense)
     c->chunk_first = c->alloc<unsigned>(gather_chunks_cap(dense ? s * maxn : c->nnz));
     if (dense) {   // sampled fibers per workgroup of the dense contraction: <= 256 partials
@@ -938,6 +958,78 @@ cpal_status cp_arls_lev_fit_estimate(cpal_ctx *c, double *fit_dev) {
   fit_eval(full_modes(c), c->R, c->fit_nz, c->fit_n, c->phi_nz, c->phi_z, c->fit_sc, c->fit_ld,
            c->fit_x, c->fit_part, c->st, fit_dev, c->stream);
   return check_hip(c, hipGetLastError(), "fit_estimate launch");
+}
+
+// The exact fit (eq. (6.1)) from the copy of the mode with the fewest rows.
+static void launch_exact_fit(cpal_ctx *c, double *fit_dev) {
+  int k = 0;
+  for (int m = 1; m < c->D; ++m)
+    if (c->dims[m] < c->dims[k]) k = m;
+  const Mode &md = c->mode[k];
+  double *A[CPAL_MAXORDER];
+  for (int m = 0; m < c->D; ++m) A[m] = c->mode[m].A;
+  const int kind = c->dense ? (c->zdt == CPAL_F64 ? 2 : c->zdt == CPAL_F32 ? 3 : 4)
+                            : (c->f64 ? 1 : 0);
+  launch_fit_exact(c->D, c->dims, A, c->R, k, kind, md.slots, md.nslots, md.pairs, md.ik, md.v64,
+                   md.dX, md.dld, c->st, c->fitx_scratch, fit_dev, c->stream);
+}
+
+cpal_status cp_arls_lev_fit_exact(cpal_ctx *c, double *fit_dev) {
+  if (!c || !fit_dev) return CPAL_E_ARG;
+  if (c->failed) return fail(c, CPAL_E_STATE, "context failed earlier");
+  launch_exact_fit(c, fit_dev);
+  return check_hip(c, hipGetLastError(), "fit_exact launch");
+}
+
+cpal_status cp_arls_lev_run(cpal_ctx *c, const cpal_run_options *ro, double *trace,
+                            cpal_run_result *res) {
+  if (!c || !ro || !trace || !res) return CPAL_E_ARG;
+  if (ro->eta < 1 || ro->pi < 1 || ro->max_epochs < 1 || !(ro->tol >= 0.0) ||
+      (ro->exact_fit != 0 && ro->exact_fit != 1))
+    return fail(c, CPAL_E_ARG, "run: invalid options");
+  if (c->failed) return fail(c, CPAL_E_STATE, "context failed earlier");
+  if (!ro->exact_fit && c->fit_n <= 0)
+    return fail(c, CPAL_E_STATE, "run: the estimated fit needs fit_samples > 0");
+  std::memset(res, 0, sizeof(*res));
+  double best = -INFINITY;
+  int fails = 0, e = 0;
+  for (; e < ro->max_epochs;) {
+    for (int it = 0; it < ro->eta; ++it)
+      for (int k = 0; k < c->D; ++k) {
+        const cpal_status st = cp_arls_lev_mode_update(c, k, nullptr);
+        if (st != CPAL_OK) return st;
+      }
+    if (ro->exact_fit) {
+      launch_exact_fit(c, c->fit_host_buf);
+    } else {
+      const cpal_status st = cp_arls_lev_fit_estimate(c, c->fit_host_buf);
+      if (st != CPAL_OK) return st;
+    }
+    double fit = 0.0;
+    hipMemcpyAsync(&fit, c->fit_host_buf, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    const cpal_status st = check_hip(c, hipStreamSynchronize(c->stream), "run: epoch fit");
+    if (st != CPAL_OK) return st;
+    trace[e++] = fit;
+    // an epoch improves when its fit beats the best earlier one by more than tol
+    if (fit > best + ro->tol) {
+      fails = 0;
+    } else {
+      ++fails;
+    }
+    if (fit > best) best = fit;
+    if (fails >= ro->pi) {
+      res->stopped = 1;
+      break;
+    }
+  }
+  res->epochs = e;
+  res->best_fit = best;
+  launch_exact_fit(c, c->fit_host_buf);
+  double fx = 0.0;
+  hipMemcpyAsync(&fx, c->fit_host_buf, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  const cpal_status st = check_hip(c, hipStreamSynchronize(c->stream), "run: final fit");
+  res->final_exact_fit = fx;
+  return st;
 }
 
 cpal_status cp_arls_lev_samples(const cpal_ctx *c, uint64_t *idx_dev, double *omega_dev,

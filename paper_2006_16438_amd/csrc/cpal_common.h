@@ -49,6 +49,7 @@ struct DevState {
   int lev_skip[CPAL_MAXORDER];  // leverage settled by the full-row-rank test
   double fit;
   double normX2;
+  double score_norm[CPAL_MAXORDER];   // total row score of a mode (other distributions)
 };
 
 // Symmetric R x R factorization: Cholesky, or eigen-decomposition when the
@@ -272,6 +273,8 @@ void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *le
 void launch_lev_cdf(const u64 *w, i64 n, int R, const u64 *blocksum, u64 *C, double *q,
                     int *flag_or, const DevState *st, int k, int D, cpal_mode_stats *stats,
                     hipStream_t s);
+void launch_scores(const double *A, i64 n, int R, int kind, double *part, double *norm,
+                   int *pinv_store, double *lev, u64 *w, u64 *blocksum, hipStream_t s);
 
 // radix sort of u64 keys with optional u32 payload, device-resident count --
 size_t sort_scratch_bytes(i64 cap, bool with_vals);

@@ -569,6 +569,73 @@ __global__ void __launch_bounds__(CDF_ROWS) k_lev_cdf(const u64 *__restrict__ w,
 
 int lev_rows_per_block(int R) { return 256 / (R <= 16 ? 16 : (R <= 32 ? 32 : 64)); }
 
+// Row scores of the other sampling distributions compared in App. B (the
+// probability of a KRP row is again the product of per-mode probabilities):
+// kind 1 uniform (score 1, total n), kind 2 length squared (score
+// ||A(i,:)||^2 summed over columns in ascending order, total = the trace of
+// the Gram matrix summed in the canonical blocked order: block partials in
+// ascending blocks, then the diagonal in ascending column order).
+__global__ void __launch_bounds__(64) k_score_norm(const double *__restrict__ part, int nblk,
+                                                  int R, i64 n, int kind, double *norm,
+                                                  int *pinv_store) {
+  if (threadIdx.x != 0) return;
+  double S = (double)n;
+  if (kind == 2) {
+    const int np = R * (R + 1) / 2;
+    S = 0.0;
+    int p = 0;
+    for (int j = 0; j < R; ++j) {   // pair index of (j, j) in the upper triangle
+      double g = 0.0;
+      for (int b = 0; b < nblk; ++b) g = g + part[(i64)b * np + p];
+      S = S + g;
+      p += R - j;
+    }
+  }
+  *norm = S;
+  if (pinv_store) *pinv_store = 0;
+}
+
+__global__ void __launch_bounds__(256) k_score_rows(const double *__restrict__ A, i64 n, int R,
+                                                  int kind, const double *__restrict__ norm,
+                                                  int rb, double *__restrict__ lev,
+                                                  u64 *__restrict__ w,
+                                                  u64 *__restrict__ blocksum) {
+  const i64 i = (i64)blockIdx.x * 256 + threadIdx.x;
+  u64 wi = 0;
+  if (i < n) {
+    double sc = 1.0;
+    if (kind == 2) {
+      sc = 0.0;
+      for (int c = 0; c < R; ++c) {
+        const double a = A[i * R + c];
+        sc = sc + a * a;
+      }
+    }
+    lev[i] = sc;
+    const double S = *norm;
+    double v = S > 0.0 ? sc / S : 0.0;
+    if (!(v > 0.0)) v = 0.0;
+    if (v > 1.0) v = 1.0;
+    wi = (u64)(v * 0x1p52);
+    w[i] = wi;
+  }
+  // sums over groups of rb consecutive rows (rb divides 64)
+  u64 g = wi;
+  for (int off = 1; off < rb; off <<= 1) g += __shfl_xor(g, off, 64);
+  if (i < n && (i % rb) == 0) blocksum[i / rb] = g;
+}
+
+void launch_scores(const double *A, i64 n, int R, int kind, double *part, double *norm,
+                   int *pinv_store, double *lev, u64 *w, u64 *blocksum, hipStream_t s) {
+  const int nblk = (int)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
+  if (kind == 2) launch_lev_gram_partial(A, n, R, part, nullptr, s);
+  hipLaunchKernelGGL(k_score_norm, dim3(1), dim3(64), 0, s, part, nblk, R, n, kind, norm,
+                     pinv_store);
+  const int rb = lev_rows_per_block(R);
+  hipLaunchKernelGGL(k_score_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, n, R,
+                     kind, norm, rb, lev, w, blocksum);
+}
+
 void launch_lev_gram_partial(const double *A, i64 n, int R, double *part, const int *skip,
                              hipStream_t s) {
   const int nblk = (int)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);

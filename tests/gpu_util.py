@@ -30,7 +30,8 @@ def dense_values(T):
 
 
 def make_ctx(T, fac, R, s, tau=None, gather="f64", seed=0, stream_id=0, det_cap=0,
-             fit_samples=0, values_f32=False, dense=False, dense_values_gpu=None):
+             fit_samples=0, values_f32=False, dense=False, dense_values_gpu=None,
+             sampling="leverage"):
     """dense_values_gpu: a dense CUDA tensor of shape T.dims handed over as is."""
     from paper_2006_16438_amd.api import CpArlsLev
     dev = torch.device("cuda:0")
@@ -47,7 +48,8 @@ def make_ctx(T, fac, R, s, tau=None, gather="f64", seed=0, stream_id=0, det_cap=
         vals = vals.float()
     F = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float64).copy()).to(dev) for f in fac]
     ctx = CpArlsLev(T.dims, coords, vals, F, R, s, tau=tau, seed=seed, stream_id=stream_id,
-                    gather_dtype=gather, det_enum_cap=det_cap, fit_samples=fit_samples)
+                    gather_dtype=gather, det_enum_cap=det_cap, fit_samples=fit_samples,
+                    sampling=sampling)
     return ctx, F
 
 
@@ -111,13 +113,18 @@ def derived_tolerance(OT, fac, k, ref, gather):
       ||dA||_F / ||A||_F <= kappa(G_s) (||dM||_F/||M||_F + ||dG||_F/||G||_2),
     kappa over the nonzero spectrum (the pseudo-inverse when G_s is singular)."""
     sy = sampled_system(OT, fac, k, ref["idx"], ref["omega"])
+    return bound_from_system(sy, len(ref["idx"]), gather)
+
+
+def bound_from_system(sy, n_g, gather):
+    """The bound of derived_tolerance from an explicit sampled system (keys
+    G, Ga, M, Ma, n_terms as made by sampled_system) with n_g sampled rows."""
     ev = np.linalg.eigvalsh(sy["G"])
     top = ev.max() if ev.size else 0.0
     keep = ev > top * sy["G"].shape[0] * 2.0 ** -52
     if not np.any(keep):
         return np.inf
     kappa = ev[keep].max() / ev[keep].min()
-    n_g = len(ref["idx"])
     eps_m = _U_IN[gather] + sy["n_terms"] * _U_ACC[gather]
     mnorm = np.linalg.norm(sy["M"])
     rel_m = eps_m * np.linalg.norm(sy["Ma"]) / mnorm if mnorm > 0 else 0.0
@@ -132,14 +139,15 @@ def fro_rel_err(a, b):
 
 def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, stream_id=0,
                det_cap=0, OT=None, check_lev=True, label="", dense=False, gather_config=None,
-               autotune=False):
+               autotune=False, sampling="leverage"):
     """Returns the list of (oracle stats, device stats) per update.  dense:
     hand the (fully stored) tensor to the library as a dense array; the
     oracle keeps the equivalent COO form with every entry.  gather_config:
     (grid, sort_min) set for every mode; autotune: run the autotuner first
     and check that it left factors, leverage and step as they were."""
     OT = OT or oracle.Tensor.from_synth(T)
-    ctx, F = make_ctx(T, fac, R, s, tau, gather, seed, stream_id, det_cap, dense=dense)
+    ctx, F = make_ctx(T, fac, R, s, tau, gather, seed, stream_id, det_cap, dense=dense,
+                      sampling=sampling)
     D = len(T.dims)
     if gather_config is not None:
         for m in range(D):
@@ -163,12 +171,16 @@ def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, str
         inputs = [h.copy() for h in host]   # the update's input factors
         if check_lev:
             for m in range(D):
-                ref_lev, _ = oracle.leverage(host[m])
+                if sampling == "leverage":
+                    ref_lev, _ = oracle.leverage(host[m])
+                else:
+                    ref_lev, _ = oracle.scores(host[m], sampling)
                 got = ctx.leverage(m).cpu().numpy()
                 assert np.array_equal(got, ref_lev), f"{label} update {u}: leverage of mode {m} differs"
         t = ctx.step
         try:
-            ref = oracle.mode_update(OT, host, k, t, R, s, tau, seed, stream_id, cap)
+            ref = oracle.mode_update(OT, host, k, t, R, s, tau, seed, stream_id, cap,
+                                     sampling=sampling)
         except RuntimeError:
             # an all-zero probability vector: the oracle rejects the update; the
             # device flags it and leaves the factor unchanged

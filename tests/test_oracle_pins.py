@@ -606,3 +606,148 @@ def test_fit_estimate_zero_stratum_weight_uses_the_zeros_drawn():
     F = sum(M[tuple(full[:, e])] ** 2 for e in missing)
     fhat = ((1 - fs.estimate(fac)) * OT.norm) ** 2
     assert abs(fhat / F - 1) < 0.1, (fhat, F)
+
+
+# ------------------------------------------------------------- Alg. 3 loop --
+def _first_stop(trace, pi, tol):
+    """Epoch count at which 'pi consecutive epochs without beating the best
+    earlier fit by more than tol' first holds (None if it never does)."""
+    best, fails = -np.inf, 0
+    for e, f in enumerate(trace):
+        fails = 0 if f > best + tol else fails + 1
+        best = max(best, f)
+        if fails >= pi:
+            return e + 1
+    return None
+
+
+@pytest.mark.parametrize("fit", ["exact", "estimated"])
+def test_full_loop_stops_by_the_epoch_rule_at_the_noise_floor(fit):
+    """Alg. 3 with epochs (eta = 5), pi = 3 and tol = 1e-4 on a fully stored
+    planted rank-3 tensor with 1% noise: the run ends at the first epoch
+    where the stopping rule holds for its recorded trace, it ends because of
+    the rule (not the epoch limit), the final factors reach the fit of the
+    planted model (1 - ||E||/||X||, up to what the sampled solves leave), and
+    the trace's exact fits equal a dense numpy evaluation of ||X - M||."""
+    dims = (30, 25, 20)
+    R = 3
+    T, planted = synth.planted(dims, R, seed=13, rel_noise=0.01)
+    OT = oracle.Tensor.from_synth(T)
+    X = np.zeros(dims)
+    X[tuple(T.coords)] = T.values
+    floor = 1 - np.linalg.norm(X - np.einsum("ir,jr,kr->ijk", *planted)) / np.linalg.norm(X)
+    fs = oracle.FitSample(OT, 4096, 1.0, seed=3) if fit == "estimated" else None
+    best_run = None
+    for restart in range(4):
+        f = synth.gaussian_factors(dims, R, 100 + restart)
+        out = oracle.cp_arls_lev_run(OT, f, R, 512, eta=5, pi=3, tol=1e-4, max_epochs=60,
+                                     seed=restart, fit_sample=fs)
+        assert out["stopped"]
+        assert _first_stop(out["trace"], 3, 1e-4) == out["epochs"]
+        M = np.einsum("ir,jr,kr->ijk", *f)
+        dense = 1 - np.linalg.norm(X - M) / np.linalg.norm(X)
+        assert abs(out["final_exact_fit"] - dense) < 1e-10
+        if fit == "exact":
+            assert abs(out["trace"][-1] - dense) < 1e-10
+        if best_run is None or out["final_exact_fit"] > best_run["final_exact_fit"]:
+            best_run = out
+    assert best_run["final_exact_fit"] > floor - 2e-3, (best_run["final_exact_fit"], floor)
+
+
+def test_epoch_rule_counts_consecutive_failures_against_the_best_fit():
+    """The rule on hand-made traces: improvements smaller than tol count as
+    failures, a later improvement resets the count, and the reference is the
+    best earlier fit (a dip and recovery to below best + tol is a failure)."""
+    assert _first_stop([0.5, 0.50005, 0.5001, 0.50015], 3, 1e-4) == 4
+    assert _first_stop([0.5, 0.50005, 0.5002, 0.50021, 0.50022, 0.50023], 3, 1e-4) == 6
+    assert _first_stop([0.5, 0.4, 0.6, 0.59, 0.6, 0.6], 3, 1e-4) == 6
+    assert _first_stop([0.1, 0.2, 0.3], 1, 1e-4) is None
+
+
+# ------------------------------------------- sampling distributions of App. B --
+def test_length_squared_probabilities_are_normalised_row_norms():
+    """App. B: length-squared sampling takes row i of A with probability
+    ||A(i,:)||^2 / ||A||_F^2; the integer weights reproduce it to the
+    2^-52 resolution of the CDF."""
+    rng = np.random.default_rng(41)
+    A = rng.standard_normal((300, 7)) * rng.uniform(0.1, 3.0, size=(300, 1))
+    sc, S = oracle.scores(A, "length_squared")
+    ref = np.sum(A * A, axis=1)
+    assert np.allclose(sc, ref, rtol=1e-14)
+    assert math.isclose(S, np.sum(A * A), rel_tol=1e-13)
+    _, Cdf, q, W = oracle.sampling_vectors_norm(sc, S)
+    assert np.all(np.abs(q - ref / np.sum(ref)) <= (A.shape[0] + 2) * 2.0 ** -52)
+    assert int(Cdf[-1]) == W
+
+
+def test_uniform_probabilities_are_equal():
+    A = np.random.default_rng(42).standard_normal((37, 4))
+    sc, S = oracle.scores(A, "uniform")
+    assert np.all(sc == 1.0) and S == 37.0
+    w, _, q, _ = oracle.sampling_vectors_norm(sc, S)
+    assert np.all(w == w[0]) and np.all(q == q[0]) and abs(q[0] - 1 / 37) < 1e-16
+
+
+def test_length_squared_krp_row_bound():
+    """App. B: ||Z(i,:)||^2 <= prod_k ||A_k(i_k,:)||^2 for the rows of the
+    KRP (brute force over every row of a small KRP)."""
+    rng = np.random.default_rng(43)
+    fac = [rng.standard_normal((n, 5)) for n in (6, 7, 5)]
+    Z = krp_rows(fac, [0, 1, 2])
+    zn = np.sum(Z * Z, axis=1)
+    bound = (np.sum(fac[2] ** 2, 1)[:, None, None] * np.sum(fac[1] ** 2, 1)[None, :, None]
+             * np.sum(fac[0] ** 2, 1)[None, None, :]).reshape(-1)
+    assert np.all(zn <= bound * (1 + 1e-13))
+
+
+@pytest.mark.parametrize("kind", ["uniform", "length_squared"])
+def test_other_distributions_draw_the_product_probabilities(kind):
+    """The per-mode draws of Alg. 2 with App. B's row probabilities give KRP
+    row i with probability prod q (chi-square over 2e5 draws, N = 24)."""
+    dims = (5, 4, 6)
+    R = 2
+    rng = np.random.default_rng(31)
+    fac = [rng.standard_normal((n, R)) for n in dims]
+    T = synth.random_sparse(dims, 40, seed=2)
+    OT = oracle.Tensor.from_synth(T)
+    s = 200_000
+    out = oracle.mode_update(OT, [f.copy() for f in fac], 0, 7, R, s, tau=1.0, sampling=kind)
+    raw = out["raw"].astype(np.int64)
+    qs = []
+    for A in fac:
+        sc = np.sum(A * A, axis=1) if kind == "length_squared" else np.ones(A.shape[0])
+        qs.append(sc / sc.sum())
+    p = (qs[2][:, None] * qs[1][None, :]).reshape(-1)
+    counts = np.bincount(raw, minlength=p.size)
+    chi2 = ((counts - s * p) ** 2 / (s * p)).sum()
+    assert stats.chi2.sf(chi2, p.size - 1) > 1e-6
+
+
+@pytest.mark.parametrize("kind", ["uniform", "length_squared"])
+def test_other_distributions_solve_the_sketched_problem(kind):
+    """Only the probability vector changes: the update is still the
+    least-squares solution of the explicit sketched problem (1.2) with the
+    returned rows and weights, and the weights follow Sec. 4.3 with the
+    distribution's probabilities."""
+    dims = (12, 10, 8)
+    R = 4
+    T = synth.random_sparse(dims, 60, seed=9)
+    OT = oracle.Tensor.from_synth(T)
+    fac = concentrated_factors(dims, R, 47)
+    for k in range(3):
+        f2 = [f.copy() for f in fac]
+        out = oracle.mode_update(OT, f2, k, 11 + k, R, 96, sampling=kind)
+        ref = _sketched_minimum_norm(dims, T, fac, k, out)
+        err = np.max(np.abs(f2[k] - ref)) / np.max(np.abs(ref))
+        assert err < 1e-9
+        others = [m for m in range(3) if m != k]
+        qk = {}
+        for m in others:
+            sc = np.sum(fac[m] ** 2, 1) if kind == "length_squared" else np.ones(dims[m])
+            qk[m] = sc / sc.sum()
+        lin = out["idx"].astype(np.int64)
+        st = out["stats"]
+        p = qk[others[0]][lin % dims[others[0]]] * qk[others[1]][lin // dims[others[0]]]
+        rnd = slice(st["s_det"], None)
+        assert np.all(p[:st["s_det"]] > 1 / 96) and np.all(p[rnd] <= 1 / 96 * (1 + 1e-12))
+        assert abs(np.sum(out["omega"][rnd] * p[rnd]) - (1 - st["p_det"])) < 1e-9
