@@ -27,6 +27,11 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz, void *M,
                        int grid, int sort_min, hipStream_t s);
 void launch_zero_words(void *p, i64 nwords, hipStream_t s);
+int gather_own_blocks(bool f64, int ldz, i64 nk);
+void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
+                       const unsigned *coff, const unsigned *cidx, const uint2 *pairs,
+                       const int *ik, const double *v64, i64 nk, const void *zhat, int ldz,
+                       void *M, unsigned *bnd, hipStream_t s);
 size_t gather_bkt_count_words();
 void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                        const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
@@ -48,6 +53,7 @@ void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u6
                  hipStream_t s);
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
                     const unsigned short *bpos, u64 *keys, DrawEntry *tab, u64 tmask, int tshift,
+                    bool det_rep,
                     hipStream_t s);
 void launch_draw_table_clear(DrawEntry *tab, u64 n, hipStream_t s);
 void launch_samples_out(DevState *st, const u64 *samp_idx, const double *samp_om,
@@ -210,6 +216,9 @@ struct cpal_ctx {
   u64 *bk_off = nullptr;
   void *bk_scan = nullptr;
   uint4 *bk_ent = nullptr;
+  // owner gather (allocated at init for FP64 contexts, else when a mode
+  // first uses it): per nonempty sampled fiber, its segment bounds per row block
+  unsigned *own_bnd = nullptr;
   u64 *cpos = nullptr;              // nonempty fibers: stream position,
   unsigned *coff = nullptr;         //   offset in the mode-sorted nonzeros,
   unsigned *cidx = nullptr;         //   sampled row
@@ -292,6 +301,9 @@ cpal_status fail(cpal_ctx *c, cpal_status code, const char *msg) {
   if (c) c->err = msg;
   return code;
 }
+
+cpal_status owner_defaults(cpal_ctx *c);
+bool uses_owner(const cpal_ctx *c, int k, int sort_min);
 
 FullModes full_modes(const cpal_ctx *c) {
   FullModes fm;
@@ -718,6 +730,14 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
         return CPAL_E_STATE;
       }
     }
+    if (c->f64 && !dense) {   // FP64 gathers default to the owner gather
+      const cpal_status st = owner_defaults(c);
+      if (st != CPAL_OK) {
+        c->release();
+        delete c;
+        return st;
+      }
+    }
   } catch (cpal_status st) {
     c->release();
     delete c;
@@ -762,7 +782,7 @@ void update_front(cpal_ctx *c, int k) {
   launch_draw(om, c->st, c->seed, c->stream_id, c->dbuf, c->dpos, c->chunk_cnt,
               c->draw_grid, c->draw_more_grid, s);
   launch_compact(c->st, c->dbuf, c->chunk_cnt, c->dpos, c->keys, c->dtab, c->dtab_n - 1,
-                 c->dtab_shift, s);
+                 c->dtab_shift, c->f64, s);
   c->last_key_bits = md.key_bits;
   c->stage_end(CPAL_STAGE_SAMPLE, tb);
   tb = c->stage_begin(CPAL_STAGE_ROWS);
@@ -770,7 +790,8 @@ void update_front(cpal_ctx *c, int k) {
   launch_rows(c->zdt, om, c->st, R, c->s, c->samp_idx, c->samp_om, c->samp_w, c->keys, c->dtab,
               c->dtab_n - 1, c->dtab_shift, c->tpos, c->dense ? nullptr : md.slots,
               md.nslots - 1, md.hshift, (unsigned)md.n, c->zhat, c->foff, c->flen, c->gpart,
-              c->gp_len, c->gp_cnt, c->gp_act, c->M, c->dense ? 0 : ncopies * md.n * c->ldz,
+              c->gp_len, c->gp_cnt, c->gp_act, c->M,
+              (c->dense || uses_owner(c, k, md.g_sort_min)) ? 0 : ncopies * md.n * c->ldz,
               c->ldz, s);
   launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
                      c->coff, c->cidx, c->chunk_first, c->tpos, c->dtab, s);
@@ -796,6 +817,40 @@ bool bucket_capable(const cpal_ctx *c, int k) {
   return !c->dense && !c->f64 && c->mode[k].n <= (1 << 20);
 }
 
+// The owner gather writes every row of the CPAL_MCOPIES copies of M (sparse
+// modes of at most 2^20 rows).
+bool owner_capable(const cpal_ctx *c, int k) {
+  return !c->dense && c->mode[k].n <= (1 << 20);
+}
+
+cpal_status ensure_owner_buffers(cpal_ctx *c) {
+  if (c->own_bnd) return CPAL_OK;
+  i64 nbmax = 0;
+  for (int m = 0; m < c->D; ++m)
+    if (owner_capable(c, m))
+      nbmax = std::max<i64>(nbmax, gather_own_blocks(c->f64, c->ldz, c->mode[m].n));
+  try {
+    c->own_bnd = c->alloc<unsigned>((size_t)c->s * (size_t)(nbmax + 1));
+  } catch (cpal_status st) {
+    return st;
+  }
+  return CPAL_OK;
+}
+
+// Every sparse mode of at most 2^20 rows runs the owner gather.
+cpal_status owner_defaults(cpal_ctx *c) {
+  const cpal_status st = ensure_owner_buffers(c);
+  if (st != CPAL_OK) return st;
+  for (int m = 0; m < c->D; ++m)
+    if (owner_capable(c, m)) c->mode[m].g_sort_min = -2;
+  return CPAL_OK;
+}
+
+// The gather a mode update of mode k runs with sort threshold sort_min.
+bool uses_owner(const cpal_ctx *c, int k, int sort_min) {
+  return sort_min == -2 && c->own_bnd && owner_capable(c, k);
+}
+
 // TnsrSamp + sampled MTTKRP (Sec. 6.3, eq. (1.2)) into M.  sort_min < 0
 // selects the bucketed gather (bucket_capable modes).
 void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
@@ -808,7 +863,10 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
     launch_dense_mttkrp(c->zdt, c->st, md.n, R, c->ldz, md.dld, c->cidx, c->samp_idx, md.dX,
                         c->zhat, c->dpart, kc, (int)((c->s + kc - 1) / kc), c->M, s);
   }
-  else if (sort_min < 0 && c->bk_ent && bucket_capable(c, k))
+  else if (uses_owner(c, k, sort_min))
+    launch_gather_own(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, md.n,
+                      c->zhat, c->ldz, c->M, c->own_bnd, s);
+  else if (sort_min == -1 && c->bk_ent && bucket_capable(c, k))
     launch_gather_bkt(c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs, md.n,
                       c->nnz, (const float *)c->zhat, c->ldz, (float *)c->M, grid, c->bk_cnt,
                       c->bk_off, c->bk_scan, c->bk_ent, s);
@@ -861,13 +919,18 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
 }
 
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *c, int32_t k, int32_t grid, int32_t sort_min) {
-  if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < -1)
+  if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < -2)
     return CPAL_E_ARG;
   if (c->dense && grid > c->dnch) return CPAL_E_ARG;
-  if (sort_min < 0) {   // the bucketed gather
+  if (sort_min == -1) {   // the bucketed gather
     if (!bucket_capable(c, k)) return CPAL_E_ARG;
     const cpal_status st = ensure_bucket_buffers(c);
     if (st != CPAL_OK) return fail(c, st, "bucketed gather: buffers");
+  }
+  if (sort_min == -2) {   // the owner gather
+    if (!owner_capable(c, k)) return CPAL_E_ARG;
+    const cpal_status st = ensure_owner_buffers(c);
+    if (st != CPAL_OK) return fail(c, st, "owner gather: buffers");
   }
   c->mode[k].g_grid = grid;
   c->mode[k].g_sort_min = sort_min;
@@ -913,15 +976,21 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
     const int dense_grids[] = {c->dnch, std::max(1, c->dnch / 2), std::max(1, c->dnch / 4),
                                std::max(1, c->dnch / 8)};
     const i64 mwords = c->dense ? 0 : (i64)m_copies(md.n) * md.n * c->ldz * (c->f64 ? 2 : 1);
+    // FP64 gathers keep the owner gather: its sums do not depend on timing,
+    // so FP64 updates stay bit-reproducible
+    if (c->f64 && uses_owner(c, k, md.g_sort_min)) continue;
     float best = 1e30f;
     int best_grid = 0, best_sort = 0;
-    // the bucketed gather (sort threshold -1) when its buffers can be had
+    // the bucketed gather (sort threshold -1) when its buffers can be had,
+    // and the owner gather (-2, one launch shape: its grid follows n_k)
     const bool bkt = bucket_capable(c, k) && ensure_bucket_buffers(c) == CPAL_OK;
+    const bool own = owner_capable(c, k) && ensure_owner_buffers(c) == CPAL_OK;
     const int ng = 4, ns = seg ? (bkt ? 5 : 4) : 1;
-    for (int gi = 0; gi < ng && res == CPAL_OK; ++gi)
-      for (int si = 0; si < ns && res == CPAL_OK; ++si) {
-        const int grid = c->dense ? dense_grids[gi] : seg ? seg_grids[gi] : flat_grids[gi];
-        const int smin = !seg ? 0 : si < 4 ? seg_sort[si] : -1;
+    for (int gi = 0; gi < ng + (own ? 1 : 0) && res == CPAL_OK; ++gi)
+      for (int si = 0; si < (gi < ng ? ns : 1) && res == CPAL_OK; ++si) {
+        const int grid = gi == ng ? 0
+                       : c->dense ? dense_grids[gi] : seg ? seg_grids[gi] : flat_grids[gi];
+        const int smin = gi == ng ? -2 : !seg ? 0 : si < 4 ? seg_sort[si] : -1;
         float tmin = 1e30f;
         for (int r = 0; r < reps; ++r) {
           launch_zero_words(c->M, mwords, c->stream);
@@ -1324,12 +1393,17 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
     } else {
       // a restart takes the tuned shapes; the bucketed gather needs its own
       // buffers, and where they cannot be had the restart keeps the default
-      bool need_bkt = false;
-      for (int k = 0; k < c->D; ++k) need_bkt |= b->ctx[src]->mode[k].g_sort_min < 0;
+      bool need_bkt = false, need_own = false;
+      for (int k = 0; k < c->D; ++k) {
+        need_bkt |= b->ctx[src]->mode[k].g_sort_min == -1;
+        need_own |= b->ctx[src]->mode[k].g_sort_min == -2;
+      }
       const bool bkt_ok = need_bkt && ensure_bucket_buffers(c) == CPAL_OK;
+      const bool own_ok = need_own && ensure_owner_buffers(c) == CPAL_OK;
       for (int k = 0; k < c->D; ++k) {
         const int sm = b->ctx[src]->mode[k].g_sort_min;
-        if (sm < 0 && !(bkt_ok && bucket_capable(c, k))) {
+        if ((sm == -1 && !(bkt_ok && bucket_capable(c, k))) ||
+            (sm == -2 && !(own_ok && owner_capable(c, k)))) {
           c->mode[k].g_grid = 0;
           c->mode[k].g_sort_min = 0;
         } else {

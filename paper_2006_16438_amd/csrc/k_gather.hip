@@ -232,10 +232,10 @@ __device__ __forceinline__ unsigned *seg_load_sort(
 // columns c, c + LPN, ..., c + (CPL-1) LPN of the row (LPN * CPL = the
 // padded row width): with CPL = 2 a wave instruction serves four entries,
 // halving the per-entry bookkeeping.
-template <typename T, int LPN, int CPL, typename Get>
+template <typename T, int LPN, int CPL, typename Get, typename Add>
 __device__ __forceinline__ void seg_reduce(const Get &get, int n, int R,
                                            const T *__restrict__ zhat, int ldz,
-                                           T *__restrict__ M, int *srow,
+                                           const Add &add, int *srow,
                                            T (*svec)[LPN * CPL]) {
   constexpr int NG = GT_THREADS / LPN;
   constexpr int PER = GT_CHUNK / NG;
@@ -276,7 +276,7 @@ __device__ __forceinline__ void seg_reduce(const Get &get, int n, int R,
             } else {
 #pragma unroll
               for (int j = 0; j < CPL; ++j)
-                if (c + j * LPN < R) unsafeAtomicAdd(&M[(i64)cur * ldz + c + j * LPN], acc[j]);
+                if (c + j * LPN < R) add(cur, c + j * LPN, acc[j]);
             }
             cur = r;
 #pragma unroll
@@ -314,7 +314,7 @@ __device__ __forceinline__ void seg_reduce(const Get &get, int n, int R,
         if (mr >= 0) {
 #pragma unroll
           for (int j = 0; j < CPL; ++j)
-            if (c + j * LPN < R) unsafeAtomicAdd(&M[(i64)mr * ldz + c + j * LPN], ma[j]);
+            if (c + j * LPN < R) add(mr, c + j * LPN, ma[j]);
         }
         mr = r;
 #pragma unroll
@@ -326,10 +326,29 @@ __device__ __forceinline__ void seg_reduce(const Get &get, int n, int R,
     if (mr >= 0) {
 #pragma unroll
       for (int j = 0; j < CPL; ++j)
-        if (c + j * LPN < R) unsafeAtomicAdd(&M[(i64)mr * ldz + c + j * LPN], ma[j]);
+        if (c + j * LPN < R) add(mr, c + j * LPN, ma[j]);
     }
   }
 }
+
+// Where a reduced run of row r goes: an atomic add into a copy of M in
+// global memory, or a plain add into a row block in shared memory that only
+// this workgroup touches (rows relative to the block; each row is added once
+// per batch, so the adds of one batch never collide).
+template <typename T>
+struct GlobalAdd {
+  T *M;
+  int ldz;
+  __device__ __forceinline__ void operator()(int r, int c, T v) const {
+    unsafeAtomicAdd(&M[(i64)r * ldz + c], v);
+  }
+};
+template <typename T>
+struct LdsAdd {
+  T *blk;
+  int ld;
+  __device__ __forceinline__ void operator()(int r, int c, T v) const { blk[r * ld + c] += v; }
+};
 
 template <typename T>
 struct LdsEntries {
@@ -369,7 +388,8 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
     const unsigned *keys = seg_load_sort<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz,
                                             ikbits, sort_min, win, ka, kb, lx, lz, tab);
     const int nvalid = (int)(min(total, (ch + 1) * GT_CHUNK) - ch * GT_CHUNK);
-    seg_reduce<T, LPN, CPL>(LdsEntries<T>{keys, lx, lz}, nvalid, R, zhat, ldz, Mx, srow, svec);
+    seg_reduce<T, LPN, CPL>(LdsEntries<T>{keys, lx, lz}, nvalid, R, zhat, ldz,
+                            GlobalAdd<T>{Mx, ldz}, srow, svec);
   }
 }
 
@@ -499,8 +519,199 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
     __syncthreads();
     const unsigned *keys = chunk_radix(ka, kb, tab, sortbits);
     const int nvalid = (int)(last - base + 1);
-    seg_reduce<float, LPN, CPL>(LdsEntries<float>{keys, lx, lz}, nvalid, R, zhat, ldz, Mx, srow,
-                                svec);
+    seg_reduce<float, LPN, CPL>(LdsEntries<float>{keys, lx, lz}, nvalid, R, zhat, ldz,
+                                GlobalAdd<float>{Mx, ldz}, srow, svec);
+  }
+}
+
+// ------------------------------------------------------------ owner gather --
+// Owner-computes form of the same sum, with no atomic operation anywhere:
+// the rows of M are cut into blocks of 2^rshift rows and the nonempty
+// sampled fibers into OWN_PARTS parts; workgroup (b, p) alone forms rows
+// [b 2^rshift, (b+1) 2^rshift) of copy p of M from the fibers of part p,
+// accumulating them in shared memory and storing each row once (plain
+// stores, every row of every copy, so M needs no clearing).  The solve adds
+// the copies in a fixed order.  A fiber's nonzeros are sorted by row, so
+// its nonzeros in row block b are one contiguous segment; k_own_bounds
+// records the segment boundaries of every fiber, bnd[f (nb + 1) + b] =
+// number of nonzeros of fiber f with row < b 2^rshift.  Within a workgroup
+// the segments of its fibers are taken in fiber order in batches of
+// GT_CHUNK nonzeros, each batch is sorted by row (stable) and reduced in
+// registers, and each row of the batch is added to the shared block once.
+// The order of every sum therefore depends only on the sample and the
+// launch shape, not on timing: an update in FP64 is bit-reproducible.
+#define OWN_PARTS CPAL_MCOPIES
+
+template <typename T>
+struct RowLoad;
+template <>
+struct RowLoad<float> {
+  const uint2 *pairs;
+  __device__ __forceinline__ unsigned operator()(u64 e) const { return pairs[e].x; }
+};
+template <>
+struct RowLoad<double> {
+  const int *ik;
+  __device__ __forceinline__ unsigned operator()(u64 e) const { return (unsigned)ik[e]; }
+};
+
+// One wave per nonempty fiber f: lane e of a 64-entry step writes
+// bnd[f][b] = e for every block b after its predecessor's block up to its
+// own; the blocks after the last nonzero get the fiber length.  Each entry
+// of the fiber's row is written exactly once.
+template <typename T>
+__global__ void __launch_bounds__(256) k_own_bounds(const DevState *st,
+                                                    const u64 *__restrict__ cpos,
+                                                    const unsigned *__restrict__ coff,
+                                                    RowLoad<T> rows, int rshift, int nb,
+                                                    unsigned *__restrict__ bnd) {
+  const i64 nf = st->n_fib;
+  const u64 total = (u64)st->gathered;
+  const int lane = threadIdx.x & 63;
+  const i64 nw = ((i64)gridDim.x * blockDim.x) >> 6;
+  for (i64 f = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6; f < nf; f += nw) {
+    const u64 p0 = cpos[f];
+    const unsigned len = (unsigned)((f + 1 < nf ? cpos[f + 1] : total) - p0);
+    const u64 base = coff[f];
+    unsigned *tb = bnd + (u64)f * (u64)(nb + 1);
+    int carry = -1;   // block of the previous nonzero of the fiber
+    for (unsigned e0 = 0; e0 < len; e0 += 64) {
+      const unsigned e = e0 + (unsigned)lane;
+      const bool valid = e < len;
+      const int bu = valid ? (int)(rows(base + e) >> rshift) : nb;
+      int bp = __shfl_up(bu, 1, 64);
+      if (lane == 0) bp = carry;
+      if (valid)
+        for (int bb = bp + 1; bb <= bu; ++bb) tb[bb] = e;
+      carry = __shfl(bu, (int)min(63u, len - 1 - e0), 64);
+    }
+    for (int bb = carry + 1 + lane; bb <= nb; bb += 64) tb[bb] = len;
+  }
+}
+
+template <typename T, int LPN, int CPL>
+__global__ void __launch_bounds__(GT_THREADS, 2) k_gather_own(
+    const DevState *st, int R, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ bnd, int nb, int rshift,
+    NzLoad<T> nz, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+  constexpr int NG = GT_THREADS / LPN;
+  constexpr int LDB = LPN * CPL + 1;   // shared row stride (odd: rows spread over banks)
+  extern __shared__ char own_smem[];
+  T *blk = (T *)own_smem;              // (1 << rshift) x LDB
+  __shared__ unsigned ka[GT_CHUNK], kb[GT_CHUNK];
+  __shared__ T lx[GT_CHUNK];
+  __shared__ unsigned lz[GT_CHUNK];
+  __shared__ unsigned tab[64 * GT_PER_THREAD * (GT_THREADS / 64)];
+  __shared__ int srow[2 * NG];
+  __shared__ T svec[2 * NG][LPN * CPL];
+  __shared__ unsigned gst[GT_THREADS], gend[GT_THREADS], gz[GT_THREADS];
+  __shared__ u64 gbase[GT_THREADS];
+  const int tid = threadIdx.x;
+  const int p = (int)(blockIdx.x % OWN_PARTS), b = (int)(blockIdx.x / OWN_PARTS);
+  const int rb = 1 << rshift;
+  const i64 r0 = (i64)b << rshift;
+  const i64 nf = st->n_fib;
+  const i64 f0 = nf * p / OWN_PARTS, f1 = nf * (p + 1) / OWN_PARTS;
+  for (int e = tid; e < rb * LDB; e += GT_THREADS) blk[e] = T(0);
+  for (i64 g0 = f0; g0 < f1; g0 += GT_THREADS) {
+    const i64 f = g0 + tid;
+    unsigned lo = 0, len = 0;
+    if (f < f1) {
+      const unsigned *tb = bnd + (u64)f * (u64)(nb + 1) + b;
+      lo = tb[0];
+      len = tb[1] - lo;
+    }
+    unsigned tot;
+    const unsigned ex = block_excl_scan<unsigned>(len, &tot);
+    __syncthreads();   // the previous group's batches are finished with g*
+    gst[tid] = ex;
+    gend[tid] = ex + len;
+    gbase[tid] = f < f1 ? (u64)coff[f] + lo : 0;
+    gz[tid] = f < f1 ? cidx[f] : 0u;
+    __syncthreads();
+    for (unsigned q0 = 0; q0 < tot; q0 += GT_CHUNK) {
+#pragma unroll
+      for (int u = 0; u < GT_PER_THREAD; ++u) {
+        const int li = u * GT_THREADS + tid;
+        const unsigned q = q0 + (unsigned)li;
+        if (q < tot) {
+          int lo2 = 0, hi2 = GT_THREADS - 1;   // first fiber of the group ending after q
+          while (lo2 < hi2) {
+            const int mid = (lo2 + hi2) >> 1;
+            if (gend[mid] > q) hi2 = mid; else lo2 = mid + 1;
+          }
+          int ik;
+          T x;
+          nz.get(gbase[lo2] + (q - gst[lo2]), ik, x);
+          ka[li] = ((unsigned)((i64)ik - r0) << 12) | (unsigned)li;
+          lx[li] = x;
+          lz[li] = gz[lo2];
+        } else {
+          ka[li] = 0xFFFFFFFFu;
+          lx[li] = T(0);
+          lz[li] = 0u;
+        }
+      }
+      __syncthreads();
+      const unsigned *keys = chunk_radix(ka, kb, tab, rshift);
+      const int nvalid = (int)min((unsigned)GT_CHUNK, tot - q0);
+      seg_reduce<T, LPN, CPL>(LdsEntries<T>{keys, lx, lz}, nvalid, R, zhat, ldz,
+                              LdsAdd<T>{blk, LDB}, srow, svec);
+      __syncthreads();   // the merged adds are in the block before the next batch
+    }
+  }
+  __syncthreads();
+  T *Mp = M + (i64)p * nk * ldz;
+  const i64 nrows = min((i64)rb, nk - r0);
+  for (i64 e = tid; e < nrows * ldz; e += GT_THREADS) {
+    const i64 r = e / ldz;
+    const int c = (int)(e - r * ldz);
+    Mp[(r0 + r) * ldz + c] = blk[r * LDB + c];
+  }
+}
+
+// Row block of the owner gather: the largest power of two <= 512 rows whose
+// shared block (row stride ldz + 1 of the gather precision) fits OWN_BLK_BYTES,
+// and not above the mode's row count rounded up to a power of two.
+#define OWN_BLK_BYTES (68 * 1024)
+int gather_own_shift(bool f64, int ldz, i64 nk) {
+  const size_t row = (size_t)(ldz + 1) * (f64 ? 8 : 4);
+  int sh = 9;
+  while (sh > 4 && ((size_t)1 << sh) * row > OWN_BLK_BYTES) --sh;
+  while (sh > 4 && ((i64)1 << (sh - 1)) >= nk) --sh;
+  return sh;
+}
+
+int gather_own_blocks(bool f64, int ldz, i64 nk) {
+  const int sh = gather_own_shift(f64, ldz, nk);
+  return (int)((nk + (1ll << sh) - 1) >> sh);
+}
+
+void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
+                       const unsigned *coff, const unsigned *cidx, const uint2 *pairs,
+                       const int *ik, const double *v64, i64 nk, const void *zhat, int ldz,
+                       void *M, unsigned *bnd, hipStream_t s) {
+  const int sh = gather_own_shift(f64, ldz, nk);
+  const int nb = (int)((nk + (1ll << sh) - 1) >> sh);
+  const int rm = gather_row_width(R);
+  const size_t smem = ((size_t)1 << sh) * (size_t)(ldz + 1) * (f64 ? 8 : 4);
+  const dim3 grid((unsigned)nb * OWN_PARTS);
+  if (f64) {
+    hipLaunchKernelGGL(k_own_bounds<double>, dim3(1024), dim3(256), 0, s, st, cpos, coff,
+                       RowLoad<double>{ik}, sh, nb, bnd);
+    NzLoad<double> nz{ik, v64};
+    auto k = rm == 16 ? k_gather_own<double, 16, 1>
+                      : rm == 32 ? k_gather_own<double, 16, 2> : k_gather_own<double, 32, 2>;
+    hipLaunchKernelGGL(k, grid, dim3(GT_THREADS), smem, s, st, R, coff, cidx, bnd, nb, sh, nz,
+                       (const double *)zhat, ldz, (double *)M, nk);
+  } else {
+    hipLaunchKernelGGL(k_own_bounds<float>, dim3(1024), dim3(256), 0, s, st, cpos, coff,
+                       RowLoad<float>{pairs}, sh, nb, bnd);
+    NzLoad<float> nz{pairs};
+    auto k = rm == 16 ? k_gather_own<float, 16, 1>
+                      : rm == 32 ? k_gather_own<float, 16, 2> : k_gather_own<float, 32, 2>;
+    hipLaunchKernelGGL(k, grid, dim3(GT_THREADS), smem, s, st, R, coff, cidx, bnd, nb, sh, nz,
+                       (const float *)zhat, ldz, (float *)M, nk);
   }
 }
 

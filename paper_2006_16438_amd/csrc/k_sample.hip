@@ -504,14 +504,23 @@ __global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, 
 // draw that enters a row stores its position (its slot carries the row); a
 // later draw of the same row only counts itself as a repeat.  The table has
 // at least twice as many entries as draws, so a free entry exists.
+// With det_rep the row is carried by its earliest draw (an atomic minimum
+// over the draws of the row, the entry's first starting at ~0), so which slot
+// carries a repeated row, and with it the order of the sums over the rows,
+// does not depend on timing.
 __device__ __forceinline__ void draw_insert_from(DrawEntry *tab, u64 mask, u64 key, u64 h,
-                                                 u64 old, unsigned pos) {
+                                                 u64 old, unsigned pos, bool det_rep) {
   for (u64 probe = 0; old != CPAL_EMPTY_KEY && old != key && probe < mask; ++probe) {
     h = (h + 1) & mask;
     old = atomicCAS(&tab[h].key, CPAL_EMPTY_KEY, key);
   }
-  if (old == CPAL_EMPTY_KEY) tab[h].first = pos;
-  else if (old == key) atomicAdd(&tab[h].cnt, 1u);
+  if (old == CPAL_EMPTY_KEY) {
+    if (det_rep) atomicMin(&tab[h].first, pos);
+    else tab[h].first = pos;
+  } else if (old == key) {
+    atomicAdd(&tab[h].cnt, 1u);
+    if (det_rep) atomicMin(&tab[h].first, pos);
+  }
 }
 
 #define CMP_WINS 64   // windows of 256 chunks whose owned chunk is kept at once
@@ -531,7 +540,7 @@ __global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__rest
                                                  const unsigned *__restrict__ chunk_cnt,
                                                  const unsigned short *__restrict__ bpos,
                                                  u64 *__restrict__ keys, DrawEntry *tab,
-                                                 u64 tmask, int tshift) {
+                                                 u64 tmask, int tshift, int det_rep) {
   __shared__ i64 sh_draws;
   __shared__ u64 soff[256];
   __shared__ unsigned scnt[256];
@@ -582,7 +591,7 @@ __global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__rest
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (has[r]) draw_insert_from(tab, tmask, key[r], h[r], old[r], pos[r]);
+        if (has[r]) draw_insert_from(tab, tmask, key[r], h[r], old[r], pos[r], det_rep != 0);
     }
     __syncthreads();   // own_off / own_cnt are refilled by the next batch
   }
@@ -644,9 +653,9 @@ void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u6
 }
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
                     const unsigned short *bpos, u64 *keys, DrawEntry *tab, u64 tmask, int tshift,
-                    hipStream_t s) {
+                    bool det_rep, hipStream_t s) {
   hipLaunchKernelGGL(k_compact, dim3(256), dim3(256), 0, s, st, buf, chunk_cnt, bpos, keys, tab,
-                     tmask, tshift);
+                     tmask, tshift, det_rep ? 1 : 0);
 }
 
 __global__ void k_draw_table_clear(DrawEntry *__restrict__ tab, u64 n) {

@@ -13,8 +13,15 @@ from one seed, and the device-memory provider of the C ABI.
   number actually drawn.
 * End to end (100x80x60, 20,000 nonzeros, R = 5, s = 1024, tau = 1/s, FP64,
   seed 0): device and oracle each run 10 iterations from the same initial
-  factors without exchanging factors; every update's sample indices agree
-  and the factors stay within 1e-10.
+  factors without exchanging factors; every update's sample indices agree,
+  the final exact fits agree to 1e-10, and the factor difference after each
+  iteration stays within 16x what the loop itself makes of a one-ulp
+  perturbation: the oracle run a second time from initial factors perturbed
+  by a relative 2^-52 per entry.  On this workload (planted model RMS below
+  the noise) ALS amplifies such a perturbation about 2.5x per iteration, to
+  ~1e-10 after 10 iterations, so no two FP64 implementations that round in
+  different orders stay within a fixed 1e-10 end to end; the bar follows the
+  amplification instead.
 * Allocator: every device allocation of a context goes through the caller's
   provider and is returned at destroy."""
 import numpy as np
@@ -24,7 +31,7 @@ import torch
 import oracle
 from paper_2006_16438_amd import synth
 from paper_2006_16438_amd._lib import CpalError
-from tests.gpu_util import fro_rel_err, log, make_ctx, rel_err, run_parity
+from tests.gpu_util import log, make_ctx, rel_err, run_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -90,25 +97,29 @@ def test_end_to_end_small3_from_seed0():
     OT = oracle.Tensor.from_synth(T)
     ctx, F = make_ctx(T, fac, R, s, tau, "f64")
     fo = [f.copy() for f in fac]
-    agree, fro, mx = [], [], []
+    rng = np.random.default_rng(11)
+    fp = [f * (1.0 + 2.0 ** -52 * rng.choice([-1.0, 1.0], size=f.shape)) for f in fac]
+    agree, mx, amp = [], [], []
     for u in range(iters * 3):
         k = u % 3
         ref = oracle.mode_update(OT, fo, k, u, R, s, tau)
+        oracle.mode_update(OT, fp, k, u, R, s, tau)
         ctx.mode_update(k)
         idx = ctx.samples_view()[0].cpu().numpy().view(np.uint64)
         agree.append(float(np.mean(idx == ref["idx"])) if idx.size == ref["idx"].size else 0.0)
         got = [F[m].cpu().numpy() for m in range(3)]
-        fro.append(max(fro_rel_err(got[m], fo[m]) for m in range(3)))
         mx.append(max(rel_err(got[m], fo[m]) for m in range(3)))
+        amp.append(max(rel_err(fp[m], fo[m]) for m in range(3)))
     fit_g = oracle.fit_exact(OT, [f.cpu().numpy() for f in F], R)
     fit_o = oracle.fit_exact(OT, fo, R)
+    per_it = lambda v: [max(v[i:i + 3]) for i in range(0, len(v), 3)]
     log(f"  end to end: index agreement min {min(agree):.4f}; per iteration max factor error "
-        f"(Frobenius) {['%.1e' % max(fro[i:i + 3]) for i in range(0, len(fro), 3)]}, "
-        f"(max-norm) {['%.1e' % max(mx[i:i + 3]) for i in range(0, len(mx), 3)]}; "
-        f"fit gpu {fit_g:.12f} oracle {fit_o:.12f}")
+        f"device {['%.1e' % e for e in per_it(mx)]}, oracle perturbed by 2^-52 "
+        f"{['%.1e' % e for e in per_it(amp)]}; fit gpu {fit_g:.12f} oracle {fit_o:.12f}")
     ctx.close()
     assert min(agree) == 1.0
-    assert max(fro) <= 1e-10
+    for i, (e, a) in enumerate(zip(per_it(mx), per_it(amp))):
+        assert e <= max(16.0 * a, 1e-13), (i, e, a)
     assert abs(fit_g - fit_o) <= 1e-10
 
 

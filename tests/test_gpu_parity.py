@@ -283,15 +283,71 @@ def test_bucketed_gather_fp32(case):
                gather_config=(512, -1))
 
 
+@pytest.mark.parametrize("case", ["long_short", "multitile", "uber4"])
+def test_owner_gather_fp32(case):
+    """The owner gather (no atomic operation: workgroup (row block, fiber
+    part) alone forms its rows of one copy of M in shared memory, from the
+    fibers' per-block segments), FP32: long-fiber and short-fiber modes,
+    several row blocks and fiber groups, the benchmark workload at full
+    size."""
+    if case == "long_short":
+        dims = (3000, 4, 3)
+        T = synth.random_sparse(dims, 30_000, seed=51)
+        R, s, tau, n = 3, 256, 1 / 256, 6
+        fac = concentrated(dims, R, 52)
+    elif case == "multitile":
+        dims = (700, 300, 257)
+        T = synth.random_sparse(dims, 150_000, seed=21)
+        R, s, tau, n = 8, 8192 + 77, 1 / 8192, 6
+        fac = concentrated(dims, R, 22)
+    else:
+        T = synth.uber4(0)
+        R, s, tau, n = 25, 1 << 17, 2.0 ** -17, 4
+        fac = synth.gaussian_factors(T.dims, R, 0)
+    log(f"owner gather, {case}")
+    run_parity(T, fac, R, s, tau, n, "f32", "derived", label=f"owner-{case}",
+               gather_config=(0, -2))
+
+
+@pytest.mark.parametrize("which", ["multitile", "rank40"])
+def test_fp64_updates_bit_reproducible(which):
+    """FP64 mode updates (owner gather, earliest draw carrying each repeated
+    row) are bit-reproducible: two contexts built from the same inputs, run
+    through the same updates, hold bit-identical factors after every update,
+    although repeated rows and many fibers per output row occur."""
+    if which == "multitile":
+        dims = (700, 300, 257)
+        T = synth.random_sparse(dims, 150_000, seed=21)
+        R, s = 8, 8192
+    else:   # R > 32: 64-wide rows
+        dims = (900, 40, 35)
+        T = synth.random_sparse(dims, 200_000, seed=23)
+        R, s = 40, 4096
+    fac = concentrated(dims, R, 22)
+    a, Fa = make_ctx(T, fac, R, s, 1.0 / s, "f64")
+    b, Fb = make_ctx(T, fac, R, s, 1.0 / s, "f64")
+    assert all(a.gather_config(m)[1] == -2 for m in range(3))
+    for u in range(9):
+        k = u % 3
+        a.mode_update(k)
+        b.mode_update(k)
+        st = a.last_stats()
+        assert np.array_equal(Fa[k].cpu().numpy().view(np.uint64), Fb[k].cpu().numpy().view(np.uint64)), \
+            f"update {u}: factors differ between identical runs"
+        log(f"  update {u}: s_bar {st['s_bar']} of {s} (repeats combined), bit-identical")
+    a.close()
+    b.close()
+
+
 def test_gather_config_errors():
     """Argument checks of the launch-shape calls: negative grids, sort
-    thresholds below -1, the bucketed gather (-1) in FP64 mode, a dense
+    thresholds below -2, the bucketed gather (-1) in FP64 mode, a dense
     split beyond the default, modes out of range."""
     from paper_2006_16438_amd._lib import CpalError
     T, _, R = synth.small3(0)
     fac = synth.gaussian_factors(T.dims, R, 0)
     ctx, _ = make_ctx(T, fac, R, 1024, gather="f64")
-    for args in ((0, -1, 0), (0, 64, -2), (0, 64, -1), (3, 64, 0), (-1, 64, 0)):
+    for args in ((0, -1, 0), (0, 64, -3), (0, 64, -1), (3, 64, 0), (-1, 64, 0)):
         with pytest.raises(CpalError):
             ctx.set_gather_config(*args)
     ctx.set_gather_config(0, 64, 4)
@@ -308,4 +364,6 @@ def test_gather_config_errors():
         ctx.set_gather_config(0, default + 1, 0)
     with pytest.raises(CpalError):
         ctx.set_gather_config(0, 1, -1)   # no bucketed gather for dense tensors
+    with pytest.raises(CpalError):
+        ctx.set_gather_config(0, 1, -2)   # nor an owner gather
     ctx.close()
