@@ -1,21 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of CP-ARLS-LEV mode updates on one MI355X.
 
-Workload (the Uber-shaped tensor of Sec. 7.3, synthetic): 4-way sparse
-183 x 24 x 1140 x 1717 with 3.3e6 distinct Zipf(1.1) coordinates and values
-log(1+c), c ~ Poisson(3) given c >= 1; rank R = 25, s = 2^17 samples,
-tau = 2^-17 (hybrid), FP32 fiber gather with FP64 Gram/solve/leverage, fit
-estimated from 2^20 stratified entries.
+Default workload (standing in for the Reddit tensor of Sec. 7, synthetic):
+sparse 3-way 8211 x 176962 x 8116 with 1e9 distinct Zipf(1.2) coordinates
+and values log(1+c), c ~ Geometric(0.3); rank R = 25, s = 2^17 samples,
+tau = 2^-17 (hybrid).  value = mode updates per second with the fiber gather,
+Gram, solve and leverage in FP64; the same decomposition with the FP32 gather
+runs beside it (mixed vs plain) and the fits of the two runs are compared.
 
-A step is one outer iteration of Alg. 3: the four mode updates followed by
-one fit estimate.  The timed run starts from a fresh context (same seed and
-initial factors as the warm-up run), so the K timed steps are the first K
-iterations of the decomposition.  value = mode updates per second.
+A step is one outer iteration of Alg. 3 (one update of every mode).  The
+timed run starts from the initial factors after warm-up iterations whose
+state is reset, so the K timed steps are the first K iterations of the
+decomposition.
 
-Also printed (same JSON line): gathered rows/s, the roofline of the fiber
-gather kernel from HIP events recorded around it during the timed region,
-the CPU oracle's throughput on the first mode updates of the same run, and
-the fit of the final factors against the FP64 oracle's own run."""
+Also printed (same JSON line): gathered rows/s, the roofline of the gather
+stage from HIP events recorded around it during the timed region, and the
+CPU oracle on the host cores (one thread and all threads) over a bounded
+sample of the same workload.  --workload uber4 / dense1000 / batch256 run
+the other configurations."""
 from __future__ import annotations
 
 import argparse
@@ -68,6 +70,14 @@ def recorded_traffic(root):
     return rec.get("traffic_bytes_per_launch") if rec else None
 
 
+def recorded_stage_traffic(root, name):
+    """HBM bytes per update of a gather stage from a committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy's
+    counters), or None when the kernel source has changed since."""
+    rec = recorded_counters(root, name)
+    return rec.get("traffic_bytes_per_launch") if rec else None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -78,19 +88,21 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--gather", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--workload", default="uber4",
+    ap.add_argument("--workload", default="large1e9",
                     choices=["uber4", "dense1000", "batch256", "large1e9"],
-                    help="uber4: the sparse 4-way benchmark (default); dense1000: dense "
-                         "1000^3, BF16 on the matrix cores vs the plain FP32 path; batch256: "
-                         "64 sparse tensors x 4 restarts stepped together vs one at a time; "
-                         "large1e9: sparse 8211x176962x8116 with 1e9 nonzeros")
+                    help="large1e9: sparse 8211x176962x8116 with 1e9 nonzeros, FP64 gather "
+                         "beside FP32 (default); uber4: the sparse 4-way Uber-shaped tensor; "
+                         "dense1000: dense 1000^3, BF16 on the matrix cores vs the plain FP32 "
+                         "path; batch256: 64 sparse tensors x 4 restarts stepped together vs "
+                         "one at a time")
     ap.add_argument("--conv-iters", type=int, default=CONV_ITERS,
                     help="dense1000: iterations of the fit comparison between precisions "
                          "(0: skip it)")
     ap.add_argument("--large-nnz", type=int, default=1_000_000_000,
                     help="nonzeros of the large1e9 workload")
-    ap.add_argument("--cpu-updates", type=int, default=80,
-                    help="mode updates of the CPU oracle baseline (20 iterations = 80)")
+    ap.add_argument("--cpu-updates", type=int, default=None,
+                    help="mode updates of the CPU oracle baseline (default 80 for uber4, "
+                         "12 for large1e9)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", choices=["on", "off"], default=None,
                     help="time the gather launch shapes after the warm-up (cp_arls_lev_autotune); "
@@ -103,6 +115,8 @@ def main():
     args = ap.parse_args()
     args.tune = (args.autotune or ("on" if args.workload in ("batch256", "large1e9")
                                    else "off")) == "on"
+    if args.cpu_updates is None:
+        args.cpu_updates = 12 if args.workload == "large1e9" else 80
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(every box has one MI355X)", file=sys.stderr)
@@ -546,14 +560,45 @@ def exact_fit_sparse(coords, vals, F, chunk=1 << 23):
     return 1.0 - math.sqrt(res2) / math.sqrt(norm_x2)
 
 
+def host_cpu_info():
+    """nproc, the CPUs this process may run on, and lscpu's model, socket and
+    core counts."""
+    import subprocess
+    info = {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "Socket(s)", "Core(s) per socket",
+                               "Thread(s) per core", "CPU(s)"):
+                info[key.strip()] = val.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def oracle_threads():
+    """Threads of the oracle's all-thread leg: the CPUs this process may run
+    on, at most OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
 def bench_large(args):
     """Sparse 3-way 8211 x 176962 x 8116 with 1e9 distinct Zipf(1.2)
     coordinates (synth_gpu.large3), values log(1 + Geometric(0.3)); R = 25,
-    s = 2^17, tau = 2^-17.  The FP32-gather path is timed over K iterations
-    from fresh factors (after W warm-up iterations whose state is reset);
-    an FP64-gather run of the same decomposition gives the reference fit."""
+    s = 2^17, tau = 2^-17.  value: mode updates per second with the FP64
+    gather (the paper's precision), K iterations from fresh factors after W
+    warm-up iterations whose state is reset.  Beside it the same run with the
+    FP32 gather (FP64 Gram, solve and leverage kept), and the fit difference
+    of the two runs' final factors (exact fits on the device)."""
+    import numpy as np
     import torch
 
+    import oracle
     from paper_2006_16438_amd import synth, synth_gpu
     from paper_2006_16438_amd.api import CpArlsLev
 
@@ -561,16 +606,16 @@ def bench_large(args):
     R, s = 25, 1 << 17
     tau = 1.0 / s
     t0 = time.time()
-    dims, coords, vals = synth_gpu.large3(0, nnz=args.large_nnz)
+    dims, coords, vals = synth_gpu.large3(0, nnz=args.large_nnz, verbose=False)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()   # the library allocates outside torch's cache
     t_gen = time.time() - t0
     nnz = int(vals.numel())
     log(f"generated {dims} with {nnz} nonzeros in {t_gen:.1f}s")
     fac0 = synth.gaussian_factors(dims, R, 0)
-    K = args.steps
+    K, W = args.steps, args.warmup
 
-    def run(gather, timed):
+    def run(gather, tune):
         F = [torch.from_numpy(f.copy()).to(dev) for f in fac0]
         torch.cuda.synchronize()
         t1 = time.time()
@@ -578,112 +623,165 @@ def bench_large(args):
                         gather_dtype=gather)
         torch.cuda.synchronize()
         t_init = time.time() - t1
-        log(f"{gather}: context initialised in {t_init:.1f}s "
-            f"(device memory in use {torch.cuda.memory_allocated() / 2**30:.1f} GiB by torch)")
-        if timed and args.warmup > 0:
-            for _ in range(args.warmup):
-                for k in range(3):
-                    ctx.mode_update(k, stats=False)
-            torch.cuda.synchronize()
-            if args.tune:   # launch shapes timed on the warmed-up state
-                t1 = time.time()
-                cfg = ctx.autotune()
-                log(f"{gather}: autotuned gather shapes {cfg} in {time.time() - t1:.1f}s")
-            for m in range(3):   # back to the initial state
-                F[m].copy_(torch.from_numpy(fac0[m]))
-                ctx.refresh(m)
-            ctx.step = 0
-            torch.cuda.synchronize()
+        log(f"{gather}: context initialised in {t_init:.1f}s")
+        for _ in range(W):
+            for k in range(3):
+                ctx.mode_update(k, stats=False)
+        torch.cuda.synchronize()
+        if tune:   # launch shapes timed on the warmed-up state
+            t1 = time.time()
+            cfg = ctx.autotune()
+            log(f"{gather}: autotuned gather shapes {cfg} in {time.time() - t1:.1f}s")
+        for m in range(3):   # back to the initial state
+            F[m].copy_(torch.from_numpy(fac0[m]))
+            ctx.refresh(m)
+        ctx.step = 0
         stats = torch.zeros((K * 3, 7), dtype=torch.int64, device=dev)
-        if timed:
-            ctx.set_timing(stages=["gather"])
+        ctx.set_timing(stages=["gather"])   # events around the gather stage only
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for it in range(K):
             for k in range(3):
                 ctx.mode_update(k, stats_buf=stats[it * 3 + k])
-            if not timed:
-                torch.cuda.synchronize()
-                log(f"{gather}: iteration {it} done")
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
-        stage = ctx.stage_times(reset=True) if timed else None
-        stage_all = None
-        if timed:   # per-stage breakdown from one more (untimed) iteration
-            ctx.set_timing(True)
-            for k in range(3):
-                ctx.mode_update(k, stats=False)
-            stage_all = ctx.stage_times(reset=True)
-            ctx.set_timing(False)
+        stage = ctx.stage_times(reset=True)
+        fit = float(ctx.fit_exact().item())
+        final = [f.clone() for f in F]
+        ctx.set_timing(True)   # per-stage breakdown from one more (untimed) iteration
+        for k in range(3):
+            ctx.mode_update(k, stats=False)
+        stage_all = ctx.stage_times(reset=True)
+        ctx.set_timing(False)
         cfg = [ctx.gather_config(k) for k in range(3)]
         ctx.close()
+        del F
+        torch.cuda.empty_cache()
         sts = [CpArlsLev.parse_stats(stats[i]) for i in range(K * 3)]
-        fit = exact_fit_sparse(coords, vals, F)
-        log(f"{gather}: {K} iterations in {el:.3f}s, exact fit {fit:.6f}")
-        return el, stage, stage_all, sts, F, fit, t_init, cfg
+        elem = 8 if gather == "f64" else 4
+        gb = sum(gather_bytes(x, R, dims[i % 3], elem) for i, x in enumerate(sts))
+        g_ms, g_cnt = stage["gather"]
+        log(f"{gather}: {K} iterations in {el:.3f}s ({3 * K / el:.1f} mode updates/s), "
+            f"gather stage {1e3 * g_ms / max(g_cnt, 1):.0f} us per update, exact fit {fit:.8f}")
+        return dict(el=el, sts=sts, gbytes=gb, g_ms=g_ms, g_cnt=g_cnt, fit=fit, final=final,
+                    stage_all=stage_all, cfg=cfg, t_init=t_init)
 
-    el, stage, stage_all, sts, F32, fit32, t_init, gcfg = run("f32", True)
-    gather_label = ("fiber gather + sampled MTTKRP, whole stage per update: "
-                    + ", ".join(f"mode {k} " + ("bucketed (k_bkt_count, scan, k_bkt_scatter, "
-                                                "k_gather_bkt)" if sm < 0 else "k_gather_seg")
-                                for k, (g, sm) in enumerate(gcfg)))
-    updates = K * 3
-    gbytes = sum(gather_bytes(x, R, dims[i % 3], 4) for i, x in enumerate(sts))
-    g_ms, g_cnt = stage["gather"]
-    achieved = gbytes / (g_ms * 1e-3) / 1e9 if g_ms > 0 else 0.0
-    _, _, _, _, F64, fit64, _, _ = run("f64", False)
-    fac_err = max(float((a - b).norm() / b.norm()) for a, b in zip(F32, F64))
+    r64 = run("f64", args.tune)
+    r32 = run("f32", args.tune)
+    updates = 3 * K
+
+    def names(cfg):
+        return {-2: "owner gather (k_own_bounds + k_gather_own)",
+                -1: "bucketed gather (k_bkt_count, scan, k_bkt_scatter, k_gather_bkt)"}.get(
+                    cfg, "segmented gather (k_gather_seg)")
+
+    achieved = r64["gbytes"] / (r64["g_ms"] * 1e-3) / 1e9 if r64["g_ms"] > 0 else 0.0
+    fac_err = max(float((a - b).norm() / b.norm()) for a, b in zip(r32["final"], r64["final"]))
+    sts = r64["sts"]
     result = {
         "metric": METRIC,
-        "value": updates / el,
+        "value": updates / r64["el"],
         "unit": "mode-updates/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * el / K,
+        "warmup": W,
+        "ms_per_step": 1e3 * r64["el"] / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": f"sparse 3-way {dims[0]}x{dims[1]}x{dims[2]}, {nnz} distinct Zipf(1.2) "
-                        "coordinates, log1p(Geometric(0.3)) FP32 values; R=25, s=2^17, "
-                        "tau=2^-17, FP32 gather, FP64 Gram/solve; a step = one iteration "
+                        "coordinates, log1p(Geometric(0.3)) values; R=25, s=2^17, tau=2^-17, "
+                        "FP64 gather, Gram, solve and leverage; a step = one iteration "
                         "(3 mode updates)",
             "rank": R, "samples": s, "tau": tau, "iterations": K, "nnz": nnz,
             "parallelism": "single GPU",
         },
-        "gathered_rows_per_s": sum(x["s_bar"] for x in sts) / el,
-        "gathered_nnz_per_s": sum(x["gathered_nnz"] for x in sts) / el,
-        "gathered_nnz_per_update": [x["gathered_nnz"] for x in sts[:3]],
-        "stage_ms_per_update": {k: v[0] / max(v[1], 1) for k, v in stage_all.items()},
+        "gathered_rows_per_s": sum(x["s_bar"] for x in sts) / r64["el"],
+        "gathered_nnz_per_s": sum(x["gathered_nnz"] for x in sts) / r64["el"],
+        "gathered_nnz_per_update_last_iteration": [x["gathered_nnz"] for x in sts[-3:]],
+        "stage_ms_per_update": {k: v[0] / max(v[1], 1) for k, v in r64["stage_all"].items()},
         "roofline": {
-            "kernel": gather_label,
+            "kernel": "FP64 fiber gather + sampled MTTKRP, whole stage per update: "
+                      + "; ".join(f"mode {k}: {names(sm)}" for k, (g, sm) in enumerate(r64["cfg"])),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "algorithmic_bytes_per_launch": gbytes / updates,
-            "avg_launch_us": 1e3 * g_ms / max(g_cnt, 1),
+            "traffic": recorded_stage_traffic(ROOT, "gather_own_large1e9_traffic.txt"),
+            "algorithmic_bytes_per_launch": r64["gbytes"] / updates,
+            "avg_launch_us": 1e3 * r64["g_ms"] / max(r64["g_cnt"], 1),
+            "timed_with": "HIP events on the library's stream around the gather stage of "
+                          "every timed update",
         },
-        "init_s": t_init,
+        "f64_bit_reproducible": all(sm == -2 for _, sm in r64["cfg"]),
+        "init_s": r64["t_init"],
         "generate_s": t_gen,
-        "gather_launch": {"autotuned": args.tune,
-                          "grid_sort_min_per_mode": gcfg},
-        "fit_exact": {"f32": fit32, "f64_reference": fit64},
-        "fit_delta": abs(fit32 - fit64),
-        "factor_rel_err_f32_vs_f64": fac_err,
-        "cpu_baseline": None,
-        "cpu_baseline_note": "the FP64 oracle cannot hold 1e9 nonzeros; the FP64-gather GPU "
-                             "path (oracle parity 1e-10) is the reference",
+        "mixed_vs_plain": {
+            "f32_gather_mode_updates_per_s": updates / r32["el"],
+            "f32_gather_stage_us": 1e3 * r32["g_ms"] / max(r32["g_cnt"], 1),
+            "f32_gather_launch": [names(sm) for _, sm in r32["cfg"]],
+            "f32_autotuned": args.tune,
+            "fit_exact_f64": r64["fit"],
+            "fit_exact_f32": r32["fit"],
+            "fit_delta": abs(r32["fit"] - r64["fit"]),
+            "factor_rel_err_f32_vs_f64": fac_err,
+            "note": "plain = one decomposition with the FP32 gather and FP64 Gram/solve/"
+                    "leverage; the FP64 run is parity-tested against the FP64 CPU oracle "
+                    "(1e-10 per update)",
+        },
         "paper_context": "Sec. 7 (Reddit tensor 8.2e6 x 176962 x 8.1e6, 4.7e9 nonzeros, R=25, "
                          "hybrid s=2^17): 2231 s per epoch of 15 mode updates, about 149 s per "
                          "update, MATLAB FP64 on 2x AMD EPYC 7601 (64 cores); a 4.7x larger "
                          "tensor on other hardware, context only",
+        "cpu_baseline": None,
     }
+    del r32, r64
+
+    if not args.no_cpu_baseline:
+        # the oracle on every 64th nonzero of the same tensor (same dims, R, s, tau)
+        stride = 64
+        t1 = time.time()
+        sc = coords[:, ::stride].cpu().numpy()
+        sv = vals[::stride].double().cpu().numpy()
+        del coords, vals
+        torch.cuda.empty_cache()
+        OT = oracle.Tensor(dims, sc, sv)
+        OT.index
+        t_index = time.time() - t1
+        n_cpu = max(3, args.cpu_updates)
+        legs = {}
+        ref_idx = None
+        for threads in (1, oracle_threads()):
+            oracle.set_threads(threads)
+            fo = [f.copy() for f in fac0]
+            t2 = time.perf_counter()
+            first = None
+            for u in range(n_cpu):
+                r = oracle.mode_update(OT, fo, u % 3, u, R, s, tau, 0, 0)
+                if u == 0:
+                    first = r["idx"].copy()
+            legs[threads] = n_cpu / (time.perf_counter() - t2)
+            if ref_idx is None:
+                ref_idx = first
+            assert np.array_equal(first, ref_idx), "threaded oracle differs from sequential"
+            log(f"oracle, {threads} thread(s): {legs[threads]:.3f} mode updates/s")
+        oracle.set_threads(1)
+        nt = max(legs)
+        result["cpu_baseline"] = {
+            "value": legs[nt],
+            "unit": "mode-updates/s",
+            "cores": nt,
+            "kind": "oracle",
+            "sample": f"the FP64 C oracle on every {stride}th nonzero of the same tensor "
+                      f"({sv.size} nonzeros, same dims, R, s, tau), first {n_cpu} mode updates "
+                      f"from the same initial factors; index build {t_index:.1f}s excluded",
+            "single_thread_value": legs[1],
+            "host": host_cpu_info(),
+        }
     print(json.dumps(result), flush=True)
 
 

@@ -259,18 +259,25 @@ cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *cou
  * gather (modes of at most 2^20 rows) keeps the nonzeros of a 2048-position
  * chunk in stream order instead of sorting them by row when the chunk spans
  * at most sort_min sampled fibers (0: always sort); sort_min = -1 selects the
- * bucketed gather instead (FP32 gather, modes of at most 2^20 rows): the
- * sampled nonzeros are first moved into 4096 buckets of consecutive output
- * rows, so that the adds of different fibers to one row are summed on chip
- * (it allocates 16 bytes per stored nonzero plus 48 MB on first use; its
- * sums are in a timing-dependent order).  Dense tensors: grid =
+ * bucketed gather instead (modes of at most 2^20 rows): the sampled nonzeros
+ * are first moved into 4096 buckets of consecutive output rows, so that the
+ * adds of different fibers to one row are summed on chip (it allocates 16
+ * bytes per stored nonzero plus 48 MB on first use).  sort_min = -2 selects
+ * the owner gather (modes of at most 2^20 rows; grid unused): no atomic
+ * operation, each workgroup alone forms a block of rows of one of 8 partial
+ * copies of M from its part of the sampled fibers, and the copies are added
+ * in a fixed order, so the update's result does not depend on timing (it
+ * allocates 4 bytes per sample and row block).  FP64 contexts start on the
+ * owner gather for every such mode, which makes their updates bit-for-bit
+ * reproducible; the segmented and bucketed gathers add with atomics and
+ * their sums are in a timing-dependent order.  Dense tensors: grid =
  * workgroups along the sampled fibers of the split contraction (each writes
  * one partial M; at most the default, which get_gather_config reports;
  * sort_min unused).  Results do not depend on either beyond the rounding
  * order of the FP32/FP64 sums.  Host-side setting, takes effect at the next
- * mode update; grid in [0, 2^20] (dense: [0, default]), sort_min >= -1 (-1
- * only where the bucketed gather applies), else CPAL_E_ARG; CPAL_E_NOMEM if
- * the bucketed gather's buffers cannot be allocated. */
+ * mode update; grid in [0, 2^20] (dense: [0, default]), sort_min >= -2 (-1
+ * and -2 only for sparse modes of at most 2^20 rows), else CPAL_E_ARG;
+ * CPAL_E_NOMEM if the chosen gather's buffers cannot be allocated. */
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *ctx, int32_t k, int32_t grid,
                                           int32_t sort_min);
 /* The launch shape mode k uses (grid_host: the effective workgroup count). */
@@ -281,11 +288,12 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_
  * system of an update of that mode at the current step (sampling, KRP rows,
  * fiber probes; the factors, leverage scores and step counter are left as
  * they were), times the gather over a fixed set of grids (and, for the
- * segmented gather, sort thresholds and the bucketed gather, whose buffers
- * it allocates where they fit; for dense tensors the default split of
- * the sampled fibers and 1/2, 1/4, 1/8 of it) with HIP events, best of
- * `reps` runs each (0: 2, at most 16), and keeps the fastest shape for the
- * mode.  Every trial samples at the current step; afterwards the step
+ * segmented gather, sort thresholds, the bucketed gather and the owner
+ * gather, whose buffers it allocates where they fit; for dense tensors the
+ * default split of the sampled fibers and 1/2, 1/4, 1/8 of it) with HIP
+ * events, best of `reps` runs each (0: 2, at most 16), and keeps the fastest
+ * shape for the mode (in FP64 contexts a shape other than the owner gather
+ * gives up bit-for-bit reproducibility for speed).  Every trial samples at the current step; afterwards the step
  * counter, factors and leverage scores are as before, and
  * cp_arls_lev_samples reports CPAL_E_STATE until the next mode update.
  * Synchronizes the stream and is not graph-capturable. */

@@ -26,7 +26,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall",
-                               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+                               "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -97,6 +97,20 @@ def lib():
         L.orc_model_entry.restype = C.c_double
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's independent loops (1 = the sequential loops);
+    every sum keeps its sequential order, so results do not depend on n."""
+    L = lib()
+    L.orc_set_threads.argtypes = [C.c_int32]
+    L.orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    L = lib()
+    L.orc_get_threads.restype = C.c_int32
+    return int(L.orc_get_threads())
 
 
 def _p(a, ct):

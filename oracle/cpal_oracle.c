@@ -29,6 +29,15 @@
 #define GRAM_BLOCK 256
 #define MAXR 64
 
+/* Threads of the loops below whose iterations are independent (rows of the
+ * Gram matrix, leverage rows, blocks of draws, sampled rows, solved rows).
+ * Every such loop keeps the summation order of the sequential loop it
+ * replaces: any thread count gives the same bits as one thread. */
+static int g_threads = 1;
+
+void orc_set_threads(int32_t n) { g_threads = n > 1 ? n : 1; }
+int32_t orc_get_threads(void) { return g_threads; }
+
 /* ------------------------------------------------------------------------ */
 /* Random numbers: Philox4x64-10, written from the published description   */
 /* (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2,  */
@@ -95,6 +104,7 @@ typedef struct {
 } decomp;
 
 void orc_gram(const double *A, int64_t n, int32_t R, double *G) {
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads) if (g_threads > 1)
   for (int a = 0; a < R; ++a) {
     for (int b = a; b < R; ++b) {
       double total = 0.0;
@@ -295,6 +305,7 @@ int32_t orc_leverage(const double *A, int64_t n, int32_t R, double *lev) {
   decomp *d = (decomp *)malloc(sizeof(decomp));
   orc_gram(A, n, R, G);
   factorize(G, R, d);
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
   for (int64_t i = 0; i < n; ++i) {
     double l = quad_form(d, A + i * R);
     lev[i] = l > 0.0 ? l : 0.0;
@@ -537,6 +548,79 @@ int64_t orc_det_set(int32_t order, const int64_t *dims, const double *const *q,
 /*   G_s = sum_j omega_j z_j z_j^T,  M = sum_j omega_j x_j z_j^T,             */
 /*   A_k = M G_s^{-1}, with omega_j = wgt_j^2.                               */
 /* ------------------------------------------------------------------------ */
+/* The sampled normal equations G = sum_j omega_j z_j z_j^T and
+ * M = sum_j omega_j X~(j,:)^T z_j^T with several threads and the sums of
+ * the sequential loop: the KRP rows and fiber ranges of the sampled rows are
+ * found in parallel, every gathered nonzero is listed as (row i_k, sample j,
+ * entry), the list is sorted by i_k stably (so j ascends within a row), and
+ * each row of M, like each row of G, is summed by one thread in ascending j.
+ * Returns nnz(X~). */
+static int64_t sampled_system_threads(const orc_tensor *X, const orc_index *ix,
+                                      double *const *factors, int k, int R, int d,
+                                      const int *O, const uint64_t *idx, const double *omega,
+                                      int64_t sb, double *G, double *M) {
+  const int64_t nk = X->dims[k];
+  double *Z = (double *)malloc(sizeof(double) * (size_t)(sb ? sb : 1) * R);
+  int64_t *lo = (int64_t *)malloc(sizeof(int64_t) * (size_t)(sb + 1));
+  int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(sb + 1));
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+  for (int64_t j = 0; j < sb; ++j) {
+    uint64_t rem = idx[j];
+    int64_t im[16];
+    for (int u = 0; u < d; ++u) { im[u] = (int64_t)(rem % (uint64_t)X->dims[O[u]]); rem /= (uint64_t)X->dims[O[u]]; }
+    for (int r = 0; r < R; ++r) {
+      double v = factors[O[0]][im[0] * R + r];
+      for (int u = 1; u < d; ++u) v = v * factors[O[u]][im[u] * R + r];
+      Z[j * R + r] = v;
+    }
+    int64_t pos = lower_bound_u64(ix->key[k], X->nnz, idx[j]);
+    int64_t end = pos;
+    while (end < X->nnz && ix->key[k][end] == idx[j]) end++;
+    lo[j] = pos;
+    cnt[j] = end - pos;
+  }
+  int64_t total = 0;
+  for (int64_t j = 0; j < sb; ++j) { int64_t c = cnt[j]; cnt[j] = total; total += c; }
+  cnt[sb] = total;
+  int64_t *rowof = (int64_t *)malloc(sizeof(int64_t) * (size_t)(total ? total : 1));
+  int64_t *jof = (int64_t *)malloc(sizeof(int64_t) * (size_t)(total ? total : 1));
+  int64_t *eof = (int64_t *)malloc(sizeof(int64_t) * (size_t)(total ? total : 1));
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+  for (int64_t j = 0; j < sb; ++j)
+    for (int64_t q = cnt[j]; q < cnt[j + 1]; ++q) {
+      int64_t e = ix->id[k][lo[j] + (q - cnt[j])];
+      rowof[q] = X->coords[(int64_t)k * X->nnz + e];
+      jof[q] = j;
+      eof[q] = e;
+    }
+  /* stable counting sort of the list by row */
+  int64_t *rstart = (int64_t *)calloc((size_t)nk + 1, sizeof(int64_t));
+  for (int64_t q = 0; q < total; ++q) rstart[rowof[q] + 1]++;
+  for (int64_t i = 0; i < nk; ++i) rstart[i + 1] += rstart[i];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nk ? nk : 1));
+  memcpy(fill, rstart, sizeof(int64_t) * (size_t)nk);
+  int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(total ? total : 1));
+  for (int64_t q = 0; q < total; ++q) order[fill[rowof[q]]++] = q;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(g_threads)
+  for (int64_t i = 0; i < nk; ++i)
+    for (int64_t u = rstart[i]; u < rstart[i + 1]; ++u) {
+      const int64_t q = order[u];
+      const double ox = omega[jof[q]] * X->vals[eof[q]];
+      const double *z = Z + jof[q] * R;
+      for (int r = 0; r < R; ++r) M[i * R + r] = M[i * R + r] + ox * z[r];
+    }
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+  for (int a = 0; a < R; ++a)
+    for (int64_t j = 0; j < sb; ++j) {
+      const double om = omega[j];
+      const double *z = Z + j * R;
+      for (int b = 0; b < R; ++b) G[a * R + b] = G[a * R + b] + (om * z[a]) * z[b];
+    }
+  free(Z); free(lo); free(cnt); free(rowof); free(jof); free(eof);
+  free(rstart); free(fill); free(order);
+  return total;
+}
+
 int32_t orc_mode_update(const orc_tensor *X, const orc_index *ix,
                         double *const *factors, const orc_opts *opt,
                         int32_t k, uint64_t t,
@@ -593,25 +677,41 @@ int32_t orc_mode_update(const orc_tensor *X, const orc_index *ix,
 
     /* Alg. 2: draw per-mode indices (Lemma 5.3), reject p > tau, keep the
      * first s_rnd accepted in draw order. */
+    /* The draws are made in blocks (each draw depends only on its index),
+     * then examined in draw order. */
     int64_t guard = 64 * s_rnd + (1 << 20);
+    const int64_t DBLK = 1 << 16;
+    uint64_t *blin = (uint64_t *)malloc(sizeof(uint64_t) * DBLK);
+    double *bpr = (double *)malloc(sizeof(double) * DBLK);
     while (nacc < s_rnd) {
       if (draws >= guard) { st->flags |= ORC_FLAG_DRAWCAP; break; }
-      uint64_t lin = 0, stride = 1;
-      double pr = 0.0;
-      for (int u = 0; u < d; ++u) {
-        int m = O[u];
-        uint64_t out[4];
-        draw_words(opt->seed, opt->stream_id, (uint64_t)draws,
-                   (uint64_t)m | ((uint64_t)k << 8), t, out);
-        uint64_t v = orc_scale128(out[0], out[1], W[m]);
-        int64_t i = orc_upper_bound(C[m], X->dims[m], v);
-        pr = (u == 0) ? q[m][i] : pr * q[m][i];
-        lin += (uint64_t)i * stride;
-        stride *= (uint64_t)X->dims[m];
+      const int64_t nb = guard - draws < DBLK ? guard - draws : DBLK;
+      const int64_t j0 = draws;
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
+      for (int64_t b = 0; b < nb; ++b) {
+        uint64_t lin = 0, stride = 1;
+        double pr = 0.0;
+        for (int u = 0; u < d; ++u) {
+          int m = O[u];
+          uint64_t out[4];
+          draw_words(opt->seed, opt->stream_id, (uint64_t)(j0 + b),
+                     (uint64_t)m | ((uint64_t)k << 8), t, out);
+          uint64_t v = orc_scale128(out[0], out[1], W[m]);
+          int64_t i = orc_upper_bound(C[m], X->dims[m], v);
+          pr = (u == 0) ? q[m][i] : pr * q[m][i];
+          lin += (uint64_t)i * stride;
+          stride *= (uint64_t)X->dims[m];
+        }
+        blin[b] = lin;
+        bpr[b] = pr;
       }
-      draws++;
-      if (pr <= tau_eff) acc[nacc++] = lin;
+      for (int64_t b = 0; b < nb && nacc < s_rnd; ++b) {
+        draws++;
+        if (bpr[b] <= tau_eff) acc[nacc++] = blin[b];
+      }
     }
+    free(blin);
+    free(bpr);
     if (raw_rnd) memcpy(raw_rnd, acc, sizeof(uint64_t) * nacc);
     int64_t s_rnd_used = nacc;  /* == s_rnd unless the draw guard tripped */
 
@@ -650,32 +750,37 @@ int32_t orc_mode_update(const orc_tensor *X, const orc_index *ix,
     double G[MAXR * MAXR];
     memset(G, 0, sizeof(G));
     int64_t gathered = 0;
-    for (int64_t j = 0; j < sb; ++j) {
-      double z[MAXR];
-      uint64_t rem = idx[j];
-      int64_t im[16];
-      for (int u = 0; u < d; ++u) { im[u] = (int64_t)(rem % (uint64_t)X->dims[O[u]]); rem /= (uint64_t)X->dims[O[u]]; }
-      for (int r = 0; r < R; ++r) {
-        double v = factors[O[0]][im[0] * R + r];
-        for (int u = 1; u < d; ++u) v = v * factors[O[u]][im[u] * R + r];
-        z[r] = v;
-      }
-      double om = omega[j];
-      for (int a = 0; a < R; ++a)
-        for (int b = 0; b < R; ++b) G[a * R + b] = G[a * R + b] + (om * z[a]) * z[b];
-      int64_t pos = lower_bound_u64(ix->key[k], X->nnz, idx[j]);
-      for (; pos < X->nnz && ix->key[k][pos] == idx[j]; ++pos) {
-        int64_t e = ix->id[k][pos];
-        int64_t ik = X->coords[(int64_t)k * X->nnz + e];
-        double ox = om * X->vals[e];
-        for (int r = 0; r < R; ++r) M[ik * R + r] = M[ik * R + r] + ox * z[r];
-        gathered++;
+    if (g_threads > 1) {
+      gathered = sampled_system_threads(X, ix, factors, k, R, d, O, idx, omega, sb, G, M);
+    } else {
+      for (int64_t j = 0; j < sb; ++j) {
+        double z[MAXR];
+        uint64_t rem = idx[j];
+        int64_t im[16];
+        for (int u = 0; u < d; ++u) { im[u] = (int64_t)(rem % (uint64_t)X->dims[O[u]]); rem /= (uint64_t)X->dims[O[u]]; }
+        for (int r = 0; r < R; ++r) {
+          double v = factors[O[0]][im[0] * R + r];
+          for (int u = 1; u < d; ++u) v = v * factors[O[u]][im[u] * R + r];
+          z[r] = v;
+        }
+        double om = omega[j];
+        for (int a = 0; a < R; ++a)
+          for (int b = 0; b < R; ++b) G[a * R + b] = G[a * R + b] + (om * z[a]) * z[b];
+        int64_t pos = lower_bound_u64(ix->key[k], X->nnz, idx[j]);
+        for (; pos < X->nnz && ix->key[k][pos] == idx[j]; ++pos) {
+          int64_t e = ix->id[k][pos];
+          int64_t ik = X->coords[(int64_t)k * X->nnz + e];
+          double ox = om * X->vals[e];
+          for (int r = 0; r < R; ++r) M[ik * R + r] = M[ik * R + r] + ox * z[r];
+          gathered++;
+        }
       }
     }
     st->gathered_nnz = gathered;
     decomp *dc = (decomp *)malloc(sizeof(decomp));
     factorize(G, R, dc);
     if (dc->pinv) st->flags |= ORC_FLAG_PINV;
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
     for (int64_t i = 0; i < nk; ++i) solve_row(dc, M + i * R, factors[k] + i * R);
     free(dc);
     free(M);

@@ -49,6 +49,11 @@ typedef struct {
 
 typedef struct orc_index orc_index;
 
+/* Threads of the oracle's independent loops (default 1); the results do not
+ * depend on the thread count. */
+void orc_set_threads(int32_t n);
+int32_t orc_get_threads(void);
+
 /* Philox4x64-10 block function (Salmon et al., SC'11). */
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 /* floor(U * W / 2^128) for U = u1*2^64 + u0. */

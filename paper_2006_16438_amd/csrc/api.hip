@@ -33,10 +33,11 @@ void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz,
                        void *M, unsigned *bnd, hipStream_t s);
 size_t gather_bkt_count_words();
-void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
-                       const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
-                       i64 nk, i64 max_total, const float *zhat, int ldz, float *M, int grid,
-                       unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s);
+void launch_gather_bkt(bool f64, const DevState *st, int R, const u64 *cpos,
+                       const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
+                       const uint2 *pairs, const int *ik, const double *v64, i64 nk,
+                       i64 max_total, const void *zhat, int ldz, void *M, int grid, unsigned *cnt,
+                       u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s);
 int lev_row_blocks(i64 n);
 void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *total,
                   void *scratch, hipStream_t s);
@@ -798,7 +799,7 @@ void update_front(cpal_ctx *c, int k) {
   c->stage_end(CPAL_STAGE_ROWS, tb);
 }
 
-// The bucketed gather's buffers (FP32 sparse contexts; nonzeros up to nnz).
+// The bucketed gather's buffers (sparse contexts; nonzeros up to nnz).
 cpal_status ensure_bucket_buffers(cpal_ctx *c) {
   if (c->bk_ent) return CPAL_OK;
   try {
@@ -814,7 +815,7 @@ cpal_status ensure_bucket_buffers(cpal_ctx *c) {
 }
 
 bool bucket_capable(const cpal_ctx *c, int k) {
-  return !c->dense && !c->f64 && c->mode[k].n <= (1 << 20);
+  return !c->dense && c->mode[k].n <= (1 << 20);
 }
 
 // The owner gather writes every row of the CPAL_MCOPIES copies of M (sparse
@@ -867,8 +868,8 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
     launch_gather_own(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, md.n,
                       c->zhat, c->ldz, c->M, c->own_bnd, s);
   else if (sort_min == -1 && c->bk_ent && bucket_capable(c, k))
-    launch_gather_bkt(c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs, md.n,
-                      c->nnz, (const float *)c->zhat, c->ldz, (float *)c->M, grid, c->bk_cnt,
+    launch_gather_bkt(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
+                      md.ik, md.v64, md.n, c->nnz, c->zhat, c->ldz, c->M, grid, c->bk_cnt,
                       c->bk_off, c->bk_scan, c->bk_ent, s);
   else if (md.n <= (1 << 20))
     launch_gather_seg(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
@@ -976,9 +977,6 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
     const int dense_grids[] = {c->dnch, std::max(1, c->dnch / 2), std::max(1, c->dnch / 4),
                                std::max(1, c->dnch / 8)};
     const i64 mwords = c->dense ? 0 : (i64)m_copies(md.n) * md.n * c->ldz * (c->f64 ? 2 : 1);
-    // FP64 gathers keep the owner gather: its sums do not depend on timing,
-    // so FP64 updates stay bit-reproducible
-    if (c->f64 && uses_owner(c, k, md.g_sort_min)) continue;
     float best = 1e30f;
     int best_grid = 0, best_sort = 0;
     // the bucketed gather (sort threshold -1) when its buffers can be had,

@@ -409,15 +409,46 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
 #define BK_PER (GT_CHUNK / BK_THREADS)
 #define BK_GRID 1024      // at most
 
-// Calls f(ik, x bits, KRP row) for every position of stream chunk ch (the
-// chunk's fiber starts are staged in win; positions find their fiber there).
-template <typename F>
+// A bucketed nonzero: one 16-byte record {row, KRP row, value} written by a
+// single store (FP32: {row, value bits, KRP row, 0}; FP64: {row, KRP row,
+// value bits low, high}).
+template <typename T>
+struct BktRec;
+template <>
+struct BktRec<float> {
+  static __device__ __forceinline__ uint4 make(int ik, float x, unsigned zr) {
+    return make_uint4((unsigned)ik, __float_as_uint(x), zr, 0u);
+  }
+  static __device__ __forceinline__ void get(const uint4 &v, unsigned &ik, float &x,
+                                             unsigned &zr) {
+    ik = v.x;
+    x = __uint_as_float(v.y);
+    zr = v.z;
+  }
+};
+template <>
+struct BktRec<double> {
+  static __device__ __forceinline__ uint4 make(int ik, double x, unsigned zr) {
+    const u64 b = (u64)__double_as_longlong(x);
+    return make_uint4((unsigned)ik, zr, (unsigned)b, (unsigned)(b >> 32));
+  }
+  static __device__ __forceinline__ void get(const uint4 &v, unsigned &ik, double &x,
+                                             unsigned &zr) {
+    ik = v.x;
+    zr = v.y;
+    x = __longlong_as_double((long long)(((u64)v.w << 32) | v.z));
+  }
+};
+
+// Calls f(ik, x, KRP row) for every position of stream chunk ch (the chunk's
+// fiber starts are staged in win; positions find their fiber there).
+template <typename T, typename F>
 __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
                                          const u64 *__restrict__ cpos,
                                          const unsigned *__restrict__ coff,
                                          const unsigned *__restrict__ cidx,
                                          const unsigned *__restrict__ chunk_first,
-                                         const uint2 *__restrict__ pairs, u64 *win, F &&f) {
+                                         const NzLoad<T> &nz, u64 *win, F &&f) {
   const int tid = threadIdx.x;
   const i64 base = ch * GT_CHUNK;
   const i64 last = min(total, base + GT_CHUNK) - 1;
@@ -436,17 +467,20 @@ __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
       const int mid = (lo + hi) >> 1;
       if (win[mid] <= (u64)p) lo = mid; else hi = mid;
     }
-    const uint2 v = pairs[(u64)coff[jlo + lo] + ((u64)p - win[lo])];
-    f(v.x, v.y, cidx[jlo + lo]);
+    int ik;
+    T x;
+    nz.get((u64)coff[jlo + lo] + ((u64)p - win[lo]), ik, x);
+    f(ik, x, cidx[jlo + lo]);
   }
 }
 
 // Workgroup w takes the consecutive chunks [w cpw, (w + 1) cpw) of the stream
 // in both passes, so its counts and its scatter see the same nonzeros.
+template <typename T>
 __global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
-    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
-    const uint2 *__restrict__ pairs, int bshift, int nb, unsigned *__restrict__ cnt) {
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
+    int bshift, int nb, unsigned *__restrict__ cnt) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned h[BK_BUCKETS];
   const i64 total = st->gathered, nf = st->n_fib;
@@ -455,19 +489,19 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
   const i64 c0 = (i64)blockIdx.x * cpw, c1 = min(nch, c0 + cpw);
   for (int b = threadIdx.x; b < nb; b += BK_THREADS) h[b] = 0u;
   for (i64 ch = c0; ch < c1; ++ch)
-    bk_chunk(ch, nch, total, nf, cpos, coff, cidx, chunk_first, pairs, win,
-             [&](unsigned ik, unsigned, unsigned) { atomicAdd(&h[ik >> bshift], 1u); });
+    bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win,
+                [&](int ik, T, unsigned) { atomicAdd(&h[(unsigned)ik >> bshift], 1u); });
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += BK_THREADS)
     cnt[(i64)b * gridDim.x + blockIdx.x] = h[b];
 }
 
 // off = exclusive scan of cnt in (bucket, workgroup) order.
+template <typename T>
 __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
-    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
-    const uint2 *__restrict__ pairs, int bshift, int nb, const u64 *__restrict__ off,
-    uint4 *__restrict__ bent) {
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
+    int bshift, int nb, const u64 *__restrict__ off, uint4 *__restrict__ bent) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned cur[BK_BUCKETS];
   const i64 total = st->gathered, nf = st->n_fib;
@@ -477,31 +511,31 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
   for (int b = threadIdx.x; b < nb; b += BK_THREADS)
     cur[b] = (unsigned)off[(i64)b * gridDim.x + blockIdx.x];
   for (i64 ch = c0; ch < c1; ++ch)
-    bk_chunk(ch, nch, total, nf, cpos, coff, cidx, chunk_first, pairs, win,
-             [&](unsigned ik, unsigned xb, unsigned zr) {
-               const unsigned pos = atomicAdd(&cur[ik >> bshift], 1u);
-               bent[pos] = make_uint4(ik, xb, zr, 0u);   // one 16-byte store
-             });
+    bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win,
+                [&](int ik, T x, unsigned zr) {
+                  const unsigned pos = atomicAdd(&cur[(unsigned)ik >> bshift], 1u);
+                  bent[pos] = BktRec<T>::make(ik, x, zr);   // one 16-byte store
+                });
 }
 
 // The bucketed nonzeros in chunks of GT_CHUNK: loaded directly, sorted on
 // the low `sortbits` bits of the row (rows of one bucket differ only there;
 // a chunk crossing a bucket boundary merges a little less, nothing else),
 // then reduced as in the segmented gather.
-template <int LPN, int CPL>
+template <typename T, int LPN, int CPL>
 __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
     const DevState *st, int R, const uint4 *__restrict__ bent, int sortbits,
-    const float *__restrict__ zhat, int ldz, float *__restrict__ M, i64 nk) {
+    const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
   constexpr int NG = GT_THREADS / LPN;
   __shared__ unsigned ka[GT_CHUNK], kb[GT_CHUNK];
-  __shared__ float lx[GT_CHUNK];
+  __shared__ T lx[GT_CHUNK];
   __shared__ unsigned lz[GT_CHUNK];
   __shared__ unsigned tab[64 * GT_PER_THREAD * (GT_THREADS / 64)];
   __shared__ int srow[2 * NG];
-  __shared__ float svec[2 * NG][LPN * CPL];
+  __shared__ T svec[2 * NG][LPN * CPL];
   const i64 total = st->gathered;
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
-  float *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * ldz;
+  T *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * ldz;
   const int tid = threadIdx.x;
   for (i64 ch = blockIdx.x; ch < nch; ch += gridDim.x) {
     const i64 base = ch * GT_CHUNK;
@@ -511,17 +545,63 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
     for (int u = 0; u < GT_PER_THREAD; ++u) {
       const int li = u * GT_THREADS + tid;
       const bool valid = base + li <= last;
-      const uint4 v = valid ? bent[base + li] : make_uint4(0u, 0u, 0u, 0u);
-      ka[li] = valid ? ((v.x << 12) | (unsigned)li) : 0xFFFFFFFFu;
-      lx[li] = __uint_as_float(v.y);
-      lz[li] = v.z;
+      unsigned ik = 0, zr = 0;
+      T x = T(0);
+      if (valid) BktRec<T>::get(bent[base + li], ik, x, zr);
+      ka[li] = valid ? ((ik << 12) | (unsigned)li) : 0xFFFFFFFFu;
+      lx[li] = x;
+      lz[li] = zr;
     }
     __syncthreads();
     const unsigned *keys = chunk_radix(ka, kb, tab, sortbits);
     const int nvalid = (int)(last - base + 1);
-    seg_reduce<float, LPN, CPL>(LdsEntries<float>{keys, lx, lz}, nvalid, R, zhat, ldz,
-                                GlobalAdd<float>{Mx, ldz}, srow, svec);
+    seg_reduce<T, LPN, CPL>(LdsEntries<T>{keys, lx, lz}, nvalid, R, zhat, ldz,
+                            GlobalAdd<T>{Mx, ldz}, srow, svec);
   }
+}
+
+size_t gather_bkt_count_words() { return (size_t)BK_BUCKETS * BK_GRID; }
+
+// max_total bounds the stream length (the context's nonzeros): the count and
+// scatter grids are sized from it (about 8 chunks per workgroup, 64 to
+// BK_GRID workgroups) and the buckets from n_k, so that small gathers do not
+// pay for a scan of BK_BUCKETS x BK_GRID counts.
+template <typename T>
+static void launch_gather_bkt_t(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                                const unsigned *cidx, const unsigned *chunk_first, NzLoad<T> nz,
+                                i64 nk, i64 max_total, const T *zhat, int ldz, T *M, int grid,
+                                unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent,
+                                hipStream_t s) {
+  int ikbits = 1;
+  while ((1ll << ikbits) < nk) ++ikbits;
+  const int bshift = ikbits > 12 ? ikbits - 12 : 0;   // row >> bshift < BK_BUCKETS
+  const int nb = (int)((nk + (1ll << bshift) - 1) >> bshift);
+  const i64 chunks = (max_total + GT_CHUNK - 1) / GT_CHUNK;
+  const int gb = (int)std::min<i64>(BK_GRID, std::max<i64>(64, (chunks + 7) / 8));
+  hipLaunchKernelGGL(k_bkt_count<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                     chunk_first, nz, bshift, nb, cnt);
+  scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, nullptr, scan_scratch, s);
+  hipLaunchKernelGGL(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                     chunk_first, nz, bshift, nb, off, bent);
+  const int rm = gather_row_width(R);
+  auto k = rm == 16 ? k_gather_bkt<T, 16, 1>
+                    : rm == 32 ? k_gather_bkt<T, 16, 2> : k_gather_bkt<T, 32, 2>;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, bent, bshift, zhat, ldz, M, nk);
+}
+
+void launch_gather_bkt(bool f64, const DevState *st, int R, const u64 *cpos,
+                       const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
+                       const uint2 *pairs, const int *ik, const double *v64, i64 nk,
+                       i64 max_total, const void *zhat, int ldz, void *M, int grid, unsigned *cnt,
+                       u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s) {
+  if (f64)
+    launch_gather_bkt_t<double>(st, R, cpos, coff, cidx, chunk_first, NzLoad<double>{ik, v64},
+                                nk, max_total, (const double *)zhat, ldz, (double *)M, grid, cnt,
+                                off, scan_scratch, bent, s);
+  else
+    launch_gather_bkt_t<float>(st, R, cpos, coff, cidx, chunk_first, NzLoad<float>{pairs}, nk,
+                               max_total, (const float *)zhat, ldz, (float *)M, grid, cnt, off,
+                               scan_scratch, bent, s);
 }
 
 // ------------------------------------------------------------ owner gather --
@@ -713,32 +793,6 @@ void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
     hipLaunchKernelGGL(k, grid, dim3(GT_THREADS), smem, s, st, R, coff, cidx, bnd, nb, sh, nz,
                        (const float *)zhat, ldz, (float *)M, nk);
   }
-}
-
-size_t gather_bkt_count_words() { return (size_t)BK_BUCKETS * BK_GRID; }
-
-// max_total bounds the stream length (the context's nonzeros): the count and
-// scatter grids are sized from it (about 8 chunks per workgroup, 64 to
-// BK_GRID workgroups) and the buckets from n_k, so that small gathers do not
-// pay for a scan of BK_BUCKETS x BK_GRID counts.
-void launch_gather_bkt(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
-                       const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
-                       i64 nk, i64 max_total, const float *zhat, int ldz, float *M, int grid,
-                       unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s) {
-  int ikbits = 1;
-  while ((1ll << ikbits) < nk) ++ikbits;
-  const int bshift = ikbits > 12 ? ikbits - 12 : 0;   // row >> bshift < BK_BUCKETS
-  const int nb = (int)((nk + (1ll << bshift) - 1) >> bshift);
-  const i64 chunks = (max_total + GT_CHUNK - 1) / GT_CHUNK;
-  const int gb = (int)std::min<i64>(BK_GRID, std::max<i64>(64, (chunks + 7) / 8));
-  hipLaunchKernelGGL(k_bkt_count, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, pairs, bshift, nb, cnt);
-  scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, nullptr, scan_scratch, s);
-  hipLaunchKernelGGL(k_bkt_scatter, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, pairs, bshift, nb, off, bent);
-  const int rm = gather_row_width(R);
-  auto k = rm == 16 ? k_gather_bkt<16, 1> : rm == 32 ? k_gather_bkt<16, 2> : k_gather_bkt<32, 2>;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, bent, bshift, zhat, ldz, M, nk);
 }
 
 int gather_row_width(int R);

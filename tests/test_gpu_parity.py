@@ -283,6 +283,25 @@ def test_bucketed_gather_fp32(case):
                gather_config=(512, -1))
 
 
+@pytest.mark.parametrize("case", ["long_short", "multitile"])
+def test_bucketed_gather_fp64(case):
+    """The bucketed gather in FP64 (16-byte records {row, KRP row, value}),
+    held to the 1e-10 parity bar."""
+    if case == "long_short":
+        dims = (3000, 4, 3)
+        T = synth.random_sparse(dims, 30_000, seed=51)
+        R, s, tau, n = 3, 256, 1 / 256, 6
+        fac = concentrated(dims, R, 52)
+    else:
+        dims = (700, 300, 257)
+        T = synth.random_sparse(dims, 150_000, seed=21)
+        R, s, tau, n = 8, 8192 + 77, 1 / 8192, 6
+        fac = concentrated(dims, R, 22)
+    log(f"bucketed gather FP64, {case}")
+    run_parity(T, fac, R, s, tau, n, "f64", 1e-10, label=f"bucketed64-{case}",
+               gather_config=(512, -1))
+
+
 @pytest.mark.parametrize("case", ["long_short", "multitile", "uber4"])
 def test_owner_gather_fp32(case):
     """The owner gather (no atomic operation: workgroup (row block, fiber
@@ -341,17 +360,20 @@ def test_fp64_updates_bit_reproducible(which):
 
 def test_gather_config_errors():
     """Argument checks of the launch-shape calls: negative grids, sort
-    thresholds below -2, the bucketed gather (-1) in FP64 mode, a dense
-    split beyond the default, modes out of range."""
+    thresholds below -2, a dense split beyond the default, modes out of
+    range; FP64 contexts start on the owner gather (-2)."""
     from paper_2006_16438_amd._lib import CpalError
     T, _, R = synth.small3(0)
     fac = synth.gaussian_factors(T.dims, R, 0)
     ctx, _ = make_ctx(T, fac, R, 1024, gather="f64")
-    for args in ((0, -1, 0), (0, 64, -3), (0, 64, -1), (3, 64, 0), (-1, 64, 0)):
+    for args in ((0, -1, 0), (0, 64, -3), (3, 64, 0), (-1, 64, 0)):
         with pytest.raises(CpalError):
             ctx.set_gather_config(*args)
+    assert ctx.gather_config(0)[1] == -2
     ctx.set_gather_config(0, 64, 4)
     assert ctx.gather_config(0) == (64, 4)
+    ctx.set_gather_config(0, 256, -1)   # the bucketed gather exists in FP64 mode too
+    assert ctx.gather_config(0) == (256, -1)
     ctx.close()
     ctx, _ = make_ctx(T, fac, R, 1024, gather="f32")
     ctx.set_gather_config(1, 256, -1)   # the bucketed gather exists in FP32 mode

@@ -751,3 +751,33 @@ def test_other_distributions_solve_the_sketched_problem(kind):
         rnd = slice(st["s_det"], None)
         assert np.all(p[:st["s_det"]] > 1 / 96) and np.all(p[rnd] <= 1 / 96 * (1 + 1e-12))
         assert abs(np.sum(out["omega"][rnd] * p[rnd]) - (1 - st["p_det"])) < 1e-9
+
+
+def test_threaded_oracle_matches_sequential():
+    """The oracle's threaded loops (blocks of draws, Gram rows, leverage
+    rows, the sampled system summed row by row in sample order, solved rows)
+    give the same bits as the sequential loops: the GPU parity bar never
+    depends on how the oracle was run, and its all-thread timing measures the
+    same computation."""
+    import oracle
+    from paper_2006_16438_amd import synth
+    T = synth.random_sparse((300, 120, 90), 60_000, seed=9)
+    R, s = 7, 2048
+    OT = oracle.Tensor.from_synth(T)
+    fac = synth.gaussian_factors(T.dims, R, 4)
+    runs = []
+    for threads in (1, 4):
+        oracle.set_threads(threads)
+        F = [f.copy() for f in fac]
+        out = []
+        for t in range(6):
+            r = oracle.mode_update(OT, F, t % 3, t, R, s, 1.0 / s)
+            out.append((r["idx"].copy(), r["omega"].copy(), r["stats"]["gathered_nnz"],
+                        r["stats"]["draws"], [f.copy() for f in F]))
+        runs.append(out)
+    oracle.set_threads(1)
+    for a, b in zip(*runs):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert a[2] == b[2] and a[3] == b[3]
+        for fa, fb in zip(a[4], b[4]):
+            assert np.array_equal(fa.view(np.uint64), fb.view(np.uint64))
