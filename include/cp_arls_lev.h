@@ -299,7 +299,28 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_
  * Synchronizes the stream and is not graph-capturable. */
 cpal_status cp_arls_lev_autotune(cpal_ctx *ctx, int32_t reps);
 
-/* Text of the last error on this context (never NULL). */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * leverage scores of the rows of an n x R FP64 row-major matrix A_dev (device
+ * memory), written to lev_dev (n doubles, device memory), computed by the
+ * same kernels and in the same order as the scores a context keeps for its
+ * factor matrices (cp_arls_lev_leverage returns the same bits for the same
+ * matrix).  No context and no allocation: the kernels' scratch (Gram
+ * partials per 256-row block, the decomposition, per-row weights) lives in a
+ * static 16 MiB device array per GPU, held until the process ends, whose
+ * address is looked up on the first call on each GPU.  Work is enqueued on
+ * hip_stream (NULL: the default stream); the caller synchronizes.  Every
+ * call on one GPU shares that array, so calls that overlap on one GPU (on
+ * different streams or host threads) race and must be serialized by the
+ * caller.  CPAL_E_ARG for null pointers, n < 1, R outside [1, 64], or a
+ * matrix whose scratch exceeds the array (about 2^17 rows at R = 64, more at
+ * smaller R); CPAL_E_DEVICE for a launch failure; the message is available
+ * from cp_arls_lev_last_error(NULL) on the calling thread. */
+cpal_status cp_arls_lev_leverage_noalloc(const double *A_dev, int64_t n, int32_t R,
+                                         double *lev_dev, void *hip_stream);
+
+/* Text of the last error on this context (never NULL); with ctx = NULL, the
+ * last error of cp_arls_lev_leverage_noalloc on the calling thread. */
 const char *cp_arls_lev_last_error(const cpal_ctx *ctx);
 
 /* Free everything the library allocated for the context (synchronizes). */

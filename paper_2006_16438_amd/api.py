@@ -69,13 +69,27 @@ def _allocator_arg(allocator, device, stream):
     return allocator, C.byref(allocator.struct)
 
 
-def _check(code, ctx_ptr=None):
+def _check(code, ctx_ptr=None, contextless=False):
     if code != L.CPAL_OK:
         msg = ""
-        if ctx_ptr:
-            m = L.load().cp_arls_lev_last_error(ctx_ptr)
+        if ctx_ptr or contextless:
+            m = L.load().cp_arls_lev_last_error(ctx_ptr if ctx_ptr else None)
             msg = m.decode() if m else ""
         raise L.CpalError(code, msg)
+
+
+def leverage_noalloc(A, out=None, stream=None):
+    """Leverage scores of the rows of a CUDA FP64 n x R matrix through
+    cp_arls_lev_leverage_noalloc (no allocation by the library; the scores a
+    context keeps for the same factor matrix, bit for bit).  out: optional
+    FP64 CUDA tensor of n entries."""
+    assert A.is_cuda and A.dtype == torch.float64 and A.dim() == 2 and A.is_contiguous()
+    if out is None:
+        out = torch.empty(A.shape[0], dtype=torch.float64, device=A.device)
+    code = L.load().cp_arls_lev_leverage_noalloc(A.data_ptr(), int(A.shape[0]), int(A.shape[1]),
+                                                 out.data_ptr(), _stream_ptr(stream))
+    _check(code, None, contextless=True)
+    return out
 
 
 class CpArlsLev:

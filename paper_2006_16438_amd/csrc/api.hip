@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -897,6 +898,101 @@ void update_back(cpal_ctx *c, int k, cpal_mode_stats *stats_dev) {
 
 }  // namespace
 
+// ------------------------------------------------------------------------
+// Scratch of the allocation-free entry point (cp_arls_lev_leverage_noalloc):
+// a file-scope device array, one per GPU, held until the process ends.  In
+// host code `scratch` only names the symbol; its device address on each GPU
+// comes from hipGetSymbolAddress with that GPU current and is used
+// everywhere host code needs the array.
+#define CPAL_NOALLOC_BYTES (16u << 20)
+#define CPAL_NOALLOC_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[CPAL_NOALLOC_BYTES];
+
+namespace {
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[CPAL_NOALLOC_DEVICES] = {};
+
+std::string &noalloc_error() {
+  static thread_local std::string e = "null context";
+  return e;
+}
+
+cpal_status noalloc_fail(cpal_status st, const char *msg) {
+  noalloc_error() = msg;
+  return st;
+}
+
+// The device address of `scratch` on the current GPU, looked up once per GPU.
+cpal_status noalloc_scratch(unsigned char **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= CPAL_NOALLOC_DEVICES)
+    return noalloc_fail(CPAL_E_DEVICE, "leverage_noalloc: no current device");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return noalloc_fail(CPAL_E_DEVICE, "leverage_noalloc: hipGetSymbolAddress failed");
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = (unsigned char *)g_noalloc_ptr[dev];
+  return CPAL_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of scratch the leverage kernels need for an n x R matrix: Gram
+// partials per 256-row block, the decomposition, per-row sampling weights
+// and their block sums, two flags.
+size_t noalloc_bytes(i64 n, int R) {
+  const size_t np = (size_t)R * (R + 1) / 2;
+  const size_t nblk = (size_t)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
+  return align256(nblk * np * sizeof(double)) + align256(sizeof(Decomp)) +
+         align256((size_t)n * sizeof(u64)) + align256((size_t)(lev_row_blocks(n) + 1) * sizeof(u64)) +
+         align256(2 * sizeof(int));
+}
+
+// The leverage computation of a context's factor (Gram, Cholesky or
+// row-space test / pseudo-inverse, per-row scores) on the caller's matrix
+// with every intermediate in the static scratch.  Nothing needs clearing:
+// every scratch word a kernel reads was written earlier in the sequence.
+cpal_status leverage_noalloc(const double *A, i64 n, int R, double *lev, hipStream_t s) {
+  if (!A || !lev || n < 1 || R < 1 || R > CPAL_MAXR)
+    return noalloc_fail(CPAL_E_ARG, "leverage_noalloc: invalid arguments");
+  if (noalloc_bytes(n, R) > CPAL_NOALLOC_BYTES)
+    return noalloc_fail(CPAL_E_ARG, "leverage_noalloc: the matrix needs more scratch than the "
+                                    "16 MiB static array (too many rows for this rank)");
+  unsigned char *base = nullptr;
+  const cpal_status st = noalloc_scratch(&base);
+  if (st != CPAL_OK) return st;
+  const size_t np = (size_t)R * (R + 1) / 2;
+  const int nblk = (int)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
+  size_t off = 0;
+  double *part = (double *)(base + off);
+  off += align256((size_t)nblk * np * sizeof(double));
+  Decomp *dc = (Decomp *)(base + off);
+  off += align256(sizeof(Decomp));
+  u64 *w = (u64 *)(base + off);
+  off += align256((size_t)n * sizeof(u64));
+  u64 *bsum = (u64 *)(base + off);
+  off += align256((size_t)(lev_row_blocks(n) + 1) * sizeof(u64));
+  int *flags = (int *)(base + off);   // [0] full-row-rank skip, [1] pseudo-inverse used
+  const int *skip = nullptr;
+  if (n < R) {
+    launch_lev_rowspace(A, (int)n, R, lev, w, bsum, &flags[0], &flags[1], s);
+    skip = &flags[0];
+  }
+  launch_lev_gram_partial(A, n, R, part, skip, s);
+  launch_decomp(part, nblk, R, dc, &flags[1], skip, s);
+  launch_lev_rows(A, n, R, dc, lev, w, bsum, skip, s);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return noalloc_fail(CPAL_E_DEVICE, hipGetErrorString(e));
+  return CPAL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 cpal_status cp_arls_lev_init(const cpal_tensor *X, const cpal_options *opt,
@@ -1165,8 +1261,13 @@ cpal_status cp_arls_lev_stage_times(cpal_ctx *c, double *ms, int64_t *count, int
 }
 
 const char *cp_arls_lev_last_error(const cpal_ctx *c) {
-  if (!c) return "null context";
+  if (!c) return noalloc_error().c_str();
   return c->err.c_str();
+}
+
+cpal_status cp_arls_lev_leverage_noalloc(const double *A_dev, int64_t n, int32_t R,
+                                         double *lev_dev, void *hip_stream) {
+  return leverage_noalloc(A_dev, n, R, lev_dev, (hipStream_t)hip_stream);
 }
 
 void cp_arls_lev_destroy(cpal_ctx *c) {
