@@ -272,6 +272,23 @@ def mode_update(T: Tensor, factors, k, t, rank, samples, tau=None, seed=0, strea
                 raw=raw[:st.s_rnd].copy(), stats=stats)
 
 
+def rrf_init(T: Tensor, k, s_init, omega, seed=0, stream_id=0):
+    """Randomized range finder initial factor of mode k (App. F): the sum
+    over s_init uniform draws of nonempty mode-k fibers of the fiber times
+    the draw's row of omega (s_init x R, given).  Returns (A, nfib)."""
+    L = lib()
+    L.orc_rrf_init.argtypes = [C.POINTER(_Tensor), C.c_void_p, C.c_int32, C.c_int64,
+                               C.c_void_p, C.c_int32, C.c_uint64, C.c_uint64, C.c_void_p]
+    L.orc_rrf_init.restype = C.c_int64
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    R = omega.shape[1]
+    assert omega.shape[0] >= s_init
+    A = np.zeros((int(T.dims[k]), R))
+    nfib = L.orc_rrf_init(C.byref(T._c), T.index, int(k), int(s_init), omega.ctypes.data, R,
+                          int(seed), int(stream_id), A.ctypes.data)
+    return A, int(nfib)
+
+
 def fit_exact(T: Tensor, factors, rank):
     return float(lib().orc_fit_exact(C.byref(T._c), _fac_ptrs(factors), rank))
 

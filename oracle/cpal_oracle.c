@@ -791,6 +791,45 @@ int32_t orc_mode_update(const orc_tensor *X, const orc_index *ix,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Randomized range finder initialisation (App. F): the columns of A_k are  */
+/* random linear combinations of mode-k fibers.  s_init fibers are drawn    */
+/* uniformly, with replacement, from the fibers holding a nonzero, and      */
+/* A_k = sum_j x_{f_j} Omega(j,:) with Omega (s_init x R, Gaussian) given.  */
+/* Fiber u is the u-th distinct other-mode linear index in ascending order; */
+/* draw j takes u = floor(U nfib / 2^128) from the Philox block at counter  */
+/* (j, k << 8 | 3 << 16, 0, 0).  Returns the number of nonempty fibers.     */
+/* ------------------------------------------------------------------------ */
+int64_t orc_rrf_init(const orc_tensor *X, const orc_index *ix, int32_t k, int64_t s_init,
+                     const double *omega, int32_t R, uint64_t seed, uint64_t stream_id,
+                     double *A) {
+  const int64_t nk = X->dims[k];
+  memset(A, 0, sizeof(double) * (size_t)nk * R);
+  const int64_t nnz = X->nnz;
+  int64_t nfib = 0;
+  for (int64_t e = 0; e < nnz; ++e)
+    if (e == 0 || ix->key[k][e] != ix->key[k][e - 1]) nfib++;
+  if (nfib == 0) return 0;
+  int64_t *start = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nfib + 1));
+  int64_t f = 0;
+  for (int64_t e = 0; e < nnz; ++e)
+    if (e == 0 || ix->key[k][e] != ix->key[k][e - 1]) start[f++] = e;
+  start[nfib] = nnz;
+  for (int64_t j = 0; j < s_init; ++j) {
+    uint64_t out[4];
+    draw_words(seed, stream_id, (uint64_t)j, ((uint64_t)k << 8) | (3ull << 16), 0, out);
+    const int64_t u = (int64_t)orc_scale128(out[0], out[1], (uint64_t)nfib);
+    for (int64_t pos = start[u]; pos < start[u + 1]; ++pos) {
+      const int64_t e = ix->id[k][pos];
+      const int64_t ik = X->coords[(int64_t)k * nnz + e];
+      const double x = X->vals[e];
+      for (int r = 0; r < R; ++r) A[ik * R + r] = A[ik * R + r] + x * omega[j * R + r];
+    }
+  }
+  free(start);
+  return nfib;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Fit (Sec. 6.2 eq. (6.1)) and its stratified estimate (Sec. 6.4).         */
 /* ------------------------------------------------------------------------ */
 double orc_model_entry(int32_t order, double *const *factors, int32_t R,

@@ -107,6 +107,14 @@ double orc_model_entry(int32_t order, double *const *factors, int32_t R,
                        const int32_t *coord);
 /* Exact fit 1 - ||X - M|| / ||X||. */
 double orc_fit_exact(const orc_tensor *X, double *const *factors, int32_t R);
+
+/* Randomized range finder initialisation of mode k (App. F): A (n_k x R) =
+ * the sum over s_init uniform draws of nonempty mode-k fibers of the fiber
+ * times the draw's row of omega (s_init x R).  Returns the number of
+ * nonempty mode-k fibers. */
+int64_t orc_rrf_init(const orc_tensor *X, const orc_index *ix, int32_t k, int64_t s_init,
+                     const double *omega, int32_t R, uint64_t seed, uint64_t stream_id,
+                     double *A);
 /* Stratified fit sample: fills sc [order][cap] (row stride cap), sx, sphi; returns the number
  * of entries written (n_nz + n_zero) or -1 on error. */
 int64_t orc_fit_sample(const orc_tensor *X, uint64_t seed, uint64_t stream_id,

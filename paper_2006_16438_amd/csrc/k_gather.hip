@@ -476,6 +476,7 @@ __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
 
 // Workgroup w takes the consecutive chunks [w cpw, (w + 1) cpw) of the stream
 // in both passes, so its counts and its scatter see the same nonzeros.
+// (The count pass reads the rows only: an NzLoad whose value is never used.)
 template <typename T>
 __global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,

@@ -41,6 +41,7 @@ __device__ __forceinline__ T block_sum(T v) {
 }
 
 #define DET_STAGE 8192
+#define DET_ROWS 8   // candidate test: rows per thread per block scan
 // Reset of the per-update state, maxima alpha_m, candidate lists (Sec. 5.3):
 // row i of mode o_t is a candidate iff the product with every other mode at
 // its maximum exceeds tau.  One block of 1024 threads; the other modes' q
@@ -104,18 +105,27 @@ __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u6
     const double *qs = sq + om.cand_off[t];
     int *out = cand + om.cand_off[t];
     u64 count = 0;
-    for (i64 base = 0; base < n; base += blockDim.x) {
-      const i64 i = base + tid;
-      unsigned pred = 0;
-      if (i < n) {
-        const double qi = staged ? qs[i] : q[i];
-        double b = (t == 0) ? qi : alpha[0];
-        for (int u = 1; u < om.d; ++u) b = b * ((u == t) ? qi : alpha[u]);
-        pred = b > tau;
+    // DET_ROWS consecutive rows per thread per pass: one block scan per
+    // DET_ROWS * blockDim.x rows keeps the candidates in ascending order
+    for (i64 base = 0; base < n; base += (i64)DET_ROWS * blockDim.x) {
+      unsigned pred[DET_ROWS], c = 0;
+#pragma unroll
+      for (int r = 0; r < DET_ROWS; ++r) {
+        const i64 i = base + (i64)tid * DET_ROWS + r;
+        pred[r] = 0;
+        if (i < n) {
+          const double qi = staged ? qs[i] : q[i];
+          double b = (t == 0) ? qi : alpha[0];
+          for (int u = 1; u < om.d; ++u) b = b * ((u == t) ? qi : alpha[u]);
+          pred[r] = b > tau;
+        }
+        c += pred[r];
       }
       unsigned tot;
-      const unsigned ex = block_excl_scan<unsigned>(pred, &tot);
-      if (pred) out[count + ex] = (int)i;
+      unsigned ex = block_excl_scan<unsigned>(c, &tot);
+#pragma unroll
+      for (int r = 0; r < DET_ROWS; ++r)
+        if (pred[r]) out[count + ex++] = (int)(base + (i64)tid * DET_ROWS + r);
       count += tot;
     }
     if (tid == 0) st->ncand[t] = count;

@@ -781,3 +781,46 @@ def test_threaded_oracle_matches_sequential():
         assert a[2] == b[2] and a[3] == b[3]
         for fa, fb in zip(a[4], b[4]):
             assert np.array_equal(fa.view(np.uint64), fb.view(np.uint64))
+
+
+# --------------------------------------------------------- RRF initialisation --
+def _np_philox_block(ctr, key):
+    v = (sum(int(c) << (64 * i) for i, c in enumerate(ctr)) - 1) % (1 << 256)
+    prev = [(v >> (64 * i)) & (2**64 - 1) for i in range(4)]
+    return np.random.Philox(key=np.array(key, dtype=np.uint64),
+                            counter=np.array(prev, dtype=np.uint64)).random_raw(4)
+
+
+@pytest.mark.parametrize("dims,nnz,k", [((9, 7, 5), 60, 0), ((9, 7, 5), 60, 2),
+                                       ((6, 5, 4, 3), 90, 1)])
+def test_rrf_init_matches_independent_recomputation(dims, nnz, k):
+    """App. F: A_k = X_(k)(:, F) Omega for uniform draws F of nonempty
+    fibers, recomputed here without the oracle: fibers from numpy's unique
+    over the other-mode linear indices, draws from numpy's Philox and exact
+    integer arithmetic, dense fiber vectors from the COO entries."""
+    from paper_2006_16438_amd import synth
+    T = synth.random_sparse(dims, nnz, seed=17)
+    OT = oracle.Tensor.from_synth(T)
+    R, s_init, seed, sid = 4, 40, 5, 2
+    omega = np.random.default_rng(3).standard_normal((s_init, R))
+    A, nfib = oracle.rrf_init(OT, k, s_init, omega, seed, sid)
+    others = [m for m in range(len(dims)) if m != k]
+    lin = np.zeros(T.coords.shape[1], dtype=np.int64)
+    stride = 1
+    for m in others:
+        lin += T.coords[m].astype(np.int64) * stride
+        stride *= dims[m]
+    keys = np.unique(lin)
+    assert nfib == keys.size
+    ref = np.zeros((dims[k], R))
+    for j in range(s_init):
+        w = _np_philox_block([j, (k << 8) | (3 << 16), 0, 0], (seed, sid))
+        U = (int(w[1]) << 64) | int(w[0])
+        u = (U * keys.size) >> 128
+        sel = lin == keys[u]
+        fiber = np.zeros(dims[k])
+        fiber[T.coords[k][sel]] = T.values[sel]
+        ref += np.outer(fiber, omega[j])
+    assert np.max(np.abs(A - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    # every column lies in the span of the drawn fibers (range finder)
+    assert np.linalg.matrix_rank(np.hstack([A, ref])) == np.linalg.matrix_rank(ref)
