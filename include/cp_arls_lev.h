@@ -299,6 +299,23 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_
  * Synchronizes the stream and is not graph-capturable. */
 cpal_status cp_arls_lev_autotune(cpal_ctx *ctx, int32_t reps);
 
+/* Randomized range finder initialisation (App. F): overwrites every factor
+ * matrix (the caller's buffers given at init) with A_k = the sum over s_init
+ * draws of a mode-k fiber times that draw's row of omega_dev[k]; the fibers
+ * are drawn uniformly with replacement from the fibers holding a nonzero
+ * (every fiber of a dense tensor), fiber u being the u-th in ascending
+ * linear index of its other-mode coordinates and u = floor(U nfib / 2^128)
+ * for the Philox4x64-10 block at counter (j, k << 8 | 3 << 16, 0, 0) under
+ * the context's (seed, stream_id).  omega_dev: host array of order device
+ * pointers, each an s_init x R FP64 row-major matrix (the caller's Gaussian
+ * draws).  The products and sums run through the mode's gather in its
+ * precision and launch shape; leverage scores and FP32 mirrors are
+ * refreshed, the step counter is unchanged.  Allocates (and frees) the
+ * fiber lists of the largest mode through the context's provider and
+ * synchronizes the stream.  CPAL_E_ARG: s_init outside [1, samples], null
+ * pointers; CPAL_E_NOMEM; CPAL_E_DEVICE. */
+cpal_status cp_arls_lev_rrf_init(cpal_ctx *ctx, int64_t s_init, const double *const *omega_dev);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
  * leverage scores of the rows of an n x R FP64 row-major matrix A_dev (device

@@ -22,7 +22,7 @@ FLAG_PINV, FLAG_DETCAP, FLAG_DET_TRUNC, FLAG_PDET_ONE, FLAG_DRAWCAP, FLAG_OVERFL
 SYMBOLS = (
     "cp_arls_lev_init", "cp_arls_lev_mode_update", "cp_arls_lev_fit_estimate",
     "cp_arls_lev_samples", "cp_arls_lev_leverage", "cp_arls_lev_refresh",
-    "cp_arls_lev_leverage_noalloc",
+    "cp_arls_lev_leverage_noalloc", "cp_arls_lev_rrf_init",
     "cp_arls_lev_get_step", "cp_arls_lev_set_step", "cp_arls_lev_set_timing",
     "cp_arls_lev_stage_times", "cp_arls_lev_last_error", "cp_arls_lev_destroy",
     "cp_arls_lev_init_batch", "cp_arls_lev_mode_step_batch", "cp_arls_lev_fit_estimate_batch",
@@ -100,6 +100,8 @@ def load(path: str | None = None):
     L.cp_arls_lev_samples.restype = C.c_int
     L.cp_arls_lev_leverage.argtypes = [vp, C.c_int32, vp]
     L.cp_arls_lev_leverage.restype = C.c_int
+    L.cp_arls_lev_rrf_init.argtypes = [vp, C.c_int64, C.POINTER(vp)]
+    L.cp_arls_lev_rrf_init.restype = C.c_int
     L.cp_arls_lev_leverage_noalloc.argtypes = [vp, C.c_int64, C.c_int32, vp, vp]
     L.cp_arls_lev_leverage_noalloc.restype = C.c_int
     L.cp_arls_lev_refresh.argtypes = [vp, C.c_int32]

@@ -230,6 +230,18 @@ class CpArlsLev:
         _check(L.load().cp_arls_lev_autotune(self._ctx, int(reps)), self._ctx)
         return [self.gather_config(k) for k in range(self.order)]
 
+    def rrf_init(self, s_init, omega):
+        """Randomized range finder initialisation (App. F): every factor is
+        overwritten by a random linear combination of s_init uniformly drawn
+        nonempty fibers, omega[k] (a CUDA FP64 s_init x R tensor per mode)
+        holding the combination weights."""
+        assert len(omega) == self.order
+        for o in omega:
+            assert o.is_cuda and o.dtype == torch.float64 and o.is_contiguous()
+            assert o.shape[0] >= s_init and o.shape[1] == self.rank
+        ptrs = (C.c_void_p * self.order)(*[o.data_ptr() for o in omega])
+        _check(L.load().cp_arls_lev_rrf_init(self._ctx, int(s_init), ptrs), self._ctx)
+
     def fit_estimate(self, out=None):
         if out is None:
             out = torch.empty(1, dtype=torch.float64, device=self.values.device)

@@ -29,6 +29,15 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
                        int grid, int sort_min, hipStream_t s);
 void launch_zero_words(void *p, i64 nwords, hipStream_t s);
 int gather_own_blocks(bool f64, int ldz, i64 nk);
+void launch_fiber_list(const FiberSlot *slots, u64 nslots, u64 *off, unsigned *len,
+                       unsigned long long *count, hipStream_t s);
+void launch_rrf_rows(int zdt, DevState *st, i64 s_init, int k, u64 seed, u64 stream_id, u64 nfib,
+                     const u64 *fib_off, const unsigned *fib_len, unsigned dense_len,
+                     const double *omega, int R, int ldz, void *zhat, unsigned *foff,
+                     unsigned *flen, u64 *samp_idx, u64 *part_len, unsigned *part_cnt,
+                     unsigned *part_act, int rows_per_blk, hipStream_t s);
+void launch_rrf_store(bool f64, const void *M, int ncopies, i64 nk, int R, int ldz, double *A,
+                      float *A32, hipStream_t s);
 void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
                        const unsigned *coff, const unsigned *cidx, const uint2 *pairs,
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz,
@@ -1192,6 +1201,61 @@ cpal_status cp_arls_lev_run(cpal_ctx *c, const cpal_run_options *ro, double *tra
   hipMemcpyAsync(&fx, c->fit_host_buf, sizeof(double), hipMemcpyDeviceToHost, c->stream);
   const cpal_status st = check_hip(c, hipStreamSynchronize(c->stream), "run: final fit");
   res->final_exact_fit = fx;
+  return st;
+}
+
+cpal_status cp_arls_lev_rrf_init(cpal_ctx *c, int64_t s_init, const double *const *omega_dev) {
+  if (!c || !omega_dev || s_init < 1 || s_init > c->s) return CPAL_E_ARG;
+  for (int k = 0; k < c->D; ++k)
+    if (!omega_dev[k]) return CPAL_E_ARG;
+  if (c->failed) return fail(c, CPAL_E_STATE, "context failed earlier");
+  hipStream_t s = c->stream;
+  u64 *off = nullptr, *off_t = nullptr;
+  unsigned *len = nullptr, *len_t = nullptr;
+  unsigned long long *cnt = nullptr;
+  u64 maxfib = 0;
+  for (int k = 0; k < c->D; ++k) maxfib = std::max<u64>(maxfib, c->mode[k].nfib);
+  if (!c->dense) {   // the nonempty fibers of each mode in ascending key order
+    off = (u64 *)c->raw_alloc(sizeof(u64) * maxfib);
+    off_t = (u64 *)c->raw_alloc(sizeof(u64) * maxfib);
+    len = (unsigned *)c->raw_alloc(sizeof(unsigned) * maxfib);
+    len_t = (unsigned *)c->raw_alloc(sizeof(unsigned) * maxfib);
+    cnt = (unsigned long long *)c->raw_alloc(sizeof(unsigned long long));
+    if (!off || !off_t || !len || !len_t || !cnt) {
+      c->raw_free(off); c->raw_free(off_t); c->raw_free(len); c->raw_free(len_t); c->raw_free(cnt);
+      return fail(c, CPAL_E_NOMEM, "rrf_init: fiber lists");
+    }
+  }
+  for (int k = 0; k < c->D; ++k) {
+    Mode &md = c->mode[k];
+    u64 nfib = 0;
+    if (c->dense) {
+      nfib = 1;
+      for (int m = 0; m < c->D; ++m)
+        if (m != k) nfib *= (u64)c->dims[m];
+    } else {
+      nfib = md.nfib;
+      hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s);
+      launch_fiber_list(md.slots, md.nslots, off, len, cnt, s);
+      sort_keys(off, len, off_t, len_t, c->sort_scratch, (i64)nfib, nullptr, (i64)nfib,
+                bits_for((u64)c->nnz + 1), s);
+    }
+    launch_rrf_rows(c->zdt, c->st, s_init, k, c->seed, c->stream_id, nfib, c->dense ? nullptr : off,
+                    c->dense ? nullptr : len, (unsigned)md.n, omega_dev[k], c->R, c->ldz, c->zhat,
+                    c->foff, c->flen, c->samp_idx, c->gp_len, c->gp_cnt, c->gp_act,
+                    rows_per_block(), s);
+    launch_gather_prep(c->st, c->flen, c->foff, s_init, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
+                       c->coff, c->cidx, c->chunk_first, c->tpos, c->dtab, s);
+    const int ncopies = c->dense ? 1 : (int)m_copies(md.n);
+    if (!c->dense && !uses_owner(c, k, md.g_sort_min))
+      launch_zero_words(c->M, (i64)ncopies * md.n * c->ldz * (c->f64 ? 2 : 1), s);
+    update_gather(c, k, md.g_grid, md.g_sort_min);
+    launch_rrf_store(c->f64, c->M, ncopies, md.n, c->R, c->ldz, md.A, md.A32, s);
+    refresh_leverage(c, k);
+  }
+  const cpal_status st = check_hip(c, hipStreamSynchronize(s), "rrf_init");
+  c->raw_free(off); c->raw_free(off_t); c->raw_free(len); c->raw_free(len_t); c->raw_free(cnt);
+  c->samples_valid = false;   // the sampled-system buffers hold the last mode's draws
   return st;
 }
 
