@@ -16,6 +16,10 @@ stand in for them):
 * ``planted`` -- any shape, every entry stored (dense as COO) or a random
   subset, planted rank-R model plus relative Gaussian noise; used for
   recovery tests.
+* ``coherent`` -- the dense tensor of App. C: N(0,1) factors whose first
+  three columns are zero except `spread` rows each (distinct rows, value
+  `magnitude` + U(0, jitter)), so that a few rows carry most of the leverage;
+  the rank-R model plus relative Gaussian noise, every entry stored.
 
 Zipf(a) on {0..n-1}: P(i) proportional to (i+1)^-a, then mapped through a
 seeded random permutation so that hot indices are scattered.  Distinct
@@ -180,6 +184,42 @@ def planted(dims, rank: int, seed: int = 0, density: float = 1.0,
     clean = _model_at(fac, coords)
     g = rng.standard_normal(lin.size)
     vals = clean + rel_noise * (np.linalg.norm(clean) / np.linalg.norm(g)) * g
+    return SparseTensor(tuple(int(n) for n in dims), coords, vals), fac
+
+
+def coherent_factors(rng, dims, rank: int, spread: int = 5, magnitude: float = 3.0,
+                     jitter: float = 0.05):
+    """Factor matrices of App. C: N(0,1) entries; columns 0, 1, 2 zeroed, then
+    column c gets magnitude + U(0, jitter) in rows [c spread, (c+1) spread)
+    (every row has at most one nonzero among the three columns)."""
+    fac = []
+    for n in dims:
+        a = rng.standard_normal((int(n), rank))
+        a[:, :min(3, rank)] = 0.0
+        for c in range(min(3, rank)):
+            rows = slice(c * spread, (c + 1) * spread)
+            a[rows, c] = magnitude + jitter * rng.random(spread)
+        fac.append(a)
+    return fac
+
+
+def coherent(dims, rank: int = 25, spread: int = 5, magnitude: float = 3.0,
+             jitter: float = 0.05, noise: float = 0.05, seed: int = 0):
+    """App. C's dense test tensor on any shape: the rank-`rank` model of
+    coherent_factors plus noise * ||X0|| / ||G|| * G, G ~ N(0,1); every entry
+    stored, in linear order with mode 0 fastest.  Returns (tensor, factors)."""
+    rng = np.random.default_rng([seed, 5])
+    fac = coherent_factors(rng, dims, rank, spread, magnitude, jitter)
+    total = int(np.prod(dims))
+    lin = np.arange(total, dtype=np.int64)
+    coords = np.empty((len(dims), total), dtype=np.int32)
+    rem = lin
+    for m, n in enumerate(dims):
+        coords[m] = rem % n
+        rem = rem // n
+    clean = _model_at(fac, coords)
+    g = rng.standard_normal(total)
+    vals = clean + noise * (np.linalg.norm(clean) / np.linalg.norm(g)) * g
     return SparseTensor(tuple(int(n) for n in dims), coords, vals), fac
 
 

@@ -156,3 +156,28 @@ def dense_planted(n, rank, seed, noise=0.01):
     X.add_(E, alpha=noise * (X.norm() / E.norm()).item())
     del E
     return X
+
+
+def coherent_dense(n=500, rank=25, spread=5, magnitude=3.0, jitter=0.05, noise=0.05, seed=0):
+    """App. C's n^3 dense tensor on the GPU (FP32, indexed [i0, i1, i2]):
+    N(0,1) factors whose first three columns are zero except `spread` rows
+    each (column c: rows [c spread, (c+1) spread), value magnitude +
+    U(0, jitter)), the rank-`rank` model plus noise * ||X0|| / ||G|| * G.
+    Returns (X, factors) with the factors as FP64 CPU tensors."""
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    dev = torch.device("cuda:0")
+    A = []
+    for _ in range(3):
+        a = torch.randn(n, rank, generator=g, device=dev, dtype=torch.float64)
+        a[:, :min(3, rank)] = 0.0
+        for c in range(min(3, rank)):
+            a[c * spread:(c + 1) * spread, c] = magnitude + jitter * torch.rand(
+                spread, generator=g, device=dev, dtype=torch.float64)
+        A.append(a)
+    Af = [a.float() for a in A]
+    X = torch.einsum("ir,jr,kr->ijk", Af[0], Af[1], Af[2])
+    E = torch.randn(X.shape, generator=g, device=dev)
+    X.add_(E, alpha=noise * (X.norm() / E.norm()).item())
+    del E
+    return X, [a.cpu() for a in A]

@@ -824,3 +824,23 @@ def test_rrf_init_matches_independent_recomputation(dims, nnz, k):
     assert np.max(np.abs(A - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
     # every column lies in the span of the drawn fibers (range finder)
     assert np.linalg.matrix_rank(np.hstack([A, ref])) == np.linalg.matrix_rank(ref)
+
+
+def test_coherent_generator_concentrates_leverage():
+    """App. C's generator: in every factor the 3 x spread seeded rows carry
+    the leverage of the three sparse columns (each seeded row >= 1/spread up
+    to the Gaussian columns' share), while a Gaussian row of an n x R
+    matrix has leverage about R/n; the tensor holds every entry."""
+    import oracle
+    from paper_2006_16438_amd import synth
+    dims, R, spread = (60, 50, 40), 6, 3
+    T, fac = synth.coherent(dims, R, spread=spread, seed=1)
+    assert T.coords.shape[1] == int(np.prod(dims))
+    for A in fac:
+        lev, _ = oracle.leverage(A)
+        seeded = lev[:3 * spread]
+        rest = lev[3 * spread:]
+        assert np.all(seeded >= 1.0 / spread - 0.05)
+        assert np.sum(seeded) >= 3.0 - 0.1
+        assert np.max(rest) < np.min(seeded)
+        assert np.all(A[3 * spread:, :3] == 0.0)
