@@ -377,7 +377,8 @@ void refresh_leverage(cpal_ctx *c, int m, cpal_mode_stats *stats = nullptr) {
   }
   launch_lev_gram_partial(md.A, md.n, c->R, c->lev_part, skip, c->stream);
   const int nblk = (int)((md.n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
-  launch_decomp(c->lev_part, nblk, c->R, c->dc, &c->st->lev_pinv[m], skip, c->stream);
+  launch_decomp_blocks(c->lev_part, nblk, c->R, c->gram_tmp, c->dc, &c->st->lev_pinv[m], skip,
+                       c->stream);
   launch_lev_rows(md.A, md.n, c->R, c->dc, md.lev, md.w, c->lev_bsum, skip, c->stream);
   launch_lev_cdf(md.w, md.n, c->R, c->lev_bsum, md.C, md.q, nullptr, c->st, m, c->D, stats,
                  c->stream);
@@ -580,8 +581,10 @@ cpal_status init_impl(const cpal_tensor *X, const cpal_options *opt, double *con
     c->fit_host_buf = c->alloc<double>(1);
     // gather stream length: at most nnz (sparse), s * max n_m (dense)
     c->chunk_first = c->alloc<unsigned>(gather_chunks_cap(dense ? s * maxn : c->nnz));
-    if (dense) {   // sampled fibers per workgroup of the dense contraction: <= 256 partials
-      i64 kc = ((s + 255) / 256 + 15) / 16 * 16;
+    if (dense) {   // sampled fibers per workgroup of the dense contraction: <= 256
+      // partials (BF16, whose row blocks are 4x shorter: <= 64 partials)
+      const i64 parts = c->zdt == CPAL_BF16 ? 64 : 256;
+      i64 kc = ((s + parts - 1) / parts + 31) / 32 * 32;
       kc = std::min<i64>(std::max<i64>(kc, 64), 1024);
       c->dkc = (int)kc;
       c->dnch = (int)((s + kc - 1) / kc);
@@ -769,10 +772,10 @@ int default_gather_grid(const cpal_ctx *c, int k) {
 
 // Dense contraction with `nch` workgroups along the sampled fibers (at most
 // the c->dnch the partials are sized for): sampled fibers per workgroup, a
-// multiple of 16.
+// multiple of 32.
 int dense_kc(const cpal_ctx *c, int nch) {
   if (nch <= 0 || nch > c->dnch) nch = c->dnch;
-  i64 kc = ((c->s + nch - 1) / nch + 15) / 16 * 16;
+  i64 kc = ((c->s + nch - 1) / nch + 31) / 32 * 32;
   return (int)std::min<i64>(std::max<i64>(kc, c->dkc), 1024);
 }
 
@@ -953,13 +956,13 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Bytes of scratch the leverage kernels need for an n x R matrix: Gram
 // partials per 256-row block, the decomposition, per-row sampling weights
-// and their block sums, two flags.
+// and their block sums, the summed Gram matrix, two flags.
 size_t noalloc_bytes(i64 n, int R) {
   const size_t np = (size_t)R * (R + 1) / 2;
   const size_t nblk = (size_t)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
   return align256(nblk * np * sizeof(double)) + align256(sizeof(Decomp)) +
          align256((size_t)n * sizeof(u64)) + align256((size_t)(lev_row_blocks(n) + 1) * sizeof(u64)) +
-         align256(2 * sizeof(int));
+         align256(np * sizeof(double)) + align256(2 * sizeof(int));
 }
 
 // The leverage computation of a context's factor (Gram, Cholesky or
@@ -986,6 +989,8 @@ cpal_status leverage_noalloc(const double *A, i64 n, int R, double *lev, hipStre
   off += align256((size_t)n * sizeof(u64));
   u64 *bsum = (u64 *)(base + off);
   off += align256((size_t)(lev_row_blocks(n) + 1) * sizeof(u64));
+  double *gram = (double *)(base + off);
+  off += align256(np * sizeof(double));
   int *flags = (int *)(base + off);   // [0] full-row-rank skip, [1] pseudo-inverse used
   const int *skip = nullptr;
   if (n < R) {
@@ -993,7 +998,7 @@ cpal_status leverage_noalloc(const double *A, i64 n, int R, double *lev, hipStre
     skip = &flags[0];
   }
   launch_lev_gram_partial(A, n, R, part, skip, s);
-  launch_decomp(part, nblk, R, dc, &flags[1], skip, s);
+  launch_decomp_blocks(part, nblk, R, gram, dc, &flags[1], skip, s);
   launch_lev_rows(A, n, R, dc, lev, w, bsum, skip, s);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return noalloc_fail(CPAL_E_DEVICE, hipGetErrorString(e));

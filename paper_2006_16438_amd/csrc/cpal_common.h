@@ -268,6 +268,8 @@ void launch_lev_rowspace(const double *A, int n, int R, double *lev, u64 *w, u64
                          int *skip, int *pinv_store, hipStream_t s);
 void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_store,
                    const int *skip, hipStream_t s);
+void launch_decomp_blocks(const double *part, int nblk, int R, double *gram, Decomp *out,
+                          int *flag_store, const int *skip, hipStream_t s);
 void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *lev, u64 *w,
                      u64 *blocksum, const int *skip, hipStream_t s);
 void launch_lev_cdf(const u64 *w, i64 n, int R, const u64 *blocksum, u64 *C, double *q,

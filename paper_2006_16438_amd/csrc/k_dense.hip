@@ -4,8 +4,8 @@
 // product: the rows of the sampled system are whole mode-k fibers, so
 //   M = X~^T diag(omega) Z   (n_k x R, inner dimension = the sampled rows)
 // runs on the matrix cores with BF16 inputs and FP32 accumulation
-// (v_mfma_f32_16x16x16_bf16), in FP32 (v_mfma_f32_16x16x4_f32) or in FP64
-// (v_mfma_f64_16x16x4_f64).
+// (v_mfma_f32_16x16x32_bf16, 32 sampled fibers per instruction), in FP32
+// (v_mfma_f32_16x16x4_f32) or in FP64 (v_mfma_f64_16x16x4_f64).
 #include "cpal_common.h"
 
 namespace cpal {
@@ -86,19 +86,23 @@ void launch_dense_copy(const void *vals, int vdt, const i64 *dims, int D, int k,
 // ------------------------------------------------------ sampled contraction
 // Workgroup (c, y) takes the sampled fibers [c kc, (c+1) kc) of the compacted
 // list (slot cidx, fiber samp_idx[slot]) and the rows [y RB, (y+1) RB) of
-// M.  Groups of 16 fibers are staged in shared memory (16-byte loads; the
-// next group's loads are in flight during the current group's products)
-// with the group's weighted KRP rows (zhat, omega z in the gather
-// precision).  Wave w owns TW row tiles of 16; every tile meets NR column
-// tiles of 16 (R <= 16 NR).  Operand layouts (lane l, g = l / 16):
+// M.  Groups of KG fibers (128 in BF16, 16 otherwise) are staged in shared
+// memory (16-byte loads; the next group's loads are in flight during the
+// current group's products) with the group's weighted KRP rows (zhat, omega
+// z in the gather precision).  Wave w owns TW row tiles of 16; every tile
+// meets NR column tiles of 16 (R <= 16 NR).  Operand layouts (lane l,
+// g = l / 16); A and B take the fibers of one instruction in the same
+// lane/element order, so the product sums each fiber once:
 //   A(i, k) = fiber k at row i: lane l has row l % 16 and fibers
-//             4g..4g+3 (BF16) or fiber g of each step of 4 (FP32, FP64);
+//             8g..8g+7 of each step of 32 (BF16) or fiber g of each step
+//             of 4 (FP32, FP64);
 //   B(k, j) = zhat(fiber k, column j), the same k assignment, j = l % 16;
 //   D(i, j): lane 16 (i / 4) + j, element i % 4 (BF16, FP32);
 //            lane 16 (i % 4) + j, element i / 4 (FP64).
 // The workgroup's partial M goes to part[c] (n_k x ldz); k_dense_reduce sums
 // the partials in workgroup order.
-typedef short s4v __attribute__((ext_vector_type(4)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 
@@ -128,13 +132,14 @@ __global__ void __launch_bounds__(DN_THREADS) k_dense_mttkrp(
     const typename P::TX *__restrict__ zhat, typename P::TA *__restrict__ part, int kc) {
   typedef typename P::TX TX;
   typedef typename P::AV AV;
+  constexpr int KG = sizeof(TX) == 2 ? 128 : 16;        // fibers per group
   constexpr int RB = 4 * TW * 16;                     // rows per workgroup
   constexpr int NC = 16 * NR;                         // columns covered
   constexpr int E = 16 / (int)sizeof(TX);             // elements per 16-byte load
-  constexpr int NV = 16 * RB / E / DN_THREADS;        // loads per thread and group
-  static_assert(NV * E * DN_THREADS == 16 * RB, "staging must tile the group");
-  __shared__ __attribute__((aligned(16))) TX sX[16][RB];
-  __shared__ TX sZ[16][NC];
+  constexpr int NV = KG * RB / E / DN_THREADS;        // loads per thread and group
+  static_assert(NV * E * DN_THREADS == KG * RB, "staging must tile the group");
+  __shared__ __attribute__((aligned(16))) TX sX[KG][RB];
+  __shared__ TX sZ[KG][NC];
   __shared__ u64 slin[DN_KCMAX];
   __shared__ unsigned sslot[DN_KCMAX];
   const i64 nf = st->n_fib;
@@ -168,19 +173,19 @@ __global__ void __launch_bounds__(DN_THREADS) k_dense_mttkrp(
     }
   };
   load_group(0);
-  for (int q0 = 0; q0 < nfc; q0 += 16) {
+  for (int q0 = 0; q0 < nfc; q0 += KG) {
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
       const int v = u * DN_THREADS + tid;
       const int q = v / (RB / E), e0 = (v % (RB / E)) * E;
       *(uint4 *)(&sX[q][e0]) = pre[u];
     }
-    for (int e = tid; e < 16 * NC; e += DN_THREADS) {
+    for (int e = tid; e < KG * NC; e += DN_THREADS) {
       const int q = e / NC, c = e - q * NC;
       sZ[q][c] = (q0 + q < nfc && c < ldz) ? zhat[(i64)sslot[q0 + q] * ldz + c] : TX(0);
     }
     __syncthreads();
-    if (q0 + 16 < nfc) load_group(q0 + 16);
+    if (q0 + KG < nfc) load_group(q0 + KG);
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
       const int row = (wid * TW + t) * 16 + (lane & 15);
@@ -188,13 +193,18 @@ __global__ void __launch_bounds__(DN_THREADS) k_dense_mttkrp(
       for (int n = 0; n < NR; ++n) {
         const int col = n * 16 + (lane & 15);
         if constexpr (sizeof(TX) == 2) {
-          s4v a, b;
 #pragma unroll
-          for (int p = 0; p < 4; ++p) {
-            a[p] = (short)sX[4 * g + p][row];
-            b[p] = (short)sZ[4 * g + p][col];
+          for (int kk = 0; kk < KG / 32; ++kk) {   // 32 fibers per instruction
+            s8v a, b;
+#pragma unroll
+            for (int p = 0; p < 8; ++p) {
+              a[p] = (short)sX[32 * kk + 8 * g + p][row];
+              b[p] = (short)sZ[32 * kk + 8 * g + p][col];
+            }
+            acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a),
+                                                                __builtin_bit_cast(bf8v, b),
+                                                                acc[t][n], 0, 0, 0);
           }
-          acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t][n], 0, 0, 0);
         } else if constexpr (sizeof(TX) == 4) {
 #pragma unroll
           for (int s = 0; s < 4; ++s)
@@ -260,10 +270,10 @@ __global__ void __launch_bounds__(256) k_dense_reduce(const DevState *st, i64 nk
 // (memory parallelism for the fiber stream) at no cost in partials, which
 // are kept per row.
 static int dense_tw(int xdt, int nr) {
+  if (xdt == CPAL_BF16) return 1;   // 128 fibers x 64 rows: four 16-byte loads per thread
   int tw = (xdt == CPAL_F64 ? 2 : 4) / nr;
   while (tw & (tw - 1)) tw &= tw - 1;
-  const int tw_min = xdt == CPAL_BF16 ? 2 : 1;   // 16 fibers x 64 TW rows >= one load per thread
-  return std::max(tw_min, tw);
+  return std::max(1, tw);
 }
 
 int dense_rows_per_block(int xdt, int R) { return 64 * dense_tw(xdt, (R + 15) / 16); }
@@ -293,11 +303,11 @@ static void launch_dense_p(const DevState *st, i64 nk, int R, int ldz, i64 ldx,
     else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
     else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
     else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-  } else {
-    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 4>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+  } else {   // BF16: one row tile per wave (dense_tw)
+    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
   }
 }
 

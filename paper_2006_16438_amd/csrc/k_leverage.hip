@@ -656,6 +656,42 @@ void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_s
                      out, (int *)nullptr, flag_store, skip);
 }
 
+// The Gram matrix of a factor from its block partials in the canonical order
+// (the partials of the 256-row blocks added one after another, ascending,
+// starting from zero), one thread per packed entry: the same sums k_decomp
+// forms in one wave, for factors with many blocks.
+__global__ void __launch_bounds__(256) k_gram_seq(const double *__restrict__ part, int nblk, int np,
+                                                  double *__restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  double acc = 0.0;
+  int b = 0;
+  for (; b + 4 <= nblk; b += 4) {
+    const double v0 = part[(i64)b * np + p], v1 = part[(i64)(b + 1) * np + p];
+    const double v2 = part[(i64)(b + 2) * np + p], v3 = part[(i64)(b + 3) * np + p];
+    acc = acc + v0;
+    acc = acc + v1;
+    acc = acc + v2;
+    acc = acc + v3;
+  }
+  for (; b < nblk; ++b) acc = acc + part[(i64)b * np + p];
+  out[p] = acc;
+}
+
+// Decomposition of a factor's Gram matrix from nblk block partials; with many
+// blocks the partials are first summed by k_gram_seq into gram (np doubles).
+void launch_decomp_blocks(const double *part, int nblk, int R, double *gram, Decomp *out,
+                          int *flag_store, const int *skip, hipStream_t s) {
+  const int np = R * (R + 1) / 2;
+  if (nblk > 64 && gram) {
+    hipLaunchKernelGGL(k_gram_seq, dim3((np + 255) / 256), dim3(256), 0, s, part, nblk, np, gram);
+    part = gram;
+    nblk = 1;
+  }
+  hipLaunchKernelGGL(k_decomp, dim3(1), dim3(64), 0, s, part, nblk, (const i64 *)nullptr, 1, R,
+                     out, (int *)nullptr, flag_store, skip);
+}
+
 void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_blk, int R,
                        Decomp *out, int *flag_or, double *gram_tmp, hipStream_t s) {
   const int np = R * (R + 1) / 2;

@@ -48,6 +48,20 @@ def test_leverage_noalloc_matches_context_leverage():
     ctx.close()
 
 
+def test_leverage_noalloc_many_gram_blocks_matches_oracle():
+    """A 40,000-row factor (157 Gram blocks: the partials are summed by a
+    separate kernel in the canonical order) gives the oracle's leverage
+    scores bit for bit, twice in a row, then a smaller matrix."""
+    import oracle
+    rng = np.random.default_rng(12)
+    for n, R in ((40_000, 25), (40_000, 25), (3000, 7)):
+        A = rng.standard_normal((n, R))
+        got = leverage_noalloc(torch.from_numpy(A).cuda())
+        torch.cuda.synchronize()
+        ref, _ = oracle.leverage(A)
+        assert np.array_equal(_bits(got), ref.view(np.uint64)), (n, R)
+
+
 def test_leverage_noalloc_rejects_oversized_matrix():
     A = torch.zeros((4, 64), dtype=torch.float64, device="cuda:0")
     out = torch.zeros(4, dtype=torch.float64, device="cuda:0")
