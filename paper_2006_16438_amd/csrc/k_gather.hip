@@ -458,20 +458,35 @@ __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
   __syncthreads();   // the previous chunk is finished with win
   for (int e = tid; e < nwin; e += BK_THREADS) win[e] = cpos[jlo + e];
   __syncthreads();
-#pragma unroll 2
+  // all BK_PER positions of the thread are located first, then every load
+  // is issued before any is used (positions past the chunk are clamped to
+  // its last one and skipped at the end)
+  int jw[BK_PER];
+  u64 pp[BK_PER];
+#pragma unroll
   for (int u = 0; u < BK_PER; ++u) {
-    const i64 p = base + (i64)u * BK_THREADS + tid;
-    if (p > last) break;   // positions grow with u
+    const u64 p = (u64)min(base + (i64)u * BK_THREADS + tid, last);
     int lo = 0, hi = nwin;   // last index with win[idx] <= p
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
-      if (win[mid] <= (u64)p) lo = mid; else hi = mid;
+      if (win[mid] <= p) lo = mid; else hi = mid;
     }
-    int ik;
-    T x;
-    nz.get((u64)coff[jlo + lo] + ((u64)p - win[lo]), ik, x);
-    f(ik, x, cidx[jlo + lo]);
+    jw[u] = lo;
+    pp[u] = p - win[lo];
   }
+  unsigned zr[BK_PER];
+#pragma unroll
+  for (int u = 0; u < BK_PER; ++u) {
+    pp[u] += coff[jlo + jw[u]];
+    zr[u] = cidx[jlo + jw[u]];
+  }
+  int ik[BK_PER];
+  T x[BK_PER];
+#pragma unroll
+  for (int u = 0; u < BK_PER; ++u) nz.get(pp[u], ik[u], x[u]);
+#pragma unroll
+  for (int u = 0; u < BK_PER; ++u)
+    if (base + (i64)u * BK_THREADS + tid <= last) f(ik[u], x[u], zr[u]);
 }
 
 // Workgroup w takes the consecutive chunks [w cpw, (w + 1) cpw) of the stream
