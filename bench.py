@@ -872,7 +872,12 @@ def bench_large(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_stage_traffic(ROOT, "gather_own_large1e9_traffic.txt"),
+            "traffic": (recorded_stage_traffic(ROOT, "gather_bkt_large1e9_traffic.txt")
+                        if all(sm == -1 for _, sm in r64["cfg"]) else None),
+            "traffic_note": "HBM bytes per FP64 gather stage from the committed FETCH_SIZE / "
+                            "WRITE_SIZE runs (profiles/gather_bkt_large1e9_traffic.txt), reported "
+                            "while k_gather.hip is unchanged and every mode ran the bucketed "
+                            "gather",
             "algorithmic_bytes_per_launch": r64["gbytes"] / updates,
             "avg_launch_us": 1e3 * r64["g_ms"] / max(r64["g_cnt"], 1),
             "timed_with": "HIP events on the library's stream around the gather stage of "
