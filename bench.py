@@ -70,12 +70,18 @@ def recorded_traffic(root):
     return rec.get("traffic_bytes_per_launch") if rec else None
 
 
-def recorded_stage_traffic(root, name):
+def recorded_stage_traffic(root, name, forms=None):
     """HBM bytes per update of a gather stage from a committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy's
-    counters), or None when the kernel source has changed since."""
+    counters), or None when the kernel source has changed since or the
+    summary was taken with other gather forms per mode."""
     rec = recorded_counters(root, name)
-    return rec.get("traffic_bytes_per_launch") if rec else None
+    if not rec:
+        return None
+    if forms is not None and rec.get("gather_forms") is not None \
+            and list(rec["gather_forms"]) != list(forms):
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def log(msg):
@@ -832,7 +838,10 @@ def bench_large(args):
     updates = 3 * K
 
     def names(cfg):
-        return {-2: "owner gather (k_own_bounds + k_gather_own)",
+        return {-4: "bucketed gather with shared blocks (k_bkt_count, scan, k_bkt_scatter, "
+                    "k_gather_bktl)",
+                -3: "tile gather (k_tile_bounds + k_gather_tile)",
+                -2: "owner gather (k_own_bounds + k_gather_own)",
                 -1: "bucketed gather (k_bkt_count, scan, k_bkt_scatter, k_gather_bkt)"}.get(
                     cfg, "segmented gather (k_gather_seg)")
 
@@ -872,12 +881,12 @@ def bench_large(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (recorded_stage_traffic(ROOT, "gather_bkt_large1e9_traffic.txt")
-                        if all(sm == -1 for _, sm in r64["cfg"]) else None),
+            "traffic": recorded_stage_traffic(ROOT, "gather_large1e9_f64_traffic.txt",
+                                              [sm for _, sm in r64["cfg"]]),
             "traffic_note": "HBM bytes per FP64 gather stage from the committed FETCH_SIZE / "
-                            "WRITE_SIZE runs (profiles/gather_bkt_large1e9_traffic.txt), reported "
-                            "while k_gather.hip is unchanged and every mode ran the bucketed "
-                            "gather",
+                            "WRITE_SIZE runs (profiles/gather_large1e9_f64_traffic.txt), reported "
+                            "while k_gather.hip is unchanged and the modes ran the gather forms "
+                            "recorded there",
             "algorithmic_bytes_per_launch": r64["gbytes"] / updates,
             "avg_launch_us": 1e3 * r64["g_ms"] / max(r64["g_cnt"], 1),
             "timed_with": "HIP events on the library's stream around the gather stage of "

@@ -42,7 +42,19 @@ void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
                        const unsigned *coff, const unsigned *cidx, const uint2 *pairs,
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz,
                        void *M, unsigned *bnd, hipStream_t s);
+int gather_tile_blocks(int R, i64 nk);
+u64 gather_tile_ldb(i64 max_fib);
+void launch_gather_tile(bool f64, const DevState *st, int R, const u64 *cpos,
+                        const unsigned *coff, const unsigned *cidx, const uint2 *pairs,
+                        const int *ik, const double *v64, i64 nk, i64 max_fib, const void *zhat,
+                        int ldz, void *M, unsigned *bnd, hipStream_t s);
 size_t gather_bkt_count_words();
+int gather_bktl_shift(int R, i64 nk);
+void launch_gather_bktl(bool f64, const DevState *st, int R, const u64 *cpos,
+                        const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
+                        const uint2 *pairs, const int *ik, const double *v64, i64 nk,
+                        i64 max_total, const void *zhat, int ldz, void *M, unsigned *cnt,
+                        u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s);
 void launch_gather_bkt(bool f64, const DevState *st, int R, const u64 *cpos,
                        const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
                        const uint2 *pairs, const int *ik, const double *v64, i64 nk,
@@ -230,6 +242,9 @@ struct cpal_ctx {
   // owner gather (allocated at init for FP64 contexts, else when a mode
   // first uses it): per nonempty sampled fiber, its segment bounds per row block
   unsigned *own_bnd = nullptr;
+  // tile gather (allocated when a mode first uses it): block-major segment
+  // bounds of the nonempty sampled fibers
+  unsigned *tile_bnd = nullptr;
   u64 *cpos = nullptr;              // nonempty fibers: stream position,
   unsigned *coff = nullptr;         //   offset in the mode-sorted nonzeros,
   unsigned *cidx = nullptr;         //   sampled row
@@ -315,6 +330,7 @@ cpal_status fail(cpal_ctx *c, cpal_status code, const char *msg) {
 
 cpal_status owner_defaults(cpal_ctx *c);
 bool uses_owner(const cpal_ctx *c, int k, int sort_min);
+bool uses_tile(const cpal_ctx *c, int k, int sort_min);
 
 FullModes full_modes(const cpal_ctx *c) {
   FullModes fm;
@@ -805,7 +821,8 @@ void update_front(cpal_ctx *c, int k) {
               c->dtab_n - 1, c->dtab_shift, c->tpos, c->dense ? nullptr : md.slots,
               md.nslots - 1, md.hshift, (unsigned)md.n, c->zhat, c->foff, c->flen, c->gpart,
               c->gp_len, c->gp_cnt, c->gp_act, c->M,
-              (c->dense || uses_owner(c, k, md.g_sort_min)) ? 0 : ncopies * md.n * c->ldz,
+              (c->dense || uses_owner(c, k, md.g_sort_min) || uses_tile(c, k, md.g_sort_min))
+                  ? 0 : ncopies * md.n * c->ldz,
               c->ldz, s);
   launch_gather_prep(c->st, c->flen, c->foff, c->s, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
                      c->coff, c->cidx, c->chunk_first, c->tpos, c->dtab, s);
@@ -829,6 +846,12 @@ cpal_status ensure_bucket_buffers(cpal_ctx *c) {
 
 bool bucket_capable(const cpal_ctx *c, int k) {
   return !c->dense && c->mode[k].n <= (1 << 20);
+}
+
+// The bucketed gather with shared-memory bucket blocks (buckets of up to 512
+// rows, at most BL_MAXNB of them).
+bool bucket_lds_capable(const cpal_ctx *c, int k) {
+  return bucket_capable(c, k) && gather_bktl_shift(c->R, c->mode[k].n) >= 0;
 }
 
 // The owner gather writes every row of the CPAL_MCOPIES copies of M (sparse
@@ -865,6 +888,29 @@ bool uses_owner(const cpal_ctx *c, int k, int sort_min) {
   return sort_min == -2 && c->own_bnd && owner_capable(c, k);
 }
 
+// The tile gather writes every row of the CPAL_MCOPIES copies of M (sparse
+// modes of at most TB_MAXNB row blocks).
+bool tile_capable(const cpal_ctx *c, int k) {
+  return !c->dense && c->mode[k].n <= (1 << 20) && gather_tile_blocks(c->R, c->mode[k].n) > 0;
+}
+
+cpal_status ensure_tile_buffers(cpal_ctx *c) {
+  if (c->tile_bnd) return CPAL_OK;
+  i64 nbmax = 0;
+  for (int m = 0; m < c->D; ++m)
+    if (tile_capable(c, m)) nbmax = std::max<i64>(nbmax, gather_tile_blocks(c->R, c->mode[m].n));
+  try {
+    c->tile_bnd = c->alloc<unsigned>((size_t)gather_tile_ldb(c->s) * (size_t)(nbmax + 1));
+  } catch (cpal_status st) {
+    return st;
+  }
+  return CPAL_OK;
+}
+
+bool uses_tile(const cpal_ctx *c, int k, int sort_min) {
+  return sort_min == -3 && c->tile_bnd && tile_capable(c, k);
+}
+
 // TnsrSamp + sampled MTTKRP (Sec. 6.3, eq. (1.2)) into M.  sort_min < 0
 // selects the bucketed gather (bucket_capable modes).
 void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
@@ -877,9 +923,16 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
     launch_dense_mttkrp(c->zdt, c->st, md.n, R, c->ldz, md.dld, c->cidx, c->samp_idx, md.dX,
                         c->zhat, c->dpart, kc, (int)((c->s + kc - 1) / kc), c->M, s);
   }
+  else if (uses_tile(c, k, sort_min))
+    launch_gather_tile(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, md.n,
+                       c->s, c->zhat, c->ldz, c->M, c->tile_bnd, s);
   else if (uses_owner(c, k, sort_min))
     launch_gather_own(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, md.n,
                       c->zhat, c->ldz, c->M, c->own_bnd, s);
+  else if (sort_min == -4 && c->bk_ent && bucket_lds_capable(c, k))
+    launch_gather_bktl(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
+                       md.ik, md.v64, md.n, c->nnz, c->zhat, c->ldz, c->M, c->bk_cnt, c->bk_off,
+                       c->bk_scan, c->bk_ent, s);
   else if (sort_min == -1 && c->bk_ent && bucket_capable(c, k))
     launch_gather_bkt(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                       md.ik, md.v64, md.n, c->nnz, c->zhat, c->ldz, c->M, grid, c->bk_cnt,
@@ -1030,7 +1083,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
 }
 
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *c, int32_t k, int32_t grid, int32_t sort_min) {
-  if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < -2)
+  if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < -4)
     return CPAL_E_ARG;
   if (c->dense && grid > c->dnch) return CPAL_E_ARG;
   if (sort_min == -1) {   // the bucketed gather
@@ -1042,6 +1095,16 @@ cpal_status cp_arls_lev_set_gather_config(cpal_ctx *c, int32_t k, int32_t grid, 
     if (!owner_capable(c, k)) return CPAL_E_ARG;
     const cpal_status st = ensure_owner_buffers(c);
     if (st != CPAL_OK) return fail(c, st, "owner gather: buffers");
+  }
+  if (sort_min == -4) {   // the bucketed gather with shared-memory blocks
+    if (!bucket_lds_capable(c, k)) return CPAL_E_ARG;
+    const cpal_status st = ensure_bucket_buffers(c);
+    if (st != CPAL_OK) return fail(c, st, "bucketed gather: buffers");
+  }
+  if (sort_min == -3) {   // the tile gather
+    if (!tile_capable(c, k)) return CPAL_E_ARG;
+    const cpal_status st = ensure_tile_buffers(c);
+    if (st != CPAL_OK) return fail(c, st, "tile gather: buffers");
   }
   c->mode[k].g_grid = grid;
   c->mode[k].g_sort_min = sort_min;
@@ -1093,12 +1156,19 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
     // and the owner gather (-2, one launch shape: its grid follows n_k)
     const bool bkt = bucket_capable(c, k) && ensure_bucket_buffers(c) == CPAL_OK;
     const bool own = owner_capable(c, k) && ensure_owner_buffers(c) == CPAL_OK;
+    const bool tile = tile_capable(c, k) && ensure_tile_buffers(c) == CPAL_OK;
+    // candidates: ng grids x ns sort thresholds, then the single-shape
+    // owner (-2), tile (-3) and shared-block bucketed (-4) gathers
+    std::vector<int> extra;
+    if (own) extra.push_back(-2);
+    if (tile) extra.push_back(-3);
+    if (bkt && bucket_lds_capable(c, k)) extra.push_back(-4);
     const int ng = 4, ns = seg ? (bkt ? 5 : 4) : 1;
-    for (int gi = 0; gi < ng + (own ? 1 : 0) && res == CPAL_OK; ++gi)
+    for (int gi = 0; gi < ng + (int)extra.size() && res == CPAL_OK; ++gi)
       for (int si = 0; si < (gi < ng ? ns : 1) && res == CPAL_OK; ++si) {
-        const int grid = gi == ng ? 0
+        const int grid = gi >= ng ? 0
                        : c->dense ? dense_grids[gi] : seg ? seg_grids[gi] : flat_grids[gi];
-        const int smin = gi == ng ? -2 : !seg ? 0 : si < 4 ? seg_sort[si] : -1;
+        const int smin = gi >= ng ? extra[gi - ng] : !seg ? 0 : si < 4 ? seg_sort[si] : -1;
         float tmin = 1e30f;
         for (int r = 0; r < reps; ++r) {
           launch_zero_words(c->M, mwords, c->stream);
@@ -1252,7 +1322,7 @@ cpal_status cp_arls_lev_rrf_init(cpal_ctx *c, int64_t s_init, const double *cons
     launch_gather_prep(c->st, c->flen, c->foff, s_init, c->gp_len, c->gp_cnt, c->gp_act, c->cpos,
                        c->coff, c->cidx, c->chunk_first, c->tpos, c->dtab, s);
     const int ncopies = c->dense ? 1 : (int)m_copies(md.n);
-    if (!c->dense && !uses_owner(c, k, md.g_sort_min))
+    if (!c->dense && !uses_owner(c, k, md.g_sort_min) && !uses_tile(c, k, md.g_sort_min))
       launch_zero_words(c->M, (i64)ncopies * md.n * c->ldz * (c->f64 ? 2 : 1), s);
     update_gather(c, k, md.g_grid, md.g_sort_min);
     launch_rrf_store(c->f64, c->M, ncopies, md.n, c->R, c->ldz, md.A, md.A32, s);
@@ -1561,17 +1631,21 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
     } else {
       // a restart takes the tuned shapes; the bucketed gather needs its own
       // buffers, and where they cannot be had the restart keeps the default
-      bool need_bkt = false, need_own = false;
+      bool need_bkt = false, need_own = false, need_tile = false;
       for (int k = 0; k < c->D; ++k) {
-        need_bkt |= b->ctx[src]->mode[k].g_sort_min == -1;
+        need_bkt |= b->ctx[src]->mode[k].g_sort_min == -1 || b->ctx[src]->mode[k].g_sort_min == -4;
         need_own |= b->ctx[src]->mode[k].g_sort_min == -2;
+        need_tile |= b->ctx[src]->mode[k].g_sort_min == -3;
       }
       const bool bkt_ok = need_bkt && ensure_bucket_buffers(c) == CPAL_OK;
       const bool own_ok = need_own && ensure_owner_buffers(c) == CPAL_OK;
+      const bool tile_ok = need_tile && ensure_tile_buffers(c) == CPAL_OK;
       for (int k = 0; k < c->D; ++k) {
         const int sm = b->ctx[src]->mode[k].g_sort_min;
         if ((sm == -1 && !(bkt_ok && bucket_capable(c, k))) ||
-            (sm == -2 && !(own_ok && owner_capable(c, k)))) {
+            (sm == -4 && !(bkt_ok && bucket_lds_capable(c, k))) ||
+            (sm == -2 && !(own_ok && owner_capable(c, k))) ||
+            (sm == -3 && !(tile_ok && tile_capable(c, k)))) {
           c->mode[k].g_grid = 0;
           c->mode[k].g_sort_min = 0;
         } else {

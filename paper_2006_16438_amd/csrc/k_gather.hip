@@ -620,6 +620,162 @@ void launch_gather_bkt(bool f64, const DevState *st, int R, const u64 *cpos,
                                scan_scratch, bent, s);
 }
 
+// brow[c] += x zp[c] for c < R (a shared FP64 row; atomic adds, since lanes
+// of one wave can meet on a row).  The column guard is uniform over the
+// wave; lanes without a nonzero pass x = 0 and a row of their own.
+template <typename T>
+__device__ __forceinline__ void tile_add_row(double *brow, double x, const T *__restrict__ zp,
+                                             int R) {
+  for (int c0 = 0; c0 < R; c0 += 16) {
+    T zv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) zv[j] = zp[c0 + j];
+    const int nc = min(16, R - c0);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j < nc)
+        __hip_atomic_fetch_add(brow + c0 + j, x * (double)zv[j], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// ------------------------------------------- bucketed gather, shared blocks --
+// The same count and scatter passes with buckets of 2^bshift = up to 512
+// output rows, so that a bucket's rows fit one FP64 block of shared memory;
+// the buckets' records are cut into slices (at least BL_SLICE records, about
+// BL_SLICES slices in all) and workgroup g takes
+// the slices g, g + G, ...: it adds every record of the slice into the
+// bucket's shared block (one record per lane, column by column, atomic FP64
+// adds as in the tile gather), then adds the block into its XCD's copy of M
+// (one global add per nonzero entry of the block and slice).  Records of a
+// bucket follow the stream order of the scatter, i.e. fiber after fiber, so
+// neighbouring lanes mostly read the same weighted KRP row.
+#define BL_THREADS 1024
+#define BL_MAXNB 2048
+#define BL_SLICE 65536
+#define BL_SLICES 4096
+#define BL_K 4
+#define BL_MAXBLK (112 * 1024)
+
+template <typename T>
+__global__ void __launch_bounds__(BL_THREADS) k_gather_bktl(
+    const DevState *st, int R, const uint4 *__restrict__ bent, const u64 *__restrict__ off,
+    int gb, int nb, int bshift, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+  extern __shared__ double bl_blk[];    // (1 << bshift) rows, odd stride LDB
+  __shared__ unsigned bst[BL_MAXNB + 1];   // first record of each bucket
+  __shared__ unsigned sst[BL_MAXNB + 1];   // first slice of each bucket
+  constexpr int NW = BL_THREADS / 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const unsigned total = (unsigned)st->gathered;
+  // slice length: at least BL_SLICE records, and about BL_SLICES slices in
+  // all, so that the per-slice block flush stays small against the adds
+  const unsigned slen = max((unsigned)BL_SLICE, (total + BL_SLICES - 1) / BL_SLICES);
+  for (int b = tid; b <= nb; b += BL_THREADS)
+    bst[b] = b < nb ? (unsigned)off[(u64)b * (u64)gb] : total;
+  __syncthreads();
+  {   // slices per bucket, two buckets per thread (nb <= 2 BL_THREADS)
+    const int b0 = 2 * tid, b1 = b0 + 1;
+    const unsigned c0 = b0 < nb ? (bst[b0 + 1] - bst[b0] + slen - 1) / slen : 0u;
+    const unsigned c1 = b1 < nb ? (bst[b1 + 1] - bst[b1] + slen - 1) / slen : 0u;
+    unsigned tot;
+    const unsigned ex = block_excl_scan<unsigned>(c0 + c1, &tot);
+    if (b0 < nb) sst[b0] = ex;
+    if (b1 < nb) sst[b1] = ex + c0;
+    if (tid == 0) sst[nb] = tot;
+  }
+  __syncthreads();
+  const unsigned nsl = sst[nb];
+  const int LDB = R | 1, RB = 1 << bshift;
+  T *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * ldz;
+  for (unsigned sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
+    int b = 0, hb = nb;   // last bucket with sst[b] <= sl
+    while (hb - b > 1) {
+      const int mid = (b + hb) >> 1;
+      if (sst[mid] <= sl) b = mid; else hb = mid;
+    }
+    const unsigned a0 = bst[b] + (sl - sst[b]) * slen;
+    const unsigned a1 = min(bst[b + 1], a0 + slen);
+    const i64 r0 = (i64)b << bshift;
+    const int nrows = (int)min((i64)RB, nk - r0);
+    for (int e = tid; e < nrows * LDB; e += BL_THREADS) bl_blk[e] = 0.0;
+    __syncthreads();
+    for (unsigned q0 = a0 + (unsigned)w * (64u * BL_K); q0 < a1; q0 += NW * 64u * BL_K) {
+      // every lane loads and adds (no divergent branch): a lane past the
+      // slice re-reads its last record and adds zeros to a row of its own
+      uint4 rec[BL_K];
+#pragma unroll
+      for (int u = 0; u < BL_K; ++u) rec[u] = bent[min(q0 + (unsigned)(u * 64 + lane), a1 - 1)];
+#pragma unroll
+      for (int u = 0; u < BL_K; ++u) {
+        if (q0 + (unsigned)(u * 64) >= a1) break;   // wave-uniform
+        unsigned ik, zr;
+        T x;
+        BktRec<T>::get(rec[u], ik, x, zr);
+        const int rl = (int)ik - (int)r0;
+        const bool ok = q0 + (unsigned)(u * 64 + lane) < a1 && (unsigned)rl < (unsigned)nrows;
+        tile_add_row<T>(bl_blk + (ok ? rl : lane % nrows) * LDB, ok ? (double)x : 0.0,
+                        zhat + (u64)(ok ? zr : 0u) * (u64)ldz, R);
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < nrows * R; e += BL_THREADS) {
+      const int r = e / R, c = e - r * R;
+      const double v = bl_blk[r * LDB + c];
+      if (v != 0.0) unsafeAtomicAdd(&Mx[(r0 + r) * ldz + c], (T)v);
+    }
+    __syncthreads();   // the block is read before the next slice clears it
+  }
+}
+
+// Bucket width of the shared-block bucketed gather: the largest power of two
+// <= 512 rows whose FP64 block fits BL_MAXBLK; -1 when the mode needs more
+// than BL_MAXNB buckets.
+int gather_bktl_shift(int R, i64 nk) {
+  const size_t row = (size_t)(R | 1) * 8;
+  int sh = 9;
+  while (sh > 0 && ((size_t)1 << sh) * row > BL_MAXBLK) --sh;
+  while (sh > 0 && ((i64)1 << (sh - 1)) >= nk) --sh;
+  if (((nk + (1ll << sh) - 1) >> sh) > BL_MAXNB) return -1;
+  return sh;
+}
+
+template <typename T>
+static void launch_gather_bktl_t(const DevState *st, int R, const u64 *cpos, const unsigned *coff,
+                                 const unsigned *cidx, const unsigned *chunk_first, NzLoad<T> nz,
+                                 i64 nk, i64 max_total, const T *zhat, int ldz, T *M,
+                                 unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent,
+                                 hipStream_t s) {
+  const int bshift = gather_bktl_shift(R, nk);
+  const int nb = (int)((nk + (1ll << bshift) - 1) >> bshift);
+  const i64 chunks = (max_total + GT_CHUNK - 1) / GT_CHUNK;
+  const int gb = (int)std::min<i64>(BK_GRID, std::max<i64>(64, (chunks + 7) / 8));
+  hipLaunchKernelGGL(k_bkt_count<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                     chunk_first, nz, bshift, nb, cnt);
+  scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, nullptr, scan_scratch, s);
+  hipLaunchKernelGGL(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                     chunk_first, nz, bshift, nb, off, bent);
+  const size_t smem = ((size_t)1 << bshift) * (size_t)(R | 1) * 8;
+  const i64 slices = max_total / BL_SLICE + nb + 1;
+  const int grid = (int)std::min<i64>(512, std::max<i64>(1, slices));
+  hipLaunchKernelGGL(k_gather_bktl<T>, dim3(grid), dim3(BL_THREADS), smem, s, st, R, bent, off,
+                     gb, nb, bshift, zhat, ldz, M, nk);
+}
+
+void launch_gather_bktl(bool f64, const DevState *st, int R, const u64 *cpos,
+                        const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
+                        const uint2 *pairs, const int *ik, const double *v64, i64 nk,
+                        i64 max_total, const void *zhat, int ldz, void *M, unsigned *cnt,
+                        u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s) {
+  if (f64)
+    launch_gather_bktl_t<double>(st, R, cpos, coff, cidx, chunk_first, NzLoad<double>{ik, v64},
+                                 nk, max_total, (const double *)zhat, ldz, (double *)M, cnt, off,
+                                 scan_scratch, bent, s);
+  else
+    launch_gather_bktl_t<float>(st, R, cpos, coff, cidx, chunk_first, NzLoad<float>{pairs}, nk,
+                                max_total, (const float *)zhat, ldz, (float *)M, cnt, off,
+                                scan_scratch, bent, s);
+}
+
 // ------------------------------------------------------------ owner gather --
 // Owner-computes form of the same sum, with no atomic operation anywhere:
 // the rows of M are cut into blocks of 2^rshift rows and the nonempty
@@ -808,6 +964,265 @@ void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
                       : rm == 32 ? k_gather_own<float, 16, 2> : k_gather_own<float, 32, 2>;
     hipLaunchKernelGGL(k, grid, dim3(GT_THREADS), smem, s, st, R, coff, cidx, bnd, nb, sh, nz,
                        (const float *)zhat, ldz, (float *)M, nk);
+  }
+}
+
+// ------------------------------------------------------------- tile gather --
+// Row blocks of M held in shared memory, fed by every sampled fiber's segment
+// in the block: the rows of M are cut into blocks of 2^rshift rows and the
+// nonempty sampled fibers into CPAL_MCOPIES parts of about equal nonzero
+// count; workgroup (b, p) forms rows of block b of copy p of M from the
+// fibers of part p (every row of every copy is stored, so M needs no
+// clearing; the solve sums the copies in a fixed order).  Part p runs on XCD
+// p (workgroups are dealt to the XCDs in turn), so a die reads only its own
+// part's weighted KRP rows and nonzeros.
+//  1. k_tile_bounds: for groups of TB_FIB fibers, bnd[b ldb + f] = number of
+//     nonzeros of fiber f with row < b 2^rshift (a fiber's rows ascend, so
+//     its nonzeros in block b are [bnd[b], bnd[b+1])), staged in shared
+//     memory and stored block-major, TB_FIB entries (64 bytes) per block;
+//  2. k_gather_tile: windows of TL_THREADS fibers, their nonempty segments
+//     in block b listed in shared memory (start in the window's stream,
+//     nonzero offset, KRP row); each wave takes 64 consecutive positions of
+//     the stream at a time, one nonzero per lane, and adds x * zhat(j, c)
+//     into the shared block column by column.  The shared block is FP64 in
+//     both precisions (shared-memory FP64 adds run at full rate on this
+//     chip, FP32 ones about ten times slower); lanes of one wave can meet on
+//     a row (nonzeros of different fibers), so the adds are atomic, and the
+//     order of a row's adds depends on timing (rounding order only).
+#define TB_FIB 16
+#define TB_THREADS 1024
+#define TB_MAXNB 1023         // (TB_MAXNB + 1) * TB_FIB entries of shared memory
+#define TL_THREADS 1024
+#define TL_K 4               // chunks of 64 positions a wave has in flight
+#define TL_MAXBLK (128 * 1024)   // bytes of the shared row block
+
+// First fiber of part p: the least f with cpos[f] >= ceil(p total / parts).
+__device__ __forceinline__ i64 tile_part_start(const u64 *__restrict__ cpos, i64 nf, u64 total,
+                                               int p, int parts) {
+  if (p <= 0) return 0;
+  if (p >= parts) return nf;
+  const u64 t = (total * (u64)p + (u64)parts - 1) / (u64)parts;
+  i64 lo = 0, hi = nf;
+  while (lo < hi) {
+    const i64 mid = (lo + hi) >> 1;
+    if (cpos[mid] >= t) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Workgroup g takes the fibers [TB_FIB g, TB_FIB (g + 1)) as one stream of their
+// nonzeros, TB_PER positions per thread and step: the first nonzero of a
+// fiber in each block it reaches marks tb[block][fiber] with its index in the
+// fiber (one writer per entry: a fiber's rows ascend); tb[nb][fiber] = the
+// fiber's length; a suffix minimum along the blocks then gives every entry
+// the index of the fiber's first nonzero in that block or a later one.
+#define TB_PER 4
+template <typename T>
+__global__ void __launch_bounds__(TB_THREADS) k_tile_bounds(
+    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    RowLoad<T> rows, int rshift, int nb, u64 ldb, unsigned *__restrict__ bnd) {
+  __shared__ unsigned tb[(TB_MAXNB + 1) * TB_FIB];   // tb[bb TB_FIB + i]
+  __shared__ u64 gs[TB_FIB + 1];
+  __shared__ unsigned gb[TB_FIB];
+  __shared__ unsigned smin[TB_FIB * (TB_THREADS / TB_FIB)];
+  const i64 nf = st->n_fib;
+  const u64 total = (u64)st->gathered;
+  const i64 f0 = (i64)blockIdx.x * TB_FIB;
+  if (f0 >= nf) return;
+  const int nfg = (int)min((i64)TB_FIB, nf - f0);
+  const int tid = threadIdx.x;
+  if (tid <= nfg) gs[tid] = f0 + tid < nf ? cpos[f0 + tid] : total;
+  if (tid < nfg) gb[tid] = coff[f0 + tid];
+  const int nent = (nb + 1) * TB_FIB;
+  for (int t = tid; t < nent; t += TB_THREADS) tb[t] = 0xFFFFFFFFu;
+  __syncthreads();
+  if (tid < TB_FIB) tb[nb * TB_FIB + tid] = tid < nfg ? (unsigned)(gs[tid + 1] - gs[tid]) : 0u;
+  const u64 s0 = gs[0];
+  const unsigned G = (unsigned)(gs[nfg] - s0);
+  for (unsigned q0 = 0; q0 < G; q0 += TB_THREADS * TB_PER) {
+    int fi[TB_PER];
+    unsigned ee[TB_PER];
+#pragma unroll
+    for (int u = 0; u < TB_PER; ++u) {
+      const unsigned q = min(q0 + (unsigned)(u * TB_THREADS + tid), G - 1);
+      int lo = 0, hi = nfg;   // last fiber starting at or before q
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((unsigned)(gs[mid] - s0) <= q) lo = mid; else hi = mid;
+      }
+      fi[u] = lo;
+      ee[u] = q - (unsigned)(gs[lo] - s0);
+    }
+    unsigned rc[TB_PER], rp[TB_PER];
+#pragma unroll
+    for (int u = 0; u < TB_PER; ++u) {
+      const u64 pos = (u64)gb[fi[u]] + ee[u];
+      rc[u] = rows(pos);
+      rp[u] = ee[u] ? rows(pos - 1) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < TB_PER; ++u) {
+      if (q0 + (unsigned)(u * TB_THREADS + tid) >= G) continue;
+      const int bu = min((int)(rc[u] >> rshift), nb - 1);
+      const int bp = ee[u] ? min((int)(rp[u] >> rshift), nb - 1) : -1;
+      if (bp != bu) tb[bu * TB_FIB + fi[u]] = ee[u];
+    }
+  }
+  __syncthreads();
+  // suffix minimum along bb per fiber column: thread (i, sg) takes the
+  // entries [sg seg, (sg + 1) seg) of column i
+  constexpr int NSEG = TB_THREADS / TB_FIB;
+  const int i = tid % TB_FIB, sg = tid / TB_FIB;
+  const int seg = (nb + 1 + NSEG - 1) / NSEG;
+  const int b0 = sg * seg, b1 = min(nb + 1, b0 + seg);
+  unsigned m = 0xFFFFFFFFu;
+  for (int bb = b1 - 1; bb >= b0; --bb) {
+    m = min(m, tb[bb * TB_FIB + i]);
+    tb[bb * TB_FIB + i] = m;
+  }
+  smin[sg * TB_FIB + i] = m;
+  __syncthreads();
+  unsigned after = 0xFFFFFFFFu;
+  for (int s2 = sg + 1; s2 < NSEG; ++s2) after = min(after, smin[s2 * TB_FIB + i]);
+  for (int bb = b0; bb < b1; ++bb) tb[bb * TB_FIB + i] = min(tb[bb * TB_FIB + i], after);
+  __syncthreads();
+  for (int t = tid; t < nent; t += TB_THREADS) {
+    const int bb = t / TB_FIB, i2 = t - bb * TB_FIB;
+    bnd[(u64)bb * ldb + (u64)f0 + i2] = tb[t];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TL_THREADS) k_gather_tile(
+    const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ bnd, u64 ldb, int rshift,
+    NzLoad<T> nz, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+  extern __shared__ double tl_blk[];   // (1 << rshift) rows, odd stride LDB
+  __shared__ unsigned cs[TL_THREADS + 1], cb[TL_THREADS], cz[TL_THREADS];
+  constexpr int NW = TL_THREADS / 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int p = (int)(blockIdx.x & (CPAL_MCOPIES - 1)), b = (int)(blockIdx.x / CPAL_MCOPIES);
+  const int LDB = R | 1;
+  const i64 r0 = (i64)b << rshift;
+  const int nrows = (int)min((i64)1 << rshift, nk - r0);
+  const i64 nf = st->n_fib;
+  const u64 total = (u64)st->gathered;
+  const i64 fa = tile_part_start(cpos, nf, total, p, CPAL_MCOPIES);
+  const i64 fb = tile_part_start(cpos, nf, total, p + 1, CPAL_MCOPIES);
+  for (int e = tid; e < nrows * LDB; e += TL_THREADS) tl_blk[e] = 0.0;
+  const unsigned *blo = bnd + (u64)b * ldb, *bhi = blo + ldb;
+  // the window's per-fiber inputs, loaded one window ahead
+  unsigned nlo = 0, nlen = 0, noff = 0, nz_ = 0;
+  auto fetch = [&](i64 f) {
+    nlo = 0; nlen = 0; noff = 0; nz_ = 0;
+    if (f < fb) {
+      nlo = blo[f];
+      nlen = min(bhi[f] - nlo, 1u << rshift);
+      noff = coff[f];
+      nz_ = cidx[f];
+    }
+  };
+  fetch(fa + tid);
+  for (i64 w0 = fa; w0 < fb; w0 += TL_THREADS) {
+    const unsigned lo = nlo, len = nlen, off = noff, zrow = nz_;
+    fetch(w0 + TL_THREADS + tid);
+    // one scan of (nonempty << 20 | length): a segment holds at most
+    // 2^rshift <= 512 nonzeros (rows are distinct within a fiber), so the
+    // window's stream length stays below 2^20
+    unsigned tot;
+    const unsigned ex = block_excl_scan<unsigned>((len ? 1u << 20 : 0u) | len, &tot);
+    const int nne = (int)(tot >> 20);
+    const unsigned nw = tot & 0xFFFFFu;
+    if (len) {
+      const int ci = (int)(ex >> 20);
+      cs[ci] = ex & 0xFFFFFu;
+      cb[ci] = off + lo;
+      cz[ci] = zrow;
+    }
+    if (tid == 0) cs[nne] = nw;
+    __syncthreads();
+    // TL_K chunks of 64 positions per wave and step: their searches and
+    // nonzero loads are all issued before the first chunk's adds
+    for (unsigned qb = (unsigned)w * (64u * TL_K); qb < nw; qb += NW * 64u * TL_K) {
+      int ik[TL_K];
+      T x[TL_K];
+      unsigned zr[TL_K];
+      u64 pos[TL_K];
+#pragma unroll
+      for (int u = 0; u < TL_K; ++u) {
+        const unsigned q = min(qb + (unsigned)(u * 64 + lane), nw - 1);
+        int lo2 = 0, hi2 = nne;   // last segment with cs[seg] <= q
+        while (hi2 - lo2 > 1) {
+          const int mid = (lo2 + hi2) >> 1;
+          if (cs[mid] <= q) lo2 = mid; else hi2 = mid;
+        }
+        pos[u] = (u64)cb[lo2] + (q - cs[lo2]);
+        zr[u] = cz[lo2];
+      }
+#pragma unroll
+      for (int u = 0; u < TL_K; ++u) nz.get(pos[u], ik[u], x[u]);
+#pragma unroll
+      for (int u = 0; u < TL_K; ++u) {
+        if (qb + (unsigned)(u * 64) >= nw) break;   // wave-uniform
+        const int rl = ik[u] - (int)r0;
+        const bool ok = qb + (unsigned)(u * 64 + lane) < nw && (unsigned)rl < (unsigned)nrows;
+        tile_add_row<T>(tl_blk + (ok ? rl : lane % nrows) * LDB, ok ? (double)x[u] : 0.0,
+                        zhat + (u64)(ok ? zr[u] : 0u) * (u64)ldz, R);
+      }
+    }
+    __syncthreads();   // the window's segment lists are finished with
+  }
+  __syncthreads();
+  T *Mp = M + (i64)p * nk * ldz;
+  for (int e = tid; e < nrows * ldz; e += TL_THREADS) {
+    const int r = e / ldz, c = e - r * ldz;
+    Mp[(r0 + r) * ldz + c] = c < R ? (T)tl_blk[r * LDB + c] : T(0);
+  }
+}
+
+// Row block of the tile gather for a mode of nk rows: the largest power of two
+// <= 512 whose FP64 block (odd row stride) fits TL_MAXBLK, made smaller while
+// the launch has fewer than 512 workgroups; -1 when the mode needs more than
+// TB_MAXNB blocks.
+int gather_tile_shift(int R, i64 nk) {
+  const size_t row = (size_t)(R | 1) * 8;
+  int sh = 9;
+  while (sh > 4 && ((size_t)1 << sh) * row > TL_MAXBLK) --sh;
+  while (sh > 5 && ((nk + (1ll << sh) - 1) >> sh) * CPAL_MCOPIES < 512) --sh;
+  if (((nk + (1ll << sh) - 1) >> sh) > TB_MAXNB) return -1;
+  return sh;
+}
+
+int gather_tile_blocks(int R, i64 nk) {
+  const int sh = gather_tile_shift(R, nk);
+  return sh < 0 ? -1 : (int)((nk + (1ll << sh) - 1) >> sh);
+}
+
+// Bounds stride (fibers, padded to TB_FIB) for up to max_fib nonempty fibers.
+u64 gather_tile_ldb(i64 max_fib) { return (u64)((max_fib + TB_FIB - 1) / TB_FIB) * TB_FIB; }
+
+void launch_gather_tile(bool f64, const DevState *st, int R, const u64 *cpos,
+                        const unsigned *coff, const unsigned *cidx, const uint2 *pairs,
+                        const int *ik, const double *v64, i64 nk, i64 max_fib, const void *zhat,
+                        int ldz, void *M, unsigned *bnd, hipStream_t s) {
+  const int sh = gather_tile_shift(R, nk);
+  const int nb = (int)((nk + (1ll << sh) - 1) >> sh);
+  const u64 ldb = gather_tile_ldb(max_fib);
+  const dim3 gb((unsigned)(ldb / TB_FIB));
+  const dim3 gt((unsigned)nb * CPAL_MCOPIES);
+  const size_t smem = ((size_t)1 << sh) * (size_t)(R | 1) * 8;
+  if (f64) {
+    hipLaunchKernelGGL(k_tile_bounds<double>, gb, dim3(TB_THREADS), 0, s, st, cpos, coff,
+                       RowLoad<double>{ik}, sh, nb, ldb, bnd);
+    hipLaunchKernelGGL(k_gather_tile<double>, gt, dim3(TL_THREADS), smem, s, st, R, cpos, coff,
+                       cidx, bnd, ldb, sh, NzLoad<double>{ik, v64}, (const double *)zhat, ldz,
+                       (double *)M, nk);
+  } else {
+    hipLaunchKernelGGL(k_tile_bounds<float>, gb, dim3(TB_THREADS), 0, s, st, cpos, coff,
+                       RowLoad<float>{pairs}, sh, nb, ldb, bnd);
+    hipLaunchKernelGGL(k_gather_tile<float>, gt, dim3(TL_THREADS), smem, s, st, R, cpos, coff,
+                       cidx, bnd, ldb, sh, NzLoad<float>{pairs}, (const float *)zhat, ldz,
+                       (float *)M, nk);
   }
 }
 

@@ -35,7 +35,8 @@ def large_tensor():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("gather", ["f64", "f32", "f32-bucketed"])
+@pytest.mark.parametrize("gather", ["f64", "f32", "f32-bucketed", "f64-tile", "f32-tile",
+                                    "f64-bktl"])
 def test_large3_shape_parity(large_tensor, gather):
     from paper_2006_16438_amd.api import CpArlsLev
     dims, coords, vals = large_tensor
@@ -45,12 +46,20 @@ def test_large3_shape_parity(large_tensor, gather):
     F = [torch.from_numpy(f.copy()).to(dev) for f in fac]
     log(f"large3 {dims} nnz={NNZ} R={R} s={s} gather={gather}: init")
     bucketed = gather == "f32-bucketed"
-    gather = "f32" if bucketed else gather
+    tile = gather.endswith("-tile")
+    bktl = gather.endswith("-bktl")
+    gather = gather.split("-")[0]
     ctx = CpArlsLev(dims, coords, vals, F, R, s, tau=1.0 / s, seed=0, stream_id=0,
                     gather_dtype=gather)
     if bucketed:   # nonzeros moved into row buckets before the reduction
         for k in range(3):
             ctx.set_gather_config(k, 512, -1)
+    elif tile:     # row blocks in shared memory (512 rows in the long mode)
+        for k in range(3):
+            ctx.set_gather_config(k, 0, -3)
+    elif bktl:     # 512-row buckets reduced in shared memory
+        for k in range(3):
+            ctx.set_gather_config(k, 0, -4)
     elif gather == "f32":   # the tuned launch shapes
         log(f"  autotuned gather shapes {ctx.autotune()}")
     OT = oracle.Tensor(np.array(dims), np.zeros((3, 1), dtype=np.int32), np.ones(1))

@@ -328,6 +328,72 @@ def test_owner_gather_fp32(case):
                gather_config=(0, -2))
 
 
+@pytest.mark.parametrize("gather,case", [("f64", "long_short"), ("f64", "multitile"),
+                                          ("f64", "rank40"), ("f64", "uber4"),
+                                          ("f32", "multitile"), ("f32", "uber4")])
+def test_tile_gather(gather, case):
+    """The tile gather (workgroup (row block, fiber part) adds the segments of
+    its part's fibers in its block into a shared FP64 row block, one
+    nonzero per lane): row blocks of 32 to 512 rows, one-block modes,
+    windows of more than one workgroup of fibers, R > 32 (three 16-column
+    groups), the benchmark workload at full size; FP64 at the 1e-10 bar."""
+    if case == "long_short":
+        dims = (3000, 4, 3)
+        T = synth.random_sparse(dims, 30_000, seed=51)
+        R, s, tau, n = 3, 256, 1 / 256, 6
+        fac = concentrated(dims, R, 52)
+    elif case == "multitile":
+        dims = (700, 300, 257)
+        T = synth.random_sparse(dims, 150_000, seed=21)
+        R, s, tau, n = 8, 8192 + 77, 1 / 8192, 6
+        fac = concentrated(dims, R, 22)
+    elif case == "rank40":
+        dims = (900, 40, 35)
+        T = synth.random_sparse(dims, 200_000, seed=23)
+        R, s, tau, n = 40, 4096, 1 / 4096, 6
+        fac = concentrated(dims, R, 22)
+    else:
+        T = synth.uber4(0)
+        R, s, tau, n = 25, 1 << 17, 2.0 ** -17, 4
+        fac = synth.gaussian_factors(T.dims, R, 0)
+    log(f"tile gather {gather}, {case}")
+    run_parity(T, fac, R, s, tau, n, gather, 1e-10 if gather == "f64" else "derived",
+               label=f"tile-{gather}-{case}", gather_config=(0, -3))
+
+
+@pytest.mark.parametrize("gather,case", [("f64", "long_short"), ("f64", "multitile"),
+                                          ("f64", "rank40"), ("f64", "uber4"),
+                                          ("f32", "multitile"), ("f32", "uber4")])
+def test_bucketed_shared_block_gather(gather, case):
+    """The bucketed gather with shared-memory bucket blocks (buckets of up to
+    512 rows; the records of a bucket cut into slices, each slice added into
+    a shared FP64 block and then into M): one-bucket and many-bucket modes,
+    slices of several workgroup passes, R > 32, the benchmark workload at
+    full size; FP64 at the 1e-10 bar."""
+    if case == "long_short":
+        dims = (3000, 4, 3)
+        T = synth.random_sparse(dims, 30_000, seed=51)
+        R, s, tau, n = 3, 256, 1 / 256, 6
+        fac = concentrated(dims, R, 52)
+    elif case == "multitile":
+        dims = (700, 300, 257)
+        T = synth.random_sparse(dims, 150_000, seed=21)
+        R, s, tau, n = 8, 8192 + 77, 1 / 8192, 6
+        fac = concentrated(dims, R, 22)
+    elif case == "rank40":
+        dims = (900, 40, 35)
+        T = synth.random_sparse(dims, 200_000, seed=23)
+        R, s, tau, n = 40, 4096, 1 / 4096, 6
+        fac = concentrated(dims, R, 22)
+    else:
+        T = synth.uber4(0)
+        R, s, tau, n = 25, 1 << 17, 2.0 ** -17, 4
+        fac = synth.gaussian_factors(T.dims, R, 0)
+    log(f"shared-block bucketed gather {gather}, {case}")
+    run_parity(T, fac, R, s, tau, n, gather, 1e-10 if gather == "f64" else "derived",
+               label=f"bktl-{gather}-{case}", gather_config=(0, -4))
+
+
 @pytest.mark.parametrize("which", ["multitile", "rank40"])
 def test_fp64_updates_bit_reproducible(which):
     """FP64 mode updates (owner gather, earliest draw carrying each repeated
@@ -360,13 +426,13 @@ def test_fp64_updates_bit_reproducible(which):
 
 def test_gather_config_errors():
     """Argument checks of the launch-shape calls: negative grids, sort
-    thresholds below -2, a dense split beyond the default, modes out of
+    thresholds below -4, a dense split beyond the default, modes out of
     range; FP64 contexts start on the owner gather (-2)."""
     from paper_2006_16438_amd._lib import CpalError
     T, _, R = synth.small3(0)
     fac = synth.gaussian_factors(T.dims, R, 0)
     ctx, _ = make_ctx(T, fac, R, 1024, gather="f64")
-    for args in ((0, -1, 0), (0, 64, -3), (3, 64, 0), (-1, 64, 0)):
+    for args in ((0, -1, 0), (0, 64, -5), (3, 64, 0), (-1, 64, 0)):
         with pytest.raises(CpalError):
             ctx.set_gather_config(*args)
     assert ctx.gather_config(0)[1] == -2
@@ -374,6 +440,10 @@ def test_gather_config_errors():
     assert ctx.gather_config(0) == (64, 4)
     ctx.set_gather_config(0, 256, -1)   # the bucketed gather exists in FP64 mode too
     assert ctx.gather_config(0) == (256, -1)
+    ctx.set_gather_config(2, 0, -3)     # and the tile gather
+    assert ctx.gather_config(2)[1] == -3
+    ctx.set_gather_config(1, 0, -4)     # and the shared-block bucketed gather
+    assert ctx.gather_config(1)[1] == -4
     ctx.close()
     ctx, _ = make_ctx(T, fac, R, 1024, gather="f32")
     ctx.set_gather_config(1, 256, -1)   # the bucketed gather exists in FP32 mode
@@ -388,4 +458,8 @@ def test_gather_config_errors():
         ctx.set_gather_config(0, 1, -1)   # no bucketed gather for dense tensors
     with pytest.raises(CpalError):
         ctx.set_gather_config(0, 1, -2)   # nor an owner gather
+    with pytest.raises(CpalError):
+        ctx.set_gather_config(0, 1, -3)   # nor a tile gather
+    with pytest.raises(CpalError):
+        ctx.set_gather_config(0, 1, -4)
     ctx.close()
