@@ -267,17 +267,26 @@ cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *cou
  * operation, each workgroup alone forms a block of rows of one of 8 partial
  * copies of M from its part of the sampled fibers, and the copies are added
  * in a fixed order, so the update's result does not depend on timing (it
- * allocates 4 bytes per sample and row block).  FP64 contexts start on the
- * owner gather for every such mode, which makes their updates bit-for-bit
- * reproducible; the segmented and bucketed gathers add with atomics and
- * their sums are in a timing-dependent order.  Dense tensors: grid =
- * workgroups along the sampled fibers of the split contraction (each writes
- * one partial M; at most the default, which get_gather_config reports;
- * sort_min unused).  Results do not depend on either beyond the rounding
- * order of the FP32/FP64 sums.  Host-side setting, takes effect at the next
- * mode update; grid in [0, 2^20] (dense: [0, default]), sort_min >= -2 (-1
- * and -2 only for sparse modes of at most 2^20 rows), else CPAL_E_ARG;
- * CPAL_E_NOMEM if the chosen gather's buffers cannot be allocated. */
+ * allocates 4 bytes per sample and row block).  sort_min = -3 selects the
+ * tile gather (grid unused; modes of at most 2^20 rows cut into at most 1023
+ * blocks of up to 512 rows): workgroup (row block, fiber part) adds the
+ * block's segment of each of its fibers into an FP64 block of M in shared
+ * memory and stores the block into one of the 8 copies (it allocates 4 bytes
+ * per sample and row block).  sort_min = -4 selects the bucketed gather with
+ * shared-memory buckets (grid unused; buckets of up to 512 rows, at most
+ * 2048 of them; the bucketed gather's buffers): each bucket's records are
+ * added into an FP64 block in shared memory slice by slice, and each slice's
+ * block into M.  FP64 contexts start on the owner gather for every such
+ * mode, which makes their updates bit-for-bit reproducible; the segmented,
+ * bucketed and tile gathers add with atomics and their sums are in a
+ * timing-dependent order.  Dense tensors: grid = workgroups along the
+ * sampled fibers of the split contraction (each writes one partial M; at
+ * most the default, which get_gather_config reports; sort_min unused).
+ * Results do not depend on either beyond the rounding order of the FP32/FP64
+ * sums.  Host-side setting, takes effect at the next mode update; grid in
+ * [0, 2^20] (dense: [0, default]), sort_min >= -4 (-1 to -4 only for sparse
+ * modes within the limits above), else CPAL_E_ARG; CPAL_E_NOMEM if the
+ * chosen gather's buffers cannot be allocated. */
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *ctx, int32_t k, int32_t grid,
                                           int32_t sort_min);
 /* The launch shape mode k uses (grid_host: the effective workgroup count). */
@@ -288,12 +297,13 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_
  * system of an update of that mode at the current step (sampling, KRP rows,
  * fiber probes; the factors, leverage scores and step counter are left as
  * they were), times the gather over a fixed set of grids (and, for the
- * segmented gather, sort thresholds, the bucketed gather and the owner
- * gather, whose buffers it allocates where they fit; for dense tensors the
- * default split of the sampled fibers and 1/2, 1/4, 1/8 of it) with HIP
- * events, best of `reps` runs each (0: 2, at most 16), and keeps the fastest
- * shape for the mode (in FP64 contexts a shape other than the owner gather
- * gives up bit-for-bit reproducibility for speed).  Every trial samples at the current step; afterwards the step
+ * segmented gather, sort thresholds, the bucketed, owner, tile and
+ * shared-block bucketed gathers, whose buffers it allocates where they fit;
+ * for dense tensors the default split of the sampled fibers and 1/2, 1/4,
+ * 1/8 of it) with HIP events, best of `reps` runs each (0: 2, at most 16),
+ * and keeps the fastest shape for the mode, a later candidate replacing an
+ * earlier one only when at least 3% faster (in FP64 contexts a shape other
+ * than the owner gather gives up bit-for-bit reproducibility for speed).  Every trial samples at the current step; afterwards the step
  * counter, factors and leverage scores are as before, and
  * cp_arls_lev_samples reports CPAL_E_STATE until the next mode update.
  * Synchronizes the stream and is not graph-capturable. */

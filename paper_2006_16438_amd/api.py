@@ -212,8 +212,10 @@ class CpArlsLev:
         _check(L.load().cp_arls_lev_refresh(self._ctx, int(m)), self._ctx)
 
     def set_gather_config(self, k, grid=0, sort_min=0):
-        """Launch shape of mode k's gather (grid 0: default; sort_min: chunks
-        spanning at most this many fibers skip the row sort)."""
+        """Launch shape of mode k's gather (grid 0: default; sort_min >= 0:
+        segmented gather, chunks spanning at most this many fibers skip the
+        row sort; -1 bucketed, -2 owner, -3 tile, -4 bucketed with
+        shared-memory buckets)."""
         _check(L.load().cp_arls_lev_set_gather_config(self._ctx, int(k), int(grid),
                                                        int(sort_min)), self._ctx)
 

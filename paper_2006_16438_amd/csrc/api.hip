@@ -1183,7 +1183,9 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
           hipEventElapsedTime(&ms, e0, e1);
           tmin = std::min(tmin, ms);
         }
-        if (tmin < best) { best = tmin; best_grid = grid; best_sort = smin; }
+        // a later candidate replaces the best one only when it is at least
+        // 3% faster, so that near ties resolve the same way from run to run
+        if (tmin < 0.97f * best) { best = tmin; best_grid = grid; best_sort = smin; }
       }
     md.g_grid = best_grid;
     md.g_sort_min = best_sort;
