@@ -838,7 +838,9 @@ def bench_large(args):
     updates = 3 * K
 
     def names(cfg):
-        return {-4: "bucketed gather with shared blocks (k_bkt_count, scan, k_bkt_scatter, "
+        return {-5: "hybrid gather (long fibers: k_tile_bounds + k_gather_tile; the others: "
+                    "k_bkt_count, scan, k_bkt_scatter, k_gather_bktl)",
+                -4: "bucketed gather with shared blocks (k_bkt_count, scan, k_bkt_scatter, "
                     "k_gather_bktl)",
                 -3: "tile gather (k_tile_bounds + k_gather_tile)",
                 -2: "owner gather (k_own_bounds + k_gather_own)",

@@ -276,7 +276,11 @@ cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *cou
  * shared-memory buckets (grid unused; buckets of up to 512 rows, at most
  * 2048 of them; the bucketed gather's buffers): each bucket's records are
  * added into an FP64 block in shared memory slice by slice, and each slice's
- * block into M.  FP64 contexts start on the owner gather for every such
+ * block into M.  sort_min = -5 selects the hybrid of the two (grid = the
+ * long-fiber factor f in [0, 256], 0: 16; both gathers' limits and
+ * buffers): fibers of at least f times the tile gather's row-block count
+ * nonzeros go through the tile gather, the others through the shared-block
+ * bucketed gather.  FP64 contexts start on the owner gather for every such
  * mode, which makes their updates bit-for-bit reproducible; the segmented,
  * bucketed and tile gathers add with atomics and their sums are in a
  * timing-dependent order.  Dense tensors: grid = workgroups along the
@@ -284,7 +288,7 @@ cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *cou
  * most the default, which get_gather_config reports; sort_min unused).
  * Results do not depend on either beyond the rounding order of the FP32/FP64
  * sums.  Host-side setting, takes effect at the next mode update; grid in
- * [0, 2^20] (dense: [0, default]), sort_min >= -4 (-1 to -4 only for sparse
+ * [0, 2^20] (dense: [0, default]), sort_min >= -5 (-1 to -5 only for sparse
  * modes within the limits above), else CPAL_E_ARG; CPAL_E_NOMEM if the
  * chosen gather's buffers cannot be allocated. */
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *ctx, int32_t k, int32_t grid,
@@ -297,8 +301,9 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_
  * system of an update of that mode at the current step (sampling, KRP rows,
  * fiber probes; the factors, leverage scores and step counter are left as
  * they were), times the gather over a fixed set of grids (and, for the
- * segmented gather, sort thresholds, the bucketed, owner, tile and
- * shared-block bucketed gathers, whose buffers it allocates where they fit;
+ * segmented gather, sort thresholds, the bucketed, owner, tile,
+ * shared-block bucketed and hybrid (f = 8, 16, 32) gathers, whose buffers it
+ * allocates where they fit;
  * for dense tensors the default split of the sampled fibers and 1/2, 1/4,
  * 1/8 of it) with HIP events, best of `reps` runs each (0: 2, at most 16),
  * and keeps the fastest shape for the mode, a later candidate replacing an

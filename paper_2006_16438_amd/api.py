@@ -215,7 +215,8 @@ class CpArlsLev:
         """Launch shape of mode k's gather (grid 0: default; sort_min >= 0:
         segmented gather, chunks spanning at most this many fibers skip the
         row sort; -1 bucketed, -2 owner, -3 tile, -4 bucketed with
-        shared-memory buckets)."""
+        shared-memory buckets, -5 tile for long fibers + -4 for the rest, grid
+        = the long-fiber factor)."""
         _check(L.load().cp_arls_lev_set_gather_config(self._ctx, int(k), int(grid),
                                                        int(sort_min)), self._ctx)
 

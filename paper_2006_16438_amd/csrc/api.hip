@@ -47,14 +47,20 @@ u64 gather_tile_ldb(i64 max_fib);
 void launch_gather_tile(bool f64, const DevState *st, int R, const u64 *cpos,
                         const unsigned *coff, const unsigned *cidx, const uint2 *pairs,
                         const int *ik, const double *v64, i64 nk, i64 max_fib, const void *zhat,
-                        int ldz, void *M, unsigned *bnd, hipStream_t s);
+                        int ldz, void *M, unsigned *bnd, unsigned lmin, hipStream_t s);
+void launch_gather_hyb(bool f64, const DevState *st, int R, const u64 *cpos,
+                       const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
+                       const uint2 *pairs, const int *ik, const double *v64, i64 nk,
+                       i64 max_total, i64 max_fib, const void *zhat, int ldz, void *M,
+                       unsigned *bnd, unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent,
+                       int lfac, hipStream_t s);
 size_t gather_bkt_count_words();
 int gather_bktl_shift(int R, i64 nk);
 void launch_gather_bktl(bool f64, const DevState *st, int R, const u64 *cpos,
                         const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
                         const uint2 *pairs, const int *ik, const double *v64, i64 nk,
                         i64 max_total, const void *zhat, int ldz, void *M, unsigned *cnt,
-                        u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s);
+                        u64 *off, void *scan_scratch, uint4 *bent, unsigned lmin, hipStream_t s);
 void launch_gather_bkt(bool f64, const DevState *st, int R, const u64 *cpos,
                        const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
                        const uint2 *pairs, const int *ik, const double *v64, i64 nk,
@@ -908,7 +914,9 @@ cpal_status ensure_tile_buffers(cpal_ctx *c) {
 }
 
 bool uses_tile(const cpal_ctx *c, int k, int sort_min) {
-  return sort_min == -3 && c->tile_bnd && tile_capable(c, k);
+  return (sort_min == -3 && c->tile_bnd && tile_capable(c, k)) ||
+         (sort_min == -5 && c->tile_bnd && c->bk_ent && tile_capable(c, k) &&
+          bucket_lds_capable(c, k));
 }
 
 // TnsrSamp + sampled MTTKRP (Sec. 6.3, eq. (1.2)) into M.  sort_min < 0
@@ -923,16 +931,21 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
     launch_dense_mttkrp(c->zdt, c->st, md.n, R, c->ldz, md.dld, c->cidx, c->samp_idx, md.dX,
                         c->zhat, c->dpart, kc, (int)((c->s + kc - 1) / kc), c->M, s);
   }
+  else if (sort_min == -5 && uses_tile(c, k, sort_min))
+    launch_gather_hyb(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
+                      md.ik, md.v64, md.n, c->nnz, c->s, c->zhat, c->ldz, c->M, c->tile_bnd,
+                      c->bk_cnt, c->bk_off, c->bk_scan, c->bk_ent, grid > 0 && grid <= 256 ? grid : 16,
+                      s);
   else if (uses_tile(c, k, sort_min))
     launch_gather_tile(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, md.n,
-                       c->s, c->zhat, c->ldz, c->M, c->tile_bnd, s);
+                       c->s, c->zhat, c->ldz, c->M, c->tile_bnd, 0u, s);
   else if (uses_owner(c, k, sort_min))
     launch_gather_own(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, md.n,
                       c->zhat, c->ldz, c->M, c->own_bnd, s);
   else if (sort_min == -4 && c->bk_ent && bucket_lds_capable(c, k))
     launch_gather_bktl(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                        md.ik, md.v64, md.n, c->nnz, c->zhat, c->ldz, c->M, c->bk_cnt, c->bk_off,
-                       c->bk_scan, c->bk_ent, s);
+                       c->bk_scan, c->bk_ent, 0u, s);
   else if (sort_min == -1 && c->bk_ent && bucket_capable(c, k))
     launch_gather_bkt(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                       md.ik, md.v64, md.n, c->nnz, c->zhat, c->ldz, c->M, grid, c->bk_cnt,
@@ -1083,7 +1096,7 @@ cpal_status cp_arls_lev_mode_update(cpal_ctx *c, int32_t k, cpal_mode_stats *sta
 }
 
 cpal_status cp_arls_lev_set_gather_config(cpal_ctx *c, int32_t k, int32_t grid, int32_t sort_min) {
-  if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < -4)
+  if (!c || k < 0 || k >= c->D || grid < 0 || grid > (1 << 20) || sort_min < -5)
     return CPAL_E_ARG;
   if (c->dense && grid > c->dnch) return CPAL_E_ARG;
   if (sort_min == -1) {   // the bucketed gather
@@ -1100,6 +1113,12 @@ cpal_status cp_arls_lev_set_gather_config(cpal_ctx *c, int32_t k, int32_t grid, 
     if (!bucket_lds_capable(c, k)) return CPAL_E_ARG;
     const cpal_status st = ensure_bucket_buffers(c);
     if (st != CPAL_OK) return fail(c, st, "bucketed gather: buffers");
+  }
+  if (sort_min == -5) {   // the hybrid gather: tile (long fibers) + shared-block bucketed
+    if (!tile_capable(c, k) || !bucket_lds_capable(c, k) || grid > 256) return CPAL_E_ARG;
+    cpal_status st = ensure_tile_buffers(c);
+    if (st == CPAL_OK) st = ensure_bucket_buffers(c);
+    if (st != CPAL_OK) return fail(c, st, "hybrid gather: buffers");
   }
   if (sort_min == -3) {   // the tile gather
     if (!tile_capable(c, k)) return CPAL_E_ARG;
@@ -1157,18 +1176,21 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
     const bool bkt = bucket_capable(c, k) && ensure_bucket_buffers(c) == CPAL_OK;
     const bool own = owner_capable(c, k) && ensure_owner_buffers(c) == CPAL_OK;
     const bool tile = tile_capable(c, k) && ensure_tile_buffers(c) == CPAL_OK;
-    // candidates: ng grids x ns sort thresholds, then the single-shape
-    // owner (-2), tile (-3) and shared-block bucketed (-4) gathers
-    std::vector<int> extra;
-    if (own) extra.push_back(-2);
-    if (tile) extra.push_back(-3);
-    if (bkt && bucket_lds_capable(c, k)) extra.push_back(-4);
+    // candidates: ng grids x ns sort thresholds, then the owner (-2), tile
+    // (-3), shared-block bucketed (-4) and hybrid (-5, three long-fiber
+    // thresholds) gathers
+    std::vector<std::pair<int, int>> extra;   // (grid, sort_min)
+    if (own) extra.push_back({0, -2});
+    if (tile) extra.push_back({0, -3});
+    if (bkt && bucket_lds_capable(c, k)) extra.push_back({0, -4});
+    if (tile && bkt && bucket_lds_capable(c, k))
+      for (int lf : {8, 16, 32}) extra.push_back({lf, -5});
     const int ng = 4, ns = seg ? (bkt ? 5 : 4) : 1;
     for (int gi = 0; gi < ng + (int)extra.size() && res == CPAL_OK; ++gi)
       for (int si = 0; si < (gi < ng ? ns : 1) && res == CPAL_OK; ++si) {
-        const int grid = gi >= ng ? 0
+        const int grid = gi >= ng ? extra[gi - ng].first
                        : c->dense ? dense_grids[gi] : seg ? seg_grids[gi] : flat_grids[gi];
-        const int smin = gi >= ng ? extra[gi - ng] : !seg ? 0 : si < 4 ? seg_sort[si] : -1;
+        const int smin = gi >= ng ? extra[gi - ng].second : !seg ? 0 : si < 4 ? seg_sort[si] : -1;
         float tmin = 1e30f;
         for (int r = 0; r < reps; ++r) {
           launch_zero_words(c->M, mwords, c->stream);
@@ -1637,7 +1659,8 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
       for (int k = 0; k < c->D; ++k) {
         need_bkt |= b->ctx[src]->mode[k].g_sort_min == -1 || b->ctx[src]->mode[k].g_sort_min == -4;
         need_own |= b->ctx[src]->mode[k].g_sort_min == -2;
-        need_tile |= b->ctx[src]->mode[k].g_sort_min == -3;
+        need_tile |= b->ctx[src]->mode[k].g_sort_min == -3 || b->ctx[src]->mode[k].g_sort_min == -5;
+        need_bkt |= b->ctx[src]->mode[k].g_sort_min == -5;
       }
       const bool bkt_ok = need_bkt && ensure_bucket_buffers(c) == CPAL_OK;
       const bool own_ok = need_own && ensure_owner_buffers(c) == CPAL_OK;
@@ -1647,7 +1670,8 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
         if ((sm == -1 && !(bkt_ok && bucket_capable(c, k))) ||
             (sm == -4 && !(bkt_ok && bucket_lds_capable(c, k))) ||
             (sm == -2 && !(own_ok && owner_capable(c, k))) ||
-            (sm == -3 && !(tile_ok && tile_capable(c, k)))) {
+            (sm == -3 && !(tile_ok && tile_capable(c, k))) ||
+            (sm == -5 && !(tile_ok && bkt_ok && tile_capable(c, k) && bucket_lds_capable(c, k)))) {
           c->mode[k].g_grid = 0;
           c->mode[k].g_sort_min = 0;
         } else {

@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(256) k_gather(const DevState *st, int R,
 static_assert(GT_CHUNK == CPAL_GATHER_CHUNK, "gather chunk must match the preparation's");
 // A chunk's window holds the fibers starting inside it (at most GT_CHUNK)
 // and the one overlapping its first position.
-#define GT_WIN (GT_CHUNK + 8)
+#define GT_WIN (GT_CHUNK + 8)   // the chunk's fiber starts and the end of its last fiber
 
 // Segmented gather: workgroup g takes the chunks g, g + G, ... of GT_CHUNK
 // stream positions; for a chunk
@@ -441,28 +441,33 @@ struct BktRec<double> {
 };
 
 // Calls f(ik, x, KRP row) for every position of stream chunk ch (the chunk's
-// fiber starts are staged in win; positions find their fiber there).
+// fiber starts are staged in win; positions find their fiber there) whose
+// fiber is shorter than lmin nonzeros (lmin = 0: every position); the other
+// positions load nothing from the nonzeros (they re-read the chunk's first
+// one, a cached line).
 template <typename T, typename F>
 __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
                                          const u64 *__restrict__ cpos,
                                          const unsigned *__restrict__ coff,
                                          const unsigned *__restrict__ cidx,
                                          const unsigned *__restrict__ chunk_first,
-                                         const NzLoad<T> &nz, u64 *win, F &&f) {
+                                         const NzLoad<T> &nz, u64 *win, unsigned lmin, F &&f) {
   const int tid = threadIdx.x;
   const i64 base = ch * GT_CHUNK;
   const i64 last = min(total, base + GT_CHUNK) - 1;
   const i64 jlo = chunk_first[ch];
   const i64 jhi = (ch + 1 < nch) ? (i64)chunk_first[ch + 1] : nf - 1;
-  const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1 <= GT_WIN
+  const int nwin = (int)(jhi - jlo + 1);   // <= GT_CHUNK + 1, plus the end below
   __syncthreads();   // the previous chunk is finished with win
-  for (int e = tid; e < nwin; e += BK_THREADS) win[e] = cpos[jlo + e];
+  for (int e = tid; e <= nwin; e += BK_THREADS)
+    win[e] = jlo + e < nf ? cpos[jlo + e] : (u64)total;
   __syncthreads();
   // all BK_PER positions of the thread are located first, then every load
   // is issued before any is used (positions past the chunk are clamped to
   // its last one and skipped at the end)
   int jw[BK_PER];
   u64 pp[BK_PER];
+  bool keep[BK_PER];
 #pragma unroll
   for (int u = 0; u < BK_PER; ++u) {
     const u64 p = (u64)min(base + (i64)u * BK_THREADS + tid, last);
@@ -473,11 +478,13 @@ __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
     }
     jw[u] = lo;
     pp[u] = p - win[lo];
+    keep[u] = base + (i64)u * BK_THREADS + tid <= last &&
+              (lmin == 0u || win[lo + 1] - win[lo] < (u64)lmin);
   }
   unsigned zr[BK_PER];
 #pragma unroll
   for (int u = 0; u < BK_PER; ++u) {
-    pp[u] += coff[jlo + jw[u]];
+    pp[u] = keep[u] ? pp[u] + coff[jlo + jw[u]] : (u64)coff[jlo];
     zr[u] = cidx[jlo + jw[u]];
   }
   int ik[BK_PER];
@@ -486,7 +493,7 @@ __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
   for (int u = 0; u < BK_PER; ++u) nz.get(pp[u], ik[u], x[u]);
 #pragma unroll
   for (int u = 0; u < BK_PER; ++u)
-    if (base + (i64)u * BK_THREADS + tid <= last) f(ik[u], x[u], zr[u]);
+    if (keep[u]) f(ik[u], x[u], zr[u]);
 }
 
 // Workgroup w takes the consecutive chunks [w cpw, (w + 1) cpw) of the stream
@@ -496,7 +503,7 @@ template <typename T>
 __global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    int bshift, int nb, unsigned *__restrict__ cnt) {
+    int bshift, int nb, unsigned lmin, unsigned *__restrict__ cnt) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned h[BK_BUCKETS];
   const i64 total = st->gathered, nf = st->n_fib;
@@ -505,7 +512,7 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
   const i64 c0 = (i64)blockIdx.x * cpw, c1 = min(nch, c0 + cpw);
   for (int b = threadIdx.x; b < nb; b += BK_THREADS) h[b] = 0u;
   for (i64 ch = c0; ch < c1; ++ch)
-    bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win,
+    bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win, lmin,
                 [&](int ik, T, unsigned) { atomicAdd(&h[(unsigned)ik >> bshift], 1u); });
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += BK_THREADS)
@@ -517,7 +524,7 @@ template <typename T>
 __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    int bshift, int nb, const u64 *__restrict__ off, uint4 *__restrict__ bent) {
+    int bshift, int nb, unsigned lmin, const u64 *__restrict__ off, uint4 *__restrict__ bent) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned cur[BK_BUCKETS];
   const i64 total = st->gathered, nf = st->n_fib;
@@ -527,7 +534,7 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
   for (int b = threadIdx.x; b < nb; b += BK_THREADS)
     cur[b] = (unsigned)off[(i64)b * gridDim.x + blockIdx.x];
   for (i64 ch = c0; ch < c1; ++ch)
-    bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win,
+    bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win, lmin,
                 [&](int ik, T x, unsigned zr) {
                   const unsigned pos = atomicAdd(&cur[(unsigned)ik >> bshift], 1u);
                   bent[pos] = BktRec<T>::make(ik, x, zr);   // one 16-byte store
@@ -595,10 +602,10 @@ static void launch_gather_bkt_t(const DevState *st, int R, const u64 *cpos, cons
   const i64 chunks = (max_total + GT_CHUNK - 1) / GT_CHUNK;
   const int gb = (int)std::min<i64>(BK_GRID, std::max<i64>(64, (chunks + 7) / 8));
   hipLaunchKernelGGL(k_bkt_count<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, nz, bshift, nb, cnt);
+                     chunk_first, nz, bshift, nb, 0u, cnt);
   scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, nullptr, scan_scratch, s);
   hipLaunchKernelGGL(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, nz, bshift, nb, off, bent);
+                     chunk_first, nz, bshift, nb, 0u, off, bent);
   const int rm = gather_row_width(R);
   auto k = rm == 16 ? k_gather_bkt<T, 16, 1>
                     : rm == 32 ? k_gather_bkt<T, 16, 2> : k_gather_bkt<T, 32, 2>;
@@ -666,12 +673,12 @@ __global__ void __launch_bounds__(BL_THREADS) k_gather_bktl(
   __shared__ unsigned sst[BL_MAXNB + 1];   // first slice of each bucket
   constexpr int NW = BL_THREADS / 64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const unsigned total = (unsigned)st->gathered;
+  // the records: off[nb gb] of them (the scan's total)
+  const unsigned total = (unsigned)off[(u64)nb * (u64)gb];
   // slice length: at least BL_SLICE records, and about BL_SLICES slices in
   // all, so that the per-slice block flush stays small against the adds
   const unsigned slen = max((unsigned)BL_SLICE, (total + BL_SLICES - 1) / BL_SLICES);
-  for (int b = tid; b <= nb; b += BL_THREADS)
-    bst[b] = b < nb ? (unsigned)off[(u64)b * (u64)gb] : total;
+  for (int b = tid; b <= nb; b += BL_THREADS) bst[b] = (unsigned)off[(u64)b * (u64)gb];
   __syncthreads();
   {   // slices per bucket, two buckets per thread (nb <= 2 BL_THREADS)
     const int b0 = 2 * tid, b1 = b0 + 1;
@@ -744,16 +751,18 @@ static void launch_gather_bktl_t(const DevState *st, int R, const u64 *cpos, con
                                  const unsigned *cidx, const unsigned *chunk_first, NzLoad<T> nz,
                                  i64 nk, i64 max_total, const T *zhat, int ldz, T *M,
                                  unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent,
-                                 hipStream_t s) {
+                                 unsigned lmin, hipStream_t s) {
   const int bshift = gather_bktl_shift(R, nk);
   const int nb = (int)((nk + (1ll << bshift) - 1) >> bshift);
   const i64 chunks = (max_total + GT_CHUNK - 1) / GT_CHUNK;
   const int gb = (int)std::min<i64>(BK_GRID, std::max<i64>(64, (chunks + 7) / 8));
   hipLaunchKernelGGL(k_bkt_count<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, nz, bshift, nb, cnt);
-  scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, nullptr, scan_scratch, s);
+                     chunk_first, nz, bshift, nb, lmin, cnt);
+  // the scan also writes the number of records after the last bucket's
+  // counts (off[nb gb]): with lmin > 0 it is below the stream length
+  scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, off + (i64)nb * gb, scan_scratch, s);
   hipLaunchKernelGGL(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, nz, bshift, nb, off, bent);
+                     chunk_first, nz, bshift, nb, lmin, off, bent);
   const size_t smem = ((size_t)1 << bshift) * (size_t)(R | 1) * 8;
   const i64 slices = max_total / BL_SLICE + nb + 1;
   const int grid = (int)std::min<i64>(512, std::max<i64>(1, slices));
@@ -765,15 +774,15 @@ void launch_gather_bktl(bool f64, const DevState *st, int R, const u64 *cpos,
                         const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
                         const uint2 *pairs, const int *ik, const double *v64, i64 nk,
                         i64 max_total, const void *zhat, int ldz, void *M, unsigned *cnt,
-                        u64 *off, void *scan_scratch, uint4 *bent, hipStream_t s) {
+                        u64 *off, void *scan_scratch, uint4 *bent, unsigned lmin, hipStream_t s) {
   if (f64)
     launch_gather_bktl_t<double>(st, R, cpos, coff, cidx, chunk_first, NzLoad<double>{ik, v64},
                                  nk, max_total, (const double *)zhat, ldz, (double *)M, cnt, off,
-                                 scan_scratch, bent, s);
+                                 scan_scratch, bent, lmin, s);
   else
     launch_gather_bktl_t<float>(st, R, cpos, coff, cidx, chunk_first, NzLoad<float>{pairs}, nk,
                                 max_total, (const float *)zhat, ldz, (float *)M, cnt, off,
-                                scan_scratch, bent, s);
+                                scan_scratch, bent, lmin, s);
 }
 
 // ------------------------------------------------------------ owner gather --
@@ -1020,9 +1029,10 @@ __device__ __forceinline__ i64 tile_part_start(const u64 *__restrict__ cpos, i64
 template <typename T>
 __global__ void __launch_bounds__(TB_THREADS) k_tile_bounds(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
-    RowLoad<T> rows, int rshift, int nb, u64 ldb, unsigned *__restrict__ bnd) {
+    RowLoad<T> rows, int rshift, int nb, u64 ldb, unsigned lmin, unsigned *__restrict__ bnd) {
   __shared__ unsigned tb[(TB_MAXNB + 1) * TB_FIB];   // tb[bb TB_FIB + i]
   __shared__ u64 gs[TB_FIB + 1];
+  __shared__ unsigned ge[TB_FIB + 1];   // starts in the stream of the fibers taken
   __shared__ unsigned gb[TB_FIB];
   __shared__ unsigned smin[TB_FIB * (TB_THREADS / TB_FIB)];
   const i64 nf = st->n_fib;
@@ -1036,22 +1046,31 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bounds(
   const int nent = (nb + 1) * TB_FIB;
   for (int t = tid; t < nent; t += TB_THREADS) tb[t] = 0xFFFFFFFFu;
   __syncthreads();
-  if (tid < TB_FIB) tb[nb * TB_FIB + tid] = tid < nfg ? (unsigned)(gs[tid + 1] - gs[tid]) : 0u;
-  const u64 s0 = gs[0];
-  const unsigned G = (unsigned)(gs[nfg] - s0);
+  if (tid == 0) {   // fibers shorter than lmin count as empty (lmin = 0: none)
+    unsigned acc = 0;
+    for (int i = 0; i < nfg; ++i) {
+      ge[i] = acc;
+      const unsigned len = (unsigned)(gs[i + 1] - gs[i]);
+      acc += (lmin == 0u || len >= lmin) ? len : 0u;
+    }
+    ge[nfg] = acc;
+  }
+  __syncthreads();
+  if (tid < TB_FIB) tb[nb * TB_FIB + tid] = tid < nfg ? ge[tid + 1] - ge[tid] : 0u;
+  const unsigned G = ge[nfg];
   for (unsigned q0 = 0; q0 < G; q0 += TB_THREADS * TB_PER) {
     int fi[TB_PER];
     unsigned ee[TB_PER];
 #pragma unroll
     for (int u = 0; u < TB_PER; ++u) {
       const unsigned q = min(q0 + (unsigned)(u * TB_THREADS + tid), G - 1);
-      int lo = 0, hi = nfg;   // last fiber starting at or before q
+      int lo = 0, hi = nfg;   // last fiber taken starting at or before q
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if ((unsigned)(gs[mid] - s0) <= q) lo = mid; else hi = mid;
+        if (ge[mid] <= q) lo = mid; else hi = mid;
       }
       fi[u] = lo;
-      ee[u] = q - (unsigned)(gs[lo] - s0);
+      ee[u] = q - ge[lo];
     }
     unsigned rc[TB_PER], rp[TB_PER];
 #pragma unroll
@@ -1201,10 +1220,12 @@ int gather_tile_blocks(int R, i64 nk) {
 // Bounds stride (fibers, padded to TB_FIB) for up to max_fib nonempty fibers.
 u64 gather_tile_ldb(i64 max_fib) { return (u64)((max_fib + TB_FIB - 1) / TB_FIB) * TB_FIB; }
 
+// lmin > 0: fibers shorter than lmin nonzeros are left out (their segments
+// are empty), for the hybrid gather below.
 void launch_gather_tile(bool f64, const DevState *st, int R, const u64 *cpos,
                         const unsigned *coff, const unsigned *cidx, const uint2 *pairs,
                         const int *ik, const double *v64, i64 nk, i64 max_fib, const void *zhat,
-                        int ldz, void *M, unsigned *bnd, hipStream_t s) {
+                        int ldz, void *M, unsigned *bnd, unsigned lmin, hipStream_t s) {
   const int sh = gather_tile_shift(R, nk);
   const int nb = (int)((nk + (1ll << sh) - 1) >> sh);
   const u64 ldb = gather_tile_ldb(max_fib);
@@ -1213,17 +1234,46 @@ void launch_gather_tile(bool f64, const DevState *st, int R, const u64 *cpos,
   const size_t smem = ((size_t)1 << sh) * (size_t)(R | 1) * 8;
   if (f64) {
     hipLaunchKernelGGL(k_tile_bounds<double>, gb, dim3(TB_THREADS), 0, s, st, cpos, coff,
-                       RowLoad<double>{ik}, sh, nb, ldb, bnd);
+                       RowLoad<double>{ik}, sh, nb, ldb, lmin, bnd);
     hipLaunchKernelGGL(k_gather_tile<double>, gt, dim3(TL_THREADS), smem, s, st, R, cpos, coff,
                        cidx, bnd, ldb, sh, NzLoad<double>{ik, v64}, (const double *)zhat, ldz,
                        (double *)M, nk);
   } else {
     hipLaunchKernelGGL(k_tile_bounds<float>, gb, dim3(TB_THREADS), 0, s, st, cpos, coff,
-                       RowLoad<float>{pairs}, sh, nb, ldb, bnd);
+                       RowLoad<float>{pairs}, sh, nb, ldb, lmin, bnd);
     hipLaunchKernelGGL(k_gather_tile<float>, gt, dim3(TL_THREADS), smem, s, st, R, cpos, coff,
                        cidx, bnd, ldb, sh, NzLoad<float>{pairs}, (const float *)zhat, ldz,
                        (float *)M, nk);
   }
+}
+
+// Hybrid gather: the tile gather takes the fibers of at least lmin nonzeros
+// (their per-block segments are long: lmin / blocks nonzeros on average) and
+// stores every row of the 8 copies of M; the shared-block bucketed gather
+// then adds the nonzeros of the shorter fibers (bucketed, so that their short
+// segments cost no per-segment work).  lmin = lfac times the tile gather's
+// row blocks.
+unsigned gather_hyb_lmin(int R, i64 nk, int lfac) {
+  return (unsigned)std::max(1, lfac) * (unsigned)std::max(1, gather_tile_blocks(R, nk));
+}
+
+void launch_gather_bktl(bool f64, const DevState *st, int R, const u64 *cpos,
+                        const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
+                        const uint2 *pairs, const int *ik, const double *v64, i64 nk,
+                        i64 max_total, const void *zhat, int ldz, void *M, unsigned *cnt,
+                        u64 *off, void *scan_scratch, uint4 *bent, unsigned lmin, hipStream_t s);
+
+void launch_gather_hyb(bool f64, const DevState *st, int R, const u64 *cpos,
+                       const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
+                       const uint2 *pairs, const int *ik, const double *v64, i64 nk,
+                       i64 max_total, i64 max_fib, const void *zhat, int ldz, void *M,
+                       unsigned *bnd, unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent,
+                       int lfac, hipStream_t s) {
+  const unsigned lmin = gather_hyb_lmin(R, nk, lfac);
+  launch_gather_tile(f64, st, R, cpos, coff, cidx, pairs, ik, v64, nk, max_fib, zhat, ldz, M, bnd,
+                     lmin, s);
+  launch_gather_bktl(f64, st, R, cpos, coff, cidx, chunk_first, pairs, ik, v64, nk, max_total,
+                     zhat, ldz, M, cnt, off, scan_scratch, bent, lmin, s);
 }
 
 int gather_row_width(int R);

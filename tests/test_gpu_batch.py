@@ -56,6 +56,13 @@ def test_batch_mixed_parity(graphs):
             b.autotune()
             log("autotuned: " + str([members[i].gather_config(k) for i in range(len(tensor_of))
                                      for k in range(len(tensors_np[tensor_of[i]].dims))]))
+            # a restart runs the launch shapes tuned on the first decomposition
+            # of its tensor (the gather form's buffers allocated for it too)
+            for i in range(1, len(tensor_of)):
+                if tensor_of[i] == tensor_of[i - 1]:
+                    for k in range(len(tensors_np[tensor_of[i]].dims)):
+                        assert members[i].gather_config(k) == members[i - 1].gather_config(k), \
+                            f"decomposition {i} mode {k}: launch shape not taken from its tensor"
         for k in range(max_order):
             refs = {}
             for i, t in enumerate(tensor_of):

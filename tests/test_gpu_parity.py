@@ -394,6 +394,45 @@ def test_bucketed_shared_block_gather(gather, case):
                label=f"bktl-{gather}-{case}", gather_config=(0, -4))
 
 
+def _zipf3(seed=61):
+    """3-way Zipf(1.2) coordinates (3000 x 400 x 300, 4e5 nonzeros): fiber
+    lengths from one to thousands in every mode."""
+    dims = (3000, 400, 300)
+    rng = np.random.default_rng([seed, 5])
+    samplers = [synth._zipf_sampler(rng, n, 1.2) for n in dims]
+    coords = synth._distinct_first(dims, lambda b: np.stack([sm(b) for sm in samplers]).astype(np.int32),
+                                   400_000, batch=1 << 19)
+    vals = rng.random(coords.shape[1]) + 0.5
+    return synth.SparseTensor(dims, coords, vals)
+
+
+@pytest.mark.parametrize("gather,lfac,case", [("f64", 8, "zipf3"), ("f64", 32, "zipf3"),
+                                               ("f64", 16, "long_short"), ("f64", 16, "uber4"),
+                                               ("f32", 16, "zipf3")])
+def test_hybrid_gather(gather, lfac, case):
+    """The hybrid gather: fibers of at least lfac x (row blocks) nonzeros
+    through the tile gather, which stores every row of M, then the shorter
+    ones through the shared-block bucketed gather, which adds into it (its
+    count and scatter passes skip the long fibers, its reduction takes the
+    record count from the scan); FP64 at the 1e-10 bar."""
+    if case == "zipf3":
+        T = _zipf3()
+        R, s, tau, n = 8, 4096, 1 / 4096, 6
+        fac = concentrated(T.dims, R, 62)
+    elif case == "long_short":
+        dims = (3000, 4, 3)
+        T = synth.random_sparse(dims, 30_000, seed=51)
+        R, s, tau, n = 3, 256, 1 / 256, 6
+        fac = concentrated(dims, R, 52)
+    else:
+        T = synth.uber4(0)
+        R, s, tau, n = 25, 1 << 17, 2.0 ** -17, 4
+        fac = synth.gaussian_factors(T.dims, R, 0)
+    log(f"hybrid gather {gather}, threshold factor {lfac}, {case}")
+    run_parity(T, fac, R, s, tau, n, gather, 1e-10 if gather == "f64" else "derived",
+               label=f"hyb-{gather}-{lfac}-{case}", gather_config=(lfac, -5))
+
+
 @pytest.mark.parametrize("which", ["multitile", "rank40"])
 def test_fp64_updates_bit_reproducible(which):
     """FP64 mode updates (owner gather, earliest draw carrying each repeated
@@ -426,13 +465,13 @@ def test_fp64_updates_bit_reproducible(which):
 
 def test_gather_config_errors():
     """Argument checks of the launch-shape calls: negative grids, sort
-    thresholds below -4, a dense split beyond the default, modes out of
+    thresholds below -5, a dense split beyond the default, modes out of
     range; FP64 contexts start on the owner gather (-2)."""
     from paper_2006_16438_amd._lib import CpalError
     T, _, R = synth.small3(0)
     fac = synth.gaussian_factors(T.dims, R, 0)
     ctx, _ = make_ctx(T, fac, R, 1024, gather="f64")
-    for args in ((0, -1, 0), (0, 64, -5), (3, 64, 0), (-1, 64, 0)):
+    for args in ((0, -1, 0), (0, 64, -6), (0, 300, -5), (3, 64, 0), (-1, 64, 0)):
         with pytest.raises(CpalError):
             ctx.set_gather_config(*args)
     assert ctx.gather_config(0)[1] == -2
@@ -444,6 +483,8 @@ def test_gather_config_errors():
     assert ctx.gather_config(2)[1] == -3
     ctx.set_gather_config(1, 0, -4)     # and the shared-block bucketed gather
     assert ctx.gather_config(1)[1] == -4
+    ctx.set_gather_config(0, 16, -5)    # and the hybrid gather
+    assert ctx.gather_config(0) == (16, -5)
     ctx.close()
     ctx, _ = make_ctx(T, fac, R, 1024, gather="f32")
     ctx.set_gather_config(1, 256, -1)   # the bucketed gather exists in FP32 mode
@@ -462,4 +503,6 @@ def test_gather_config_errors():
         ctx.set_gather_config(0, 1, -3)   # nor a tile gather
     with pytest.raises(CpalError):
         ctx.set_gather_config(0, 1, -4)
+    with pytest.raises(CpalError):
+        ctx.set_gather_config(0, 1, -5)
     ctx.close()
