@@ -70,18 +70,26 @@ def recorded_traffic(root):
     return rec.get("traffic_bytes_per_launch") if rec else None
 
 
-def recorded_stage_traffic(root, name, forms=None):
+def form_key(mode, grid, sort_min):
+    """Key of a mode's gather form in the recorded traffic table (the
+    hybrid gather's grid is its long-fiber factor and changes the split)."""
+    return f"{mode}:{sort_min}:{grid}" if sort_min == -5 else f"{mode}:{sort_min}"
+
+
+def recorded_stage_traffic(root, name, cfg):
     """HBM bytes per update of a gather stage from a committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs, scaled by a plain copy's
-    counters), or None when the kernel source has changed since or the
-    summary was taken with other gather forms per mode."""
+    counters): the mean over the modes of each mode's recorded traffic with
+    the gather form it ran (cfg: (grid, sort_min) per mode), or None when the
+    kernel source has changed since or a mode's form was not recorded."""
     rec = recorded_counters(root, name)
     if not rec:
         return None
-    if forms is not None and rec.get("gather_forms") is not None \
-            and list(rec["gather_forms"]) != list(forms):
+    table = rec.get("traffic_bytes_per_mode_form", {})
+    vals = [table.get(form_key(m, g, sm)) for m, (g, sm) in enumerate(cfg)]
+    if any(v is None for v in vals):
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return sum(vals) / len(vals)
 
 
 def log(msg):
@@ -118,6 +126,9 @@ def main():
                          "default on for batch256 and large1e9 (where the bucketed gather wins), "
                          "off for uber4 and dense1000 (whose default shapes measured as fast as "
                          "the tuned ones)")
+    ap.add_argument("--gather-forms", default=None, metavar="G:S,G:S,...",
+                    help="large1e9: set each mode's gather launch shape (grid:sort_min) instead "
+                         "of autotuning (for counter runs of a given configuration)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of MB mebibytes (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -795,7 +806,12 @@ def bench_large(args):
             for k in range(3):
                 ctx.mode_update(k, stats=False)
         torch.cuda.synchronize()
-        if tune:   # launch shapes timed on the warmed-up state
+        if args.gather_forms:   # given launch shapes
+            for k, f in enumerate(args.gather_forms.split(",")):
+                g, sm = (int(v) for v in f.split(":"))
+                ctx.set_gather_config(k, g, sm)
+            log(f"{gather}: gather shapes set to {[ctx.gather_config(k) for k in range(3)]}")
+        elif tune:   # launch shapes timed on the warmed-up state
             t1 = time.time()
             cfg = ctx.autotune()
             log(f"{gather}: autotuned gather shapes {cfg} in {time.time() - t1:.1f}s")
@@ -884,11 +900,11 @@ def bench_large(args):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": recorded_stage_traffic(ROOT, "gather_large1e9_f64_traffic.txt",
-                                              [sm for _, sm in r64["cfg"]]),
-            "traffic_note": "HBM bytes per FP64 gather stage from the committed FETCH_SIZE / "
-                            "WRITE_SIZE runs (profiles/gather_large1e9_f64_traffic.txt), reported "
-                            "while k_gather.hip is unchanged and the modes ran the gather forms "
-                            "recorded there",
+                                              r64["cfg"]),
+            "traffic_note": "HBM bytes per FP64 gather stage, mean over the modes of each mode's "
+                            "traffic with the gather form it ran, from the committed FETCH_SIZE / "
+                            "WRITE_SIZE runs (profiles/gather_large1e9_f64_traffic.txt); null once "
+                            "k_gather.hip has changed or for a form not recorded there",
             "algorithmic_bytes_per_launch": r64["gbytes"] / updates,
             "avg_launch_us": 1e3 * r64["g_ms"] / max(r64["g_cnt"], 1),
             "timed_with": "HIP events on the library's stream around the gather stage of "
