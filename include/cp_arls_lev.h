@@ -268,13 +268,13 @@ cpal_status cp_arls_lev_stage_times(cpal_ctx *ctx, double *ms_host, int64_t *cou
  * copies of M from its part of the sampled fibers, and the copies are added
  * in a fixed order, so the update's result does not depend on timing (it
  * allocates 4 bytes per sample and row block).  sort_min = -3 selects the
- * tile gather (grid unused; modes of at most 2^20 rows cut into at most 1023
+ * tile gather (grid unused; modes of 1024 to 2^20 rows cut into 32 to 1023
  * blocks of up to 512 rows): workgroup (row block, fiber part) adds the
  * block's segment of each of its fibers into an FP64 block of M in shared
  * memory and stores the block into one of the 8 copies (it allocates 4 bytes
  * per sample and row block).  sort_min = -4 selects the bucketed gather with
- * shared-memory buckets (grid unused; buckets of up to 512 rows, at most
- * 2048 of them; the bucketed gather's buffers): each bucket's records are
+ * shared-memory buckets (grid unused; modes of at least 1024 rows, buckets of
+ * up to 512 rows, at most 2048 of them; the bucketed gather's buffers): each bucket's records are
  * added into an FP64 block in shared memory slice by slice, and each slice's
  * block into M.  sort_min = -5 selects the hybrid of the two (grid = the
  * long-fiber factor f in [0, 256], 0: 16; both gathers' limits and
@@ -305,7 +305,9 @@ cpal_status cp_arls_lev_get_gather_config(const cpal_ctx *ctx, int32_t k, int32_
  * shared-block bucketed and hybrid (f = 8, 16, 32) gathers, whose buffers it
  * allocates where they fit;
  * for dense tensors the default split of the sampled fibers and 1/2, 1/4,
- * 1/8 of it) with HIP events, best of `reps` runs each (0: 2, at most 16),
+ * 1/8 of it) with HIP events, best of `reps` runs each (0: 2, at most 16;
+ * every candidate once per round, so that clock changes during the trials
+ * affect all alike),
  * and keeps the fastest shape for the mode, a later candidate replacing an
  * earlier one only when at least 3% faster (in FP64 contexts a shape other
  * than the owner gather gives up bit-for-bit reproducibility for speed).  Every trial samples at the current step; afterwards the step

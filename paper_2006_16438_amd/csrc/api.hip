@@ -855,9 +855,11 @@ bool bucket_capable(const cpal_ctx *c, int k) {
 }
 
 // The bucketed gather with shared-memory bucket blocks (buckets of up to 512
-// rows, at most BL_MAXNB of them).
+// rows, at most BL_MAXNB of them; modes of at least 1024 rows, where the
+// slices of the buckets keep the chip busy).
 bool bucket_lds_capable(const cpal_ctx *c, int k) {
-  return bucket_capable(c, k) && gather_bktl_shift(c->R, c->mode[k].n) >= 0;
+  return bucket_capable(c, k) && c->mode[k].n >= 1024 &&
+         gather_bktl_shift(c->R, c->mode[k].n) >= 0;
 }
 
 // The owner gather writes every row of the CPAL_MCOPIES copies of M (sparse
@@ -895,9 +897,12 @@ bool uses_owner(const cpal_ctx *c, int k, int sort_min) {
 }
 
 // The tile gather writes every row of the CPAL_MCOPIES copies of M (sparse
-// modes of at most TB_MAXNB row blocks).
+// modes of at most TB_MAXNB row blocks).  Its workgroups are (row block,
+// fiber part) pairs: modes of fewer than 32 blocks (1024 rows) would leave
+// most of the chip idle, and are left to the other gathers.
 bool tile_capable(const cpal_ctx *c, int k) {
-  return !c->dense && c->mode[k].n <= (1 << 20) && gather_tile_blocks(c->R, c->mode[k].n) > 0;
+  const int nb = c->dense || c->mode[k].n > (1 << 20) ? -1 : gather_tile_blocks(c->R, c->mode[k].n);
+  return nb >= 32;
 }
 
 cpal_status ensure_tile_buffers(cpal_ctx *c) {
@@ -1186,28 +1191,37 @@ cpal_status cp_arls_lev_autotune(cpal_ctx *c, int32_t reps) {
     if (tile && bkt && bucket_lds_capable(c, k))
       for (int lf : {8, 16, 32}) extra.push_back({lf, -5});
     const int ng = 4, ns = seg ? (bkt ? 5 : 4) : 1;
-    for (int gi = 0; gi < ng + (int)extra.size() && res == CPAL_OK; ++gi)
-      for (int si = 0; si < (gi < ng ? ns : 1) && res == CPAL_OK; ++si) {
-        const int grid = gi >= ng ? extra[gi - ng].first
-                       : c->dense ? dense_grids[gi] : seg ? seg_grids[gi] : flat_grids[gi];
-        const int smin = gi >= ng ? extra[gi - ng].second : !seg ? 0 : si < 4 ? seg_sort[si] : -1;
-        float tmin = 1e30f;
-        for (int r = 0; r < reps; ++r) {
-          launch_zero_words(c->M, mwords, c->stream);
-          hipEventRecord(e0, c->stream);
-          update_gather(c, k, grid, smin);
-          hipEventRecord(e1, c->stream);
-          if (hipEventSynchronize(e1) != hipSuccess) {
-            res = check_hip(c, hipGetLastError(), "autotune trial");
-            break;
-          }
-          float ms = 0.f;
-          hipEventElapsedTime(&ms, e0, e1);
-          tmin = std::min(tmin, ms);
+    std::vector<std::pair<int, int>> cand;   // (grid, sort_min), in order of preference
+    for (int gi = 0; gi < ng; ++gi)
+      for (int si = 0; si < ns; ++si)
+        cand.push_back({c->dense ? dense_grids[gi] : seg ? seg_grids[gi] : flat_grids[gi],
+                        !seg ? 0 : si < 4 ? seg_sort[si] : -1});
+    cand.insert(cand.end(), extra.begin(), extra.end());
+    // every candidate once per round, `reps` rounds, best time of each: a
+    // drift of the clocks during the trials (a cold GPU speeding up) then
+    // affects all candidates alike
+    std::vector<float> tmin(cand.size(), 1e30f);
+    for (int r = 0; r < reps && res == CPAL_OK; ++r)
+      for (size_t ci = 0; ci < cand.size() && res == CPAL_OK; ++ci) {
+        launch_zero_words(c->M, mwords, c->stream);
+        hipEventRecord(e0, c->stream);
+        update_gather(c, k, cand[ci].first, cand[ci].second);
+        hipEventRecord(e1, c->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          res = check_hip(c, hipGetLastError(), "autotune trial");
+          break;
         }
-        // a later candidate replaces the best one only when it is at least
-        // 3% faster, so that near ties resolve the same way from run to run
-        if (tmin < 0.97f * best) { best = tmin; best_grid = grid; best_sort = smin; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        tmin[ci] = std::min(tmin[ci], ms);
+      }
+    // a later candidate replaces the best one only when it is at least 3%
+    // faster, so that near ties resolve the same way from run to run
+    for (size_t ci = 0; ci < cand.size(); ++ci)
+      if (tmin[ci] < 0.97f * best) {
+        best = tmin[ci];
+        best_grid = cand[ci].first;
+        best_sort = cand[ci].second;
       }
     md.g_grid = best_grid;
     md.g_sort_min = best_sort;

@@ -150,8 +150,19 @@ def run_parity(T, fac, R, s, tau, updates, gather="f64", ftol=1e-10, seed=0, str
                       sampling=sampling)
     D = len(T.dims)
     if gather_config is not None:
+        from paper_2006_16438_amd._lib import CpalError
+        took = []
         for m in range(D):
-            ctx.set_gather_config(m, *gather_config)
+            try:
+                ctx.set_gather_config(m, *gather_config)
+                took.append(m)
+            except CpalError:
+                # the row-block gathers (sort_min -3 to -5) need modes of at
+                # least 1024 rows; the other modes keep their default
+                if gather_config[1] > -3:
+                    raise
+        assert took, f"no mode of {T.dims} takes gather form {gather_config}"
+        log(f"  {label}: gather form {gather_config} in modes {took}")
     if autotune:
         before = [f.cpu().numpy().copy() for f in F]
         lev0 = [ctx.leverage(m).cpu().numpy() for m in range(D)]

@@ -328,76 +328,61 @@ def test_owner_gather_fp32(case):
                gather_config=(0, -2))
 
 
-@pytest.mark.parametrize("gather,case", [("f64", "long_short"), ("f64", "multitile"),
-                                          ("f64", "rank40"), ("f64", "uber4"),
-                                          ("f32", "multitile"), ("f32", "uber4")])
-def test_tile_gather(gather, case):
-    """The tile gather (workgroup (row block, fiber part) adds the segments of
-    its part's fibers in its block into a shared FP64 row block, one
-    nonzero per lane): row blocks of 32 to 512 rows, one-block modes,
-    windows of more than one workgroup of fibers, R > 32 (three 16-column
-    groups), the benchmark workload at full size; FP64 at the 1e-10 bar."""
+def _rowblock_case(case):
+    """Workloads of the row-block gathers (modes of at least 1024 rows take
+    them): one long-fiber 3000-row mode; 2100- and 1100-row modes of 66 and
+    35 blocks with a 300-row mode beside them; R = 40 (three 16-column
+    groups) on a 1500-row mode; the Uber-shaped workload at full size."""
     if case == "long_short":
         dims = (3000, 4, 3)
         T = synth.random_sparse(dims, 30_000, seed=51)
-        R, s, tau, n = 3, 256, 1 / 256, 6
-        fac = concentrated(dims, R, 52)
-    elif case == "multitile":
-        dims = (700, 300, 257)
+        return T, 3, 256, 1 / 256, 6, concentrated(dims, 3, 52)
+    if case == "multiblock":
+        dims = (2100, 300, 1100)
         T = synth.random_sparse(dims, 150_000, seed=21)
-        R, s, tau, n = 8, 8192 + 77, 1 / 8192, 6
-        fac = concentrated(dims, R, 22)
-    elif case == "rank40":
-        dims = (900, 40, 35)
+        return T, 8, 8192 + 77, 1 / 8192, 6, concentrated(dims, 8, 22)
+    if case == "rank40":
+        dims = (1500, 40, 35)
         T = synth.random_sparse(dims, 200_000, seed=23)
-        R, s, tau, n = 40, 4096, 1 / 4096, 6
-        fac = concentrated(dims, R, 22)
-    else:
-        T = synth.uber4(0)
-        R, s, tau, n = 25, 1 << 17, 2.0 ** -17, 4
-        fac = synth.gaussian_factors(T.dims, R, 0)
+        return T, 40, 4096, 1 / 4096, 6, concentrated(dims, 40, 22)
+    T = synth.uber4(0)
+    return T, 25, 1 << 17, 2.0 ** -17, 4, synth.gaussian_factors(T.dims, 25, 0)
+
+
+@pytest.mark.parametrize("gather,case", [("f64", "long_short"), ("f64", "multiblock"),
+                                          ("f64", "rank40"), ("f64", "uber4"),
+                                          ("f32", "multiblock"), ("f32", "uber4")])
+def test_tile_gather(gather, case):
+    """The tile gather (workgroup (row block, fiber part) adds the segments of
+    its part's fibers in its block into a shared FP64 row block, one
+    nonzero per lane): row blocks of 32 to 512 rows, windows of more than
+    one workgroup of fibers, R > 32, the benchmark workload at full size;
+    FP64 at the 1e-10 bar."""
+    T, R, s, tau, n, fac = _rowblock_case(case)
     log(f"tile gather {gather}, {case}")
     run_parity(T, fac, R, s, tau, n, gather, 1e-10 if gather == "f64" else "derived",
                label=f"tile-{gather}-{case}", gather_config=(0, -3))
 
 
-@pytest.mark.parametrize("gather,case", [("f64", "long_short"), ("f64", "multitile"),
+@pytest.mark.parametrize("gather,case", [("f64", "long_short"), ("f64", "multiblock"),
                                           ("f64", "rank40"), ("f64", "uber4"),
-                                          ("f32", "multitile"), ("f32", "uber4")])
+                                          ("f32", "multiblock"), ("f32", "uber4")])
 def test_bucketed_shared_block_gather(gather, case):
     """The bucketed gather with shared-memory bucket blocks (buckets of up to
     512 rows; the records of a bucket cut into slices, each slice added into
     a shared FP64 block and then into M): one-bucket and many-bucket modes,
     slices of several workgroup passes, R > 32, the benchmark workload at
     full size; FP64 at the 1e-10 bar."""
-    if case == "long_short":
-        dims = (3000, 4, 3)
-        T = synth.random_sparse(dims, 30_000, seed=51)
-        R, s, tau, n = 3, 256, 1 / 256, 6
-        fac = concentrated(dims, R, 52)
-    elif case == "multitile":
-        dims = (700, 300, 257)
-        T = synth.random_sparse(dims, 150_000, seed=21)
-        R, s, tau, n = 8, 8192 + 77, 1 / 8192, 6
-        fac = concentrated(dims, R, 22)
-    elif case == "rank40":
-        dims = (900, 40, 35)
-        T = synth.random_sparse(dims, 200_000, seed=23)
-        R, s, tau, n = 40, 4096, 1 / 4096, 6
-        fac = concentrated(dims, R, 22)
-    else:
-        T = synth.uber4(0)
-        R, s, tau, n = 25, 1 << 17, 2.0 ** -17, 4
-        fac = synth.gaussian_factors(T.dims, R, 0)
+    T, R, s, tau, n, fac = _rowblock_case(case)
     log(f"shared-block bucketed gather {gather}, {case}")
     run_parity(T, fac, R, s, tau, n, gather, 1e-10 if gather == "f64" else "derived",
                label=f"bktl-{gather}-{case}", gather_config=(0, -4))
 
 
 def _zipf3(seed=61):
-    """3-way Zipf(1.2) coordinates (3000 x 400 x 300, 4e5 nonzeros): fiber
+    """3-way Zipf(1.2) coordinates (3000 x 1200 x 300, 4e5 nonzeros): fiber
     lengths from one to thousands in every mode."""
-    dims = (3000, 400, 300)
+    dims = (3000, 1200, 300)
     rng = np.random.default_rng([seed, 5])
     samplers = [synth._zipf_sampler(rng, n, 1.2) for n in dims]
     coords = synth._distinct_first(dims, lambda b: np.stack([sm(b) for sm in samplers]).astype(np.int32),
@@ -465,8 +450,9 @@ def test_fp64_updates_bit_reproducible(which):
 
 def test_gather_config_errors():
     """Argument checks of the launch-shape calls: negative grids, sort
-    thresholds below -5, a dense split beyond the default, modes out of
-    range; FP64 contexts start on the owner gather (-2)."""
+    thresholds below -5, row-block gathers (-3 to -5) on modes of fewer than
+    1024 rows, a dense split beyond the default, modes out of range; FP64
+    contexts start on the owner gather (-2)."""
     from paper_2006_16438_amd._lib import CpalError
     T, _, R = synth.small3(0)
     fac = synth.gaussian_factors(T.dims, R, 0)
@@ -479,12 +465,20 @@ def test_gather_config_errors():
     assert ctx.gather_config(0) == (64, 4)
     ctx.set_gather_config(0, 256, -1)   # the bucketed gather exists in FP64 mode too
     assert ctx.gather_config(0) == (256, -1)
-    ctx.set_gather_config(2, 0, -3)     # and the tile gather
-    assert ctx.gather_config(2)[1] == -3
-    ctx.set_gather_config(1, 0, -4)     # and the shared-block bucketed gather
-    assert ctx.gather_config(1)[1] == -4
-    ctx.set_gather_config(0, 16, -5)    # and the hybrid gather
+    for args in ((2, 0, -3), (1, 0, -4), (0, 16, -5)):   # modes of fewer than 1024 rows
+        with pytest.raises(CpalError):
+            ctx.set_gather_config(*args)
+    ctx.close()
+    W = synth.random_sparse((1100, 50, 40), 20_000, seed=9)   # a 1100-row mode takes them
+    ctx, _ = make_ctx(W, synth.gaussian_factors(W.dims, R, 0), R, 1024, gather="f64")
+    ctx.set_gather_config(0, 0, -3)     # the tile gather
+    assert ctx.gather_config(0)[1] == -3
+    ctx.set_gather_config(0, 0, -4)     # the shared-block bucketed gather
+    assert ctx.gather_config(0)[1] == -4
+    ctx.set_gather_config(0, 16, -5)    # the hybrid gather
     assert ctx.gather_config(0) == (16, -5)
+    with pytest.raises(CpalError):
+        ctx.set_gather_config(1, 16, -5)
     ctx.close()
     ctx, _ = make_ctx(T, fac, R, 1024, gather="f32")
     ctx.set_gather_config(1, 256, -1)   # the bucketed gather exists in FP32 mode
