@@ -514,27 +514,33 @@ def bench_batch(args):
     torch.cuda.synchronize()
     el_b = time.perf_counter() - t2
     rows_b = int(stats[:, :, 2].sum())
-    # the same batched steps replayed from captured HIP graphs (one per mode),
-    # from the initial factors: these K iterations are the decompositions' first
-    b.set_graphs(True)
-    for k in range(3):   # captures
-        b.mode_step(k)
-    torch.cuda.synchronize()
-    for i in range(n):
-        mem = b.member(i)
-        for m in range(3):
-            factors[i][m].copy_(init[i][m])
-            mem.refresh(m)
-        mem.step = 0
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for it in range(K):
-        for k in range(3):
-            b.mode_step(k, stats_buf=stats[it * 3 + k])
-    torch.cuda.synchronize()
-    el_g = time.perf_counter() - t2
+    # the same batched steps replayed from captured HIP graphs (one per mode;
+    # graph of branches, then stage-major), each from the initial factors:
+    # these K iterations are the decompositions' first
+    def replay(kind):
+        b.set_graphs(kind)
+        for k in range(3):   # captures
+            b.mode_step(k)
+        torch.cuda.synchronize()
+        for i in range(n):
+            mem = b.member(i)
+            for m in range(3):
+                factors[i][m].copy_(init[i][m])
+                mem.refresh(m)
+            mem.step = 0
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for it in range(K):
+            for k in range(3):
+                b.mode_step(k, stats_buf=stats[it * 3 + k])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t2, [b.graph_kernels(k, kind) for k in range(3)]
+    el_br, kern_br = replay(1)
+    el_g, kern_st = replay(2)
     rows_g = int(stats[:, :, 2].sum())
-    log(f"batched {K} iterations: eager {el_b * 1e3:.1f} ms, graphs {el_g * 1e3:.1f} ms")
+    log(f"batched {K} iterations: eager {el_b * 1e3:.1f} ms, graph of branches "
+        f"{el_br * 1e3:.1f} ms ({kern_br} kernels per mode step), stage-major graph "
+        f"{el_g * 1e3:.1f} ms ({kern_st} kernels per mode step)")
     # algorithmic gather bytes of the replayed steps (FP32 gather)
     st_np = stats.cpu().numpy()
     gb_all = 0.0
@@ -603,11 +609,18 @@ def bench_batch(args):
                         "rank, s=2^15, tau=2^-15, FP32 gather, FP64 solve; a step = one "
                         "iteration (3 batched mode steps)",
             "decompositions": n, "samples": s, "iterations": K,
-            "parallelism": "single GPU; one captured HIP graph per mode step (kernels of all "
-                           "decompositions on 16 streams as parallel branches)",
+            "parallelism": "single GPU; one captured stage-major HIP graph per mode step: "
+                           "one launch per stage for all 256 decompositions where the kernel "
+                           "has a batched form, the others per decomposition on 15 streams "
+                           "beside it",
             "autotuned_gather": args.tune,
         },
         "gathered_rows_per_s": rows_g / el_g,
+        "kernels_per_mode_step": kern_st,
+        "graph_of_branches": {"value": updates / el_br, "unit": "mode-updates/s",
+                              "kernels_per_mode_step": kern_br,
+                              "note": "the same batched steps replayed from a graph holding "
+                                      "each decomposition's kernels as a branch (16 streams)"},
         "eager_batched": {"value": updates / el_b, "unit": "mode-updates/s",
                           "gathered_rows_per_s": rows_b / el_b,
                           "note": "the same batched steps launched kernel by kernel"},

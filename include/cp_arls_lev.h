@@ -389,13 +389,31 @@ cpal_status cp_arls_lev_mode_step_batch(cpal_batch *batch, int32_t mode,
 /* cp_arls_lev_fit_estimate of every decomposition into fits_dev[0..n). */
 cpal_status cp_arls_lev_fit_estimate_batch(cpal_batch *batch, double *fits_dev);
 
-/* on != 0: from now on every cp_arls_lev_mode_step_batch of a mode replays
- * one HIP graph holding that mode's update of every decomposition, captured
- * on the first such call (the step counter t lives in device memory, so a
- * replay samples with the next t; statistics are copied to stats_dev after
- * the replay; stage timing is not recorded in replays).  Changing a
- * decomposition's options afterwards is not supported. */
+/* on = 1 or 2: from now on every cp_arls_lev_mode_step_batch of a mode
+ * replays one HIP graph holding that mode's update of every decomposition,
+ * captured on the first such call (the step counter t lives in device
+ * memory, so a replay samples with the next t; statistics are copied to
+ * stats_dev after the replay; stage timing is not recorded in replays).
+ *   on = 1: each decomposition's kernels as a branch of the graph (the
+ *           decompositions spread over the batch's streams);
+ *   on = 2: stage-major: the kernels of one stage of all decompositions run
+ *           as one launch where the kernel has a batched form (sampling,
+ *           KRP rows, gather preparation, segmented gather, Gram matrix
+ *           and solve, leverage), each workgroup finding its decomposition
+ *           in a table of launch arguments the capture writes to device
+ *           memory (allocated with the batch's allocator, freed when the
+ *           graph is dropped); other kernels (the bucketed, owner and tile
+ *           gathers, dense contractions) run per decomposition beside them.
+ *           Results equal those of on = 1 (same kernels, same arguments).
+ * on = 0 launches the kernels of every step again.  Changing a
+ * decomposition's options afterwards is not supported.  CPAL_E_ARG for
+ * other values of on. */
 cpal_status cp_arls_lev_batch_set_graphs(cpal_batch *batch, int32_t on);
+
+/* Kernel launches in the captured graph of `mode` (kind 1: graph of
+ * branches, kind 2: stage-major), 0 while none is captured. */
+cpal_status cp_arls_lev_batch_graph_kernels(const cpal_batch *batch, int32_t kind, int32_t mode,
+                                            int64_t *kernels);
 
 /* cp_arls_lev_autotune for the first decomposition of every tensor; the
  * other decompositions of that tensor take its launch shapes.  Graphs

@@ -26,7 +26,8 @@ SYMBOLS = (
     "cp_arls_lev_get_step", "cp_arls_lev_set_step", "cp_arls_lev_set_timing",
     "cp_arls_lev_stage_times", "cp_arls_lev_last_error", "cp_arls_lev_destroy",
     "cp_arls_lev_init_batch", "cp_arls_lev_mode_step_batch", "cp_arls_lev_fit_estimate_batch",
-    "cp_arls_lev_batch_set_graphs", "cp_arls_lev_batch_ctx", "cp_arls_lev_destroy_batch",
+    "cp_arls_lev_batch_set_graphs", "cp_arls_lev_batch_graph_kernels", "cp_arls_lev_batch_ctx",
+    "cp_arls_lev_destroy_batch",
     "cp_arls_lev_set_gather_config", "cp_arls_lev_get_gather_config", "cp_arls_lev_autotune",
     "cp_arls_lev_autotune_batch", "cp_arls_lev_fit_exact", "cp_arls_lev_run",
 )
@@ -136,6 +137,8 @@ def load(path: str | None = None):
     L.cp_arls_lev_autotune_batch.restype = C.c_int
     L.cp_arls_lev_batch_set_graphs.argtypes = [vp, C.c_int32]
     L.cp_arls_lev_batch_set_graphs.restype = C.c_int
+    L.cp_arls_lev_batch_graph_kernels.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]
+    L.cp_arls_lev_batch_graph_kernels.restype = C.c_int
     L.cp_arls_lev_batch_ctx.argtypes = [vp, C.c_int32, P(vp)]
     L.cp_arls_lev_batch_ctx.restype = C.c_int
     L.cp_arls_lev_destroy_batch.argtypes = [vp]

@@ -398,7 +398,7 @@ class CpArlsLevBatch:
         self.n = n
         self._stats = torch.zeros((n, L.STATS_BYTES // 8), dtype=torch.int64, device=self.device)
         if use_graphs:
-            self.set_graphs(True)
+            self.set_graphs(use_graphs)
 
     def autotune(self, reps=2):
         """cp_arls_lev_autotune_batch: tune the first decomposition of every
@@ -407,8 +407,19 @@ class CpArlsLevBatch:
 
     def set_graphs(self, on):
         """on: each later mode step replays the HIP graph captured for that
-        mode on its first step (kernels of all decompositions in one launch)."""
-        _check(L.load().cp_arls_lev_batch_set_graphs(self._b, 1 if on else 0))
+        mode on its first step.  True or 1: every decomposition's kernels as
+        a branch of the graph; "stages" or 2: stage-major (one launch per
+        stage for all decompositions where the kernel has a batched form);
+        False or 0: kernels launched step by step."""
+        kind = 2 if on in ("stages", 2) else (1 if on else 0)
+        _check(L.load().cp_arls_lev_batch_set_graphs(self._b, kind))
+
+    def graph_kernels(self, k, kind=2):
+        """Kernel launches in the captured graph of mode k (kind 1: branches,
+        2: stage-major; 0 while none is captured)."""
+        out = C.c_int64()
+        _check(L.load().cp_arls_lev_batch_graph_kernels(self._b, int(kind), int(k), C.byref(out)))
+        return out.value
 
     def mode_step(self, k, stats_buf=None):
         """Update mode k of every decomposition (whose tensor has > k modes);

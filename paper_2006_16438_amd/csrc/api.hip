@@ -8,8 +8,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "cpal_common.h"
@@ -141,6 +144,12 @@ void launch_fit_exact(int D, const i64 *dims, double *const *A, int R, int k, in
                       const FiberSlot *slots, u64 nslots, const uint2 *pairs, const int *ik,
                       const double *v64, const void *dX, i64 ldx, const DevState *st,
                       double *scratch, double *fit_out, hipStream_t s);
+
+// The calling thread's launch sink (cpal_launch.h).
+LaunchSink *&launch_sink() {
+  static thread_local LaunchSink *sink = nullptr;
+  return sink;
+}
 }  // namespace cpal
 
 using namespace cpal;
@@ -1463,8 +1472,11 @@ struct cpal_batch {
   std::vector<hipStream_t> streams;
   hipEvent_t start = nullptr;
   std::vector<hipEvent_t> done;
-  bool graphs = false;                              // replay captured mode steps
-  hipGraphExec_t exec[CPAL_MAXORDER] = {nullptr};   // one captured step per mode
+  int graphs = 0;   // 0: launch each step; 1 / 2: replay the step's graph of branches / stages
+  hipGraphExec_t exec[CPAL_MAXORDER] = {nullptr};    // graph of branches per mode
+  hipGraphExec_t exec2[CPAL_MAXORDER] = {nullptr};   // stage-major graph per mode
+  void *plan_mem[CPAL_MAXORDER] = {nullptr};         // its launch tables (device)
+  int64_t kernels[2][CPAL_MAXORDER] = {};            // kernel launches per captured graph
   cpal_mode_stats *stats = nullptr;                 // statistics written by the graphs
   std::vector<int> tensor_of;                       // tensor of each decomposition
   cpal_allocator al{};                              // alloc == nullptr: hipMalloc / hipFree
@@ -1477,9 +1489,26 @@ namespace {
 // 16 streams (graph replay 11.7k-11.9k either way)
 constexpr int kBatchStreams = 16;
 
+// Kernel nodes of a captured graph.
+int64_t kernel_nodes(hipGraph_t g) {
+  size_t n = 0;
+  if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess || n == 0) return 0;
+  std::vector<hipGraphNode_t> nodes(n);
+  if (hipGraphGetNodes(g, nodes.data(), &n) != hipSuccess) return 0;
+  int64_t k = 0;
+  for (size_t i = 0; i < n; ++i) {
+    hipGraphNodeType t;
+    if (hipGraphNodeGetType(nodes[i], &t) == hipSuccess && t == hipGraphNodeTypeKernel) ++k;
+  }
+  return k;
+}
+
+void drop_stage_graph(cpal_batch *b, int mode);
+
 void batch_free(cpal_batch *b) {
   for (hipGraphExec_t g : b->exec)
     if (g) hipGraphExecDestroy(g);
+  for (int m = 0; m < CPAL_MAXORDER; ++m) drop_stage_graph(b, m);
   if (b->stats) {
     if (b->al.alloc) b->al.free(b->stats, b->al.user);
     else hipFree(b->stats);
@@ -1534,7 +1563,222 @@ cpal_status batch_capture(cpal_batch *b, int mode) {
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(s0, &g);
   if (e != hipSuccess || !g) return CPAL_E_DEVICE;
+  b->kernels[0][mode] = kernel_nodes(g);
   if (res == CPAL_OK && hipGraphInstantiate(&b->exec[mode], g, nullptr, nullptr, 0) != hipSuccess)
+    res = CPAL_E_DEVICE;
+  hipGraphDestroy(g);
+  return res;
+}
+
+// ------------------------------------------------------- stage-major steps
+// A batch's mode step as a few launches per stage instead of one launch per
+// stage per decomposition: every decomposition's update is described (not
+// launched) through the launch sink, giving it a sequence of launches; the
+// launches are then issued in rounds, each taking the next launch of some
+// decompositions.  Launches of one body and block size in a round become one
+// k_multi launch over all of them (argument packs and block prefix in device
+// memory); launches without a batched form run on the batch's other streams
+// beside it.  A round starts after the previous one has finished, so each
+// decomposition's launches keep their order.
+
+// One described launch of an update.
+struct DescLaunch {
+  MultiLaunch ml = nullptr;   // batched form; nullptr: solo
+  std::vector<unsigned char> pack;
+  size_t align = 1;
+  unsigned grid = 0, block = 0;
+  size_t shmem = 0;
+  int occ = 0;                // earlier launches of the same form in the sequence
+  std::function<void(hipStream_t)> solo;
+};
+
+struct SeqSink : LaunchSink {
+  std::vector<DescLaunch> seq;
+  void batchable(MultiLaunch ml, const void *pack, size_t bytes, size_t align, unsigned grid,
+                 unsigned block, size_t shmem) override {
+    DescLaunch l;
+    l.ml = ml;
+    l.pack.assign((const unsigned char *)pack, (const unsigned char *)pack + bytes);
+    l.align = align;
+    l.grid = grid;
+    l.block = block;
+    l.shmem = shmem;
+    for (const DescLaunch &e : seq) l.occ += e.ml == ml && e.block == block;
+    seq.push_back(std::move(l));
+  }
+  void solo(std::function<void(hipStream_t)> f) override {
+    DescLaunch l;
+    l.solo = std::move(f);
+    seq.push_back(std::move(l));
+  }
+};
+
+// A batched launch of a round: launches `members` (decomposition, position)
+// of one form; its packs and prefix sit at the given offsets of the tables.
+struct MultiGroup {
+  MultiLaunch ml;
+  unsigned block;
+  size_t shmem = 0;
+  unsigned blocks = 0;
+  std::vector<std::pair<int, size_t>> members;
+  size_t packs_off = 0, pre_off = 0;
+};
+struct StageRound {
+  std::vector<MultiGroup> groups;
+  std::vector<std::pair<int, size_t>> solos;
+};
+
+// Rounds for the sequences: every solo launch at the head of a sequence runs
+// in the next round; a batched head runs once no other sequence still has
+// the same launch (form and occurrence) ahead of its head, so that launches
+// of one stage meet in one round (when every head waits, all run).
+std::vector<StageRound> plan_rounds(const std::vector<std::vector<DescLaunch>> &seqs) {
+  const size_t n = seqs.size();
+  std::vector<size_t> pos(n, 0);
+  std::vector<StageRound> rounds;
+  typedef std::tuple<MultiLaunch, unsigned, int> Form;
+  for (;;) {
+    StageRound r;
+    std::map<Form, std::vector<std::pair<int, size_t>>> heads;
+    for (size_t i = 0; i < n; ++i) {
+      if (pos[i] >= seqs[i].size()) continue;
+      const DescLaunch &h = seqs[i][pos[i]];
+      if (!h.ml) r.solos.push_back({(int)i, pos[i]});
+      else heads[Form(h.ml, h.block, h.occ)].push_back({(int)i, pos[i]});
+    }
+    if (r.solos.empty() && heads.empty()) break;
+    std::vector<const std::vector<std::pair<int, size_t>> *> ready;
+    for (const auto &kv : heads) {
+      bool wait = false;
+      for (size_t j = 0; j < n && !wait; ++j)
+        for (size_t q = pos[j] + 1; q < seqs[j].size() && !wait; ++q) {
+          const DescLaunch &e = seqs[j][q];
+          wait = Form(e.ml, e.block, e.occ) == kv.first;
+        }
+      if (!wait) ready.push_back(&kv.second);
+    }
+    if (ready.empty() && r.solos.empty())
+      for (const auto &kv : heads) ready.push_back(&kv.second);
+    for (const auto *m : ready) {
+      MultiGroup g;
+      const DescLaunch &h = seqs[(*m)[0].first][(*m)[0].second];
+      g.ml = h.ml;
+      g.block = h.block;
+      g.members = *m;
+      r.groups.push_back(std::move(g));
+    }
+    for (const auto &p : r.solos) ++pos[p.first];
+    for (const MultiGroup &g : r.groups)
+      for (const auto &p : g.members) ++pos[p.first];
+    rounds.push_back(std::move(r));
+  }
+  return rounds;
+}
+
+void drop_stage_graph(cpal_batch *b, int mode) {
+  if (b->exec2[mode]) hipGraphExecDestroy(b->exec2[mode]);
+  b->exec2[mode] = nullptr;
+  if (b->plan_mem[mode]) {
+    if (b->al.alloc) b->al.free(b->plan_mem[mode], b->al.user);
+    else hipFree(b->plan_mem[mode]);
+  }
+  b->plan_mem[mode] = nullptr;
+  b->kernels[1][mode] = 0;
+}
+
+cpal_status batch_stage_capture(cpal_batch *b, int mode) {
+  const size_t n = b->ctx.size();
+  // 1. describe every decomposition's update
+  std::vector<std::vector<DescLaunch>> seqs(n);
+  cpal_status res = CPAL_OK;
+  for (size_t i = 0; i < n; ++i) {
+    cpal_ctx *c = b->ctx[i];
+    if (mode >= c->D) continue;
+    const u64 t = c->t;
+    const unsigned timing = c->timing;
+    c->timing = 0;
+    SeqSink sink;
+    launch_sink() = &sink;
+    const cpal_status st = cp_arls_lev_mode_update(c, mode, b->stats + i);
+    launch_sink() = nullptr;
+    c->timing = timing;
+    c->t = t;
+    if (st != CPAL_OK && res == CPAL_OK) res = st;
+    seqs[i] = std::move(sink.seq);
+  }
+  if (res != CPAL_OK) return res;
+  // 2. rounds and the launch tables of their batched launches
+  std::vector<StageRound> rounds = plan_rounds(seqs);
+  std::vector<unsigned char> tab;
+  auto place = [&tab](size_t bytes) {
+    const size_t off = (tab.size() + 255) / 256 * 256;
+    tab.resize(off + bytes);
+    return off;
+  };
+  for (StageRound &r : rounds)
+    for (MultiGroup &g : r.groups) {
+      const DescLaunch &h0 = seqs[g.members[0].first][g.members[0].second];
+      const size_t stride = (h0.pack.size() + h0.align - 1) / h0.align * h0.align;
+      g.packs_off = place(stride * g.members.size());
+      for (size_t m = 0; m < g.members.size(); ++m) {
+        const DescLaunch &l = seqs[g.members[m].first][g.members[m].second];
+        std::memcpy(tab.data() + g.packs_off + m * stride, l.pack.data(), l.pack.size());
+      }
+      g.pre_off = place(sizeof(unsigned) * (g.members.size() + 1));
+      unsigned acc = 0;
+      for (size_t m = 0; m <= g.members.size(); ++m) {
+        std::memcpy(tab.data() + g.pre_off + m * sizeof(unsigned), &acc, sizeof(unsigned));
+        if (m < g.members.size()) {
+          const DescLaunch &l = seqs[g.members[m].first][g.members[m].second];
+          acc += l.grid;
+          g.shmem = std::max(g.shmem, l.shmem);
+        }
+      }
+      g.blocks = acc;
+    }
+  drop_stage_graph(b, mode);
+  void *mem = nullptr;
+  if (!tab.empty()) {
+    if (b->al.alloc) mem = b->al.alloc(tab.size(), b->al.user);
+    else if (hipMalloc(&mem, tab.size()) != hipSuccess) mem = nullptr;
+    if (!mem) return CPAL_E_NOMEM;
+    b->plan_mem[mode] = mem;
+    if (hipMemcpy(mem, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return CPAL_E_DEVICE;
+  }
+  // 3. capture the rounds: batched launches on streams[0], solo launches on
+  // the other streams (by decomposition), joined back at the end of a round
+  hipStream_t s0 = b->streams[0];
+  const size_t ns = b->streams.size();
+  if (hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed) != hipSuccess) return CPAL_E_DEVICE;
+  for (const StageRound &r : rounds) {
+    std::vector<char> used(ns, 0);
+    if (!r.solos.empty() && ns > 1) {
+      hipEventRecord(b->start, s0);
+      for (const auto &p : r.solos) {
+        const size_t j = 1 + (size_t)p.first % (ns - 1);
+        if (!used[j]) hipStreamWaitEvent(b->streams[j], b->start, 0);
+        used[j] = 1;
+      }
+    }
+    for (const auto &p : r.solos)
+      seqs[p.first][p.second].solo(ns > 1 ? b->streams[1 + (size_t)p.first % (ns - 1)] : s0);
+    for (const MultiGroup &g : r.groups)
+      if (g.blocks > 0)
+        g.ml((const unsigned char *)mem + g.packs_off,
+             (const unsigned *)((const unsigned char *)mem + g.pre_off),
+             (unsigned)g.members.size(), g.blocks, g.block, g.shmem, s0);
+    for (size_t j = 1; j < ns; ++j)
+      if (used[j]) {
+        hipEventRecord(b->done[j], b->streams[j]);
+        hipStreamWaitEvent(s0, b->done[j], 0);
+      }
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s0, &g);
+  if (e != hipSuccess || !g) return CPAL_E_DEVICE;
+  b->kernels[1][mode] = kernel_nodes(g);
+  if (hipGraphInstantiate(&b->exec2[mode], g, nullptr, nullptr, 0) != hipSuccess)
     res = CPAL_E_DEVICE;
   hipGraphDestroy(g);
   return res;
@@ -1607,13 +1851,14 @@ cpal_status cp_arls_lev_init_batch(int32_t m, const cpal_tensor *Xs, int32_t n,
 cpal_status cp_arls_lev_mode_step_batch(cpal_batch *b, int32_t mode, cpal_mode_stats *stats_dev) {
   if (!b || mode < 0 || mode >= CPAL_MAXORDER) return CPAL_E_ARG;
   if (b->graphs) {
-    if (!b->exec[mode]) {
-      const cpal_status st = batch_capture(b, mode);
+    hipGraphExec_t &ex = b->graphs == 2 ? b->exec2[mode] : b->exec[mode];
+    if (!ex) {
+      const cpal_status st = b->graphs == 2 ? batch_stage_capture(b, mode) : batch_capture(b, mode);
       if (st != CPAL_OK) return st;
     }
     hipEventRecord(b->start, b->user);
     hipStreamWaitEvent(b->streams[0], b->start, 0);
-    if (hipGraphLaunch(b->exec[mode], b->streams[0]) != hipSuccess) return CPAL_E_DEVICE;
+    if (hipGraphLaunch(ex, b->streams[0]) != hipSuccess) return CPAL_E_DEVICE;
     for (cpal_ctx *c : b->ctx)
       if (mode < c->D) {   // host state an eager step would have left
         c->t += 1;
@@ -1697,14 +1942,28 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
     }
   }
   // captured graphs hold the old launch shapes
-  for (hipGraphExec_t &g : b->exec)
-    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+  for (hipStream_t s : b->streams) hipStreamSynchronize(s);
+  for (int m = 0; m < CPAL_MAXORDER; ++m) {
+    if (b->exec[m]) hipGraphExecDestroy(b->exec[m]);
+    b->exec[m] = nullptr;
+    b->kernels[0][m] = 0;
+    drop_stage_graph(b, m);
+  }
   return CPAL_OK;
 }
 
 cpal_status cp_arls_lev_batch_set_graphs(cpal_batch *b, int32_t on) {
   if (!b) return CPAL_E_ARG;
-  b->graphs = on != 0;
+  if (on < 0 || on > 2) return CPAL_E_ARG;
+  b->graphs = on;
+  return CPAL_OK;
+}
+
+cpal_status cp_arls_lev_batch_graph_kernels(const cpal_batch *b, int32_t kind, int32_t mode,
+                                            int64_t *kernels) {
+  if (!b || !kernels || kind < 1 || kind > 2 || mode < 0 || mode >= CPAL_MAXORDER)
+    return CPAL_E_ARG;
+  *kernels = b->kernels[kind - 1][mode];
   return CPAL_OK;
 }
 

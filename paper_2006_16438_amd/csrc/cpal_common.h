@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/cp_arls_lev.h"
+#include "cpal_launch.h"
 
 #define CPAL_MAXR 64
 #define CPAL_MAXORDER 8

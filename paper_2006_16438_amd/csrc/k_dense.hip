@@ -53,12 +53,12 @@ static void dense_copy(const TI *in, TO *out, i64 A, i64 nk, i64 B, i64 ldx, hip
   if (A == 1) {
     const i64 total = B * nk;
     const i64 g = std::min<i64>((total + 255) / 256, 1 << 20);
-    hipLaunchKernelGGL((k_dense_copy_0<TI, TO>), dim3((unsigned)g), dim3(256), 0, s, in, out, nk,
-                       ldx, total);
+    launch_1((k_dense_copy_0<TI, TO>), dim3((unsigned)g), dim3(256), 0, s, in, out, nk,
+             ldx, total);
   } else {
     const i64 ta = (A + 31) / 32, tk = (nk + 31) / 32;
-    hipLaunchKernelGGL((k_dense_copy_t<TI, TO>), dim3((unsigned)(B * ta * tk)), dim3(256), 0, s,
-                       in, out, A, nk, ldx, ta, tk);
+    launch_1((k_dense_copy_t<TI, TO>), dim3((unsigned)(B * ta * tk)), dim3(256), 0, s,
+             in, out, A, nk, ldx, ta, tk);
   }
 }
 
@@ -294,20 +294,20 @@ static void launch_dense_p(const DevState *st, i64 nk, int R, int ldz, i64 ldx,
   TA *p = (TA *)part;
   // TW follows dense_tw()
   if constexpr (sizeof(TX) == 8) {
-    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    if (nr == 1) launch_1((k_dense_mttkrp<P, 1, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 2) launch_1((k_dense_mttkrp<P, 2, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 3) launch_1((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else launch_1((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
   } else if constexpr (sizeof(TX) == 4) {
-    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 4>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    if (nr == 1) launch_1((k_dense_mttkrp<P, 1, 4>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 2) launch_1((k_dense_mttkrp<P, 2, 2>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 3) launch_1((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else launch_1((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
   } else {   // BF16: one row tile per wave (dense_tw)
-    if (nr == 1) hipLaunchKernelGGL((k_dense_mttkrp<P, 1, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 2) hipLaunchKernelGGL((k_dense_mttkrp<P, 2, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else if (nr == 3) hipLaunchKernelGGL((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
-    else hipLaunchKernelGGL((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    if (nr == 1) launch_1((k_dense_mttkrp<P, 1, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 2) launch_1((k_dense_mttkrp<P, 2, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else if (nr == 3) launch_1((k_dense_mttkrp<P, 3, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
+    else launch_1((k_dense_mttkrp<P, 4, 1>), grid, dim3(DN_THREADS), 0, s, st, nk, ldz, ldx, cidx, samp_idx, x, z, p, kc);
   }
 }
 
@@ -330,11 +330,11 @@ void launch_dense_mttkrp(int xdt, const DevState *st, i64 nk, int R, int ldz, i6
   const i64 total = nk * ldz;
   const unsigned g = (unsigned)((total + 15) / 16);
   if (xdt == CPAL_F64)
-    hipLaunchKernelGGL(k_dense_reduce<double>, dim3(g), dim3(256), 0, s, st, nk, R, ldz,
-                       (const double *)part, kc, (double *)M);
+    launch_1(k_dense_reduce<double>, dim3(g), dim3(256), 0, s, st, nk, R, ldz,
+             (const double *)part, kc, (double *)M);
   else
-    hipLaunchKernelGGL(k_dense_reduce<float>, dim3(g), dim3(256), 0, s, st, nk, R, ldz,
-                       (const float *)part, kc, (float *)M);
+    launch_1(k_dense_reduce<float>, dim3(g), dim3(256), 0, s, st, nk, R, ldz,
+             (const float *)part, kc, (float *)M);
 }
 
 }  // namespace cpal

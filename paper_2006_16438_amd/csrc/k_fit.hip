@@ -252,28 +252,28 @@ static int gridc(i64 n, int blk) {
 
 void fit_build_set(const int *coords, i64 nnz, const FullModes &fm, u64 *set, u64 nslots,
                    int shift, hipStream_t s) {
-  hipLaunchKernelGGL(k_fullkey_clear, dim3(gridc((i64)nslots, 256)), dim3(256), 0, s, set, nslots);
-  hipLaunchKernelGGL(k_fullkey_insert, dim3(gridc(nnz, 256)), dim3(256), 0, s, coords, nnz, fm, set,
-                     nslots - 1, shift);
+  launch_1(k_fullkey_clear, dim3(gridc((i64)nslots, 256)), dim3(256), 0, s, set, nslots);
+  launch_1(k_fullkey_insert, dim3(gridc(nnz, 256)), dim3(256), 0, s, coords, nnz, fm, set,
+           nslots - 1, shift);
 }
 
 void fit_draw(const int *coords, const void *vals, int vdt, i64 nnz, const FullModes &fm, i64 n_nz,
               i64 n_z, u64 seed, u64 stream_id, const u64 *set, u64 nslots, int shift, u64 *ctl,
               u64 *buf, unsigned *chunk_cnt, int *sc, i64 ld, double *sx, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit_nz, dim3(gridc(n_nz, 256)), dim3(256), 0, s, coords, vals, vdt, nnz,
-                     fm.D, n_nz, seed, stream_id, sc, ld, sx);
+  launch_1(k_fit_nz, dim3(gridc(n_nz, 256)), dim3(256), 0, s, coords, vals, vdt, nnz,
+           fm.D, n_nz, seed, stream_id, sc, ld, sx);
   if (n_z > 0) {
-    hipLaunchKernelGGL(k_fit_zero_draw, dim3(1024), dim3(256), 0, s, fm, n_z, seed, stream_id, set,
-                       nslots - 1, shift, ctl, buf, chunk_cnt);
-    hipLaunchKernelGGL(k_fit_zero_finish, dim3(1), dim3(CPAL_DRAW_CHUNK), 0, s, fm, n_z, n_nz, ctl,
-                       buf, chunk_cnt, sc, ld, sx);
+    launch_1(k_fit_zero_draw, dim3(1024), dim3(256), 0, s, fm, n_z, seed, stream_id, set,
+             nslots - 1, shift, ctl, buf, chunk_cnt);
+    launch_1(k_fit_zero_finish, dim3(1), dim3(CPAL_DRAW_CHUNK), 0, s, fm, n_z, n_nz, ctl,
+             buf, chunk_cnt, sc, ld, sx);
   }
 }
 
 void fit_norm(const void *vals, int vdt, i64 nnz, double *part, DevState *st, hipStream_t s) {
   const i64 nb = (nnz + FIT_BLK - 1) / FIT_BLK;
-  hipLaunchKernelGGL(k_norm_part, dim3((unsigned)nb), dim3(FIT_BLK), 0, s, vals, vdt, nnz, part);
-  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(1024), 0, s, part, nb, st);
+  launch_1(k_norm_part, dim3((unsigned)nb), dim3(FIT_BLK), 0, s, vals, vdt, nnz, part);
+  launch_1(k_norm_final, dim3(1), dim3(1024), 0, s, part, nb, st);
 }
 
 void fit_eval(const FullModes &fm, int R, i64 n_nz, i64 n_fit, double phi_nz, double phi_z,
@@ -294,9 +294,9 @@ void fit_eval(const FullModes &fm, int R, i64 n_nz, i64 n_fit, double phi_nz, do
   else
     k = pick(k_fit_eval<64, 2>, k_fit_eval<64, 3>, k_fit_eval<64, 4>, k_fit_eval<64, 5>,
              k_fit_eval<64, 0>);
-  hipLaunchKernelGGL(k, dim3(nb), dim3(256), 0, s, fm, R, n_nz, n_fit, phi_nz, phi_z, sc, ld, sx,
-                     part);
-  hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(256), 0, s, part, nb, st, fit_out);
+  launch_1(k, dim3(nb), dim3(256), 0, s, fm, R, n_nz, n_fit, phi_nz, phi_z, sc, ld, sx,
+           part);
+  launch_1(k_fit_final, dim3(1), dim3(256), 0, s, part, nb, st, fit_out);
 }
 
 }  // namespace cpal

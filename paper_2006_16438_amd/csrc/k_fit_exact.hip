@@ -226,24 +226,24 @@ void launch_fit_exact(int D, const i64 *dims, double *const *A, int R, int k, in
   double *gpart = H + np;
   if (kind <= 1) {
     FxVals v{kind, pairs, ik, v64};
-    hipLaunchKernelGGL(k_fitx_sparse, dim3(FX_GRID), dim3(FX_THREADS), 0, s, fm, R, slots,
-                       nslots, v, part);
+    launch_1(k_fitx_sparse, dim3(FX_GRID), dim3(FX_THREADS), 0, s, fm, R, slots,
+             nslots, v, part);
   } else if (kind == 2) {
-    hipLaunchKernelGGL(k_fitx_dense<double>, dim3(FX_GRID), dim3(FX_THREADS), 0, s, fm, R,
-                       dims[k], nfib, (const double *)dX, ldx, part);
+    launch_1(k_fitx_dense<double>, dim3(FX_GRID), dim3(FX_THREADS), 0, s, fm, R,
+             dims[k], nfib, (const double *)dX, ldx, part);
   } else if (kind == 3) {
-    hipLaunchKernelGGL(k_fitx_dense<float>, dim3(FX_GRID), dim3(FX_THREADS), 0, s, fm, R,
-                       dims[k], nfib, (const float *)dX, ldx, part);
+    launch_1(k_fitx_dense<float>, dim3(FX_GRID), dim3(FX_THREADS), 0, s, fm, R,
+             dims[k], nfib, (const float *)dX, ldx, part);
   } else {
-    hipLaunchKernelGGL(k_fitx_dense<bf16s>, dim3(FX_GRID), dim3(FX_THREADS), 0, s, fm, R,
-                       dims[k], nfib, (const bf16s *)dX, ldx, part);
+    launch_1(k_fitx_dense<bf16s>, dim3(FX_GRID), dim3(FX_THREADS), 0, s, fm, R,
+             dims[k], nfib, (const bf16s *)dX, ldx, part);
   }
   for (int m = 0; m < D; ++m) {
     const int nblk = (int)((dims[m] + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
     launch_lev_gram_partial(A[m], dims[m], R, gpart, nullptr, s);
-    hipLaunchKernelGGL(k_fitx_hadamard, dim3(1), dim3(256), 0, s, gpart, nblk, R, H, m == 0 ? 1 : 0);
+    launch_1(k_fitx_hadamard, dim3(1), dim3(256), 0, s, gpart, nblk, R, H, m == 0 ? 1 : 0);
   }
-  hipLaunchKernelGGL(k_fitx_final, dim3(1), dim3(256), 0, s, part, FX_GRID, H, R, st, fit_out);
+  launch_1(k_fitx_final, dim3(1), dim3(256), 0, s, part, FX_GRID, H, R, st, fit_out);
 }
 
 }  // namespace cpal

@@ -367,10 +367,11 @@ struct LdsEntries {
 // kernel's shared memory fits twice).  Lane groups of LPN lanes, CPL columns
 // per lane (LPN * CPL = the padded row width ldz).
 template <typename T, int LPN, int CPL>
-__global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
-    const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
-    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    int ikbits, int sort_min, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+__device__ __forceinline__ void gather_seg_body(Blk bk, const DevState *st, int R,
+    const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
+    const NzLoad<T> &nz, int ikbits, int sort_min, const T *__restrict__ zhat, int ldz,
+    T *__restrict__ M, i64 nk) {
   constexpr int NG = GT_THREADS / LPN;
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned ka[GT_CHUNK], kb[GT_CHUNK];
@@ -384,7 +385,7 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
   // this XCD's copy of M: the adds of workgroups on one XCD stay in its L2
   T *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * ldz;
-  for (i64 ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+  for (i64 ch = bk.x; ch < nch; ch += bk.n) {
     const unsigned *keys = seg_load_sort<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz,
                                             ikbits, sort_min, win, ka, kb, lx, lz, tab);
     const int nvalid = (int)(min(total, (ch + 1) * GT_CHUNK) - ch * GT_CHUNK);
@@ -392,6 +393,22 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
                             GlobalAdd<T>{Mx, ldz}, srow, svec);
   }
 }
+template <typename T, int LPN, int CPL>
+__global__ void __launch_bounds__(GT_THREADS, 4) k_gather_seg(
+    const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
+    int ikbits, int sort_min, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+  gather_seg_body<T, LPN, CPL>(CPAL_BLK, st, R, cpos, coff, cidx, chunk_first, nz, ikbits, sort_min,
+    zhat, ldz, M, nk);
+}
+template <typename T, int LPN, int CPL>
+struct B_gather_seg {
+  static constexpr int NT = GT_THREADS, MW = 4;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    gather_seg_body<T, LPN, CPL>(b, a...);
+  }
+};
 
 // ----------------------------------------------------------- bucketed gather --
 // For modes whose sampled fibers are long, a stream chunk spans one or two
@@ -500,39 +517,55 @@ __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
 // in both passes, so its counts and its scatter see the same nonzeros.
 // (The count pass reads the rows only: an NzLoad whose value is never used.)
 template <typename T>
-__global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
-    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
-    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    int bshift, int nb, unsigned lmin, unsigned *__restrict__ cnt) {
+__device__ __forceinline__ void bkt_count_body(Blk bk, const DevState *st,
+    const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
+    const NzLoad<T> &nz, int bshift, int nb, unsigned lmin, unsigned *__restrict__ cnt) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned h[BK_BUCKETS];
   const i64 total = st->gathered, nf = st->n_fib;
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
-  const i64 cpw = (nch + gridDim.x - 1) / gridDim.x;
-  const i64 c0 = (i64)blockIdx.x * cpw, c1 = min(nch, c0 + cpw);
+  const i64 cpw = (nch + bk.n - 1) / bk.n;
+  const i64 c0 = (i64)bk.x * cpw, c1 = min(nch, c0 + cpw);
   for (int b = threadIdx.x; b < nb; b += BK_THREADS) h[b] = 0u;
   for (i64 ch = c0; ch < c1; ++ch)
     bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win, lmin,
                 [&](int ik, T, unsigned) { atomicAdd(&h[(unsigned)ik >> bshift], 1u); });
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += BK_THREADS)
-    cnt[(i64)b * gridDim.x + blockIdx.x] = h[b];
+    cnt[(i64)b * bk.n + bk.x] = h[b];
 }
+template <typename T>
+__global__ void __launch_bounds__(BK_THREADS) k_bkt_count(
+    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
+    int bshift, int nb, unsigned lmin, unsigned *__restrict__ cnt) {
+  bkt_count_body<T>(CPAL_BLK, st, cpos, coff, cidx, chunk_first, nz, bshift, nb, lmin, cnt);
+}
+template <typename T>
+struct B_bkt_count {
+  static constexpr int NT = BK_THREADS, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    bkt_count_body<T>(b, a...);
+  }
+};
 
 // off = exclusive scan of cnt in (bucket, workgroup) order.
 template <typename T>
-__global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
-    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
-    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    int bshift, int nb, unsigned lmin, const u64 *__restrict__ off, uint4 *__restrict__ bent) {
+__device__ __forceinline__ void bkt_scatter_body(Blk bk, const DevState *st,
+    const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
+    const NzLoad<T> &nz, int bshift, int nb, unsigned lmin, const u64 *__restrict__ off,
+    uint4 *__restrict__ bent) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned cur[BK_BUCKETS];
   const i64 total = st->gathered, nf = st->n_fib;
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
-  const i64 cpw = (nch + gridDim.x - 1) / gridDim.x;
-  const i64 c0 = (i64)blockIdx.x * cpw, c1 = min(nch, c0 + cpw);
+  const i64 cpw = (nch + bk.n - 1) / bk.n;
+  const i64 c0 = (i64)bk.x * cpw, c1 = min(nch, c0 + cpw);
   for (int b = threadIdx.x; b < nb; b += BK_THREADS)
-    cur[b] = (unsigned)off[(i64)b * gridDim.x + blockIdx.x];
+    cur[b] = (unsigned)off[(i64)b * bk.n + bk.x];
   for (i64 ch = c0; ch < c1; ++ch)
     bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win, lmin,
                 [&](int ik, T x, unsigned zr) {
@@ -540,15 +573,30 @@ __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
                   bent[pos] = BktRec<T>::make(ik, x, zr);   // one 16-byte store
                 });
 }
+template <typename T>
+__global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
+    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
+    int bshift, int nb, unsigned lmin, const u64 *__restrict__ off, uint4 *__restrict__ bent) {
+  bkt_scatter_body<T>(CPAL_BLK, st, cpos, coff, cidx, chunk_first, nz, bshift, nb, lmin, off, bent);
+}
+template <typename T>
+struct B_bkt_scatter {
+  static constexpr int NT = BK_THREADS, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    bkt_scatter_body<T>(b, a...);
+  }
+};
 
 // The bucketed nonzeros in chunks of GT_CHUNK: loaded directly, sorted on
 // the low `sortbits` bits of the row (rows of one bucket differ only there;
 // a chunk crossing a bucket boundary merges a little less, nothing else),
 // then reduced as in the segmented gather.
 template <typename T, int LPN, int CPL>
-__global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
-    const DevState *st, int R, const uint4 *__restrict__ bent, int sortbits,
-    const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+__device__ __forceinline__ void gather_bkt_body(Blk bk, const DevState *st, int R,
+    const uint4 *__restrict__ bent, int sortbits, const T *__restrict__ zhat, int ldz,
+    T *__restrict__ M, i64 nk) {
   constexpr int NG = GT_THREADS / LPN;
   __shared__ unsigned ka[GT_CHUNK], kb[GT_CHUNK];
   __shared__ T lx[GT_CHUNK];
@@ -560,7 +608,7 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
   const i64 nch = (total + GT_CHUNK - 1) / GT_CHUNK;
   T *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * ldz;
   const int tid = threadIdx.x;
-  for (i64 ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+  for (i64 ch = bk.x; ch < nch; ch += bk.n) {
     const i64 base = ch * GT_CHUNK;
     const i64 last = min(total, base + GT_CHUNK) - 1;
     __syncthreads();   // the previous chunk is finished with every shared array
@@ -582,6 +630,20 @@ __global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
                             GlobalAdd<T>{Mx, ldz}, srow, svec);
   }
 }
+template <typename T, int LPN, int CPL>
+__global__ void __launch_bounds__(GT_THREADS, 4) k_gather_bkt(
+    const DevState *st, int R, const uint4 *__restrict__ bent, int sortbits,
+    const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+  gather_bkt_body<T, LPN, CPL>(CPAL_BLK, st, R, bent, sortbits, zhat, ldz, M, nk);
+}
+template <typename T, int LPN, int CPL>
+struct B_gather_bkt {
+  static constexpr int NT = GT_THREADS, MW = 4;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    gather_bkt_body<T, LPN, CPL>(b, a...);
+  }
+};
 
 size_t gather_bkt_count_words() { return (size_t)BK_BUCKETS * BK_GRID; }
 
@@ -601,15 +663,19 @@ static void launch_gather_bkt_t(const DevState *st, int R, const u64 *cpos, cons
   const int nb = (int)((nk + (1ll << bshift) - 1) >> bshift);
   const i64 chunks = (max_total + GT_CHUNK - 1) / GT_CHUNK;
   const int gb = (int)std::min<i64>(BK_GRID, std::max<i64>(64, (chunks + 7) / 8));
-  hipLaunchKernelGGL(k_bkt_count<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, nz, bshift, nb, 0u, cnt);
+  launch_b<B_bkt_count<T>>(k_bkt_count<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                           chunk_first, nz, bshift, nb, 0u, cnt);
   scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, nullptr, scan_scratch, s);
-  hipLaunchKernelGGL(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, nz, bshift, nb, 0u, off, bent);
+  launch_b<B_bkt_scatter<T>>(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff,
+                             cidx, chunk_first, nz, bshift, nb, 0u, off, bent);
   const int rm = gather_row_width(R);
-  auto k = rm == 16 ? k_gather_bkt<T, 16, 1>
-                    : rm == 32 ? k_gather_bkt<T, 16, 2> : k_gather_bkt<T, 32, 2>;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, bent, bshift, zhat, ldz, M, nk);
+#define CPAL_BKT_LAUNCH(LPN, CPL)                                                                 \
+  launch_b<B_gather_bkt<T, LPN, CPL>>(k_gather_bkt<T, LPN, CPL>, dim3(grid), dim3(GT_THREADS), 0, \
+                                      s, st, R, bent, bshift, zhat, ldz, M, nk)
+  if (rm == 16) CPAL_BKT_LAUNCH(16, 1);
+  else if (rm == 32) CPAL_BKT_LAUNCH(16, 2);
+  else CPAL_BKT_LAUNCH(32, 2);
+#undef CPAL_BKT_LAUNCH
 }
 
 void launch_gather_bkt(bool f64, const DevState *st, int R, const u64 *cpos,
@@ -665,9 +731,9 @@ __device__ __forceinline__ void tile_add_row(double *brow, double x, const T *__
 #define BL_MAXBLK (112 * 1024)
 
 template <typename T>
-__global__ void __launch_bounds__(BL_THREADS) k_gather_bktl(
-    const DevState *st, int R, const uint4 *__restrict__ bent, const u64 *__restrict__ off,
-    int gb, int nb, int bshift, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+__device__ __forceinline__ void gather_bktl_body(Blk bk, const DevState *st, int R,
+    const uint4 *__restrict__ bent, const u64 *__restrict__ off, int gb, int nb, int bshift,
+    const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
   extern __shared__ double bl_blk[];    // (1 << bshift) rows, odd stride LDB
   __shared__ unsigned bst[BL_MAXNB + 1];   // first record of each bucket
   __shared__ unsigned sst[BL_MAXNB + 1];   // first slice of each bucket
@@ -694,7 +760,7 @@ __global__ void __launch_bounds__(BL_THREADS) k_gather_bktl(
   const unsigned nsl = sst[nb];
   const int LDB = R | 1, RB = 1 << bshift;
   T *Mx = M + (i64)(xcd_id() & (CPAL_MCOPIES - 1)) * nk * ldz;
-  for (unsigned sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
+  for (unsigned sl = bk.x; sl < nsl; sl += bk.n) {
     int b = 0, hb = nb;   // last bucket with sst[b] <= sl
     while (hb - b > 1) {
       const int mid = (b + hb) >> 1;
@@ -733,6 +799,20 @@ __global__ void __launch_bounds__(BL_THREADS) k_gather_bktl(
     __syncthreads();   // the block is read before the next slice clears it
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(BL_THREADS) k_gather_bktl(
+    const DevState *st, int R, const uint4 *__restrict__ bent, const u64 *__restrict__ off,
+    int gb, int nb, int bshift, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+  gather_bktl_body<T>(CPAL_BLK, st, R, bent, off, gb, nb, bshift, zhat, ldz, M, nk);
+}
+template <typename T>
+struct B_gather_bktl {
+  static constexpr int NT = BL_THREADS, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    gather_bktl_body<T>(b, a...);
+  }
+};
 
 // Bucket width of the shared-block bucketed gather: the largest power of two
 // <= 512 rows whose FP64 block fits BL_MAXBLK; -1 when the mode needs more
@@ -756,18 +836,18 @@ static void launch_gather_bktl_t(const DevState *st, int R, const u64 *cpos, con
   const int nb = (int)((nk + (1ll << bshift) - 1) >> bshift);
   const i64 chunks = (max_total + GT_CHUNK - 1) / GT_CHUNK;
   const int gb = (int)std::min<i64>(BK_GRID, std::max<i64>(64, (chunks + 7) / 8));
-  hipLaunchKernelGGL(k_bkt_count<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, nz, bshift, nb, lmin, cnt);
+  launch_b<B_bkt_count<T>>(k_bkt_count<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
+                           chunk_first, nz, bshift, nb, lmin, cnt);
   // the scan also writes the number of records after the last bucket's
   // counts (off[nb gb]): with lmin > 0 it is below the stream length
   scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, off + (i64)nb * gb, scan_scratch, s);
-  hipLaunchKernelGGL(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff, cidx,
-                     chunk_first, nz, bshift, nb, lmin, off, bent);
+  launch_b<B_bkt_scatter<T>>(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff,
+                             cidx, chunk_first, nz, bshift, nb, lmin, off, bent);
   const size_t smem = ((size_t)1 << bshift) * (size_t)(R | 1) * 8;
   const i64 slices = max_total / BL_SLICE + nb + 1;
   const int grid = (int)std::min<i64>(512, std::max<i64>(1, slices));
-  hipLaunchKernelGGL(k_gather_bktl<T>, dim3(grid), dim3(BL_THREADS), smem, s, st, R, bent, off,
-                     gb, nb, bshift, zhat, ldz, M, nk);
+  launch_b<B_gather_bktl<T>>(k_gather_bktl<T>, dim3(grid), dim3(BL_THREADS), smem, s, st, R, bent,
+                             off, gb, nb, bshift, zhat, ldz, M, nk);
 }
 
 void launch_gather_bktl(bool f64, const DevState *st, int R, const u64 *cpos,
@@ -821,16 +901,14 @@ struct RowLoad<double> {
 // own; the blocks after the last nonzero get the fiber length.  Each entry
 // of the fiber's row is written exactly once.
 template <typename T>
-__global__ void __launch_bounds__(256) k_own_bounds(const DevState *st,
-                                                    const u64 *__restrict__ cpos,
-                                                    const unsigned *__restrict__ coff,
-                                                    RowLoad<T> rows, int rshift, int nb,
-                                                    unsigned *__restrict__ bnd) {
+__device__ __forceinline__ void own_bounds_body(Blk bk, const DevState *st,
+    const u64 *__restrict__ cpos, const unsigned *__restrict__ coff, RowLoad<T> rows, int rshift,
+    int nb, unsigned *__restrict__ bnd) {
   const i64 nf = st->n_fib;
   const u64 total = (u64)st->gathered;
   const int lane = threadIdx.x & 63;
-  const i64 nw = ((i64)gridDim.x * blockDim.x) >> 6;
-  for (i64 f = ((i64)blockIdx.x * blockDim.x + threadIdx.x) >> 6; f < nf; f += nw) {
+  const i64 nw = ((i64)bk.n * blockDim.x) >> 6;
+  for (i64 f = ((i64)bk.x * blockDim.x + threadIdx.x) >> 6; f < nf; f += nw) {
     const u64 p0 = cpos[f];
     const unsigned len = (unsigned)((f + 1 < nf ? cpos[f + 1] : total) - p0);
     const u64 base = coff[f];
@@ -849,12 +927,28 @@ __global__ void __launch_bounds__(256) k_own_bounds(const DevState *st,
     for (int bb = carry + 1 + lane; bb <= nb; bb += 64) tb[bb] = len;
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(256) k_own_bounds(const DevState *st,
+                                                    const u64 *__restrict__ cpos,
+                                                    const unsigned *__restrict__ coff,
+                                                    RowLoad<T> rows, int rshift, int nb,
+                                                    unsigned *__restrict__ bnd) {
+  own_bounds_body<T>(CPAL_BLK, st, cpos, coff, rows, rshift, nb, bnd);
+}
+template <typename T>
+struct B_own_bounds {
+  static constexpr int NT = 256, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    own_bounds_body<T>(b, a...);
+  }
+};
 
 template <typename T, int LPN, int CPL>
-__global__ void __launch_bounds__(GT_THREADS, 2) k_gather_own(
-    const DevState *st, int R, const unsigned *__restrict__ coff,
-    const unsigned *__restrict__ cidx, const unsigned *__restrict__ bnd, int nb, int rshift,
-    NzLoad<T> nz, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+__device__ __forceinline__ void gather_own_body(Blk bk, const DevState *st, int R,
+    const unsigned *__restrict__ coff, const unsigned *__restrict__ cidx,
+    const unsigned *__restrict__ bnd, int nb, int rshift, const NzLoad<T> &nz,
+    const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
   constexpr int NG = GT_THREADS / LPN;
   constexpr int LDB = LPN * CPL + 1;   // shared row stride (odd: rows spread over banks)
   extern __shared__ char own_smem[];
@@ -868,7 +962,7 @@ __global__ void __launch_bounds__(GT_THREADS, 2) k_gather_own(
   __shared__ unsigned gst[GT_THREADS], gend[GT_THREADS], gz[GT_THREADS];
   __shared__ u64 gbase[GT_THREADS];
   const int tid = threadIdx.x;
-  const int p = (int)(blockIdx.x % OWN_PARTS), b = (int)(blockIdx.x / OWN_PARTS);
+  const int p = (int)(bk.x % OWN_PARTS), b = (int)(bk.x / OWN_PARTS);
   const int rb = 1 << rshift;
   const i64 r0 = (i64)b << rshift;
   const i64 nf = st->n_fib;
@@ -930,6 +1024,21 @@ __global__ void __launch_bounds__(GT_THREADS, 2) k_gather_own(
     Mp[(r0 + r) * ldz + c] = blk[r * LDB + c];
   }
 }
+template <typename T, int LPN, int CPL>
+__global__ void __launch_bounds__(GT_THREADS, 2) k_gather_own(
+    const DevState *st, int R, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ bnd, int nb, int rshift,
+    NzLoad<T> nz, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+  gather_own_body<T, LPN, CPL>(CPAL_BLK, st, R, coff, cidx, bnd, nb, rshift, nz, zhat, ldz, M, nk);
+}
+template <typename T, int LPN, int CPL>
+struct B_gather_own {
+  static constexpr int NT = GT_THREADS, MW = 2;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    gather_own_body<T, LPN, CPL>(b, a...);
+  }
+};
 
 // Row block of the owner gather: the largest power of two <= 512 rows whose
 // shared block (row stride ldz + 1 of the gather precision) fits OWN_BLK_BYTES,
@@ -948,6 +1057,22 @@ int gather_own_blocks(bool f64, int ldz, i64 nk) {
   return (int)((nk + (1ll << sh) - 1) >> sh);
 }
 
+template <typename T>
+static void launch_gather_own_t(int rm, dim3 grid, size_t smem, hipStream_t s, const DevState *st,
+                                int R, const u64 *cpos, const unsigned *coff, const unsigned *cidx,
+                                RowLoad<T> rows, const NzLoad<T> &nz, unsigned *bnd, int nb, int sh,
+                                const T *zhat, int ldz, T *M, i64 nk) {
+  launch_b<B_own_bounds<T>>(k_own_bounds<T>, dim3(1024), dim3(256), 0, s, st, cpos, coff, rows, sh,
+                            nb, bnd);
+#define CPAL_OWN_LAUNCH(LPN, CPL)                                                              \
+  launch_b<B_gather_own<T, LPN, CPL>>(k_gather_own<T, LPN, CPL>, grid, dim3(GT_THREADS), smem, \
+                                      s, st, R, coff, cidx, bnd, nb, sh, nz, zhat, ldz, M, nk)
+  if (rm == 16) CPAL_OWN_LAUNCH(16, 1);
+  else if (rm == 32) CPAL_OWN_LAUNCH(16, 2);
+  else CPAL_OWN_LAUNCH(32, 2);
+#undef CPAL_OWN_LAUNCH
+}
+
 void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
                        const unsigned *coff, const unsigned *cidx, const uint2 *pairs,
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz,
@@ -958,21 +1083,13 @@ void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
   const size_t smem = ((size_t)1 << sh) * (size_t)(ldz + 1) * (f64 ? 8 : 4);
   const dim3 grid((unsigned)nb * OWN_PARTS);
   if (f64) {
-    hipLaunchKernelGGL(k_own_bounds<double>, dim3(1024), dim3(256), 0, s, st, cpos, coff,
-                       RowLoad<double>{ik}, sh, nb, bnd);
-    NzLoad<double> nz{ik, v64};
-    auto k = rm == 16 ? k_gather_own<double, 16, 1>
-                      : rm == 32 ? k_gather_own<double, 16, 2> : k_gather_own<double, 32, 2>;
-    hipLaunchKernelGGL(k, grid, dim3(GT_THREADS), smem, s, st, R, coff, cidx, bnd, nb, sh, nz,
-                       (const double *)zhat, ldz, (double *)M, nk);
+    launch_gather_own_t<double>(rm, grid, smem, s, st, R, cpos, coff, cidx, RowLoad<double>{ik},
+                                NzLoad<double>{ik, v64}, bnd, nb, sh, (const double *)zhat, ldz,
+                                (double *)M, nk);
   } else {
-    hipLaunchKernelGGL(k_own_bounds<float>, dim3(1024), dim3(256), 0, s, st, cpos, coff,
-                       RowLoad<float>{pairs}, sh, nb, bnd);
-    NzLoad<float> nz{pairs};
-    auto k = rm == 16 ? k_gather_own<float, 16, 1>
-                      : rm == 32 ? k_gather_own<float, 16, 2> : k_gather_own<float, 32, 2>;
-    hipLaunchKernelGGL(k, grid, dim3(GT_THREADS), smem, s, st, R, coff, cidx, bnd, nb, sh, nz,
-                       (const float *)zhat, ldz, (float *)M, nk);
+    launch_gather_own_t<float>(rm, grid, smem, s, st, R, cpos, coff, cidx, RowLoad<float>{pairs},
+                               NzLoad<float>{pairs}, bnd, nb, sh, (const float *)zhat, ldz,
+                               (float *)M, nk);
   }
 }
 
@@ -1027,9 +1144,9 @@ __device__ __forceinline__ i64 tile_part_start(const u64 *__restrict__ cpos, i64
 // the index of the fiber's first nonzero in that block or a later one.
 #define TB_PER 4
 template <typename T>
-__global__ void __launch_bounds__(TB_THREADS) k_tile_bounds(
-    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
-    RowLoad<T> rows, int rshift, int nb, u64 ldb, unsigned lmin, unsigned *__restrict__ bnd) {
+__device__ __forceinline__ void tile_bounds_body(Blk bk, const DevState *st,
+    const u64 *__restrict__ cpos, const unsigned *__restrict__ coff, RowLoad<T> rows, int rshift,
+    int nb, u64 ldb, unsigned lmin, unsigned *__restrict__ bnd) {
   __shared__ unsigned tb[(TB_MAXNB + 1) * TB_FIB];   // tb[bb TB_FIB + i]
   __shared__ u64 gs[TB_FIB + 1];
   __shared__ unsigned ge[TB_FIB + 1];   // starts in the stream of the fibers taken
@@ -1037,7 +1154,7 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bounds(
   __shared__ unsigned smin[TB_FIB * (TB_THREADS / TB_FIB)];
   const i64 nf = st->n_fib;
   const u64 total = (u64)st->gathered;
-  const i64 f0 = (i64)blockIdx.x * TB_FIB;
+  const i64 f0 = (i64)bk.x * TB_FIB;
   if (f0 >= nf) return;
   const int nfg = (int)min((i64)TB_FIB, nf - f0);
   const int tid = threadIdx.x;
@@ -1110,17 +1227,31 @@ __global__ void __launch_bounds__(TB_THREADS) k_tile_bounds(
     bnd[(u64)bb * ldb + (u64)f0 + i2] = tb[t];
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(TB_THREADS) k_tile_bounds(
+    const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    RowLoad<T> rows, int rshift, int nb, u64 ldb, unsigned lmin, unsigned *__restrict__ bnd) {
+  tile_bounds_body<T>(CPAL_BLK, st, cpos, coff, rows, rshift, nb, ldb, lmin, bnd);
+}
+template <typename T>
+struct B_tile_bounds {
+  static constexpr int NT = TB_THREADS, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    tile_bounds_body<T>(b, a...);
+  }
+};
 
 template <typename T>
-__global__ void __launch_bounds__(TL_THREADS) k_gather_tile(
-    const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+__device__ __forceinline__ void gather_tile_body(Blk bk, const DevState *st, int R,
+    const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ bnd, u64 ldb, int rshift,
-    NzLoad<T> nz, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+    const NzLoad<T> &nz, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
   extern __shared__ double tl_blk[];   // (1 << rshift) rows, odd stride LDB
   __shared__ unsigned cs[TL_THREADS + 1], cb[TL_THREADS], cz[TL_THREADS];
   constexpr int NW = TL_THREADS / 64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int p = (int)(blockIdx.x & (CPAL_MCOPIES - 1)), b = (int)(blockIdx.x / CPAL_MCOPIES);
+  const int p = (int)(bk.x & (CPAL_MCOPIES - 1)), b = (int)(bk.x / CPAL_MCOPIES);
   const int LDB = R | 1;
   const i64 r0 = (i64)b << rshift;
   const int nrows = (int)min((i64)1 << rshift, nk - r0);
@@ -1198,6 +1329,21 @@ __global__ void __launch_bounds__(TL_THREADS) k_gather_tile(
     Mp[(r0 + r) * ldz + c] = c < R ? (T)tl_blk[r * LDB + c] : T(0);
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(TL_THREADS) k_gather_tile(
+    const DevState *st, int R, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
+    const unsigned *__restrict__ cidx, const unsigned *__restrict__ bnd, u64 ldb, int rshift,
+    NzLoad<T> nz, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+  gather_tile_body<T>(CPAL_BLK, st, R, cpos, coff, cidx, bnd, ldb, rshift, nz, zhat, ldz, M, nk);
+}
+template <typename T>
+struct B_gather_tile {
+  static constexpr int NT = TL_THREADS, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    gather_tile_body<T>(b, a...);
+  }
+};
 
 // Row block of the tile gather for a mode of nk rows: the largest power of two
 // <= 512 whose FP64 block (odd row stride) fits TL_MAXBLK, made smaller while
@@ -1233,17 +1379,17 @@ void launch_gather_tile(bool f64, const DevState *st, int R, const u64 *cpos,
   const dim3 gt((unsigned)nb * CPAL_MCOPIES);
   const size_t smem = ((size_t)1 << sh) * (size_t)(R | 1) * 8;
   if (f64) {
-    hipLaunchKernelGGL(k_tile_bounds<double>, gb, dim3(TB_THREADS), 0, s, st, cpos, coff,
-                       RowLoad<double>{ik}, sh, nb, ldb, lmin, bnd);
-    hipLaunchKernelGGL(k_gather_tile<double>, gt, dim3(TL_THREADS), smem, s, st, R, cpos, coff,
-                       cidx, bnd, ldb, sh, NzLoad<double>{ik, v64}, (const double *)zhat, ldz,
-                       (double *)M, nk);
+    launch_b<B_tile_bounds<double>>(k_tile_bounds<double>, gb, dim3(TB_THREADS), 0, s, st, cpos,
+                                    coff, RowLoad<double>{ik}, sh, nb, ldb, lmin, bnd);
+    launch_b<B_gather_tile<double>>(k_gather_tile<double>, gt, dim3(TL_THREADS), smem, s, st, R,
+                                    cpos, coff, cidx, bnd, ldb, sh, NzLoad<double>{ik, v64},
+                                    (const double *)zhat, ldz, (double *)M, nk);
   } else {
-    hipLaunchKernelGGL(k_tile_bounds<float>, gb, dim3(TB_THREADS), 0, s, st, cpos, coff,
-                       RowLoad<float>{pairs}, sh, nb, ldb, lmin, bnd);
-    hipLaunchKernelGGL(k_gather_tile<float>, gt, dim3(TL_THREADS), smem, s, st, R, cpos, coff,
-                       cidx, bnd, ldb, sh, NzLoad<float>{pairs}, (const float *)zhat, ldz,
-                       (float *)M, nk);
+    launch_b<B_tile_bounds<float>>(k_tile_bounds<float>, gb, dim3(TB_THREADS), 0, s, st, cpos,
+                                   coff, RowLoad<float>{pairs}, sh, nb, ldb, lmin, bnd);
+    launch_b<B_gather_tile<float>>(k_gather_tile<float>, gt, dim3(TL_THREADS), smem, s, st, R,
+                                   cpos, coff, cidx, bnd, ldb, sh, NzLoad<float>{pairs},
+                                   (const float *)zhat, ldz, (float *)M, nk);
   }
 }
 
@@ -1278,6 +1424,21 @@ void launch_gather_hyb(bool f64, const DevState *st, int R, const u64 *cpos,
 
 int gather_row_width(int R);
 
+template <typename T>
+static void launch_gather_seg_t(int rm, int grid, hipStream_t s, const DevState *st, int R,
+                                const u64 *cpos, const unsigned *coff, const unsigned *cidx,
+                                const unsigned *chunk_first, const NzLoad<T> &nz, int ikbits,
+                                int sort_min, const T *zhat, int ldz, T *M, i64 nk) {
+#define CPAL_SEG_LAUNCH(LPN, CPL)                                                                 \
+  launch_b<B_gather_seg<T, LPN, CPL>>(k_gather_seg<T, LPN, CPL>, dim3(grid), dim3(GT_THREADS), 0, \
+                                      s, st, R, cpos, coff, cidx, chunk_first, nz, ikbits,         \
+                                      sort_min, zhat, ldz, M, nk)
+  if (rm == 16) CPAL_SEG_LAUNCH(16, 1);
+  else if (rm == 32) CPAL_SEG_LAUNCH(16, 2);
+  else CPAL_SEG_LAUNCH(32, 2);
+#undef CPAL_SEG_LAUNCH
+}
+
 void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, const unsigned *coff,
                        const unsigned *cidx, const unsigned *chunk_first, const uint2 *pairs,
                        const int *ik, const double *v64, i64 nk, const void *zhat, int ldz, void *M,
@@ -1287,18 +1448,12 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
   const int rm = gather_row_width(R);
   if (f64) {
     NzLoad<double> nz{ik, v64};
-    auto k = rm == 16 ? k_gather_seg<double, 16, 1>
-                      : rm == 32 ? k_gather_seg<double, 16, 2> : k_gather_seg<double, 32, 2>;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
-                       chunk_first, nz, ikbits, sort_min, (const double *)zhat, ldz, (double *)M,
-                       nk);
+    launch_gather_seg_t<double>(rm, grid, s, st, R, cpos, coff, cidx, chunk_first, nz, ikbits,
+                                sort_min, (const double *)zhat, ldz, (double *)M, nk);
   } else {
     NzLoad<float> nz{pairs};
-    auto k = rm == 16 ? k_gather_seg<float, 16, 1>
-                      : rm == 32 ? k_gather_seg<float, 16, 2> : k_gather_seg<float, 32, 2>;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(GT_THREADS), 0, s, st, R, cpos, coff, cidx,
-                       chunk_first, nz, ikbits, sort_min, (const float *)zhat, ldz, (float *)M,
-                       nk);
+    launch_gather_seg_t<float>(rm, grid, s, st, R, cpos, coff, cidx, chunk_first, nz, ikbits,
+                               sort_min, (const float *)zhat, ldz, (float *)M, nk);
   }
 }
 
@@ -1311,7 +1466,7 @@ void launch_zero_words(void *p, i64 nwords, hipStream_t s) {
   if (nwords <= 0) return;
   i64 g = (nwords + 255) / 256;
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_zero_words, dim3((int)g), dim3(256), 0, s, (unsigned *)p, nwords);
+  launch_1(k_zero_words, dim3((int)g), dim3(256), 0, s, (unsigned *)p, nwords);
 }
 
 i64 gather_chunks_cap(i64 nnz) { return nnz / GT_CHUNK + 2; }
@@ -1323,12 +1478,12 @@ void launch_gather(bool f64, const DevState *st, int R, const u64 *cpos, const u
                    const void *zhat, void *M, int ldz, int grid, hipStream_t s) {
   if (f64) {
     NzLoad<double> nz{ik, v64};
-    hipLaunchKernelGGL(k_gather<double>, dim3(grid), dim3(256), 0, s, st, R, cpos, coff, cidx, nz,
-                       (const double *)zhat, (double *)M, ldz);
+    launch_1(k_gather<double>, dim3(grid), dim3(256), 0, s, st, R, cpos, coff, cidx, nz,
+             (const double *)zhat, (double *)M, ldz);
   } else {
     NzLoad<float> nz{pairs};
-    hipLaunchKernelGGL(k_gather<float>, dim3(grid), dim3(256), 0, s, st, R, cpos, coff, cidx, nz,
-                       (const float *)zhat, (float *)M, ldz);
+    launch_1(k_gather<float>, dim3(grid), dim3(256), 0, s, st, R, cpos, coff, cidx, nz,
+             (const float *)zhat, (float *)M, ldz);
   }
 }
 }  // namespace cpal

@@ -96,34 +96,34 @@ __global__ void k_mode_pairs(const u64 *__restrict__ comp, const unsigned *__res
 
 void launch_mode_keys(const int *coords, i64 nnz, int D, const OtherModes &om, i64 nk, u64 *comp,
                       unsigned *ids, int *err, hipStream_t s) {
-  hipLaunchKernelGGL(k_mode_keys, dim3(grid_for(nnz, 256)), dim3(256), 0, s, coords, nnz, D, om,
-                     nk, comp, ids, err);
+  launch_1(k_mode_keys, dim3(grid_for(nnz, 256)), dim3(256), 0, s, coords, nnz, D, om,
+           nk, comp, ids, err);
 }
 
 void launch_fiber_mark(const u64 *comp, i64 nnz, i64 nk, unsigned *flag, int *err,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_fiber_mark, dim3(grid_for(nnz, 256)), dim3(256), 0, s, comp, nnz, nk, flag,
-                     err);
+  launch_1(k_fiber_mark, dim3(grid_for(nnz, 256)), dim3(256), 0, s, comp, nnz, nk, flag,
+           err);
 }
 
 void launch_fiber_starts(const unsigned *flag, const u64 *fid, i64 nnz, unsigned *fstart,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_fiber_starts, dim3(grid_for(nnz, 256)), dim3(256), 0, s, flag, fid, nnz,
-                     fstart);
+  launch_1(k_fiber_starts, dim3(grid_for(nnz, 256)), dim3(256), 0, s, flag, fid, nnz,
+           fstart);
 }
 
 void launch_hash_build(const u64 *comp, i64 nnz, i64 nk, const unsigned *fstart, u64 nfib,
                        FiberSlot *slots, u64 nslots, int hshift, hipStream_t s) {
-  hipLaunchKernelGGL(k_slots_clear, dim3(grid_for((i64)nslots, 256)), dim3(256), 0, s, slots,
-                     nslots);
-  hipLaunchKernelGGL(k_hash_insert, dim3(grid_for((i64)nfib, 256)), dim3(256), 0, s, comp, nnz,
-                     nk, fstart, nfib, slots, nslots - 1, hshift);
+  launch_1(k_slots_clear, dim3(grid_for((i64)nslots, 256)), dim3(256), 0, s, slots,
+           nslots);
+  launch_1(k_hash_insert, dim3(grid_for((i64)nfib, 256)), dim3(256), 0, s, comp, nnz,
+           nk, fstart, nfib, slots, nslots - 1, hshift);
 }
 
 void launch_mode_pairs(const u64 *comp, const unsigned *ids, i64 nnz, i64 nk, const void *vals,
                        int vdt, uint2 *pairs, int *ik32, double *v64, hipStream_t s) {
-  hipLaunchKernelGGL(k_mode_pairs, dim3(grid_for(nnz, 256)), dim3(256), 0, s, comp, ids, nnz, nk,
-                     vals, vdt, pairs, ik32, v64);
+  launch_1(k_mode_pairs, dim3(grid_for(nnz, 256)), dim3(256), 0, s, comp, ids, nnz, nk,
+           vals, vdt, pairs, ik32, v64);
 }
 
 }  // namespace cpal

@@ -22,12 +22,11 @@ __device__ __forceinline__ void pair_of(int p, int R, int &a, int &c) {
 
 // part[b][p]: sum over the rows of block b of A(r,a)*A(r,c), pair p = (a<=c).
 #define GRAM_THREADS 512
-__global__ void __launch_bounds__(GRAM_THREADS) k_lev_gram_partial(const double *__restrict__ A, i64 n,
-                                                          int R, double *__restrict__ part,
-                                                          const int *skip) {
+__device__ __forceinline__ void lev_gram_partial_body(Blk bk, const double *__restrict__ A, i64 n,
+    int R, double *__restrict__ part, const int *skip) {
   extern __shared__ double sA[];  // CPAL_GRAM_ROWS x R
   if (skip && *skip) return;
-  const i64 r0 = (i64)blockIdx.x * CPAL_GRAM_ROWS;
+  const i64 r0 = (i64)bk.x * CPAL_GRAM_ROWS;
   const int rows = (int)min((i64)CPAL_GRAM_ROWS, n - r0);
   for (int e = threadIdx.x; e < rows * R; e += blockDim.x) sA[e] = A[r0 * R + e];
   __syncthreads();
@@ -45,9 +44,15 @@ __global__ void __launch_bounds__(GRAM_THREADS) k_lev_gram_partial(const double 
       for (int q = 0; q < 8; ++q) acc = acc + t[q];
     }
     for (; r < rows; ++r) acc = acc + sA[r * R + a] * sA[r * R + c];
-    part[(i64)blockIdx.x * np + p] = acc;
+    part[(i64)bk.x * np + p] = acc;
   }
 }
+__global__ void __launch_bounds__(GRAM_THREADS) k_lev_gram_partial(const double *__restrict__ A, i64 n,
+                                                          int R, double *__restrict__ part,
+                                                          const int *skip) {
+  lev_gram_partial_body(CPAL_BLK, A, n, R, part, skip);
+}
+CPAL_BODY(B_lev_gram_partial, GRAM_THREADS, 1, lev_gram_partial_body);
 
 // Cyclic Jacobi eigendecomposition of the symmetric matrix S (R x R, shared
 // memory), one wavefront.  Pairs (p,q) are visited row by row; the rotation
@@ -297,10 +302,9 @@ __device__ bool decomp_regs(const double *__restrict__ part, int nblk, int R,
 // Cholesky pivot test, A has full row rank, range(A) = R^n and every
 // leverage score is exactly 1; the generic kernels are then skipped (*skip =
 // 1).  Otherwise *skip = 0 and the Gram / eigen path runs.  One block.
-__global__ void __launch_bounds__(64) k_lev_rowspace(const double *__restrict__ A, int n, int R,
-                                                     double *__restrict__ lev, u64 *__restrict__ w,
-                                                     u64 *__restrict__ blocksum, int rb,
-                                                     int *skip, int *pinv_store) {
+__device__ __forceinline__ void lev_rowspace_body(Blk bk, const double *__restrict__ A, int n,
+    int R, double *__restrict__ lev, u64 *__restrict__ w, u64 *__restrict__ blocksum, int rb,
+    int *skip, int *pinv_store) {
   __shared__ double K[CPAL_MAXR * CPAL_MAXR];
   __shared__ double L[CPAL_MAXR * CPAL_MAXR];
   __shared__ double sA[CPAL_MAXR * CPAL_MAXR];   // A, n x R with n < R
@@ -335,6 +339,13 @@ __global__ void __launch_bounds__(64) k_lev_rowspace(const double *__restrict__ 
   }
   if (tid == 0) *skip = ok ? 1 : 0;
 }
+__global__ void __launch_bounds__(64) k_lev_rowspace(const double *__restrict__ A, int n, int R,
+                                                     double *__restrict__ lev, u64 *__restrict__ w,
+                                                     u64 *__restrict__ blocksum, int rb,
+                                                     int *skip, int *pinv_store) {
+  lev_rowspace_body(CPAL_BLK, A, n, R, lev, w, blocksum, rb, skip, pinv_store);
+}
+CPAL_BODY(B_lev_rowspace, 64, 1, lev_rowspace_body);
 
 // Sum the block partials in block order into G, then factor G.  One block of
 // 64 threads (one wavefront); lane i owns row i during the Cholesky sweep.
@@ -342,10 +353,9 @@ __global__ void __launch_bounds__(64) k_lev_rowspace(const double *__restrict__ 
 // ceil(*nrows_dev / rows_per_blk).  Partials are staged through shared
 // memory in slabs so that each pair's sum stays in block order.
 #define DECOMP_SLAB 4096
-__global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, int nblk,
-                                               const i64 *nrows_dev, int rows_per_blk, int R,
-                                               Decomp *__restrict__ out, int *flag_or,
-                                               int *flag_store, const int *skip) {
+__device__ __forceinline__ void decomp_body(Blk bk, const double *__restrict__ part, int nblk,
+    const i64 *nrows_dev, int rows_per_blk, int R, Decomp *__restrict__ out, int *flag_or,
+    int *flag_store, const int *skip) {
   __shared__ double G[CPAL_MAXR * CPAL_MAXR];
   __shared__ double L[CPAL_MAXR * CPAL_MAXR];
   __shared__ double slab[DECOMP_SLAB];
@@ -438,16 +448,22 @@ __global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, 
     }
   }
 }
+__global__ void __launch_bounds__(64) k_decomp(const double *__restrict__ part, int nblk,
+                                               const i64 *nrows_dev, int rows_per_blk, int R,
+                                               Decomp *__restrict__ out, int *flag_or,
+                                               int *flag_store, const int *skip) {
+  decomp_body(CPAL_BLK, part, nblk, nrows_dev, rows_per_blk, R, out, flag_or, flag_store, skip);
+}
+CPAL_BODY(B_decomp, 64, 1, decomp_body);
 
 // Parallel reduction of Gram partials (any order; used for the sampled G_s,
 // which is not part of the reproducible sampling state): out[p] = sum_b
 // part[b][p] for b < ceil(*nrows_dev / rows_per_blk).
-__global__ void __launch_bounds__(256) k_gram_reduce(const double *__restrict__ part,
-                                                     const i64 *nrows_dev, int rows_per_blk,
-                                                     int np, double *__restrict__ out) {
+__device__ __forceinline__ void gram_reduce_body(Blk bk, const double *__restrict__ part,
+    const i64 *nrows_dev, int rows_per_blk, int np, double *__restrict__ out) {
   __shared__ double red[256];
   const int nblk = (int)((*nrows_dev + rows_per_blk - 1) / rows_per_blk);
-  const int p = blockIdx.x;
+  const int p = bk.x;
   double acc = 0.0;
   for (int b = threadIdx.x; b < nblk; b += 256) acc += part[(i64)b * np + p];
   red[threadIdx.x] = acc;
@@ -458,6 +474,12 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double *__restrict__ 
   }
   if (threadIdx.x == 0) out[p] = red[0];
 }
+__global__ void __launch_bounds__(256) k_gram_reduce(const double *__restrict__ part,
+                                                     const i64 *nrows_dev, int rows_per_blk,
+                                                     int np, double *__restrict__ out) {
+  gram_reduce_body(CPAL_BLK, part, nrows_dev, rows_per_blk, np, out);
+}
+CPAL_BODY(B_gram_reduce, 256, 1, gram_reduce_body);
 
 // Leverage of the rows of A (Def. 3.4): l_i = ||L^{-1} a_i||^2 with the
 // Cholesky factor (forward substitution, y_j subtracted in ascending order,
@@ -467,12 +489,9 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double *__restrict__ 
 // operation of a row in the same order as the sequential form.  Blocks of
 // 256 threads = 256 / LPN rows.
 template <int LPN>
-__global__ void __launch_bounds__(256) k_lev_rows(const double *__restrict__ A, i64 n, int R,
-                                                  const Decomp *__restrict__ dc,
-                                                  double *__restrict__ lev,
-                                                  u64 *__restrict__ w,
-                                                  u64 *__restrict__ blocksum,
-                                                  const int *skip) {
+__device__ __forceinline__ void lev_rows_body(Blk bk, const double *__restrict__ A, i64 n, int R,
+    const Decomp *__restrict__ dc, double *__restrict__ lev, u64 *__restrict__ w,
+    u64 *__restrict__ blocksum, const int *skip) {
   extern __shared__ double sL[];          // R*R (L, or V)
   __shared__ u64 wsum[4];
   if (skip && *skip) return;
@@ -481,7 +500,7 @@ __global__ void __launch_bounds__(256) k_lev_rows(const double *__restrict__ A, 
   __syncthreads();
   const int tid = threadIdx.x, wid = tid >> 6;
   const int c = (tid & 63) % LPN;
-  const i64 row = (i64)blockIdx.x * (256 / LPN) + tid / LPN;
+  const i64 row = (i64)bk.x * (256 / LPN) + tid / LPN;
   const double etol = dc->etol;
   u64 wacc = 0;
   {
@@ -519,22 +538,36 @@ __global__ void __launch_bounds__(256) k_lev_rows(const double *__restrict__ A, 
   wacc = wave_sum(wacc);
   if ((tid & 63) == 0) wsum[wid] = wacc;
   __syncthreads();
-  if (tid == 0) blocksum[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  if (tid == 0) blocksum[bk.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
+template <int LPN>
+__global__ void __launch_bounds__(256) k_lev_rows(const double *__restrict__ A, i64 n, int R,
+                                                  const Decomp *__restrict__ dc,
+                                                  double *__restrict__ lev,
+                                                  u64 *__restrict__ w,
+                                                  u64 *__restrict__ blocksum,
+                                                  const int *skip) {
+  lev_rows_body<LPN>(CPAL_BLK, A, n, R, dc, lev, w, blocksum, skip);
+}
+template <int LPN>
+struct B_lev_rows {
+  static constexpr int NT = 256, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    lev_rows_body<LPN>(b, a...);
+  }
+};
 
 // C = inclusive prefix of w, q = w / W.  Blocks of CDF_ROWS rows; blocksum
 // holds the sums of w over consecutive groups of rb rows (rb divides
 // CDF_ROWS), nbs of them.
 #define CDF_ROWS 64
-__global__ void __launch_bounds__(CDF_ROWS) k_lev_cdf(const u64 *__restrict__ w, i64 n,
-                                                     const u64 *__restrict__ blocksum, int nbs,
-                                                     int rb, u64 *__restrict__ C,
-                                                     double *__restrict__ q, int *flag_or,
-                                                     const DevState *st, int k, int D,
-                                                     cpal_mode_stats *stats) {
+__device__ __forceinline__ void lev_cdf_body(Blk bk, const u64 *__restrict__ w, i64 n,
+    const u64 *__restrict__ blocksum, int nbs, int rb, u64 *__restrict__ C, double *__restrict__ q,
+    int *flag_or, const DevState *st, int k, int D, cpal_mode_stats *stats) {
   // the update's statistics, when asked for (this is the update's last kernel;
   // every count and flag is final by now)
-  if (stats && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (stats && bk.x == 0 && threadIdx.x == 0) {
     int fl = st->flags;
     for (int m = 0; m < D; ++m)
       if (m != k && st->lev_pinv[m]) fl |= CPAL_FLAG_PINV;
@@ -547,7 +580,7 @@ __global__ void __launch_bounds__(CDF_ROWS) k_lev_cdf(const u64 *__restrict__ w,
     stats->flags = fl;
     stats->pad = 0;
   }
-  const int lim = (int)(blockIdx.x * (CDF_ROWS / rb));
+  const int lim = (int)(bk.x * (CDF_ROWS / rb));
   u64 before = 0, all = 0;
   for (int b = threadIdx.x; b < nbs; b += blockDim.x) {
     const u64 v = blocksum[b];
@@ -556,7 +589,7 @@ __global__ void __launch_bounds__(CDF_ROWS) k_lev_cdf(const u64 *__restrict__ w,
   }
   before = wave_sum(before);
   all = wave_sum(all);
-  const i64 i = (i64)blockIdx.x * CDF_ROWS + threadIdx.x;
+  const i64 i = (i64)bk.x * CDF_ROWS + threadIdx.x;
   const u64 wi = i < n ? w[i] : 0;
   u64 tot;
   const u64 ex = block_excl_scan<u64>(wi, &tot);
@@ -566,6 +599,15 @@ __global__ void __launch_bounds__(CDF_ROWS) k_lev_cdf(const u64 *__restrict__ w,
   }
   if (i == 0 && all == 0 && flag_or) atomicOr(flag_or, CPAL_FLAG_STATE);
 }
+__global__ void __launch_bounds__(CDF_ROWS) k_lev_cdf(const u64 *__restrict__ w, i64 n,
+                                                     const u64 *__restrict__ blocksum, int nbs,
+                                                     int rb, u64 *__restrict__ C,
+                                                     double *__restrict__ q, int *flag_or,
+                                                     const DevState *st, int k, int D,
+                                                     cpal_mode_stats *stats) {
+  lev_cdf_body(CPAL_BLK, w, n, blocksum, nbs, rb, C, q, flag_or, st, k, D, stats);
+}
+CPAL_BODY(B_lev_cdf, CDF_ROWS, 1, lev_cdf_body);
 
 int lev_rows_per_block(int R) { return 256 / (R <= 16 ? 16 : (R <= 32 ? 32 : 64)); }
 
@@ -575,9 +617,8 @@ int lev_rows_per_block(int R) { return 256 / (R <= 16 ? 16 : (R <= 32 ? 32 : 64)
 // ||A(i,:)||^2 summed over columns in ascending order, total = the trace of
 // the Gram matrix summed in the canonical blocked order: block partials in
 // ascending blocks, then the diagonal in ascending column order).
-__global__ void __launch_bounds__(64) k_score_norm(const double *__restrict__ part, int nblk,
-                                                  int R, i64 n, int kind, double *norm,
-                                                  int *pinv_store) {
+__device__ __forceinline__ void score_norm_body(Blk bk, const double *__restrict__ part, int nblk,
+    int R, i64 n, int kind, double *norm, int *pinv_store) {
   if (threadIdx.x != 0) return;
   double S = (double)n;
   if (kind == 2) {
@@ -594,13 +635,17 @@ __global__ void __launch_bounds__(64) k_score_norm(const double *__restrict__ pa
   *norm = S;
   if (pinv_store) *pinv_store = 0;
 }
+__global__ void __launch_bounds__(64) k_score_norm(const double *__restrict__ part, int nblk,
+                                                  int R, i64 n, int kind, double *norm,
+                                                  int *pinv_store) {
+  score_norm_body(CPAL_BLK, part, nblk, R, n, kind, norm, pinv_store);
+}
+CPAL_BODY(B_score_norm, 64, 1, score_norm_body);
 
-__global__ void __launch_bounds__(256) k_score_rows(const double *__restrict__ A, i64 n, int R,
-                                                  int kind, const double *__restrict__ norm,
-                                                  int rb, double *__restrict__ lev,
-                                                  u64 *__restrict__ w,
-                                                  u64 *__restrict__ blocksum) {
-  const i64 i = (i64)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void score_rows_body(Blk bk, const double *__restrict__ A, i64 n, int R,
+    int kind, const double *__restrict__ norm, int rb, double *__restrict__ lev,
+    u64 *__restrict__ w, u64 *__restrict__ blocksum) {
+  const i64 i = (i64)bk.x * 256 + threadIdx.x;
   u64 wi = 0;
   if (i < n) {
     double sc = 1.0;
@@ -624,35 +669,43 @@ __global__ void __launch_bounds__(256) k_score_rows(const double *__restrict__ A
   for (int off = 1; off < rb; off <<= 1) g += __shfl_xor(g, off, 64);
   if (i < n && (i % rb) == 0) blocksum[i / rb] = g;
 }
+__global__ void __launch_bounds__(256) k_score_rows(const double *__restrict__ A, i64 n, int R,
+                                                  int kind, const double *__restrict__ norm,
+                                                  int rb, double *__restrict__ lev,
+                                                  u64 *__restrict__ w,
+                                                  u64 *__restrict__ blocksum) {
+  score_rows_body(CPAL_BLK, A, n, R, kind, norm, rb, lev, w, blocksum);
+}
+CPAL_BODY(B_score_rows, 256, 1, score_rows_body);
 
 void launch_scores(const double *A, i64 n, int R, int kind, double *part, double *norm,
                    int *pinv_store, double *lev, u64 *w, u64 *blocksum, hipStream_t s) {
   const int nblk = (int)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
   if (kind == 2) launch_lev_gram_partial(A, n, R, part, nullptr, s);
-  hipLaunchKernelGGL(k_score_norm, dim3(1), dim3(64), 0, s, part, nblk, R, n, kind, norm,
-                     pinv_store);
+  launch_b<B_score_norm>(k_score_norm, dim3(1), dim3(64), 0, s, part, nblk, R, n, kind, norm,
+                         pinv_store);
   const int rb = lev_rows_per_block(R);
-  hipLaunchKernelGGL(k_score_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, n, R,
-                     kind, norm, rb, lev, w, blocksum);
+  launch_b<B_score_rows>(k_score_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, n,
+                         R, kind, norm, rb, lev, w, blocksum);
 }
 
 void launch_lev_gram_partial(const double *A, i64 n, int R, double *part, const int *skip,
                              hipStream_t s) {
   const int nblk = (int)((n + CPAL_GRAM_ROWS - 1) / CPAL_GRAM_ROWS);
   const size_t sh = sizeof(double) * CPAL_GRAM_ROWS * R;
-  hipLaunchKernelGGL(k_lev_gram_partial, dim3(nblk), dim3(GRAM_THREADS), sh, s, A, n, R, part,
-                     skip);
+  launch_b<B_lev_gram_partial>(k_lev_gram_partial, dim3(nblk), dim3(GRAM_THREADS), sh, s, A, n, R,
+                               part, skip);
 }
 
 void launch_lev_rowspace(const double *A, int n, int R, double *lev, u64 *w, u64 *blocksum,
                          int *skip, int *pinv_store, hipStream_t s) {
-  hipLaunchKernelGGL(k_lev_rowspace, dim3(1), dim3(64), 0, s, A, n, R, lev, w, blocksum,
-                     lev_rows_per_block(R), skip, pinv_store);
+  launch_b<B_lev_rowspace>(k_lev_rowspace, dim3(1), dim3(64), 0, s, A, n, R, lev, w, blocksum,
+                           lev_rows_per_block(R), skip, pinv_store);
 }
 
 void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_store,
                    const int *skip, hipStream_t s) {
-  hipLaunchKernelGGL(k_decomp, dim3(1), dim3(64), 0, s, part, nblk, (const i64 *)nullptr, 1, R,
+  launch_b<B_decomp>(k_decomp, dim3(1), dim3(64), 0, s, part, nblk, (const i64 *)nullptr, 1, R,
                      out, (int *)nullptr, flag_store, skip);
 }
 
@@ -660,9 +713,9 @@ void launch_decomp(const double *part, int nblk, int R, Decomp *out, int *flag_s
 // (the partials of the 256-row blocks added one after another, ascending,
 // starting from zero), one thread per packed entry: the same sums k_decomp
 // forms in one wave, for factors with many blocks.
-__global__ void __launch_bounds__(256) k_gram_seq(const double *__restrict__ part, int nblk, int np,
-                                                  double *__restrict__ out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gram_seq_body(Blk bk, const double *__restrict__ part, int nblk,
+    int np, double *__restrict__ out) {
+  const int p = bk.x * blockDim.x + threadIdx.x;
   if (p >= np) return;
   double acc = 0.0;
   int b = 0;
@@ -677,6 +730,11 @@ __global__ void __launch_bounds__(256) k_gram_seq(const double *__restrict__ par
   for (; b < nblk; ++b) acc = acc + part[(i64)b * np + p];
   out[p] = acc;
 }
+__global__ void __launch_bounds__(256) k_gram_seq(const double *__restrict__ part, int nblk, int np,
+                                                  double *__restrict__ out) {
+  gram_seq_body(CPAL_BLK, part, nblk, np, out);
+}
+CPAL_BODY(B_gram_seq, 256, 1, gram_seq_body);
 
 // Decomposition of a factor's Gram matrix from nblk block partials; with many
 // blocks the partials are first summed by k_gram_seq into gram (np doubles).
@@ -684,20 +742,21 @@ void launch_decomp_blocks(const double *part, int nblk, int R, double *gram, Dec
                           int *flag_store, const int *skip, hipStream_t s) {
   const int np = R * (R + 1) / 2;
   if (nblk > 64 && gram) {
-    hipLaunchKernelGGL(k_gram_seq, dim3((np + 255) / 256), dim3(256), 0, s, part, nblk, np, gram);
+    launch_b<B_gram_seq>(k_gram_seq, dim3((np + 255) / 256), dim3(256), 0, s, part, nblk, np,
+                         gram);
     part = gram;
     nblk = 1;
   }
-  hipLaunchKernelGGL(k_decomp, dim3(1), dim3(64), 0, s, part, nblk, (const i64 *)nullptr, 1, R,
+  launch_b<B_decomp>(k_decomp, dim3(1), dim3(64), 0, s, part, nblk, (const i64 *)nullptr, 1, R,
                      out, (int *)nullptr, flag_store, skip);
 }
 
 void launch_decomp_dev(const double *part, const i64 *nrows_dev, int rows_per_blk, int R,
                        Decomp *out, int *flag_or, double *gram_tmp, hipStream_t s) {
   const int np = R * (R + 1) / 2;
-  hipLaunchKernelGGL(k_gram_reduce, dim3(np), dim3(256), 0, s, part, nrows_dev, rows_per_blk, np,
-                     gram_tmp);
-  hipLaunchKernelGGL(k_decomp, dim3(1), dim3(64), 0, s, (const double *)gram_tmp, 1,
+  launch_b<B_gram_reduce>(k_gram_reduce, dim3(np), dim3(256), 0, s, part, nrows_dev, rows_per_blk,
+                          np, gram_tmp);
+  launch_b<B_decomp>(k_decomp, dim3(1), dim3(64), 0, s, (const double *)gram_tmp, 1,
                      (const i64 *)nullptr, 1, R, out, flag_or, (int *)nullptr, (const int *)nullptr);
 }
 
@@ -706,8 +765,15 @@ void launch_lev_rows(const double *A, i64 n, int R, const Decomp *dc, double *le
   const int rb = lev_rows_per_block(R);
   const int nblk = (int)((n + rb - 1) / rb);
   const size_t sh = sizeof(double) * (size_t)R * R;
-  auto k = R <= 16 ? k_lev_rows<16> : R <= 32 ? k_lev_rows<32> : k_lev_rows<64>;
-  hipLaunchKernelGGL(k, dim3(nblk), dim3(256), sh, s, A, n, R, dc, lev, w, blocksum, skip);
+  if (R <= 16)
+    launch_b<B_lev_rows<16>>(k_lev_rows<16>, dim3(nblk), dim3(256), sh, s, A, n, R, dc, lev, w,
+                             blocksum, skip);
+  else if (R <= 32)
+    launch_b<B_lev_rows<32>>(k_lev_rows<32>, dim3(nblk), dim3(256), sh, s, A, n, R, dc, lev, w,
+                             blocksum, skip);
+  else
+    launch_b<B_lev_rows<64>>(k_lev_rows<64>, dim3(nblk), dim3(256), sh, s, A, n, R, dc, lev, w,
+                             blocksum, skip);
 }
 
 void launch_lev_cdf(const u64 *w, i64 n, int R, const u64 *blocksum, u64 *C, double *q,
@@ -716,8 +782,8 @@ void launch_lev_cdf(const u64 *w, i64 n, int R, const u64 *blocksum, u64 *C, dou
   const int rb = lev_rows_per_block(R);
   const int nbs = (int)((n + rb - 1) / rb);
   const int nblk = (int)((n + CDF_ROWS - 1) / CDF_ROWS);
-  hipLaunchKernelGGL(k_lev_cdf, dim3(nblk), dim3(CDF_ROWS), 0, s, w, n, blocksum, nbs, rb, C, q,
-                     flag_or, st, k, D, stats);
+  launch_b<B_lev_cdf>(k_lev_cdf, dim3(nblk), dim3(CDF_ROWS), 0, s, w, n, blocksum, nbs, rb, C, q,
+                      flag_or, st, k, D, stats);
 }
 
 int lev_row_blocks(i64 n) { return (int)((n + 3) / 4); }   // blocksums at 4 rows per block

@@ -88,14 +88,14 @@ __device__ __forceinline__ void gs_tiles(const double *sz, const double *som, in
 }
 
 template <typename TZ, typename TM, int DD>
-__global__ void __launch_bounds__(ROWS_BLK) k_rows(
-    OtherModes om, DevState *st, int R, u64 *__restrict__ samp_idx, double *__restrict__ samp_om,
-    double *__restrict__ samp_w, const u64 *__restrict__ dkeys, const DrawEntry *__restrict__ tab,
-    u64 tmask, int tshift, unsigned *__restrict__ tpos,
-    const FiberSlot *__restrict__ slots, u64 hmask, int hshift, unsigned dense_len,
-    TZ *__restrict__ zhat, unsigned *__restrict__ foff, unsigned *__restrict__ flen,
-    double *__restrict__ gpart, u64 *__restrict__ part_len, unsigned *__restrict__ part_cnt,
-    unsigned *__restrict__ part_act, TM *__restrict__ M, i64 mlen, int ldz) {
+__device__ __forceinline__ void rows_body(Blk bk, const OtherModes &om, DevState *st, int R,
+    u64 *__restrict__ samp_idx, double *__restrict__ samp_om, double *__restrict__ samp_w,
+    const u64 *__restrict__ dkeys, const DrawEntry *__restrict__ tab, u64 tmask, int tshift,
+    unsigned *__restrict__ tpos, const FiberSlot *__restrict__ slots, u64 hmask, int hshift,
+    unsigned dense_len, TZ *__restrict__ zhat, unsigned *__restrict__ foff,
+    unsigned *__restrict__ flen, double *__restrict__ gpart, u64 *__restrict__ part_len,
+    unsigned *__restrict__ part_cnt, unsigned *__restrict__ part_act, TM *__restrict__ M, i64 mlen,
+    int ldz) {
   extern __shared__ double sz[];           // ROWS_BLK x (R+1); phase 3 reuses it
   __shared__ double som[ROWS_BLK];
   __shared__ unsigned sim[CPAL_MAXORDER][ROWS_BLK];
@@ -105,10 +105,10 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
   const i64 s_det = st->s_det, s_used = st->s_rnd_used;
   const i64 n_slots = s_det + s_used;
   const double p_det = st->p_det;
-  if (blockIdx.x == 0 && tid == 0) st->n_slots = n_slots;
-  for (i64 e = (i64)blockIdx.x * blockDim.x + tid; e < mlen; e += (i64)gridDim.x * blockDim.x)
+  if (bk.x == 0 && tid == 0) st->n_slots = n_slots;
+  for (i64 e = (i64)bk.x * blockDim.x + tid; e < mlen; e += (i64)bk.n * blockDim.x)
     M[e] = TM(0);
-  const i64 base = (i64)blockIdx.x * ROWS_BLK;
+  const i64 base = (i64)bk.x * ROWS_BLK;
   if (base >= n_slots) return;   // uniform per block
   const int rows = (int)min((i64)ROWS_BLK, n_slots - base);
   // phase 1: the first draw-table probe, the first fiber probe and the q
@@ -195,9 +195,9 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
       unsigned t = 0, f = 0;
       u64 l = 0;
       for (int q = 0; q < ROWS_BLK / 64; ++q) { t += wact[q]; f += wnf[q]; l += wln[q]; }
-      part_act[blockIdx.x] = t;
-      part_len[blockIdx.x] = l;
-      part_cnt[blockIdx.x] = f;
+      part_act[bk.x] = t;
+      part_len[bk.x] = l;
+      part_cnt[bk.x] = f;
     }
   }
   som[tid] = omj;
@@ -257,13 +257,34 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
   }
   __syncthreads();
   // phase 3
-  double *gp = gpart + (i64)blockIdx.x * (R * (R + 1) / 2);
+  double *gp = gpart + (i64)bk.x * (R * (R + 1) / 2);
   const int nt = (R + 15) / 16;
   if (nt == 1) gs_tiles<1>(sz, som, ld, R, rows, sz, gp);
   else if (nt == 2) gs_tiles<2>(sz, som, ld, R, rows, sz, gp);
   else if (nt == 3) gs_tiles<3>(sz, som, ld, R, rows, sz, gp);
   else gs_tiles<4>(sz, som, ld, R, rows, sz, gp);
 }
+template <typename TZ, typename TM, int DD>
+__global__ void __launch_bounds__(ROWS_BLK) k_rows(
+    OtherModes om, DevState *st, int R, u64 *__restrict__ samp_idx, double *__restrict__ samp_om,
+    double *__restrict__ samp_w, const u64 *__restrict__ dkeys, const DrawEntry *__restrict__ tab,
+    u64 tmask, int tshift, unsigned *__restrict__ tpos,
+    const FiberSlot *__restrict__ slots, u64 hmask, int hshift, unsigned dense_len,
+    TZ *__restrict__ zhat, unsigned *__restrict__ foff, unsigned *__restrict__ flen,
+    double *__restrict__ gpart, u64 *__restrict__ part_len, unsigned *__restrict__ part_cnt,
+    unsigned *__restrict__ part_act, TM *__restrict__ M, i64 mlen, int ldz) {
+  rows_body<TZ, TM, DD>(CPAL_BLK, om, st, R, samp_idx, samp_om, samp_w, dkeys, tab, tmask, tshift,
+    tpos, slots, hmask, hshift, dense_len, zhat, foff, flen, gpart, part_len, part_cnt, part_act, M,
+    mlen, ldz);
+}
+template <typename TZ, typename TM, int DD>
+struct B_rows {
+  static constexpr int NT = ROWS_BLK, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    rows_body<TZ, TM, DD>(b, a...);
+  }
+};
 
 
 // Gather preparation: the stream position of every fiber (exclusive prefix
@@ -278,21 +299,15 @@ __global__ void __launch_bounds__(ROWS_BLK) k_rows(
 // workgroup sums the totals before its own, workgroup 0 also stores the
 // grand totals.  It also empties the draw-table entries of its slots (every
 // entry the update filled belongs to exactly one combined row).
-__global__ void __launch_bounds__(ROWS_BLK) k_gather_prep(DevState *st,
-                                                          const unsigned *__restrict__ flen,
-                                                          const unsigned *__restrict__ foff,
-                                                          const u64 *__restrict__ part_len,
-                                                          const unsigned *__restrict__ part_cnt,
-                                                          const unsigned *__restrict__ part_act,
-                                                          u64 *__restrict__ cpos,
-                                                          unsigned *__restrict__ coff,
-                                                          unsigned *__restrict__ cidx,
-                                                          unsigned *__restrict__ chunk_first,
-                                                          const unsigned *__restrict__ tpos,
-                                                          DrawEntry *__restrict__ tab) {
+__device__ __forceinline__ void gather_prep_body(Blk bk, DevState *st,
+    const unsigned *__restrict__ flen, const unsigned *__restrict__ foff,
+    const u64 *__restrict__ part_len, const unsigned *__restrict__ part_cnt,
+    const unsigned *__restrict__ part_act, u64 *__restrict__ cpos, unsigned *__restrict__ coff,
+    unsigned *__restrict__ cidx, unsigned *__restrict__ chunk_first,
+    const unsigned *__restrict__ tpos, DrawEntry *__restrict__ tab) {
   const i64 n = st->n_slots;
   const int nb = (int)((n + ROWS_BLK - 1) / ROWS_BLK);
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int b = bk.x, tid = threadIdx.x;
   if (b >= nb && !(b == 0 && nb == 0)) return;   // uniform per block
   u64 bl = 0, al = 0, bc = 0, ac = 0, aa = 0;
   for (int q = tid; q < nb; q += ROWS_BLK) {
@@ -339,6 +354,22 @@ __global__ void __launch_bounds__(ROWS_BLK) k_gather_prep(DevState *st,
     for (u64 ch = c0; ch <= c1; ++ch) chunk_first[ch] = (unsigned)c;
   }
 }
+__global__ void __launch_bounds__(ROWS_BLK) k_gather_prep(DevState *st,
+                                                          const unsigned *__restrict__ flen,
+                                                          const unsigned *__restrict__ foff,
+                                                          const u64 *__restrict__ part_len,
+                                                          const unsigned *__restrict__ part_cnt,
+                                                          const unsigned *__restrict__ part_act,
+                                                          u64 *__restrict__ cpos,
+                                                          unsigned *__restrict__ coff,
+                                                          unsigned *__restrict__ cidx,
+                                                          unsigned *__restrict__ chunk_first,
+                                                          const unsigned *__restrict__ tpos,
+                                                          DrawEntry *__restrict__ tab) {
+  gather_prep_body(CPAL_BLK, st, flen, foff, part_len, part_cnt, part_act, cpos, coff, cidx,
+    chunk_first, tpos, tab);
+}
+CPAL_BODY(B_gather_prep, ROWS_BLK, 1, gather_prep_body);
 
 // ------------------------------------------------------------- launchers ---
 template <typename TZ, typename TM>
@@ -349,11 +380,16 @@ static void launch_rows_t(const OtherModes &om, DevState *st, int R, int nb, siz
                           unsigned *flen, double *gpart, u64 *part_len, unsigned *part_cnt,
                           unsigned *part_act, void *M, i64 mlen, int ldz, hipStream_t s) {
   const int dd = (om.d >= 2 && om.d <= 4) ? om.d : 0;
-  auto k = dd == 2 ? k_rows<TZ, TM, 2> : dd == 3 ? k_rows<TZ, TM, 3>
-         : dd == 4 ? k_rows<TZ, TM, 4> : k_rows<TZ, TM, 0>;
-  hipLaunchKernelGGL(k, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R, samp_idx, samp_om, samp_w,
-                     dkeys, tab, tmask, tshift, tpos, slots, hmask, hshift, dense_len, (TZ *)zhat,
-                     foff, flen, gpart, part_len, part_cnt, part_act, (TM *)M, mlen, ldz);
+#define CPAL_ROWS_LAUNCH(DD)                                                                    \
+  launch_b<B_rows<TZ, TM, DD>>(k_rows<TZ, TM, DD>, dim3(nb), dim3(ROWS_BLK), sh, s, om, st, R,   \
+                               samp_idx, samp_om, samp_w, dkeys, tab, tmask, tshift, tpos, slots, \
+                               hmask, hshift, dense_len, (TZ *)zhat, foff, flen, gpart, part_len, \
+                               part_cnt, part_act, (TM *)M, mlen, ldz)
+  if (dd == 2) CPAL_ROWS_LAUNCH(2);
+  else if (dd == 3) CPAL_ROWS_LAUNCH(3);
+  else if (dd == 4) CPAL_ROWS_LAUNCH(4);
+  else CPAL_ROWS_LAUNCH(0);
+#undef CPAL_ROWS_LAUNCH
 }
 
 // zdt: precision of the weighted KRP rows (CPAL_F64, CPAL_F32 or CPAL_BF16);
@@ -392,8 +428,8 @@ void launch_gather_prep(DevState *st, const unsigned *flen, const unsigned *foff
                         u64 *cpos, unsigned *coff, unsigned *cidx, unsigned *chunk_first,
                         const unsigned *tpos, DrawEntry *tab, hipStream_t s) {
   const int nb = std::max(1, (int)((cap + ROWS_BLK - 1) / ROWS_BLK));
-  hipLaunchKernelGGL(k_gather_prep, dim3(nb), dim3(ROWS_BLK), 0, s, st, flen, foff, part_len,
-                     part_cnt, part_act, cpos, coff, cidx, chunk_first, tpos, tab);
+  launch_b<B_gather_prep>(k_gather_prep, dim3(nb), dim3(ROWS_BLK), 0, s, st, flen, foff, part_len,
+                          part_cnt, part_act, cpos, coff, cidx, chunk_first, tpos, tab);
 }
 
 // Sampled rows for callers (audit path): the deterministic rows in their
@@ -457,13 +493,13 @@ void launch_samples_out(DevState *st, const u64 *samp_idx, const double *samp_om
                         const double *samp_w, i64 slots_cap, int key_bits, u64 *rkeys,
                         u64 *rkeys_tmp, unsigned *rslot, unsigned *rslot_tmp, void *sort_scratch,
                         i64 cap, u64 *idx, double *om, double *w, i64 *count, hipStream_t s) {
-  hipLaunchKernelGGL(k_samples_list, dim3(1), dim3(1024), 0, s, st, samp_idx, samp_om, samp_w,
-                     cap, idx, om, w, rkeys, rslot);
+  launch_1(k_samples_list, dim3(1), dim3(1024), 0, s, st, samp_idx, samp_om, samp_w,
+           cap, idx, om, w, rkeys, rslot);
   const u64 *sk = sort_keys_pp(rkeys, rslot, rkeys_tmp, rslot_tmp, sort_scratch, slots_cap,
                                &st->n_rnd_rows, 0, key_bits, s);
   const unsigned *sv = sk == rkeys ? rslot : rslot_tmp;
   const int nb = (int)std::min<i64>(std::max<i64>((slots_cap + 255) / 256, 1), 1024);
-  hipLaunchKernelGGL(k_samples_write, dim3(nb), dim3(256), 0, s, st, sk, sv, samp_om, samp_w, cap,
-                     idx, om, w, count);
+  launch_1(k_samples_write, dim3(nb), dim3(256), 0, s, st, sk, sv, samp_om, samp_w, cap,
+           idx, om, w, count);
 }
 }  // namespace cpal

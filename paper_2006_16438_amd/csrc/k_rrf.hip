@@ -29,8 +29,8 @@ __global__ void k_fiber_list(const FiberSlot *__restrict__ slots, u64 nslots, u6
 void launch_fiber_list(const FiberSlot *slots, u64 nslots, u64 *off, unsigned *len,
                        unsigned long long *count, hipStream_t s) {
   const u64 g = std::min<u64>((nslots + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_fiber_list, dim3((unsigned)std::max<u64>(g, 1)), dim3(256), 0, s, slots,
-                     nslots, off, len, count);
+  launch_1(k_fiber_list, dim3((unsigned)std::max<u64>(g, 1)), dim3(256), 0, s, slots,
+           nslots, off, len, count);
 }
 
 // One thread per draw j < s_init (blocks of rpb slots, as the row kernel):
@@ -94,17 +94,17 @@ void launch_rrf_rows(int zdt, DevState *st, i64 s_init, int k, u64 seed, u64 str
                      unsigned *part_act, int rows_per_blk, hipStream_t s) {
   const unsigned nb = (unsigned)((s_init + rows_per_blk - 1) / rows_per_blk);
   if (zdt == CPAL_F64)
-    hipLaunchKernelGGL(k_rrf_rows<double>, dim3(nb), dim3(rows_per_blk), 0, s, st, s_init, k, seed,
-                       stream_id, nfib, fib_off, fib_len, dense_len, omega, R, ldz,
-                       (double *)zhat, foff, flen, samp_idx, part_len, part_cnt, part_act);
+    launch_1(k_rrf_rows<double>, dim3(nb), dim3(rows_per_blk), 0, s, st, s_init, k, seed,
+             stream_id, nfib, fib_off, fib_len, dense_len, omega, R, ldz,
+             (double *)zhat, foff, flen, samp_idx, part_len, part_cnt, part_act);
   else if (zdt == CPAL_F32)
-    hipLaunchKernelGGL(k_rrf_rows<float>, dim3(nb), dim3(rows_per_blk), 0, s, st, s_init, k, seed,
-                       stream_id, nfib, fib_off, fib_len, dense_len, omega, R, ldz, (float *)zhat,
-                       foff, flen, samp_idx, part_len, part_cnt, part_act);
+    launch_1(k_rrf_rows<float>, dim3(nb), dim3(rows_per_blk), 0, s, st, s_init, k, seed,
+             stream_id, nfib, fib_off, fib_len, dense_len, omega, R, ldz, (float *)zhat,
+             foff, flen, samp_idx, part_len, part_cnt, part_act);
   else
-    hipLaunchKernelGGL(k_rrf_rows<bf16s>, dim3(nb), dim3(rows_per_blk), 0, s, st, s_init, k, seed,
-                       stream_id, nfib, fib_off, fib_len, dense_len, omega, R, ldz, (bf16s *)zhat,
-                       foff, flen, samp_idx, part_len, part_cnt, part_act);
+    launch_1(k_rrf_rows<bf16s>, dim3(nb), dim3(rows_per_blk), 0, s, st, s_init, k, seed,
+             stream_id, nfib, fib_off, fib_len, dense_len, omega, R, ldz, (bf16s *)zhat,
+             foff, flen, samp_idx, part_len, part_cnt, part_act);
 }
 
 // A_k(i, r) = the sum of the gather's copies of M(i, r) in copy order; the
@@ -127,11 +127,11 @@ void launch_rrf_store(bool f64, const void *M, int ncopies, i64 nk, int R, int l
                       float *A32, hipStream_t s) {
   const i64 g = std::min<i64>((nk * R + 255) / 256, 16384);
   if (f64)
-    hipLaunchKernelGGL(k_rrf_store<double>, dim3((unsigned)std::max<i64>(g, 1)), dim3(256), 0, s,
-                       (const double *)M, ncopies, nk, R, ldz, A, A32);
+    launch_1(k_rrf_store<double>, dim3((unsigned)std::max<i64>(g, 1)), dim3(256), 0, s,
+             (const double *)M, ncopies, nk, R, ldz, A, A32);
   else
-    hipLaunchKernelGGL(k_rrf_store<float>, dim3((unsigned)std::max<i64>(g, 1)), dim3(256), 0, s,
-                       (const float *)M, ncopies, nk, R, ldz, A, A32);
+    launch_1(k_rrf_store<float>, dim3((unsigned)std::max<i64>(g, 1)), dim3(256), 0, s,
+             (const float *)M, ncopies, nk, R, ldz, A, A32);
 }
 
 }  // namespace cpal

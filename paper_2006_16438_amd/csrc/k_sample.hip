@@ -47,8 +47,8 @@ __device__ __forceinline__ T block_sum(T v) {
 // its maximum exceeds tau.  One block of 1024 threads; the other modes' q
 // are read once (into shared memory, at the candidate-list offsets, when
 // those end within DET_STAGE entries).
-__global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u64 cap,
-                                                   DevState *st, int *__restrict__ cand) {
+__device__ __forceinline__ void det_cand_body(Blk bk, const OtherModes &om, double tau, u64 cap,
+    DevState *st, int *__restrict__ cand) {
   __shared__ double sq[DET_STAGE];
   __shared__ double red[16][CPAL_MAXORDER];
   __shared__ double alpha[CPAL_MAXORDER];
@@ -143,6 +143,11 @@ __global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u6
     }
   }
 }
+__global__ void __launch_bounds__(1024) k_det_cand(OtherModes om, double tau, u64 cap,
+                                                   DevState *st, int *__restrict__ cand) {
+  det_cand_body(CPAL_BLK, om, tau, cap, st, cand);
+}
+CPAL_BODY(B_det_cand, 1024, 1, det_cand_body);
 
 // Enumeration of the candidate product set in mixed-radix order (first other
 // mode fastest).  The candidate lists are ascending, so this order is
@@ -167,14 +172,13 @@ __device__ __forceinline__ bool det_row(const OtherModes &om, const int *__restr
   return p > tau;
 }
 
-__global__ void __launch_bounds__(256) k_det_count(OtherModes om, double tau, DevState *st,
-                                                   const int *__restrict__ cand,
-                                                   unsigned *__restrict__ blk_cnt) {
+__device__ __forceinline__ void det_count_body(Blk bk, const OtherModes &om, double tau,
+    DevState *st, const int *__restrict__ cand, unsigned *__restrict__ blk_cnt) {
   const u64 combos = st->combos;
   unsigned nc[CPAL_MAXORDER];
   for (int u = 0; u < om.d; ++u) nc[u] = (unsigned)st->ncand[u];
   const u64 per = (combos + DET_BLOCKS - 1) / DET_BLOCKS;
-  const u64 b0 = (u64)blockIdx.x * per, b1 = min(combos, b0 + per);
+  const u64 b0 = (u64)bk.x * per, b1 = min(combos, b0 + per);
   unsigned cnt = 0;
   for (u64 e = b0 + threadIdx.x; e < b1; e += blockDim.x) {
     u64 lin;
@@ -184,31 +188,36 @@ __global__ void __launch_bounds__(256) k_det_count(OtherModes om, double tau, De
   __shared__ unsigned ws[4];
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = cnt;
   __syncthreads();
-  if (threadIdx.x == 0) blk_cnt[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+  if (threadIdx.x == 0) blk_cnt[bk.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
+__global__ void __launch_bounds__(256) k_det_count(OtherModes om, double tau, DevState *st,
+                                                   const int *__restrict__ cand,
+                                                   unsigned *__restrict__ blk_cnt) {
+  det_count_body(CPAL_BLK, om, tau, st, cand, blk_cnt);
+}
+CPAL_BODY(B_det_count, 256, 1, det_count_body);
 
-__global__ void __launch_bounds__(256) k_det_scatter(OtherModes om, double tau, DevState *st,
-                                                     const int *__restrict__ cand,
-                                                     const unsigned *__restrict__ blk_cnt,
-                                                     u64 *__restrict__ det_keys, u64 det_cap) {
+__device__ __forceinline__ void det_scatter_body(Blk bk, const OtherModes &om, double tau,
+    DevState *st, const int *__restrict__ cand, const unsigned *__restrict__ blk_cnt,
+    u64 *__restrict__ det_keys, u64 det_cap) {
   const u64 combos = st->combos;
   unsigned nc[CPAL_MAXORDER];
   for (int u = 0; u < om.d; ++u) nc[u] = (unsigned)st->ncand[u];
   const u64 per = (combos + DET_BLOCKS - 1) / DET_BLOCKS;
-  const u64 b0 = (u64)blockIdx.x * per, b1 = min(combos, b0 + per);
+  const u64 b0 = (u64)bk.x * per, b1 = min(combos, b0 + per);
   __shared__ u64 sh_off;
   if (threadIdx.x < 64) {
     u64 before = 0, all = 0;
     for (int b = threadIdx.x; b < DET_BLOCKS; b += 64) {
       const u64 v = blk_cnt[b];
       all += v;
-      if (b < (int)blockIdx.x) before += v;
+      if (b < (int)bk.x) before += v;
     }
     before = wave_sum(before);
     all = wave_sum(all);
     if (threadIdx.x == 0) {
       sh_off = before;
-      if (blockIdx.x == 0) st->det_count = all;
+      if (bk.x == 0) st->det_count = all;
     }
   }
   __syncthreads();
@@ -223,6 +232,13 @@ __global__ void __launch_bounds__(256) k_det_scatter(OtherModes om, double tau, 
     off += tot;
   }
 }
+__global__ void __launch_bounds__(256) k_det_scatter(OtherModes om, double tau, DevState *st,
+                                                     const int *__restrict__ cand,
+                                                     const unsigned *__restrict__ blk_cnt,
+                                                     u64 *__restrict__ det_keys, u64 det_cap) {
+  det_scatter_body(CPAL_BLK, om, tau, st, cand, blk_cnt, det_keys, det_cap);
+}
+CPAL_BODY(B_det_scatter, 256, 1, det_scatter_body);
 
 // Sizes of the sampled system once p_det (tot) is known.
 __device__ __forceinline__ void det_finish_state(DevState *st, i64 n, i64 s, double tot) {
@@ -242,13 +258,10 @@ __device__ __forceinline__ void det_finish_state(DevState *st, i64 n, i64 s, dou
 // to samp_idx[0..s_det), p_det, s_rnd.  One block of 1024 threads.  Fewer
 // than s rows that fit in shared memory (the usual case) stay there: p, the
 // partial sums and the total never leave the block.
-__global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st,
-                                                     const u64 *__restrict__ det_keys,
-                                                     double *__restrict__ det_p,
-                                                     double *__restrict__ kept_p,
-                                                     double *__restrict__ psum, u64 det_cap,
-                                                     i64 s, u64 *__restrict__ samp_idx,
-                                                     unsigned char *__restrict__ keep) {
+__device__ __forceinline__ void det_finish_body(Blk bk, const OtherModes &om, DevState *st,
+    const u64 *__restrict__ det_keys, double *__restrict__ det_p, double *__restrict__ kept_p,
+    double *__restrict__ psum, u64 det_cap, i64 s, u64 *__restrict__ samp_idx,
+    unsigned char *__restrict__ keep) {
   const int tid = threadIdx.x;
   if (st->flags & CPAL_FLAG_STATE) {
     if (tid == 0) { st->s_det = 0; st->s_rnd = 0; st->p_det = 0.0; }
@@ -351,6 +364,16 @@ __global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st
   }
   (void)keep;
 }
+__global__ void __launch_bounds__(1024) k_det_finish(OtherModes om, DevState *st,
+                                                     const u64 *__restrict__ det_keys,
+                                                     double *__restrict__ det_p,
+                                                     double *__restrict__ kept_p,
+                                                     double *__restrict__ psum, u64 det_cap,
+                                                     i64 s, u64 *__restrict__ samp_idx,
+                                                     unsigned char *__restrict__ keep) {
+  det_finish_body(CPAL_BLK, om, st, det_keys, det_p, kept_p, psum, det_cap, s, samp_idx, keep);
+}
+CPAL_BODY(B_det_finish, 1024, 1, det_finish_body);
 
 __device__ __forceinline__ i64 max_draws_of(i64 s_rnd) { return 64 * s_rnd + (1ll << 20); }
 
@@ -440,35 +463,47 @@ __device__ __forceinline__ unsigned draw_chunk(const OtherModes &om, const DrawM
 }
 
 template <int DD>
-__global__ void __launch_bounds__(256) k_draw_first(OtherModes om, DevState *st, u64 seed,
-                                                    u64 stream_id, u64 *__restrict__ buf,
-                                                    unsigned short *__restrict__ bpos,
-                                                    unsigned *__restrict__ chunk_cnt,
-                                                    int stage_n) {
+__device__ __forceinline__ void draw_first_body(Blk bk, const OtherModes &om, DevState *st,
+    u64 seed, u64 stream_id, u64 *__restrict__ buf, unsigned short *__restrict__ bpos,
+    unsigned *__restrict__ chunk_cnt, int stage_n) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
   const i64 s_rnd = st->s_rnd;
   const u64 t = st->t_cur;
   const i64 max_draws = max_draws_of(s_rnd);
   const i64 max_chunks = (max_draws + CPAL_KRP_CHUNK - 1) / CPAL_KRP_CHUNK;
   const i64 first = s_rnd == 0 ? 0 : min(min(draw_need_chunks(st, s_rnd), max_chunks),
-                                         (i64)gridDim.x);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+                                         (i64)bk.n);
+  if (bk.x == 0 && threadIdx.x == 0) {
     st->first_chunks = (u64)first;
     st->chunk_next = (u64)first;
   }
-  if ((i64)blockIdx.x >= first) return;   // uniform per block
+  if ((i64)bk.x >= first) return;   // uniform per block
   DrawModes dm;
   draw_setup<DD>(om, stage_n, dsm, dm);
-  draw_chunk<DD>(om, dm, blockIdx.x, st->tau_eff, max_draws, seed, stream_id, t, buf, bpos,
+  draw_chunk<DD>(om, dm, bk.x, st->tau_eff, max_draws, seed, stream_id, t, buf, bpos,
              chunk_cnt);
 }
+template <int DD>
+__global__ void __launch_bounds__(256) k_draw_first(OtherModes om, DevState *st, u64 seed,
+                                                    u64 stream_id, u64 *__restrict__ buf,
+                                                    unsigned short *__restrict__ bpos,
+                                                    unsigned *__restrict__ chunk_cnt,
+                                                    int stage_n) {
+  draw_first_body<DD>(CPAL_BLK, om, st, seed, stream_id, buf, bpos, chunk_cnt, stage_n);
+}
+template <int DD>
+struct B_draw_first {
+  static constexpr int NT = 256, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    draw_first_body<DD>(b, a...);
+  }
+};
 
 template <int DD>
-__global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, u64 seed,
-                                                   u64 stream_id, u64 *__restrict__ buf,
-                                                   unsigned short *__restrict__ bpos,
-                                                   unsigned *__restrict__ chunk_cnt,
-                                                   int stage_n) {
+__device__ __forceinline__ void draw_more_body(Blk bk, const OtherModes &om, DevState *st, u64 seed,
+    u64 stream_id, u64 *__restrict__ buf, unsigned short *__restrict__ bpos,
+    unsigned *__restrict__ chunk_cnt, int stage_n) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
   __shared__ u64 sh_c;
   __shared__ int stop;
@@ -508,6 +543,22 @@ __global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, 
     __syncthreads();
   }
 }
+template <int DD>
+__global__ void __launch_bounds__(256) k_draw_more(OtherModes om, DevState *st, u64 seed,
+                                                   u64 stream_id, u64 *__restrict__ buf,
+                                                   unsigned short *__restrict__ bpos,
+                                                   unsigned *__restrict__ chunk_cnt,
+                                                   int stage_n) {
+  draw_more_body<DD>(CPAL_BLK, om, st, seed, stream_id, buf, bpos, chunk_cnt, stage_n);
+}
+template <int DD>
+struct B_draw_more {
+  static constexpr int NT = 256, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    draw_more_body<DD>(b, a...);
+  }
+};
 
 // Finishes the entry of accepted draw `pos` of row `key` in the draw table
 // (linear probing from slot h, whose compare-and-swap returned old).  The
@@ -546,14 +597,10 @@ __device__ __forceinline__ void draw_insert_from(DrawEntry *tab, u64 mask, u64 k
 // of Sec. 4.1 without sorting the draws (which draw represents the row
 // depends on timing; the row, its count and weight do not).  Block 0 also records the number of rows used and the
 // draw count (index of the s_rnd-th accepted draw + 1).
-__global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__restrict__ buf,
-                                                 const unsigned *__restrict__ chunk_cnt,
-                                                 const unsigned short *__restrict__ bpos,
-                                                 u64 *__restrict__ keys, DrawEntry *tab,
-                                                 u64 tmask, int tshift, int det_rep) {
+__device__ __forceinline__ void compact_body(Blk bk, DevState *st, const u64 *__restrict__ buf,
+    const unsigned *__restrict__ chunk_cnt, const unsigned short *__restrict__ bpos,
+    u64 *__restrict__ keys, DrawEntry *tab, u64 tmask, int tshift, int det_rep) {
   __shared__ i64 sh_draws;
-  __shared__ u64 soff[256];
-  __shared__ unsigned scnt[256];
   __shared__ u64 own_off[CMP_WINS];
   __shared__ unsigned own_cnt[CMP_WINS];
   const int tid = threadIdx.x;
@@ -574,7 +621,7 @@ __global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__rest
       const u64 off = carry + block_excl_scan<u64>((u64)v, &tot);
       if (q < Q && s_rnd > 0 && off <= (u64)(s_rnd - 1) && (u64)(s_rnd - 1) < off + v)
         sh_draws = (i64)q * CPAL_KRP_CHUNK + bpos[q * CPAL_KRP_CHUNK + (s_rnd - 1 - off)] + 1;
-      if (tid == (int)blockIdx.x) {
+      if (tid == (int)bk.x) {
         // rows of the owned chunk that fall among the first s_rnd
         own_off[wi] = off;
         own_cnt[wi] = off < (u64)s_rnd ? (unsigned)min((u64)v, (u64)s_rnd - off) : 0u;
@@ -591,7 +638,7 @@ __global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__rest
         const int wi = w0 + r;
         has[r] = wi < nw && (unsigned)tid < own_cnt[wi];
         if (has[r]) {
-          const u64 q = (wb + wi) * 256 + blockIdx.x;
+          const u64 q = (wb + wi) * 256 + bk.x;
           key[r] = buf[q * CPAL_KRP_CHUNK + tid];
           pos[r] = (unsigned)(own_off[wi] + tid);
           keys[pos[r]] = key[r];
@@ -606,7 +653,7 @@ __global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__rest
     __syncthreads();   // own_off / own_cnt are refilled by the next batch
   }
   __syncthreads();
-  if (blockIdx.x == 0 && tid == 0) {
+  if (bk.x == 0 && tid == 0) {
     st->nchunks = (i64)Q;
     if (s_rnd == 0) {
       st->s_rnd_used = 0;
@@ -621,28 +668,46 @@ __global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__rest
     }
   }
 }
+__global__ void __launch_bounds__(256) k_compact(DevState *st, const u64 *__restrict__ buf,
+                                                 const unsigned *__restrict__ chunk_cnt,
+                                                 const unsigned short *__restrict__ bpos,
+                                                 u64 *__restrict__ keys, DrawEntry *tab,
+                                                 u64 tmask, int tshift, int det_rep) {
+  compact_body(CPAL_BLK, st, buf, chunk_cnt, bpos, keys, tab, tmask, tshift, det_rep);
+}
+CPAL_BODY(B_compact, 256, 1, compact_body);
 
 __global__ void k_set_step(DevState *st, u64 t) { st->t_next = t; }
 
 void launch_set_step(DevState *st, u64 t, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, st, t);
+  launch_1(k_set_step, dim3(1), dim3(1), 0, s, st, t);
 }
 
 void launch_det_cand(const OtherModes &om, double tau, u64 cap, DevState *st, int *cand,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_det_cand, dim3(1), dim3(1024), 0, s, om, tau, cap, st, cand);
+  launch_b<B_det_cand>(k_det_cand, dim3(1), dim3(1024), 0, s, om, tau, cap, st, cand);
 }
 void launch_det_enum(const OtherModes &om, double tau, DevState *st, const int *cand,
                      unsigned *blk_cnt, u64 *det_keys, u64 det_cap, hipStream_t s) {
-  hipLaunchKernelGGL(k_det_count, dim3(DET_BLOCKS), dim3(256), 0, s, om, tau, st, cand, blk_cnt);
-  hipLaunchKernelGGL(k_det_scatter, dim3(DET_BLOCKS), dim3(256), 0, s, om, tau, st, cand, blk_cnt,
-                     det_keys, det_cap);
+  launch_b<B_det_count>(k_det_count, dim3(DET_BLOCKS), dim3(256), 0, s, om, tau, st, cand,
+                        blk_cnt);
+  launch_b<B_det_scatter>(k_det_scatter, dim3(DET_BLOCKS), dim3(256), 0, s, om, tau, st, cand,
+                          blk_cnt, det_keys, det_cap);
 }
 void launch_det_finish(const OtherModes &om, DevState *st, const u64 *det_keys, double *det_p,
                        double *kept_p, double *psum, u64 det_cap, i64 s, u64 *samp_idx,
                        hipStream_t st_) {
-  hipLaunchKernelGGL(k_det_finish, dim3(1), dim3(1024), 0, st_, om, st, det_keys, det_p, kept_p,
-                     psum, det_cap, s, samp_idx, (unsigned char *)nullptr);
+  launch_b<B_det_finish>(k_det_finish, dim3(1), dim3(1024), 0, st_, om, st, det_keys, det_p,
+                         kept_p, psum, det_cap, s, samp_idx, (unsigned char *)nullptr);
+}
+template <int DD>
+static void launch_draw_t(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 *buf,
+                          unsigned short *bpos, unsigned *chunk_cnt, int grid_first,
+                          int grid_more, int stage_n, size_t sh, hipStream_t s) {
+  launch_b<B_draw_first<DD>>(k_draw_first<DD>, dim3(grid_first), dim3(256), sh, s, om, st, seed,
+                             stream_id, buf, bpos, chunk_cnt, stage_n);
+  launch_b<B_draw_more<DD>>(k_draw_more<DD>, dim3(grid_more), dim3(256), sh, s, om, st, seed,
+                            stream_id, buf, bpos, chunk_cnt, stage_n);
 }
 void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u64 *buf,
                  unsigned short *bpos, unsigned *chunk_cnt, int grid_first, int grid_more,
@@ -652,20 +717,27 @@ void launch_draw(const OtherModes &om, DevState *st, u64 seed, u64 stream_id, u6
   const int stage_n = tot <= 8192 ? (int)tot : 0;   // <= 64 KB of shared memory
   const size_t sh = (size_t)stage_n * sizeof(u64);
   const int dd = om.d <= 4 ? om.d : 0;
-  auto kf = dd == 1 ? k_draw_first<1> : dd == 2 ? k_draw_first<2> : dd == 3 ? k_draw_first<3>
-          : dd == 4 ? k_draw_first<4> : k_draw_first<0>;
-  auto km = dd == 1 ? k_draw_more<1> : dd == 2 ? k_draw_more<2> : dd == 3 ? k_draw_more<3>
-          : dd == 4 ? k_draw_more<4> : k_draw_more<0>;
-  hipLaunchKernelGGL(kf, dim3(grid_first), dim3(256), sh, s, om, st, seed, stream_id, buf, bpos,
-                     chunk_cnt, stage_n);
-  hipLaunchKernelGGL(km, dim3(grid_more), dim3(256), sh, s, om, st, seed, stream_id, buf, bpos,
-                     chunk_cnt, stage_n);
+  if (dd == 1)
+    launch_draw_t<1>(om, st, seed, stream_id, buf, bpos, chunk_cnt, grid_first, grid_more, stage_n,
+                     sh, s);
+  else if (dd == 2)
+    launch_draw_t<2>(om, st, seed, stream_id, buf, bpos, chunk_cnt, grid_first, grid_more, stage_n,
+                     sh, s);
+  else if (dd == 3)
+    launch_draw_t<3>(om, st, seed, stream_id, buf, bpos, chunk_cnt, grid_first, grid_more, stage_n,
+                     sh, s);
+  else if (dd == 4)
+    launch_draw_t<4>(om, st, seed, stream_id, buf, bpos, chunk_cnt, grid_first, grid_more, stage_n,
+                     sh, s);
+  else
+    launch_draw_t<0>(om, st, seed, stream_id, buf, bpos, chunk_cnt, grid_first, grid_more, stage_n,
+                     sh, s);
 }
 void launch_compact(DevState *st, const u64 *buf, const unsigned *chunk_cnt,
                     const unsigned short *bpos, u64 *keys, DrawEntry *tab, u64 tmask, int tshift,
                     bool det_rep, hipStream_t s) {
-  hipLaunchKernelGGL(k_compact, dim3(256), dim3(256), 0, s, st, buf, chunk_cnt, bpos, keys, tab,
-                     tmask, tshift, det_rep ? 1 : 0);
+  launch_b<B_compact>(k_compact, dim3(256), dim3(256), 0, s, st, buf, chunk_cnt, bpos, keys, tab,
+                      tmask, tshift, det_rep ? 1 : 0);
 }
 
 __global__ void k_draw_table_clear(DrawEntry *__restrict__ tab, u64 n) {
@@ -675,8 +747,7 @@ __global__ void k_draw_table_clear(DrawEntry *__restrict__ tab, u64 n) {
 
 void launch_draw_table_clear(DrawEntry *tab, u64 n, hipStream_t s) {
   const u64 g = std::min<u64>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_draw_table_clear, dim3((unsigned)std::max<u64>(g, 1)), dim3(256), 0, s, tab,
-                     n);
+  launch_1(k_draw_table_clear, dim3((unsigned)std::max<u64>(g, 1)), dim3(256), 0, s, tab, n);
 }
 
 }  // namespace cpal

@@ -21,18 +21,15 @@ static int grid_for(i64 n, int blk, int maxg = 8192) {
 // factor is staged.
 // Skipped when the update hit a state error.  256 threads.
 template <typename T, int LPN>
-__global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, int R,
-                                                    const T *__restrict__ M, int ldm,
-                                                    int ncopies,
-                                                    const Decomp *__restrict__ dc,
-                                                    double *__restrict__ A,
-                                                    float *__restrict__ A32) {
+__device__ __forceinline__ void solve_rows_body(Blk bk, const DevState *st, i64 n, int R,
+    const T *__restrict__ M, int ldm, int ncopies, const Decomp *__restrict__ dc,
+    double *__restrict__ A, float *__restrict__ A32) {
   extern __shared__ double sL[];   // R*R factor (L, or V)
   __shared__ double rdiag[CPAL_MAXR];
   if (st->flags & CPAL_FLAG_STATE) return;
   const int tid = threadIdx.x;
   const int c = (tid & 63) % LPN;
-  const i64 row = ((i64)blockIdx.x * blockDim.x + tid) / LPN;
+  const i64 row = ((i64)bk.x * blockDim.x + tid) / LPN;
   const bool live = row < n;
   const bool col = c < R;
   const int cl = col ? c : R - 1;
@@ -84,10 +81,42 @@ __global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, i
     A32[row * R + c] = (float)v;
   }
 }
+template <typename T, int LPN>
+__global__ void __launch_bounds__(256) k_solve_rows(const DevState *st, i64 n, int R,
+                                                    const T *__restrict__ M, int ldm,
+                                                    int ncopies,
+                                                    const Decomp *__restrict__ dc,
+                                                    double *__restrict__ A,
+                                                    float *__restrict__ A32) {
+  solve_rows_body<T, LPN>(CPAL_BLK, st, n, R, M, ldm, ncopies, dc, A, A32);
+}
+template <typename T, int LPN>
+struct B_solve_rows {
+  static constexpr int NT = 256, MW = 1;
+  template <class... A>
+  __device__ __forceinline__ static void run(Blk b, const A &...a) {
+    solve_rows_body<T, LPN>(b, a...);
+  }
+};
 
 __global__ void k_to_f32(const double *__restrict__ a, float *__restrict__ b, i64 n) {
   for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
     b[i] = (float)a[i];
+}
+
+template <typename T>
+static void launch_solve_rows_t(int lpn, int nb, size_t sh, const DevState *st, i64 n, int R,
+                                const T *M, int ldm, int ncopies, const Decomp *dc, double *A,
+                                float *A32, hipStream_t s) {
+  if (lpn == 16)
+    launch_b<B_solve_rows<T, 16>>(k_solve_rows<T, 16>, dim3(nb), dim3(256), sh, s, st, n, R, M,
+                                  ldm, ncopies, dc, A, A32);
+  else if (lpn == 32)
+    launch_b<B_solve_rows<T, 32>>(k_solve_rows<T, 32>, dim3(nb), dim3(256), sh, s, st, n, R, M,
+                                  ldm, ncopies, dc, A, A32);
+  else
+    launch_b<B_solve_rows<T, 64>>(k_solve_rows<T, 64>, dim3(nb), dim3(256), sh, s, st, n, R, M,
+                                  ldm, ncopies, dc, A, A32);
 }
 
 void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M, int ldm,
@@ -96,20 +125,15 @@ void launch_solve_rows(bool f64, const DevState *st, i64 n, int R, const void *M
   const int lpn = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
   const int nb = (int)((n * lpn + 255) / 256);
   const size_t sh = sizeof(double) * (size_t)R * R;
-  if (f64) {
-    auto k = lpn == 16 ? k_solve_rows<double, 16> : lpn == 32 ? k_solve_rows<double, 32>
-                                                              : k_solve_rows<double, 64>;
-    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const double *)M, ldm, ncopies, dc, A,
-                       A32);
-  } else {
-    auto k = lpn == 16 ? k_solve_rows<float, 16> : lpn == 32 ? k_solve_rows<float, 32>
-                                                             : k_solve_rows<float, 64>;
-    hipLaunchKernelGGL(k, dim3(nb), dim3(256), sh, s, st, n, R, (const float *)M, ldm, ncopies, dc, A,
-                       A32);
-  }
+  if (f64)
+    launch_solve_rows_t<double>(lpn, nb, sh, st, n, R, (const double *)M, ldm, ncopies, dc, A, A32,
+                                s);
+  else
+    launch_solve_rows_t<float>(lpn, nb, sh, st, n, R, (const float *)M, ldm, ncopies, dc, A, A32,
+                               s);
 }
 
 void launch_to_f32(const double *a, float *b, i64 n, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, n);
+  launch_1(k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, n);
 }
 }  // namespace cpal

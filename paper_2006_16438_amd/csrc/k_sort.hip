@@ -18,10 +18,10 @@ namespace cpal {
 #define SCAN_TILE 1024
 
 // ------------------------------------------------------------------ scan ---
-__global__ void __launch_bounds__(256) k_scan_part(const unsigned *__restrict__ in, i64 cap,
-                                                   const i64 *n_dev, u64 *__restrict__ part) {
+__device__ __forceinline__ void scan_part_body(Blk bk, const unsigned *__restrict__ in, i64 cap,
+    const i64 *n_dev, u64 *__restrict__ part) {
   const i64 n = n_dev ? min(*n_dev, cap) : cap;
-  const i64 base = (i64)blockIdx.x * SCAN_TILE;
+  const i64 base = (i64)bk.x * SCAN_TILE;
   u64 s = 0;
   for (int r = 0; r < SCAN_TILE / 256; ++r) {
     const i64 i = base + r * 256 + threadIdx.x;
@@ -31,11 +31,15 @@ __global__ void __launch_bounds__(256) k_scan_part(const unsigned *__restrict__ 
   __shared__ u64 ws[4];
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+  if (threadIdx.x == 0) part[bk.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
+__global__ void __launch_bounds__(256) k_scan_part(const unsigned *__restrict__ in, i64 cap,
+                                                   const i64 *n_dev, u64 *__restrict__ part) {
+  scan_part_body(CPAL_BLK, in, cap, n_dev, part);
+}
+CPAL_BODY(B_scan_part, 256, 1, scan_part_body);
 
-__global__ void __launch_bounds__(1024) k_scan_top(u64 *__restrict__ part, int nb,
-                                                   u64 *total) {
+__device__ __forceinline__ void scan_top_body(Blk bk, u64 *__restrict__ part, int nb, u64 *total) {
   u64 carry = 0;
   for (int b0 = 0; b0 < nb; b0 += 1024) {
     const int b = b0 + threadIdx.x;
@@ -47,14 +51,18 @@ __global__ void __launch_bounds__(1024) k_scan_top(u64 *__restrict__ part, int n
   }
   if (threadIdx.x == 0 && total) *total = carry;
 }
+__global__ void __launch_bounds__(1024) k_scan_top(u64 *__restrict__ part, int nb,
+                                                   u64 *total) {
+  scan_top_body(CPAL_BLK, part, nb, total);
+}
+CPAL_BODY(B_scan_top, 1024, 1, scan_top_body);
 
-__global__ void __launch_bounds__(256) k_scan_apply(const unsigned *__restrict__ in, i64 cap,
-                                                    const i64 *n_dev, const u64 *__restrict__ part,
-                                                    u64 *__restrict__ out) {
+__device__ __forceinline__ void scan_apply_body(Blk bk, const unsigned *__restrict__ in, i64 cap,
+    const i64 *n_dev, const u64 *__restrict__ part, u64 *__restrict__ out) {
   const i64 n = n_dev ? min(*n_dev, cap) : cap;
-  const i64 base = (i64)blockIdx.x * SCAN_TILE;
+  const i64 base = (i64)bk.x * SCAN_TILE;
   if (base >= n) return;
-  u64 carry = part[blockIdx.x];
+  u64 carry = part[bk.x];
   for (int r = 0; r < SCAN_TILE / 256; ++r) {
     const i64 i = base + r * 256 + threadIdx.x;
     const u64 v = i < n ? in[i] : 0;
@@ -64,6 +72,12 @@ __global__ void __launch_bounds__(256) k_scan_apply(const unsigned *__restrict__
     carry += tot;
   }
 }
+__global__ void __launch_bounds__(256) k_scan_apply(const unsigned *__restrict__ in, i64 cap,
+                                                    const i64 *n_dev, const u64 *__restrict__ part,
+                                                    u64 *__restrict__ out) {
+  scan_apply_body(CPAL_BLK, in, cap, n_dev, part, out);
+}
+CPAL_BODY(B_scan_apply, 256, 1, scan_apply_body);
 
 size_t scan_scratch_bytes(i64 n) {
   return sizeof(u64) * (size_t)((n + SCAN_TILE - 1) / SCAN_TILE + 1);
@@ -76,9 +90,9 @@ void scan_u32_dev(const unsigned *in, u64 *out, i64 cap, const i64 *n_dev, u64 *
   const int nb = (int)((cap + SCAN_TILE - 1) / SCAN_TILE);
   u64 *part = (u64 *)scratch;
   if (nb == 0) return;
-  hipLaunchKernelGGL(k_scan_part, dim3(nb), dim3(256), 0, s, in, cap, n_dev, part);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, part, nb, total);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, s, in, cap, n_dev, part, out);
+  launch_b<B_scan_part>(k_scan_part, dim3(nb), dim3(256), 0, s, in, cap, n_dev, part);
+  launch_b<B_scan_top>(k_scan_top, dim3(1), dim3(1024), 0, s, part, nb, total);
+  launch_b<B_scan_apply>(k_scan_apply, dim3(nb), dim3(256), 0, s, in, cap, n_dev, part, out);
 }
 
 void scan_u32_to_u64(const unsigned *in, u64 *out, i64 n, u64 *total, void *scratch,
@@ -220,12 +234,12 @@ u64 *sort_keys_pp(u64 *keys, unsigned *vals, u64 *tmp_keys, unsigned *tmp_vals, 
   unsigned *src_v = vals, *dst_v = vals ? tmp_vals : nullptr;
   for (int ps = 0; ps < passes; ++ps) {
     const int shift = 8 * ps;
-    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, s, src_k, capn, count_dev,
-                       shift, hist, nb);
+    launch_1(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, s, src_k, capn, count_dev,
+             shift, hist, nb);
     if (!fused) scan_u32_to_u64(hist, hoff, nh, nullptr, scan_scratch, s);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, s, src_k, src_v, capn,
-                       count_dev, shift, hist, fused ? (const u64 *)nullptr : hoff, nb, dst_k,
-                       dst_v);
+    launch_1(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, s, src_k, src_v, capn,
+             count_dev, shift, hist, fused ? (const u64 *)nullptr : hoff, nb, dst_k,
+             dst_v);
     u64 *tk = src_k; src_k = dst_k; dst_k = tk;
     unsigned *tv = src_v; src_v = dst_v; dst_v = tv;
   }

@@ -18,13 +18,19 @@ from tests.gpu_util import dense_values, log, rel_err
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("graphs", [False, True, "autotune"])
+@pytest.mark.parametrize("graphs", [False, True, "autotune", "stages", "stages_seg",
+                                    "stages_autotune"])
 def test_batch_mixed_parity(graphs):
     """graphs=True: every mode step after the first replays the captured
     graph of that mode; each replay is checked against the oracle.
     graphs="autotune": as True, and after the first iteration the autotuner
     changes the launch shapes, which drops the captured graphs (the next
-    steps capture again with the new shapes)."""
+    steps capture again with the new shapes).  "stages": the stage-major
+    graph (one launch per stage for all decompositions where the kernel has
+    a batched form; the owner gather of these FP64 decompositions and the
+    dense contraction run per decomposition beside it); "stages_seg": every
+    sparse decomposition on the segmented gather, which has a batched form
+    too; "stages_autotune": stage-major with the autotuner's shapes."""
     from paper_2006_16438_amd.api import CpArlsLevBatch
     dev = torch.device("cuda:0")
     A = synth.random_sparse((30, 25, 20), 3000, seed=5)
@@ -46,13 +52,20 @@ def test_batch_mixed_parity(graphs):
     factors = [[torch.from_numpy(f.copy()).to(dev)
                 for f in synth.gaussian_factors(tensors_np[t].dims, ranks[i], 10 + i)]
                for i, t in enumerate(tensor_of)]
+    stages = isinstance(graphs, str) and graphs.startswith("stages")
     b = CpArlsLevBatch(tensors, tensor_of, factors, ranks, samples, seeds=3,
-                       stream_ids=stream_ids, gather_dtype="f64", use_graphs=bool(graphs))
+                       stream_ids=stream_ids, gather_dtype="f64",
+                       use_graphs="stages" if stages else bool(graphs))
     OTs = [oracle.Tensor.from_synth(T) for T in tensors_np]
     members = [b.member(i) for i in range(len(tensor_of))]
+    if graphs == "stages_seg":
+        for i, t in enumerate(tensor_of):
+            if t != 3:
+                for k in range(len(tensors_np[t].dims)):
+                    members[i].set_gather_config(k, 0, 0)
     max_order = max(len(T.dims) for T in tensors_np)
     for it in range(3):
-        if graphs == "autotune" and it == 1:
+        if graphs in ("autotune", "stages_autotune") and it == 1:
             b.autotune()
             log("autotuned: " + str([members[i].gather_config(k) for i in range(len(tensor_of))
                                      for k in range(len(tensors_np[tensor_of[i]].dims))]))
@@ -86,16 +99,20 @@ def test_batch_mixed_parity(graphs):
                 assert np.array_equal(w.cpu().numpy(), ref["wgt"])
                 err = rel_err(factors[i][k].cpu().numpy(), new)
                 assert err <= 1e-10, f"decomposition {i} mode {k}: factor rel err {err:.3e}"
-            log(f"iteration {it} mode {k}: {len(refs)} decompositions match (graphs={graphs})")
+            nk = b.graph_kernels(k, 2 if stages else 1) if graphs else 0
+            log(f"iteration {it} mode {k}: {len(refs)} decompositions match (graphs={graphs}, "
+                f"{nk} kernels in the step's graph)")
     b.close()
 
 
-def test_batch256_full_size_members():
+@pytest.mark.parametrize("graphs", [True, "stages"])
+def test_batch256_full_size_members(graphs):
     """The benchmark's batch at full size (64 generated sparse tensors, nnz up
     to 5e6, x 4 restarts, FP32 gather, s = 2^15), stepped from captured graphs
-    after an autotuned warm-up iteration; two decompositions on different
-    tensors are checked at every mode step of the next iteration against the
-    oracle: bit-exact samples, factors within 1e-4 (FP32 gather)."""
+    (graph of branches, or stage-major) after an autotuned warm-up iteration;
+    two decompositions on different tensors are checked at every mode step of
+    the next iteration against the oracle: bit-exact samples, factors within
+    1e-4 (FP32 gather)."""
     from paper_2006_16438_amd import synth_gpu
     from paper_2006_16438_amd.api import CpArlsLevBatch
     dev = torch.device("cuda:0")
@@ -112,7 +129,7 @@ def test_batch256_full_size_members():
     for k in range(3):   # warm-up iteration, kernel by kernel
         b.mode_step(k)
     b.autotune()
-    b.set_graphs(True)
+    b.set_graphs(graphs)
     check = [0, 4 * 37 + 2]
     OTs, members = {}, {}
     for i in check:
@@ -137,4 +154,6 @@ def test_batch256_full_size_members():
             err = rel_err(factors[i][k].cpu().numpy(), new)
             log(f"  mode {k} decomposition {i}: s_bar={idx.numel()} factor rel err {err:.2e}")
             assert err <= 1e-4, f"decomposition {i} mode {k}: factor rel err {err:.3e}"
+        log(f"  mode {k}: {b.graph_kernels(k, 2 if graphs == 'stages' else 1)} kernels in the "
+            f"step's graph ({graphs})")
     b.close()
