@@ -157,3 +157,68 @@ def test_batch256_full_size_members(graphs):
         log(f"  mode {k}: {b.graph_kernels(k, 2 if graphs == 'stages' else 1)} kernels in the "
             f"step's graph ({graphs})")
     b.close()
+
+
+def test_batch_stage_major_rowblock_forms():
+    """The stage-major graph with the row-block gathers in their batched form:
+    two sparse 3-way tensors with modes of 1024 rows and more (2100 x 300 x
+    1100, 1.5e5 nonzeros; Zipf(1.2) 3000 x 1200 x 300, 4e5 nonzeros), four
+    restarts each, restart r of a tensor on the tile (r = 0), shared-block
+    bucketed (r = 1), hybrid (r = 2, long-fiber factor 16) or segmented (r = 3)
+    gather in every mode that takes it (the others keep the default), FP64.
+    Two iterations, every mode step of every decomposition checked against
+    the oracle: bit-exact samples, factors within 1e-10."""
+    from paper_2006_16438_amd import _lib as L
+    from paper_2006_16438_amd.api import CpArlsLevBatch
+    from tests.test_gpu_parity import _zipf3
+    dev = torch.device("cuda:0")
+    tensors_np = [synth.random_sparse((2100, 300, 1100), 150_000, seed=21), _zipf3()]
+    tensors = [(T.dims, torch.from_numpy(np.ascontiguousarray(T.coords)).to(dev),
+                torch.from_numpy(np.ascontiguousarray(T.values)).to(dev)) for T in tensors_np]
+    restarts = 4
+    tensor_of = [t for t in range(2) for _ in range(restarts)]
+    n = len(tensor_of)
+    R = 8
+    samples = [8192 + 77 if t == 0 else 4096 for t in tensor_of]
+    taus = [1 / 8192 if t == 0 else 1 / 4096 for t in tensor_of]
+    stream_ids = [i % restarts for i in range(n)]
+    factors = [[torch.from_numpy(f.copy()).to(dev)
+                for f in synth.gaussian_factors(tensors_np[t].dims, R, 30 + i)]
+               for i, t in enumerate(tensor_of)]
+    b = CpArlsLevBatch(tensors, tensor_of, factors, R, samples, taus=taus, seeds=3,
+                       stream_ids=stream_ids, gather_dtype="f64")
+    members = [b.member(i) for i in range(n)]
+    forms = [(0, -3), (0, -4), (16, -5), (0, 0)]
+    taken = {f: 0 for f in forms}
+    for i in range(n):
+        f = forms[i % restarts]
+        for k in range(3):
+            try:
+                members[i].set_gather_config(k, *f)
+                taken[f] += 1
+            except L.CpalError:
+                pass   # a mode below 1024 rows keeps its default gather
+    assert all(v > 0 for v in taken.values()), taken
+    b.set_graphs("stages")
+    OTs = [oracle.Tensor.from_synth(T) for T in tensors_np]
+    for it in range(2):
+        for k in range(3):
+            refs = {}
+            for i, t in enumerate(tensor_of):
+                host = [f.cpu().numpy().copy() for f in factors[i]]
+                ref = oracle.mode_update(OTs[t], host, k, members[i].step, R, samples[i],
+                                         taus[i], 3, stream_ids[i])
+                refs[i] = (ref, host[k])
+            b.mode_step(k)
+            for i, (ref, new) in refs.items():
+                idx, om, w = members[i].samples_view()
+                assert np.array_equal(idx.cpu().numpy().view(np.uint64), ref["idx"]), \
+                    f"iteration {it} mode {k} decomposition {i}: sample indices differ"
+                assert np.array_equal(om.cpu().numpy(), ref["omega"])
+                assert np.array_equal(w.cpu().numpy(), ref["wgt"])
+                err = rel_err(factors[i][k].cpu().numpy(), new)
+                assert err <= 1e-10, f"decomposition {i} mode {k}: factor rel err {err:.3e}"
+            log(f"iteration {it} mode {k}: {n} decompositions match, "
+                f"{b.graph_kernels(k, 2)} kernels in the step's graph, forms "
+                f"{[members[i].gather_config(k) for i in range(n)]}")
+    b.close()
