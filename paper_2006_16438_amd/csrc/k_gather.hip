@@ -509,8 +509,30 @@ __device__ __forceinline__ void bk_chunk(i64 ch, i64 nch, i64 total, i64 nf,
 #pragma unroll
   for (int u = 0; u < BK_PER; ++u) nz.get(pp[u], ik[u], x[u]);
 #pragma unroll
-  for (int u = 0; u < BK_PER; ++u)
-    if (keep[u]) f(ik[u], x[u], zr[u]);
+  for (int u = 0; u < BK_PER; ++u) f(keep[u], ik[u], x[u], zr[u]);   // every lane
+}
+
+// Runs of equal buckets among a wave's lanes (lanes in stream order): run
+// heads, the run's length at its head, and each lane's head.
+struct BucketRuns {
+  int bkt;       // this lane's bucket, -1 without a position
+  bool head;
+  int len;       // at a head: lanes in its run
+  int headlane;
+};
+__device__ __forceinline__ BucketRuns bucket_runs(bool kp, int bkt) {
+  const int lane = threadIdx.x & 63;
+  bkt = kp ? bkt : -1;
+  const int prev = __shfl_up(bkt, 1, 64);
+  const bool bnd = lane == 0 || prev != bkt;
+  const u64 bm = __ballot(bnd);
+  const u64 rest = (bm >> lane) >> 1;
+  BucketRuns r;
+  r.bkt = bkt;
+  r.head = kp && bnd;
+  r.len = rest ? __ffsll((long long)rest) : 64 - lane;
+  r.headlane = 63 - __clzll(bm & ((2ull << lane) - 1ull));
+  return r;
 }
 
 // Workgroup w takes the consecutive chunks [w cpw, (w + 1) cpw) of the stream
@@ -530,7 +552,10 @@ __device__ __forceinline__ void bkt_count_body(Blk bk, const DevState *st,
   for (int b = threadIdx.x; b < nb; b += BK_THREADS) h[b] = 0u;
   for (i64 ch = c0; ch < c1; ++ch)
     bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win, lmin,
-                [&](int ik, T, unsigned) { atomicAdd(&h[(unsigned)ik >> bshift], 1u); });
+                [&](bool kp, int ik, T, unsigned) {
+                  const BucketRuns r = bucket_runs(kp, (int)((unsigned)ik >> bshift));
+                  if (r.head) atomicAdd(&h[r.bkt], (unsigned)r.len);
+                });
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += BK_THREADS)
     cnt[(i64)b * bk.n + bk.x] = h[b];
@@ -568,9 +593,15 @@ __device__ __forceinline__ void bkt_scatter_body(Blk bk, const DevState *st,
     cur[b] = (unsigned)off[(i64)b * bk.n + bk.x];
   for (i64 ch = c0; ch < c1; ++ch)
     bk_chunk<T>(ch, nch, total, nf, cpos, coff, cidx, chunk_first, nz, win, lmin,
-                [&](int ik, T x, unsigned zr) {
-                  const unsigned pos = atomicAdd(&cur[(unsigned)ik >> bshift], 1u);
-                  bent[pos] = BktRec<T>::make(ik, x, zr);   // one 16-byte store
+                [&](bool kp, int ik, T x, unsigned zr) {
+                  // one cursor add per run of equal buckets; the run's records
+                  // take consecutive slots in stream order
+                  const BucketRuns r = bucket_runs(kp, (int)((unsigned)ik >> bshift));
+                  unsigned base = 0;
+                  if (r.head) base = atomicAdd(&cur[r.bkt], (unsigned)r.len);
+                  const unsigned hb = (unsigned)__shfl((int)base, r.headlane, 64);
+                  if (kp) bent[hb + (unsigned)((threadIdx.x & 63) - r.headlane)] =
+                      BktRec<T>::make(ik, x, zr);   // one 16-byte store
                 });
 }
 template <typename T>
