@@ -416,9 +416,15 @@ cpal_status cp_arls_lev_batch_graph_kernels(const cpal_batch *batch, int32_t kin
                                             int64_t *kernels);
 
 /* cp_arls_lev_autotune for the first decomposition of every tensor; the
- * other decompositions of that tensor take its launch shapes.  Graphs
- * captured earlier are dropped (the next graph step captures again).
- * Synchronizes the batch's streams. */
+ * other decompositions of that tensor take its launch shapes.  Then, per
+ * mode, the gather stage of all decompositions is timed together as
+ * stage-major launches (as the stage-major graph runs it), once with those
+ * shapes and once with the shared-block bucketed gather (sort_min -4) in
+ * every mode that takes it; the latter is kept when at least 3% faster.  The
+ * timing runs one more sampling pass per mode (factors unchanged, step
+ * counters restored; cp_arls_lev_samples is invalid until the next mode
+ * update).  Graphs captured earlier are dropped (the next graph step
+ * captures again).  Synchronizes the batch's streams. */
 cpal_status cp_arls_lev_autotune_batch(cpal_batch *batch, int32_t reps);
 
 /* The context of decomposition i (for samples, leverage, step counter and

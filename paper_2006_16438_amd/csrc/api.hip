@@ -1686,10 +1686,95 @@ void drop_stage_graph(cpal_batch *b, int mode) {
   b->kernels[1][mode] = 0;
 }
 
+// Launch rounds of described sequences and their tables in device memory.
+struct StagePlan {
+  std::vector<std::vector<DescLaunch>> seqs;
+  std::vector<StageRound> rounds;
+  void *mem = nullptr;   // packs and prefixes (batch allocator)
+};
+
+void plan_free(cpal_batch *b, StagePlan &p) {
+  if (p.mem) {
+    if (b->al.alloc) b->al.free(p.mem, b->al.user);
+    else hipFree(p.mem);
+  }
+  p.mem = nullptr;
+}
+
+// Rounds of p.seqs and their tables, written to device memory (synchronous copy).
+cpal_status plan_build(cpal_batch *b, StagePlan &p) {
+  p.rounds = plan_rounds(p.seqs);
+  std::vector<unsigned char> tab;
+  auto place = [&tab](size_t bytes) {
+    const size_t off = (tab.size() + 255) / 256 * 256;
+    tab.resize(off + bytes);
+    return off;
+  };
+  for (StageRound &r : p.rounds)
+    for (MultiGroup &g : r.groups) {
+      const DescLaunch &h0 = p.seqs[g.members[0].first][g.members[0].second];
+      const size_t stride = (h0.pack.size() + h0.align - 1) / h0.align * h0.align;
+      g.packs_off = place(stride * g.members.size());
+      for (size_t m = 0; m < g.members.size(); ++m) {
+        const DescLaunch &l = p.seqs[g.members[m].first][g.members[m].second];
+        std::memcpy(tab.data() + g.packs_off + m * stride, l.pack.data(), l.pack.size());
+      }
+      g.pre_off = place(sizeof(unsigned) * (g.members.size() + 1));
+      unsigned acc = 0;
+      for (size_t m = 0; m <= g.members.size(); ++m) {
+        std::memcpy(tab.data() + g.pre_off + m * sizeof(unsigned), &acc, sizeof(unsigned));
+        if (m < g.members.size()) {
+          const DescLaunch &l = p.seqs[g.members[m].first][g.members[m].second];
+          acc += l.grid;
+          g.shmem = std::max(g.shmem, l.shmem);
+        }
+      }
+      g.blocks = acc;
+    }
+  if (tab.empty()) return CPAL_OK;
+  if (b->al.alloc) p.mem = b->al.alloc(tab.size(), b->al.user);
+  else if (hipMalloc(&p.mem, tab.size()) != hipSuccess) p.mem = nullptr;
+  if (!p.mem) return CPAL_E_NOMEM;
+  return hipMemcpy(p.mem, tab.data(), tab.size(), hipMemcpyHostToDevice) == hipSuccess
+             ? CPAL_OK : CPAL_E_DEVICE;
+}
+
+// The rounds in order on streams[0] (batched launches) and the batch's other
+// streams (solo launches, by decomposition), each round joined back into
+// streams[0] before the next; capturable.
+void plan_issue(cpal_batch *b, const StagePlan &p) {
+  hipStream_t s0 = b->streams[0];
+  const size_t ns = b->streams.size();
+  for (const StageRound &r : p.rounds) {
+    std::vector<char> used(ns, 0);
+    if (!r.solos.empty() && ns > 1) {
+      hipEventRecord(b->start, s0);
+      for (const auto &q : r.solos) {
+        const size_t j = 1 + (size_t)q.first % (ns - 1);
+        if (!used[j]) hipStreamWaitEvent(b->streams[j], b->start, 0);
+        used[j] = 1;
+      }
+    }
+    for (const auto &q : r.solos)
+      p.seqs[q.first][q.second].solo(ns > 1 ? b->streams[1 + (size_t)q.first % (ns - 1)] : s0);
+    for (const MultiGroup &g : r.groups)
+      if (g.blocks > 0)
+        g.ml((const unsigned char *)p.mem + g.packs_off,
+             (const unsigned *)((const unsigned char *)p.mem + g.pre_off),
+             (unsigned)g.members.size(), g.blocks, g.block, g.shmem, s0);
+    for (size_t j = 1; j < ns; ++j)
+      if (used[j]) {
+        hipEventRecord(b->done[j], b->streams[j]);
+        hipStreamWaitEvent(s0, b->done[j], 0);
+      }
+  }
+}
+
 cpal_status batch_stage_capture(cpal_batch *b, int mode) {
   const size_t n = b->ctx.size();
   // 1. describe every decomposition's update
-  std::vector<std::vector<DescLaunch>> seqs(n);
+  StagePlan p;
+  p.seqs.resize(n);
   cpal_status res = CPAL_OK;
   for (size_t i = 0; i < n; ++i) {
     cpal_ctx *c = b->ctx[i];
@@ -1704,76 +1789,18 @@ cpal_status batch_stage_capture(cpal_batch *b, int mode) {
     c->timing = timing;
     c->t = t;
     if (st != CPAL_OK && res == CPAL_OK) res = st;
-    seqs[i] = std::move(sink.seq);
+    p.seqs[i] = std::move(sink.seq);
   }
   if (res != CPAL_OK) return res;
-  // 2. rounds and the launch tables of their batched launches
-  std::vector<StageRound> rounds = plan_rounds(seqs);
-  std::vector<unsigned char> tab;
-  auto place = [&tab](size_t bytes) {
-    const size_t off = (tab.size() + 255) / 256 * 256;
-    tab.resize(off + bytes);
-    return off;
-  };
-  for (StageRound &r : rounds)
-    for (MultiGroup &g : r.groups) {
-      const DescLaunch &h0 = seqs[g.members[0].first][g.members[0].second];
-      const size_t stride = (h0.pack.size() + h0.align - 1) / h0.align * h0.align;
-      g.packs_off = place(stride * g.members.size());
-      for (size_t m = 0; m < g.members.size(); ++m) {
-        const DescLaunch &l = seqs[g.members[m].first][g.members[m].second];
-        std::memcpy(tab.data() + g.packs_off + m * stride, l.pack.data(), l.pack.size());
-      }
-      g.pre_off = place(sizeof(unsigned) * (g.members.size() + 1));
-      unsigned acc = 0;
-      for (size_t m = 0; m <= g.members.size(); ++m) {
-        std::memcpy(tab.data() + g.pre_off + m * sizeof(unsigned), &acc, sizeof(unsigned));
-        if (m < g.members.size()) {
-          const DescLaunch &l = seqs[g.members[m].first][g.members[m].second];
-          acc += l.grid;
-          g.shmem = std::max(g.shmem, l.shmem);
-        }
-      }
-      g.blocks = acc;
-    }
+  // 2. rounds and their tables (kept until the graph is dropped)
   drop_stage_graph(b, mode);
-  void *mem = nullptr;
-  if (!tab.empty()) {
-    if (b->al.alloc) mem = b->al.alloc(tab.size(), b->al.user);
-    else if (hipMalloc(&mem, tab.size()) != hipSuccess) mem = nullptr;
-    if (!mem) return CPAL_E_NOMEM;
-    b->plan_mem[mode] = mem;
-    if (hipMemcpy(mem, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess)
-      return CPAL_E_DEVICE;
-  }
-  // 3. capture the rounds: batched launches on streams[0], solo launches on
-  // the other streams (by decomposition), joined back at the end of a round
+  res = plan_build(b, p);
+  b->plan_mem[mode] = p.mem;
+  if (res != CPAL_OK) return res;
+  // 3. capture the rounds
   hipStream_t s0 = b->streams[0];
-  const size_t ns = b->streams.size();
   if (hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed) != hipSuccess) return CPAL_E_DEVICE;
-  for (const StageRound &r : rounds) {
-    std::vector<char> used(ns, 0);
-    if (!r.solos.empty() && ns > 1) {
-      hipEventRecord(b->start, s0);
-      for (const auto &p : r.solos) {
-        const size_t j = 1 + (size_t)p.first % (ns - 1);
-        if (!used[j]) hipStreamWaitEvent(b->streams[j], b->start, 0);
-        used[j] = 1;
-      }
-    }
-    for (const auto &p : r.solos)
-      seqs[p.first][p.second].solo(ns > 1 ? b->streams[1 + (size_t)p.first % (ns - 1)] : s0);
-    for (const MultiGroup &g : r.groups)
-      if (g.blocks > 0)
-        g.ml((const unsigned char *)mem + g.packs_off,
-             (const unsigned *)((const unsigned char *)mem + g.pre_off),
-             (unsigned)g.members.size(), g.blocks, g.block, g.shmem, s0);
-    for (size_t j = 1; j < ns; ++j)
-      if (used[j]) {
-        hipEventRecord(b->done[j], b->streams[j]);
-        hipStreamWaitEvent(s0, b->done[j], 0);
-      }
-  }
+  plan_issue(b, p);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(s0, &g);
   if (e != hipSuccess || !g) return CPAL_E_DEVICE;
@@ -1781,6 +1808,53 @@ cpal_status batch_stage_capture(cpal_batch *b, int mode) {
   if (hipGraphInstantiate(&b->exec2[mode], g, nullptr, nullptr, 0) != hipSuccess)
     res = CPAL_E_DEVICE;
   hipGraphDestroy(g);
+  return res;
+}
+
+// Milliseconds per run of the gather stage of mode `mode` of every
+// decomposition (with the launch shapes they hold), issued as stage-major
+// rounds: M cleared, then the gather; the best of `reps` runs.  Runs on the
+// sampled system each decomposition's last update_front left.
+cpal_status time_batch_gathers(cpal_batch *b, int mode, int reps, double *ms) {
+  const size_t n = b->ctx.size();
+  StagePlan p;
+  p.seqs.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    cpal_ctx *c = b->ctx[i];
+    if (mode >= c->D || c->dense) continue;
+    Mode &md = c->mode[mode];
+    SeqSink sink;
+    launch_sink() = &sink;
+    launch_zero_words(c->M, (i64)m_copies(md.n) * md.n * c->ldz * (c->f64 ? 2 : 1), c->stream);
+    update_gather(c, mode, md.g_grid, md.g_sort_min);
+    launch_sink() = nullptr;
+    p.seqs[i] = std::move(sink.seq);
+  }
+  cpal_status res = plan_build(b, p);
+  if (res == CPAL_OK) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      res = CPAL_E_DEVICE;
+    } else {
+      double best = 1e30;
+      for (int r = 0; r < reps; ++r) {
+        hipEventRecord(e0, b->streams[0]);
+        plan_issue(b, p);
+        hipEventRecord(e1, b->streams[0]);
+        float t = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+          res = CPAL_E_DEVICE;
+          break;
+        }
+        best = std::min(best, (double)t);
+      }
+      *ms = best;
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  }
+  for (hipStream_t st : b->streams) hipStreamSynchronize(st);
+  plan_free(b, p);
   return res;
 }
 
@@ -1940,6 +2014,50 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
       }
       tuned[i] = src;
     }
+  }
+  // In a batch the decompositions' gathers run together (the stage-major
+  // graph launches each gather kernel once for all of them), which the
+  // per-tensor timings above (one decomposition alone) cannot see: forms whose
+  // grids are small alone fill the chip in a batch.  Per mode, the gather
+  // stage of all decompositions is timed as stage-major rounds with the shapes
+  // chosen so far and with the shared-block bucketed gather in every mode that
+  // takes it; the latter is kept when at least 3% faster.  The sampled systems
+  // are those of one more update_front (the step counters are restored).
+  for (int k = 0; k < CPAL_MAXORDER; ++k) {
+    bool any = false;
+    for (cpal_ctx *c : b->ctx) any |= k < c->D && !c->dense;
+    if (!any) continue;
+    for (cpal_ctx *c : b->ctx)
+      if (k < c->D) update_front(c, k);
+    for (hipStream_t s : b->streams) hipStreamSynchronize(s);
+    double t_kept = 0.0, t_bktl = 0.0;
+    cpal_status st = time_batch_gathers(b, k, std::max(reps, 1) + 1, &t_kept);
+    std::vector<std::pair<int, int>> saved(b->ctx.size());
+    int switched = 0;
+    for (size_t i = 0; i < b->ctx.size(); ++i) {
+      cpal_ctx *c = b->ctx[i];
+      if (k >= c->D || c->dense) continue;
+      saved[i] = {c->mode[k].g_grid, c->mode[k].g_sort_min};
+      if (st == CPAL_OK && c->mode[k].g_sort_min != -4 && ensure_bucket_buffers(c) == CPAL_OK &&
+          bucket_lds_capable(c, k)) {
+        c->mode[k].g_grid = 0;
+        c->mode[k].g_sort_min = -4;
+        ++switched;
+      }
+    }
+    if (switched > 0) st = time_batch_gathers(b, k, std::max(reps, 1) + 1, &t_bktl);
+    if (!(switched > 0 && st == CPAL_OK && t_bktl < 0.97 * t_kept))
+      for (size_t i = 0; i < b->ctx.size(); ++i) {
+        cpal_ctx *c = b->ctx[i];
+        if (k >= c->D || c->dense) continue;
+        c->mode[k].g_grid = saved[i].first;
+        c->mode[k].g_sort_min = saved[i].second;
+      }
+    for (cpal_ctx *c : b->ctx) {
+      launch_set_step(c->st, c->t, c->stream);
+      c->samples_valid = false;
+    }
+    if (st != CPAL_OK) return st;
   }
   // captured graphs hold the old launch shapes
   for (hipStream_t s : b->streams) hipStreamSynchronize(s);

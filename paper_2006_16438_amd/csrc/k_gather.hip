@@ -1536,16 +1536,20 @@ void launch_gather_seg(bool f64, const DevState *st, int R, const u64 *cpos, con
   }
 }
 
-__global__ void k_zero_words(unsigned *__restrict__ p, i64 n) {
-  for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x)
+__device__ __forceinline__ void zero_words_body(Blk bk, unsigned *__restrict__ p, i64 n) {
+  for (i64 i = (i64)bk.x * blockDim.x + threadIdx.x; i < n; i += (i64)bk.n * blockDim.x)
     p[i] = 0u;
 }
+__global__ void k_zero_words(unsigned *__restrict__ p, i64 n) {
+  zero_words_body(CPAL_BLK, p, n);
+}
+CPAL_BODY(B_zero_words, 256, 1, zero_words_body);
 
 void launch_zero_words(void *p, i64 nwords, hipStream_t s) {
   if (nwords <= 0) return;
   i64 g = (nwords + 255) / 256;
   if (g > 8192) g = 8192;
-  launch_1(k_zero_words, dim3((int)g), dim3(256), 0, s, (unsigned *)p, nwords);
+  launch_b<B_zero_words>(k_zero_words, dim3((int)g), dim3(256), 0, s, (unsigned *)p, nwords);
 }
 
 i64 gather_chunks_cap(i64 nnz) { return nnz / GT_CHUNK + 2; }
