@@ -2023,7 +2023,8 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
   // chosen so far and with the shared-block bucketed gather in every mode that
   // takes it; the latter is kept when at least 3% faster.  The sampled systems
   // are those of one more update_front (the step counters are restored).
-  for (int k = 0; k < CPAL_MAXORDER; ++k) {
+  cpal_status res = CPAL_OK;
+  for (int k = 0; k < CPAL_MAXORDER && res == CPAL_OK; ++k) {
     bool any = false;
     for (cpal_ctx *c : b->ctx) any |= k < c->D && !c->dense;
     if (!any) continue;
@@ -2057,7 +2058,7 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
       launch_set_step(c->st, c->t, c->stream);
       c->samples_valid = false;
     }
-    if (st != CPAL_OK) return st;
+    res = st;   // on an error the shapes chosen so far stay
   }
   // captured graphs hold the old launch shapes
   for (hipStream_t s : b->streams) hipStreamSynchronize(s);
@@ -2067,7 +2068,7 @@ cpal_status cp_arls_lev_autotune_batch(cpal_batch *b, int32_t reps) {
     b->kernels[0][m] = 0;
     drop_stage_graph(b, m);
   }
-  return CPAL_OK;
+  return res;
 }
 
 cpal_status cp_arls_lev_batch_set_graphs(cpal_batch *b, int32_t on) {
