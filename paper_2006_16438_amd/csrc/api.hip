@@ -56,14 +56,15 @@ void launch_gather_hyb(bool f64, const DevState *st, int R, const u64 *cpos,
                        const uint2 *pairs, const int *ik, const double *v64, i64 nk,
                        i64 max_total, i64 max_fib, const void *zhat, int ldz, void *M,
                        unsigned *bnd, unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent,
-                       int lfac, hipStream_t s);
+                       int lfac, int compact, hipStream_t s);
 size_t gather_bkt_count_words();
 int gather_bktl_shift(int R, i64 nk);
 void launch_gather_bktl(bool f64, const DevState *st, int R, const u64 *cpos,
                         const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
                         const uint2 *pairs, const int *ik, const double *v64, i64 nk,
                         i64 max_total, const void *zhat, int ldz, void *M, unsigned *cnt,
-                        u64 *off, void *scan_scratch, uint4 *bent, unsigned lmin, hipStream_t s);
+                        u64 *off, void *scan_scratch, uint4 *bent, unsigned lmin, int compact,
+                        hipStream_t s);
 void launch_gather_bkt(bool f64, const DevState *st, int R, const u64 *cpos,
                        const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
                        const uint2 *pairs, const int *ik, const double *v64, i64 nk,
@@ -933,6 +934,10 @@ bool uses_tile(const cpal_ctx *c, int k, int sort_min) {
           bucket_lds_capable(c, k));
 }
 
+// The shared-block bucketed gather's records pack the KRP row (slot index,
+// below the sample count) into 23 bits: compact records while it fits.
+int bktl_compact(const cpal_ctx *c) { return c->s < ((i64)1 << 23) ? 1 : 0; }
+
 // TnsrSamp + sampled MTTKRP (Sec. 6.3, eq. (1.2)) into M.  sort_min < 0
 // selects the bucketed gather (bucket_capable modes).
 void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
@@ -949,7 +954,7 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
     launch_gather_hyb(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                       md.ik, md.v64, md.n, c->nnz, c->s, c->zhat, c->ldz, c->M, c->tile_bnd,
                       c->bk_cnt, c->bk_off, c->bk_scan, c->bk_ent, grid > 0 && grid <= 256 ? grid : 16,
-                      s);
+                      bktl_compact(c), s);
   else if (uses_tile(c, k, sort_min))
     launch_gather_tile(c->f64, c->st, R, c->cpos, c->coff, c->cidx, md.pairs, md.ik, md.v64, md.n,
                        c->s, c->zhat, c->ldz, c->M, c->tile_bnd, 0u, s);
@@ -959,7 +964,7 @@ void update_gather(cpal_ctx *c, int k, int grid, int sort_min) {
   else if (sort_min == -4 && c->bk_ent && bucket_lds_capable(c, k))
     launch_gather_bktl(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                        md.ik, md.v64, md.n, c->nnz, c->zhat, c->ldz, c->M, c->bk_cnt, c->bk_off,
-                       c->bk_scan, c->bk_ent, 0u, s);
+                       c->bk_scan, c->bk_ent, 0u, bktl_compact(c), s);
   else if (sort_min == -1 && c->bk_ent && bucket_capable(c, k))
     launch_gather_bkt(c->f64, c->st, R, c->cpos, c->coff, c->cidx, c->chunk_first, md.pairs,
                       md.ik, md.v64, md.n, c->nnz, c->zhat, c->ldz, c->M, grid, c->bk_cnt,

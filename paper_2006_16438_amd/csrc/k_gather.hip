@@ -457,6 +457,41 @@ struct BktRec<double> {
   }
 };
 
+// A compact record of the shared-block bucketed gather: the row within its
+// bucket (bucket width at most 2^9 rows) and the KRP row in one word
+// ((zr << 9) | local row; zr < 2^23), then the value: 12 bytes in FP64,
+// 8 in FP32.
+#define BK_CROWBITS 9
+template <typename T>
+struct BktC;
+template <>
+struct BktC<double> {
+  typedef uint3 V;
+  static __device__ __forceinline__ V make(unsigned local, double x, unsigned zr) {
+    const u64 b = (u64)__double_as_longlong(x);
+    return make_uint3((zr << BK_CROWBITS) | local, (unsigned)b, (unsigned)(b >> 32));
+  }
+  static __device__ __forceinline__ void get(const V &v, unsigned &local, double &x,
+                                             unsigned &zr) {
+    local = v.x & ((1u << BK_CROWBITS) - 1u);
+    zr = v.x >> BK_CROWBITS;
+    x = __longlong_as_double((long long)(((u64)v.z << 32) | v.y));
+  }
+};
+template <>
+struct BktC<float> {
+  typedef uint2 V;
+  static __device__ __forceinline__ V make(unsigned local, float x, unsigned zr) {
+    return make_uint2((zr << BK_CROWBITS) | local, __float_as_uint(x));
+  }
+  static __device__ __forceinline__ void get(const V &v, unsigned &local, float &x,
+                                             unsigned &zr) {
+    local = v.x & ((1u << BK_CROWBITS) - 1u);
+    zr = v.x >> BK_CROWBITS;
+    x = __uint_as_float(v.y);
+  }
+};
+
 // Calls f(ik, x, KRP row) for every position of stream chunk ch (the chunk's
 // fiber starts are staged in win; positions find their fiber there) whose
 // fiber is shorter than lmin nonzeros (lmin = 0: every position); the other
@@ -582,7 +617,7 @@ __device__ __forceinline__ void bkt_scatter_body(Blk bk, const DevState *st,
     const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first,
     const NzLoad<T> &nz, int bshift, int nb, unsigned lmin, const u64 *__restrict__ off,
-    uint4 *__restrict__ bent) {
+    uint4 *__restrict__ bent, int compact) {
   __shared__ u64 win[GT_WIN];
   __shared__ unsigned cur[BK_BUCKETS];
   const i64 total = st->gathered, nf = st->n_fib;
@@ -600,16 +635,24 @@ __device__ __forceinline__ void bkt_scatter_body(Blk bk, const DevState *st,
                   unsigned base = 0;
                   if (r.head) base = atomicAdd(&cur[r.bkt], (unsigned)r.len);
                   const unsigned hb = (unsigned)__shfl((int)base, r.headlane, 64);
-                  if (kp) bent[hb + (unsigned)((threadIdx.x & 63) - r.headlane)] =
-                      BktRec<T>::make(ik, x, zr);   // one 16-byte store
+                  const unsigned slot = hb + (unsigned)((threadIdx.x & 63) - r.headlane);
+                  if (kp) {
+                    if (compact)
+                      ((typename BktC<T>::V *)bent)[slot] =
+                          BktC<T>::make((unsigned)ik & ((1u << bshift) - 1u), x, zr);
+                    else
+                      bent[slot] = BktRec<T>::make(ik, x, zr);   // one 16-byte store
+                  }
                 });
 }
 template <typename T>
 __global__ void __launch_bounds__(BK_THREADS) k_bkt_scatter(
     const DevState *st, const u64 *__restrict__ cpos, const unsigned *__restrict__ coff,
     const unsigned *__restrict__ cidx, const unsigned *__restrict__ chunk_first, NzLoad<T> nz,
-    int bshift, int nb, unsigned lmin, const u64 *__restrict__ off, uint4 *__restrict__ bent) {
-  bkt_scatter_body<T>(CPAL_BLK, st, cpos, coff, cidx, chunk_first, nz, bshift, nb, lmin, off, bent);
+    int bshift, int nb, unsigned lmin, const u64 *__restrict__ off, uint4 *__restrict__ bent,
+    int compact) {
+  bkt_scatter_body<T>(CPAL_BLK, st, cpos, coff, cidx, chunk_first, nz, bshift, nb, lmin, off, bent,
+                      compact);
 }
 template <typename T>
 struct B_bkt_scatter {
@@ -698,7 +741,7 @@ static void launch_gather_bkt_t(const DevState *st, int R, const u64 *cpos, cons
                            chunk_first, nz, bshift, nb, 0u, cnt);
   scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, nullptr, scan_scratch, s);
   launch_b<B_bkt_scatter<T>>(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff,
-                             cidx, chunk_first, nz, bshift, nb, 0u, off, bent);
+                             cidx, chunk_first, nz, bshift, nb, 0u, off, bent, 0);
   const int rm = gather_row_width(R);
 #define CPAL_BKT_LAUNCH(LPN, CPL)                                                                 \
   launch_b<B_gather_bkt<T, LPN, CPL>>(k_gather_bkt<T, LPN, CPL>, dim3(grid), dim3(GT_THREADS), 0, \
@@ -810,7 +853,7 @@ __device__ __forceinline__ void tile_add_rows(double *blk, int LDB, int rl, doub
 template <typename T>
 __device__ __forceinline__ void gather_bktl_body(Blk bk, const DevState *st, int R,
     const uint4 *__restrict__ bent, const u64 *__restrict__ off, int gb, int nb, int bshift,
-    const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
+    const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk, int compact) {
   extern __shared__ double bl_blk[];    // (1 << bshift) rows, odd stride LDB
   __shared__ unsigned bst[BL_MAXNB + 1];   // first record of each bucket
   __shared__ unsigned sst[BL_MAXNB + 1];   // first slice of each bucket
@@ -852,17 +895,32 @@ __device__ __forceinline__ void gather_bktl_body(Blk bk, const DevState *st, int
     for (unsigned q0 = a0 + (unsigned)w * (64u * BL_K); q0 < a1; q0 += NW * 64u * BL_K) {
       // every lane loads and adds (no divergent branch): a lane past the
       // slice re-reads its last record and adds zeros to a row of its own
-      uint4 rec[BL_K];
+      unsigned rk[BL_K], rz[BL_K];
+      T rx[BL_K];
       const unsigned pl = rec_lane(lane);
+      if (compact) {
+        typename BktC<T>::V rec[BL_K];
+        const typename BktC<T>::V *cb = (const typename BktC<T>::V *)bent;
 #pragma unroll
-      for (int u = 0; u < BL_K; ++u) rec[u] = bent[min(q0 + (unsigned)(u * 64) + pl, a1 - 1)];
+        for (int u = 0; u < BL_K; ++u) rec[u] = cb[min(q0 + (unsigned)(u * 64) + pl, a1 - 1)];
+#pragma unroll
+        for (int u = 0; u < BL_K; ++u) BktC<T>::get(rec[u], rk[u], rx[u], rz[u]);
+      } else {
+        uint4 rec[BL_K];
+#pragma unroll
+        for (int u = 0; u < BL_K; ++u) rec[u] = bent[min(q0 + (unsigned)(u * 64) + pl, a1 - 1)];
+#pragma unroll
+        for (int u = 0; u < BL_K; ++u) {
+          BktRec<T>::get(rec[u], rk[u], rx[u], rz[u]);
+          rk[u] -= (unsigned)r0;
+        }
+      }
 #pragma unroll
       for (int u = 0; u < BL_K; ++u) {
         if (q0 + (unsigned)(u * 64) >= a1) break;   // wave-uniform
-        unsigned ik, zr;
-        T x;
-        BktRec<T>::get(rec[u], ik, x, zr);
-        const int rl = (int)ik - (int)r0;
+        const unsigned zr = rz[u];
+        const T x = rx[u];
+        const int rl = (int)rk[u];
         const bool ok = q0 + (unsigned)(u * 64) + pl < a1 && (unsigned)rl < (unsigned)nrows;
         tile_add_rows<T>(bl_blk, LDB, ok ? rl : lane % nrows, ok ? (double)x : 0.0,
                          ok ? zr : 0u, zhat, ldz, R);
@@ -880,8 +938,9 @@ __device__ __forceinline__ void gather_bktl_body(Blk bk, const DevState *st, int
 template <typename T>
 __global__ void __launch_bounds__(BL_THREADS) k_gather_bktl(
     const DevState *st, int R, const uint4 *__restrict__ bent, const u64 *__restrict__ off,
-    int gb, int nb, int bshift, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
-  gather_bktl_body<T>(CPAL_BLK, st, R, bent, off, gb, nb, bshift, zhat, ldz, M, nk);
+    int gb, int nb, int bshift, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk,
+    int compact) {
+  gather_bktl_body<T>(CPAL_BLK, st, R, bent, off, gb, nb, bshift, zhat, ldz, M, nk, compact);
 }
 template <typename T>
 struct B_gather_bktl {
@@ -909,7 +968,7 @@ static void launch_gather_bktl_t(const DevState *st, int R, const u64 *cpos, con
                                  const unsigned *cidx, const unsigned *chunk_first, NzLoad<T> nz,
                                  i64 nk, i64 max_total, const T *zhat, int ldz, T *M,
                                  unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent,
-                                 unsigned lmin, hipStream_t s) {
+                                 unsigned lmin, int compact, hipStream_t s) {
   const int bshift = gather_bktl_shift(R, nk);
   const int nb = (int)((nk + (1ll << bshift) - 1) >> bshift);
   const i64 chunks = (max_total + GT_CHUNK - 1) / GT_CHUNK;
@@ -920,27 +979,28 @@ static void launch_gather_bktl_t(const DevState *st, int R, const u64 *cpos, con
   // counts (off[nb gb]): with lmin > 0 it is below the stream length
   scan_u32_dev(cnt, off, (i64)nb * gb, nullptr, off + (i64)nb * gb, scan_scratch, s);
   launch_b<B_bkt_scatter<T>>(k_bkt_scatter<T>, dim3(gb), dim3(BK_THREADS), 0, s, st, cpos, coff,
-                             cidx, chunk_first, nz, bshift, nb, lmin, off, bent);
+                             cidx, chunk_first, nz, bshift, nb, lmin, off, bent, compact);
   const size_t smem = ((size_t)1 << bshift) * (size_t)(R | 1) * 8;
   const i64 slices = max_total / BL_SLICE + nb + 1;
   const int grid = (int)std::min<i64>(512, std::max<i64>(1, slices));
   launch_b<B_gather_bktl<T>>(k_gather_bktl<T>, dim3(grid), dim3(BL_THREADS), smem, s, st, R, bent,
-                             off, gb, nb, bshift, zhat, ldz, M, nk);
+                             off, gb, nb, bshift, zhat, ldz, M, nk, compact);
 }
 
 void launch_gather_bktl(bool f64, const DevState *st, int R, const u64 *cpos,
                         const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
                         const uint2 *pairs, const int *ik, const double *v64, i64 nk,
                         i64 max_total, const void *zhat, int ldz, void *M, unsigned *cnt,
-                        u64 *off, void *scan_scratch, uint4 *bent, unsigned lmin, hipStream_t s) {
+                        u64 *off, void *scan_scratch, uint4 *bent, unsigned lmin, int compact,
+                        hipStream_t s) {
   if (f64)
     launch_gather_bktl_t<double>(st, R, cpos, coff, cidx, chunk_first, NzLoad<double>{ik, v64},
                                  nk, max_total, (const double *)zhat, ldz, (double *)M, cnt, off,
-                                 scan_scratch, bent, lmin, s);
+                                 scan_scratch, bent, lmin, compact, s);
   else
     launch_gather_bktl_t<float>(st, R, cpos, coff, cidx, chunk_first, NzLoad<float>{pairs}, nk,
                                 max_total, (const float *)zhat, ldz, (float *)M, cnt, off,
-                                scan_scratch, bent, lmin, s);
+                                scan_scratch, bent, lmin, compact, s);
 }
 
 // ------------------------------------------------------------ owner gather --
@@ -1486,19 +1546,20 @@ void launch_gather_bktl(bool f64, const DevState *st, int R, const u64 *cpos,
                         const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
                         const uint2 *pairs, const int *ik, const double *v64, i64 nk,
                         i64 max_total, const void *zhat, int ldz, void *M, unsigned *cnt,
-                        u64 *off, void *scan_scratch, uint4 *bent, unsigned lmin, hipStream_t s);
+                        u64 *off, void *scan_scratch, uint4 *bent, unsigned lmin, int compact,
+                        hipStream_t s);
 
 void launch_gather_hyb(bool f64, const DevState *st, int R, const u64 *cpos,
                        const unsigned *coff, const unsigned *cidx, const unsigned *chunk_first,
                        const uint2 *pairs, const int *ik, const double *v64, i64 nk,
                        i64 max_total, i64 max_fib, const void *zhat, int ldz, void *M,
                        unsigned *bnd, unsigned *cnt, u64 *off, void *scan_scratch, uint4 *bent,
-                       int lfac, hipStream_t s) {
+                       int lfac, int compact, hipStream_t s) {
   const unsigned lmin = gather_hyb_lmin(R, nk, lfac);
   launch_gather_tile(f64, st, R, cpos, coff, cidx, pairs, ik, v64, nk, max_fib, zhat, ldz, M, bnd,
                      lmin, s);
   launch_gather_bktl(f64, st, R, cpos, coff, cidx, chunk_first, pairs, ik, v64, nk, max_total,
-                     zhat, ldz, M, cnt, off, scan_scratch, bent, lmin, s);
+                     zhat, ldz, M, cnt, off, scan_scratch, bent, lmin, compact, s);
 }
 
 int gather_row_width(int R);

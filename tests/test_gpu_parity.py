@@ -379,6 +379,19 @@ def test_bucketed_shared_block_gather(gather, case):
                label=f"bktl-{gather}-{case}", gather_config=(0, -4))
 
 
+def test_bucketed_shared_block_gather_full_records():
+    """The shared-block bucketed gather with 2^23 samples: a KRP row (slot
+    index) no longer fits the compact record's 23 bits, so the records are
+    the full 16-byte ones (row, KRP row, value); 1100- and 4096-row modes,
+    FP64 at the 1e-10 bar."""
+    T = synth.random_sparse((1100, 4096, 4096), 1_000_000, seed=71)
+    fac = synth.gaussian_factors(T.dims, 8, 3)
+    s = 1 << 23
+    log("shared-block bucketed gather, 2^23 samples")
+    run_parity(T, fac, 8, s, 1.0 / s, 3, "f64", 1e-10, label="bktl-full-records",
+               gather_config=(0, -4))
+
+
 def _zipf3(seed=61):
     """3-way Zipf(1.2) coordinates (3000 x 1200 x 300, 4e5 nonzeros): fiber
     lengths from one to thousands in every mode."""
