@@ -838,11 +838,12 @@ __device__ __forceinline__ void tile_add_rows(double *blk, int LDB, int rl, doub
 // the buckets' records are cut into slices (at least BL_SLICE records, about
 // BL_SLICES slices in all) and workgroup g takes
 // the slices g, g + G, ...: it adds every record of the slice into the
-// bucket's shared block (one record per lane, column by column, atomic FP64
-// adds as in the tile gather), then adds the block into its XCD's copy of M
-// (one global add per nonzero entry of the block and slice).  Records of a
-// bucket follow the stream order of the scatter, i.e. fiber after fiber, so
-// neighbouring lanes mostly read the same weighted KRP row.
+// bucket's shared block (tile_add_rows: 4 records x 16 columns per atomic
+// FP64 add, as in the tile gather), then adds the block into its XCD's copy
+// of M (one global add per nonzero entry of the block and slice).  Records
+// of a bucket follow the stream order of the scatter, i.e. fiber after fiber,
+// so the records of a pass mostly share one weighted KRP row.  The records
+// are compact (BktC) while the KRP row fits 23 bits, else 16-byte BktRec.
 #define BL_THREADS 1024
 #define BL_MAXNB 2048
 #define BL_SLICE 65536
