@@ -1260,6 +1260,7 @@ void launch_gather_own(bool f64, const DevState *st, int R, const u64 *cpos,
 #define TL_THREADS 1024
 #define TL_K 4               // chunks of 64 positions a wave has in flight
 #define TL_MAXBLK (128 * 1024)   // bytes of the shared row block
+#define TL_CHUNKS 8192            // 64-position chunks of a window with a segment table
 
 // First fiber of part p: the least f with cpos[f] >= ceil(p total / parts).
 __device__ __forceinline__ i64 tile_part_start(const u64 *__restrict__ cpos, i64 nf, u64 total,
@@ -1388,6 +1389,7 @@ __device__ __forceinline__ void gather_tile_body(Blk bk, const DevState *st, int
     const NzLoad<T> &nz, const T *__restrict__ zhat, int ldz, T *__restrict__ M, i64 nk) {
   extern __shared__ double tl_blk[];   // (1 << rshift) rows, odd stride LDB
   __shared__ unsigned cs[TL_THREADS + 1], cb[TL_THREADS], cz[TL_THREADS];
+  __shared__ unsigned short csa[TL_CHUNKS];   // segment holding position 64 c of the window
   constexpr int NW = TL_THREADS / 64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int p = (int)(bk.x & (CPAL_MCOPIES - 1)), b = (int)(bk.x / CPAL_MCOPIES);
@@ -1430,6 +1432,15 @@ __device__ __forceinline__ void gather_tile_body(Blk bk, const DevState *st, int
     }
     if (tid == 0) cs[nne] = nw;
     __syncthreads();
+    // the segment of every 64-position chunk's first position (segments
+    // partition the window: one writer per chunk); windows of more chunks
+    // search all segments
+    const unsigned nck = (nw + 63) >> 6;
+    const bool tab = nck <= TL_CHUNKS;
+    if (tab)
+      for (int sg = tid; sg < nne; sg += TL_THREADS)
+        for (unsigned c = (cs[sg] + 63) >> 6; (c << 6) < cs[sg + 1]; ++c) csa[c] = (unsigned short)sg;
+    __syncthreads();
     // TL_K chunks of 64 positions per wave and step: their searches and
     // nonzero loads are all issued before the first chunk's adds
     for (unsigned qb = (unsigned)w * (64u * TL_K); qb < nw; qb += NW * 64u * TL_K) {
@@ -1442,6 +1453,11 @@ __device__ __forceinline__ void gather_tile_body(Blk bk, const DevState *st, int
       for (int u = 0; u < TL_K; ++u) {
         const unsigned q = min(qb + (unsigned)(u * 64) + pl, nw - 1);
         int lo2 = 0, hi2 = nne;   // last segment with cs[seg] <= q
+        if (tab) {   // between the segments of q's chunk start and the next chunk's
+          const unsigned cq = q >> 6;
+          lo2 = csa[cq];
+          hi2 = cq + 1 < nck ? (int)csa[cq + 1] + 1 : nne;
+        }
         while (hi2 - lo2 > 1) {
           const int mid = (lo2 + hi2) >> 1;
           if (cs[mid] <= q) lo2 = mid; else hi2 = mid;
