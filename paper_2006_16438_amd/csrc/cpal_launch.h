@@ -6,7 +6,8 @@
 // form) or launch_1 (any other kernel).  With no sink installed both launch at
 // once; with a sink installed on the calling thread they only describe the
 // launch to it: launch_b hands over the arguments as one trivially copyable
-// pack and a function that launches the batched kernel k_multi, launch_1 a
+// pack and a function that launches the batched kernel k_multi (a launch
+// with a 2-D or 3-D grid is handed over as launch_1's is), launch_1 a
 // closure that launches the kernel on a given stream.
 //
 // k_multi runs one body for many independent launches at once: launch d owns
